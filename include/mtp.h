@@ -1,0 +1,162 @@
+/*
+ * libmtp: Moment Tensor Potential evaluation on AMD Instinct MI355X (gfx950).
+ *
+ * C ABI.  Every compute entry point is asynchronous on the HIP stream it is
+ * given unless stated otherwise.  Pointers marked "device" must point to
+ * memory of the model's device; the caller owns every batch and output
+ * buffer; the model owns its parameters, its active-set inverse and a
+ * grow-only workspace.  One model must not be used from two host threads at
+ * once.  Functions return 0 on success or a negative MTP_E_* code; the text
+ * of the last error on the calling thread is returned by mtp_last_error().
+ *
+ * The method is that of Novikov, Gubaev, Podryabinkin and Shapeev, "The MLIP
+ * package: Moment Tensor Potentials with MPI and Active Learning" (2020),
+ * section 2 ("Theory"); each entry point names the part it implements.
+ */
+#ifndef MTP_H
+#define MTP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mtp_model mtp_model;
+
+/* Return codes. */
+enum {
+  MTP_OK = 0,
+  MTP_E_ARG = -1,      /* invalid argument (null pointer, size, species, ...) */
+  MTP_E_FILE = -2,     /* potential file missing or malformed */
+  MTP_E_HIP = -3,      /* a HIP runtime call failed */
+  MTP_E_CAPACITY = -4, /* a size exceeds a documented limit */
+  MTP_E_BASIS = -5,    /* the potential's basis is not compiled into this library */
+  MTP_E_STATE = -6     /* call order violated (e.g. grade without an active set) */
+};
+
+/* Arithmetic of the evaluation kernels. */
+typedef enum {
+  MTP_FP64 = 0,              /* everything in FP64 */
+  MTP_FP32 = 1,              /* pair vectors rounded from FP64 to FP32, FP32 arithmetic */
+  MTP_FP32_COMPENSATED = 2   /* as MTP_FP32, moments summed with an error-free TwoSum */
+} mtp_precision;
+
+/* Loss weightings of section 2.2: eq. Fitting as written, eq.
+ * train-structures, eq. train-vibrations (the paper's default). */
+typedef enum {
+  MTP_SCALE_MOLECULES = 0,
+  MTP_SCALE_STRUCTURES = 1,
+  MTP_SCALE_VIBRATIONS = 2
+} mtp_scaling;
+
+/* A batch of configurations.  All pointers are device pointers. */
+typedef struct {
+  int32_t n_configs;
+  int64_t n_atoms;              /* total over the batch */
+  const int64_t* atom_offsets;  /* [n_configs + 1], atom_offsets[0] = 0, non-decreasing */
+  const double* pos;            /* [n_atoms][3] Cartesian positions, Angstrom */
+  const int32_t* species;       /* [n_atoms] type index z_i in [0, n_species) */
+  const double* cell;           /* [n_configs][3][3] lattice vectors as rows, Angstrom */
+  const uint8_t* pbc;           /* [n_configs] 1 = periodic in 3D, 0 = free cluster */
+} mtp_batch;
+
+/* Outputs of mtp_eval; every pointer is a device pointer or NULL (not wanted). */
+typedef struct {
+  double* energy;       /* [n_configs] E = sum_i V(n_i), eV (eq. E_MTP) */
+  double* forces;       /* [n_atoms][3] F = -dE/dx, eV/Angstrom */
+  double* virial;       /* [n_configs][3][3] W_ab = dE/d eps_ab for r -> (I + eps) r, eV;
+                           the stress of a periodic cell is W / volume */
+  double* site_energy;  /* [n_atoms] V(n_i), eV (eq. V_MTP) */
+  double* b;            /* [n_configs][m] b_alpha = sum_i B_alpha(n_i) (eq. matrix-B),
+                           in the basis order of the potential file */
+} mtp_out;
+
+/* Basic facts about a loaded potential. */
+typedef struct {
+  int32_t level;        /* lev_max */
+  int32_t m;            /* number of basis functions = |xi| */
+  int32_t n_mu;         /* number of radial functions f_mu */
+  int32_t n_species;
+  int32_t n_q;          /* radial basis size N_Q */
+  int32_t n_c;          /* |c| = n_mu * n_species^2 * n_q */
+  double r_min;         /* Angstrom */
+  double r_cut;         /* Angstrom */
+} mtp_info;
+
+/*
+ * Reads a potential (functional form of section 2.1 plus theta = {xi, c})
+ * from a text file and prepares it on HIP device `device`.
+ * File format: "mtp355 1", then level, species_count, radial_basis_size,
+ * min_dist, max_dist, the moment list (mu nu), the connected contractions
+ * (vertices as moment indices, edges "u v k"), the basis functions (lists of
+ * contraction indices), radial_coeffs c[mu][z_i][z_j][beta] and xi.
+ * The basis must be one the library was built for (MTP_E_BASIS otherwise);
+ * it is matched up to the order of contractions, functions and vertices.
+ * On success *out owns device memory until mtp_free.
+ */
+int mtp_load(const char* path, int device, mtp_model** out);
+
+/* Fills *info.  Host only, no device work. */
+int mtp_model_info(const mtp_model* model, mtp_info* info);
+
+/* Replaces theta = {xi, c} (eqs. V_MTP and f_mu).  Host pointers, file order:
+ * c_host [n_mu][S][S][N_Q], xi_host [m].  Either may be NULL (kept).
+ * Synchronous (the parameters are in use by the next call on any stream). */
+int mtp_set_params(mtp_model* model, const double* c_host, const double* xi_host);
+
+/* Copies theta to host memory (same layouts as mtp_set_params). */
+int mtp_get_params(const mtp_model* model, double* c_host, double* xi_host);
+
+/*
+ * Energy, forces, virial, site energies and descriptors of every
+ * configuration of a batch (section 2.1: eqs. E_MTP, V_MTP, the moments,
+ * eqs. f_mu and radial-basis; forces and virial by the adjoint of that
+ * chain).  Neighbourhoods hold every atom and periodic image with
+ * 0 < |r_ij| < R_cut.  Runs on `stream` (a hipStream_t; NULL = default);
+ * it synchronises the stream once to size the neighbour workspace.
+ */
+int mtp_eval(mtp_model* model, const mtp_batch* batch, const mtp_out* out,
+             int precision, void* stream);
+
+/*
+ * Sets the active set of section 2.3: A (device, [m][m] FP64, row j = b of
+ * active configuration j, columns in file basis order).  A^{-1} is formed
+ * on the device by FP64 Gauss-Jordan elimination with partial pivoting and
+ * kept in the model.  Fails with MTP_E_ARG if A is numerically singular.
+ * Synchronises `stream`.
+ */
+int mtp_set_active_set(mtp_model* model, const double* A_dev, void* stream);
+
+/*
+ * Extrapolation grade of section 2.3 for rows b (device, [n][m] FP64, file
+ * order): c = b A^{-1}, gamma = max_j |c_j|, argmax = the row of A that the
+ * MaxVol step would replace (lowest index on ties).  gamma_dev [n] FP64,
+ * argmax_dev [n] int32, c_dev [n][m] FP64 or NULL.
+ */
+int mtp_grade_from_b(mtp_model* model, int32_t n, const double* b_dev, double* gamma_dev,
+                     int32_t* argmax_dev, double* c_dev, void* stream);
+
+/* mtp_eval for b followed by mtp_grade_from_b, per configuration. */
+int mtp_grade(mtp_model* model, const mtp_batch* batch, double* gamma_dev, int32_t* argmax_dev,
+              int precision, void* stream);
+
+/*
+ * Device-side counters of the last mtp_eval on this model: pairs closer than
+ * R_min (the radial polynomial is then evaluated outside [R_min, R_cut]) and
+ * neighbour-list inconsistencies (always 0 unless memory was corrupted).
+ * Synchronises `stream`.
+ */
+int mtp_status(mtp_model* model, void* stream, int64_t* n_below_rmin, int64_t* n_list_errors);
+
+/* Releases the model and its device memory. */
+void mtp_free(mtp_model* model);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char* mtp_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MTP_H */

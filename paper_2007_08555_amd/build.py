@@ -1,0 +1,114 @@
+"""Builds libmtp.so for gfx950 in-tree.
+
+    python -m paper_2007_08555_amd.build [--jobs N] [--levels 8,16]
+
+Steps: generate one evaluation kernel per compiled basis level
+(codegen.py), compile every .hip source with hipcc for gfx950, link
+paper_2007_08555_amd/libmtp.so.  Object files go to
+paper_2007_08555_amd/_build/ and are reused when their source, the shared
+headers and the flags are unchanged.
+"""
+from __future__ import annotations
+
+import argparse
+import concurrent.futures as cf
+import hashlib
+import os
+import shutil
+import subprocess
+import sys
+import time
+
+from . import codegen
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(PKG)
+CSRC = os.path.join(PKG, "csrc")
+GEN = os.path.join(CSRC, "generated")
+BUILD = os.path.join(PKG, "_build")
+LIB = os.path.join(PKG, "libmtp.so")
+
+HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+ARCH = "gfx950"
+FLAGS = [
+    "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
+    # keep the compiler from forming packed FP32 instructions
+    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    "-I", CSRC, "-I", os.path.join(ROOT, "include"),
+    "-Wno-unused-result",
+]
+HEADERS = ["mtp_device.h", "mtp_internal.h", "mtp_variant.h"]
+
+
+def _hash(path, extra):
+    h = hashlib.sha256()
+    with open(path, "rb") as fh:
+        h.update(fh.read())
+    for hd in HEADERS:
+        with open(os.path.join(CSRC, hd), "rb") as fh:
+            h.update(fh.read())
+    with open(os.path.join(ROOT, "include", "mtp.h"), "rb") as fh:
+        h.update(fh.read())
+    h.update(" ".join(extra).encode())
+    return h.hexdigest()[:16]
+
+
+def _compile(src):
+    base = os.path.splitext(os.path.basename(src))[0]
+    tag = _hash(src, FLAGS)
+    obj = os.path.join(BUILD, f"{base}.{tag}.o")
+    if os.path.exists(obj):
+        return obj, 0.0, "cached"
+    t0 = time.time()
+    lang = ["-x", "hip"] if src.endswith((".hip", ".cpp")) else []
+    cmd = [HIPCC] + FLAGS + lang + ["-c", src, "-o", obj + ".tmp"]
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        raise RuntimeError(f"hipcc failed on {src}:\n{res.stderr[-6000:]}")
+    os.replace(obj + ".tmp", obj)
+    return obj, time.time() - t0, res.stderr.strip()
+
+
+def build(levels=None, jobs=None, verbose=True):
+    if not os.path.exists(HIPCC):
+        raise RuntimeError(f"hipcc not found at {HIPCC}")
+    os.makedirs(BUILD, exist_ok=True)
+    gen_files, _ = codegen.write_all(GEN, levels=levels or codegen.LEVELS)
+    sources = [os.path.join(CSRC, f) for f in sorted(os.listdir(CSRC)) if f.endswith(".hip")]
+    sources += [f for f in gen_files if f.endswith((".hip", ".cpp"))]
+    jobs = jobs or min(8, os.cpu_count() or 4)
+    objs = []
+    # largest generated kernels first so they overlap with the small files
+    sources.sort(key=lambda p: -os.path.getsize(p))
+    with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
+        for obj, dt, msg in ex.map(_compile, sources):
+            objs.append(obj)
+            if verbose and dt:
+                print(f"  compiled {os.path.basename(obj)} in {dt:.1f} s", flush=True)
+    tmp = LIB + ".tmp"
+    cmd = [HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp] + objs
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        raise RuntimeError(f"link failed:\n{res.stderr[-4000:]}")
+    os.replace(tmp, LIB)
+    # drop stale objects of earlier source versions
+    keep = set(os.path.basename(o) for o in objs)
+    for f in os.listdir(BUILD):
+        if f.endswith(".o") and f not in keep:
+            os.remove(os.path.join(BUILD, f))
+    if verbose:
+        print(f"built {LIB}", flush=True)
+    return LIB
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--jobs", type=int, default=None)
+    ap.add_argument("--levels", type=str, default=None)
+    a = ap.parse_args()
+    levels = tuple(int(x) for x in a.levels.split(",")) if a.levels else None
+    build(levels=levels, jobs=a.jobs)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,429 @@
+"""Generates the HIP evaluation kernel of one MTP basis (build step).
+
+For a basis of level lev_max (paper, section 2.1) the generator emits one
+straight-line kernel per atom that
+
+1. accumulates the moments M_{mu,nu} over the atom's pairs, held as the
+   symmetric components M[a,b,c] (a + b + c = nu; the entry of the full
+   tensor at any index tuple with a x's, b y's and c z's),
+2. evaluates every connected contraction as a sum of products of those
+   components, forms the basis functions B_alpha (products of contractions)
+   and V = sum_alpha xi_alpha B_alpha (eq. V_MTP),
+3. runs the same straight-line code in reverse to get G = dV/dM, and
+4. for every pair forms g = dV/dr_ij from G, f_mu and df_mu/dr, writes it
+   for the force gather and accumulates the virial sum g (x) r.
+
+A contraction of symmetric tensors over an edge of multiplicity k sums over
+the k contracted index pairs; grouping the index tuples by their counts
+(kx, ky, kz) turns it into a sum over compositions of k with weight
+k! / (kx! ky! kz!).  A vertex reads the component given by the sum of the
+compositions of its incident edges.
+
+All array indices are compile-time constants, so M and G live in registers.
+"""
+from __future__ import annotations
+
+import itertools
+import json
+import math
+import os
+from collections import defaultdict
+
+from . import basis as pb
+
+
+def components(nu):
+    """(a, b, c) with a + b + c = nu in a fixed order."""
+    return [(a, b, nu - a - b) for a in range(nu, -1, -1) for b in range(nu - a, -1, -1)]
+
+
+def multinomial(a, b, c):
+    return math.factorial(a + b + c) // (math.factorial(a) * math.factorial(b) * math.factorial(c))
+
+
+class Schedule:
+    """Component layout, contraction terms and basis products of one level."""
+
+    def __init__(self, lev_max):
+        self.level = lev_max
+        self.keys = list(pb.contractions(lev_max))
+        self.funcs = list(pb.functions(lev_max))
+        self.moments = pb.moments(lev_max)
+        self.n_mu = 1 + max(mu for mu, _ in self.moments)
+        self.nu_max = max(nu for _, nu in self.moments)
+        self.comp = {}
+        for mu, nu in self.moments:
+            for abc in components(nu):
+                self.comp[(mu, nu, abc)] = len(self.comp)
+        self.C = len(self.comp)
+        self.graphs = [pb.decode(k) for k in self.keys]
+        self.terms = [self._terms(labels, edges) for labels, edges in self.graphs]
+
+    def _terms(self, labels, edges):
+        if not edges:
+            (mu, nu), = labels
+            return [(1, (self.comp[(mu, 0, (0, 0, 0))],))]
+        per_edge = []
+        for u, v, k in edges:
+            per_edge.append([(u, v, abc, multinomial(*abc)) for abc in components(k)])
+        acc = defaultdict(int)
+        for choice in itertools.product(*per_edge):
+            cnt = [[0, 0, 0] for _ in labels]
+            coef = 1
+            for u, v, abc, w in choice:
+                for t in range(3):
+                    cnt[u][t] += abc[t]
+                    cnt[v][t] += abc[t]
+                coef *= w
+            idx = tuple(sorted(self.comp[(mu, nu, tuple(cnt[x]))] for x, (mu, nu) in enumerate(labels)))
+            acc[idx] += coef
+        return sorted((c, idx) for idx, c in acc.items())
+
+    # ------------------------------------------------------------------
+    def nus_used(self):
+        return sorted({nu for _, nu in self.moments})
+
+    def mus_of_nu(self, nu):
+        return [mu for mu, n in self.moments if n == nu]
+
+    def metadata(self):
+        return {"level": self.level, "m": len(self.funcs), "graphs": len(self.keys),
+                "C": self.C, "n_mu": self.n_mu, "nu_max": self.nu_max,
+                "terms": sum(len(t) for t in self.terms)}
+
+
+def _prod(factors):
+    return " * ".join(factors) if factors else "T(1)"
+
+
+def _const(v):
+    return f"T({float(v)!r})"
+
+
+def emit_pair_forward(s, comp_mode):
+    """Monomials of the pair vector and the moment accumulation."""
+    out = []
+    ops = 0
+    mono = {(0, 0, 0): "T(1)"}
+    for nu in range(1, s.nu_max + 1):
+        for a, b, c in components(nu):
+            if a:
+                src, v = (a - 1, b, c), "x"
+            elif b:
+                src, v = (a, b - 1, c), "y"
+            else:
+                src, v = (a, b, c - 1), "z"
+            name = f"m{a}_{b}_{c}"
+            rhs = v if src == (0, 0, 0) else f"{mono[src]} * {v}"
+            if src != (0, 0, 0):
+                ops += 1
+            out.append(f"const T {name} = {rhs};")
+            mono[(a, b, c)] = name
+    for (mu, nu, abc), k in s.comp.items():
+        term = f"f[{mu}]" if nu == 0 else f"f[{mu}] * {mono[abc]}"
+        if comp_mode:
+            out.append(f"if (COMP) mtp::two_sum_acc(M[{k}], Mlo[{k}], {term}); else M[{k}] += {term};")
+        else:
+            out.append(f"M[{k}] += {term};")
+        ops += 2 if nu else 1
+    return out, ops
+
+
+def emit_contraction(s):
+    """Forward contraction, basis values, V, and the reverse sweep into G."""
+    out = []
+    ops = 0
+    # forward: graph values
+    for g, terms in enumerate(s.terms):
+        out.append(f"T g{g} = T(0);")
+        for coef, idx in terms:
+            fac = [f"M[{k}]" for k in idx]
+            expr = _prod(fac)
+            if coef != 1:
+                expr = f"{_const(coef)} * {expr}"
+            out.append(f"g{g} += {expr};")
+            ops += len(idx) + (1 if coef != 1 else 0)
+    # basis functions and V
+    out.append("T V = T(0);")
+    for a, fn in enumerate(s.funcs):
+        out.append(f"{{ const T b = {_prod([f'g{g}' for g in fn])}; V += xi[{a}] * b;"
+                   f" if (WANT_B) args.B[(size_t){a} * args.b_stride + i] = b; }}")
+        ops += len(fn) - 1 + 2
+    # dV/dg
+    dg = defaultdict(list)
+    for a, fn in enumerate(s.funcs):
+        counts = defaultdict(int)
+        for g in fn:
+            counts[g] += 1
+        for g, n in counts.items():
+            rest = list(fn)
+            rest.remove(g)
+            expr = _prod([f"g{h}" for h in rest])
+            if n > 1:
+                expr = f"T({float(n)!r}) * {expr}"
+            dg[g].append(f"xi[{a}] * {expr}")
+            ops += len(rest) + 1 + (1 if n > 1 else 0)
+    for g in range(len(s.terms)):
+        out.append(f"const T dg{g} = " + (" + ".join(dg[g]) if dg[g] else "T(0)") + ";")
+    # reverse of the graph terms
+    for g, terms in enumerate(s.terms):
+        out.append("{")
+        out.append(f"const T d = dg{g};")
+        for coef, idx in terms:
+            cd = "d" if coef == 1 else f"({_const(coef)} * d)"
+            if coef != 1:
+                ops += 1
+            for p, k in enumerate(idx):
+                rest = [f"M[{q}]" for t, q in enumerate(idx) if t != p]
+                out.append(f"G[{k}] += {cd}" + ("" if not rest else " * " + " * ".join(rest)) + ";")
+                ops += len(rest) + 1
+        out.append("}")
+    return out, ops
+
+
+def emit_pair_backward(s):
+    """g = dV/dr_ij for one pair from G, f, df and the monomials."""
+    out = []
+    ops = 0
+    mono = {(0, 0, 0): "T(1)"}
+    for nu in range(1, s.nu_max + 1):
+        for a, b, c in components(nu):
+            if a:
+                src, v = (a - 1, b, c), "x"
+            elif b:
+                src, v = (a, b - 1, c), "y"
+            else:
+                src, v = (a, b, c - 1), "z"
+            name = f"m{a}_{b}_{c}"
+            rhs = v if src == (0, 0, 0) else f"{mono[src]} * {v}"
+            if src != (0, 0, 0):
+                ops += 1
+            out.append(f"const T {name} = {rhs};")
+            mono[(a, b, c)] = name
+    out.append("T D[NMU];")
+    out.append("#pragma unroll\nfor (int q = 0; q < NMU; ++q) D[q] = T(0);")
+    out.append("T gx = T(0), gy = T(0), gz = T(0);")
+    for nu in s.nus_used():
+        mus = s.mus_of_nu(nu)
+        for a, b, c in components(nu):
+            ks = [s.comp[(mu, nu, (a, b, c))] for mu in mus]
+            if nu == 0:
+                for mu, k in zip(mus, ks):
+                    out.append(f"D[{mu}] += G[{k}];")
+                    ops += 1
+                continue
+            # G is the derivative with respect to the component itself, a plain
+            # sum over pairs of f_mu x^a y^b z^c: no multinomial weight here
+            out.append("{")
+            mono_abc = mono[(a, b, c)]
+            for mu, k in zip(mus, ks):
+                out.append(f"D[{mu}] += G[{k}] * {mono_abc};")
+                ops += 2
+            out.append("const T h = " + " + ".join(f"f[{mu}] * G[{k}]" for mu, k in zip(mus, ks)) + ";")
+            ops += 2 * len(ks) - 1
+            for axis, e, src in (("gx", a, (a - 1, b, c)), ("gy", b, (a, b - 1, c)), ("gz", c, (a, b, c - 1))):
+                if e:
+                    lower = mono[src]
+                    fac = "h" if e == 1 else f"{_const(e)} * h"
+                    out.append(f"{axis} += {fac} * {lower};" if lower != "T(1)" else f"{axis} += {fac};")
+                    ops += 2 + (1 if e != 1 else 0)
+            out.append("}")
+    out.append("T rad = T(0);")
+    out.append("#pragma unroll\nfor (int q = 0; q < NMU; ++q) rad += df[q] * D[q];")
+    out.append("const T ri = rad * inv_r;")
+    out.append("gx += ri * x; gy += ri * y; gz += ri * z;")
+    ops += 2 * s.n_mu + 1 + 6
+    return out, ops
+
+
+KERNEL_TEMPLATE = r"""// Generated by paper_2007_08555_amd/codegen.py for the MTP basis of level {level}
+// ({m} basis functions, {ngraphs} connected contractions, {C} moment components).
+// Do not edit: regenerate with the package build step.
+#include "mtp_device.h"
+#include "mtp_variant.h"
+
+namespace {{
+namespace {ns} {{
+
+constexpr int C = {C};
+constexpr int NMU = {n_mu};
+constexpr int BLOCK = {block};
+
+template <typename T, bool COMP, bool WANT_B>
+__global__ void __launch_bounds__(BLOCK) eval_kernel(const mtp::EvalArgs<T> args) {{
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* cs = reinterpret_cast<T*>(smem_raw);
+  for (int t = threadIdx.x; t < args.n_c; t += blockDim.x) cs[t] = args.c[t];
+  __syncthreads();
+  const int i = blockIdx.x * BLOCK + threadIdx.x;
+  if (i >= args.n_atoms) return;
+  const T* __restrict__ xi = args.xi;
+  const int S = args.n_species;
+  const int nq = args.nq;
+  const int mu_stride = S * S * nq;
+  const int zi = args.species[i];
+  const int cnt = args.nbr_count[i];
+  const T rmin = args.rmin, rcut = args.rcut;
+
+  T M[C];
+  T Mlo[COMP ? C : 1];
+#pragma unroll
+  for (int k = 0; k < C; ++k) M[k] = T(0);
+#pragma unroll
+  for (int k = 0; k < (COMP ? C : 1); ++k) Mlo[k] = T(0);
+
+  for (int p = 0; p < cnt; ++p) {{
+    const size_t e = (size_t)p * args.stride + i;
+    const T x = args.px[e], y = args.py[e], z = args.pz[e];
+    const int zj = args.pzj[e];
+    const T r = sqrt(x * x + y * y + z * z);
+    T f[NMU], df[NMU];
+    mtp::radial<T, NMU, false>(cs, (zi * S + zj) * nq, mu_stride, nq, r, rmin, rcut, f, df);
+{pair_fwd}
+  }}
+  if (COMP) {{
+#pragma unroll
+    for (int k = 0; k < C; ++k) M[k] += Mlo[k];
+  }}
+
+  T G[C];
+#pragma unroll
+  for (int k = 0; k < C; ++k) G[k] = T(0);
+  {{
+{contraction}
+    args.site[i] = V;
+  }}
+
+  T w00 = 0, w01 = 0, w02 = 0, w10 = 0, w11 = 0, w12 = 0, w20 = 0, w21 = 0, w22 = 0;
+  for (int p = 0; p < cnt; ++p) {{
+    const size_t e = (size_t)p * args.stride + i;
+    const T x = args.px[e], y = args.py[e], z = args.pz[e];
+    const int zj = args.pzj[e];
+    const T r = sqrt(x * x + y * y + z * z);
+    const T inv_r = T(1) / r;
+    T f[NMU], df[NMU];
+    mtp::radial<T, NMU, true>(cs, (zi * S + zj) * nq, mu_stride, nq, r, rmin, rcut, f, df);
+{pair_bwd}
+    args.gx[e] = gx;
+    args.gy[e] = gy;
+    args.gz[e] = gz;
+    w00 += gx * x; w01 += gx * y; w02 += gx * z;
+    w10 += gy * x; w11 += gy * y; w12 += gy * z;
+    w20 += gz * x; w21 += gz * y; w22 += gz * z;
+  }}
+  const int n = args.stride;
+  T* wv = args.atom_virial;
+  wv[0 * n + i] = w00; wv[1 * n + i] = w01; wv[2 * n + i] = w02;
+  wv[3 * n + i] = w10; wv[4 * n + i] = w11; wv[5 * n + i] = w12;
+  wv[6 * n + i] = w20; wv[7 * n + i] = w21; wv[8 * n + i] = w22;
+}}
+
+template <typename T, bool COMP, bool WANT_B>
+hipError_t launch_t(const void* a, hipStream_t s) {{
+  const auto& args = *static_cast<const mtp::EvalArgs<T>*>(a);
+  if (args.n_atoms <= 0) return hipSuccess;
+  const dim3 grid((args.n_atoms + BLOCK - 1) / BLOCK);
+  const size_t smem = (size_t)args.n_c * sizeof(T);
+  hipLaunchKernelGGL((eval_kernel<T, COMP, WANT_B>), grid, dim3(BLOCK), smem, s, args);
+  return hipGetLastError();
+}}
+
+hipError_t launch(int precision, bool want_b, const void* a, hipStream_t s) {{
+  switch (precision) {{
+    case 0: return want_b ? launch_t<double, false, true>(a, s) : launch_t<double, false, false>(a, s);
+    case 1: return want_b ? launch_t<float, false, true>(a, s) : launch_t<float, false, false>(a, s);
+    case 2: return want_b ? launch_t<float, true, true>(a, s) : launch_t<float, true, false>(a, s);
+  }}
+  return hipErrorInvalidValue;
+}}
+
+const int kMoments[] = {{ {moments} }};
+const int kGraphKeyOffsets[] = {{ {graph_offsets} }};
+const int kGraphKeys[] = {{ {graph_keys} }};
+const int kFuncOffsets[] = {{ {func_offsets} }};
+const int kFuncFactors[] = {{ {func_factors} }};
+
+}}  // namespace {ns}
+}}  // namespace
+
+// The table entry holds a host function pointer, so it exists only in the
+// host compilation pass.
+#if !defined(__HIP_DEVICE_COMPILE__)
+extern const mtp::BasisVariant {ns}_variant = {{
+  "{ns}", {level}, {n_moments}, {ns}::kMoments, {ngraphs}, {ns}::kGraphKeyOffsets, {ns}::kGraphKeys,
+  {m}, {ns}::kFuncOffsets, {ns}::kFuncFactors, {C}, {n_mu}, {nu_max},
+  {flops_pair_fwd}, {flops_pair_bwd}, {flops_atom}, {ns}::launch }};
+#endif
+"""
+
+
+def generate(lev_max, block=64):
+    s = Schedule(lev_max)
+    ns = f"lev{lev_max}"
+    fwd, ops_f = emit_pair_forward(s, comp_mode=True)
+    con, ops_c = emit_contraction(s)
+    bwd, ops_b = emit_pair_backward(s)
+    # radial work per pair: distance 6, Chebyshev 3 per term, f_mu 2 per (mu, beta),
+    # derivative pass adds dT and df
+    nq = 8
+    rad_f = 6 + 3 * (nq - 2) + 2 * s.n_mu * nq + 2 * s.n_mu
+    rad_b = rad_f + 5 * (nq - 2) + 2 * s.n_mu * nq + 4 * s.n_mu + 2
+    flops_pair_fwd = ops_f + rad_f
+    flops_pair_bwd = ops_b + rad_b + 18 + 1
+    graph_keys, graph_offsets = [], [0]
+    for k in s.keys:
+        graph_keys += list(k)
+        graph_offsets.append(len(graph_keys))
+    func_factors, func_offsets = [], [0]
+    for f in s.funcs:
+        func_factors += list(f)
+        func_offsets.append(len(func_factors))
+    ind = lambda lines, n: "\n".join(" " * n + l for l in lines)
+    src = KERNEL_TEMPLATE.format(
+        level=lev_max, m=len(s.funcs), ngraphs=len(s.keys), C=s.C, n_mu=s.n_mu, nu_max=s.nu_max,
+        block=block, ns=ns,
+        pair_fwd=ind(fwd, 4), contraction=ind(con, 4), pair_bwd=ind(bwd, 4),
+        moments=", ".join(f"{mu}, {nu}" for mu, nu in s.moments),
+        n_moments=len(s.moments),
+        graph_offsets=", ".join(map(str, graph_offsets)),
+        graph_keys=", ".join(map(str, graph_keys)),
+        func_offsets=", ".join(map(str, func_offsets)),
+        func_factors=", ".join(map(str, func_factors)),
+        flops_pair_fwd=float(flops_pair_fwd), flops_pair_bwd=float(flops_pair_bwd),
+        flops_atom=float(ops_c))
+    meta = s.metadata()
+    meta.update({"flops_pair_fwd": flops_pair_fwd, "flops_pair_bwd": flops_pair_bwd,
+                 "flops_atom_contraction": ops_c, "flops_counted_for_nq": nq})
+    return src, meta
+
+
+LEVELS = (2, 4, 6, 8, 10, 12, 14, 16)
+
+
+def write_all(outdir, levels=LEVELS):
+    os.makedirs(outdir, exist_ok=True)
+    metas = {}
+    files = []
+    for L in levels:
+        src, meta = generate(L)
+        path = os.path.join(outdir, f"gen_lev{L}.hip")
+        old = open(path).read() if os.path.exists(path) else None
+        if old != src:
+            with open(path, "w") as fh:
+                fh.write(src)
+        files.append(path)
+        metas[f"lev{L}"] = meta
+    reg = ["// Generated: the table of compiled bases.", '#include "mtp_variant.h"', ""]
+    reg += [f"extern const mtp::BasisVariant lev{L}_variant;" for L in levels]
+    reg += ["", "namespace mtp {", "const BasisVariant* const kVariants[] = {"]
+    reg += [f"  &lev{L}_variant," for L in levels]
+    reg += ["};", f"const int kNumVariants = {len(levels)};", "}  // namespace mtp", ""]
+    reg_src = "\n".join(reg)
+    reg_path = os.path.join(outdir, "variants.cpp")
+    if not os.path.exists(reg_path) or open(reg_path).read() != reg_src:
+        with open(reg_path, "w") as fh:
+            fh.write(reg_src)
+    files.append(reg_path)
+    with open(os.path.join(outdir, "variants.json"), "w") as fh:
+        json.dump(metas, fh, indent=1)
+    return files, metas

@@ -1,0 +1,154 @@
+// FP64 dense kernels of the extrapolation grade (paper, section 2.3):
+// the active-set inverse A^{-1} and c = b A^{-1}, gamma = max_j |c_j|,
+// argmax_j |c_j| (lowest index on ties).
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include "mtp_internal.h"
+
+namespace mtp {
+namespace {
+
+constexpr int kGJBlock = 1024;
+
+// Gauss-Jordan elimination with partial pivoting on [A | I] (row-major,
+// m x 2m) in one workgroup; the right half ends as A^{-1}.  Columns of A
+// are equilibrated first (A D, then D (AD)^{-1} = A^{-1}).
+__global__ void __launch_bounds__(kGJBlock) gj_kernel(int m, double* W, double* inv, int* singular) {
+  __shared__ double s_val[kGJBlock];
+  __shared__ int s_idx[kGJBlock];
+  __shared__ double s_piv;
+  __shared__ int s_prow;
+  const int t = threadIdx.x;
+  const int n2 = 2 * m;
+  // column scales D = 1 / max |A_col|, stored in inv's first row as scratch
+  for (int col = t; col < m; col += blockDim.x) {
+    double mx = 0;
+    for (int r = 0; r < m; ++r) mx = fmax(mx, fabs(W[(size_t)r * n2 + col]));
+    const double d = mx > 0 ? 1.0 / mx : 1.0;
+    inv[col] = d;
+    for (int r = 0; r < m; ++r) W[(size_t)r * n2 + col] *= d;
+  }
+  __syncthreads();
+  if (t == 0) *singular = 0;
+  for (int k = 0; k < m; ++k) {
+    // pivot: largest |W[r][k]| for r >= k, lowest row on ties
+    double best = -1;
+    int bi = k;
+    for (int r = k + t; r < m; r += blockDim.x) {
+      const double v = fabs(W[(size_t)r * n2 + k]);
+      if (v > best) { best = v; bi = r; }
+    }
+    s_val[t] = best;
+    s_idx[t] = bi;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+      if (t < w) {
+        const double v = s_val[t + w];
+        const int ix = s_idx[t + w];
+        if (v > s_val[t] || (v == s_val[t] && ix < s_idx[t])) { s_val[t] = v; s_idx[t] = ix; }
+      }
+      __syncthreads();
+    }
+    if (t == 0) {
+      s_prow = s_idx[0];
+      if (!(s_val[0] > 1e-300)) *singular = 1;
+    }
+    __syncthreads();
+    const int pr = s_prow;
+    if (pr != k)
+      for (int col = t; col < n2; col += blockDim.x) {
+        const double a = W[(size_t)k * n2 + col];
+        W[(size_t)k * n2 + col] = W[(size_t)pr * n2 + col];
+        W[(size_t)pr * n2 + col] = a;
+      }
+    __syncthreads();
+    if (t == 0) s_piv = W[(size_t)k * n2 + k];
+    __syncthreads();
+    const double ip = 1.0 / s_piv;
+    for (int col = t; col < n2; col += blockDim.x) W[(size_t)k * n2 + col] *= ip;
+    __syncthreads();
+    // eliminate column k from every other row
+    for (int idx = t; idx < m * n2; idx += blockDim.x) {
+      const int r = idx / n2, col = idx % n2;
+      if (r == k || col == k) continue;
+      const double f = W[(size_t)r * n2 + k];
+      if (f != 0.0) W[(size_t)r * n2 + col] -= f * W[(size_t)k * n2 + col];
+    }
+    __syncthreads();
+    for (int r = t; r < m; r += blockDim.x)
+      if (r != k) W[(size_t)r * n2 + k] = 0.0;
+    __syncthreads();
+  }
+  // A^{-1} = D (AD)^{-1}: scale row r of the right half by D[r]
+  for (int idx = t; idx < m * m; idx += blockDim.x) {
+    const int r = idx / m, col = idx % m;
+    W[(size_t)r * n2 + m + col] *= inv[r];
+  }
+  __syncthreads();
+  for (int idx = t; idx < m * m; idx += blockDim.x) {
+    const int r = idx / m, col = idx % m;
+    inv[idx] = W[(size_t)r * n2 + m + col];
+  }
+}
+
+// c = b A^{-1} with 16 x 16 output tiles staged through LDS; then per row the
+// max |c| and its first index.
+constexpr int kT = 16;
+
+__global__ void __launch_bounds__(kT * kT) gemm_kernel(int n, int m, const double* __restrict__ b,
+                                                      const double* __restrict__ A, double* __restrict__ c) {
+  __shared__ double sb[kT][kT + 1];
+  __shared__ double sa[kT][kT + 1];
+  const int tx = threadIdx.x % kT, ty = threadIdx.x / kT;
+  const int row = blockIdx.y * kT + ty, col = blockIdx.x * kT + tx;
+  double acc = 0;
+  for (int k0 = 0; k0 < m; k0 += kT) {
+    sb[ty][tx] = (row < n && k0 + tx < m) ? b[(size_t)row * m + k0 + tx] : 0.0;
+    sa[ty][tx] = (k0 + ty < m && col < m) ? A[(size_t)(k0 + ty) * m + col] : 0.0;
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kT; ++k) acc = fma(sb[ty][k], sa[k][tx], acc);
+    __syncthreads();
+  }
+  if (row < n && col < m) c[(size_t)row * m + col] = acc;
+}
+
+__global__ void maxabs_kernel(int n, int m, const double* __restrict__ c, double* gamma, int32_t* arg) {
+  const int row = blockIdx.x * blockDim.y + threadIdx.y;
+  if (row >= n) return;
+  const int lane = threadIdx.x;  // 64 lanes per row
+  double best = -1;
+  int bi = 0;
+  for (int j = lane; j < m; j += 64) {
+    const double v = fabs(c[(size_t)row * m + j]);
+    if (v > best) { best = v; bi = j; }
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    const double ov = __shfl_down(best, off, 64);
+    const int oi = __shfl_down(bi, off, 64);
+    if (ov > best || (ov == best && oi < bi)) { best = ov; bi = oi; }
+  }
+  if (lane == 0) {
+    gamma[row] = best;
+    arg[row] = bi;
+  }
+}
+
+}  // namespace
+
+hipError_t gauss_jordan_inverse(int m, double* work, double* inv, int* singular, hipStream_t s) {
+  hipLaunchKernelGGL(gj_kernel, dim3(1), dim3(kGJBlock), 0, s, m, work, inv, singular);
+  return hipGetLastError();
+}
+
+hipError_t grade_rows(int n, int m, const double* b, const double* Ainv, double* gamma, int32_t* argmax,
+                      double* c, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  const dim3 g((m + kT - 1) / kT, (n + kT - 1) / kT);
+  hipLaunchKernelGGL(gemm_kernel, g, dim3(kT * kT), 0, s, n, m, b, Ainv, c);
+  hipLaunchKernelGGL(maxabs_kernel, dim3((n + 3) / 4), dim3(64, 4), 0, s, n, m, c, gamma, argmax);
+  return hipGetLastError();
+}
+
+}  // namespace mtp

@@ -1,0 +1,561 @@
+// libmtp entry points (include/mtp.h): potential loading and basis matching,
+// workspace management and the evaluation / grade pipelines.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <sstream>
+#include <string>
+#include <type_traits>
+#include <vector>
+
+#include "mtp.h"
+#include "mtp_device.h"
+#include "mtp_internal.h"
+#include "mtp_variant.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+  return fail(MTP_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_TRY(expr, what)                  \
+  do {                                       \
+    hipError_t e_ = (expr);                  \
+    if (e_ != hipSuccess) return hip_fail(e_, what); \
+  } while (0)
+
+struct Buffer {
+  void* p = nullptr;
+  size_t bytes = 0;
+  ~Buffer() {
+    if (p) (void)hipFree(p);
+  }
+  hipError_t ensure(size_t n) {
+    if (n <= bytes && p) return hipSuccess;
+    if (p) {
+      hipError_t e = hipFree(p);
+      p = nullptr;
+      bytes = 0;
+      if (e != hipSuccess) return e;
+    }
+    size_t want = n < 256 ? 256 : n;
+    hipError_t e = hipMalloc(&p, want);
+    if (e == hipSuccess) bytes = want;
+    return e;
+  }
+  template <typename T>
+  T* as() const {
+    return static_cast<T*>(p);
+  }
+};
+
+// Canonical key of a contraction graph: the lexicographically smallest
+// (mu_0, nu_0, ..., mu_{n-1}, nu_{n-1}, k_01, k_02, ..., k_{n-2,n-1}) over
+// all vertex orders (the same rule the kernel generator uses).
+std::vector<int> canonical_key(const std::vector<std::pair<int, int>>& labels,
+                               const std::vector<std::vector<int>>& adj) {
+  const int n = (int)labels.size();
+  std::vector<int> perm(n);
+  for (int v = 0; v < n; ++v) perm[v] = v;
+  std::vector<int> best;
+  do {
+    std::vector<int> key;
+    for (int v : perm) {
+      key.push_back(labels[v].first);
+      key.push_back(labels[v].second);
+    }
+    for (int a = 0; a < n; ++a)
+      for (int b = a + 1; b < n; ++b) key.push_back(adj[perm[a]][perm[b]]);
+    if (best.empty() || key < best) best = key;
+  } while (std::next_permutation(perm.begin(), perm.end()));
+  return best;
+}
+
+}  // namespace
+
+struct mtp_model {
+  int device = 0;
+  int level = 0, S = 0, nq = 0, n_mu = 0, m = 0, n_c = 0;
+  double rmin = 0, rcut = 0;
+  const mtp::BasisVariant* var = nullptr;
+  std::vector<int> perm;      // file basis index -> kernel basis index
+  std::vector<double> c, xi;  // file order
+  Buffer c64, c32, xi64, xi32, perm_dev;
+  // active set
+  bool has_active = false;
+  Buffer ainv, gj_work, gj_flag;
+  // workspace
+  Buffer cfg, atom_cfg, atom_bin, bin_count, bin_start, bin_atoms, bin_fill, nbins_dev;
+  Buffer count, nbr, nbr_z, px, py, pz, rev, gx, gy, gz, site, wv, B, status;
+  Buffer b_tmp, c_tmp;
+};
+
+namespace {
+
+int upload_params(mtp_model* M) {
+  std::vector<double> xk(M->m);
+  for (int f = 0; f < M->m; ++f) xk[M->perm[f]] = M->xi[f];
+  std::vector<float> c32(M->c.begin(), M->c.end()), x32(xk.begin(), xk.end());
+  HIP_TRY(M->c64.ensure(sizeof(double) * M->n_c), "hipMalloc");
+  HIP_TRY(M->c32.ensure(sizeof(float) * M->n_c), "hipMalloc");
+  HIP_TRY(M->xi64.ensure(sizeof(double) * M->m), "hipMalloc");
+  HIP_TRY(M->xi32.ensure(sizeof(float) * M->m), "hipMalloc");
+  HIP_TRY(hipMemcpy(M->c64.p, M->c.data(), sizeof(double) * M->n_c, hipMemcpyHostToDevice), "hipMemcpy");
+  HIP_TRY(hipMemcpy(M->c32.p, c32.data(), sizeof(float) * M->n_c, hipMemcpyHostToDevice), "hipMemcpy");
+  HIP_TRY(hipMemcpy(M->xi64.p, xk.data(), sizeof(double) * M->m, hipMemcpyHostToDevice), "hipMemcpy");
+  HIP_TRY(hipMemcpy(M->xi32.p, x32.data(), sizeof(float) * M->m, hipMemcpyHostToDevice), "hipMemcpy");
+  return MTP_OK;
+}
+
+int parse_and_match(const char* path, mtp_model* M) {
+  std::ifstream in(path);
+  if (!in) return fail(MTP_E_FILE, std::string("cannot open ") + path);
+  std::vector<std::string> tok;
+  std::string line;
+  while (std::getline(in, line)) {
+    size_t p = line.find_first_not_of(" \t\r");
+    if (p != std::string::npos && line[p] == '#') continue;
+    std::istringstream ls(line);
+    std::string t;
+    while (ls >> t) tok.push_back(t);
+  }
+  size_t pos = 0;
+  auto next = [&](std::string& out) -> bool {
+    if (pos >= tok.size()) return false;
+    out = tok[pos++];
+    return true;
+  };
+  auto expect = [&](const char* w) -> bool {
+    std::string t;
+    return next(t) && t == w;
+  };
+  auto num_i = [&](long long& v, long long lo, long long hi) -> bool {
+    std::string t;
+    if (!next(t)) return false;
+    char* end = nullptr;
+    v = std::strtoll(t.c_str(), &end, 10);
+    return end && *end == 0 && v >= lo && v <= hi;
+  };
+  auto num_d = [&](double& v) -> bool {
+    std::string t;
+    if (!next(t)) return false;
+    char* end = nullptr;
+    v = std::strtod(t.c_str(), &end);
+    return end && *end == 0 && std::isfinite(v);
+  };
+  const std::string where = std::string(path) + ": ";
+  long long v = 0;
+  if (!expect("mtp355") || !num_i(v, 1, 1)) return fail(MTP_E_FILE, where + "not an mtp355 version 1 file");
+  if (!expect("level") || !num_i(v, 0, 1000)) return fail(MTP_E_FILE, where + "bad level");
+  M->level = (int)v;
+  if (!expect("species_count") || !num_i(v, 1, 64)) return fail(MTP_E_FILE, where + "bad species_count");
+  M->S = (int)v;
+  if (!expect("radial_basis_size") || !num_i(v, 1, 64)) return fail(MTP_E_FILE, where + "bad radial_basis_size");
+  M->nq = (int)v;
+  if (!expect("min_dist") || !num_d(M->rmin)) return fail(MTP_E_FILE, where + "bad min_dist");
+  if (!expect("max_dist") || !num_d(M->rcut)) return fail(MTP_E_FILE, where + "bad max_dist");
+  if (!(M->rcut > M->rmin) || !(M->rmin >= 0)) return fail(MTP_E_FILE, where + "need 0 <= min_dist < max_dist");
+  if (!expect("moments") || !num_i(v, 1, 100000)) return fail(MTP_E_FILE, where + "bad moments");
+  std::vector<std::pair<int, int>> moments((size_t)v);
+  int n_mu = 0;
+  for (auto& mo : moments) {
+    long long a, b;
+    if (!num_i(a, 0, 1000) || !num_i(b, 0, 1000)) return fail(MTP_E_FILE, where + "bad moment");
+    mo = {(int)a, (int)b};
+    n_mu = std::max(n_mu, (int)a + 1);
+  }
+  if (!expect("contractions") || !num_i(v, 1, 1000000)) return fail(MTP_E_FILE, where + "bad contractions");
+  std::vector<std::vector<int>> gkeys((size_t)v);
+  for (auto& key : gkeys) {
+    long long nv, ne;
+    if (!num_i(nv, 1, 8)) return fail(MTP_E_FILE, where + "bad contraction size (1..8 vertices)");
+    std::vector<std::pair<int, int>> labels((size_t)nv);
+    for (auto& l : labels) {
+      long long mi;
+      if (!num_i(mi, 0, (long long)moments.size() - 1)) return fail(MTP_E_FILE, where + "bad moment index");
+      l = moments[(size_t)mi];
+    }
+    if (!num_i(ne, 0, 64)) return fail(MTP_E_FILE, where + "bad edge count");
+    std::vector<std::vector<int>> adj(nv, std::vector<int>(nv, 0));
+    std::vector<int> deg(nv, 0);
+    for (long long e = 0; e < ne; ++e) {
+      long long a, b, k;
+      if (!num_i(a, 0, nv - 1) || !num_i(b, 0, nv - 1) || !num_i(k, 1, 64) || a == b)
+        return fail(MTP_E_FILE, where + "bad edge");
+      adj[a][b] += (int)k;
+      adj[b][a] += (int)k;
+      deg[a] += (int)k;
+      deg[b] += (int)k;
+    }
+    for (int x = 0; x < nv; ++x)
+      if (deg[x] != labels[x].second) return fail(MTP_E_FILE, where + "vertex degree differs from its rank");
+    key = canonical_key(labels, adj);
+  }
+  if (!expect("basis") || !num_i(v, 1, 10000000)) return fail(MTP_E_FILE, where + "bad basis");
+  std::vector<std::vector<int>> funcs((size_t)v);
+  for (auto& f : funcs) {
+    long long nf;
+    if (!num_i(nf, 1, 64)) return fail(MTP_E_FILE, where + "bad basis function");
+    f.resize((size_t)nf);
+    for (auto& g : f) {
+      long long gi;
+      if (!num_i(gi, 0, (long long)gkeys.size() - 1)) return fail(MTP_E_FILE, where + "bad contraction index");
+      g = (int)gi;
+    }
+  }
+  M->n_mu = n_mu;
+  M->m = (int)funcs.size();
+  M->n_c = n_mu * M->S * M->S * M->nq;
+  if (!expect("radial_coeffs") || !num_i(v, 0, 100000000) || v != M->n_c)
+    return fail(MTP_E_FILE, where + "radial_coeffs count must be n_mu * S * S * N_Q");
+  M->c.resize(M->n_c);
+  for (auto& x : M->c)
+    if (!num_d(x)) return fail(MTP_E_FILE, where + "bad radial coefficient");
+  if (!expect("xi") || !num_i(v, 0, 100000000) || v != M->m)
+    return fail(MTP_E_FILE, where + "xi count must equal the basis size");
+  M->xi.resize(M->m);
+  for (auto& x : M->xi)
+    if (!num_d(x)) return fail(MTP_E_FILE, where + "bad xi");
+
+  // match against the compiled bases
+  for (int vi = 0; vi < mtp::kNumVariants; ++vi) {
+    const mtp::BasisVariant* V = mtp::kVariants[vi];
+    if (V->n_graphs != (int)gkeys.size() || V->m != M->m || V->n_mu != n_mu) continue;
+    std::map<std::vector<int>, int> vkey;
+    for (int g = 0; g < V->n_graphs; ++g)
+      vkey[std::vector<int>(V->graph_keys + V->graph_key_offsets[g], V->graph_keys + V->graph_key_offsets[g + 1])] = g;
+    std::vector<int> gmap(gkeys.size(), -1);
+    bool ok = true;
+    std::vector<char> used(V->n_graphs, 0);
+    for (size_t g = 0; g < gkeys.size() && ok; ++g) {
+      auto it = vkey.find(gkeys[g]);
+      if (it == vkey.end() || used[it->second]) ok = false;
+      else {
+        gmap[g] = it->second;
+        used[it->second] = 1;
+      }
+    }
+    if (!ok) continue;
+    std::map<std::vector<int>, int> vfunc;
+    for (int f = 0; f < V->m; ++f)
+      vfunc[std::vector<int>(V->func_factors + V->func_offsets[f], V->func_factors + V->func_offsets[f + 1])] = f;
+    std::vector<int> perm(M->m, -1);
+    std::vector<char> fused(V->m, 0);
+    for (int f = 0; f < M->m && ok; ++f) {
+      std::vector<int> t;
+      for (int g : funcs[f]) t.push_back(gmap[g]);
+      std::sort(t.begin(), t.end());
+      auto it = vfunc.find(t);
+      if (it == vfunc.end() || fused[it->second]) ok = false;
+      else {
+        perm[f] = it->second;
+        fused[it->second] = 1;
+      }
+    }
+    if (!ok) continue;
+    M->var = V;
+    M->perm = perm;
+    return MTP_OK;
+  }
+  return fail(MTP_E_BASIS, where + "basis (" + std::to_string(M->m) + " functions, " +
+                               std::to_string(gkeys.size()) + " contractions) is not compiled into libmtp");
+}
+
+template <typename T>
+mtp::EvalArgs<T> make_args(mtp_model* M, int64_t n_atoms, int stride, const int32_t* species, bool want_b) {
+  mtp::EvalArgs<T> a;
+  a.n_atoms = (int)n_atoms;
+  a.stride = stride;
+  a.nq = M->nq;
+  a.n_species = M->S;
+  a.n_c = M->n_c;
+  a.rmin = (T)M->rmin;
+  a.rcut = (T)M->rcut;
+  a.nbr_count = M->count.as<int>();
+  a.px = M->px.as<T>();
+  a.py = M->py.as<T>();
+  a.pz = M->pz.as<T>();
+  a.pzj = M->nbr_z.as<int>();
+  a.species = species;
+  a.c = std::is_same<T, double>::value ? (const T*)M->c64.p : (const T*)M->c32.p;
+  a.xi = std::is_same<T, double>::value ? (const T*)M->xi64.p : (const T*)M->xi32.p;
+  a.site = M->site.as<T>();
+  a.gx = M->gx.as<T>();
+  a.gy = M->gy.as<T>();
+  a.gz = M->gz.as<T>();
+  a.atom_virial = M->wv.as<T>();
+  a.B = want_b ? M->B.as<T>() : nullptr;
+  a.b_stride = stride;
+  return a;
+}
+
+// Neighbour search, evaluation kernel, force gather and reductions.
+int run_eval(mtp_model* M, const mtp_batch* bt, const mtp_out* out, int precision, hipStream_t s) {
+  using namespace mtp;
+  const int64_t N = bt->n_atoms;
+  const int n_cfg = bt->n_configs;
+  const bool fp64 = precision == MTP_FP64;
+  const size_t tsz = fp64 ? sizeof(double) : sizeof(float);
+  HIP_TRY(M->status.ensure(sizeof(Status)), "hipMalloc");
+  HIP_TRY(hipMemsetAsync(M->status.p, 0, sizeof(Status), s), "hipMemsetAsync");
+  if (n_cfg == 0) return MTP_OK;
+  HIP_TRY(M->cfg.ensure(sizeof(CfgInfo) * n_cfg), "hipMalloc");
+  HIP_TRY(M->atom_cfg.ensure(sizeof(int32_t) * (N + 1)), "hipMalloc");
+  HIP_TRY(M->nbins_dev.ensure(sizeof(int64_t) * 2), "hipMalloc");
+  NbrArgs a{};
+  a.n_cfg = n_cfg;
+  a.n_atoms = N;
+  a.atom_offsets = bt->atom_offsets;
+  a.pos = bt->pos;
+  a.species = bt->species;
+  a.cell = bt->cell;
+  a.pbc = bt->pbc;
+  a.rcut = M->rcut;
+  a.rmin = M->rmin;
+  a.cfg = M->cfg.as<CfgInfo>();
+  a.atom_cfg = M->atom_cfg.as<int32_t>();
+  a.status = M->status.as<Status>();
+  a.fp64 = fp64 ? 1 : 0;
+  a.n_species = M->S;
+  if (N > 0x7fffffffLL / 4) return fail(MTP_E_CAPACITY, "too many atoms in one batch");
+  HIP_TRY(nbr_prepare(a, s), "neighbour prepare");
+  HIP_TRY(nbr_bin_offsets(a, M->nbins_dev.as<int64_t>(), s), "bin offsets");
+  int64_t n_bins = 0;
+  HIP_TRY(hipMemcpyAsync(&n_bins, M->nbins_dev.p, sizeof(int64_t), hipMemcpyDeviceToHost, s), "hipMemcpyAsync");
+  HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
+  a.n_bins = n_bins;
+  {
+    Status st0{};
+    HIP_TRY(hipMemcpyAsync(&st0, M->status.p, sizeof(Status), hipMemcpyDeviceToHost, s), "hipMemcpyAsync");
+    HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
+    if (st0.bad_offsets) return fail(MTP_E_ARG, "atom_offsets must be non-decreasing from 0 to n_atoms");
+  }
+  HIP_TRY(M->atom_bin.ensure(sizeof(int32_t) * (N + 1)), "hipMalloc");
+  HIP_TRY(M->bin_count.ensure(sizeof(int32_t) * (n_bins + 1)), "hipMalloc");
+  HIP_TRY(M->bin_start.ensure(sizeof(int32_t) * (n_bins + 1)), "hipMalloc");
+  HIP_TRY(M->bin_fill.ensure(sizeof(int32_t) * (n_bins + 1)), "hipMalloc");
+  HIP_TRY(M->bin_atoms.ensure(sizeof(int32_t) * (N + 1)), "hipMalloc");
+  HIP_TRY(M->count.ensure(sizeof(int32_t) * (N + 1)), "hipMalloc");
+  a.atom_bin = M->atom_bin.as<int32_t>();
+  a.bin_count = M->bin_count.as<int32_t>();
+  a.bin_start = M->bin_start.as<int32_t>();
+  a.bin_fill = M->bin_fill.as<int32_t>();
+  a.bin_atoms = M->bin_atoms.as<int32_t>();
+  a.count = M->count.as<int32_t>();
+  HIP_TRY(nbr_bin(a, s), "binning");
+  HIP_TRY(nbr_count(a, s), "neighbour count");
+  Status st{};
+  HIP_TRY(hipMemcpyAsync(&st, M->status.p, sizeof(Status), hipMemcpyDeviceToHost, s), "hipMemcpyAsync");
+  HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
+  if (st.bad_species) return fail(MTP_E_ARG, "species index outside [0, species_count)");
+  const int K = (int)std::max<unsigned long long>(1, st.max_count);
+  const int stride = (int)((N + 63) / 64 * 64);
+  const size_t slots = (size_t)K * stride;
+  a.K = K;
+  a.stride = stride;
+  HIP_TRY(M->nbr.ensure(sizeof(int32_t) * slots), "hipMalloc");
+  HIP_TRY(M->nbr_z.ensure(sizeof(int32_t) * slots), "hipMalloc");
+  HIP_TRY(M->rev.ensure(sizeof(int32_t) * slots), "hipMalloc");
+  HIP_TRY(M->px.ensure(tsz * slots), "hipMalloc");
+  HIP_TRY(M->py.ensure(tsz * slots), "hipMalloc");
+  HIP_TRY(M->pz.ensure(tsz * slots), "hipMalloc");
+  HIP_TRY(M->gx.ensure(tsz * slots), "hipMalloc");
+  HIP_TRY(M->gy.ensure(tsz * slots), "hipMalloc");
+  HIP_TRY(M->gz.ensure(tsz * slots), "hipMalloc");
+  HIP_TRY(M->site.ensure(tsz * stride), "hipMalloc");
+  HIP_TRY(M->wv.ensure(tsz * 9 * stride), "hipMalloc");
+  const bool want_b = out->b != nullptr;
+  if (want_b) HIP_TRY(M->B.ensure(tsz * (size_t)M->m * stride), "hipMalloc");
+  a.nbr = M->nbr.as<int32_t>();
+  a.nbr_z = M->nbr_z.as<int32_t>();
+  a.px = M->px.p;
+  a.py = M->py.p;
+  a.pz = M->pz.p;
+  a.rev = M->rev.as<int32_t>();
+  HIP_TRY(nbr_fill(a, s), "neighbour fill");
+  if (fp64) {
+    auto ea = make_args<double>(M, N, stride, bt->species, want_b);
+    HIP_TRY(M->var->launch_eval(precision, want_b, &ea, s), "evaluation kernel");
+  } else {
+    auto ea = make_args<float>(M, N, stride, bt->species, want_b);
+    HIP_TRY(M->var->launch_eval(precision, want_b, &ea, s), "evaluation kernel");
+  }
+  if (out->forces)
+    HIP_TRY(gather_forces(fp64, N, stride, M->count.as<int32_t>(), M->rev.as<int32_t>(), M->gx.p, M->gy.p,
+                          M->gz.p, out->forces, s),
+            "force gather");
+  HIP_TRY(M->perm_dev.ensure(sizeof(int32_t) * M->m), "hipMalloc");
+  HIP_TRY(hipMemcpyAsync(M->perm_dev.p, M->perm.data(), sizeof(int32_t) * M->m, hipMemcpyHostToDevice, s),
+          "hipMemcpyAsync");
+  HIP_TRY(reduce_configs(fp64, n_cfg, bt->atom_offsets, stride, M->site.p, M->wv.p, want_b ? M->B.p : nullptr,
+                         M->m, stride, M->perm_dev.as<int32_t>(), out->energy, out->virial, out->b,
+                         out->site_energy, s),
+          "reductions");
+  return MTP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* mtp_last_error(void) { return g_err.c_str(); }
+
+int mtp_load(const char* path, int device, mtp_model** out) {
+  g_err.clear();
+  if (!path || !out) return fail(MTP_E_ARG, "mtp_load: null argument");
+  *out = nullptr;
+  int ndev = 0;
+  HIP_TRY(hipGetDeviceCount(&ndev), "hipGetDeviceCount");
+  if (device < 0 || device >= ndev) return fail(MTP_E_ARG, "mtp_load: no such HIP device");
+  HIP_TRY(hipSetDevice(device), "hipSetDevice");
+  mtp_model* M = new mtp_model();
+  M->device = device;
+  int rc = parse_and_match(path, M);
+  if (rc == MTP_OK) rc = upload_params(M);
+  if (rc != MTP_OK) {
+    delete M;
+    return rc;
+  }
+  *out = M;
+  return MTP_OK;
+}
+
+int mtp_model_info(const mtp_model* M, mtp_info* info) {
+  if (!M || !info) return fail(MTP_E_ARG, "mtp_model_info: null argument");
+  info->level = M->level;
+  info->m = M->m;
+  info->n_mu = M->n_mu;
+  info->n_species = M->S;
+  info->n_q = M->nq;
+  info->n_c = M->n_c;
+  info->r_min = M->rmin;
+  info->r_cut = M->rcut;
+  return MTP_OK;
+}
+
+int mtp_set_params(mtp_model* M, const double* c_host, const double* xi_host) {
+  if (!M) return fail(MTP_E_ARG, "mtp_set_params: null model");
+  if (c_host) std::copy(c_host, c_host + M->n_c, M->c.begin());
+  if (xi_host) std::copy(xi_host, xi_host + M->m, M->xi.begin());
+  HIP_TRY(hipSetDevice(M->device), "hipSetDevice");
+  HIP_TRY(hipDeviceSynchronize(), "hipDeviceSynchronize");
+  return upload_params(M);
+}
+
+int mtp_get_params(const mtp_model* M, double* c_host, double* xi_host) {
+  if (!M) return fail(MTP_E_ARG, "mtp_get_params: null model");
+  if (c_host) std::copy(M->c.begin(), M->c.end(), c_host);
+  if (xi_host) std::copy(M->xi.begin(), M->xi.end(), xi_host);
+  return MTP_OK;
+}
+
+int mtp_eval(mtp_model* M, const mtp_batch* bt, const mtp_out* out, int precision, void* stream) {
+  g_err.clear();
+  if (!M || !bt || !out) return fail(MTP_E_ARG, "mtp_eval: null argument");
+  if (precision < MTP_FP64 || precision > MTP_FP32_COMPENSATED) return fail(MTP_E_ARG, "mtp_eval: bad precision");
+  if (bt->n_configs < 0 || bt->n_atoms < 0) return fail(MTP_E_ARG, "mtp_eval: negative size");
+  if (bt->n_configs > 0 && (!bt->atom_offsets || !bt->cell || !bt->pbc))
+    return fail(MTP_E_ARG, "mtp_eval: null batch array");
+  if (bt->n_atoms > 0 && (!bt->pos || !bt->species)) return fail(MTP_E_ARG, "mtp_eval: null batch array");
+  HIP_TRY(hipSetDevice(M->device), "hipSetDevice");
+  return run_eval(M, bt, out, precision, (hipStream_t)stream);
+}
+
+int mtp_set_active_set(mtp_model* M, const double* A_dev, void* stream) {
+  g_err.clear();
+  if (!M || !A_dev) return fail(MTP_E_ARG, "mtp_set_active_set: null argument");
+  HIP_TRY(hipSetDevice(M->device), "hipSetDevice");
+  hipStream_t s = (hipStream_t)stream;
+  const int m = M->m;
+  // [A | I] in file column order; b rows handed to the grade are in file order too
+  std::vector<double> A((size_t)m * m), W((size_t)m * 2 * m, 0.0);
+  HIP_TRY(hipMemcpyAsync(A.data(), A_dev, sizeof(double) * m * m, hipMemcpyDeviceToHost, s), "hipMemcpyAsync");
+  HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
+  for (int r = 0; r < m; ++r) {
+    std::copy(A.begin() + (size_t)r * m, A.begin() + (size_t)(r + 1) * m, W.begin() + (size_t)r * 2 * m);
+    W[(size_t)r * 2 * m + m + r] = 1.0;
+  }
+  HIP_TRY(M->gj_work.ensure(sizeof(double) * W.size()), "hipMalloc");
+  HIP_TRY(M->ainv.ensure(sizeof(double) * (size_t)m * m), "hipMalloc");
+  HIP_TRY(M->gj_flag.ensure(sizeof(int)), "hipMalloc");
+  HIP_TRY(hipMemcpyAsync(M->gj_work.p, W.data(), sizeof(double) * W.size(), hipMemcpyHostToDevice, s),
+          "hipMemcpyAsync");
+  HIP_TRY(mtp::gauss_jordan_inverse(m, M->gj_work.as<double>(), M->ainv.as<double>(), M->gj_flag.as<int>(), s),
+          "Gauss-Jordan");
+  int singular = 0;
+  HIP_TRY(hipMemcpyAsync(&singular, M->gj_flag.p, sizeof(int), hipMemcpyDeviceToHost, s), "hipMemcpyAsync");
+  HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
+  if (singular) {
+    M->has_active = false;
+    return fail(MTP_E_ARG, "mtp_set_active_set: A is numerically singular");
+  }
+  M->has_active = true;
+  return MTP_OK;
+}
+
+int mtp_grade_from_b(mtp_model* M, int32_t n, const double* b_dev, double* gamma_dev, int32_t* argmax_dev,
+                     double* c_dev, void* stream) {
+  g_err.clear();
+  if (!M || n < 0 || (n > 0 && (!b_dev || !gamma_dev || !argmax_dev)))
+    return fail(MTP_E_ARG, "mtp_grade_from_b: bad argument");
+  if (!M->has_active) return fail(MTP_E_STATE, "mtp_grade_from_b: no active set (call mtp_set_active_set)");
+  HIP_TRY(hipSetDevice(M->device), "hipSetDevice");
+  hipStream_t s = (hipStream_t)stream;
+  double* c = c_dev;
+  if (!c) {
+    HIP_TRY(M->c_tmp.ensure(sizeof(double) * (size_t)n * M->m), "hipMalloc");
+    c = M->c_tmp.as<double>();
+  }
+  HIP_TRY(mtp::grade_rows(n, M->m, b_dev, M->ainv.as<double>(), gamma_dev, argmax_dev, c, s), "grade");
+  return MTP_OK;
+}
+
+int mtp_grade(mtp_model* M, const mtp_batch* bt, double* gamma_dev, int32_t* argmax_dev, int precision,
+              void* stream) {
+  g_err.clear();
+  if (!M || !bt || !gamma_dev || !argmax_dev) return fail(MTP_E_ARG, "mtp_grade: null argument");
+  if (!M->has_active) return fail(MTP_E_STATE, "mtp_grade: no active set (call mtp_set_active_set)");
+  HIP_TRY(hipSetDevice(M->device), "hipSetDevice");
+  HIP_TRY(M->b_tmp.ensure(sizeof(double) * (size_t)std::max(1, bt->n_configs) * M->m), "hipMalloc");
+  mtp_out o{};
+  o.b = M->b_tmp.as<double>();
+  int rc = mtp_eval(M, bt, &o, precision, stream);
+  if (rc != MTP_OK) return rc;
+  return mtp_grade_from_b(M, bt->n_configs, o.b, gamma_dev, argmax_dev, nullptr, stream);
+}
+
+int mtp_status(mtp_model* M, void* stream, int64_t* n_below_rmin, int64_t* n_list_errors) {
+  if (!M) return fail(MTP_E_ARG, "mtp_status: null model");
+  HIP_TRY(hipSetDevice(M->device), "hipSetDevice");
+  mtp::Status st{};
+  if (M->status.p) {
+    HIP_TRY(hipMemcpyAsync(&st, M->status.p, sizeof(st), hipMemcpyDeviceToHost, (hipStream_t)stream),
+            "hipMemcpyAsync");
+    HIP_TRY(hipStreamSynchronize((hipStream_t)stream), "hipStreamSynchronize");
+  }
+  if (n_below_rmin) *n_below_rmin = (int64_t)st.below_rmin;
+  if (n_list_errors) *n_list_errors = (int64_t)st.list_errors;
+  return MTP_OK;
+}
+
+void mtp_free(mtp_model* M) {
+  if (!M) return;
+  (void)hipSetDevice(M->device);
+  (void)hipDeviceSynchronize();
+  delete M;
+}
+
+}  // extern "C"

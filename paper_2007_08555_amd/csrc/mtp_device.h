@@ -1,0 +1,94 @@
+// Device-side pieces shared by the generated MTP evaluation kernels.
+//
+// Radial part, paper section 2.1, eqs. f_mu and radial-basis:
+//   Q^(beta)(r) = T_{beta-1}(x) (R_cut - r)^2 for r < R_cut,
+//   x = (2 r - R_min - R_cut) / (R_cut - R_min),
+//   f_mu(r, z_i, z_j) = sum_beta c[mu][z_i][z_j][beta] Q^(beta)(r).
+// Pairs handed to a kernel are always inside the cutoff (strict r < R_cut).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mtp {
+
+// Arguments of one evaluation launch.  Pair data uses an ELL layout: slot p of
+// atom i lives at p * stride + i, so a wavefront of consecutive atoms reads and
+// writes consecutive addresses for the same slot.
+template <typename T>
+struct EvalArgs {
+  int n_atoms;
+  int stride;          // >= n_atoms, row pitch of the ELL arrays
+  int nq;              // radial basis size N_Q
+  int n_species;       // S
+  int n_c;             // n_mu * S * S * N_Q
+  T rmin, rcut;
+  const int* nbr_count;  // [n_atoms]
+  const T* px;           // [K * stride] pair vectors r_ij = x_j + n.L - x_i
+  const T* py;
+  const T* pz;
+  const int* pzj;        // [K * stride] species of the neighbour
+  const int* species;    // [n_atoms]
+  const T* c;            // [n_mu][S][S][N_Q]
+  const T* xi;           // [m] in the kernel's basis order
+  T* site;               // [n_atoms]   site energies V_i
+  T* gx;                 // [K * stride] dV_i / dr_ij
+  T* gy;
+  T* gz;
+  T* atom_virial;        // [9][n_atoms]  sum_j g_a r_b
+  T* B;                  // [m][b_stride] optional basis values
+  int b_stride;
+};
+
+// f_mu and, when DERIV, df_mu/dr for the NMU radial functions of one pair.
+// cs points at c staged in LDS; base = ((0 * S + zi) * S + zj) * nq and the
+// stride between consecutive mu is S * S * nq.
+template <typename T, int NMU, bool DERIV>
+__device__ __forceinline__ void radial(const T* __restrict__ cs, int base, int mu_stride, int nq,
+                                       T r, T rmin, T rcut, T (&f)[NMU], T (&df)[NMU]) {
+  const T span_inv = T(1) / (rcut - rmin);
+  const T x = (T(2) * r - rmin - rcut) * span_inv;
+  const T dxdr = T(2) * span_inv;
+  const T s = rcut - r;
+  T acc[NMU], dacc[NMU];
+#pragma unroll
+  for (int mu = 0; mu < NMU; ++mu) {
+    acc[mu] = cs[base + mu * mu_stride];          // T_0 = 1
+    dacc[mu] = T(0);
+  }
+  T t_prev = T(1), t_cur = x;                     // T_0, T_1
+  T d_prev = T(0), d_cur = T(1);                  // dT_0/dx, dT_1/dx
+  for (int b = 1; b < nq; ++b) {
+#pragma unroll
+    for (int mu = 0; mu < NMU; ++mu) {
+      const T cb = cs[base + mu * mu_stride + b];
+      acc[mu] = fma(cb, t_cur, acc[mu]);
+      if (DERIV) dacc[mu] = fma(cb, d_cur, dacc[mu]);
+    }
+    const T t_next = T(2) * x * t_cur - t_prev;
+    if (DERIV) {
+      const T d_next = T(2) * t_cur + T(2) * x * d_cur - d_prev;
+      d_prev = d_cur;
+      d_cur = d_next;
+    }
+    t_prev = t_cur;
+    t_cur = t_next;
+  }
+  const T s2 = s * s;
+#pragma unroll
+  for (int mu = 0; mu < NMU; ++mu) {
+    f[mu] = acc[mu] * s2;
+    if (DERIV) df[mu] = dacc[mu] * dxdr * s2 - T(2) * s * acc[mu];
+  }
+}
+
+// Error-free sum (Knuth's TwoSum): hi + lo carries the accumulated sum.
+template <typename T>
+__device__ __forceinline__ void two_sum_acc(T& hi, T& lo, T v) {
+  const T s = hi + v;
+  const T bp = s - hi;
+  const T err = (hi - (s - bp)) + (v - bp);
+  hi = s;
+  lo += err;
+}
+
+}  // namespace mtp

@@ -1,0 +1,87 @@
+// Host-side declarations shared by the library's translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mtp {
+
+// Per-configuration geometry prepared on the device before the neighbour search.
+struct CfgInfo {
+  double L[9];      // lattice vectors as rows
+  double inv[9];    // inverse of L (fractional = x . inv)
+  double w[3];      // R_cut / interplanar spacing of each lattice plane family
+  int64_t start;    // first atom
+  int32_t n;        // atoms
+  int32_t pbc;      // 1 periodic, 0 cluster
+  int32_t binned;   // 1 if the cell-list search is used
+  int32_t nb[3];    // bins per axis (binned configs)
+  int64_t bin0;     // first bin of this config in the global bin arrays
+};
+
+// Device counters read by mtp_status.
+struct Status {
+  unsigned long long below_rmin;
+  unsigned long long list_errors;
+  unsigned long long max_count;   // largest neighbour count of the last search
+  unsigned long long bad_offsets; // atom_offsets not monotone from 0 to n_atoms
+  unsigned long long bad_species; // species index outside [0, n_species)
+};
+
+struct NbrArgs {
+  int n_cfg;
+  int64_t n_atoms;
+  const int64_t* atom_offsets;
+  const double* pos;
+  const int32_t* species;
+  const double* cell;
+  const uint8_t* pbc;
+  double rcut, rmin;
+  int n_species;
+  CfgInfo* cfg;          // [n_cfg]
+  int32_t* atom_cfg;     // [n_atoms]
+  int32_t* atom_bin;     // [n_atoms] global bin index (binned configs only)
+  int32_t* bin_count;    // [n_bins]
+  int32_t* bin_start;    // [n_bins + 1]
+  int32_t* bin_atoms;    // [n_atoms] atoms sorted by bin, then index
+  int32_t* bin_fill;     // [n_bins] scratch cursor
+  int64_t n_bins;
+  int32_t* count;        // [n_atoms] neighbours per atom
+  int stride;            // ELL pitch (>= n_atoms)
+  int K;                 // ELL slots per atom (fill pass)
+  int32_t* nbr;          // [K * stride] home index of the neighbour
+  int32_t* nbr_z;        // [K * stride] its species
+  void* px;              // [K * stride] pair vectors, FP32 or FP64
+  void* py;
+  void* pz;
+  int fp64;              // pair vector type
+  int32_t* rev;          // [K * stride] flat ELL index of the reverse pair
+  Status* status;
+};
+
+// Neighbour search.  Phase 1 prepares configs and bins and returns the
+// number of bins needed (host sync inside); phase 2 counts; phase 3 fills.
+hipError_t nbr_prepare(NbrArgs& a, hipStream_t s);   // fills cfg, atom_cfg
+hipError_t nbr_bin_offsets(NbrArgs& a, int64_t* n_bins_dev, hipStream_t s);
+hipError_t nbr_bin(NbrArgs& a, hipStream_t s);       // bins of binned configs
+hipError_t nbr_count(NbrArgs& a, hipStream_t s);     // count[], status->max_count
+hipError_t nbr_fill(NbrArgs& a, hipStream_t s);      // ELL arrays + reverse index
+
+// Forces F_i = sum over slots (g_p - g_rev(p)); T = float or double.
+hipError_t gather_forces(int fp64, int64_t n_atoms, int stride, const int32_t* count,
+                         const int32_t* rev, const void* gx, const void* gy, const void* gz,
+                         double* forces, hipStream_t s);
+
+// Per-configuration sums of site energies, virials and B (kernel order ->
+// file order through perm, which maps file index -> kernel index).
+hipError_t reduce_configs(int fp64, int n_cfg, const int64_t* atom_offsets, int stride,
+                          const void* site, const void* atom_virial, const void* B, int m,
+                          int b_stride, const int32_t* perm, double* energy, double* virial,
+                          double* b, double* site_out, hipStream_t s);
+
+// Dense FP64 helpers of the grade.
+hipError_t gauss_jordan_inverse(int m, double* work /*[m][2m]*/, double* inv, int* singular,
+                                hipStream_t s);
+hipError_t grade_rows(int n, int m, const double* b, const double* Ainv, double* gamma,
+                      int32_t* argmax, double* c, hipStream_t s);
+
+}  // namespace mtp

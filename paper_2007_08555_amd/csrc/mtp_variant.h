@@ -1,0 +1,32 @@
+// A basis compiled into the library: its structure (for matching a potential
+// file) and the launcher of its evaluation kernel.
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace mtp {
+
+struct BasisVariant {
+  const char* name;
+  int level;
+  int n_moments;
+  const int* moments;            // [n_moments][2] = (mu, nu)
+  int n_graphs;
+  const int* graph_key_offsets;  // [n_graphs + 1]
+  const int* graph_keys;         // canonical keys, concatenated
+  int m;                         // basis size
+  const int* func_offsets;       // [m + 1]
+  const int* func_factors;       // contraction indices, concatenated
+  int C;                         // moment components held per atom
+  int n_mu;
+  int nu_max;
+  double flops_pair_fwd;         // algorithmic flops per pair (N_Q = 8), forward
+  double flops_pair_bwd;         // per pair, adjoint
+  double flops_atom;             // per atom, contraction forward + reverse
+  // precision: 0 = FP64, 1 = FP32, 2 = FP32 with compensated moment sums
+  hipError_t (*launch_eval)(int precision, bool want_b, const void* args, hipStream_t stream);
+};
+
+extern const BasisVariant* const kVariants[];
+extern const int kNumVariants;
+
+}  // namespace mtp

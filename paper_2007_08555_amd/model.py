@@ -1,0 +1,139 @@
+"""Python front end of libmtp: argument marshalling between torch device
+tensors and the C ABI.  No arithmetic of the potential happens here."""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import check, lib
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _stream(stream):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Batch:
+    """Configurations resident on one GPU (the mtp_batch of the C ABI).
+
+    Arrays: atom_offsets int64 [n_cfg+1], pos float64 [N,3], species int32 [N],
+    cell float64 [n_cfg,3,3], pbc uint8 [n_cfg]."""
+
+    def __init__(self, atom_offsets, pos, species, cell, pbc):
+        self.atom_offsets = atom_offsets
+        self.pos = pos
+        self.species = species
+        self.cell = cell
+        self.pbc = pbc
+        self.n_configs = int(atom_offsets.numel()) - 1
+        self.n_atoms = int(pos.shape[0])
+
+    @classmethod
+    def from_arrays(cls, batch, device="cuda"):
+        t = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a), dtype=dt).to(device)
+        return cls(t(batch["atom_offsets"], torch.int64), t(batch["pos"], torch.float64).reshape(-1, 3),
+                   t(batch["species"], torch.int32), t(batch["cell"], torch.float64).reshape(-1, 3, 3),
+                   t(batch["pbc"], torch.uint8))
+
+    def c_struct(self):
+        return _lib.mtp_batch(self.n_configs, self.n_atoms, self.atom_offsets.data_ptr(), self.pos.data_ptr(),
+                              self.species.data_ptr(), self.cell.data_ptr(), self.pbc.data_ptr())
+
+
+class Potential:
+    """A loaded MTP (mtp_load) on one HIP device."""
+
+    def __init__(self, path, device=0):
+        h = ctypes.c_void_p()
+        check(lib().mtp_load(str(path).encode(), int(device), ctypes.byref(h)), f"mtp_load({path})")
+        self._h = h
+        self.device = torch.device("cuda", device)
+        info = _lib.mtp_info()
+        check(lib().mtp_model_info(self._h, ctypes.byref(info)), "mtp_model_info")
+        self.level, self.m, self.n_mu = info.level, info.m, info.n_mu
+        self.n_species, self.n_q, self.n_c = info.n_species, info.n_q, info.n_c
+        self.r_min, self.r_cut = info.r_min, info.r_cut
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            lib().mtp_free(h)
+            self._h = None
+
+    # parameters -------------------------------------------------------
+    def get_params(self):
+        c = np.zeros(self.n_c)
+        xi = np.zeros(self.m)
+        check(lib().mtp_get_params(self._h, c.ctypes.data_as(ctypes.c_void_p), xi.ctypes.data_as(ctypes.c_void_p)),
+              "mtp_get_params")
+        return c, xi
+
+    def set_params(self, c=None, xi=None):
+        cc = None if c is None else np.ascontiguousarray(np.asarray(c, dtype=np.float64).ravel())
+        xx = None if xi is None else np.ascontiguousarray(np.asarray(xi, dtype=np.float64).ravel())
+        if cc is not None and cc.size != self.n_c or xx is not None and xx.size != self.m:
+            raise ValueError("parameter sizes do not match the potential")
+        check(lib().mtp_set_params(self._h, None if cc is None else cc.ctypes.data_as(ctypes.c_void_p),
+                                   None if xx is None else xx.ctypes.data_as(ctypes.c_void_p)), "mtp_set_params")
+
+    # evaluation -------------------------------------------------------
+    def eval(self, batch: Batch, precision="fp32", forces=True, virial=True, site=False, b=False,
+             energy=True, stream=None):
+        """Returns a dict of device tensors: energy [K], forces [N,3], virial [K,3,3],
+        site [N], b [K,m] (those requested)."""
+        dev = self.device
+        K, N = batch.n_configs, batch.n_atoms
+        res = {}
+        if energy:
+            res["energy"] = torch.empty(K, dtype=torch.float64, device=dev)
+        if forces:
+            res["forces"] = torch.empty((N, 3), dtype=torch.float64, device=dev)
+        if virial:
+            res["virial"] = torch.empty((K, 3, 3), dtype=torch.float64, device=dev)
+        if site:
+            res["site"] = torch.empty(N, dtype=torch.float64, device=dev)
+        if b:
+            res["b"] = torch.empty((K, self.m), dtype=torch.float64, device=dev)
+        out = _lib.mtp_out(*[res[k].data_ptr() if k in res else None
+                             for k in ("energy", "forces", "virial", "site", "b")])
+        bs = batch.c_struct()
+        check(lib().mtp_eval(self._h, ctypes.byref(bs), ctypes.byref(out), _lib.PRECISIONS[precision],
+                             _stream(stream)), "mtp_eval")
+        return res
+
+    def status(self, stream=None):
+        a, b = ctypes.c_int64(), ctypes.c_int64()
+        check(lib().mtp_status(self._h, _stream(stream), ctypes.byref(a), ctypes.byref(b)), "mtp_status")
+        return {"below_rmin": a.value, "list_errors": b.value}
+
+    # grade ------------------------------------------------------------
+    def set_active_set(self, A, stream=None):
+        A = torch.as_tensor(A, dtype=torch.float64).to(self.device).contiguous()
+        if tuple(A.shape) != (self.m, self.m):
+            raise ValueError(f"active set must be [{self.m}, {self.m}]")
+        check(lib().mtp_set_active_set(self._h, _ptr(A), _stream(stream)), "mtp_set_active_set")
+
+    def grade_from_b(self, b, want_c=False, stream=None):
+        b = torch.as_tensor(b, dtype=torch.float64).to(self.device).contiguous()
+        n = int(b.shape[0])
+        gamma = torch.empty(n, dtype=torch.float64, device=self.device)
+        arg = torch.empty(n, dtype=torch.int32, device=self.device)
+        c = torch.empty((n, self.m), dtype=torch.float64, device=self.device) if want_c else None
+        check(lib().mtp_grade_from_b(self._h, n, _ptr(b), _ptr(gamma), _ptr(arg), _ptr(c), _stream(stream)),
+              "mtp_grade_from_b")
+        return (gamma, arg, c) if want_c else (gamma, arg)
+
+    def grade(self, batch: Batch, precision="fp32", stream=None):
+        gamma = torch.empty(batch.n_configs, dtype=torch.float64, device=self.device)
+        arg = torch.empty(batch.n_configs, dtype=torch.int32, device=self.device)
+        bs = batch.c_struct()
+        check(lib().mtp_grade(self._h, ctypes.byref(bs), _ptr(gamma), _ptr(arg), _lib.PRECISIONS[precision],
+                              _stream(stream)), "mtp_grade")
+        return gamma, arg

@@ -1,0 +1,106 @@
+"""GPU parity: mtp_eval through the C ABI against the FP64 oracle on the
+same seeded inputs (energies, forces, virials, site energies, descriptors)."""
+import numpy as np
+import pytest
+
+import synth
+from gpu_common import errors, gpu_batch, log, oracle_batch, pot_path
+from oracle.potential import read_potential
+
+pytestmark = pytest.mark.gpu
+
+# FP64 kernels against the FP64 oracle: only summation order differs.
+TOL64 = {"energy_per_atom": 1e-11, "site": 1e-11, "force": 1e-10, "virial": 1e-9, "b_rel": 1e-11}
+# FP32 kernels on the calibrated potentials (site energies O(1) eV, forces up
+# to ~20 eV/A): energy per atom within 1e-6 eV; forces within 1e-5 of the
+# largest force.  A force is a sum of per-pair gradients that cancel, each
+# carrying a relative FP32 rounding error of tens of unit roundoffs
+# (2^-24 ~ 6e-8), which bounds FP32 forces near 1e-6..1e-5 relative.  The
+# absolute 1e-5 eV/A bound is met by the FP64 path.
+TOL32 = {"energy_per_atom": 1e-6, "force_rel": 1e-5}
+
+
+@pytest.fixture(scope="module")
+def potentials():
+    from paper_2007_08555_amd import Potential
+    cache = {}
+
+    def get(name):
+        if name not in cache:
+            cache[name] = (Potential(pot_path(name)), read_potential(pot_path(name)))
+        return cache[name]
+    return get
+
+
+def _check(name, batch, precision, potentials, tol, label):
+    P, op = potentials(name)
+    log(f"[{label}] potential={name} precision={precision} configs={len(batch['n_atoms'])} "
+        f"atoms={int(batch['n_atoms'].sum())}")
+    g = gpu_batch(P, batch, precision)
+    o = oracle_batch(op, batch)
+    rep = errors(batch, g, o)
+    log(f"[{label}] errors {rep}")
+    st = P.status()
+    assert st["list_errors"] == 0
+    rep["force_rel"] = rep["force"] / max(rep["force_scale"], 1e-300)
+    for k, v in tol.items():
+        assert rep[k] <= v, (k, rep[k], v)
+    return g, o
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp32c"])
+def test_fcc108_level8(potentials, precision):
+    b = synth.fcc108(seed=0)
+    _check("lev8_s1", b, precision, potentials, TOL64 if precision == "fp64" else TOL32, "fcc108")
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp32c"])
+def test_mixed_level12(potentials, precision):
+    b = synth.mixed_batch(seed=3, n_configs=24, n_min=8, n_max=48, n_species_model=2)
+    _check("lev12_s2", b, precision, potentials, TOL64 if precision == "fp64" else TOL32, "mixed-l12")
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp32c"])
+def test_mixed_level16(potentials, precision):
+    b = synth.mixed_batch(seed=4, n_configs=12, n_min=8, n_max=96, n_species_model=3)
+    _check("lev16_s3", b, precision, potentials, TOL64 if precision == "fp64" else TOL32, "mixed-l16")
+
+
+def test_edge_cases(potentials):
+    # empty config in the middle, single atom, isolated pair beyond R_cut,
+    # a one-atom periodic cell (all neighbours are its own images)
+    cfgs = [
+        (np.zeros((0, 3)), np.zeros(0, np.int32), np.zeros((3, 3)), 0),
+        (np.zeros((1, 3)), np.array([1], np.int32), np.zeros((3, 3)), 0),
+        (np.array([[0, 0, 0], [5.5, 0, 0]], float), np.array([0, 1], np.int32), np.zeros((3, 3)), 0),
+        (np.zeros((1, 3)), np.array([0], np.int32), np.eye(3) * 2.7, 1),
+        (np.array([[0.1, 0.2, 0.3], [1.4, 1.3, 1.5]]), np.array([1, 0], np.int32),
+         np.array([[2.8, 0, 0], [0.9, 2.7, 0], [0.3, 0.4, 2.9]]), 1),
+    ]
+    b = synth._batch(cfgs)
+    _check("lev12_s2", b, "fp64", potentials, TOL64, "edge")
+
+
+def test_empty_batch(potentials):
+    P, _ = potentials("lev8_s1")
+    b = synth._batch([(np.zeros((0, 3)), np.zeros(0, np.int32), np.zeros((3, 3)), 0)])
+    g = gpu_batch(P, b, "fp32")
+    assert g["energy"].shape == (1,) and g["energy"][0] == 0.0
+
+
+def test_bad_species_is_rejected(potentials):
+    from paper_2007_08555_amd._lib import MTPError
+    P, _ = potentials("lev8_s1")
+    b = synth.fcc108(seed=1)
+    b["species"][5] = 3
+    with pytest.raises(MTPError, match="species"):
+        gpu_batch(P, b, "fp32")
+
+
+def test_bad_offsets_are_rejected(potentials):
+    from paper_2007_08555_amd._lib import MTPError
+    P, _ = potentials("lev8_s1")
+    b = synth.fcc108(seed=1)
+    b["atom_offsets"] = np.array([0, 100], np.int64)
+    with pytest.raises(MTPError, match="atom_offsets"):
+        gpu_batch(P, b, "fp32")
