@@ -1,0 +1,172 @@
+#!/usr/bin/env python
+"""Throughput of batched MTP E + F + stress evaluation on one MI355X.
+
+One step is one pass of the whole evaluation path over one batch resident in
+HBM: neighbour lists, radial functions, moments, contractions, adjoint,
+force gather, per-configuration energy / virial sums.
+
+Workload (default): 4096 configurations of 8..256 atoms (about 530 k atoms),
+random fcc/bcc/hcp periodic cells with vacancies and free fragments,
+displacements sigma in [0.05, 0.3] A, 1..3 species per configuration drawn
+from 3, level-16 MTP with N_Q = 8, R_cut = 5 A (seeded synthetic data; the
+calibrated potential tests/golden/potentials/lev16_s3.mtp).
+
+Prints one JSON line.  Besides the contract fields it reports the roofline
+of the evaluation kernels, the plain one-configuration-per-call path on the
+same configurations, the single 16 000-atom bcc box, and the FP64 CPU
+oracle timed on a bounded sample of the same workload.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "atom-evals/s (E+F+stress) MTP lev16; batched vs plain at force err ≤1e-5 eV/Å"
+PEAK = {"fp64": 78.6, "fp32": 157.3, "fp32c": 157.3}   # TFLOP/s, MI355X vector FP64 / FP32
+DTYPE = {"fp64": "f64", "fp32": "f32", "fp32c": "f32"}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(batch, pot_path, budget_s):
+    """The FP64 oracle on the host, one thread, over whole configurations of
+    the same batch until budget_s seconds have passed."""
+    from threadpoolctl import threadpool_limits
+
+    import synth
+    from oracle import mtp as omtp
+    from oracle.potential import read_potential
+    pot = read_potential(pot_path)
+    atoms, done = 0, 0
+    t0 = time.perf_counter()
+    with threadpool_limits(limits=1):
+        for k in range(len(batch["n_atoms"])):
+            omtp.evaluate(pot, *synth.config_of(batch, k))
+            atoms += int(batch["n_atoms"][k])
+            done += 1
+            if time.perf_counter() - t0 > budget_s:
+                break
+    dt = time.perf_counter() - t0
+    return {"value": atoms / dt, "unit": "atom-evals/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {done} configurations ({atoms} atoms) of the benchmark batch, "
+                      f"E+F+virial in FP64, {dt:.1f} s on one host thread"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "fp32c"])
+    ap.add_argument("--configs", type=int, default=4096)
+    ap.add_argument("--plain-configs", type=int, default=256)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-extras", action="store_true", help="skip plain path, bcc box and CPU baseline")
+    a = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if a.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(configurations would be sharded across GPUs by cost with no exchange during evaluation)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2007_08555_amd import Batch, Potential
+
+    pot_path = os.path.join(ROOT, "tests", "golden", "potentials", "lev16_s3.mtp")
+    t0 = time.time()
+    batch = synth.mixed_batch(seed=0, n_configs=a.configs, n_min=8, n_max=256, n_species_model=3)
+    n_atoms = int(batch["n_atoms"].sum())
+    log(f"generated {a.configs} configurations, {n_atoms} atoms in {time.time() - t0:.1f} s")
+    P = Potential(pot_path, device=0)
+    B = Batch.from_arrays(batch, "cuda:0")
+    stream = torch.cuda.current_stream()
+
+    def step():
+        return P.eval(B, precision=a.precision, forces=True, virial=True, energy=True, stream=stream)
+
+    for _ in range(a.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        step()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / a.steps
+    value = n_atoms / dt
+    log(f"batched: {dt * 1e3:.3f} ms/step, {value:.4g} atom-evals/s")
+
+    # per-phase device times of the same call, HIP events on the call's stream
+    P.set_timing(True)
+    ms = {"ms_neighbours": [], "ms_eval": [], "ms_forces": [], "ms_reduce": []}
+    for _ in range(5):
+        step()
+        st = P.stats()
+        for k in ms:
+            ms[k].append(st[k])
+    P.set_timing(False)
+    ms = {k: float(np.mean(v)) for k, v in ms.items()}
+    flops = st["n_pairs"] * (st["flops_pair_fwd"] + st["flops_pair_bwd"]) + st["n_atoms"] * st["flops_atom"]
+    achieved = flops / (ms["ms_eval"] * 1e-3) / 1e12
+    roofline = {"bound": "alu", "achieved": achieved, "peak": PEAK[a.precision], "unit": "TFLOP/s",
+                "frac": achieved / PEAK[a.precision], "traffic": None,
+                "kernel": "evaluation kernel (moments, contractions, adjoint)",
+                "flops_per_launch": flops, "kernel_ms": ms["ms_eval"],
+                "n_pairs": st["n_pairs"], "phase_ms": ms}
+    log(f"roofline: {roofline}")
+
+    line = {"metric": METRIC, "value": value, "unit": "atom-evals/s", "n_gpus": 1, "steps": a.steps,
+            "warmup": a.warmup, "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": DTYPE[a.precision], "data": "synthetic",
+            "config": {"workload": f"batched: {a.configs} mixed fcc/bcc/hcp cells and fragments, 8-256 atoms, "
+                                   f"{n_atoms} atoms, 1-3 of 3 species, MTP level 16, N_Q 8, R_cut 5 A",
+                       "precision": a.precision, "level": 16, "atoms": n_atoms, "configs": a.configs},
+            "roofline": roofline}
+
+    if not a.no_extras:
+        # the plain path: one configuration per call, same configurations
+        nplain = min(a.plain_configs, a.configs)
+        sub = [Batch.from_arrays(synth.subset(batch, [k]), "cuda:0") for k in range(nplain)]
+        for s_ in sub[:8]:
+            P.eval(s_, precision=a.precision, stream=stream)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for s_ in sub:
+            P.eval(s_, precision=a.precision, stream=stream)
+        torch.cuda.synchronize()
+        tp = time.perf_counter() - t0
+        atoms_p = int(batch["n_atoms"][:nplain].sum())
+        line["plain"] = {"value": atoms_p / tp, "unit": "atom-evals/s", "configs": nplain,
+                         "note": "one mtp_eval call per configuration on the first configurations of the batch"}
+        line["batched_over_plain"] = value / (atoms_p / tp)
+        log(f"plain: {atoms_p / tp:.4g} atom-evals/s")
+        # the single 16 000-atom bcc box (two species)
+        box = synth.bcc_alloy(seed=0)
+        P2 = Potential(os.path.join(ROOT, "tests", "golden", "potentials", "lev16_s2.mtp"), device=0)
+        Bb = Batch.from_arrays(box, "cuda:0")
+        for _ in range(2):
+            P2.eval(Bb, precision=a.precision, stream=stream)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(10):
+            P2.eval(Bb, precision=a.precision, stream=stream)
+        torch.cuda.synchronize()
+        tb = (time.perf_counter() - t0) / 10
+        line["bcc16000"] = {"value": 16000 / tb, "unit": "atom-evals/s", "ms_per_step": tb * 1e3}
+        log(f"bcc16000: {16000 / tb:.4g} atom-evals/s")
+        line["cpu_baseline"] = cpu_baseline(batch, pot_path, a.cpu_seconds)
+        log(f"cpu baseline: {line['cpu_baseline']}")
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

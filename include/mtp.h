@@ -149,6 +149,29 @@ int mtp_grade(mtp_model* model, const mtp_batch* batch, double* gamma_dev, int32
  */
 int mtp_status(mtp_model* model, void* stream, int64_t* n_below_rmin, int64_t* n_list_errors);
 
+/* Counters and device timings of the last mtp_eval on a model. */
+typedef struct {
+  int64_t n_atoms;          /* atoms of the last batch */
+  int64_t n_pairs;          /* neighbour pairs (i, j, image) of the last batch */
+  int32_t max_neighbours;   /* largest neighbour count of one atom */
+  int32_t level;
+  double flops_pair_fwd;    /* algorithmic flops per pair of the compiled schedule, N_Q = 8:
+                               radial functions, monomials, moment sums */
+  double flops_pair_bwd;    /* per pair: adjoint g = dV/dr_ij, virial */
+  double flops_atom;        /* per atom: contractions, basis products and their reverse */
+  float ms_neighbours;      /* device time of the neighbour search (-1 when timing is off) */
+  float ms_eval;            /* evaluation kernels (moments, contractions, adjoint) */
+  float ms_forces;          /* force gather */
+  float ms_reduce;          /* per-configuration sums */
+} mtp_stats;
+
+/* Turns HIP-event timing of the phases of mtp_eval on (enable = 1) or off.
+ * Events are recorded on the stream of each call. */
+int mtp_set_timing(mtp_model* model, int enable);
+
+/* Fills *stats for the last mtp_eval; synchronises that call's stream. */
+int mtp_get_stats(mtp_model* model, mtp_stats* stats);
+
 /* Releases the model and its device memory. */
 void mtp_free(mtp_model* model);
 

@@ -40,6 +40,13 @@ class mtp_info(ctypes.Structure):
                 ("r_min", ctypes.c_double), ("r_cut", ctypes.c_double)]
 
 
+class mtp_stats(ctypes.Structure):
+    _fields_ = [("n_atoms", ctypes.c_int64), ("n_pairs", ctypes.c_int64), ("max_neighbours", ctypes.c_int32),
+                ("level", ctypes.c_int32), ("flops_pair_fwd", ctypes.c_double), ("flops_pair_bwd", ctypes.c_double),
+                ("flops_atom", ctypes.c_double), ("ms_neighbours", ctypes.c_float), ("ms_eval", ctypes.c_float),
+                ("ms_forces", ctypes.c_float), ("ms_reduce", ctypes.c_float)]
+
+
 _P = ctypes.c_void_p
 _SIGNATURES = {
     "mtp_load": (ctypes.c_int, [ctypes.c_char_p, ctypes.c_int, ctypes.POINTER(_P)]),
@@ -51,6 +58,8 @@ _SIGNATURES = {
     "mtp_grade_from_b": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, _P, _P, _P]),
     "mtp_grade": (ctypes.c_int, [_P, ctypes.POINTER(mtp_batch), _P, _P, ctypes.c_int, _P]),
     "mtp_status": (ctypes.c_int, [_P, _P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]),
+    "mtp_set_timing": (ctypes.c_int, [_P, ctypes.c_int]),
+    "mtp_get_stats": (ctypes.c_int, [_P, ctypes.POINTER(mtp_stats)]),
     "mtp_free": (None, [_P]),
     "mtp_last_error": (ctypes.c_char_p, []),
 }

@@ -101,6 +101,16 @@ struct mtp_model {
   Buffer cfg, atom_cfg, atom_bin, bin_count, bin_start, bin_atoms, bin_fill, nbins_dev;
   Buffer count, nbr, nbr_z, px, py, pz, rev, gx, gy, gz, site, wv, B, status;
   Buffer b_tmp, c_tmp;
+  // statistics of the last evaluation
+  int64_t last_atoms = 0, last_pairs = 0;
+  int32_t last_max_nb = 0;
+  bool timing = false, timed = false;
+  hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  hipStream_t last_stream = nullptr;
+  ~mtp_model() {
+    for (auto& e : ev)
+      if (e) (void)hipEventDestroy(e);
+  }
 };
 
 namespace {
@@ -117,6 +127,8 @@ int upload_params(mtp_model* M) {
   HIP_TRY(hipMemcpy(M->c32.p, c32.data(), sizeof(float) * M->n_c, hipMemcpyHostToDevice), "hipMemcpy");
   HIP_TRY(hipMemcpy(M->xi64.p, xk.data(), sizeof(double) * M->m, hipMemcpyHostToDevice), "hipMemcpy");
   HIP_TRY(hipMemcpy(M->xi32.p, x32.data(), sizeof(float) * M->m, hipMemcpyHostToDevice), "hipMemcpy");
+  HIP_TRY(M->perm_dev.ensure(sizeof(int32_t) * M->m), "hipMalloc");
+  HIP_TRY(hipMemcpy(M->perm_dev.p, M->perm.data(), sizeof(int32_t) * M->m, hipMemcpyHostToDevice), "hipMemcpy");
   return MTP_OK;
 }
 
@@ -309,6 +321,10 @@ int run_eval(mtp_model* M, const mtp_batch* bt, const mtp_out* out, int precisio
   const int n_cfg = bt->n_configs;
   const bool fp64 = precision == MTP_FP64;
   const size_t tsz = fp64 ? sizeof(double) : sizeof(float);
+  M->timed = false;
+  M->last_stream = s;
+  auto mark = [&](int k) -> hipError_t { return M->timing ? hipEventRecord(M->ev[k], s) : hipSuccess; };
+  HIP_TRY(mark(0), "hipEventRecord");
   HIP_TRY(M->status.ensure(sizeof(Status)), "hipMalloc");
   HIP_TRY(hipMemsetAsync(M->status.p, 0, sizeof(Status), s), "hipMemsetAsync");
   if (n_cfg == 0) return MTP_OK;
@@ -361,6 +377,9 @@ int run_eval(mtp_model* M, const mtp_batch* bt, const mtp_out* out, int precisio
   HIP_TRY(hipMemcpyAsync(&st, M->status.p, sizeof(Status), hipMemcpyDeviceToHost, s), "hipMemcpyAsync");
   HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
   if (st.bad_species) return fail(MTP_E_ARG, "species index outside [0, species_count)");
+  M->last_atoms = N;
+  M->last_pairs = (int64_t)st.n_pairs;
+  M->last_max_nb = (int32_t)st.max_count;
   const int K = (int)std::max<unsigned long long>(1, st.max_count);
   const int stride = (int)((N + 63) / 64 * 64);
   const size_t slots = (size_t)K * stride;
@@ -386,6 +405,7 @@ int run_eval(mtp_model* M, const mtp_batch* bt, const mtp_out* out, int precisio
   a.pz = M->pz.p;
   a.rev = M->rev.as<int32_t>();
   HIP_TRY(nbr_fill(a, s), "neighbour fill");
+  HIP_TRY(mark(1), "hipEventRecord");
   if (fp64) {
     auto ea = make_args<double>(M, N, stride, bt->species, want_b);
     HIP_TRY(M->var->launch_eval(precision, want_b, &ea, s), "evaluation kernel");
@@ -393,17 +413,18 @@ int run_eval(mtp_model* M, const mtp_batch* bt, const mtp_out* out, int precisio
     auto ea = make_args<float>(M, N, stride, bt->species, want_b);
     HIP_TRY(M->var->launch_eval(precision, want_b, &ea, s), "evaluation kernel");
   }
+  HIP_TRY(mark(2), "hipEventRecord");
   if (out->forces)
     HIP_TRY(gather_forces(fp64, N, stride, M->count.as<int32_t>(), M->rev.as<int32_t>(), M->gx.p, M->gy.p,
                           M->gz.p, out->forces, s),
             "force gather");
-  HIP_TRY(M->perm_dev.ensure(sizeof(int32_t) * M->m), "hipMalloc");
-  HIP_TRY(hipMemcpyAsync(M->perm_dev.p, M->perm.data(), sizeof(int32_t) * M->m, hipMemcpyHostToDevice, s),
-          "hipMemcpyAsync");
+  HIP_TRY(mark(3), "hipEventRecord");
   HIP_TRY(reduce_configs(fp64, n_cfg, bt->atom_offsets, stride, M->site.p, M->wv.p, want_b ? M->B.p : nullptr,
                          M->m, stride, M->perm_dev.as<int32_t>(), out->energy, out->virial, out->b,
                          out->site_energy, s),
           "reductions");
+  HIP_TRY(mark(4), "hipEventRecord");
+  M->timed = M->timing;
   return MTP_OK;
 }
 
@@ -548,6 +569,34 @@ int mtp_status(mtp_model* M, void* stream, int64_t* n_below_rmin, int64_t* n_lis
   }
   if (n_below_rmin) *n_below_rmin = (int64_t)st.below_rmin;
   if (n_list_errors) *n_list_errors = (int64_t)st.list_errors;
+  return MTP_OK;
+}
+
+int mtp_set_timing(mtp_model* M, int enable) {
+  if (!M) return fail(MTP_E_ARG, "mtp_set_timing: null model");
+  HIP_TRY(hipSetDevice(M->device), "hipSetDevice");
+  if (enable && !M->ev[0])
+    for (auto& e : M->ev) HIP_TRY(hipEventCreate(&e), "hipEventCreate");
+  M->timing = enable != 0;
+  return MTP_OK;
+}
+
+int mtp_get_stats(mtp_model* M, mtp_stats* st) {
+  if (!M || !st) return fail(MTP_E_ARG, "mtp_get_stats: null argument");
+  HIP_TRY(hipSetDevice(M->device), "hipSetDevice");
+  st->n_atoms = M->last_atoms;
+  st->n_pairs = M->last_pairs;
+  st->max_neighbours = M->last_max_nb;
+  st->level = M->level;
+  st->flops_pair_fwd = M->var->flops_pair_fwd;
+  st->flops_pair_bwd = M->var->flops_pair_bwd;
+  st->flops_atom = M->var->flops_atom;
+  st->ms_neighbours = st->ms_eval = st->ms_forces = st->ms_reduce = -1.0f;
+  if (M->timed) {
+    HIP_TRY(hipEventSynchronize(M->ev[4]), "hipEventSynchronize");
+    float* outs[4] = {&st->ms_neighbours, &st->ms_eval, &st->ms_forces, &st->ms_reduce};
+    for (int k = 0; k < 4; ++k) HIP_TRY(hipEventElapsedTime(outs[k], M->ev[k], M->ev[k + 1]), "hipEventElapsedTime");
+  }
   return MTP_OK;
 }
 

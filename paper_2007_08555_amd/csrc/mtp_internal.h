@@ -25,6 +25,7 @@ struct Status {
   unsigned long long max_count;   // largest neighbour count of the last search
   unsigned long long bad_offsets; // atom_offsets not monotone from 0 to n_atoms
   unsigned long long bad_species; // species index outside [0, n_species)
+  unsigned long long n_pairs;     // total neighbour pairs of the last search
 };
 
 struct NbrArgs {

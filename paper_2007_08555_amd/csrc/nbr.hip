@@ -273,7 +273,10 @@ __global__ void __launch_bounds__(kBlock) search_kernel(NbrArgs a) {
         }
   }
   a.count[i] = FILL ? (emit.count < a.K ? emit.count : a.K) : emit.count;
-  if (!FILL) atomicMax(&a.status->max_count, (unsigned long long)emit.count);
+  if (!FILL) {
+    atomicMax(&a.status->max_count, (unsigned long long)emit.count);
+    atomicAdd(&a.status->n_pairs, (unsigned long long)emit.count);
+  }
 }
 
 template <typename T>

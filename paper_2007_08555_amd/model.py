@@ -108,6 +108,14 @@ class Potential:
                              _stream(stream)), "mtp_eval")
         return res
 
+    def set_timing(self, enable=True):
+        check(lib().mtp_set_timing(self._h, 1 if enable else 0), "mtp_set_timing")
+
+    def stats(self):
+        st = _lib.mtp_stats()
+        check(lib().mtp_get_stats(self._h, ctypes.byref(st)), "mtp_get_stats")
+        return {k: getattr(st, k) for k, _ in st._fields_}
+
     def status(self, stream=None):
         a, b = ctypes.c_int64(), ctypes.c_int64()
         check(lib().mtp_status(self._h, _stream(stream), ctypes.byref(a), ctypes.byref(b)), "mtp_status")
