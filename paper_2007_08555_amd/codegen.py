@@ -100,12 +100,12 @@ def _const(v):
     return f"T({float(v)!r})"
 
 
-def emit_pair_forward(s, comp_mode):
-    """Monomials of the pair vector and the moment accumulation."""
-    out = []
-    ops = 0
+def _mono_steps(s):
+    """Per degree nu, the statements defining its monomials from degree nu - 1."""
+    steps = {}
     mono = {(0, 0, 0): "T(1)"}
     for nu in range(1, s.nu_max + 1):
+        lines = []
         for a, b, c in components(nu):
             if a:
                 src, v = (a - 1, b, c), "x"
@@ -115,17 +115,32 @@ def emit_pair_forward(s, comp_mode):
                 src, v = (a, b, c - 1), "z"
             name = f"m{a}_{b}_{c}"
             rhs = v if src == (0, 0, 0) else f"{mono[src]} * {v}"
-            if src != (0, 0, 0):
-                ops += 1
-            out.append(f"const T {name} = {rhs};")
+            lines.append((f"const T {name} = {rhs};", src != (0, 0, 0)))
             mono[(a, b, c)] = name
+        steps[nu] = lines
+    return steps, mono
+
+
+def emit_pair_forward(s, comp_mode):
+    """Monomials of the pair vector, degree by degree, each followed by the
+    moment components that use it (only two degrees are live at once)."""
+    out = []
+    ops = 0
+    steps, mono = _mono_steps(s)
+    by_nu = defaultdict(list)
     for (mu, nu, abc), k in s.comp.items():
-        term = f"f[{mu}]" if nu == 0 else f"f[{mu}] * {mono[abc]}"
-        if comp_mode:
-            out.append(f"if (COMP) mtp::two_sum_acc(M[{k}], Mlo[{k}], {term}); else M[{k}] += {term};")
-        else:
-            out.append(f"M[{k}] += {term};")
-        ops += 2 if nu else 1
+        by_nu[nu].append((mu, abc, k))
+    for nu in range(0, s.nu_max + 1):
+        for line, counted in steps.get(nu, []):
+            out.append(line)
+            ops += 1 if counted else 0
+        for mu, abc, k in by_nu.get(nu, []):
+            term = f"f[{mu}]" if nu == 0 else f"f[{mu}] * {mono[abc]}"
+            if comp_mode:
+                out.append(f"if (COMP) mtp::two_sum_acc(M[{k}], Mlo[{k}], {term}); else M[{k}] += {term};")
+            else:
+                out.append(f"M[{k}] += {term};")
+            ops += 2 if nu else 1
     return out, ops
 
 
@@ -165,55 +180,67 @@ def emit_contraction(s):
             ops += len(rest) + 1 + (1 if n > 1 else 0)
     for g in range(len(s.terms)):
         out.append(f"const T dg{g} = " + (" + ".join(dg[g]) if dg[g] else "T(0)") + ";")
-    # reverse of the graph terms
+    # reverse of the graph terms, gathered per component so that each
+    # G[k] is complete when written and nothing but M stays live
+    contrib = defaultdict(lambda: defaultdict(list))
     for g, terms in enumerate(s.terms):
-        out.append("{")
-        out.append(f"const T d = dg{g};")
         for coef, idx in terms:
-            cd = "d" if coef == 1 else f"({_const(coef)} * d)"
-            if coef != 1:
-                ops += 1
-            for p, k in enumerate(idx):
-                rest = [f"M[{q}]" for t, q in enumerate(idx) if t != p]
-                out.append(f"G[{k}] += {cd}" + ("" if not rest else " * " + " * ".join(rest)) + ";")
-                ops += len(rest) + 1
-        out.append("}")
+            for k in set(idx):
+                cnt = idx.count(k)
+                rest = list(idx)
+                rest.remove(k)
+                contrib[k][g].append((coef * cnt, rest))
+    for k in range(s.C):
+        if not contrib[k]:
+            out.append(f"args.G[(size_t){k} * args.stride + i] = T(0);")
+            continue
+        parts = []
+        for g, lst in sorted(contrib[k].items()):
+            inner = []
+            for c, rest in lst:
+                expr = _prod([f"M[{q}]" for q in rest])
+                if c != 1:
+                    expr = f"{_const(c)} * {expr}" if rest else _const(c)
+                    ops += 1
+                inner.append(expr)
+                ops += max(len(rest) - 1, 0) + 1
+            parts.append(f"dg{g} * (" + " + ".join(inner) + ")")
+            ops += 1
+        out.append(f"args.G[(size_t){k} * args.stride + i] = " + " + ".join(parts) + ";")
     return out, ops
 
 
-def emit_pair_backward(s):
-    """g = dV/dr_ij for one pair from G, f, df and the monomials."""
+def emit_pair_backward(s, nus=None, gmap=None):
+    """g = dV/dr_ij for one pair from G, f, df and the monomials, restricted
+    to the components of the degrees in nus (all when None); gmap maps a
+    component index to its register slot in G.
+
+    G[k] is the derivative with respect to the component itself, a plain sum
+    over pairs of f_mu x^a y^b z^c, so d/dr of one pair's share is
+    df_mu x^a y^b z^c r/|r| + f_mu grad(x^a y^b z^c)."""
     out = []
     ops = 0
-    mono = {(0, 0, 0): "T(1)"}
-    for nu in range(1, s.nu_max + 1):
-        for a, b, c in components(nu):
-            if a:
-                src, v = (a - 1, b, c), "x"
-            elif b:
-                src, v = (a, b - 1, c), "y"
-            else:
-                src, v = (a, b, c - 1), "z"
-            name = f"m{a}_{b}_{c}"
-            rhs = v if src == (0, 0, 0) else f"{mono[src]} * {v}"
-            if src != (0, 0, 0):
-                ops += 1
-            out.append(f"const T {name} = {rhs};")
-            mono[(a, b, c)] = name
+    steps, mono = _mono_steps(s)
     out.append("T D[NMU];")
     out.append("#pragma unroll\nfor (int q = 0; q < NMU; ++q) D[q] = T(0);")
     out.append("T gx = T(0), gy = T(0), gz = T(0);")
-    for nu in s.nus_used():
+    used = set(s.nus_used()) if nus is None else set(nus)
+    gmap = gmap or {k: k for k in range(s.C)}
+    top = max(used)
+    for nu in range(0, top + 1):
+        for line, counted in steps.get(nu, []):
+            out.append(line)
+            ops += 1 if counted else 0
+        if nu not in used:
+            continue
         mus = s.mus_of_nu(nu)
         for a, b, c in components(nu):
-            ks = [s.comp[(mu, nu, (a, b, c))] for mu in mus]
+            ks = [gmap[s.comp[(mu, nu, (a, b, c))]] for mu in mus]
             if nu == 0:
                 for mu, k in zip(mus, ks):
                     out.append(f"D[{mu}] += G[{k}];")
                     ops += 1
                 continue
-            # G is the derivative with respect to the component itself, a plain
-            # sum over pairs of f_mu x^a y^b z^c: no multinomial weight here
             out.append("{")
             mono_abc = mono[(a, b, c)]
             for mu, k in zip(mus, ks):
@@ -236,6 +263,70 @@ def emit_pair_backward(s):
     return out, ops
 
 
+def adjoint_passes(s, budget):
+    """Degrees grouped into passes of at most `budget` components (a degree
+    is never split); one pass when everything fits."""
+    per_nu = defaultdict(list)
+    for (mu, nu, abc), k in s.comp.items():
+        per_nu[nu].append(k)
+    passes, cur, n = [], [], 0
+    for nu in sorted(per_nu):
+        if cur and n + len(per_nu[nu]) > budget:
+            passes.append(cur)
+            cur, n = [], 0
+        cur.append(nu)
+        n += len(per_nu[nu])
+    passes.append(cur)
+    return [(p, sorted(k for nu in p for k in per_nu[nu])) for p in passes]
+
+
+ADJOINT_TEMPLATE = r"""
+// Adjoint pass {pidx} over the pairs of one atom, components of degrees {nus}:
+// its share of g = dV_i/dr_ij from G, f_mu and df_mu/dr, stored (first pass)
+// or added (later passes) per pair for the force and virial gather.
+template <typename T, bool FIRST>
+__global__ void __launch_bounds__(BLOCK) adjoint_{tag}_kernel(const mtp::EvalArgs<T> args) {{
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* cs = reinterpret_cast<T*>(smem_raw);
+  for (int t = threadIdx.x; t < args.n_c; t += blockDim.x) cs[t] = args.c[t];
+  __syncthreads();
+  const int i = blockIdx.x * BLOCK + threadIdx.x;
+  if (i >= args.n_atoms) return;
+  const int S = args.n_species;
+  const int nq = args.nq;
+  const int mu_stride = S * S * nq;
+  const int zi = clamp_species(args.species[i], S);
+  const int cnt = args.nbr_count[i];
+  const T rmin = args.rmin, rcut = args.rcut;
+  constexpr int CP = {ncomp};
+  constexpr int kIdx[CP] = {{ {comp_list} }};
+  T G[CP];
+#pragma unroll
+  for (int k = 0; k < CP; ++k) G[k] = args.G[(size_t)kIdx[k] * args.stride + i];
+#pragma unroll 1
+  for (int p = 0; p < cnt; ++p) {{
+    const size_t e = (size_t)p * args.stride + i;
+    const T x = args.px[e], y = args.py[e], z = args.pz[e];
+    const int zj = args.pzj[e];
+    const T r = sqrt(x * x + y * y + z * z);
+    const T inv_r = T(1) / r;
+    T f[NMU], df[NMU];
+    mtp::radial<T, NMU, true>(cs, (zi * S + zj) * nq, mu_stride, nq, r, rmin, rcut, f, df);
+{body}
+    if (FIRST) {{
+      args.g[3 * e] = gx;
+      args.g[3 * e + 1] = gy;
+      args.g[3 * e + 2] = gz;
+    }} else {{
+      args.g[3 * e] += gx;
+      args.g[3 * e + 1] += gy;
+      args.g[3 * e + 2] += gz;
+    }}
+  }}
+}}
+"""
+
+
 KERNEL_TEMPLATE = r"""// Generated by paper_2007_08555_amd/codegen.py for the MTP basis of level {level}
 // ({m} basis functions, {ngraphs} connected contractions, {C} moment components).
 // Do not edit: regenerate with the package build step.
@@ -249,8 +340,11 @@ constexpr int C = {C};
 constexpr int NMU = {n_mu};
 constexpr int BLOCK = {block};
 
-template <typename T, bool COMP, bool WANT_B>
-__global__ void __launch_bounds__(BLOCK) eval_kernel(const mtp::EvalArgs<T> args) {{
+__device__ __forceinline__ int clamp_species(int z, int S) {{ return z < 0 ? 0 : (z >= S ? S - 1 : z); }}
+
+// Moments of one atom over its pairs, written to args.M.
+template <typename T, bool COMP>
+__global__ void __launch_bounds__(BLOCK) moments_kernel(const mtp::EvalArgs<T> args) {{
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* cs = reinterpret_cast<T*>(smem_raw);
   for (int t = threadIdx.x; t < args.n_c; t += blockDim.x) cs[t] = args.c[t];
@@ -261,7 +355,7 @@ __global__ void __launch_bounds__(BLOCK) eval_kernel(const mtp::EvalArgs<T> args
   const int S = args.n_species;
   const int nq = args.nq;
   const int mu_stride = S * S * nq;
-  const int zi = args.species[i];
+  const int zi = clamp_species(args.species[i], S);
   const int cnt = args.nbr_count[i];
   const T rmin = args.rmin, rcut = args.rcut;
 
@@ -272,6 +366,7 @@ __global__ void __launch_bounds__(BLOCK) eval_kernel(const mtp::EvalArgs<T> args
 #pragma unroll
   for (int k = 0; k < (COMP ? C : 1); ++k) Mlo[k] = T(0);
 
+#pragma unroll 1
   for (int p = 0; p < cnt; ++p) {{
     const size_t e = (size_t)p * args.stride + i;
     const T x = args.px[e], y = args.py[e], z = args.pz[e];
@@ -285,46 +380,37 @@ __global__ void __launch_bounds__(BLOCK) eval_kernel(const mtp::EvalArgs<T> args
 #pragma unroll
     for (int k = 0; k < C; ++k) M[k] += Mlo[k];
   }}
-
-  T G[C];
 #pragma unroll
-  for (int k = 0; k < C; ++k) G[k] = T(0);
-  {{
-{contraction}
-    args.site[i] = V;
-  }}
-
-  T w00 = 0, w01 = 0, w02 = 0, w10 = 0, w11 = 0, w12 = 0, w20 = 0, w21 = 0, w22 = 0;
-  for (int p = 0; p < cnt; ++p) {{
-    const size_t e = (size_t)p * args.stride + i;
-    const T x = args.px[e], y = args.py[e], z = args.pz[e];
-    const int zj = args.pzj[e];
-    const T r = sqrt(x * x + y * y + z * z);
-    const T inv_r = T(1) / r;
-    T f[NMU], df[NMU];
-    mtp::radial<T, NMU, true>(cs, (zi * S + zj) * nq, mu_stride, nq, r, rmin, rcut, f, df);
-{pair_bwd}
-    args.gx[e] = gx;
-    args.gy[e] = gy;
-    args.gz[e] = gz;
-    w00 += gx * x; w01 += gx * y; w02 += gx * z;
-    w10 += gy * x; w11 += gy * y; w12 += gy * z;
-    w20 += gz * x; w21 += gz * y; w22 += gz * z;
-  }}
-  const int n = args.stride;
-  T* wv = args.atom_virial;
-  wv[0 * n + i] = w00; wv[1 * n + i] = w01; wv[2 * n + i] = w02;
-  wv[3 * n + i] = w10; wv[4 * n + i] = w11; wv[5 * n + i] = w12;
-  wv[6 * n + i] = w20; wv[7 * n + i] = w21; wv[8 * n + i] = w22;
+  for (int k = 0; k < C; ++k) args.M[(size_t)k * args.stride + i] = M[k];
 }}
 
+// Contractions of one atom's moments: V, optional B, and G = dV/dM.
+template <typename T, bool WANT_B>
+__global__ void __launch_bounds__(BLOCK) contract_kernel(const mtp::EvalArgs<T> args) {{
+  const int i = blockIdx.x * BLOCK + threadIdx.x;
+  if (i >= args.n_atoms) return;
+  const T* __restrict__ xi = args.xi;
+  T M[C];
+#pragma unroll
+  for (int k = 0; k < C; ++k) M[k] = args.M[(size_t)k * args.stride + i];
+{contraction}
+  args.site[i] = V;
+}}
+
+{adjoint_kernels}
 template <typename T, bool COMP, bool WANT_B>
 hipError_t launch_t(const void* a, hipStream_t s) {{
   const auto& args = *static_cast<const mtp::EvalArgs<T>*>(a);
   if (args.n_atoms <= 0) return hipSuccess;
   const dim3 grid((args.n_atoms + BLOCK - 1) / BLOCK);
   const size_t smem = (size_t)args.n_c * sizeof(T);
-  hipLaunchKernelGGL((eval_kernel<T, COMP, WANT_B>), grid, dim3(BLOCK), smem, s, args);
+  hipLaunchKernelGGL((moments_kernel<T, COMP>), grid, dim3(BLOCK), smem, s, args);
+  hipLaunchKernelGGL((contract_kernel<T, WANT_B>), grid, dim3(BLOCK), 0, s, args);
+  if constexpr (sizeof(T) == 8) {{
+{launch_f64}
+  }} else {{
+{launch_f32}
+  }}
   return hipGetLastError();
 }}
 
@@ -363,13 +449,30 @@ def generate(lev_max, block=64):
     fwd, ops_f = emit_pair_forward(s, comp_mode=True)
     con, ops_c = emit_contraction(s)
     bwd, ops_b = emit_pair_backward(s)
+    adj_src, launches = [], {}
+    for prec, budget in (("f32", 10 ** 9), ("f64", 90)):
+        lines = []
+        passes = adjoint_passes(s, budget)
+        for pidx, (nus, comps) in enumerate(passes):
+            tag = f"{prec}_p{pidx}"
+            gmap = {k: j for j, k in enumerate(comps)}
+            body, _ = emit_pair_backward(s, nus=nus, gmap=gmap)
+            import re as _re
+            used = {int(v) for line in body for v in _re.findall(r"G\[(\d+)\]", line)}
+            assert used <= set(range(len(comps))), "adjoint pass reads a component outside its range"
+            adj_src.append(ADJOINT_TEMPLATE.format(pidx=pidx, nus=nus, tag=tag, ncomp=len(comps),
+                                                   comp_list=", ".join(map(str, comps)),
+                                                   body="\n".join(" " * 4 + l for l in body)))
+            lines.append(f"    hipLaunchKernelGGL((adjoint_{tag}_kernel<T, {'true' if pidx == 0 else 'false'}>), "
+                         f"grid, dim3(BLOCK), smem, s, args);")
+        launches[prec] = "\n".join(lines)
     # radial work per pair: distance 6, Chebyshev 3 per term, f_mu 2 per (mu, beta),
     # derivative pass adds dT and df
     nq = 8
     rad_f = 6 + 3 * (nq - 2) + 2 * s.n_mu * nq + 2 * s.n_mu
     rad_b = rad_f + 5 * (nq - 2) + 2 * s.n_mu * nq + 4 * s.n_mu + 2
     flops_pair_fwd = ops_f + rad_f
-    flops_pair_bwd = ops_b + rad_b + 18 + 1
+    flops_pair_bwd = ops_b + rad_b + 1
     graph_keys, graph_offsets = [], [0]
     for k in s.keys:
         graph_keys += list(k)
@@ -382,7 +485,8 @@ def generate(lev_max, block=64):
     src = KERNEL_TEMPLATE.format(
         level=lev_max, m=len(s.funcs), ngraphs=len(s.keys), C=s.C, n_mu=s.n_mu, nu_max=s.nu_max,
         block=block, ns=ns,
-        pair_fwd=ind(fwd, 4), contraction=ind(con, 4), pair_bwd=ind(bwd, 4),
+        pair_fwd=ind(fwd, 4), contraction=ind(con, 2), adjoint_kernels="\n".join(adj_src),
+        launch_f64=launches["f64"], launch_f32=launches["f32"],
         moments=", ".join(f"{mu}, {nu}" for mu, nu in s.moments),
         n_moments=len(s.moments),
         graph_offsets=", ".join(map(str, graph_offsets)),

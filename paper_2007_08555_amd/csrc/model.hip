@@ -99,7 +99,8 @@ struct mtp_model {
   Buffer ainv, gj_work, gj_flag;
   // workspace
   Buffer cfg, atom_cfg, atom_bin, bin_count, bin_start, bin_atoms, bin_fill, nbins_dev;
-  Buffer count, nbr, nbr_z, px, py, pz, rev, gx, gy, gz, site, wv, B, status;
+  Buffer count, nbr_row, nbr_z, px, py, pz, rev, gpair, Mbuf, Gbuf, site, wv, B, status;
+  int K = 64;  // neighbour capacity per atom, grown on overflow
   Buffer b_tmp, c_tmp;
   // statistics of the last evaluation
   int64_t last_atoms = 0, last_pairs = 0;
@@ -305,16 +306,18 @@ mtp::EvalArgs<T> make_args(mtp_model* M, int64_t n_atoms, int stride, const int3
   a.c = std::is_same<T, double>::value ? (const T*)M->c64.p : (const T*)M->c32.p;
   a.xi = std::is_same<T, double>::value ? (const T*)M->xi64.p : (const T*)M->xi32.p;
   a.site = M->site.as<T>();
-  a.gx = M->gx.as<T>();
-  a.gy = M->gy.as<T>();
-  a.gz = M->gz.as<T>();
+  a.M = M->Mbuf.as<T>();
+  a.G = M->Gbuf.as<T>();
+  a.g = M->gpair.as<T>();
   a.atom_virial = M->wv.as<T>();
   a.B = want_b ? M->B.as<T>() : nullptr;
   a.b_stride = stride;
   return a;
 }
 
-// Neighbour search, evaluation kernel, force gather and reductions.
+// Neighbour search, evaluation kernels, force gather and reductions, with
+// one host synchronisation at the end to read the status (and a second pass
+// if an atom had more neighbours than the current capacity).
 int run_eval(mtp_model* M, const mtp_batch* bt, const mtp_out* out, int precision, hipStream_t s) {
   using namespace mtp;
   const int64_t N = bt->n_atoms;
@@ -323,109 +326,102 @@ int run_eval(mtp_model* M, const mtp_batch* bt, const mtp_out* out, int precisio
   const size_t tsz = fp64 ? sizeof(double) : sizeof(float);
   M->timed = false;
   M->last_stream = s;
+  if (N > 0x7fffffffLL / 8) return fail(MTP_E_CAPACITY, "too many atoms in one batch");
   auto mark = [&](int k) -> hipError_t { return M->timing ? hipEventRecord(M->ev[k], s) : hipSuccess; };
-  HIP_TRY(mark(0), "hipEventRecord");
   HIP_TRY(M->status.ensure(sizeof(Status)), "hipMalloc");
-  HIP_TRY(hipMemsetAsync(M->status.p, 0, sizeof(Status), s), "hipMemsetAsync");
   if (n_cfg == 0) return MTP_OK;
   HIP_TRY(M->cfg.ensure(sizeof(CfgInfo) * n_cfg), "hipMalloc");
-  HIP_TRY(M->atom_cfg.ensure(sizeof(int32_t) * (N + 1)), "hipMalloc");
-  HIP_TRY(M->nbins_dev.ensure(sizeof(int64_t) * 2), "hipMalloc");
-  NbrArgs a{};
-  a.n_cfg = n_cfg;
-  a.n_atoms = N;
-  a.atom_offsets = bt->atom_offsets;
-  a.pos = bt->pos;
-  a.species = bt->species;
-  a.cell = bt->cell;
-  a.pbc = bt->pbc;
-  a.rcut = M->rcut;
-  a.rmin = M->rmin;
-  a.cfg = M->cfg.as<CfgInfo>();
-  a.atom_cfg = M->atom_cfg.as<int32_t>();
-  a.status = M->status.as<Status>();
-  a.fp64 = fp64 ? 1 : 0;
-  a.n_species = M->S;
-  if (N > 0x7fffffffLL / 4) return fail(MTP_E_CAPACITY, "too many atoms in one batch");
-  HIP_TRY(nbr_prepare(a, s), "neighbour prepare");
-  HIP_TRY(nbr_bin_offsets(a, M->nbins_dev.as<int64_t>(), s), "bin offsets");
-  int64_t n_bins = 0;
-  HIP_TRY(hipMemcpyAsync(&n_bins, M->nbins_dev.p, sizeof(int64_t), hipMemcpyDeviceToHost, s), "hipMemcpyAsync");
-  HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
-  a.n_bins = n_bins;
-  {
-    Status st0{};
-    HIP_TRY(hipMemcpyAsync(&st0, M->status.p, sizeof(Status), hipMemcpyDeviceToHost, s), "hipMemcpyAsync");
-    HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
-    if (st0.bad_offsets) return fail(MTP_E_ARG, "atom_offsets must be non-decreasing from 0 to n_atoms");
-  }
-  HIP_TRY(M->atom_bin.ensure(sizeof(int32_t) * (N + 1)), "hipMalloc");
-  HIP_TRY(M->bin_count.ensure(sizeof(int32_t) * (n_bins + 1)), "hipMalloc");
-  HIP_TRY(M->bin_start.ensure(sizeof(int32_t) * (n_bins + 1)), "hipMalloc");
-  HIP_TRY(M->bin_fill.ensure(sizeof(int32_t) * (n_bins + 1)), "hipMalloc");
-  HIP_TRY(M->bin_atoms.ensure(sizeof(int32_t) * (N + 1)), "hipMalloc");
-  HIP_TRY(M->count.ensure(sizeof(int32_t) * (N + 1)), "hipMalloc");
-  a.atom_bin = M->atom_bin.as<int32_t>();
-  a.bin_count = M->bin_count.as<int32_t>();
-  a.bin_start = M->bin_start.as<int32_t>();
-  a.bin_fill = M->bin_fill.as<int32_t>();
-  a.bin_atoms = M->bin_atoms.as<int32_t>();
-  a.count = M->count.as<int32_t>();
-  HIP_TRY(nbr_bin(a, s), "binning");
-  HIP_TRY(nbr_count(a, s), "neighbour count");
-  Status st{};
-  HIP_TRY(hipMemcpyAsync(&st, M->status.p, sizeof(Status), hipMemcpyDeviceToHost, s), "hipMemcpyAsync");
-  HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
-  if (st.bad_species) return fail(MTP_E_ARG, "species index outside [0, species_count)");
-  M->last_atoms = N;
-  M->last_pairs = (int64_t)st.n_pairs;
-  M->last_max_nb = (int32_t)st.max_count;
-  const int K = (int)std::max<unsigned long long>(1, st.max_count);
+  for (Buffer* b : {&M->atom_cfg, &M->atom_bin, &M->bin_count, &M->bin_start, &M->bin_fill, &M->bin_atoms,
+                    &M->count})
+    HIP_TRY(b->ensure(sizeof(int32_t) * (N + 1)), "hipMalloc");
   const int stride = (int)((N + 63) / 64 * 64);
-  const size_t slots = (size_t)K * stride;
-  a.K = K;
-  a.stride = stride;
-  HIP_TRY(M->nbr.ensure(sizeof(int32_t) * slots), "hipMalloc");
-  HIP_TRY(M->nbr_z.ensure(sizeof(int32_t) * slots), "hipMalloc");
-  HIP_TRY(M->rev.ensure(sizeof(int32_t) * slots), "hipMalloc");
-  HIP_TRY(M->px.ensure(tsz * slots), "hipMalloc");
-  HIP_TRY(M->py.ensure(tsz * slots), "hipMalloc");
-  HIP_TRY(M->pz.ensure(tsz * slots), "hipMalloc");
-  HIP_TRY(M->gx.ensure(tsz * slots), "hipMalloc");
-  HIP_TRY(M->gy.ensure(tsz * slots), "hipMalloc");
-  HIP_TRY(M->gz.ensure(tsz * slots), "hipMalloc");
-  HIP_TRY(M->site.ensure(tsz * stride), "hipMalloc");
-  HIP_TRY(M->wv.ensure(tsz * 9 * stride), "hipMalloc");
   const bool want_b = out->b != nullptr;
-  if (want_b) HIP_TRY(M->B.ensure(tsz * (size_t)M->m * stride), "hipMalloc");
-  a.nbr = M->nbr.as<int32_t>();
-  a.nbr_z = M->nbr_z.as<int32_t>();
-  a.px = M->px.p;
-  a.py = M->py.p;
-  a.pz = M->pz.p;
-  a.rev = M->rev.as<int32_t>();
-  HIP_TRY(nbr_fill(a, s), "neighbour fill");
-  HIP_TRY(mark(1), "hipEventRecord");
-  if (fp64) {
-    auto ea = make_args<double>(M, N, stride, bt->species, want_b);
-    HIP_TRY(M->var->launch_eval(precision, want_b, &ea, s), "evaluation kernel");
-  } else {
-    auto ea = make_args<float>(M, N, stride, bt->species, want_b);
-    HIP_TRY(M->var->launch_eval(precision, want_b, &ea, s), "evaluation kernel");
-  }
-  HIP_TRY(mark(2), "hipEventRecord");
-  if (out->forces)
-    HIP_TRY(gather_forces(fp64, N, stride, M->count.as<int32_t>(), M->rev.as<int32_t>(), M->gx.p, M->gy.p,
-                          M->gz.p, out->forces, s),
+  for (int attempt = 0; attempt < 2; ++attempt) {
+    const int K = M->K;
+    const size_t slots = (size_t)K * stride;
+    if (slots >= (size_t)0x7fffffff) return fail(MTP_E_CAPACITY, "neighbour slots exceed 2^31 (split the batch)");
+    HIP_TRY(M->nbr_row.ensure(sizeof(int32_t) * (size_t)K * (N + 1)), "hipMalloc");
+    HIP_TRY(M->nbr_z.ensure(sizeof(int32_t) * slots), "hipMalloc");
+    HIP_TRY(M->rev.ensure(sizeof(int32_t) * slots), "hipMalloc");
+    HIP_TRY(M->px.ensure(tsz * slots), "hipMalloc");
+    HIP_TRY(M->py.ensure(tsz * slots), "hipMalloc");
+    HIP_TRY(M->pz.ensure(tsz * slots), "hipMalloc");
+    HIP_TRY(M->gpair.ensure(tsz * 3 * slots), "hipMalloc");
+    HIP_TRY(M->Gbuf.ensure(tsz * (size_t)M->var->C * stride), "hipMalloc");
+    HIP_TRY(M->Mbuf.ensure(tsz * (size_t)M->var->C * stride), "hipMalloc");
+    HIP_TRY(M->site.ensure(tsz * stride), "hipMalloc");
+    HIP_TRY(M->wv.ensure(tsz * 9 * stride), "hipMalloc");
+    if (want_b) HIP_TRY(M->B.ensure(tsz * (size_t)M->m * stride), "hipMalloc");
+
+    HIP_TRY(mark(0), "hipEventRecord");
+    HIP_TRY(zero_words((int32_t*)M->status.p, sizeof(Status) / sizeof(int32_t), s), "status reset");
+    NbrArgs a{};
+    a.n_cfg = n_cfg;
+    a.n_atoms = N;
+    a.atom_offsets = bt->atom_offsets;
+    a.pos = bt->pos;
+    a.species = bt->species;
+    a.cell = bt->cell;
+    a.pbc = bt->pbc;
+    a.rcut = M->rcut;
+    a.rmin = M->rmin;
+    a.n_species = M->S;
+    a.cfg = M->cfg.as<CfgInfo>();
+    a.atom_cfg = M->atom_cfg.as<int32_t>();
+    a.atom_bin = M->atom_bin.as<int32_t>();
+    a.bin_count = M->bin_count.as<int32_t>();
+    a.bin_start = M->bin_start.as<int32_t>();
+    a.bin_fill = M->bin_fill.as<int32_t>();
+    a.bin_atoms = M->bin_atoms.as<int32_t>();
+    a.count = M->count.as<int32_t>();
+    a.stride = stride;
+    a.K = K;
+    a.nbr_row = M->nbr_row.as<int32_t>();
+    a.nbr_z = M->nbr_z.as<int32_t>();
+    a.px = M->px.p;
+    a.py = M->py.p;
+    a.pz = M->pz.p;
+    a.fp64 = fp64 ? 1 : 0;
+    a.rev = M->rev.as<int32_t>();
+    a.status = M->status.as<Status>();
+    HIP_TRY(nbr_build(a, s), "neighbour search");
+    HIP_TRY(mark(1), "hipEventRecord");
+    if (N > 0) {
+      if (fp64) {
+        auto ea = make_args<double>(M, N, stride, bt->species, want_b);
+        HIP_TRY(M->var->launch_eval(precision, want_b, &ea, s), "evaluation kernels");
+      } else {
+        auto ea = make_args<float>(M, N, stride, bt->species, want_b);
+        HIP_TRY(M->var->launch_eval(precision, want_b, &ea, s), "evaluation kernels");
+      }
+    }
+    HIP_TRY(mark(2), "hipEventRecord");
+    HIP_TRY(gather_forces(fp64, N, stride, M->count.as<int32_t>(), M->rev.as<int32_t>(), M->gpair.p, M->px.p,
+                          M->py.p, M->pz.p, out->forces, out->virial ? M->wv.p : nullptr, s),
             "force gather");
-  HIP_TRY(mark(3), "hipEventRecord");
-  HIP_TRY(reduce_configs(fp64, n_cfg, bt->atom_offsets, stride, M->site.p, M->wv.p, want_b ? M->B.p : nullptr,
-                         M->m, stride, M->perm_dev.as<int32_t>(), out->energy, out->virial, out->b,
-                         out->site_energy, s),
-          "reductions");
-  HIP_TRY(mark(4), "hipEventRecord");
-  M->timed = M->timing;
-  return MTP_OK;
+    HIP_TRY(mark(3), "hipEventRecord");
+    HIP_TRY(reduce_configs(fp64, n_cfg, M->cfg.as<CfgInfo>(), stride, M->site.p, out->virial ? M->wv.p : nullptr,
+                           want_b ? M->B.p : nullptr, M->m, stride, M->perm_dev.as<int32_t>(), out->energy,
+                           out->virial, out->b, out->site_energy, s),
+            "reductions");
+    HIP_TRY(mark(4), "hipEventRecord");
+    Status st{};
+    HIP_TRY(hipMemcpyAsync(&st, M->status.p, sizeof(Status), hipMemcpyDeviceToHost, s), "hipMemcpyAsync");
+    HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
+    if (st.bad_offsets) return fail(MTP_E_ARG, "atom_offsets must be non-decreasing from 0 to n_atoms");
+    if (st.bad_species) return fail(MTP_E_ARG, "species index outside [0, species_count)");
+    if (st.overflow) {
+      if (st.max_count > 4096) return fail(MTP_E_CAPACITY, "more than 4096 neighbours of one atom");
+      M->K = (int)((st.max_count + 7) / 8 * 8);
+      continue;
+    }
+    M->last_atoms = N;
+    M->last_pairs = (int64_t)st.n_pairs;
+    M->last_max_nb = (int32_t)st.max_count;
+    M->timed = M->timing;
+    return MTP_OK;
+  }
+  return fail(MTP_E_CAPACITY, "neighbour capacity did not converge");
 }
 
 }  // namespace

@@ -31,10 +31,10 @@ struct EvalArgs {
   const T* c;            // [n_mu][S][S][N_Q]
   const T* xi;           // [m] in the kernel's basis order
   T* site;               // [n_atoms]   site energies V_i
-  T* gx;                 // [K * stride] dV_i / dr_ij
-  T* gy;
-  T* gz;
-  T* atom_virial;        // [9][n_atoms]  sum_j g_a r_b
+  T* M;                  // [C][stride] moment components of every atom
+  T* G;                  // [C][stride] dV_i / dM (moment components)
+  T* g;                  // [K * stride][3] dV_i / dr_ij, packed per pair
+  T* atom_virial;        // [9][stride]  sum_j g_a r_b
   T* B;                  // [m][b_stride] optional basis values
   int b_stride;
 };

@@ -18,7 +18,7 @@ struct CfgInfo {
   int64_t bin0;     // first bin of this config in the global bin arrays
 };
 
-// Device counters read by mtp_status.
+// Device counters read by mtp_status and by mtp_eval after its kernels.
 struct Status {
   unsigned long long below_rmin;
   unsigned long long list_errors;
@@ -26,6 +26,7 @@ struct Status {
   unsigned long long bad_offsets; // atom_offsets not monotone from 0 to n_atoms
   unsigned long long bad_species; // species index outside [0, n_species)
   unsigned long long n_pairs;     // total neighbour pairs of the last search
+  unsigned long long overflow;    // atoms with more neighbours than the ELL capacity
 };
 
 struct NbrArgs {
@@ -41,40 +42,40 @@ struct NbrArgs {
   CfgInfo* cfg;          // [n_cfg]
   int32_t* atom_cfg;     // [n_atoms]
   int32_t* atom_bin;     // [n_atoms] global bin index (binned configs only)
-  int32_t* bin_count;    // [n_bins]
-  int32_t* bin_start;    // [n_bins + 1]
+  int32_t* bin_count;    // [n_atoms + 1]  bins of a binned config sit at its atom offset
+  int32_t* bin_start;    // [n_atoms + 1]
   int32_t* bin_atoms;    // [n_atoms] atoms sorted by bin, then index
-  int32_t* bin_fill;     // [n_bins] scratch cursor
-  int64_t n_bins;
-  int32_t* count;        // [n_atoms] neighbours per atom
+  int32_t* bin_fill;     // [n_atoms + 1] scratch cursor
+  int32_t* count;        // [n_atoms] neighbours per atom (clamped to K)
   int stride;            // ELL pitch (>= n_atoms)
-  int K;                 // ELL slots per atom (fill pass)
-  int32_t* nbr;          // [K * stride] home index of the neighbour
-  int32_t* nbr_z;        // [K * stride] its species
+  int K;                 // ELL slots per atom
+  int32_t* nbr_row;      // [n_atoms][K] neighbour home index, row-major per atom
+  int32_t* nbr_z;        // [K * stride] neighbour species
   void* px;              // [K * stride] pair vectors, FP32 or FP64
   void* py;
   void* pz;
   int fp64;              // pair vector type
-  int32_t* rev;          // [K * stride] flat ELL index of the reverse pair
+  int32_t* rev;          // [K * stride] ELL index of the reverse pair
   Status* status;
 };
 
-// Neighbour search.  Phase 1 prepares configs and bins and returns the
-// number of bins needed (host sync inside); phase 2 counts; phase 3 fills.
-hipError_t nbr_prepare(NbrArgs& a, hipStream_t s);   // fills cfg, atom_cfg
-hipError_t nbr_bin_offsets(NbrArgs& a, int64_t* n_bins_dev, hipStream_t s);
-hipError_t nbr_bin(NbrArgs& a, hipStream_t s);       // bins of binned configs
-hipError_t nbr_count(NbrArgs& a, hipStream_t s);     // count[], status->max_count
-hipError_t nbr_fill(NbrArgs& a, hipStream_t s);      // ELL arrays + reverse index
+// Neighbour search without host synchronisation: prepare configs and bins,
+// fill the ELL lists up to K slots (counting overflow), reverse indices.
+hipError_t nbr_build(NbrArgs& a, hipStream_t s);
 
-// Forces F_i = sum over slots (g_p - g_rev(p)); T = float or double.
+// Sets n 32-bit words to zero with a kernel (capturable, unlike memset nodes).
+hipError_t zero_words(int32_t* p, int64_t n, hipStream_t s);
+
+// Forces F_i = sum over slots (g_p - g_rev(p)) and per-atom virials
+// sum_p g_p (x) r_p; g packed [K * stride][3]; either output may be null.
 hipError_t gather_forces(int fp64, int64_t n_atoms, int stride, const int32_t* count,
-                         const int32_t* rev, const void* gx, const void* gy, const void* gz,
-                         double* forces, hipStream_t s);
+                         const int32_t* rev, const void* g, const void* px, const void* py,
+                         const void* pz, double* forces, void* atom_virial, hipStream_t s);
 
 // Per-configuration sums of site energies, virials and B (kernel order ->
-// file order through perm, which maps file index -> kernel index).
-hipError_t reduce_configs(int fp64, int n_cfg, const int64_t* atom_offsets, int stride,
+// file order through perm, which maps file index -> kernel index), over the
+// validated atom ranges of cfg.
+hipError_t reduce_configs(int fp64, int n_cfg, const CfgInfo* cfg, int stride,
                           const void* site, const void* atom_virial, const void* B, int m,
                           int b_stride, const int32_t* perm, double* energy, double* virial,
                           double* b, double* site_out, hipStream_t s);

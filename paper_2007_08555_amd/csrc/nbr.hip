@@ -5,13 +5,20 @@
 // Pair vectors are formed so that the reverse pair is the exact negation:
 // d = x_j - x_i is negated exactly when i and j swap, the fractional offset
 // s = d . L^{-1} and every image shift n . L change sign exactly, and
-// round-to-nearest is symmetric.  Hence |r_ij| == |r_ji| bit for bit, the
-// lists are symmetric, and the reverse of a pair is found by matching the
-// negated vector.
+// round-to-nearest is symmetric.  Hence |r_ij| == |r_ji| bit for bit and the
+// lists are symmetric.
 //
 // Small or free configurations are searched by brute force over atoms and
-// over the image box that can reach R_cut; large periodic boxes (at least
-// three bins of width >= R_cut along each lattice direction) use a cell list.
+// over the box of images that can reach R_cut; the entries of one neighbour
+// j are then contiguous and ordered by image n.  Large periodic boxes (at
+// least three bins of width >= R_cut along each lattice direction, so at most
+// one image of any atom is in range) use a cell list.  Either way the
+// reverse of the r-th entry of the run of j in i's list is the
+// (k - 1 - r)-th entry of the run of i in j's list (negation reverses the
+// image order), which gives the reverse index without comparing vectors.
+//
+// No host synchronisation: the lists have a fixed capacity of K slots per
+// atom and the number of atoms that exceed it is counted in the status.
 #include <hip/hip_runtime.h>
 #include <math.h>
 
@@ -29,17 +36,19 @@ __global__ void cfg_prepare_kernel(NbrArgs a) {
   CfgInfo c;
   c.start = a.atom_offsets[k];
   c.n = (int32_t)(a.atom_offsets[k + 1] - a.atom_offsets[k]);
-  const bool bad = a.atom_offsets[k + 1] < a.atom_offsets[k] || (k == 0 && a.atom_offsets[0] != 0) ||
-                   (k == a.n_cfg - 1 && a.atom_offsets[k + 1] != a.n_atoms) ||
-                   a.atom_offsets[k + 1] - a.atom_offsets[k] > 0x7fffffffLL;
+  const bool bad = a.atom_offsets[k + 1] < a.atom_offsets[k] || a.atom_offsets[k] < 0 ||
+                   a.atom_offsets[k + 1] > a.n_atoms || (k == 0 && a.atom_offsets[0] != 0) ||
+                   (k == a.n_cfg - 1 && a.atom_offsets[k + 1] != a.n_atoms);
   if (bad) {
+    // an invalid range is searched as empty; the call then fails
     atomicAdd(&a.status->bad_offsets, 1ull);
+    c.start = 0;
     c.n = 0;
   }
   c.pbc = a.pbc[k] ? 1 : 0;
   c.binned = 0;
   c.nb[0] = c.nb[1] = c.nb[2] = 1;
-  c.bin0 = 0;
+  c.bin0 = c.start;
   for (int t = 0; t < 9; ++t) {
     c.L[t] = a.cell[9 * k + t];
     c.inv[t] = 0.0;
@@ -64,41 +73,45 @@ __global__ void cfg_prepare_kernel(NbrArgs a) {
     const double cr[3] = {sqrt(c00 * c00 + c01 * c01 + c02 * c02),
                           sqrt(c10 * c10 + c11 * c11 + c12 * c12),
                           sqrt(c20 * c20 + c21 * c21 + c22 * c22)};
-    bool ok = c.n >= kBinnedMinAtoms;
+    int nb[3];
+    bool ok = c.n >= kBinnedMinAtoms && det != 0.0;
     for (int d = 0; d < 3; ++d) {
       const double spacing = fabs(det) / cr[d];
       c.w[d] = a.rcut / spacing;
-      const int nb = (int)floor(spacing / a.rcut);
-      c.nb[d] = nb < 1 ? 1 : (nb > 1024 ? 1024 : nb);
-      if (nb < 3) ok = false;
+      const double q = floor(spacing / a.rcut);
+      nb[d] = q > 1024.0 ? 1024 : (int)q;
+      if (nb[d] < 3) ok = false;
     }
-    c.binned = ok ? 1 : 0;
-    if (!ok) c.nb[0] = c.nb[1] = c.nb[2] = 1;
+    // the bins of a config live in its own atom range: at most n bins
+    while (ok && (int64_t)nb[0] * nb[1] * nb[2] > c.n) {
+      int d = nb[0] >= nb[1] ? (nb[0] >= nb[2] ? 0 : 2) : (nb[1] >= nb[2] ? 1 : 2);
+      if (nb[d] <= 3) ok = false;
+      else --nb[d];
+    }
+    if (ok) {
+      c.binned = 1;
+      c.nb[0] = nb[0];
+      c.nb[1] = nb[1];
+      c.nb[2] = nb[2];
+    }
   }
   a.cfg[k] = c;
-}
-
-// Prefix sum of bins over binned configs (one thread; configs are few
-// thousand at most) and the total in *n_bins.
-__global__ void bin_offsets_kernel(NbrArgs a, int64_t* n_bins) {
-  int64_t acc = 0;
-  for (int k = 0; k < a.n_cfg; ++k) {
-    CfgInfo& c = a.cfg[k];
-    c.bin0 = acc;
-    if (c.binned) acc += (int64_t)c.nb[0] * c.nb[1] * c.nb[2];
-  }
-  *n_bins = acc;
 }
 
 __global__ void atom_cfg_kernel(NbrArgs a) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= a.n_atoms) return;
-  int lo = 0, hi = a.n_cfg;  // find k with offsets[k] <= i < offsets[k+1]
+  int lo = 0, hi = a.n_cfg;  // k with offsets[k] <= i < offsets[k+1] when the offsets are valid
   while (hi - lo > 1) {
     const int mid = (lo + hi) >> 1;
     if (a.atom_offsets[mid] <= i) lo = mid; else hi = mid;
   }
   a.atom_cfg[i] = lo;
+}
+
+__global__ void zero_kernel(int32_t* p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0;
 }
 
 __device__ inline int3 bin_of(const CfgInfo& c, double x, double y, double z) {
@@ -112,11 +125,13 @@ __device__ inline int3 bin_of(const CfgInfo& c, double x, double y, double z) {
   return make_int3(b[0], b[1], b[2]);
 }
 
+__device__ inline bool in_cfg(const CfgInfo& c, int64_t i) { return i >= c.start && i < c.start + c.n; }
+
 __global__ void bin_count_kernel(NbrArgs a) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= a.n_atoms) return;
   const CfgInfo& c = a.cfg[a.atom_cfg[i]];
-  if (!c.binned) {
+  if (!c.binned || !in_cfg(c, i)) {
     a.atom_bin[i] = -1;
     return;
   }
@@ -126,34 +141,39 @@ __global__ void bin_count_kernel(NbrArgs a) {
   atomicAdd(&a.bin_count[flat], 1);
 }
 
-// Exclusive scan of bin counts, one block.
-__global__ void bin_scan_kernel(NbrArgs a) {
-  __shared__ int32_t part[1024];
+// Exclusive scan of the bin counts of one binned configuration (one block
+// per configuration; the others return at once).  Bin b of a configuration
+// starting at atom `start` lists its atoms at bin_atoms[bin_start[b] ..
+// bin_start[b + 1]), inside [start, start + n).
+__global__ void __launch_bounds__(256) bin_scan_kernel(NbrArgs a) {
+  __shared__ int32_t part[256];
+  __shared__ int32_t carry;
+  const CfgInfo& c = a.cfg[blockIdx.x];
+  if (!c.binned) return;
   const int t = threadIdx.x;
-  const int64_t n = a.n_bins;
-  const int64_t per = (n + blockDim.x - 1) / blockDim.x;
-  const int64_t lo = t * per, hi = lo + per < n ? lo + per : n;
-  int32_t s = 0;
-  for (int64_t b = lo; b < hi; ++b) s += a.bin_count[b];
-  part[t] = s;
+  const int64_t nbins = (int64_t)c.nb[0] * c.nb[1] * c.nb[2];
+  if (t == 0) carry = (int32_t)c.start;
   __syncthreads();
-  if (t == 0) {
-    int32_t acc = 0;
-    for (int u = 0; u < (int)blockDim.x; ++u) {
-      const int32_t v = part[u];
-      part[u] = acc;
-      acc += v;
+  for (int64_t base = 0; base < nbins; base += blockDim.x) {
+    const int64_t b = c.bin0 + base + t;
+    const int32_t v = base + t < nbins ? a.bin_count[b] : 0;
+    part[t] = v;
+    __syncthreads();
+    for (int w = 1; w < (int)blockDim.x; w <<= 1) {  // inclusive Hillis-Steele scan
+      const int32_t u = t >= w ? part[t - w] : 0;
+      __syncthreads();
+      part[t] += u;
+      __syncthreads();
     }
+    if (base + t < nbins) {
+      a.bin_start[b] = carry + part[t] - v;
+      a.bin_fill[b] = 0;
+    }
+    __syncthreads();
+    if (t == (int)blockDim.x - 1) carry += part[t];
+    __syncthreads();
   }
-  __syncthreads();
-  int32_t acc = part[t];
-  for (int64_t b = lo; b < hi; ++b) {
-    a.bin_start[b] = acc;
-    acc += a.bin_count[b];
-    a.bin_fill[b] = 0;
-  }
-  if (hi == n && lo < hi) a.bin_start[n] = acc;
-  if (n == 0 && t == 0) a.bin_start[0] = 0;
+  if (t == 0) a.bin_start[c.bin0 + nbins] = carry;
 }
 
 __global__ void bin_fill_kernel(NbrArgs a) {
@@ -169,9 +189,13 @@ __global__ void bin_fill_kernel(NbrArgs a) {
 // order in which atomics landed.
 __global__ void bin_sort_kernel(NbrArgs a) {
   const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= a.n_bins) return;
-  int32_t* v = a.bin_atoms + a.bin_start[b];
+  if (b >= a.n_atoms) return;
+  // bins of a binned configuration occupy the first nb0 nb1 nb2 indices of its atom range
+  const CfgInfo& c = a.cfg[a.atom_cfg[b]];
+  if (!c.binned || b < c.bin0 || b >= c.bin0 + (int64_t)c.nb[0] * c.nb[1] * c.nb[2]) return;
   const int n = a.bin_start[b + 1] - a.bin_start[b];
+  if (n < 2) return;
+  int32_t* v = a.bin_atoms + a.bin_start[b];
   for (int x = 1; x < n; ++x) {
     const int32_t key = v[x];
     int y = x - 1;
@@ -183,17 +207,19 @@ __global__ void bin_sort_kernel(NbrArgs a) {
   }
 }
 
-template <bool FILL>
 struct Emitter {
   NbrArgs& a;
   int64_t i;
   int count;
   double rmin2;
+  int below;
   __device__ void operator()(int32_t j, double rx, double ry, double rz, double r2) {
-    if (FILL && count < a.K) {
+    if (count < a.K) {
       const size_t e = (size_t)count * a.stride + i;
-      a.nbr[e] = j;
-      a.nbr_z[e] = a.species[j];
+      int zj = a.species[j];
+      zj = zj < 0 ? 0 : (zj >= a.n_species ? a.n_species - 1 : zj);
+      a.nbr_z[e] = zj;
+      a.nbr_row[(size_t)i * a.K + count] = j;
       if (a.fp64) {
         ((double*)a.px)[e] = rx;
         ((double*)a.py)[e] = ry;
@@ -203,151 +229,160 @@ struct Emitter {
         ((float*)a.py)[e] = (float)ry;
         ((float*)a.pz)[e] = (float)rz;
       }
-      if (r2 < rmin2) atomicAdd(&a.status->below_rmin, 1ull);
     }
+    if (r2 < rmin2) ++below;
     ++count;
   }
 };
 
-template <bool FILL>
+// Sum and max over the 64 lanes of a wavefront (every lane must call it).
+__device__ inline int wave_sum(int v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ inline int wave_max(int v) {
+  for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
 __global__ void __launch_bounds__(kBlock) search_kernel(NbrArgs a) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= a.n_atoms) return;
-  if (!FILL && (a.species[i] < 0 || a.species[i] >= a.n_species)) atomicAdd(&a.status->bad_species, 1ull);
+  const bool active = i < a.n_atoms;
+  Emitter emit{a, i, 0, a.rmin * a.rmin, 0};
+  int bad = 0;
+  if (active) {
+  if (a.species[i] < 0 || a.species[i] >= a.n_species) bad = 1;
   const CfgInfo& c = a.cfg[a.atom_cfg[i]];
-  const double xi = a.pos[3 * i], yi = a.pos[3 * i + 1], zi = a.pos[3 * i + 2];
-  const double rc2 = a.rcut * a.rcut;
-  Emitter<FILL> emit{a, i, 0, a.rmin * a.rmin};
-  const double* L = c.L;
-  const double* inv = c.inv;
-  if (!c.binned) {
-    const int64_t j0 = c.start, j1 = c.start + c.n;
-    for (int64_t j = j0; j < j1; ++j) {
-      const double dx = a.pos[3 * j] - xi, dy = a.pos[3 * j + 1] - yi, dz = a.pos[3 * j + 2] - zi;
-      if (!c.pbc) {
-        const double r2 = dx * dx + dy * dy + dz * dz;
-        if (j != i && r2 < rc2) emit((int32_t)j, dx, dy, dz, r2);
-        continue;
+  if (in_cfg(c, i)) {
+    const double xi = a.pos[3 * i], yi = a.pos[3 * i + 1], zi = a.pos[3 * i + 2];
+    const double rc2 = a.rcut * a.rcut;
+    const double* L = c.L;
+    const double* inv = c.inv;
+    if (!c.binned) {
+      const int64_t j0 = c.start, j1 = c.start + c.n;
+      for (int64_t j = j0; j < j1; ++j) {
+        const double dx = a.pos[3 * j] - xi, dy = a.pos[3 * j + 1] - yi, dz = a.pos[3 * j + 2] - zi;
+        if (!c.pbc) {
+          const double r2 = dx * dx + dy * dy + dz * dz;
+          if (j != i && r2 < rc2) emit((int32_t)j, dx, dy, dz, r2);
+          continue;
+        }
+        // images with |s_d + n_d| <= w_d can lie within R_cut
+        int lo[3], hi[3];
+        for (int d = 0; d < 3; ++d) {
+          const double s = dx * inv[0 * 3 + d] + dy * inv[1 * 3 + d] + dz * inv[2 * 3 + d];
+          lo[d] = -(int)floor(c.w[d] + s + 1e-9);
+          hi[d] = (int)floor(c.w[d] - s + 1e-9);
+        }
+        for (int n0 = lo[0]; n0 <= hi[0]; ++n0)
+          for (int n1 = lo[1]; n1 <= hi[1]; ++n1)
+            for (int n2 = lo[2]; n2 <= hi[2]; ++n2) {
+              if (j == i && n0 == 0 && n1 == 0 && n2 == 0) continue;
+              const double sx = (double)n0 * L[0] + (double)n1 * L[3] + (double)n2 * L[6];
+              const double sy = (double)n0 * L[1] + (double)n1 * L[4] + (double)n2 * L[7];
+              const double sz = (double)n0 * L[2] + (double)n1 * L[5] + (double)n2 * L[8];
+              const double rx = dx + sx, ry = dy + sy, rz = dz + sz;
+              const double r2 = rx * rx + ry * ry + rz * rz;
+              if (r2 < rc2) emit((int32_t)j, rx, ry, rz, r2);
+            }
       }
-      int lo[3], hi[3];
-      for (int d = 0; d < 3; ++d) {
-        const double s = dx * inv[0 * 3 + d] + dy * inv[1 * 3 + d] + dz * inv[2 * 3 + d];
-        lo[d] = -(int)floor(c.w[d] + s + 1e-9);
-        hi[d] = (int)floor(c.w[d] - s + 1e-9);
-      }
-      for (int n0 = lo[0]; n0 <= hi[0]; ++n0)
-        for (int n1 = lo[1]; n1 <= hi[1]; ++n1)
-          for (int n2 = lo[2]; n2 <= hi[2]; ++n2) {
-            if (j == i && n0 == 0 && n1 == 0 && n2 == 0) continue;
-            const double sx = (double)n0 * L[0] + (double)n1 * L[3] + (double)n2 * L[6];
-            const double sy = (double)n0 * L[1] + (double)n1 * L[4] + (double)n2 * L[7];
-            const double sz = (double)n0 * L[2] + (double)n1 * L[5] + (double)n2 * L[8];
-            const double rx = dx + sx, ry = dy + sy, rz = dz + sz;
-            const double r2 = rx * rx + ry * ry + rz * rz;
-            if (r2 < rc2) emit((int32_t)j, rx, ry, rz, r2);
+    } else {
+      const int3 b = bin_of(c, xi, yi, zi);
+      for (int ox = -1; ox <= 1; ++ox)
+        for (int oy = -1; oy <= 1; ++oy)
+          for (int oz = -1; oz <= 1; ++oz) {
+            const int bx = (b.x + ox + c.nb[0]) % c.nb[0];
+            const int by = (b.y + oy + c.nb[1]) % c.nb[1];
+            const int bz = (b.z + oz + c.nb[2]) % c.nb[2];
+            const int64_t flat = c.bin0 + ((int64_t)bx * c.nb[1] + by) * c.nb[2] + bz;
+            const int32_t s0 = a.bin_start[flat], s1 = a.bin_start[flat + 1];
+            for (int32_t t = s0; t < s1; ++t) {
+              const int32_t j = a.bin_atoms[t];
+              if (j == i) continue;
+              const double dx = a.pos[3 * j] - xi, dy = a.pos[3 * j + 1] - yi, dz = a.pos[3 * j + 2] - zi;
+              double n[3];
+              for (int d = 0; d < 3; ++d)
+                n[d] = -rint(dx * inv[0 * 3 + d] + dy * inv[1 * 3 + d] + dz * inv[2 * 3 + d]);
+              const double rx = dx + (n[0] * L[0] + n[1] * L[3] + n[2] * L[6]);
+              const double ry = dy + (n[0] * L[1] + n[1] * L[4] + n[2] * L[7]);
+              const double rz = dz + (n[0] * L[2] + n[1] * L[5] + n[2] * L[8]);
+              const double r2 = rx * rx + ry * ry + rz * rz;
+              if (r2 < rc2) emit(j, rx, ry, rz, r2);
+            }
           }
     }
-  } else {
-    const int3 b = bin_of(c, xi, yi, zi);
-    for (int ox = -1; ox <= 1; ++ox)
-      for (int oy = -1; oy <= 1; ++oy)
-        for (int oz = -1; oz <= 1; ++oz) {
-          const int bx = (b.x + ox + c.nb[0]) % c.nb[0];
-          const int by = (b.y + oy + c.nb[1]) % c.nb[1];
-          const int bz = (b.z + oz + c.nb[2]) % c.nb[2];
-          const int64_t flat = c.bin0 + ((int64_t)bx * c.nb[1] + by) * c.nb[2] + bz;
-          const int32_t s0 = a.bin_start[flat], s1 = a.bin_start[flat + 1];
-          for (int32_t t = s0; t < s1; ++t) {
-            const int32_t j = a.bin_atoms[t];
-            if (j == i) continue;
-            const double dx = a.pos[3 * j] - xi, dy = a.pos[3 * j + 1] - yi, dz = a.pos[3 * j + 2] - zi;
-            double n[3];
-            for (int d = 0; d < 3; ++d)
-              n[d] = -rint(dx * inv[0 * 3 + d] + dy * inv[1 * 3 + d] + dz * inv[2 * 3 + d]);
-            const double rx = dx + (n[0] * L[0] + n[1] * L[3] + n[2] * L[6]);
-            const double ry = dy + (n[0] * L[1] + n[1] * L[4] + n[2] * L[7]);
-            const double rz = dz + (n[0] * L[2] + n[1] * L[5] + n[2] * L[8]);
-            const double r2 = rx * rx + ry * ry + rz * rz;
-            if (r2 < rc2) emit(j, rx, ry, rz, r2);
-          }
-        }
   }
-  a.count[i] = FILL ? (emit.count < a.K ? emit.count : a.K) : emit.count;
-  if (!FILL) {
-    atomicMax(&a.status->max_count, (unsigned long long)emit.count);
-    atomicAdd(&a.status->n_pairs, (unsigned long long)emit.count);
+  a.count[i] = emit.count < a.K ? emit.count : a.K;
+  }
+  // one atomic per wavefront and counter
+  const int cmax = wave_max(emit.count);
+  const int csum = wave_sum(emit.count);
+  const int over = wave_sum(emit.count > a.K ? 1 : 0);
+  const int below = wave_sum(emit.below);
+  const int nbad = wave_sum(bad);
+  if ((threadIdx.x & 63) == 0) {
+    atomicMax(&a.status->max_count, (unsigned long long)cmax);
+    atomicAdd(&a.status->n_pairs, (unsigned long long)csum);
+    if (over) atomicAdd(&a.status->overflow, (unsigned long long)over);
+    if (below) atomicAdd(&a.status->below_rmin, (unsigned long long)below);
+    if (nbad) atomicAdd(&a.status->bad_species, (unsigned long long)nbad);
   }
 }
 
-template <typename T>
+// rev[p, i] for every stored pair; see the file comment for the rule.
 __global__ void reverse_kernel(NbrArgs a) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int p = blockIdx.y;
   if (i >= a.n_atoms || p >= a.count[i]) return;
   const size_t e = (size_t)p * a.stride + i;
-  const int32_t j = a.nbr[e];
-  const T* px = (const T*)a.px;
-  const T* py = (const T*)a.py;
-  const T* pz = (const T*)a.pz;
-  const T rx = -px[e], ry = -py[e], rz = -pz[e];
+  const int32_t* row_i = a.nbr_row + (size_t)i * a.K;
+  const int32_t j = row_i[p];
+  int rank = 0;
+  while (p - rank - 1 >= 0 && row_i[p - rank - 1] == j) ++rank;
+  const int32_t* row_j = a.nbr_row + (size_t)j * a.K;
   const int cj = a.count[j];
-  for (int q = 0; q < cj; ++q) {
-    const size_t f = (size_t)q * a.stride + j;
-    if (a.nbr[f] == (int32_t)i && px[f] == rx && py[f] == ry && pz[f] == rz) {
-      a.rev[e] = (int32_t)f;
-      return;
+  int q0 = 0;
+  if (a.cfg[a.atom_cfg[i]].binned) {
+    while (q0 < cj && row_j[q0] != (int32_t)i) ++q0;        // one image per atom
+  } else {
+    int hi = cj;                                             // rows ascend in neighbour index
+    while (q0 < hi) {
+      const int mid = (q0 + hi) >> 1;
+      if (row_j[mid] < (int32_t)i) q0 = mid + 1; else hi = mid;
     }
   }
-  a.rev[e] = (int32_t)e;
-  atomicAdd(&a.status->list_errors, 1ull);
+  int k = 0;
+  while (q0 + k < cj && row_j[q0 + k] == (int32_t)i) ++k;
+  if (k > rank) {
+    a.rev[e] = (int32_t)((size_t)(q0 + k - 1 - rank) * a.stride + j);
+  } else {
+    a.rev[e] = (int32_t)e;
+    atomicAdd(&a.status->list_errors, 1ull);
+  }
 }
 
 inline dim3 grid_for(int64_t n) { return dim3((unsigned)((n + kBlock - 1) / kBlock)); }
 
 }  // namespace
 
-hipError_t nbr_prepare(NbrArgs& a, hipStream_t s) {
+hipError_t zero_words(int32_t* p, int64_t n, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(zero_kernel, grid_for(n), dim3(kBlock), 0, s, p, n);
+  return hipGetLastError();
+}
+
+hipError_t nbr_build(NbrArgs& a, hipStream_t s) {
   if (a.n_cfg > 0)
     hipLaunchKernelGGL(cfg_prepare_kernel, grid_for(a.n_cfg), dim3(kBlock), 0, s, a);
-  if (a.n_atoms > 0)
-    hipLaunchKernelGGL(atom_cfg_kernel, grid_for(a.n_atoms), dim3(kBlock), 0, s, a);
-  return hipGetLastError();
-}
-
-hipError_t nbr_bin(NbrArgs& a, hipStream_t s) {
-  // caller has set n_bins and sized the bin arrays; bin_count must be zeroed
-  if (a.n_atoms == 0) return hipSuccess;
-  hipError_t e = hipMemsetAsync(a.bin_count, 0, sizeof(int32_t) * (a.n_bins + 1), s);
-  if (e != hipSuccess) return e;
+  if (a.n_atoms == 0) return hipGetLastError();
+  hipLaunchKernelGGL(atom_cfg_kernel, grid_for(a.n_atoms), dim3(kBlock), 0, s, a);
+  hipLaunchKernelGGL(zero_kernel, grid_for(a.n_atoms + 1), dim3(kBlock), 0, s, a.bin_count, a.n_atoms + 1);
   hipLaunchKernelGGL(bin_count_kernel, grid_for(a.n_atoms), dim3(kBlock), 0, s, a);
-  hipLaunchKernelGGL(bin_scan_kernel, dim3(1), dim3(1024), 0, s, a);
+  if (a.n_cfg > 0) hipLaunchKernelGGL(bin_scan_kernel, dim3(a.n_cfg), dim3(256), 0, s, a);
   hipLaunchKernelGGL(bin_fill_kernel, grid_for(a.n_atoms), dim3(kBlock), 0, s, a);
-  if (a.n_bins > 0)
-    hipLaunchKernelGGL(bin_sort_kernel, grid_for(a.n_bins), dim3(kBlock), 0, s, a);
-  return hipGetLastError();
-}
-
-hipError_t nbr_bin_offsets(NbrArgs& a, int64_t* n_bins_dev, hipStream_t s) {
-  hipLaunchKernelGGL(bin_offsets_kernel, dim3(1), dim3(1), 0, s, a, n_bins_dev);
-  return hipGetLastError();
-}
-
-hipError_t nbr_count(NbrArgs& a, hipStream_t s) {
-  if (a.n_atoms == 0) return hipSuccess;
-  hipLaunchKernelGGL(search_kernel<false>, grid_for(a.n_atoms), dim3(kBlock), 0, s, a);
-  return hipGetLastError();
-}
-
-hipError_t nbr_fill(NbrArgs& a, hipStream_t s) {
-  if (a.n_atoms == 0) return hipSuccess;
-  hipLaunchKernelGGL(search_kernel<true>, grid_for(a.n_atoms), dim3(kBlock), 0, s, a);
-  if (a.K > 0) {
-    const dim3 g((unsigned)((a.n_atoms + kBlock - 1) / kBlock), (unsigned)a.K);
-    if (a.fp64)
-      hipLaunchKernelGGL(reverse_kernel<double>, g, dim3(kBlock), 0, s, a);
-    else
-      hipLaunchKernelGGL(reverse_kernel<float>, g, dim3(kBlock), 0, s, a);
-  }
+  hipLaunchKernelGGL(bin_sort_kernel, grid_for(a.n_atoms), dim3(kBlock), 0, s, a);
+  hipLaunchKernelGGL(search_kernel, grid_for(a.n_atoms), dim3(kBlock), 0, s, a);
+  const dim3 g((unsigned)((a.n_atoms + kBlock - 1) / kBlock), (unsigned)a.K);
+  hipLaunchKernelGGL(reverse_kernel, g, dim3(kBlock), 0, s, a);
   return hipGetLastError();
 }
 
