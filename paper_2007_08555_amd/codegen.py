@@ -180,6 +180,9 @@ def emit_contraction(s):
             ops += len(rest) + 1 + (1 if n > 1 else 0)
     for g in range(len(s.terms)):
         out.append(f"const T dg{g} = " + (" + ".join(dg[g]) if dg[g] else "T(0)") + ";")
+    # keep the products of the forward sweep from being reused (and held in
+    # registers) by the reverse sweep: M is opaque to the optimiser from here
+    out.append("mtp::opaque(M);")
     # reverse of the graph terms, gathered per component so that each
     # G[k] is complete when written and nothing but M stays live
     contrib = defaultdict(lambda: defaultdict(list))
@@ -207,6 +210,8 @@ def emit_contraction(s):
             parts.append(f"dg{g} * (" + " + ".join(inner) + ")")
             ops += 1
         out.append(f"args.G[(size_t){k} * args.stride + i] = " + " + ".join(parts) + ";")
+        if k % 2 == 1:
+            out.append("mtp::opaque(M);")
     return out, ops
 
 
@@ -303,11 +308,24 @@ __global__ void __launch_bounds__(BLOCK) adjoint_{tag}_kernel(const mtp::EvalArg
   T G[CP];
 #pragma unroll
   for (int k = 0; k < CP; ++k) G[k] = args.G[(size_t)kIdx[k] * args.stride + i];
+  // pair p + 1 (and its partial g) is loaded while pair p is processed
+  T xn = T(0), yn = T(0), zn = T(0), g0n = T(0), g1n = T(0), g2n = T(0);
+  int zjn = 0;
+  if (cnt > 0) {{
+    xn = args.px[i]; yn = args.py[i]; zn = args.pz[i]; zjn = args.pzj[i];
+    if (!FIRST) {{ g0n = args.g[3 * (size_t)i]; g1n = args.g[3 * (size_t)i + 1]; g2n = args.g[3 * (size_t)i + 2]; }}
+  }}
 #pragma unroll 1
   for (int p = 0; p < cnt; ++p) {{
     const size_t e = (size_t)p * args.stride + i;
-    const T x = args.px[e], y = args.py[e], z = args.pz[e];
-    const int zj = args.pzj[e];
+    const T x = xn, y = yn, z = zn;
+    const int zj = zjn;
+    const T gp0 = g0n, gp1 = g1n, gp2 = g2n;
+    if (p + 1 < cnt) {{
+      const size_t en = e + args.stride;
+      xn = args.px[en]; yn = args.py[en]; zn = args.pz[en]; zjn = args.pzj[en];
+      if (!FIRST) {{ g0n = args.g[3 * en]; g1n = args.g[3 * en + 1]; g2n = args.g[3 * en + 2]; }}
+    }}
     const T r = sqrt(x * x + y * y + z * z);
     const T inv_r = T(1) / r;
     T f[NMU], df[NMU];
@@ -318,9 +336,9 @@ __global__ void __launch_bounds__(BLOCK) adjoint_{tag}_kernel(const mtp::EvalArg
       args.g[3 * e + 1] = gy;
       args.g[3 * e + 2] = gz;
     }} else {{
-      args.g[3 * e] += gx;
-      args.g[3 * e + 1] += gy;
-      args.g[3 * e + 2] += gz;
+      args.g[3 * e] = gp0 + gx;
+      args.g[3 * e + 1] = gp1 + gy;
+      args.g[3 * e + 2] = gp2 + gz;
     }}
   }}
 }}
@@ -366,11 +384,20 @@ __global__ void __launch_bounds__(BLOCK) moments_kernel(const mtp::EvalArgs<T> a
 #pragma unroll
   for (int k = 0; k < (COMP ? C : 1); ++k) Mlo[k] = T(0);
 
+  // pair p + 1 is loaded while pair p is processed
+  T xn = T(0), yn = T(0), zn = T(0);
+  int zjn = 0;
+  if (cnt > 0) {{
+    xn = args.px[i]; yn = args.py[i]; zn = args.pz[i]; zjn = args.pzj[i];
+  }}
 #pragma unroll 1
   for (int p = 0; p < cnt; ++p) {{
-    const size_t e = (size_t)p * args.stride + i;
-    const T x = args.px[e], y = args.py[e], z = args.pz[e];
-    const int zj = args.pzj[e];
+    const T x = xn, y = yn, z = zn;
+    const int zj = zjn;
+    if (p + 1 < cnt) {{
+      const size_t en = (size_t)(p + 1) * args.stride + i;
+      xn = args.px[en]; yn = args.py[en]; zn = args.pz[en]; zjn = args.pzj[en];
+    }}
     const T r = sqrt(x * x + y * y + z * z);
     T f[NMU], df[NMU];
     mtp::radial<T, NMU, false>(cs, (zi * S + zj) * nq, mu_stride, nq, r, rmin, rcut, f, df);

@@ -81,6 +81,15 @@ __device__ __forceinline__ void radial(const T* __restrict__ cs, int base, int m
   }
 }
 
+// Makes the values of a register array opaque to the optimiser (an empty asm
+// that may rewrite them), so that products formed before it are not kept
+// alive to be reused after it.
+template <typename T, int N>
+__device__ __forceinline__ void opaque(T (&v)[N]) {
+#pragma unroll
+  for (int k = 0; k < N; ++k) asm volatile("" : "+v"(v[k]));
+}
+
 // Error-free sum (Knuth's TwoSum): hi + lo carries the accumulated sum.
 template <typename T>
 __device__ __forceinline__ void two_sum_acc(T& hi, T& lo, T v) {

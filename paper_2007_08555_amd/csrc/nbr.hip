@@ -29,6 +29,10 @@ namespace {
 
 constexpr int kBlock = 256;
 constexpr int kBinnedMinAtoms = 2048;
+constexpr int kSmallMax = 1024;   // configurations searched by one workgroup from LDS
+constexpr int kSmallBlock = 128;
+
+__device__ inline bool is_small(const CfgInfo& c) { return !c.binned && c.n <= kSmallMax; }
 
 __global__ void cfg_prepare_kernel(NbrArgs a) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
@@ -247,7 +251,9 @@ __device__ inline int wave_max(int v) {
 
 __global__ void __launch_bounds__(kBlock) search_kernel(NbrArgs a) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const bool active = i < a.n_atoms;
+  // atoms of small configurations are searched by search_small_kernel; every
+  // lane stays to the end for the wavefront reductions
+  const bool active = i < a.n_atoms && !(is_small(a.cfg[a.atom_cfg[i]]) && in_cfg(a.cfg[a.atom_cfg[i]], i));
   Emitter emit{a, i, 0, a.rmin * a.rmin, 0};
   int bad = 0;
   if (active) {
@@ -320,7 +326,7 @@ __global__ void __launch_bounds__(kBlock) search_kernel(NbrArgs a) {
   const int over = wave_sum(emit.count > a.K ? 1 : 0);
   const int below = wave_sum(emit.below);
   const int nbad = wave_sum(bad);
-  if ((threadIdx.x & 63) == 0) {
+  if ((threadIdx.x & 63) == 0 && (csum || nbad)) {
     atomicMax(&a.status->max_count, (unsigned long long)cmax);
     atomicAdd(&a.status->n_pairs, (unsigned long long)csum);
     if (over) atomicAdd(&a.status->overflow, (unsigned long long)over);
@@ -334,6 +340,7 @@ __global__ void reverse_kernel(NbrArgs a) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int p = blockIdx.y;
   if (i >= a.n_atoms || p >= a.count[i]) return;
+  if (is_small(a.cfg[a.atom_cfg[i]]) && in_cfg(a.cfg[a.atom_cfg[i]], i)) return;
   const size_t e = (size_t)p * a.stride + i;
   const int32_t* row_i = a.nbr_row + (size_t)i * a.K;
   const int32_t j = row_i[p];
@@ -361,6 +368,126 @@ __global__ void reverse_kernel(NbrArgs a) {
   }
 }
 
+
+// Whole search of one small configuration in one workgroup: positions staged
+// in LDS, lists written to the ELL arrays, then (after a barrier) the reverse
+// index of every pair of the configuration.
+__global__ void __launch_bounds__(kSmallBlock) search_small_kernel(NbrArgs a) {
+  __shared__ double sp[3 * kSmallMax];
+  __shared__ unsigned long long red[5];
+  const CfgInfo c = a.cfg[blockIdx.x];
+  if (!is_small(c)) return;
+  const int t = threadIdx.x;
+  const int n = c.n;
+  if (t < 5) red[t] = 0;
+  for (int q = t; q < 3 * n; q += blockDim.x) sp[q] = a.pos[3 * c.start + q];
+  __syncthreads();
+  const double rc2 = a.rcut * a.rcut;
+  const double rmin2 = a.rmin * a.rmin;
+  const double* L = c.L;
+  const double* inv = c.inv;
+  int cmax = 0, csum = 0, over = 0, below = 0, bad = 0;
+  for (int li = t; li < n; li += blockDim.x) {
+    const int64_t i = c.start + li;
+    if (a.species[i] < 0 || a.species[i] >= a.n_species) ++bad;
+    const double xi = sp[3 * li], yi = sp[3 * li + 1], zi = sp[3 * li + 2];
+    int count = 0;
+    int32_t* row = a.nbr_row + (size_t)i * a.K;
+    auto emit = [&](int lj, double rx, double ry, double rz, double r2) {
+      if (count < a.K) {
+        const size_t e = (size_t)count * a.stride + i;
+        const int64_t j = c.start + lj;
+        int zj = a.species[j];
+        zj = zj < 0 ? 0 : (zj >= a.n_species ? a.n_species - 1 : zj);
+        a.nbr_z[e] = zj;
+        row[count] = (int32_t)j;
+        if (a.fp64) {
+          ((double*)a.px)[e] = rx;
+          ((double*)a.py)[e] = ry;
+          ((double*)a.pz)[e] = rz;
+        } else {
+          ((float*)a.px)[e] = (float)rx;
+          ((float*)a.py)[e] = (float)ry;
+          ((float*)a.pz)[e] = (float)rz;
+        }
+      }
+      if (r2 < rmin2) ++below;
+      ++count;
+    };
+    for (int lj = 0; lj < n; ++lj) {
+      const double dx = sp[3 * lj] - xi, dy = sp[3 * lj + 1] - yi, dz = sp[3 * lj + 2] - zi;
+      if (!c.pbc) {
+        const double r2 = dx * dx + dy * dy + dz * dz;
+        if (lj != li && r2 < rc2) emit(lj, dx, dy, dz, r2);
+        continue;
+      }
+      int lo[3], hi[3];
+      for (int d = 0; d < 3; ++d) {
+        const double s = dx * inv[0 * 3 + d] + dy * inv[1 * 3 + d] + dz * inv[2 * 3 + d];
+        lo[d] = -(int)floor(c.w[d] + s + 1e-9);
+        hi[d] = (int)floor(c.w[d] - s + 1e-9);
+      }
+      for (int n0 = lo[0]; n0 <= hi[0]; ++n0)
+        for (int n1 = lo[1]; n1 <= hi[1]; ++n1)
+          for (int n2 = lo[2]; n2 <= hi[2]; ++n2) {
+            if (lj == li && n0 == 0 && n1 == 0 && n2 == 0) continue;
+            const double sx = (double)n0 * L[0] + (double)n1 * L[3] + (double)n2 * L[6];
+            const double sy = (double)n0 * L[1] + (double)n1 * L[4] + (double)n2 * L[7];
+            const double sz = (double)n0 * L[2] + (double)n1 * L[5] + (double)n2 * L[8];
+            const double rx = dx + sx, ry = dy + sy, rz = dz + sz;
+            const double r2 = rx * rx + ry * ry + rz * rz;
+            if (r2 < rc2) emit(lj, rx, ry, rz, r2);
+          }
+    }
+    a.count[i] = count < a.K ? count : a.K;
+    cmax = max(cmax, count);
+    csum += count;
+    if (count > a.K) ++over;
+  }
+  atomicMax(&red[0], (unsigned long long)cmax);
+  atomicAdd(&red[1], (unsigned long long)csum);
+  if (over) atomicAdd(&red[2], (unsigned long long)over);
+  if (below) atomicAdd(&red[3], (unsigned long long)below);
+  if (bad) atomicAdd(&red[4], (unsigned long long)bad);
+  __syncthreads();  // lists of the whole configuration are written
+  if (t == 0) {
+    atomicMax(&a.status->max_count, red[0]);
+    atomicAdd(&a.status->n_pairs, red[1]);
+    if (red[2]) atomicAdd(&a.status->overflow, red[2]);
+    if (red[3]) atomicAdd(&a.status->below_rmin, red[3]);
+    if (red[4]) atomicAdd(&a.status->bad_species, red[4]);
+  }
+  // reverse indices: the run of j in row_i and the run of i in row_j
+  unsigned long long errs = 0;
+  for (int li = t; li < n; li += blockDim.x) {
+    const int64_t i = c.start + li;
+    const int ci = a.count[i];
+    const int32_t* row_i = a.nbr_row + (size_t)i * a.K;
+    int rank = 0;
+    for (int p = 0; p < ci; ++p) {
+      const int32_t j = row_i[p];
+      rank = (p > 0 && row_i[p - 1] == j) ? rank + 1 : 0;
+      const int32_t* row_j = a.nbr_row + (size_t)j * a.K;
+      const int cj = a.count[j];
+      int q0 = 0, hi = cj;
+      while (q0 < hi) {
+        const int mid = (q0 + hi) >> 1;
+        if (row_j[mid] < (int32_t)i) q0 = mid + 1; else hi = mid;
+      }
+      int k = 0;
+      while (q0 + k < cj && row_j[q0 + k] == (int32_t)i) ++k;
+      const size_t e = (size_t)p * a.stride + i;
+      if (k > rank) {
+        a.rev[e] = (int32_t)((size_t)(q0 + k - 1 - rank) * a.stride + j);
+      } else {
+        a.rev[e] = (int32_t)e;
+        ++errs;
+      }
+    }
+  }
+  if (errs) atomicAdd(&a.status->list_errors, errs);
+}
+
 inline dim3 grid_for(int64_t n) { return dim3((unsigned)((n + kBlock - 1) / kBlock)); }
 
 }  // namespace
@@ -380,6 +507,7 @@ hipError_t nbr_build(NbrArgs& a, hipStream_t s) {
   if (a.n_cfg > 0) hipLaunchKernelGGL(bin_scan_kernel, dim3(a.n_cfg), dim3(256), 0, s, a);
   hipLaunchKernelGGL(bin_fill_kernel, grid_for(a.n_atoms), dim3(kBlock), 0, s, a);
   hipLaunchKernelGGL(bin_sort_kernel, grid_for(a.n_atoms), dim3(kBlock), 0, s, a);
+  if (a.n_cfg > 0) hipLaunchKernelGGL(search_small_kernel, dim3(a.n_cfg), dim3(kSmallBlock), 0, s, a);
   hipLaunchKernelGGL(search_kernel, grid_for(a.n_atoms), dim3(kBlock), 0, s, a);
   const dim3 g((unsigned)((a.n_atoms + kBlock - 1) / kBlock), (unsigned)a.K);
   hipLaunchKernelGGL(reverse_kernel, g, dim3(kBlock), 0, s, a);
