@@ -123,7 +123,8 @@ int mtp_eval(mtp_model* model, const mtp_batch* batch, const mtp_out* out,
  * Sets the active set of section 2.3: A (device, [m][m] FP64, row j = b of
  * active configuration j, columns in file basis order).  A^{-1} is formed
  * on the device by FP64 Gauss-Jordan elimination with partial pivoting and
- * kept in the model.  Fails with MTP_E_ARG if A is numerically singular.
+ * kept in the model.  Fails with MTP_E_ARG if A is numerically singular
+ * (a pivot below 1e-13 once every column is scaled to max |entry| = 1).
  * Synchronises `stream`.
  */
 int mtp_set_active_set(mtp_model* model, const double* A_dev, void* stream);

@@ -52,7 +52,9 @@ __global__ void __launch_bounds__(kGJBlock) gj_kernel(int m, double* W, double* 
     }
     if (t == 0) {
       s_prow = s_idx[0];
-      if (!(s_val[0] > 1e-300)) *singular = 1;
+      // columns are scaled to max |entry| = 1: a pivot at rounding level
+      // means A is numerically singular
+      if (!(s_val[0] > 1e-13)) *singular = 1;
     }
     __syncthreads();
     const int pr = s_prow;
