@@ -143,6 +143,23 @@ int mtp_grade(mtp_model* model, const mtp_batch* batch, double* gamma_dev, int32
               int precision, void* stream);
 
 /*
+ * Training loss of section 2.2 (eq. Fitting; weighting `scaling` = molecules,
+ * structures (eq. train-structures) or vibrations (eq. train-vibrations)) and
+ * its gradient with respect to theta = {xi, c}.  Targets (device, FP64):
+ * E_t [n_configs] eV, F_t [n_atoms][3] eV/Angstrom, W_t [n_configs][3][3] the
+ * extensive virial stress in eV (volume * stress; ignored for clusters, which
+ * have no stress term).  Outputs (device): loss_dev [1]; grad_dev [m + n_c]:
+ * dL/dxi in the file's basis order, then dL/dc in the layout
+ * c[mu][z_i][z_j][beta].  The gradient is formed by forward-mode tangents of
+ * the moments and of the contraction's reverse sweep (directional
+ * derivatives along the force and virial residuals).  precision: MTP_FP64 or
+ * MTP_FP32.  Synchronises `stream` once (inside the evaluation).
+ */
+int mtp_loss_grad(mtp_model* model, const mtp_batch* batch, const double* E_t, const double* F_t,
+                  const double* W_t, double w_e, double w_f, double w_s, int scaling, int precision,
+                  double* loss_dev, double* grad_dev, void* stream);
+
+/*
  * Device-side counters of the last mtp_eval on this model: pairs closer than
  * R_min (the radial polynomial is then evaluated outside [R_min, R_cut]) and
  * neighbour-list inconsistencies (always 0 unless memory was corrupted).

@@ -161,8 +161,7 @@ def emit_contraction(s):
     # basis functions and V
     out.append("T V = T(0);")
     for a, fn in enumerate(s.funcs):
-        out.append(f"{{ const T b = {_prod([f'g{g}' for g in fn])}; V += xi[{a}] * b;"
-                   f" if (WANT_B) args.B[(size_t){a} * args.b_stride + i] = b; }}")
+        out.append(f"{{ const T b = {_prod([f'g{g}' for g in fn])}; V += xi[{a}] * b; MTP_OUT_B({a}, b); }}")
         ops += len(fn) - 1 + 2
     # dV/dg
     dg = defaultdict(list)
@@ -195,7 +194,7 @@ def emit_contraction(s):
                 contrib[k][g].append((coef * cnt, rest))
     for k in range(s.C):
         if not contrib[k]:
-            out.append(f"args.G[(size_t){k} * args.stride + i] = T(0);")
+            out.append(f"MTP_OUT_G({k}, T(0));")
             continue
         parts = []
         for g, lst in sorted(contrib[k].items()):
@@ -209,7 +208,7 @@ def emit_contraction(s):
                 ops += max(len(rest) - 1, 0) + 1
             parts.append(f"dg{g} * (" + " + ".join(inner) + ")")
             ops += 1
-        out.append(f"args.G[(size_t){k} * args.stride + i] = " + " + ".join(parts) + ";")
+        out.append(f"MTP_OUT_G({k}, " + " + ".join(parts) + ");")
         if k % 2 == 1:
             out.append("mtp::opaque(M);")
     return out, ops
@@ -345,6 +344,252 @@ __global__ void __launch_bounds__(BLOCK) adjoint_{tag}_kernel(const mtp::EvalArg
 """
 
 
+def _dual_mono_steps(s, top):
+    """Statements defining monomials m and their tangents dm along (dx, dy, dz)
+    for degrees 1..top, grouped by degree."""
+    steps = {}
+    mono = {(0, 0, 0): ("T(1)", "T(0)")}
+    for nu in range(1, top + 1):
+        lines = []
+        for a, b, c in components(nu):
+            if a:
+                src, v, dv = (a - 1, b, c), "x", "dx"
+            elif b:
+                src, v, dv = (a, b - 1, c), "y", "dy"
+            else:
+                src, v, dv = (a, b, c - 1), "z", "dz"
+            m, dm = f"m{a}_{b}_{c}", f"dm{a}_{b}_{c}"
+            if src == (0, 0, 0):
+                lines.append(f"const T {m} = {v}; const T {dm} = {dv};")
+            else:
+                ms, dms = mono[src]
+                lines.append(f"const T {m} = {ms} * {v}; const T {dm} = {dms} * {v} + {ms} * {dv};")
+            mono[(a, b, c)] = (m, dm)
+        steps[nu] = lines
+    return steps, mono
+
+
+def emit_tangent_moments(s, nus, gmap):
+    """dM_k += df_mu (r.dr / r) m_k + f_mu dm_k for the components of degrees nus."""
+    out = []
+    top = max(nus)
+    steps, mono = _dual_mono_steps(s, top)
+    out.append("const T rdot = (x * dx + y * dy + z * dz) * inv_r;")
+    for nu in range(0, top + 1):
+        out += steps.get(nu, [])
+        if nu not in nus:
+            continue
+        for mu in s.mus_of_nu(nu):
+            for abc in components(nu):
+                j = gmap[s.comp[(mu, nu, abc)]]
+                if nu == 0:
+                    out.append(f"DM[{j}] += df[{mu}] * rdot;")
+                else:
+                    m, dm = mono[abc]
+                    out.append(f"DM[{j}] += df[{mu}] * rdot * {m} + f[{mu}] * {dm};")
+    return out
+
+
+def emit_cgrad_pass(s, nus, gmap):
+    """Per pair: s1_mu += H m, s2_mu += G m, s3_mu += G dm over the components of
+    degrees nus (H = a G + dG)."""
+    out = []
+    top = max(nus)
+    steps, mono = _dual_mono_steps(s, top)
+    out.append("const T rdot = (x * dx + y * dy + z * dz) * inv_r;")
+    out.append("T s1[NMU], s2[NMU], s3[NMU];")
+    out.append("#pragma unroll\nfor (int q = 0; q < NMU; ++q) { s1[q] = T(0); s2[q] = T(0); s3[q] = T(0); }")
+    for nu in range(0, top + 1):
+        out += steps.get(nu, [])
+        if nu not in nus:
+            continue
+        for mu in s.mus_of_nu(nu):
+            for abc in components(nu):
+                j = gmap[s.comp[(mu, nu, abc)]]
+                if nu == 0:
+                    out.append(f"s1[{mu}] += H[{j}]; s2[{mu}] += G[{j}];")
+                else:
+                    m, dm = mono[abc]
+                    out.append(f"s1[{mu}] += H[{j}] * {m}; s2[{mu}] += G[{j}] * {m}; s3[{mu}] += G[{j}] * {dm};")
+    return out
+
+
+def pass_mus(s, nus):
+    return sorted({mu for mu, nu in s.moments if nu in nus})
+
+
+LOSS_PASS_HEAD = r"""
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* cs = reinterpret_cast<T*>(smem_raw);
+  for (int t = threadIdx.x; t < args.n_c; t += blockDim.x) cs[t] = args.c[t];
+  __syncthreads();
+  const int i = blockIdx.x * BLOCK + threadIdx.x;
+  if (i >= args.n_atoms) return;
+  const int S = args.n_species;
+  const int nq = args.nq;
+  const int mu_stride = S * S * nq;
+  const int zi = clamp_species(args.species[i], S);
+  const int cnt = args.nbr_count[i];
+  const T rmin = args.rmin, rcut = args.rcut;
+  const size_t n = args.stride;
+  const T ux = la.u[3 * (size_t)i], uy = la.u[3 * (size_t)i + 1], uz = la.u[3 * (size_t)i + 2];
+  const T e00 = la.eps_atom[0 * n + i], e01 = la.eps_atom[1 * n + i], e02 = la.eps_atom[2 * n + i];
+  const T e10 = la.eps_atom[3 * n + i], e11 = la.eps_atom[4 * n + i], e12 = la.eps_atom[5 * n + i];
+  const T e20 = la.eps_atom[6 * n + i], e21 = la.eps_atom[7 * n + i], e22 = la.eps_atom[8 * n + i];
+"""
+
+LOSS_PAIR_HEAD = r"""
+    const size_t e = (size_t)p * args.stride + i;
+    const T x = args.px[e], y = args.py[e], z = args.pz[e];
+    const int zj = args.pzj[e];
+    const int j = la.nbr_row[(size_t)i * la.K + p];
+    // delta r_ij = u_j - u_i + eps r_ij
+    const T dx = la.u[3 * (size_t)j] - ux + (e00 * x + e01 * y + e02 * z);
+    const T dy = la.u[3 * (size_t)j + 1] - uy + (e10 * x + e11 * y + e12 * z);
+    const T dz = la.u[3 * (size_t)j + 2] - uz + (e20 * x + e21 * y + e22 * z);
+    const T r = sqrt(x * x + y * y + z * z);
+    const T inv_r = T(1) / r;
+    T f[NMU], df[NMU];
+    mtp::radial<T, NMU, true>(cs, (zi * S + zj) * nq, mu_stride, nq, r, rmin, rcut, f, df);
+"""
+
+
+def emit_loss_kernels(s, budget):
+    """Sources of the loss-gradient kernels and the body of their launcher."""
+    src, launch = [], []
+    passes = adjoint_passes(s, budget)
+    ind = lambda lines, k: "\n".join(" " * k + l for l in lines)
+    for pidx, (nus, comps) in enumerate(passes):
+        gmap = {k: j for j, k in enumerate(comps)}
+        body = emit_tangent_moments(s, nus, gmap)
+        src.append(f"""
+// Tangent of the moments of degrees {nus} along delta r (loss gradient).
+template <typename T>
+__global__ void __launch_bounds__(BLOCK) tmom_p{pidx}_kernel(const mtp::EvalArgs<T> args, const mtp::LossArgs<T> la) {{{LOSS_PASS_HEAD}
+  constexpr int CP = {len(comps)};
+  constexpr int kIdx[CP] = {{ {", ".join(map(str, comps))} }};
+  T DM[CP];
+#pragma unroll
+  for (int k = 0; k < CP; ++k) DM[k] = T(0);
+#pragma unroll 1
+  for (int p = 0; p < cnt; ++p) {{{LOSS_PAIR_HEAD}
+{ind(body, 4)}
+  }}
+#pragma unroll
+  for (int k = 0; k < CP; ++k) la.dM[(size_t)kIdx[k] * args.stride + i] = DM[k];
+}}
+""")
+        launch.append(f"  hipLaunchKernelGGL((tmom_p{pidx}_kernel<T>), grid, dim3(BLOCK), smem, s, args, la);")
+    launch.append("  hipLaunchKernelGGL((tangent_contract_kernel<T>), grid, dim3(BLOCK), 0, s, args, la);")
+    for pidx, (nus, comps) in enumerate(passes):
+        gmap = {k: j for j, k in enumerate(comps)}
+        body = emit_cgrad_pass(s, nus, gmap)
+        mus = pass_mus(s, nus)
+        if pidx == 0:
+            store = "\n".join(f"    la.pa[(size_t){mu} * n_slots + e] = {'s1[%d] + s3[%d]' % (mu, mu) if mu in mus else 'T(0)'};\n"
+                              f"    la.pb[(size_t){mu} * n_slots + e] = {'s2[%d] * rdot' % mu if mu in mus else 'T(0)'};"
+                              for mu in range(s.n_mu))
+        else:
+            store = "\n".join(f"    la.pa[(size_t){mu} * n_slots + e] += s1[{mu}] + s3[{mu}];\n"
+                              f"    la.pb[(size_t){mu} * n_slots + e] += s2[{mu}] * rdot;" for mu in mus)
+        src.append(f"""
+// Radial sensitivities of the pairs from the components of degrees {nus}:
+// coefficients of Q_beta and dQ_beta/dr in dL/dc (loss gradient).
+template <typename T>
+__global__ void __launch_bounds__(BLOCK) cgrad_p{pidx}_kernel(const mtp::EvalArgs<T> args, const mtp::LossArgs<T> la) {{{LOSS_PASS_HEAD}
+  const T aw = la.a_atom[i];
+  const size_t n_slots = (size_t)la.K * args.stride;
+  constexpr int CP = {len(comps)};
+  constexpr int kIdx[CP] = {{ {", ".join(map(str, comps))} }};
+  T G[CP], H[CP];
+#pragma unroll
+  for (int k = 0; k < CP; ++k) {{
+    G[k] = args.G[(size_t)kIdx[k] * args.stride + i];
+    H[k] = aw * G[k] + la.dG[(size_t)kIdx[k] * args.stride + i];
+  }}
+#pragma unroll 1
+  for (int p = 0; p < cnt; ++p) {{{LOSS_PAIR_HEAD}
+{ind(body, 4)}
+{store}
+  }}
+}}
+""")
+        launch.append(f"  hipLaunchKernelGGL((cgrad_p{pidx}_kernel<T>), grid, dim3(BLOCK), smem, s, args, la);")
+    launch.append("  hipLaunchKernelGGL((creduce_kernel<T>), grid, dim3(BLOCK), (size_t)args.n_c * sizeof(double), s, args, la);")
+    return "\n".join(src), "\n".join(launch)
+
+
+CREDUCE_TEMPLATE = r"""
+// dL/dc[mu][z_i][z_j][beta] = sum over pairs of species (z_i, z_j) of
+// pa_mu Q_beta(r) + pb_mu dQ_beta/dr: per thread over its pairs for one z_j
+// at a time, then per workgroup in LDS, then per workgroup to cpart.
+template <typename T>
+__global__ void __launch_bounds__(BLOCK) creduce_kernel(const mtp::EvalArgs<T> args, const mtp::LossArgs<T> la) {{
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  double* acc_blk = reinterpret_cast<double*>(smem_raw);
+  for (int t = threadIdx.x; t < args.n_c; t += blockDim.x) acc_blk[t] = 0.0;
+  __syncthreads();
+  const int i = blockIdx.x * BLOCK + threadIdx.x;
+  const int S = args.n_species;
+  const int nq = args.nq;
+  const size_t n_slots = (size_t)la.K * args.stride;
+  if (i < args.n_atoms) {{
+    const int zi = clamp_species(args.species[i], S);
+    const int cnt = args.nbr_count[i];
+    const T span_inv = T(1) / (args.rcut - args.rmin);
+    for (int zj = 0; zj < S; ++zj) {{
+      T acc[NMU][16];
+#pragma unroll
+      for (int mu = 0; mu < NMU; ++mu)
+#pragma unroll
+        for (int b = 0; b < 16; ++b) acc[mu][b] = T(0);
+      bool any = false;
+      for (int p = 0; p < cnt; ++p) {{
+        const size_t e = (size_t)p * args.stride + i;
+        if (args.pzj[e] != zj) continue;
+        any = true;
+        const T x = args.px[e], y = args.py[e], z = args.pz[e];
+        const T r = sqrt(x * x + y * y + z * z);
+        const T q = (T(2) * r - args.rmin - args.rcut) * span_inv;
+        const T dqdr = T(2) * span_inv;
+        const T sc = args.rcut - r;
+        T pa[NMU], pb[NMU];
+#pragma unroll
+        for (int mu = 0; mu < NMU; ++mu) {{
+          pa[mu] = la.pa[(size_t)mu * n_slots + e];
+          pb[mu] = la.pb[(size_t)mu * n_slots + e];
+        }}
+        T t0 = T(1), t1 = q, d0 = T(0), d1 = T(1);
+#pragma unroll
+        for (int b = 0; b < 16; ++b) {{
+          if (b < nq) {{
+            const T tb = b == 0 ? t0 : t1;
+            const T db = b == 0 ? d0 : d1;
+            const T Qb = tb * sc * sc;
+            const T dQb = db * dqdr * sc * sc - T(2) * tb * sc;
+#pragma unroll
+            for (int mu = 0; mu < NMU; ++mu) acc[mu][b] += pa[mu] * Qb + pb[mu] * dQb;
+            if (b >= 1) {{
+              const T t2 = T(2) * q * t1 - t0;
+              const T d2 = T(2) * t1 + T(2) * q * d1 - d0;
+              t0 = t1; t1 = t2; d0 = d1; d1 = d2;
+            }}
+          }}
+        }}
+      }}
+      if (any)
+        for (int mu = 0; mu < NMU; ++mu)
+#pragma unroll
+          for (int b = 0; b < 16; ++b)
+            if (b < nq) atomicAdd(&acc_blk[((mu * S + zi) * S + zj) * nq + b], (double)acc[mu][b]);
+    }}
+  }}
+  __syncthreads();
+  for (int t = threadIdx.x; t < args.n_c; t += blockDim.x) la.cpart[(size_t)blockIdx.x * args.n_c + t] = acc_blk[t];
+}}
+"""
+
+
 KERNEL_TEMPLATE = r"""// Generated by paper_2007_08555_amd/codegen.py for the MTP basis of level {level}
 // ({m} basis functions, {ngraphs} connected contractions, {C} moment components).
 // Do not edit: regenerate with the package build step.
@@ -420,11 +665,55 @@ __global__ void __launch_bounds__(BLOCK) contract_kernel(const mtp::EvalArgs<T> 
   T M[C];
 #pragma unroll
   for (int k = 0; k < C; ++k) M[k] = args.M[(size_t)k * args.stride + i];
+#define MTP_OUT_B(a_, v_) do {{ if (WANT_B) args.B[(size_t)(a_) * args.b_stride + i] = (v_); }} while (0)
+#define MTP_OUT_G(k_, v_) args.G[(size_t)(k_) * args.stride + i] = (v_)
 {contraction}
+#undef MTP_OUT_B
+#undef MTP_OUT_G
   args.site[i] = V;
 }}
 
+// The same contraction code on dual numbers M + dM e: the tangents of G and of
+// every B_alpha along the moment tangent dM (forward mode over the reverse
+// sweep).  Writes dG and a_k B_alpha + dB_alpha.
+template <typename R>
+__global__ void __launch_bounds__(BLOCK) tangent_contract_kernel(const mtp::EvalArgs<R> args,
+                                                                 const mtp::LossArgs<R> la) {{
+  using T = mtp::Dual<R>;
+  const int i = blockIdx.x * BLOCK + threadIdx.x;
+  if (i >= args.n_atoms) return;
+  const R* __restrict__ xi = args.xi;
+  const R aw = la.a_atom[i];
+  T M[C];
+#pragma unroll
+  for (int k = 0; k < C; ++k) M[k] = T(args.M[(size_t)k * args.stride + i], la.dM[(size_t)k * args.stride + i]);
+#define MTP_OUT_B(a_, v_) la.xi_terms[(size_t)(a_) * args.stride + i] = aw * (v_).v + (v_).d
+#define MTP_OUT_G(k_, v_) la.dG[(size_t)(k_) * args.stride + i] = (v_).d
+{contraction}
+#undef MTP_OUT_B
+#undef MTP_OUT_G
+  (void)V;
+}}
+
 {adjoint_kernels}
+{loss_kernels}
+{creduce}
+
+template <typename T>
+hipError_t launch_loss_t(const void* a, const void* l, hipStream_t s) {{
+  const auto& args = *static_cast<const mtp::EvalArgs<T>*>(a);
+  const auto& la = *static_cast<const mtp::LossArgs<T>*>(l);
+  if (args.n_atoms <= 0) return hipSuccess;
+  const dim3 grid((args.n_atoms + BLOCK - 1) / BLOCK);
+  const size_t smem = (size_t)args.n_c * sizeof(T);
+{launch_loss}
+  return hipGetLastError();
+}}
+
+hipError_t launch_loss(int precision, const void* a, const void* l, hipStream_t s) {{
+  return precision == 0 ? launch_loss_t<double>(a, l, s) : launch_loss_t<float>(a, l, s);
+}}
+
 template <typename T, bool COMP, bool WANT_B>
 hipError_t launch_t(const void* a, hipStream_t s) {{
   const auto& args = *static_cast<const mtp::EvalArgs<T>*>(a);
@@ -465,7 +754,7 @@ const int kFuncFactors[] = {{ {func_factors} }};
 extern const mtp::BasisVariant {ns}_variant = {{
   "{ns}", {level}, {n_moments}, {ns}::kMoments, {ngraphs}, {ns}::kGraphKeyOffsets, {ns}::kGraphKeys,
   {m}, {ns}::kFuncOffsets, {ns}::kFuncFactors, {C}, {n_mu}, {nu_max},
-  {flops_pair_fwd}, {flops_pair_bwd}, {flops_atom}, {ns}::launch }};
+  {flops_pair_fwd}, {flops_pair_bwd}, {flops_atom}, {ns}::launch, {ns}::launch_loss, {ns}::BLOCK }};
 #endif
 """
 
@@ -476,6 +765,7 @@ def generate(lev_max, block=64):
     fwd, ops_f = emit_pair_forward(s, comp_mode=True)
     con, ops_c = emit_contraction(s)
     bwd, ops_b = emit_pair_backward(s)
+    loss_src, loss_launch = emit_loss_kernels(s, budget=45)
     adj_src, launches = [], {}
     for prec, budget in (("f32", 10 ** 9), ("f64", 90)):
         lines = []
@@ -514,6 +804,7 @@ def generate(lev_max, block=64):
         block=block, ns=ns,
         pair_fwd=ind(fwd, 4), contraction=ind(con, 2), adjoint_kernels="\n".join(adj_src),
         launch_f64=launches["f64"], launch_f32=launches["f32"],
+        loss_kernels=loss_src, launch_loss=loss_launch, creduce=CREDUCE_TEMPLATE.format(),
         moments=", ".join(f"{mu}, {nu}" for mu, nu in s.moments),
         n_moments=len(s.moments),
         graph_offsets=", ".join(map(str, graph_offsets)),

@@ -102,6 +102,10 @@ struct mtp_model {
   Buffer count, nbr_row, nbr_z, px, py, pz, rev, gpair, Mbuf, Gbuf, site, wv, B, status;
   int K = 64;  // neighbour capacity per atom, grown on overflow
   Buffer b_tmp, c_tmp;
+  int last_stride = 0;
+  // loss gradient
+  Buffer lo_E, lo_F, lo_W, lo_a, lo_u, lo_eps, lo_dM, lo_dG, lo_xit, lo_pa, lo_pb, lo_cpart;
+  Buffer lo_acfg, lo_wfcfg, lo_epscfg, lo_losscfg, lo_lossatom;
   // statistics of the last evaluation
   int64_t last_atoms = 0, last_pairs = 0;
   int32_t last_max_nb = 0;
@@ -416,6 +420,7 @@ int run_eval(mtp_model* M, const mtp_batch* bt, const mtp_out* out, int precisio
       continue;
     }
     M->last_atoms = N;
+    M->last_stride = stride;
     M->last_pairs = (int64_t)st.n_pairs;
     M->last_max_nb = (int32_t)st.max_count;
     M->timed = M->timing;
@@ -552,6 +557,98 @@ int mtp_grade(mtp_model* M, const mtp_batch* bt, double* gamma_dev, int32_t* arg
   int rc = mtp_eval(M, bt, &o, precision, stream);
   if (rc != MTP_OK) return rc;
   return mtp_grade_from_b(M, bt->n_configs, o.b, gamma_dev, argmax_dev, nullptr, stream);
+}
+
+int mtp_loss_grad(mtp_model* M, const mtp_batch* bt, const double* E_t, const double* F_t, const double* W_t,
+                  double w_e, double w_f, double w_s, int scaling, int precision, double* loss_dev,
+                  double* grad_dev, void* stream) {
+  g_err.clear();
+  if (!M || !bt || !E_t || !F_t || !W_t || !loss_dev || !grad_dev)
+    return fail(MTP_E_ARG, "mtp_loss_grad: null argument");
+  if (scaling < MTP_SCALE_MOLECULES || scaling > MTP_SCALE_VIBRATIONS) return fail(MTP_E_ARG, "mtp_loss_grad: bad scaling");
+  if (precision != MTP_FP64 && precision != MTP_FP32) return fail(MTP_E_ARG, "mtp_loss_grad: precision must be FP64 or FP32");
+  if (!(w_e >= 0 && w_f >= 0 && w_s >= 0)) return fail(MTP_E_ARG, "mtp_loss_grad: weights must be non-negative");
+  HIP_TRY(hipSetDevice(M->device), "hipSetDevice");
+  hipStream_t s = (hipStream_t)stream;
+  const int K_cfg = bt->n_configs;
+  const int64_t N = bt->n_atoms;
+  if (K_cfg <= 0) return fail(MTP_E_ARG, "mtp_loss_grad: empty batch");
+  HIP_TRY(M->lo_E.ensure(sizeof(double) * K_cfg), "hipMalloc");
+  HIP_TRY(M->lo_W.ensure(sizeof(double) * 9 * K_cfg), "hipMalloc");
+  HIP_TRY(M->lo_F.ensure(sizeof(double) * 3 * (N + 1)), "hipMalloc");
+  mtp_out o{};
+  o.energy = M->lo_E.as<double>();
+  o.forces = M->lo_F.as<double>();
+  o.virial = M->lo_W.as<double>();
+  int rc = run_eval(M, bt, &o, precision, s);
+  if (rc != MTP_OK) return rc;
+  const bool fp64 = precision == MTP_FP64;
+  const size_t tsz = fp64 ? sizeof(double) : sizeof(float);
+  const int stride = M->last_stride;
+  const int K = M->K;
+  const int C = M->var->C;
+  const int block = M->var->block;
+  const int n_blocks = (int)((N + block - 1) / block);
+  HIP_TRY(M->lo_a.ensure(tsz * (N + 1)), "hipMalloc");
+  HIP_TRY(M->lo_u.ensure(tsz * 3 * (N + 1)), "hipMalloc");
+  HIP_TRY(M->lo_eps.ensure(tsz * 9 * stride), "hipMalloc");
+  HIP_TRY(M->lo_dM.ensure(tsz * (size_t)C * stride), "hipMalloc");
+  HIP_TRY(M->lo_dG.ensure(tsz * (size_t)C * stride), "hipMalloc");
+  HIP_TRY(M->lo_xit.ensure(tsz * (size_t)M->m * stride), "hipMalloc");
+  HIP_TRY(M->lo_pa.ensure(tsz * (size_t)M->n_mu * K * stride), "hipMalloc");
+  HIP_TRY(M->lo_pb.ensure(tsz * (size_t)M->n_mu * K * stride), "hipMalloc");
+  HIP_TRY(M->lo_cpart.ensure(sizeof(double) * (size_t)std::max(1, n_blocks) * M->n_c), "hipMalloc");
+  HIP_TRY(M->lo_acfg.ensure(sizeof(double) * K_cfg), "hipMalloc");
+  HIP_TRY(M->lo_wfcfg.ensure(sizeof(double) * K_cfg), "hipMalloc");
+  HIP_TRY(M->lo_epscfg.ensure(sizeof(double) * 9 * K_cfg), "hipMalloc");
+  HIP_TRY(M->lo_losscfg.ensure(sizeof(double) * K_cfg), "hipMalloc");
+  HIP_TRY(M->lo_lossatom.ensure(sizeof(double) * (N + 1)), "hipMalloc");
+  mtp::LossResidualArgs r{};
+  r.n_cfg = K_cfg;
+  r.N = N;
+  r.stride = stride;
+  r.cfg = M->cfg.as<mtp::CfgInfo>();
+  r.atom_cfg = M->atom_cfg.as<int32_t>();
+  r.E = o.energy;
+  r.F = o.forces;
+  r.W = o.virial;
+  r.Et = E_t;
+  r.Ft = F_t;
+  r.Wt = W_t;
+  r.we = w_e;
+  r.wf = w_f;
+  r.ws = w_s;
+  r.scaling = scaling;
+  r.a_cfg = M->lo_acfg.as<double>();
+  r.wf_cfg = M->lo_wfcfg.as<double>();
+  r.eps_cfg = M->lo_epscfg.as<double>();
+  r.loss_cfg = M->lo_losscfg.as<double>();
+  r.loss_atom = M->lo_lossatom.as<double>();
+  HIP_TRY(mtp::loss_residuals(r, fp64, M->lo_a.p, M->lo_u.p, M->lo_eps.p, s), "loss residuals");
+  auto fill = [&](auto* tag) -> int {
+    using T = std::remove_pointer_t<decltype(tag)>;
+    auto ea = make_args<T>(M, N, stride, bt->species, false);
+    mtp::LossArgs<T> la;
+    la.a_atom = M->lo_a.as<T>();
+    la.u = M->lo_u.as<T>();
+    la.eps_atom = M->lo_eps.as<T>();
+    la.nbr_row = M->nbr_row.as<int>();
+    la.K = K;
+    la.dM = M->lo_dM.as<T>();
+    la.dG = M->lo_dG.as<T>();
+    la.xi_terms = M->lo_xit.as<T>();
+    la.pa = M->lo_pa.as<T>();
+    la.pb = M->lo_pb.as<T>();
+    la.cpart = M->lo_cpart.as<double>();
+    HIP_TRY(M->var->launch_loss(precision, &ea, &la, s), "loss-gradient kernels");
+    return MTP_OK;
+  };
+  rc = fp64 ? fill((double*)nullptr) : fill((float*)nullptr);
+  if (rc != MTP_OK) return rc;
+  HIP_TRY(mtp::loss_finish(fp64, K_cfg, N, stride, M->m, M->n_c, n_blocks, r.loss_cfg, r.loss_atom, M->lo_xit.p,
+                           M->perm_dev.as<int32_t>(), M->lo_cpart.as<double>(), loss_dev, grad_dev, s),
+          "loss reductions");
+  return MTP_OK;
 }
 
 int mtp_status(mtp_model* M, void* stream, int64_t* n_below_rmin, int64_t* n_list_errors) {

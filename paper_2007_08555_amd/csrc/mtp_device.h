@@ -90,6 +90,48 @@ __device__ __forceinline__ void opaque(T (&v)[N]) {
   for (int k = 0; k < N; ++k) asm volatile("" : "+v"(v[k]));
 }
 
+// First-order dual number v + d e (e^2 = 0): running the contraction code on
+// duals gives the directional derivative of every value along the tangent
+// carried in d (forward mode over the reverse sweep for the loss gradient).
+template <typename R>
+struct Dual {
+  R v, d;
+  __device__ __forceinline__ Dual() = default;
+  __device__ __forceinline__ constexpr Dual(R x) : v(x), d(R(0)) {}
+  __device__ __forceinline__ constexpr Dual(R x, R y) : v(x), d(y) {}
+};
+template <typename R>
+__device__ __forceinline__ Dual<R> operator+(Dual<R> a, Dual<R> b) { return Dual<R>(a.v + b.v, a.d + b.d); }
+template <typename R>
+__device__ __forceinline__ Dual<R> operator*(Dual<R> a, Dual<R> b) { return Dual<R>(a.v * b.v, fma(a.d, b.v, a.v * b.d)); }
+template <typename R>
+__device__ __forceinline__ Dual<R> operator*(R a, Dual<R> b) { return Dual<R>(a * b.v, a * b.d); }
+template <typename R>
+__device__ __forceinline__ Dual<R>& operator+=(Dual<R>& a, Dual<R> b) { a.v += b.v; a.d += b.d; return a; }
+
+template <typename R, int N>
+__device__ __forceinline__ void opaque(Dual<R> (&v)[N]) {
+#pragma unroll
+  for (int k = 0; k < N; ++k) asm volatile("" : "+v"(v[k].v), "+v"(v[k].d));
+}
+
+// Per-launch arguments of the loss-gradient kernels (all [.][stride] arrays
+// are indexed like EvalArgs).
+template <typename T>
+struct LossArgs {
+  const T* a_atom;     // [n_atoms] a_k = 2 w_e (E_k - E_k^t) of the atom's configuration
+  const T* u;          // [n_atoms][3] u_i = -2 w_f (F_i - F_i^t)
+  const T* eps_atom;   // [9][stride] eps_k = 2 w_s (W_k - W_k^t) of the atom's configuration
+  const int* nbr_row;  // [n_atoms][K] neighbour home indices
+  int K;
+  T* dM;               // [C][stride] tangent of the moments along delta r
+  T* dG;               // [C][stride] tangent of G = dV/dM
+  T* xi_terms;         // [m][stride] a B_alpha + tangent of B_alpha
+  T* pa;               // [NMU][K * stride] per pair: coefficient of Q_beta
+  T* pb;               // [NMU][K * stride] per pair: coefficient of dQ_beta/dr
+  double* cpart;       // [blocks][n_c] partial sums of dL/dc per workgroup
+};
+
 // Error-free sum (Knuth's TwoSum): hi + lo carries the accumulated sum.
 template <typename T>
 __device__ __forceinline__ void two_sum_acc(T& hi, T& lo, T v) {

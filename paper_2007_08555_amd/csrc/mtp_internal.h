@@ -80,6 +80,32 @@ hipError_t reduce_configs(int fp64, int n_cfg, const CfgInfo* cfg, int stride,
                           int b_stride, const int32_t* perm, double* energy, double* virial,
                           double* b, double* site_out, hipStream_t s);
 
+// Residuals of the training loss (per configuration and per atom).
+struct LossResidualArgs {
+  int n_cfg;
+  int64_t N;
+  int stride;
+  const CfgInfo* cfg;
+  const int32_t* atom_cfg;
+  const double* E;    // [n_cfg] predictions
+  const double* F;    // [N][3]
+  const double* W;    // [n_cfg][9]
+  const double* Et;   // targets
+  const double* Ft;
+  const double* Wt;
+  double we, wf, ws;
+  int scaling;        // 0 molecules, 1 structures, 2 vibrations
+  double* a_cfg;      // [n_cfg]
+  double* wf_cfg;     // [n_cfg]
+  double* eps_cfg;    // [n_cfg][9]
+  double* loss_cfg;   // [n_cfg]
+  double* loss_atom;  // [N]
+};
+hipError_t loss_residuals(LossResidualArgs& r, int fp64, void* a_atom, void* u, void* eps_atom, hipStream_t s);
+hipError_t loss_finish(int fp64, int n_cfg, int64_t N, int stride, int m, int n_c, int n_blocks,
+                       const double* loss_cfg, const double* loss_atom, const void* xi_terms, const int32_t* perm,
+                       const double* cpart, double* loss, double* grad, hipStream_t s);
+
 // Dense FP64 helpers of the grade.
 hipError_t gauss_jordan_inverse(int m, double* work /*[m][2m]*/, double* inv, int* singular,
                                 hipStream_t s);

@@ -24,6 +24,9 @@ struct BasisVariant {
   double flops_atom;             // per atom, contraction forward + reverse
   // precision: 0 = FP64, 1 = FP32, 2 = FP32 with compensated moment sums
   hipError_t (*launch_eval)(int precision, bool want_b, const void* args, hipStream_t stream);
+  // loss-gradient kernels after an evaluation that left M and G in place
+  hipError_t (*launch_loss)(int precision, const void* eval_args, const void* loss_args, hipStream_t stream);
+  int block;                     // atoms per workgroup of the per-atom kernels
 };
 
 extern const BasisVariant* const kVariants[];

@@ -108,6 +108,21 @@ class Potential:
                              _stream(stream)), "mtp_eval")
         return res
 
+    def loss_grad(self, batch: Batch, E_t, F_t, W_t, w_e=1.0, w_f=0.01, w_s=0.001, scaling="vibrations",
+                  precision="fp64", stream=None):
+        """Loss of eq. Fitting and dL/d(xi, c) (mtp_loss_grad); targets are
+        device or host arrays: E_t [K], F_t [N,3], W_t [K,3,3] (virial, eV)."""
+        dev = self.device
+        t = lambda a: torch.as_tensor(a, dtype=torch.float64).to(dev).contiguous()
+        E_t, F_t, W_t = t(E_t), t(F_t), t(W_t)
+        loss = torch.empty(1, dtype=torch.float64, device=dev)
+        grad = torch.empty(self.m + self.n_c, dtype=torch.float64, device=dev)
+        bs = batch.c_struct()
+        check(lib().mtp_loss_grad(self._h, ctypes.byref(bs), _ptr(E_t), _ptr(F_t), _ptr(W_t), float(w_e), float(w_f),
+                                  float(w_s), _lib.SCALINGS[scaling], _lib.PRECISIONS[precision], _ptr(loss),
+                                  _ptr(grad), _stream(stream)), "mtp_loss_grad")
+        return loss, grad
+
     def set_timing(self, enable=True):
         check(lib().mtp_set_timing(self._h, 1 if enable else 0), "mtp_set_timing")
 
