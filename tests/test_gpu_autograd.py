@@ -1,0 +1,83 @@
+"""torch.autograd wrappers of the library: their gradients against central
+finite differences of the same GPU path (h = 1e-6, FP64)."""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from gpu_common import log, pot_path
+
+pytestmark = pytest.mark.gpu
+
+
+def _setup(name="lev12_s2", seed=31):
+    from paper_2007_08555_amd import Batch, Potential
+    P = Potential(pot_path(name))
+    b = synth.mixed_batch(seed=seed, n_configs=5, n_min=8, n_max=24, n_species_model=P.n_species)
+    B = Batch.from_arrays(b)
+    c0, xi0 = P.get_params()
+    return P, B, torch.tensor(c0, device="cuda"), torch.tensor(xi0, device="cuda")
+
+
+def test_energy_gradients_match_finite_differences():
+    from paper_2007_08555_amd.autograd import MTPEnergy
+    P, B, c, xi = _setup()
+    pos = B.pos.clone().requires_grad_(True)
+    c_ = c.clone().requires_grad_(True)
+    xi_ = xi.clone().requires_grad_(True)
+    w = torch.linspace(0.5, 1.5, B.n_configs, dtype=torch.float64, device="cuda")
+    E = MTPEnergy.apply(pos, c_, xi_, P, B)
+    (E * w).sum().backward()
+
+    def f(p=None, cc=None, xx=None):
+        with torch.no_grad():
+            return (MTPEnergy.apply(B.pos if p is None else p, c if cc is None else cc,
+                                    xi if xx is None else xx, P, B) * w).sum().item()
+
+    h = 1e-6
+    rng = np.random.default_rng(0)
+    for _ in range(4):
+        a, d = int(rng.integers(B.n_atoms)), int(rng.integers(3))
+        pp, pm = B.pos.clone(), B.pos.clone()
+        pp[a, d] += h
+        pm[a, d] -= h
+        fd = (f(p=pp) - f(p=pm)) / (2 * h)
+        assert abs(fd - pos.grad[a, d].item()) <= 1e-6 * max(1.0, abs(fd))
+    for vec, grad, name in ((c, c_.grad, "c"), (xi, xi_.grad, "xi")):
+        for k in rng.choice(len(vec), size=4, replace=False):
+            hh = h * max(1.0, abs(vec[k].item()))
+            vp, vm = vec.clone(), vec.clone()
+            vp[k] += hh
+            vm[k] -= hh
+            fd = (f(**{("cc" if name == "c" else "xx"): vp}) - f(**{("cc" if name == "c" else "xx"): vm})) / (2 * hh)
+            log(f"[autograd] d sum(wE)/d{name}[{k}]: fd {fd:.8e} autograd {grad[k].item():.8e}")
+            assert abs(fd - grad[k].item()) <= 1e-6 * max(abs(fd), 1e-8 * grad.abs().max().item())
+
+
+def test_loss_gradient_matches_finite_differences():
+    from paper_2007_08555_amd.autograd import MTPLoss
+    P, B, c, xi = _setup(seed=32)
+    with torch.no_grad():
+        out = P.eval(B, precision="fp64", forces=True, virial=True)
+    g = torch.Generator(device="cpu").manual_seed(0)
+    E_t = out["energy"] + 0.05 * torch.randn(B.n_configs, generator=g, dtype=torch.float64).cuda()
+    F_t = out["forces"] * 0.9
+    W_t = out["virial"] * 1.1
+    c_ = c.clone().requires_grad_(True)
+    xi_ = xi.clone().requires_grad_(True)
+    L = MTPLoss.apply(c_, xi_, P, B, E_t, F_t, W_t)
+    L.backward()
+    h = 1e-6
+    rng = np.random.default_rng(1)
+    for vec, grad, which in ((c, c_.grad, 0), (xi, xi_.grad, 1)):
+        for k in rng.choice(len(vec), size=6, replace=False):
+            hh = h * max(1.0, abs(vec[k].item()))
+            vals = []
+            for sgn in (1, -1):
+                v = vec.clone()
+                v[k] += sgn * hh
+                args = (v, xi) if which == 0 else (c, v)
+                with torch.no_grad():
+                    vals.append(MTPLoss.apply(*args, P, B, E_t, F_t, W_t).item())
+            fd = (vals[0] - vals[1]) / (2 * hh)
+            assert abs(fd - grad[k].item()) <= 1e-6 * max(abs(fd), 1e-6 * grad.abs().max().item()), (which, k)
