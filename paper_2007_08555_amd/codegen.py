@@ -137,7 +137,7 @@ def emit_pair_forward(s, comp_mode):
         for mu, abc, k in by_nu.get(nu, []):
             term = f"f[{mu}]" if nu == 0 else f"f[{mu}] * {mono[abc]}"
             if comp_mode:
-                out.append(f"if (COMP) mtp::two_sum_acc(M[{k}], Mlo[{k}], {term}); else M[{k}] += {term};")
+                out.append(f"if constexpr (COMP) mtp::two_sum_acc(M[{k}], Mlo[{k}], {term}); else M[{k}] += {term};")
             else:
                 out.append(f"M[{k}] += {term};")
             ops += 2 if nu else 1
@@ -311,7 +311,8 @@ __global__ void __launch_bounds__(BLOCK) adjoint_{tag}_kernel(const mtp::EvalArg
   T xn = T(0), yn = T(0), zn = T(0), g0n = T(0), g1n = T(0), g2n = T(0);
   int zjn = 0;
   if (cnt > 0) {{
-    xn = args.px[i]; yn = args.py[i]; zn = args.pz[i]; zjn = args.pzj[i];
+    const mtp::PairRec<T> q = args.pr[i];
+    xn = q.x; yn = q.y; zn = q.z; zjn = q.zj;
     if (!FIRST) {{ g0n = args.g[3 * (size_t)i]; g1n = args.g[3 * (size_t)i + 1]; g2n = args.g[3 * (size_t)i + 2]; }}
   }}
 #pragma unroll 1
@@ -322,7 +323,8 @@ __global__ void __launch_bounds__(BLOCK) adjoint_{tag}_kernel(const mtp::EvalArg
     const T gp0 = g0n, gp1 = g1n, gp2 = g2n;
     if (p + 1 < cnt) {{
       const size_t en = e + args.stride;
-      xn = args.px[en]; yn = args.py[en]; zn = args.pz[en]; zjn = args.pzj[en];
+      const mtp::PairRec<T> q = args.pr[en];
+      xn = q.x; yn = q.y; zn = q.z; zjn = q.zj;
       if (!FIRST) {{ g0n = args.g[3 * en]; g1n = args.g[3 * en + 1]; g2n = args.g[3 * en + 2]; }}
     }}
     const T r = sqrt(x * x + y * y + z * z);
@@ -440,8 +442,9 @@ LOSS_PASS_HEAD = r"""
 
 LOSS_PAIR_HEAD = r"""
     const size_t e = (size_t)p * args.stride + i;
-    const T x = args.px[e], y = args.py[e], z = args.pz[e];
-    const int zj = args.pzj[e];
+    const mtp::PairRec<T> q = args.pr[e];
+    const T x = q.x, y = q.y, z = q.z;
+    const int zj = q.zj;
     const int j = la.nbr_row[(size_t)i * la.K + p];
     // delta r_ij = u_j - u_i + eps r_ij
     const T dx = la.u[3 * (size_t)j] - ux + (e00 * x + e01 * y + e02 * z);
@@ -546,9 +549,10 @@ __global__ void __launch_bounds__(BLOCK) creduce_kernel(const mtp::EvalArgs<T> a
       bool any = false;
       for (int p = 0; p < cnt; ++p) {{
         const size_t e = (size_t)p * args.stride + i;
-        if (args.pzj[e] != zj) continue;
+        const mtp::PairRec<T> pq = args.pr[e];
+        if (pq.zj != zj) continue;
         any = true;
-        const T x = args.px[e], y = args.py[e], z = args.pz[e];
+        const T x = pq.x, y = pq.y, z = pq.z;
         const T r = sqrt(x * x + y * y + z * z);
         const T q = (T(2) * r - args.rmin - args.rcut) * span_inv;
         const T dqdr = T(2) * span_inv;
@@ -633,7 +637,8 @@ __global__ void __launch_bounds__(BLOCK) moments_kernel(const mtp::EvalArgs<T> a
   T xn = T(0), yn = T(0), zn = T(0);
   int zjn = 0;
   if (cnt > 0) {{
-    xn = args.px[i]; yn = args.py[i]; zn = args.pz[i]; zjn = args.pzj[i];
+    const mtp::PairRec<T> q = args.pr[i];
+    xn = q.x; yn = q.y; zn = q.z; zjn = q.zj;
   }}
 #pragma unroll 1
   for (int p = 0; p < cnt; ++p) {{
@@ -641,14 +646,15 @@ __global__ void __launch_bounds__(BLOCK) moments_kernel(const mtp::EvalArgs<T> a
     const int zj = zjn;
     if (p + 1 < cnt) {{
       const size_t en = (size_t)(p + 1) * args.stride + i;
-      xn = args.px[en]; yn = args.py[en]; zn = args.pz[en]; zjn = args.pzj[en];
+      const mtp::PairRec<T> q = args.pr[en];
+      xn = q.x; yn = q.y; zn = q.z; zjn = q.zj;
     }}
     const T r = sqrt(x * x + y * y + z * z);
     T f[NMU], df[NMU];
     mtp::radial<T, NMU, false>(cs, (zi * S + zj) * nq, mu_stride, nq, r, rmin, rcut, f, df);
 {pair_fwd}
   }}
-  if (COMP) {{
+  if constexpr (COMP) {{
 #pragma unroll
     for (int k = 0; k < C; ++k) M[k] += Mlo[k];
   }}

@@ -99,7 +99,7 @@ struct mtp_model {
   Buffer ainv, gj_work, gj_flag;
   // workspace
   Buffer cfg, atom_cfg, atom_bin, bin_count, bin_start, bin_atoms, bin_fill, nbins_dev;
-  Buffer count, nbr_row, nbr_z, px, py, pz, rev, gpair, Mbuf, Gbuf, site, wv, B, status;
+  Buffer count, nbr_row, pr, rev, gpair, Mbuf, Gbuf, site, wv, B, status, run_start;
   int K = 64;  // neighbour capacity per atom, grown on overflow
   Buffer b_tmp, c_tmp;
   int last_stride = 0;
@@ -302,10 +302,7 @@ mtp::EvalArgs<T> make_args(mtp_model* M, int64_t n_atoms, int stride, const int3
   a.rmin = (T)M->rmin;
   a.rcut = (T)M->rcut;
   a.nbr_count = M->count.as<int>();
-  a.px = M->px.as<T>();
-  a.py = M->py.as<T>();
-  a.pz = M->pz.as<T>();
-  a.pzj = M->nbr_z.as<int>();
+  a.pr = M->pr.as<mtp::PairRec<T>>();
   a.species = species;
   a.c = std::is_same<T, double>::value ? (const T*)M->c64.p : (const T*)M->c32.p;
   a.xi = std::is_same<T, double>::value ? (const T*)M->xi64.p : (const T*)M->xi32.p;
@@ -340,16 +337,14 @@ int run_eval(mtp_model* M, const mtp_batch* bt, const mtp_out* out, int precisio
     HIP_TRY(b->ensure(sizeof(int32_t) * (N + 1)), "hipMalloc");
   const int stride = (int)((N + 63) / 64 * 64);
   const bool want_b = out->b != nullptr;
+  HIP_TRY(M->run_start.ensure(sizeof(int16_t) * 256 * (size_t)(N + 1)), "hipMalloc");
   for (int attempt = 0; attempt < 2; ++attempt) {
     const int K = M->K;
     const size_t slots = (size_t)K * stride;
     if (slots >= (size_t)0x7fffffff) return fail(MTP_E_CAPACITY, "neighbour slots exceed 2^31 (split the batch)");
     HIP_TRY(M->nbr_row.ensure(sizeof(int32_t) * (size_t)K * (N + 1)), "hipMalloc");
-    HIP_TRY(M->nbr_z.ensure(sizeof(int32_t) * slots), "hipMalloc");
     HIP_TRY(M->rev.ensure(sizeof(int32_t) * slots), "hipMalloc");
-    HIP_TRY(M->px.ensure(tsz * slots), "hipMalloc");
-    HIP_TRY(M->py.ensure(tsz * slots), "hipMalloc");
-    HIP_TRY(M->pz.ensure(tsz * slots), "hipMalloc");
+    HIP_TRY(M->pr.ensure((fp64 ? sizeof(PairRec<double>) : sizeof(PairRec<float>)) * slots), "hipMalloc");
     HIP_TRY(M->gpair.ensure(tsz * 3 * slots), "hipMalloc");
     HIP_TRY(M->Gbuf.ensure(tsz * (size_t)M->var->C * stride), "hipMalloc");
     HIP_TRY(M->Mbuf.ensure(tsz * (size_t)M->var->C * stride), "hipMalloc");
@@ -381,12 +376,10 @@ int run_eval(mtp_model* M, const mtp_batch* bt, const mtp_out* out, int precisio
     a.stride = stride;
     a.K = K;
     a.nbr_row = M->nbr_row.as<int32_t>();
-    a.nbr_z = M->nbr_z.as<int32_t>();
-    a.px = M->px.p;
-    a.py = M->py.p;
-    a.pz = M->pz.p;
+    a.pr = M->pr.p;
     a.fp64 = fp64 ? 1 : 0;
     a.rev = M->rev.as<int32_t>();
+    a.run_start = M->run_start.as<int16_t>();
     a.status = M->status.as<Status>();
     HIP_TRY(nbr_build(a, s), "neighbour search");
     HIP_TRY(mark(1), "hipEventRecord");
@@ -400,8 +393,8 @@ int run_eval(mtp_model* M, const mtp_batch* bt, const mtp_out* out, int precisio
       }
     }
     HIP_TRY(mark(2), "hipEventRecord");
-    HIP_TRY(gather_forces(fp64, N, stride, M->count.as<int32_t>(), M->rev.as<int32_t>(), M->gpair.p, M->px.p,
-                          M->py.p, M->pz.p, out->forces, out->virial ? M->wv.p : nullptr, s),
+    HIP_TRY(gather_forces(fp64, N, stride, M->count.as<int32_t>(), M->rev.as<int32_t>(), M->gpair.p, M->pr.p,
+                          out->forces, out->virial ? M->wv.p : nullptr, s),
             "force gather");
     HIP_TRY(mark(3), "hipEventRecord");
     HIP_TRY(reduce_configs(fp64, n_cfg, M->cfg.as<CfgInfo>(), stride, M->site.p, out->virial ? M->wv.p : nullptr,

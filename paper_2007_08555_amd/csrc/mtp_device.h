@@ -11,6 +11,22 @@
 
 namespace mtp {
 
+// One neighbour pair as stored in the ELL lists: r_ij = x_j + n.L - x_i and
+// the neighbour's species, written and read as one 16-byte-aligned record.
+template <typename T>
+struct PairRec;
+template <>
+struct alignas(16) PairRec<double> {
+  double x, y, z;
+  int zj;
+  int pad;
+};
+template <>
+struct alignas(16) PairRec<float> {
+  float x, y, z;
+  int zj;
+};
+
 // Arguments of one evaluation launch.  Pair data uses an ELL layout: slot p of
 // atom i lives at p * stride + i, so a wavefront of consecutive atoms reads and
 // writes consecutive addresses for the same slot.
@@ -23,10 +39,7 @@ struct EvalArgs {
   int n_c;             // n_mu * S * S * N_Q
   T rmin, rcut;
   const int* nbr_count;  // [n_atoms]
-  const T* px;           // [K * stride] pair vectors r_ij = x_j + n.L - x_i
-  const T* py;
-  const T* pz;
-  const int* pzj;        // [K * stride] species of the neighbour
+  const PairRec<T>* pr;  // [K * stride] pair vectors and neighbour species
   const int* species;    // [n_atoms]
   const T* c;            // [n_mu][S][S][N_Q]
   const T* xi;           // [m] in the kernel's basis order

@@ -50,12 +50,10 @@ struct NbrArgs {
   int stride;            // ELL pitch (>= n_atoms)
   int K;                 // ELL slots per atom
   int32_t* nbr_row;      // [n_atoms][K] neighbour home index, row-major per atom
-  int32_t* nbr_z;        // [K * stride] neighbour species
-  void* px;              // [K * stride] pair vectors, FP32 or FP64
-  void* py;
-  void* pz;
-  int fp64;              // pair vector type
+  void* pr;              // [K * stride] PairRec<double> or PairRec<float>
+  int fp64;              // pair record type
   int32_t* rev;          // [K * stride] ELL index of the reverse pair
+  int16_t* run_start;    // [n_atoms][256] scratch of the small-configuration search
   Status* status;
 };
 
@@ -69,8 +67,8 @@ hipError_t zero_words(int32_t* p, int64_t n, hipStream_t s);
 // Forces F_i = sum over slots (g_p - g_rev(p)) and per-atom virials
 // sum_p g_p (x) r_p; g packed [K * stride][3]; either output may be null.
 hipError_t gather_forces(int fp64, int64_t n_atoms, int stride, const int32_t* count,
-                         const int32_t* rev, const void* g, const void* px, const void* py,
-                         const void* pz, double* forces, void* atom_virial, hipStream_t s);
+                         const int32_t* rev, const void* g, const void* pr, double* forces,
+                         void* atom_virial, hipStream_t s);
 
 // Per-configuration sums of site energies, virials and B (kernel order ->
 // file order through perm, which maps file index -> kernel index), over the

@@ -22,6 +22,7 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 
+#include "mtp_device.h"
 #include "mtp_internal.h"
 
 namespace mtp {
@@ -29,8 +30,8 @@ namespace {
 
 constexpr int kBlock = 256;
 constexpr int kBinnedMinAtoms = 2048;
-constexpr int kSmallMax = 1024;   // configurations searched by one workgroup from LDS
-constexpr int kSmallBlock = 128;
+constexpr int kSmallMax = 256;    // configurations searched by one workgroup from LDS
+constexpr int kSmallBlock = 256;
 
 __device__ inline bool is_small(const CfgInfo& c) { return !c.binned && c.n <= kSmallMax; }
 
@@ -131,6 +132,32 @@ __device__ inline int3 bin_of(const CfgInfo& c, double x, double y, double z) {
 
 __device__ inline bool in_cfg(const CfgInfo& c, int64_t i) { return i >= c.start && i < c.start + c.n; }
 
+// One record per pair (the FP32 path rounds the FP64 pair vector).
+__device__ inline void store_pair(const NbrArgs& a, size_t e, double rx, double ry, double rz, int zj) {
+  if (a.fp64) {
+    PairRec<double> q;
+    q.x = rx; q.y = ry; q.z = rz; q.zj = zj; q.pad = 0;
+    ((PairRec<double>*)a.pr)[e] = q;
+  } else {
+    PairRec<float> q;
+    q.x = (float)rx; q.y = (float)ry; q.z = (float)rz; q.zj = zj;
+    ((PairRec<float>*)a.pr)[e] = q;
+  }
+}
+
+// Conservative image box of one pair: every integer n_d with
+// |s_d + n_d| <= w_d, widened by a small margin (bounds in FP32; membership
+// is decided by the exact FP64 distance test).
+__device__ inline void image_box(const CfgInfo& c, double dx, double dy, double dz, int (&lo)[3], int (&hi)[3]) {
+  const float fx = (float)dx, fy = (float)dy, fz = (float)dz;
+  for (int d = 0; d < 3; ++d) {
+    const float s = fx * (float)c.inv[0 * 3 + d] + fy * (float)c.inv[1 * 3 + d] + fz * (float)c.inv[2 * 3 + d];
+    const float w = (float)c.w[d] + 1e-3f;
+    lo[d] = -(int)floorf(w + s);
+    hi[d] = (int)floorf(w - s);
+  }
+}
+
 __global__ void bin_count_kernel(NbrArgs a) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= a.n_atoms) return;
@@ -222,17 +249,8 @@ struct Emitter {
       const size_t e = (size_t)count * a.stride + i;
       int zj = a.species[j];
       zj = zj < 0 ? 0 : (zj >= a.n_species ? a.n_species - 1 : zj);
-      a.nbr_z[e] = zj;
       a.nbr_row[(size_t)i * a.K + count] = j;
-      if (a.fp64) {
-        ((double*)a.px)[e] = rx;
-        ((double*)a.py)[e] = ry;
-        ((double*)a.pz)[e] = rz;
-      } else {
-        ((float*)a.px)[e] = (float)rx;
-        ((float*)a.py)[e] = (float)ry;
-        ((float*)a.pz)[e] = (float)rz;
-      }
+      store_pair(a, e, rx, ry, rz, zj);
     }
     if (r2 < rmin2) ++below;
     ++count;
@@ -264,6 +282,7 @@ __global__ void __launch_bounds__(kBlock) search_kernel(NbrArgs a) {
     const double rc2 = a.rcut * a.rcut;
     const double* L = c.L;
     const double* inv = c.inv;
+    (void)inv;
     if (!c.binned) {
       const int64_t j0 = c.start, j1 = c.start + c.n;
       for (int64_t j = j0; j < j1; ++j) {
@@ -275,11 +294,7 @@ __global__ void __launch_bounds__(kBlock) search_kernel(NbrArgs a) {
         }
         // images with |s_d + n_d| <= w_d can lie within R_cut
         int lo[3], hi[3];
-        for (int d = 0; d < 3; ++d) {
-          const double s = dx * inv[0 * 3 + d] + dy * inv[1 * 3 + d] + dz * inv[2 * 3 + d];
-          lo[d] = -(int)floor(c.w[d] + s + 1e-9);
-          hi[d] = (int)floor(c.w[d] - s + 1e-9);
-        }
+        image_box(c, dx, dy, dz, lo, hi);
         for (int n0 = lo[0]; n0 <= hi[0]; ++n0)
           for (int n1 = lo[1]; n1 <= hi[1]; ++n1)
             for (int n2 = lo[2]; n2 <= hi[2]; ++n2) {
@@ -370,8 +385,10 @@ __global__ void reverse_kernel(NbrArgs a) {
 
 
 // Whole search of one small configuration in one workgroup: positions staged
-// in LDS, lists written to the ELL arrays, then (after a barrier) the reverse
-// index of every pair of the configuration.
+// in LDS, one atom per thread, lists written to the ELL arrays.  While atom i
+// walks its neighbours in order it records where the run of each neighbour j
+// starts in its own list (run_start[i][j]); after a barrier the reverse of
+// the r-th image in i's run of j is run_start[j][i] + k - 1 - r (k images).
 __global__ void __launch_bounds__(kSmallBlock) search_small_kernel(NbrArgs a) {
   __shared__ double sp[3 * kSmallMax];
   __shared__ unsigned long long red[5];
@@ -386,70 +403,60 @@ __global__ void __launch_bounds__(kSmallBlock) search_small_kernel(NbrArgs a) {
   const double rmin2 = a.rmin * a.rmin;
   const double* L = c.L;
   const double* inv = c.inv;
-  int cmax = 0, csum = 0, over = 0, below = 0, bad = 0;
-  for (int li = t; li < n; li += blockDim.x) {
+  // run starts of this configuration: rows of n int16 at the config's atom offset
+  int16_t* run_start = a.run_start + (size_t)c.start * kSmallMax;
+  const int li = t;
+  int count = 0, below = 0, bad = 0;
+  if (li < n) {
     const int64_t i = c.start + li;
-    if (a.species[i] < 0 || a.species[i] >= a.n_species) ++bad;
+    if (a.species[i] < 0 || a.species[i] >= a.n_species) bad = 1;
     const double xi = sp[3 * li], yi = sp[3 * li + 1], zi = sp[3 * li + 2];
-    int count = 0;
     int32_t* row = a.nbr_row + (size_t)i * a.K;
+    int16_t* my_starts = run_start + (size_t)li * n;
     auto emit = [&](int lj, double rx, double ry, double rz, double r2) {
       if (count < a.K) {
         const size_t e = (size_t)count * a.stride + i;
         const int64_t j = c.start + lj;
         int zj = a.species[j];
         zj = zj < 0 ? 0 : (zj >= a.n_species ? a.n_species - 1 : zj);
-        a.nbr_z[e] = zj;
         row[count] = (int32_t)j;
-        if (a.fp64) {
-          ((double*)a.px)[e] = rx;
-          ((double*)a.py)[e] = ry;
-          ((double*)a.pz)[e] = rz;
-        } else {
-          ((float*)a.px)[e] = (float)rx;
-          ((float*)a.py)[e] = (float)ry;
-          ((float*)a.pz)[e] = (float)rz;
-        }
+        store_pair(a, e, rx, ry, rz, zj);
       }
       if (r2 < rmin2) ++below;
       ++count;
     };
     for (int lj = 0; lj < n; ++lj) {
+      const int before = count;
       const double dx = sp[3 * lj] - xi, dy = sp[3 * lj + 1] - yi, dz = sp[3 * lj + 2] - zi;
       if (!c.pbc) {
         const double r2 = dx * dx + dy * dy + dz * dz;
         if (lj != li && r2 < rc2) emit(lj, dx, dy, dz, r2);
-        continue;
+      } else {
+        int lo[3], hi[3];
+        image_box(c, dx, dy, dz, lo, hi);
+        for (int n0 = lo[0]; n0 <= hi[0]; ++n0)
+          for (int n1 = lo[1]; n1 <= hi[1]; ++n1)
+            for (int n2 = lo[2]; n2 <= hi[2]; ++n2) {
+              if (lj == li && n0 == 0 && n1 == 0 && n2 == 0) continue;
+              const double sx = (double)n0 * L[0] + (double)n1 * L[3] + (double)n2 * L[6];
+              const double sy = (double)n0 * L[1] + (double)n1 * L[4] + (double)n2 * L[7];
+              const double sz = (double)n0 * L[2] + (double)n1 * L[5] + (double)n2 * L[8];
+              const double rx = dx + sx, ry = dy + sy, rz = dz + sz;
+              const double r2 = rx * rx + ry * ry + rz * rz;
+              if (r2 < rc2) emit(lj, rx, ry, rz, r2);
+            }
       }
-      int lo[3], hi[3];
-      for (int d = 0; d < 3; ++d) {
-        const double s = dx * inv[0 * 3 + d] + dy * inv[1 * 3 + d] + dz * inv[2 * 3 + d];
-        lo[d] = -(int)floor(c.w[d] + s + 1e-9);
-        hi[d] = (int)floor(c.w[d] - s + 1e-9);
-      }
-      for (int n0 = lo[0]; n0 <= hi[0]; ++n0)
-        for (int n1 = lo[1]; n1 <= hi[1]; ++n1)
-          for (int n2 = lo[2]; n2 <= hi[2]; ++n2) {
-            if (lj == li && n0 == 0 && n1 == 0 && n2 == 0) continue;
-            const double sx = (double)n0 * L[0] + (double)n1 * L[3] + (double)n2 * L[6];
-            const double sy = (double)n0 * L[1] + (double)n1 * L[4] + (double)n2 * L[7];
-            const double sz = (double)n0 * L[2] + (double)n1 * L[5] + (double)n2 * L[8];
-            const double rx = dx + sx, ry = dy + sy, rz = dz + sz;
-            const double r2 = rx * rx + ry * ry + rz * rz;
-            if (r2 < rc2) emit(lj, rx, ry, rz, r2);
-          }
+      if (count > before && before < a.K) my_starts[lj] = (int16_t)before;
     }
     a.count[i] = count < a.K ? count : a.K;
-    cmax = max(cmax, count);
-    csum += count;
-    if (count > a.K) ++over;
   }
-  atomicMax(&red[0], (unsigned long long)cmax);
-  atomicAdd(&red[1], (unsigned long long)csum);
-  if (over) atomicAdd(&red[2], (unsigned long long)over);
+  const int over = count > a.K ? 1 : 0;
+  atomicMax(&red[0], (unsigned long long)count);
+  atomicAdd(&red[1], (unsigned long long)count);
+  if (over) atomicAdd(&red[2], 1ull);
   if (below) atomicAdd(&red[3], (unsigned long long)below);
-  if (bad) atomicAdd(&red[4], (unsigned long long)bad);
-  __syncthreads();  // lists of the whole configuration are written
+  if (bad) atomicAdd(&red[4], 1ull);
+  __syncthreads();  // lists and run starts of the whole configuration are written
   if (t == 0) {
     atomicMax(&a.status->max_count, red[0]);
     atomicAdd(&a.status->n_pairs, red[1]);
@@ -457,33 +464,29 @@ __global__ void __launch_bounds__(kSmallBlock) search_small_kernel(NbrArgs a) {
     if (red[3]) atomicAdd(&a.status->below_rmin, red[3]);
     if (red[4]) atomicAdd(&a.status->bad_species, red[4]);
   }
-  // reverse indices: the run of j in row_i and the run of i in row_j
+  if (li >= n || red[2]) return;   // on overflow the call is repeated with more slots
+  const int64_t i = c.start + li;
+  const int ci = a.count[i];
+  const int32_t* row_i = a.nbr_row + (size_t)i * a.K;
   unsigned long long errs = 0;
-  for (int li = t; li < n; li += blockDim.x) {
-    const int64_t i = c.start + li;
-    const int ci = a.count[i];
-    const int32_t* row_i = a.nbr_row + (size_t)i * a.K;
-    int rank = 0;
-    for (int p = 0; p < ci; ++p) {
-      const int32_t j = row_i[p];
-      rank = (p > 0 && row_i[p - 1] == j) ? rank + 1 : 0;
-      const int32_t* row_j = a.nbr_row + (size_t)j * a.K;
-      const int cj = a.count[j];
-      int q0 = 0, hi = cj;
-      while (q0 < hi) {
-        const int mid = (q0 + hi) >> 1;
-        if (row_j[mid] < (int32_t)i) q0 = mid + 1; else hi = mid;
-      }
-      int k = 0;
-      while (q0 + k < cj && row_j[q0 + k] == (int32_t)i) ++k;
-      const size_t e = (size_t)p * a.stride + i;
-      if (k > rank) {
-        a.rev[e] = (int32_t)((size_t)(q0 + k - 1 - rank) * a.stride + j);
+  int p = 0;
+  while (p < ci) {
+    const int32_t j = row_i[p];
+    int k = 1;
+    while (p + k < ci && row_i[p + k] == j) ++k;
+    const int lj = (int)(j - c.start);
+    const int q0 = run_start[(size_t)lj * n + li];
+    for (int r = 0; r < k; ++r) {
+      const size_t e = (size_t)(p + r) * a.stride + i;
+      const int q = q0 + k - 1 - r;
+      if (q >= 0 && q < a.count[j]) {
+        a.rev[e] = (int32_t)((size_t)q * a.stride + j);
       } else {
         a.rev[e] = (int32_t)e;
         ++errs;
       }
     }
+    p += k;
   }
   if (errs) atomicAdd(&a.status->list_errors, errs);
 }

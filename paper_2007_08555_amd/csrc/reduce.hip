@@ -6,6 +6,7 @@
 // x_i through r_ji (dr_ji/dx_i = +I).  The gather is deterministic.
 #include <hip/hip_runtime.h>
 
+#include "mtp_device.h"
 #include "mtp_internal.h"
 
 namespace mtp {
@@ -18,8 +19,7 @@ constexpr int kBlock = 256;
 template <typename T>
 __global__ void gather_kernel(int64_t n_atoms, int stride, const int32_t* __restrict__ count,
                               const int32_t* __restrict__ rev, const T* __restrict__ g,
-                              const T* __restrict__ px, const T* __restrict__ py,
-                              const T* __restrict__ pz, double* __restrict__ F, T* __restrict__ wv) {
+                              const PairRec<T>* __restrict__ pr, double* __restrict__ F, T* __restrict__ wv) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n_atoms) return;
   double fx = 0, fy = 0, fz = 0;
@@ -35,7 +35,8 @@ __global__ void gather_kernel(int64_t n_atoms, int stride, const int32_t* __rest
       fz += gz - (double)g[3 * q + 2];
     }
     if (wv) {
-      const double x = (double)px[e], y = (double)py[e], z = (double)pz[e];
+      const PairRec<T> q = pr[e];
+      const double x = (double)q.x, y = (double)q.y, z = (double)q.z;
       w[0] += gx * x; w[1] += gx * y; w[2] += gx * z;
       w[3] += gy * x; w[4] += gy * y; w[5] += gy * z;
       w[6] += gz * x; w[7] += gz * y; w[8] += gz * z;
@@ -104,18 +105,16 @@ __global__ void __launch_bounds__(kBlock) b_kernel(int n_cfg, const CfgInfo* __r
 }  // namespace
 
 hipError_t gather_forces(int fp64, int64_t n_atoms, int stride, const int32_t* count,
-                         const int32_t* rev, const void* gp, const void* px, const void* py,
-                         const void* pz, double* forces, void* atom_virial, hipStream_t s) {
+                         const int32_t* rev, const void* gp, const void* pr, double* forces,
+                         void* atom_virial, hipStream_t s) {
   if (n_atoms == 0 || (!forces && !atom_virial)) return hipSuccess;
   const dim3 g((unsigned)((n_atoms + kBlock - 1) / kBlock));
   if (fp64)
     hipLaunchKernelGGL(gather_kernel<double>, g, dim3(kBlock), 0, s, n_atoms, stride, count, rev,
-                       (const double*)gp, (const double*)px, (const double*)py, (const double*)pz, forces,
-                       (double*)atom_virial);
+                       (const double*)gp, (const PairRec<double>*)pr, forces, (double*)atom_virial);
   else
     hipLaunchKernelGGL(gather_kernel<float>, g, dim3(kBlock), 0, s, n_atoms, stride, count, rev,
-                       (const float*)gp, (const float*)px, (const float*)py, (const float*)pz, forces,
-                       (float*)atom_virial);
+                       (const float*)gp, (const PairRec<float>*)pr, forces, (float*)atom_virial);
   return hipGetLastError();
 }
 
