@@ -3,7 +3,8 @@
 
 One step is one pass of the whole evaluation path over one batch resident in
 HBM: neighbour lists, radial functions, moments, contractions, adjoint,
-force gather, per-configuration energy / virial sums.
+force gather, per-configuration energy / virial sums.  The step is captured
+once in a HIP graph (mtp_eval_async) and replayed; eager calls are timed too.
 
 Workload (default): 4096 configurations of 8..256 atoms (about 530 k atoms),
 random fcc/bcc/hcp periodic cells with vacancies and free fragments,
@@ -68,6 +69,7 @@ def main():
     ap.add_argument("--plain-configs", type=int, default=256)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-extras", action="store_true", help="skip plain path, bcc box and CPU baseline")
+    ap.add_argument("--no-graph", action="store_true", help="time eager calls instead of HIP-graph replays")
     a = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if a.gpus != 1 or world != 1:
@@ -94,14 +96,38 @@ def main():
     def step():
         return P.eval(B, precision=a.precision, forces=True, virial=True, energy=True, stream=stream)
 
-    for _ in range(a.warmup):
+    for _ in range(max(1, a.warmup)):
         step()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(a.steps):
         step()
     torch.cuda.synchronize()
-    dt = (time.perf_counter() - t0) / a.steps
+    dt_eager = (time.perf_counter() - t0) / a.steps
+    log(f"batched, eager calls: {dt_eager * 1e3:.3f} ms/step")
+    dt = dt_eager
+    if not a.no_graph:
+        # the same step captured once in a HIP graph and replayed
+        out = P.outputs(B)
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            P.eval_async(B, out, precision=a.precision, stream=side)
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            P.eval_async(B, out, precision=a.precision)
+        for _ in range(a.warmup):
+            graph.replay()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(a.steps):
+            graph.replay()
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / a.steps
+        P.status()   # raises if a replay met a capacity or input problem
+        log(f"batched, graph replay: {dt * 1e3:.3f} ms/step")
     value = n_atoms / dt
     log(f"batched: {dt * 1e3:.3f} ms/step, {value:.4g} atom-evals/s")
 
@@ -129,8 +155,9 @@ def main():
             "vs_baseline": None, "dtype": DTYPE[a.precision], "data": "synthetic",
             "config": {"workload": f"batched: {a.configs} mixed fcc/bcc/hcp cells and fragments, 8-256 atoms, "
                                    f"{n_atoms} atoms, 1-3 of 3 species, MTP level 16, N_Q 8, R_cut 5 A",
-                       "precision": a.precision, "level": 16, "atoms": n_atoms, "configs": a.configs},
-            "roofline": roofline}
+                       "precision": a.precision, "level": 16, "atoms": n_atoms, "configs": a.configs,
+                       "graph_replay": not a.no_graph},
+            "roofline": roofline, "eager_ms_per_step": dt_eager * 1e3}
 
     if not a.no_extras:
         # the plain path: one configuration per call, same configurations

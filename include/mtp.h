@@ -120,6 +120,17 @@ int mtp_eval(mtp_model* model, const mtp_batch* batch, const mtp_out* out,
              int precision, void* stream);
 
 /*
+ * mtp_eval without any host synchronisation or allocation, for capture into
+ * a HIP graph and replay: the workspace (including the neighbour capacity)
+ * must have been sized by an earlier mtp_eval on the same batch or a larger
+ * one (MTP_E_STATE otherwise).  Conditions the synchronous call would report
+ * (invalid offsets or species, more neighbours than the capacity) are only
+ * recorded on the device; mtp_status returns them.  Timing is not recorded.
+ */
+int mtp_eval_async(mtp_model* model, const mtp_batch* batch, const mtp_out* out,
+                   int precision, void* stream);
+
+/*
  * Sets the active set of section 2.3: A (device, [m][m] FP64, row j = b of
  * active configuration j, columns in file basis order).  A^{-1} is formed
  * on the device by FP64 Gauss-Jordan elimination with partial pivoting and
@@ -163,6 +174,8 @@ int mtp_loss_grad(mtp_model* model, const mtp_batch* batch, const double* E_t, c
  * Device-side counters of the last mtp_eval on this model: pairs closer than
  * R_min (the radial polynomial is then evaluated outside [R_min, R_cut]) and
  * neighbour-list inconsistencies (always 0 unless memory was corrupted).
+ * Returns MTP_E_ARG or MTP_E_CAPACITY when the last (asynchronous)
+ * evaluation met invalid input or exceeded the neighbour capacity.
  * Synchronises `stream`.
  */
 int mtp_status(mtp_model* model, void* stream, int64_t* n_below_rmin, int64_t* n_list_errors);

@@ -319,7 +319,8 @@ mtp::EvalArgs<T> make_args(mtp_model* M, int64_t n_atoms, int stride, const int3
 // Neighbour search, evaluation kernels, force gather and reductions, with
 // one host synchronisation at the end to read the status (and a second pass
 // if an atom had more neighbours than the current capacity).
-int run_eval(mtp_model* M, const mtp_batch* bt, const mtp_out* out, int precision, hipStream_t s) {
+int run_eval(mtp_model* M, const mtp_batch* bt, const mtp_out* out, int precision, hipStream_t s,
+             bool async = false) {
   using namespace mtp;
   const int64_t N = bt->n_atoms;
   const int n_cfg = bt->n_configs;
@@ -328,29 +329,47 @@ int run_eval(mtp_model* M, const mtp_batch* bt, const mtp_out* out, int precisio
   M->timed = false;
   M->last_stream = s;
   if (N > 0x7fffffffLL / 8) return fail(MTP_E_CAPACITY, "too many atoms in one batch");
-  auto mark = [&](int k) -> hipError_t { return M->timing ? hipEventRecord(M->ev[k], s) : hipSuccess; };
-  HIP_TRY(M->status.ensure(sizeof(Status)), "hipMalloc");
+  const bool timing = M->timing && !async;
+  auto mark = [&](int k) -> hipError_t { return timing ? hipEventRecord(M->ev[k], s) : hipSuccess; };
+  // in the asynchronous form nothing is allocated: every buffer must already
+  // be large enough (sized by an earlier synchronous call)
+  auto need = [&](Buffer& b, size_t bytes) -> int {
+    if (async) {
+      if (!b.p || b.bytes < bytes)
+        return fail(MTP_E_STATE, "workspace too small for an asynchronous call: run mtp_eval on this batch first");
+      return MTP_OK;
+    }
+    HIP_TRY(b.ensure(bytes), "hipMalloc");
+    return MTP_OK;
+  };
+#define NEED(buf, bytes)                     \
+  do {                                       \
+    int rc_ = need(buf, bytes);              \
+    if (rc_ != MTP_OK) return rc_;           \
+  } while (0)
+  NEED(M->status, sizeof(Status));
   if (n_cfg == 0) return MTP_OK;
-  HIP_TRY(M->cfg.ensure(sizeof(CfgInfo) * n_cfg), "hipMalloc");
+  NEED(M->cfg, sizeof(CfgInfo) * n_cfg);
   for (Buffer* b : {&M->atom_cfg, &M->atom_bin, &M->bin_count, &M->bin_start, &M->bin_fill, &M->bin_atoms,
                     &M->count})
-    HIP_TRY(b->ensure(sizeof(int32_t) * (N + 1)), "hipMalloc");
+    NEED(*b, sizeof(int32_t) * (N + 1));
   const int stride = (int)((N + 63) / 64 * 64);
   const bool want_b = out->b != nullptr;
-  HIP_TRY(M->run_start.ensure(sizeof(int16_t) * 256 * (size_t)(N + 1)), "hipMalloc");
+  NEED(M->run_start, sizeof(int16_t) * 256 * (size_t)(N + 1));
   for (int attempt = 0; attempt < 2; ++attempt) {
     const int K = M->K;
     const size_t slots = (size_t)K * stride;
     if (slots >= (size_t)0x7fffffff) return fail(MTP_E_CAPACITY, "neighbour slots exceed 2^31 (split the batch)");
-    HIP_TRY(M->nbr_row.ensure(sizeof(int32_t) * (size_t)K * (N + 1)), "hipMalloc");
-    HIP_TRY(M->rev.ensure(sizeof(int32_t) * slots), "hipMalloc");
-    HIP_TRY(M->pr.ensure((fp64 ? sizeof(PairRec<double>) : sizeof(PairRec<float>)) * slots), "hipMalloc");
-    HIP_TRY(M->gpair.ensure(tsz * 3 * slots), "hipMalloc");
-    HIP_TRY(M->Gbuf.ensure(tsz * (size_t)M->var->C * stride), "hipMalloc");
-    HIP_TRY(M->Mbuf.ensure(tsz * (size_t)M->var->C * stride), "hipMalloc");
-    HIP_TRY(M->site.ensure(tsz * stride), "hipMalloc");
-    HIP_TRY(M->wv.ensure(tsz * 9 * stride), "hipMalloc");
-    if (want_b) HIP_TRY(M->B.ensure(tsz * (size_t)M->m * stride), "hipMalloc");
+    NEED(M->nbr_row, sizeof(int32_t) * (size_t)K * (N + 1));
+    NEED(M->rev, sizeof(int32_t) * slots);
+    NEED(M->pr, (fp64 ? sizeof(PairRec<double>) : sizeof(PairRec<float>)) * slots);
+    NEED(M->gpair, tsz * 3 * slots);
+    NEED(M->Gbuf, tsz * (size_t)M->var->C * stride);
+    NEED(M->Mbuf, tsz * (size_t)M->var->C * stride);
+    NEED(M->site, tsz * stride);
+    NEED(M->wv, tsz * 9 * stride);
+    if (want_b) NEED(M->B, tsz * (size_t)M->m * stride);
+#undef NEED
 
     HIP_TRY(mark(0), "hipEventRecord");
     HIP_TRY(zero_words((int32_t*)M->status.p, sizeof(Status) / sizeof(int32_t), s), "status reset");
@@ -402,6 +421,7 @@ int run_eval(mtp_model* M, const mtp_batch* bt, const mtp_out* out, int precisio
                            out->virial, out->b, out->site_energy, s),
             "reductions");
     HIP_TRY(mark(4), "hipEventRecord");
+    if (async) return MTP_OK;  // the caller reads the status later (mtp_status)
     Status st{};
     HIP_TRY(hipMemcpyAsync(&st, M->status.p, sizeof(Status), hipMemcpyDeviceToHost, s), "hipMemcpyAsync");
     HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
@@ -487,6 +507,19 @@ int mtp_eval(mtp_model* M, const mtp_batch* bt, const mtp_out* out, int precisio
   if (bt->n_atoms > 0 && (!bt->pos || !bt->species)) return fail(MTP_E_ARG, "mtp_eval: null batch array");
   HIP_TRY(hipSetDevice(M->device), "hipSetDevice");
   return run_eval(M, bt, out, precision, (hipStream_t)stream);
+}
+
+int mtp_eval_async(mtp_model* M, const mtp_batch* bt, const mtp_out* out, int precision, void* stream) {
+  g_err.clear();
+  if (!M || !bt || !out) return fail(MTP_E_ARG, "mtp_eval_async: null argument");
+  if (precision < MTP_FP64 || precision > MTP_FP32_COMPENSATED) return fail(MTP_E_ARG, "mtp_eval_async: bad precision");
+  if (bt->n_configs < 0 || bt->n_atoms < 0) return fail(MTP_E_ARG, "mtp_eval_async: negative size");
+  if (bt->n_configs > 0 && (!bt->atom_offsets || !bt->cell || !bt->pbc))
+    return fail(MTP_E_ARG, "mtp_eval_async: null batch array");
+  if (bt->n_atoms > 0 && (!bt->pos || !bt->species)) return fail(MTP_E_ARG, "mtp_eval_async: null batch array");
+  HIP_TRY(hipSetDevice(M->device), "hipSetDevice");
+  M->timed = false;
+  return run_eval(M, bt, out, precision, (hipStream_t)stream, true);
 }
 
 int mtp_set_active_set(mtp_model* M, const double* A_dev, void* stream) {
@@ -655,6 +688,10 @@ int mtp_status(mtp_model* M, void* stream, int64_t* n_below_rmin, int64_t* n_lis
   }
   if (n_below_rmin) *n_below_rmin = (int64_t)st.below_rmin;
   if (n_list_errors) *n_list_errors = (int64_t)st.list_errors;
+  // conditions an asynchronous evaluation could only record
+  if (st.bad_offsets) return fail(MTP_E_ARG, "last evaluation: atom_offsets must be non-decreasing from 0 to n_atoms");
+  if (st.bad_species) return fail(MTP_E_ARG, "last evaluation: species index outside [0, species_count)");
+  if (st.overflow) return fail(MTP_E_CAPACITY, "last evaluation: an atom had more neighbours than the workspace holds");
   return MTP_OK;
 }
 

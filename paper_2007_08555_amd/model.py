@@ -123,6 +123,34 @@ class Potential:
                                   _ptr(grad), _stream(stream)), "mtp_loss_grad")
         return loss, grad
 
+    def outputs(self, batch: Batch, forces=True, virial=True, site=False, b=False, energy=True):
+        """Preallocated output tensors for eval_async (dict as returned by eval)."""
+        dev = self.device
+        K, N = batch.n_configs, batch.n_atoms
+        res = {}
+        if energy:
+            res["energy"] = torch.empty(K, dtype=torch.float64, device=dev)
+        if forces:
+            res["forces"] = torch.empty((N, 3), dtype=torch.float64, device=dev)
+        if virial:
+            res["virial"] = torch.empty((K, 3, 3), dtype=torch.float64, device=dev)
+        if site:
+            res["site"] = torch.empty(N, dtype=torch.float64, device=dev)
+        if b:
+            res["b"] = torch.empty((K, self.m), dtype=torch.float64, device=dev)
+        return res
+
+    def eval_async(self, batch: Batch, out: dict, precision="fp32", stream=None):
+        """mtp_eval_async into preallocated outputs: no host synchronisation or
+        allocation, so it can be captured in a HIP graph (torch.cuda.graph).
+        Check self.status() afterwards."""
+        o = _lib.mtp_out(*[out[k].data_ptr() if k in out else None
+                           for k in ("energy", "forces", "virial", "site", "b")])
+        bs = batch.c_struct()
+        check(lib().mtp_eval_async(self._h, ctypes.byref(bs), ctypes.byref(o), _lib.PRECISIONS[precision],
+                                   _stream(stream)), "mtp_eval_async")
+        return out
+
     def set_timing(self, enable=True):
         check(lib().mtp_set_timing(self._h, 1 if enable else 0), "mtp_set_timing")
 
