@@ -171,6 +171,36 @@ int mtp_loss_grad(mtp_model* model, const mtp_batch* batch, const double* E_t, c
                   double* loss_dev, double* grad_dev, void* stream);
 
 /*
+ * Normal equations of section 2.2, eq. Fitting, in xi at the model's current
+ * radial coefficients c.  E, forces and the virial are linear in xi, so the
+ * loss of mtp_loss_grad (same targets, weights and scaling) equals
+ *   L(xi) = xi^T H xi - 2 g^T xi + yy,
+ * H = J^T W J [m][m], g = J^T W y [m], yy = y^T W y, where J holds the
+ * energies, forces and virials of every basis function alone (xi = e_alpha)
+ * and W the per-row weights of the scaling.  Outputs (device, FP64, file
+ * basis order): H_dev row-major [m][m] (exactly symmetric), g_dev [m] or
+ * NULL, yy_dev [1] or NULL; with accumulate = 1 the values are added to what
+ * the buffers hold (summing over batches of a training set larger than one
+ * batch), with 0 they are overwritten.  J is evaluated in `precision`
+ * (MTP_FP64 or MTP_FP32) and held in the model's workspace:
+ * 8 (m + 1)(10 n_configs + 3 n_atoms) bytes.  Synchronises `stream` once.
+ */
+int mtp_normal_equations(mtp_model* model, const mtp_batch* batch, const double* E_t, const double* F_t,
+                         const double* W_t, double w_e, double w_f, double w_s, int scaling, int precision,
+                         int accumulate, double* H_dev, double* g_dev, double* yy_dev, void* stream);
+
+/*
+ * Minimiser xi_dev [m] (device, FP64, file order) of xi^T H xi - 2 g^T xi for
+ * H, g of mtp_normal_equations: H is scaled to unit diagonal and inverted by
+ * Gauss-Jordan elimination with partial pivoting in FP64.  Returns MTP_E_ARG
+ * (xi_dev untouched in meaning) when the scaled H is numerically singular,
+ * e.g. when a basis function vanishes on every configuration of the set.
+ * Does not change the model's xi (see mtp_set_params).  Synchronises
+ * `stream`.
+ */
+int mtp_solve_normal(mtp_model* model, const double* H_dev, const double* g_dev, double* xi_dev, void* stream);
+
+/*
  * Device-side counters of the last mtp_eval on this model: pairs closer than
  * R_min (the radial polynomial is then evaluated outside [R_min, R_cut]) and
  * neighbour-list inconsistencies (always 0 unless memory was corrupted).

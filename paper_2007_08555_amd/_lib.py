@@ -61,6 +61,10 @@ _SIGNATURES = {
     "mtp_status": (ctypes.c_int, [_P, _P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]),
     "mtp_loss_grad": (ctypes.c_int, [_P, ctypes.POINTER(mtp_batch), _P, _P, _P, ctypes.c_double, ctypes.c_double,
                                      ctypes.c_double, ctypes.c_int, ctypes.c_int, _P, _P, _P]),
+    "mtp_normal_equations": (ctypes.c_int, [_P, ctypes.POINTER(mtp_batch), _P, _P, _P, ctypes.c_double,
+                                            ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_int,
+                                            ctypes.c_int, _P, _P, _P, _P]),
+    "mtp_solve_normal": (ctypes.c_int, [_P, _P, _P, _P, _P]),
     "mtp_set_timing": (ctypes.c_int, [_P, ctypes.c_int]),
     "mtp_get_stats": (ctypes.c_int, [_P, ctypes.POINTER(mtp_stats)]),
     "mtp_free": (None, [_P]),

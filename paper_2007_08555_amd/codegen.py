@@ -721,12 +721,12 @@ hipError_t launch_loss(int precision, const void* a, const void* l, hipStream_t 
 }}
 
 template <typename T, bool COMP, bool WANT_B>
-hipError_t launch_t(const void* a, hipStream_t s) {{
+hipError_t launch_t(const void* a, bool reuse_moments, hipStream_t s) {{
   const auto& args = *static_cast<const mtp::EvalArgs<T>*>(a);
   if (args.n_atoms <= 0) return hipSuccess;
   const dim3 grid((args.n_atoms + BLOCK - 1) / BLOCK);
   const size_t smem = (size_t)args.n_c * sizeof(T);
-  hipLaunchKernelGGL((moments_kernel<T, COMP>), grid, dim3(BLOCK), smem, s, args);
+  if (!reuse_moments) hipLaunchKernelGGL((moments_kernel<T, COMP>), grid, dim3(BLOCK), smem, s, args);
   hipLaunchKernelGGL((contract_kernel<T, WANT_B>), grid, dim3(BLOCK), 0, s, args);
   if constexpr (sizeof(T) == 8) {{
 {launch_f64}
@@ -736,11 +736,13 @@ hipError_t launch_t(const void* a, hipStream_t s) {{
   return hipGetLastError();
 }}
 
-hipError_t launch(int precision, bool want_b, const void* a, hipStream_t s) {{
+hipError_t launch(int precision, unsigned flags, const void* a, hipStream_t s) {{
+  const bool want_b = (flags & mtp::kEvalWantB) != 0;
+  const bool reuse = (flags & mtp::kEvalReuseMoments) != 0;
   switch (precision) {{
-    case 0: return want_b ? launch_t<double, false, true>(a, s) : launch_t<double, false, false>(a, s);
-    case 1: return want_b ? launch_t<float, false, true>(a, s) : launch_t<float, false, false>(a, s);
-    case 2: return want_b ? launch_t<float, true, true>(a, s) : launch_t<float, true, false>(a, s);
+    case 0: return want_b ? launch_t<double, false, true>(a, reuse, s) : launch_t<double, false, false>(a, reuse, s);
+    case 1: return want_b ? launch_t<float, false, true>(a, reuse, s) : launch_t<float, false, false>(a, reuse, s);
+    case 2: return want_b ? launch_t<float, true, true>(a, reuse, s) : launch_t<float, true, false>(a, reuse, s);
   }}
   return hipErrorInvalidValue;
 }}

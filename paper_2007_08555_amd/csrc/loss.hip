@@ -17,17 +17,6 @@ namespace {
 
 constexpr int kBlock = 256;
 
-__device__ inline void weights(int scaling, double n, double we, double wf, double ws, double& a, double& b,
-                               double& c) {
-  if (scaling == 1) {         // structures
-    a = we / (n * n); b = wf / n; c = ws / (n * n);
-  } else if (scaling == 2) {  // vibrations
-    a = we / n; b = wf; c = ws / n;
-  } else {                    // molecules: eq. Fitting as written
-    a = we; b = wf; c = ws;
-  }
-}
-
 __global__ void residual_config_kernel(LossResidualArgs r) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= r.n_cfg) return;

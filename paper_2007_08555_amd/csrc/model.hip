@@ -106,6 +106,8 @@ struct mtp_model {
   // loss gradient
   Buffer lo_E, lo_F, lo_W, lo_a, lo_u, lo_eps, lo_dM, lo_dG, lo_xit, lo_pa, lo_pb, lo_cpart;
   Buffer lo_acfg, lo_wfcfg, lo_epscfg, lo_losscfg, lo_lossatom;
+  // normal equations
+  Buffer fit_J, fit_w, fit_P, fit_eye, fit_D, fit_W2, fit_inv, fit_flag;
   // statistics of the last evaluation
   int64_t last_atoms = 0, last_pairs = 0;
   int32_t last_max_nb = 0;
@@ -405,10 +407,10 @@ int run_eval(mtp_model* M, const mtp_batch* bt, const mtp_out* out, int precisio
     if (N > 0) {
       if (fp64) {
         auto ea = make_args<double>(M, N, stride, bt->species, want_b);
-        HIP_TRY(M->var->launch_eval(precision, want_b, &ea, s), "evaluation kernels");
+        HIP_TRY(M->var->launch_eval(precision, want_b ? kEvalWantB : 0u, &ea, s), "evaluation kernels");
       } else {
         auto ea = make_args<float>(M, N, stride, bt->species, want_b);
-        HIP_TRY(M->var->launch_eval(precision, want_b, &ea, s), "evaluation kernels");
+        HIP_TRY(M->var->launch_eval(precision, want_b ? kEvalWantB : 0u, &ea, s), "evaluation kernels");
       }
     }
     HIP_TRY(mark(2), "hipEventRecord");
@@ -674,6 +676,89 @@ int mtp_loss_grad(mtp_model* M, const mtp_batch* bt, const double* E_t, const do
   HIP_TRY(mtp::loss_finish(fp64, K_cfg, N, stride, M->m, M->n_c, n_blocks, r.loss_cfg, r.loss_atom, M->lo_xit.p,
                            M->perm_dev.as<int32_t>(), M->lo_cpart.as<double>(), loss_dev, grad_dev, s),
           "loss reductions");
+  return MTP_OK;
+}
+
+int mtp_normal_equations(mtp_model* M, const mtp_batch* bt, const double* E_t, const double* F_t,
+                         const double* W_t, double w_e, double w_f, double w_s, int scaling, int precision,
+                         int accumulate, double* H_dev, double* g_dev, double* yy_dev, void* stream) {
+  g_err.clear();
+  if (!M || !bt || !E_t || !F_t || !W_t || !H_dev) return fail(MTP_E_ARG, "mtp_normal_equations: null argument");
+  if (scaling < MTP_SCALE_MOLECULES || scaling > MTP_SCALE_VIBRATIONS)
+    return fail(MTP_E_ARG, "mtp_normal_equations: bad scaling");
+  if (precision != MTP_FP64 && precision != MTP_FP32)
+    return fail(MTP_E_ARG, "mtp_normal_equations: precision must be FP64 or FP32");
+  if (!(w_e >= 0 && w_f >= 0 && w_s >= 0)) return fail(MTP_E_ARG, "mtp_normal_equations: weights must be non-negative");
+  const int K_cfg = bt->n_configs;
+  const int64_t N = bt->n_atoms;
+  if (K_cfg <= 0) return fail(MTP_E_ARG, "mtp_normal_equations: empty batch");
+  HIP_TRY(hipSetDevice(M->device), "hipSetDevice");
+  hipStream_t s = (hipStream_t)stream;
+  // neighbour lists and moments at the current c (nothing written out)
+  mtp_out none{};
+  int rc = run_eval(M, bt, &none, precision, s);
+  if (rc != MTP_OK) return rc;
+  const bool fp64 = precision == MTP_FP64;
+  const size_t tsz = fp64 ? sizeof(double) : sizeof(float);
+  const int m = M->m, n = m + 1;
+  const int64_t R = (int64_t)K_cfg + 3 * N + 9 * (int64_t)K_cfg;
+  const int stride = M->last_stride;
+  HIP_TRY(M->fit_J.ensure(sizeof(double) * (size_t)n * R), "hipMalloc");
+  HIP_TRY(M->fit_w.ensure(sizeof(double) * (size_t)R), "hipMalloc");
+  HIP_TRY(M->fit_eye.ensure(tsz * (size_t)m * m), "hipMalloc");
+  const int splits = mtp::gram_splits(n, R);
+  HIP_TRY(M->fit_P.ensure(sizeof(double) * (size_t)splits * n * n), "hipMalloc");
+  HIP_TRY(mtp::fill_eye(fp64, m, M->fit_eye.p, s), "identity");
+  double* J = M->fit_J.as<double>();
+  // column alpha: energies, forces and virials of the potential xi = e_alpha
+  for (int al = 0; al < m; ++al) {
+    double* col = J + (size_t)al * R;
+    const size_t row = (size_t)M->perm[al] * m;  // e_alpha in the kernel's basis order
+    if (N > 0) {
+      if (fp64) {
+        auto ea = make_args<double>(M, N, stride, bt->species, false);
+        ea.xi = M->fit_eye.as<double>() + row;
+        HIP_TRY(M->var->launch_eval(precision, mtp::kEvalReuseMoments, &ea, s), "evaluation kernels");
+      } else {
+        auto ea = make_args<float>(M, N, stride, bt->species, false);
+        ea.xi = M->fit_eye.as<float>() + row;
+        HIP_TRY(M->var->launch_eval(precision, mtp::kEvalReuseMoments, &ea, s), "evaluation kernels");
+      }
+    }
+    HIP_TRY(mtp::gather_forces(fp64, N, stride, M->count.as<int32_t>(), M->rev.as<int32_t>(), M->gpair.p, M->pr.p,
+                               col + K_cfg, M->wv.p, s),
+            "force gather");
+    HIP_TRY(mtp::reduce_configs(fp64, K_cfg, M->cfg.as<mtp::CfgInfo>(), stride, M->site.p, M->wv.p, nullptr, m,
+                                stride, M->perm_dev.as<int32_t>(), col, col + K_cfg + 3 * N, nullptr, nullptr, s),
+            "reductions");
+  }
+  HIP_TRY(mtp::fit_rows(K_cfg, N, R, M->cfg.as<mtp::CfgInfo>(), M->atom_cfg.as<int32_t>(), w_e, w_f, w_s, scaling,
+                        E_t, F_t, W_t, M->fit_w.as<double>(), J + (size_t)m * R, s),
+          "row weights");
+  HIP_TRY(mtp::gram(n, R, J, M->fit_w.as<double>(), M->fit_P.as<double>(), splits, accumulate ? 1 : 0, H_dev, g_dev,
+                    yy_dev, s),
+          "Gram product");
+  return MTP_OK;
+}
+
+int mtp_solve_normal(mtp_model* M, const double* H_dev, const double* g_dev, double* xi_dev, void* stream) {
+  g_err.clear();
+  if (!M || !H_dev || !g_dev || !xi_dev) return fail(MTP_E_ARG, "mtp_solve_normal: null argument");
+  HIP_TRY(hipSetDevice(M->device), "hipSetDevice");
+  hipStream_t s = (hipStream_t)stream;
+  const int m = M->m;
+  HIP_TRY(M->fit_D.ensure(sizeof(double) * m), "hipMalloc");
+  HIP_TRY(M->fit_W2.ensure(sizeof(double) * 2 * (size_t)m * m), "hipMalloc");
+  HIP_TRY(M->fit_inv.ensure(sizeof(double) * (size_t)m * m), "hipMalloc");
+  HIP_TRY(M->fit_flag.ensure(sizeof(int)), "hipMalloc");
+  HIP_TRY(mtp::solve_prepare(m, H_dev, M->fit_D.as<double>(), M->fit_W2.as<double>(), s), "scaling");
+  HIP_TRY(mtp::gauss_jordan_inverse(m, M->fit_W2.as<double>(), M->fit_inv.as<double>(), M->fit_flag.as<int>(), s),
+          "Gauss-Jordan");
+  HIP_TRY(mtp::solve_apply(m, M->fit_inv.as<double>(), M->fit_D.as<double>(), g_dev, xi_dev, s), "solve");
+  int singular = 0;
+  HIP_TRY(hipMemcpyAsync(&singular, M->fit_flag.p, sizeof(int), hipMemcpyDeviceToHost, s), "hipMemcpyAsync");
+  HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
+  if (singular) return fail(MTP_E_ARG, "mtp_solve_normal: H is numerically singular");
   return MTP_OK;
 }
 

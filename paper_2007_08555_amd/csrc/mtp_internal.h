@@ -78,6 +78,32 @@ hipError_t reduce_configs(int fp64, int n_cfg, const CfgInfo* cfg, int stride,
                           int b_stride, const int32_t* perm, double* energy, double* virial,
                           double* b, double* site_out, hipStream_t s);
 
+// Normal equations in xi (fit.hip).  Ja is column-major [m + 1][R]: columns
+// 0..m-1 the Jacobian, column m the targets.
+hipError_t fit_rows(int n_cfg, int64_t N, int64_t R, const CfgInfo* cfg, const int32_t* atom_cfg, double we,
+                    double wf, double ws, int scaling, const double* Et, const double* Ft, const double* Wt,
+                    double* w, double* y, hipStream_t s);
+int gram_splits(int n, int64_t R);
+hipError_t gram(int n, int64_t R, const double* Ja, const double* w, double* P, int splits, int accumulate,
+                double* H, double* g, double* yy, hipStream_t s);
+hipError_t fill_eye(int fp64, int m, void* eye, hipStream_t s);
+hipError_t solve_prepare(int m, const double* H, double* D, double* W2, hipStream_t s);
+hipError_t solve_apply(int m, const double* inv, const double* D, const double* g, double* xi, hipStream_t s);
+
+// Weights (a, b, c) of energy, force and stress terms of one configuration
+// of n atoms under a weighting of eq. Fitting: 0 molecules (as written),
+// 1 structures (eq. train-structures), 2 vibrations (eq. train-vibrations).
+__device__ inline void weights(int scaling, double n, double we, double wf, double ws, double& a, double& b,
+                               double& c) {
+  if (scaling == 1) {
+    a = we / (n * n); b = wf / n; c = ws / (n * n);
+  } else if (scaling == 2) {
+    a = we / n; b = wf; c = ws / n;
+  } else {
+    a = we; b = wf; c = ws;
+  }
+}
+
 // Residuals of the training loss (per configuration and per atom).
 struct LossResidualArgs {
   int n_cfg;

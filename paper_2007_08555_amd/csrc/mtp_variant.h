@@ -5,6 +5,10 @@
 
 namespace mtp {
 
+// Flags of launch_eval: also write every B_alpha; keep the moments already in
+// args.M (same pairs and radial coefficients) instead of recomputing them.
+enum : unsigned { kEvalWantB = 1u, kEvalReuseMoments = 2u };
+
 struct BasisVariant {
   const char* name;
   int level;
@@ -23,7 +27,7 @@ struct BasisVariant {
   double flops_pair_bwd;         // per pair, adjoint
   double flops_atom;             // per atom, contraction forward + reverse
   // precision: 0 = FP64, 1 = FP32, 2 = FP32 with compensated moment sums
-  hipError_t (*launch_eval)(int precision, bool want_b, const void* args, hipStream_t stream);
+  hipError_t (*launch_eval)(int precision, unsigned flags, const void* args, hipStream_t stream);
   // loss-gradient kernels after an evaluation that left M and G in place
   hipError_t (*launch_loss)(int precision, const void* eval_args, const void* loss_args, hipStream_t stream);
   int block;                     // atoms per workgroup of the per-atom kernels

@@ -123,6 +123,42 @@ class Potential:
                                   _ptr(grad), _stream(stream)), "mtp_loss_grad")
         return loss, grad
 
+    def normal_equations(self, batch: Batch, E_t, F_t, W_t, w_e=1.0, w_f=0.01, w_s=0.001, scaling="vibrations",
+                         precision="fp64", out=None, stream=None):
+        """H = J^T W J, g = J^T W y, yy = y^T W y of the loss in xi at the
+        current c (mtp_normal_equations).  With out=(H, g, yy) from an earlier
+        call the batch's terms are added to them (a training set in several
+        batches)."""
+        dev = self.device
+        t = lambda a: torch.as_tensor(a, dtype=torch.float64).to(dev).contiguous()
+        E_t, F_t, W_t = t(E_t), t(F_t), t(W_t)
+        acc = out is not None
+        if out is None:
+            out = (torch.empty((self.m, self.m), dtype=torch.float64, device=dev),
+                   torch.empty(self.m, dtype=torch.float64, device=dev),
+                   torch.empty(1, dtype=torch.float64, device=dev))
+        H, g, yy = out
+        bs = batch.c_struct()
+        check(lib().mtp_normal_equations(self._h, ctypes.byref(bs), _ptr(E_t), _ptr(F_t), _ptr(W_t), float(w_e),
+                                         float(w_f), float(w_s), _lib.SCALINGS[scaling], _lib.PRECISIONS[precision],
+                                         int(acc), _ptr(H), _ptr(g), _ptr(yy), _stream(stream)),
+              "mtp_normal_equations")
+        return H, g, yy
+
+    def solve_normal(self, H, g, stream=None):
+        """xi minimising xi^T H xi - 2 g^T xi (mtp_solve_normal)."""
+        xi = torch.empty(self.m, dtype=torch.float64, device=self.device)
+        check(lib().mtp_solve_normal(self._h, _ptr(H), _ptr(g), _ptr(xi), _stream(stream)), "mtp_solve_normal")
+        return xi
+
+    def fit_xi(self, batch: Batch, E_t, F_t, W_t, precision="fp64", stream=None, **weights):
+        """Least-squares xi of eq. Fitting at fixed c, installed in the model;
+        returns it (device tensor, file basis order)."""
+        H, g, _ = self.normal_equations(batch, E_t, F_t, W_t, precision=precision, stream=stream, **weights)
+        xi = self.solve_normal(H, g, stream=stream)
+        self.set_params(xi=xi.cpu().numpy())
+        return xi
+
     def outputs(self, batch: Batch, forces=True, virial=True, site=False, b=False, energy=True):
         """Preallocated output tensors for eval_async (dict as returned by eval)."""
         dev = self.device

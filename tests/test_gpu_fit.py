@@ -1,0 +1,157 @@
+"""GPU parity of the normal equations in xi at fixed c (paper, section 2.2,
+eq. Fitting) against the FP64 oracle: H = J^T W J, g = J^T W y, yy, the
+solve, accumulation over batches, and the degenerate cases.
+
+Tolerances: J agrees with the oracle's to about 1e-14 of each column's scale
+in FP64 (the evaluation parity), so an entry of H or g differs by at most a
+few 1e-14 of sqrt(H_aa H_bb) (resp. sqrt(H_aa yy)) plus the rounding of the
+sums over rows (relative 1e-16 * sqrt(R)); 1e-11 leaves a wide margin.  In
+FP32, J carries about 1e-6 relative error (the FP32 evaluation parity), so
+1e-4.  xi is compared in the scaled variables z = xi / D (D = diag(H)^-1/2),
+where the solve amplifies the error of H by at most cond(D H D)."""
+import numpy as np
+import pytest
+
+import synth
+from gpu_common import log, pot_path
+from oracle import fit as of
+from oracle import mtp as omtp
+from oracle.potential import read_potential
+
+pytestmark = pytest.mark.gpu
+
+
+def predictions(pot, batch):
+    E, F, W = [], [], []
+    for k in range(len(batch["n_atoms"])):
+        r = omtp.evaluate(pot, *synth.config_of(batch, k))
+        E.append(r["energy"])
+        F.append(r["forces"])
+        W.append(r["virial"])
+    return {"energy": np.array(E), "forces": np.concatenate(F), "virial": np.array(W)}
+
+
+def noisy(pred, seed, sigma=0.02):
+    rng = np.random.default_rng(seed)
+    return {k: v + rng.normal(0, sigma, np.shape(v)) for k, v in pred.items()}
+
+
+def scaled_errors(H, g, yy, Ho, go, yyo):
+    dd = np.sqrt(np.outer(np.diag(Ho), np.diag(Ho)))
+    eH = float(np.max(np.abs(H - Ho) / dd))
+    eg = float(np.max(np.abs(g - go) / np.sqrt(np.diag(Ho) * yyo)))
+    ey = abs(yy - yyo) / yyo
+    return eH, eg, ey
+
+
+def gpu_system(P, batch, tg, precision="fp64", **w):
+    from paper_2007_08555_amd import Batch
+    H, g, yy = P.normal_equations(Batch.from_arrays(batch), tg["energy"], tg["forces"], tg["virial"],
+                                  precision=precision, **w)
+    return H, g, yy
+
+
+@pytest.mark.parametrize("name,scaling,n_cfg", [("lev8_s1", "vibrations", 12), ("lev12_s2", "structures", 6),
+                                                ("lev12_s2", "molecules", 6), ("lev16_s3", "vibrations", 3)])
+def test_normal_equations_match_oracle(name, scaling, n_cfg):
+    from paper_2007_08555_amd import Potential
+    pot = read_potential(pot_path(name))
+    batch = synth.mixed_batch(seed=31, n_configs=n_cfg, n_min=6, n_max=20, n_species_model=pot["n_species"])
+    assert batch["pbc"].any() and not batch["pbc"].all()
+    tg = noisy(predictions(pot, batch), 7)
+    w = dict(w_e=1.0, w_f=0.01, w_s=0.001, scaling=scaling)
+    P = Potential(pot_path(name))
+    H, g, yy = gpu_system(P, batch, tg, **w)
+    H, g, yy = H.cpu().numpy(), g.cpu().numpy(), float(yy.item())
+    Ho, go, yyo = of.normal_equations(pot, batch, tg, **w)
+    eH, eg, ey = scaled_errors(H, g, yy, Ho, go, yyo)
+    log(f"[fit {name} {scaling}] H {eH:.2e} g {eg:.2e} yy {ey:.2e}")
+    assert np.array_equal(H, H.T)
+    assert eH <= 1e-11 and eg <= 1e-11 and ey <= 1e-12
+    # the solve, against the oracle's solve of its own system
+    xi = P.solve_normal(*[torch_of(x) for x in (H, g)]).cpu().numpy()
+    xo = of.solve(Ho, go)
+    d = 1 / np.sqrt(np.diag(Ho))
+    cond = np.linalg.cond(Ho * d[:, None] * d[None, :])
+    ez = np.max(np.abs((xi - xo) / d)) / np.max(np.abs(xo / d))
+    log(f"[fit {name} {scaling}] xi (scaled) {ez:.2e}, cond(DHD) {cond:.2e}")
+    assert ez <= max(1e-10, 1e-12 * cond)
+
+
+def torch_of(a):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda:0")
+
+
+@pytest.mark.parametrize("name", ["lev12_s2", "lev16_s3"])
+def test_noiseless_targets_recover_reference_xi(name):
+    # targets from a reference potential with the same c: fit_xi returns the
+    # reference xi (to cond * eps) and installs it
+    from paper_2007_08555_amd import Batch, Potential
+    pot = read_potential(pot_path(name))
+    ref = dict(pot, xi=pot["xi"] * (1 + 0.3 * np.random.default_rng(3).normal(size=pot["xi"].shape)))
+    batch = synth.mixed_batch(seed=32, n_configs=24, n_min=8, n_max=40, n_species_model=pot["n_species"])
+    tg = predictions(ref, batch)
+    P = Potential(pot_path(name))
+    B = Batch.from_arrays(batch)
+    H, g, _ = P.normal_equations(B, tg["energy"], tg["forces"], tg["virial"])
+    Hn = H.cpu().numpy()
+    d = 1 / np.sqrt(np.diag(Hn))
+    cond = np.linalg.cond(Hn * d[:, None] * d[None, :])
+    xi = P.fit_xi(B, tg["energy"], tg["forces"], tg["virial"]).cpu().numpy()
+    ez = np.max(np.abs((xi - ref["xi"]) / d)) / np.max(np.abs(ref["xi"] / d))
+    log(f"[fit recover {name}] scaled xi error {ez:.2e}, cond(DHD) {cond:.2e}")
+    assert ez <= max(1e-10, 1e-12 * cond)
+    assert np.array_equal(P.get_params()[1], xi)
+
+
+def test_accumulation_over_batches():
+    from paper_2007_08555_amd import Batch, Potential
+    pot = read_potential(pot_path("lev12_s2"))
+    batch = synth.mixed_batch(seed=33, n_configs=10, n_min=6, n_max=30, n_species_model=2)
+    tg = noisy(predictions(pot, batch), 8)
+    P = Potential(pot_path("lev12_s2"))
+    w = dict(w_e=1.0, w_f=0.01, w_s=0.001, scaling="vibrations")
+    Hf, gf, yyf = [x.cpu().numpy() for x in gpu_system(P, batch, tg, **w)]
+    offs = batch["atom_offsets"]
+    parts = [[0, 1, 2, 3], [4, 5, 6, 7, 8, 9]]
+    out = None
+    for idx in parts:
+        sb = synth.subset(batch, idx)
+        a = np.concatenate([np.arange(offs[k], offs[k + 1]) for k in idx])
+        t = {"energy": tg["energy"][idx], "forces": tg["forces"][a], "virial": tg["virial"][idx]}
+        out = P.normal_equations(Batch.from_arrays(sb), t["energy"], t["forces"], t["virial"], out=out, **w)
+    H, g, yy = out[0].cpu().numpy(), out[1].cpu().numpy(), float(out[2].item())
+    eH, eg, ey = scaled_errors(H, g, yy, Hf, gf, float(yyf[0]))
+    log(f"[fit accumulate] H {eH:.2e} g {eg:.2e} yy {ey:.2e}")
+    assert eH <= 1e-13 and eg <= 1e-13 and ey <= 1e-13
+
+
+def test_fp32_jacobian():
+    from paper_2007_08555_amd import Potential
+    pot = read_potential(pot_path("lev12_s2"))
+    batch = synth.mixed_batch(seed=34, n_configs=6, n_min=6, n_max=20, n_species_model=2)
+    tg = noisy(predictions(pot, batch), 9)
+    P = Potential(pot_path("lev12_s2"))
+    H, g, yy = [x.cpu().numpy() for x in gpu_system(P, batch, tg, precision="fp32")]
+    H64, g64, yy64 = [x.cpu().numpy() for x in gpu_system(P, batch, tg, precision="fp64")]
+    eH, eg, ey = scaled_errors(H, g, float(yy[0]), H64, g64, float(yy64[0]))
+    log(f"[fit fp32] H {eH:.2e} g {eg:.2e} yy {ey:.2e}")
+    assert eH <= 1e-4 and eg <= 1e-4 and ey <= 1e-12   # yy does not depend on J
+
+
+def test_singular_system_and_empty_batch():
+    from paper_2007_08555_amd import Batch, Potential
+    from paper_2007_08555_amd._lib import MTPError
+    # one free dimer: every force row is +-g along one axis, so rank J <= 3 < m
+    dimer = synth._batch([(np.array([[0.0, 0.0, 0.0], [2.6, 0.0, 0.0]]), np.array([0, 0]), np.eye(3) * 20.0, False)])
+    P = Potential(pot_path("lev8_s1"))
+    B = Batch.from_arrays(dimer)
+    H, g, _ = P.normal_equations(B, np.zeros(1), np.zeros((2, 3)), np.zeros((1, 3, 3)))
+    with pytest.raises(MTPError):
+        P.solve_normal(H, g)
+    empty = {"n_atoms": np.zeros(0, np.int64), "atom_offsets": np.zeros(1, np.int64),
+             "pos": np.zeros((0, 3)), "species": np.zeros(0, np.int32), "cell": np.zeros((0, 3, 3)),
+             "pbc": np.zeros(0, np.uint8)}
+    with pytest.raises(MTPError):
+        P.normal_equations(Batch.from_arrays(empty), np.zeros(0), np.zeros((0, 3)), np.zeros((0, 3, 3)))
