@@ -3,8 +3,10 @@
 
 One step is one pass of the whole evaluation path over one batch resident in
 HBM: neighbour lists, radial functions, moments, contractions, adjoint,
-force gather, per-configuration energy / virial sums.  The step is captured
-once in a HIP graph (mtp_eval_async) and replayed; eager calls are timed too.
+force gather, per-configuration energy / virial / basis sums, and the
+extrapolation grade gamma of every configuration against a fixed FP64 active
+set (c = b A^-1, gamma = max |c|).  The step is captured once in a HIP graph
+(mtp_eval_async + mtp_grade_from_b) and replayed; eager calls are timed too.
 
 Workload (default): 4096 configurations of 8..256 atoms (about 530 k atoms),
 random fcc/bcc/hcp periodic cells with vacancies and free fragments,
@@ -70,6 +72,10 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-extras", action="store_true", help="skip plain path, bcc box and CPU baseline")
     ap.add_argument("--no-graph", action="store_true", help="time eager calls instead of HIP-graph replays")
+    ap.add_argument("--batch-cache", default="",
+                    help="npz file holding the generated batch (written if missing, read if present)")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="run one plain device copy of this size first (reference for HBM counters)")
     a = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if a.gpus != 1 or world != 1:
@@ -86,15 +92,32 @@ def main():
 
     pot_path = os.path.join(ROOT, "tests", "golden", "potentials", "lev16_s3.mtp")
     t0 = time.time()
-    batch = synth.mixed_batch(seed=0, n_configs=a.configs, n_min=8, n_max=256, n_species_model=3)
+    if a.batch_cache and os.path.exists(a.batch_cache):
+        with np.load(a.batch_cache) as z:
+            batch = {k: z[k] for k in z.files}
+        assert len(batch["n_atoms"]) == a.configs, "batch cache holds another batch size"
+    else:
+        batch = synth.mixed_batch(seed=0, n_configs=a.configs, n_min=8, n_max=256, n_species_model=3)
+        if a.batch_cache:
+            np.savez(a.batch_cache, **batch)
     n_atoms = int(batch["n_atoms"].sum())
     log(f"generated {a.configs} configurations, {n_atoms} atoms in {time.time() - t0:.1f} s")
     P = Potential(pot_path, device=0)
     B = Batch.from_arrays(batch, "cuda:0")
+    P.set_active_set(np.load(os.path.join(ROOT, "tests", "golden", "active_lev16_s3.npz"))["A"])
     stream = torch.cuda.current_stream()
+    if a.calib_copy_mib > 0:
+        src = torch.ones(a.calib_copy_mib << 18, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"calibration copy: {a.calib_copy_mib} MiB read, {a.calib_copy_mib} MiB written")
+        del src, dst
 
     def step():
-        return P.eval(B, precision=a.precision, forces=True, virial=True, energy=True, stream=stream)
+        out = P.eval(B, precision=a.precision, forces=True, virial=True, energy=True, b=True, stream=stream)
+        out["gamma"], out["argmax"] = P.grade_from_b(out["b"], stream=stream)
+        return out
 
     for _ in range(max(1, a.warmup)):
         step()
@@ -108,16 +131,18 @@ def main():
     dt = dt_eager
     if not a.no_graph:
         # the same step captured once in a HIP graph and replayed
-        out = P.outputs(B)
+        out = P.outputs(B, b=True)
         side = torch.cuda.Stream()
         side.wait_stream(torch.cuda.current_stream())
         with torch.cuda.stream(side):
             P.eval_async(B, out, precision=a.precision, stream=side)
+            P.grade_from_b(out["b"], want_c=True, stream=side)
         torch.cuda.current_stream().wait_stream(side)
         torch.cuda.synchronize()
         graph = torch.cuda.CUDAGraph()
         with torch.cuda.graph(graph):
             P.eval_async(B, out, precision=a.precision)
+            gamma, argmax, _ = P.grade_from_b(out["b"], want_c=True)
         for _ in range(a.warmup):
             graph.replay()
         torch.cuda.synchronize()
@@ -127,7 +152,11 @@ def main():
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / a.steps
         P.status()   # raises if a replay met a capacity or input problem
-        log(f"batched, graph replay: {dt * 1e3:.3f} ms/step")
+        ref = step()
+        torch.cuda.synchronize()
+        if not (torch.equal(ref["energy"], out["energy"]) and torch.equal(ref["gamma"], gamma)):
+            raise RuntimeError("graph replay differs from the eager step")
+        log(f"batched, graph replay: {dt * 1e3:.3f} ms/step (gamma max {gamma.max().item():.3g})")
     value = n_atoms / dt
     log(f"batched: {dt * 1e3:.3f} ms/step, {value:.4g} atom-evals/s")
 
@@ -154,7 +183,8 @@ def main():
             "warmup": a.warmup, "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak",
             "vs_baseline": None, "dtype": DTYPE[a.precision], "data": "synthetic",
             "config": {"workload": f"batched: {a.configs} mixed fcc/bcc/hcp cells and fragments, 8-256 atoms, "
-                                   f"{n_atoms} atoms, 1-3 of 3 species, MTP level 16, N_Q 8, R_cut 5 A",
+                                   f"{n_atoms} atoms, 1-3 of 3 species, MTP level 16, N_Q 8, R_cut 5 A; "
+                                   f"E, F, stress and the extrapolation grade per configuration",
                        "precision": a.precision, "level": 16, "atoms": n_atoms, "configs": a.configs,
                        "graph_replay": not a.no_graph},
             "roofline": roofline, "eager_ms_per_step": dt_eager * 1e3}

@@ -121,16 +121,20 @@ def _mono_steps(s):
     return steps, mono
 
 
-def emit_pair_forward(s, comp_mode):
+def emit_pair_forward(s, comp_mode, nus=None, kmap=None):
     """Monomials of the pair vector, degree by degree, each followed by the
-    moment components that use it (only two degrees are live at once)."""
+    moment components that use it (only two degrees are live at once).
+    Restricted to the degrees in nus (all when None); kmap maps a component
+    index to its register slot in M."""
     out = []
     ops = 0
     steps, mono = _mono_steps(s)
     by_nu = defaultdict(list)
     for (mu, nu, abc), k in s.comp.items():
-        by_nu[nu].append((mu, abc, k))
-    for nu in range(0, s.nu_max + 1):
+        if nus is None or nu in nus:
+            by_nu[nu].append((mu, abc, k if kmap is None else kmap[k]))
+    top = s.nu_max if nus is None else max(nus)
+    for nu in range(0, top + 1):
         for line, counted in steps.get(nu, []):
             out.append(line)
             ops += 1 if counted else 0
@@ -142,6 +146,63 @@ def emit_pair_forward(s, comp_mode):
                 out.append(f"M[{k}] += {term};")
             ops += 2 if nu else 1
     return out, ops
+
+
+MOMENTS_TEMPLATE = r"""
+// Moments pass {pidx}: the components of degrees {nus} of one atom, summed
+// over its pairs and written to args.M.
+template <typename T, bool COMP>
+__global__ void __launch_bounds__(BLOCK) moments_{tag}_kernel(const mtp::EvalArgs<T> args) {{
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* cs = reinterpret_cast<T*>(smem_raw);
+  for (int t = threadIdx.x; t < args.n_c; t += blockDim.x) cs[t] = args.c[t];
+  __syncthreads();
+  const int i = blockIdx.x * BLOCK + threadIdx.x;
+  if (i >= args.n_atoms) return;
+  const int S = args.n_species;
+  const int nq = args.nq;
+  const int mu_stride = S * S * nq;
+  const int zi = clamp_species(args.species[i], S);
+  const int cnt = args.nbr_count[i];
+  const T rmin = args.rmin, rcut = args.rcut;
+  constexpr int CP = {ncomp};
+  constexpr int NMP = {nmu};
+  constexpr int kIdx[CP] = {{ {comp_list} }};
+  T M[CP];
+  T Mlo[COMP ? CP : 1];
+#pragma unroll
+  for (int k = 0; k < CP; ++k) M[k] = T(0);
+#pragma unroll
+  for (int k = 0; k < (COMP ? CP : 1); ++k) Mlo[k] = T(0);
+  // pair p + 1 is loaded while pair p is processed
+  T xn = T(0), yn = T(0), zn = T(0);
+  int zjn = 0;
+  if (cnt > 0) {{
+    const mtp::PairRec<T> q = args.pr[i];
+    xn = q.x; yn = q.y; zn = q.z; zjn = q.zj;
+  }}
+#pragma unroll 1
+  for (int p = 0; p < cnt; ++p) {{
+    const T x = xn, y = yn, z = zn;
+    const int zj = zjn;
+    if (p + 1 < cnt) {{
+      const size_t en = (size_t)(p + 1) * args.stride + i;
+      const mtp::PairRec<T> q = args.pr[en];
+      xn = q.x; yn = q.y; zn = q.z; zjn = q.zj;
+    }}
+    const T r = sqrt(x * x + y * y + z * z);
+    T f[NMP], df[NMP];
+    mtp::radial<T, NMP, false>(cs, (zi * S + zj) * nq, mu_stride, nq, r, rmin, rcut, f, df);
+{body}
+  }}
+  if constexpr (COMP) {{
+#pragma unroll
+    for (int k = 0; k < CP; ++k) M[k] += Mlo[k];
+  }}
+#pragma unroll
+  for (int k = 0; k < CP; ++k) args.M[(size_t)kIdx[k] * args.stride + i] = M[k];
+}}
+"""
 
 
 def emit_contraction(s):
@@ -180,8 +241,9 @@ def emit_contraction(s):
     for g in range(len(s.terms)):
         out.append(f"const T dg{g} = " + (" + ".join(dg[g]) if dg[g] else "T(0)") + ";")
     # keep the products of the forward sweep from being reused (and held in
-    # registers) by the reverse sweep: M is opaque to the optimiser from here
-    out.append("mtp::opaque(M);")
+    # registers) by the reverse sweep: M is reloaded (or made opaque to the
+    # optimiser) here, so that it is dead while B, V and dV/dg are formed
+    out.append("MTP_RELOAD_M();")
     # reverse of the graph terms, gathered per component so that each
     # G[k] is complete when written and nothing but M stays live
     contrib = defaultdict(lambda: defaultdict(list))
@@ -209,12 +271,13 @@ def emit_contraction(s):
             parts.append(f"dg{g} * (" + " + ".join(inner) + ")")
             ops += 1
         out.append(f"MTP_OUT_G({k}, " + " + ".join(parts) + ");")
-        if k % 2 == 1:
-            out.append("mtp::opaque(M);")
+        # one fence per component keeps each G[k]'s products from being
+        # interleaved with the next ones (FP64 then needs no scratch)
+        out.append("mtp::opaque(M);")
     return out, ops
 
 
-def emit_pair_backward(s, nus=None, gmap=None):
+def emit_pair_backward(s, nus=None, gmap=None, nmu=None):
     """g = dV/dr_ij for one pair from G, f, df and the monomials, restricted
     to the components of the degrees in nus (all when None); gmap maps a
     component index to its register slot in G.
@@ -225,8 +288,9 @@ def emit_pair_backward(s, nus=None, gmap=None):
     out = []
     ops = 0
     steps, mono = _mono_steps(s)
-    out.append("T D[NMU];")
-    out.append("#pragma unroll\nfor (int q = 0; q < NMU; ++q) D[q] = T(0);")
+    nm = "NMU" if nmu is None else str(nmu)
+    out.append(f"T D[{nm}];")
+    out.append(f"#pragma unroll\nfor (int q = 0; q < {nm}; ++q) D[q] = T(0);")
     out.append("T gx = T(0), gy = T(0), gz = T(0);")
     used = set(s.nus_used()) if nus is None else set(nus)
     gmap = gmap or {k: k for k in range(s.C)}
@@ -260,7 +324,7 @@ def emit_pair_backward(s, nus=None, gmap=None):
                     ops += 2 + (1 if e != 1 else 0)
             out.append("}")
     out.append("T rad = T(0);")
-    out.append("#pragma unroll\nfor (int q = 0; q < NMU; ++q) rad += df[q] * D[q];")
+    out.append(f"#pragma unroll\nfor (int q = 0; q < {nm}; ++q) rad += df[q] * D[q];")
     out.append("const T ri = rad * inv_r;")
     out.append("gx += ri * x; gy += ri * y; gz += ri * z;")
     ops += 2 * s.n_mu + 1 + 6
@@ -329,8 +393,8 @@ __global__ void __launch_bounds__(BLOCK) adjoint_{tag}_kernel(const mtp::EvalArg
     }}
     const T r = sqrt(x * x + y * y + z * z);
     const T inv_r = T(1) / r;
-    T f[NMU], df[NMU];
-    mtp::radial<T, NMU, true>(cs, (zi * S + zj) * nq, mu_stride, nq, r, rmin, rcut, f, df);
+    T f[{nmu}], df[{nmu}];
+    mtp::radial<T, {nmu}, true>(cs, (zi * S + zj) * nq, mu_stride, nq, r, rmin, rcut, f, df);
 {body}
     if (FIRST) {{
       args.g[3 * e] = gx;
@@ -609,62 +673,11 @@ constexpr int BLOCK = {block};
 
 __device__ __forceinline__ int clamp_species(int z, int S) {{ return z < 0 ? 0 : (z >= S ? S - 1 : z); }}
 
-// Moments of one atom over its pairs, written to args.M.
-template <typename T, bool COMP>
-__global__ void __launch_bounds__(BLOCK) moments_kernel(const mtp::EvalArgs<T> args) {{
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  T* cs = reinterpret_cast<T*>(smem_raw);
-  for (int t = threadIdx.x; t < args.n_c; t += blockDim.x) cs[t] = args.c[t];
-  __syncthreads();
-  const int i = blockIdx.x * BLOCK + threadIdx.x;
-  if (i >= args.n_atoms) return;
-  const T* __restrict__ xi = args.xi;
-  const int S = args.n_species;
-  const int nq = args.nq;
-  const int mu_stride = S * S * nq;
-  const int zi = clamp_species(args.species[i], S);
-  const int cnt = args.nbr_count[i];
-  const T rmin = args.rmin, rcut = args.rcut;
-
-  T M[C];
-  T Mlo[COMP ? C : 1];
-#pragma unroll
-  for (int k = 0; k < C; ++k) M[k] = T(0);
-#pragma unroll
-  for (int k = 0; k < (COMP ? C : 1); ++k) Mlo[k] = T(0);
-
-  // pair p + 1 is loaded while pair p is processed
-  T xn = T(0), yn = T(0), zn = T(0);
-  int zjn = 0;
-  if (cnt > 0) {{
-    const mtp::PairRec<T> q = args.pr[i];
-    xn = q.x; yn = q.y; zn = q.z; zjn = q.zj;
-  }}
-#pragma unroll 1
-  for (int p = 0; p < cnt; ++p) {{
-    const T x = xn, y = yn, z = zn;
-    const int zj = zjn;
-    if (p + 1 < cnt) {{
-      const size_t en = (size_t)(p + 1) * args.stride + i;
-      const mtp::PairRec<T> q = args.pr[en];
-      xn = q.x; yn = q.y; zn = q.z; zjn = q.zj;
-    }}
-    const T r = sqrt(x * x + y * y + z * z);
-    T f[NMU], df[NMU];
-    mtp::radial<T, NMU, false>(cs, (zi * S + zj) * nq, mu_stride, nq, r, rmin, rcut, f, df);
-{pair_fwd}
-  }}
-  if constexpr (COMP) {{
-#pragma unroll
-    for (int k = 0; k < C; ++k) M[k] += Mlo[k];
-  }}
-#pragma unroll
-  for (int k = 0; k < C; ++k) args.M[(size_t)k * args.stride + i] = M[k];
-}}
-
-// Contractions of one atom's moments: V, optional B, and G = dV/dM.
+{moments_kernels}
+// Forward contractions of one atom's moments: graph values, V, optional B,
+// and dV/dg of every connected graph g (to args.D).
 template <typename T, bool WANT_B>
-__global__ void __launch_bounds__(BLOCK) contract_kernel(const mtp::EvalArgs<T> args) {{
+__global__ void __launch_bounds__(BLOCK) contract_fwd_kernel(const mtp::EvalArgs<T> args) {{
   const int i = blockIdx.x * BLOCK + threadIdx.x;
   if (i >= args.n_atoms) return;
   const T* __restrict__ xi = args.xi;
@@ -672,11 +685,24 @@ __global__ void __launch_bounds__(BLOCK) contract_kernel(const mtp::EvalArgs<T> 
 #pragma unroll
   for (int k = 0; k < C; ++k) M[k] = args.M[(size_t)k * args.stride + i];
 #define MTP_OUT_B(a_, v_) do {{ if (WANT_B) args.B[(size_t)(a_) * args.b_stride + i] = (v_); }} while (0)
-#define MTP_OUT_G(k_, v_) args.G[(size_t)(k_) * args.stride + i] = (v_)
-{contraction}
+{contraction_fwd}
 #undef MTP_OUT_B
-#undef MTP_OUT_G
+{store_dg}
   args.site[i] = V;
+}}
+
+// Reverse sweep: G = dV/dM from M and dV/dg.
+template <typename T>
+__global__ void __launch_bounds__(BLOCK) contract_rev_kernel(const mtp::EvalArgs<T> args) {{
+  const int i = blockIdx.x * BLOCK + threadIdx.x;
+  if (i >= args.n_atoms) return;
+  T M[C];
+#pragma unroll
+  for (int k = 0; k < C; ++k) M[k] = args.M[(size_t)k * args.stride + i];
+{load_dg}
+#define MTP_OUT_G(k_, v_) args.G[(size_t)(k_) * args.stride + i] = (v_)
+{contraction_rev}
+#undef MTP_OUT_G
 }}
 
 // The same contraction code on dual numbers M + dM e: the tangents of G and of
@@ -695,7 +721,9 @@ __global__ void __launch_bounds__(BLOCK) tangent_contract_kernel(const mtp::Eval
   for (int k = 0; k < C; ++k) M[k] = T(args.M[(size_t)k * args.stride + i], la.dM[(size_t)k * args.stride + i]);
 #define MTP_OUT_B(a_, v_) la.xi_terms[(size_t)(a_) * args.stride + i] = aw * (v_).v + (v_).d
 #define MTP_OUT_G(k_, v_) la.dG[(size_t)(k_) * args.stride + i] = (v_).d
+#define MTP_RELOAD_M() mtp::opaque(M)
 {contraction}
+#undef MTP_RELOAD_M
 #undef MTP_OUT_B
 #undef MTP_OUT_G
   (void)V;
@@ -726,8 +754,15 @@ hipError_t launch_t(const void* a, bool reuse_moments, hipStream_t s) {{
   if (args.n_atoms <= 0) return hipSuccess;
   const dim3 grid((args.n_atoms + BLOCK - 1) / BLOCK);
   const size_t smem = (size_t)args.n_c * sizeof(T);
-  if (!reuse_moments) hipLaunchKernelGGL((moments_kernel<T, COMP>), grid, dim3(BLOCK), smem, s, args);
-  hipLaunchKernelGGL((contract_kernel<T, WANT_B>), grid, dim3(BLOCK), 0, s, args);
+  if (!reuse_moments) {{
+    if constexpr (sizeof(T) == 8) {{
+{launch_mom_f64}
+    }} else {{
+{launch_mom_f32}
+    }}
+  }}
+  hipLaunchKernelGGL((contract_fwd_kernel<T, WANT_B>), grid, dim3(BLOCK), 0, s, args);
+  hipLaunchKernelGGL((contract_rev_kernel<T>), grid, dim3(BLOCK), 0, s, args);
   if constexpr (sizeof(T) == 8) {{
 {launch_f64}
   }} else {{
@@ -767,25 +802,45 @@ extern const mtp::BasisVariant {ns}_variant = {{
 """
 
 
+ADJ_BUDGET_F64 = 90   # components per FP64 adjoint pass
+
+
 def generate(lev_max, block=64):
     s = Schedule(lev_max)
     ns = f"lev{lev_max}"
     fwd, ops_f = emit_pair_forward(s, comp_mode=True)
+    # moments passes: FP64 accumulators of all 130 components of level 16 do
+    # not fit the register file next to the pair's temporaries, so FP64 sums
+    # the degrees in two groups (each pass recomputes r and f_mu)
+    mom_src, mom_launch = [], {}
+    for prec, budget in (("f32", 10 ** 9), ("f64", 85)):
+        lines = []
+        for pidx, (nus, comps) in enumerate(adjoint_passes(s, budget)):
+            tag = f"{prec}_p{pidx}"
+            kmap = {k: j for j, k in enumerate(comps)}
+            body, _ = emit_pair_forward(s, comp_mode=True, nus=set(nus), kmap=kmap)
+            nmu = 1 + max(mu for (mu, nu, abc), k in s.comp.items() if nu in nus)
+            mom_src.append(MOMENTS_TEMPLATE.format(pidx=pidx, nus=nus, tag=tag, ncomp=len(comps), nmu=nmu,
+                                                   comp_list=", ".join(map(str, comps)),
+                                                   body="\n".join(" " * 4 + l for l in body)))
+            lines.append(f"      hipLaunchKernelGGL((moments_{tag}_kernel<T, COMP>), grid, dim3(BLOCK), smem, s, args);")
+        mom_launch[prec] = "\n".join(lines)
     con, ops_c = emit_contraction(s)
     bwd, ops_b = emit_pair_backward(s)
     loss_src, loss_launch = emit_loss_kernels(s, budget=45)
     adj_src, launches = [], {}
-    for prec, budget in (("f32", 10 ** 9), ("f64", 90)):
+    for prec, budget in (("f32", 10 ** 9), ("f64", ADJ_BUDGET_F64)):
         lines = []
         passes = adjoint_passes(s, budget)
         for pidx, (nus, comps) in enumerate(passes):
             tag = f"{prec}_p{pidx}"
             gmap = {k: j for j, k in enumerate(comps)}
-            body, _ = emit_pair_backward(s, nus=nus, gmap=gmap)
+            nmu = 1 + max(mu for (mu, nu, abc), k in s.comp.items() if nu in nus)
+            body, _ = emit_pair_backward(s, nus=nus, gmap=gmap, nmu=nmu)
             import re as _re
             used = {int(v) for line in body for v in _re.findall(r"G\[(\d+)\]", line)}
             assert used <= set(range(len(comps))), "adjoint pass reads a component outside its range"
-            adj_src.append(ADJOINT_TEMPLATE.format(pidx=pidx, nus=nus, tag=tag, ncomp=len(comps),
+            adj_src.append(ADJOINT_TEMPLATE.format(pidx=pidx, nus=nus, tag=tag, ncomp=len(comps), nmu=nmu,
                                                    comp_list=", ".join(map(str, comps)),
                                                    body="\n".join(" " * 4 + l for l in body)))
             lines.append(f"    hipLaunchKernelGGL((adjoint_{tag}_kernel<T, {'true' if pidx == 0 else 'false'}>), "
@@ -810,7 +865,12 @@ def generate(lev_max, block=64):
     src = KERNEL_TEMPLATE.format(
         level=lev_max, m=len(s.funcs), ngraphs=len(s.keys), C=s.C, n_mu=s.n_mu, nu_max=s.nu_max,
         block=block, ns=ns,
-        pair_fwd=ind(fwd, 4), contraction=ind(con, 2), adjoint_kernels="\n".join(adj_src),
+        moments_kernels="\n".join(mom_src), launch_mom_f64=mom_launch["f64"], launch_mom_f32=mom_launch["f32"],
+        contraction=ind(con, 2),
+        contraction_fwd=ind(con[:con.index("MTP_RELOAD_M();")], 2),
+        contraction_rev=ind(con[con.index("MTP_RELOAD_M();") + 1:], 2),
+        store_dg=ind([f"args.D[(size_t){g} * args.stride + i] = dg{g};" for g in range(len(s.terms))], 2),
+        load_dg=ind([f"const T dg{g} = args.D[(size_t){g} * args.stride + i];" for g in range(len(s.terms))], 2), adjoint_kernels="\n".join(adj_src),
         launch_f64=launches["f64"], launch_f32=launches["f32"],
         loss_kernels=loss_src, launch_loss=loss_launch, creduce=CREDUCE_TEMPLATE.format(),
         moments=", ".join(f"{mu}, {nu}" for mu, nu in s.moments),

@@ -99,7 +99,7 @@ struct mtp_model {
   Buffer ainv, gj_work, gj_flag;
   // workspace
   Buffer cfg, atom_cfg, atom_bin, bin_count, bin_start, bin_atoms, bin_fill, nbins_dev;
-  Buffer count, nbr_row, pr, rev, gpair, Mbuf, Gbuf, site, wv, B, status, run_start;
+  Buffer count, nbr_row, pr, rev, gpair, Mbuf, Gbuf, Dbuf, site, wv, B, status, run_start;
   int K = 64;  // neighbour capacity per atom, grown on overflow
   Buffer b_tmp, c_tmp;
   int last_stride = 0;
@@ -311,6 +311,7 @@ mtp::EvalArgs<T> make_args(mtp_model* M, int64_t n_atoms, int stride, const int3
   a.site = M->site.as<T>();
   a.M = M->Mbuf.as<T>();
   a.G = M->Gbuf.as<T>();
+  a.D = M->Dbuf.as<T>();
   a.g = M->gpair.as<T>();
   a.atom_virial = M->wv.as<T>();
   a.B = want_b ? M->B.as<T>() : nullptr;
@@ -368,6 +369,7 @@ int run_eval(mtp_model* M, const mtp_batch* bt, const mtp_out* out, int precisio
     NEED(M->gpair, tsz * 3 * slots);
     NEED(M->Gbuf, tsz * (size_t)M->var->C * stride);
     NEED(M->Mbuf, tsz * (size_t)M->var->C * stride);
+    NEED(M->Dbuf, tsz * (size_t)M->var->n_graphs * stride);
     NEED(M->site, tsz * stride);
     NEED(M->wv, tsz * 9 * stride);
     if (want_b) NEED(M->B, tsz * (size_t)M->m * stride);

@@ -350,105 +350,218 @@ __global__ void __launch_bounds__(kBlock) search_kernel(NbrArgs a) {
   }
 }
 
-// rev[p, i] for every stored pair; see the file comment for the rule.
-__global__ void reverse_kernel(NbrArgs a) {
+// rev[p, i] for every stored pair, one thread per slot; see the file comment
+// for the rule.  The run of j around slot p gives r (entries of j before p)
+// and k; the start of i's run in j's list comes from the run-start table of
+// the small search, else from a search of j's list.
+__global__ void reverse_kernel(NbrArgs a, int small_done) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int p = blockIdx.y;
   if (i >= a.n_atoms || p >= a.count[i]) return;
-  if (is_small(a.cfg[a.atom_cfg[i]]) && in_cfg(a.cfg[a.atom_cfg[i]], i)) return;
+  const CfgInfo& c = a.cfg[a.atom_cfg[i]];
+  if (!in_cfg(c, i) || (small_done && is_small(c))) return;
   const size_t e = (size_t)p * a.stride + i;
   const int32_t* row_i = a.nbr_row + (size_t)i * a.K;
+  const int ci = a.count[i];
   const int32_t j = row_i[p];
   int rank = 0;
   while (p - rank - 1 >= 0 && row_i[p - rank - 1] == j) ++rank;
-  const int32_t* row_j = a.nbr_row + (size_t)j * a.K;
+  int after = 0;
+  while (p + after + 1 < ci && row_i[p + after + 1] == j) ++after;
+  const int k = rank + 1 + after;
   const int cj = a.count[j];
-  int q0 = 0;
-  if (a.cfg[a.atom_cfg[i]].binned) {
-    while (q0 < cj && row_j[q0] != (int32_t)i) ++q0;        // one image per atom
+  int q0 = -1;
+  if (is_small(c)) {
+    const int n = c.n;
+    const int li = (int)(i - c.start), lj = (int)(j - c.start);
+    if (lj >= 0 && lj < n) q0 = a.run_start[(size_t)c.start * kSmallMax + (size_t)lj * n + li];
   } else {
-    int hi = cj;                                             // rows ascend in neighbour index
-    while (q0 < hi) {
-      const int mid = (q0 + hi) >> 1;
-      if (row_j[mid] < (int32_t)i) q0 = mid + 1; else hi = mid;
+    const int32_t* row_j = a.nbr_row + (size_t)j * a.K;
+    int lo = 0;
+    if (c.binned) {
+      while (lo < cj && row_j[lo] != (int32_t)i) ++lo;        // one image per atom
+    } else {
+      int hi = cj;                                             // rows ascend in neighbour index
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (row_j[mid] < (int32_t)i) lo = mid + 1; else hi = mid;
+      }
     }
+    q0 = lo;
   }
-  int k = 0;
-  while (q0 + k < cj && row_j[q0 + k] == (int32_t)i) ++k;
-  if (k > rank) {
-    a.rev[e] = (int32_t)((size_t)(q0 + k - 1 - rank) * a.stride + j);
+  const int q = q0 + k - 1 - rank;
+  if (q0 >= 0 && q < cj && a.nbr_row[(size_t)j * a.K + q] == (int32_t)i) {
+    a.rev[e] = (int32_t)((size_t)q * a.stride + j);
   } else {
     a.rev[e] = (int32_t)e;
     atomicAdd(&a.status->list_errors, 1ull);
   }
 }
 
+// Whole search of one small configuration in one workgroup.  Positions,
+// clamped species and (periodic cells) FP32 fractional coordinates are
+// staged in LDS; one atom per thread walks the atoms j of its configuration.
+// For a periodic cell the images n of j that can lie within R_cut satisfy
+// |s_j - s_i + n_d| <= w_d per lattice direction (s fractional coordinates,
+// w_d = R_cut / interplanar spacing).  With s = u + m, u = s - floor(s) in
+// [0, 1) held in FP32 and m integer, the box is taken over n' = n + m_j - m_i
+// with |u_j - u_i + n'_d| <= w_d (plus a margin for the rounding of u): j is
+// rejected at once when the nearest integer to u_j - u_i is farther than w_d
+// along some direction, otherwise the images of the box are tested with the
+// exact FP64 pair vector.  When every w_d < 1/2 the box holds at most that
+// nearest integer, and no loop over images is needed.  u_j - u_i changes
+// sign exactly when i and j swap, so the box of (j, i) is the negated box of
+// (i, j).
+//
+// Reverse indices: the r-th of the k images in i's run of j is reversed by
+// entry q0 + k - 1 - r of j's list, q0 the start of j's run of i.  With
+// neighbour capacity K <= kLdsSlots the lists are also kept in LDS as local
+// indices (one byte each) and, after a barrier, every thread finds q0 by a
+// binary search of j's LDS list, so the workgroup issues no global load after
+// its first global store.  With a larger K the search records run starts in
+// a global table (run_start[i][j]) and reverse_kernel reads them.
+constexpr int kLdsSlots = 128;
 
-// Whole search of one small configuration in one workgroup: positions staged
-// in LDS, one atom per thread, lists written to the ELL arrays.  While atom i
-// walks its neighbours in order it records where the run of each neighbour j
-// starts in its own list (run_start[i][j]); after a barrier the reverse of
-// the r-th image in i's run of j is run_start[j][i] + k - 1 - r (k images).
-__global__ void __launch_bounds__(kSmallBlock) search_small_kernel(NbrArgs a) {
+template <typename Visit>
+__device__ inline void small_candidates(const CfgInfo& c, const double* sp, const float* sf, const int32_t* sm,
+                                        int n, int li, double rc2, Visit&& visit) {
+  const double xi = sp[3 * li], yi = sp[3 * li + 1], zi = sp[3 * li + 2];
+  const double* L = c.L;
+  if (!c.pbc) {
+    for (int lj = 0; lj < n; ++lj) {
+      const double dx = sp[3 * lj] - xi, dy = sp[3 * lj + 1] - yi, dz = sp[3 * lj + 2] - zi;
+      const double r2 = dx * dx + dy * dy + dz * dz;
+      if (lj != li && r2 < rc2) {
+        visit.pair(lj, dx, dy, dz, r2);
+        visit.run_end(lj, 1);
+      }
+    }
+    return;
+  }
+  const float w0 = (float)c.w[0] + 1e-3f, w1 = (float)c.w[1] + 1e-3f, w2 = (float)c.w[2] + 1e-3f;
+  const float fi0 = sf[3 * li], fi1 = sf[3 * li + 1], fi2 = sf[3 * li + 2];
+  const int mi0 = sm[3 * li], mi1 = sm[3 * li + 1], mi2 = sm[3 * li + 2];
+  if (w0 < 0.5f && w1 < 0.5f && w2 < 0.5f) {
+    for (int lj = 0; lj < n; ++lj) {
+      const float s0 = sf[3 * lj] - fi0, s1 = sf[3 * lj + 1] - fi1, s2 = sf[3 * lj + 2] - fi2;
+      const float r0 = rintf(s0), r1 = rintf(s1), r2f = rintf(s2);
+      if (fabsf(s0 - r0) > w0 || fabsf(s1 - r1) > w1 || fabsf(s2 - r2f) > w2) continue;
+      // n = n' - m_j + m_i with n' = -rint(u_j - u_i)
+      const int n0 = -(int)r0 + mi0 - sm[3 * lj], n1 = -(int)r1 + mi1 - sm[3 * lj + 1],
+                n2 = -(int)r2f + mi2 - sm[3 * lj + 2];
+      if (lj == li && n0 == 0 && n1 == 0 && n2 == 0) continue;
+      const double dx = sp[3 * lj] - xi, dy = sp[3 * lj + 1] - yi, dz = sp[3 * lj + 2] - zi;
+      const double rx = dx + ((double)n0 * L[0] + (double)n1 * L[3] + (double)n2 * L[6]);
+      const double ry = dy + ((double)n0 * L[1] + (double)n1 * L[4] + (double)n2 * L[7]);
+      const double rz = dz + ((double)n0 * L[2] + (double)n1 * L[5] + (double)n2 * L[8]);
+      const double r2 = rx * rx + ry * ry + rz * rz;
+      if (r2 < rc2) {
+        visit.pair(lj, rx, ry, rz, r2);
+        visit.run_end(lj, 1);
+      }
+    }
+    return;
+  }
+  for (int lj = 0; lj < n; ++lj) {
+    const float s0 = sf[3 * lj] - fi0, s1 = sf[3 * lj + 1] - fi1, s2 = sf[3 * lj + 2] - fi2;
+    if (fabsf(s0 - rintf(s0)) > w0 || fabsf(s1 - rintf(s1)) > w1 || fabsf(s2 - rintf(s2)) > w2) continue;
+    const int lo0 = -(int)floorf(w0 + s0), hi0 = (int)floorf(w0 - s0);
+    const int lo1 = -(int)floorf(w1 + s1), hi1 = (int)floorf(w1 - s1);
+    const int lo2 = -(int)floorf(w2 + s2), hi2 = (int)floorf(w2 - s2);
+    const double dx = sp[3 * lj] - xi, dy = sp[3 * lj + 1] - yi, dz = sp[3 * lj + 2] - zi;
+    // n = n' - m_j + m_i
+    const int o0 = mi0 - sm[3 * lj], o1 = mi1 - sm[3 * lj + 1], o2 = mi2 - sm[3 * lj + 2];
+    int k = 0;
+    for (int n0 = lo0 + o0; n0 <= hi0 + o0; ++n0)
+      for (int n1 = lo1 + o1; n1 <= hi1 + o1; ++n1)
+        for (int n2 = lo2 + o2; n2 <= hi2 + o2; ++n2) {
+          if (lj == li && n0 == 0 && n1 == 0 && n2 == 0) continue;
+          const double sx = (double)n0 * L[0] + (double)n1 * L[3] + (double)n2 * L[6];
+          const double sy = (double)n0 * L[1] + (double)n1 * L[4] + (double)n2 * L[7];
+          const double sz = (double)n0 * L[2] + (double)n1 * L[5] + (double)n2 * L[8];
+          const double rx = dx + sx, ry = dy + sy, rz = dz + sz;
+          const double r2 = rx * rx + ry * ry + rz * rz;
+          if (r2 < rc2) {
+            visit.pair(lj, rx, ry, rz, r2);
+            ++k;
+          }
+        }
+    if (k > 0) visit.run_end(lj, k);
+  }
+}
+
+// Lists, run starts (global table or LDS list) and counters of one atom.
+struct SmallEmit {
+  const NbrArgs& a;
+  int64_t i, start;
+  const int32_t* sz;
+  int32_t* row;
+  int16_t* my_starts;   // global run-start row (null when the LDS lists are used)
+  uint8_t* lds_row;     // LDS list of local neighbour indices (null otherwise)
+  double rmin2;
+  int count = 0, below = 0, before = 0;
+  __device__ void pair(int lj, double rx, double ry, double rz, double r2) {
+    if (count < a.K) {
+      row[count] = (int32_t)(start + lj);
+      store_pair(a, (size_t)count * a.stride + i, rx, ry, rz, sz[lj]);
+      if (lds_row) lds_row[count] = (uint8_t)lj;
+    }
+    if (r2 < rmin2) ++below;
+    ++count;
+  }
+  __device__ void run_end(int lj, int) {
+    if (my_starts && before < a.K) my_starts[lj] = (int16_t)before;
+    before = count;
+  }
+};
+
+__global__ void __launch_bounds__(kSmallBlock) search_small_kernel(NbrArgs a, int lds_lists) {
   __shared__ double sp[3 * kSmallMax];
+  __shared__ float sf[3 * kSmallMax];
+  __shared__ int32_t sm[3 * kSmallMax];
+  __shared__ int32_t sz[kSmallMax];
+  __shared__ int32_t scount[kSmallMax];
   __shared__ unsigned long long red[5];
+  extern __shared__ uint8_t lists[];   // [kSmallMax][K] when lds_lists
   const CfgInfo c = a.cfg[blockIdx.x];
   if (!is_small(c)) return;
   const int t = threadIdx.x;
   const int n = c.n;
+  const int KL = a.K;
   if (t < 5) red[t] = 0;
   for (int q = t; q < 3 * n; q += blockDim.x) sp[q] = a.pos[3 * c.start + q];
+  int bad = 0;
+  for (int q = t; q < n; q += blockDim.x) {
+    const int z = a.species[c.start + q];
+    if (z < 0 || z >= a.n_species) bad = 1;
+    sz[q] = z < 0 ? 0 : (z >= a.n_species ? a.n_species - 1 : z);
+  }
+  __syncthreads();
+  if (c.pbc)
+    for (int q = t; q < n; q += blockDim.x)
+      for (int d = 0; d < 3; ++d) {
+        const double f = sp[3 * q] * c.inv[0 * 3 + d] + sp[3 * q + 1] * c.inv[1 * 3 + d] +
+                         sp[3 * q + 2] * c.inv[2 * 3 + d];
+        const double fl = floor(f);
+        sf[3 * q + d] = (float)(f - fl);
+        sm[3 * q + d] = (int32_t)fl;
+      }
   __syncthreads();
   const double rc2 = a.rcut * a.rcut;
-  const double rmin2 = a.rmin * a.rmin;
-  const double* L = c.L;
-  const double* inv = c.inv;
-  // run starts of this configuration: rows of n int16 at the config's atom offset
+  // global run starts of this configuration: rows of n int16 at the config's atom offset
   int16_t* run_start = a.run_start + (size_t)c.start * kSmallMax;
   const int li = t;
-  int count = 0, below = 0, bad = 0;
+  int count = 0, below = 0;
   if (li < n) {
     const int64_t i = c.start + li;
-    if (a.species[i] < 0 || a.species[i] >= a.n_species) bad = 1;
-    const double xi = sp[3 * li], yi = sp[3 * li + 1], zi = sp[3 * li + 2];
-    int32_t* row = a.nbr_row + (size_t)i * a.K;
-    int16_t* my_starts = run_start + (size_t)li * n;
-    auto emit = [&](int lj, double rx, double ry, double rz, double r2) {
-      if (count < a.K) {
-        const size_t e = (size_t)count * a.stride + i;
-        const int64_t j = c.start + lj;
-        int zj = a.species[j];
-        zj = zj < 0 ? 0 : (zj >= a.n_species ? a.n_species - 1 : zj);
-        row[count] = (int32_t)j;
-        store_pair(a, e, rx, ry, rz, zj);
-      }
-      if (r2 < rmin2) ++below;
-      ++count;
-    };
-    for (int lj = 0; lj < n; ++lj) {
-      const int before = count;
-      const double dx = sp[3 * lj] - xi, dy = sp[3 * lj + 1] - yi, dz = sp[3 * lj + 2] - zi;
-      if (!c.pbc) {
-        const double r2 = dx * dx + dy * dy + dz * dz;
-        if (lj != li && r2 < rc2) emit(lj, dx, dy, dz, r2);
-      } else {
-        int lo[3], hi[3];
-        image_box(c, dx, dy, dz, lo, hi);
-        for (int n0 = lo[0]; n0 <= hi[0]; ++n0)
-          for (int n1 = lo[1]; n1 <= hi[1]; ++n1)
-            for (int n2 = lo[2]; n2 <= hi[2]; ++n2) {
-              if (lj == li && n0 == 0 && n1 == 0 && n2 == 0) continue;
-              const double sx = (double)n0 * L[0] + (double)n1 * L[3] + (double)n2 * L[6];
-              const double sy = (double)n0 * L[1] + (double)n1 * L[4] + (double)n2 * L[7];
-              const double sz = (double)n0 * L[2] + (double)n1 * L[5] + (double)n2 * L[8];
-              const double rx = dx + sx, ry = dy + sy, rz = dz + sz;
-              const double r2 = rx * rx + ry * ry + rz * rz;
-              if (r2 < rc2) emit(lj, rx, ry, rz, r2);
-            }
-      }
-      if (count > before && before < a.K) my_starts[lj] = (int16_t)before;
-    }
+    SmallEmit em{a, i, c.start, sz, a.nbr_row + (size_t)i * a.K,
+                 lds_lists ? nullptr : run_start + (size_t)li * n,
+                 lds_lists ? lists + (size_t)li * KL : nullptr, a.rmin * a.rmin};
+    small_candidates(c, sp, sf, sm, n, li, rc2, em);
+    count = em.count;
+    below = em.below;
     a.count[i] = count < a.K ? count : a.K;
+    scount[li] = count < a.K ? count : a.K;
   }
   const int over = count > a.K ? 1 : 0;
   atomicMax(&red[0], (unsigned long long)count);
@@ -456,7 +569,7 @@ __global__ void __launch_bounds__(kSmallBlock) search_small_kernel(NbrArgs a) {
   if (over) atomicAdd(&red[2], 1ull);
   if (below) atomicAdd(&red[3], (unsigned long long)below);
   if (bad) atomicAdd(&red[4], 1ull);
-  __syncthreads();  // lists and run starts of the whole configuration are written
+  __syncthreads();  // LDS lists and counts of the whole configuration are complete
   if (t == 0) {
     atomicMax(&a.status->max_count, red[0]);
     atomicAdd(&a.status->n_pairs, red[1]);
@@ -464,22 +577,29 @@ __global__ void __launch_bounds__(kSmallBlock) search_small_kernel(NbrArgs a) {
     if (red[3]) atomicAdd(&a.status->below_rmin, red[3]);
     if (red[4]) atomicAdd(&a.status->bad_species, red[4]);
   }
-  if (li >= n || red[2]) return;   // on overflow the call is repeated with more slots
+  if (!lds_lists || li >= n || red[2]) return;   // on overflow the call is repeated with more slots
   const int64_t i = c.start + li;
-  const int ci = a.count[i];
-  const int32_t* row_i = a.nbr_row + (size_t)i * a.K;
+  const uint8_t* mine = lists + (size_t)li * KL;
+  const int ci = scount[li];
   unsigned long long errs = 0;
   int p = 0;
   while (p < ci) {
-    const int32_t j = row_i[p];
+    const int lj = mine[p];
     int k = 1;
-    while (p + k < ci && row_i[p + k] == j) ++k;
-    const int lj = (int)(j - c.start);
-    const int q0 = run_start[(size_t)lj * n + li];
+    while (p + k < ci && mine[p + k] == lj) ++k;
+    // start of the run of li in lj's list (ascending local indices)
+    const uint8_t* other = lists + (size_t)lj * KL;
+    const int cj = scount[lj];
+    int lo = 0, hi = cj;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if ((int)other[mid] < li) lo = mid + 1; else hi = mid;
+    }
+    const int64_t j = c.start + lj;
     for (int r = 0; r < k; ++r) {
       const size_t e = (size_t)(p + r) * a.stride + i;
-      const int q = q0 + k - 1 - r;
-      if (q >= 0 && q < a.count[j]) {
+      const int q = lo + k - 1 - r;
+      if (q < cj && other[q] == (uint8_t)li) {
         a.rev[e] = (int32_t)((size_t)q * a.stride + j);
       } else {
         a.rev[e] = (int32_t)e;
@@ -510,10 +630,12 @@ hipError_t nbr_build(NbrArgs& a, hipStream_t s) {
   if (a.n_cfg > 0) hipLaunchKernelGGL(bin_scan_kernel, dim3(a.n_cfg), dim3(256), 0, s, a);
   hipLaunchKernelGGL(bin_fill_kernel, grid_for(a.n_atoms), dim3(kBlock), 0, s, a);
   hipLaunchKernelGGL(bin_sort_kernel, grid_for(a.n_atoms), dim3(kBlock), 0, s, a);
-  if (a.n_cfg > 0) hipLaunchKernelGGL(search_small_kernel, dim3(a.n_cfg), dim3(kSmallBlock), 0, s, a);
+  const int lds_lists = a.K <= kLdsSlots ? 1 : 0;
+  const size_t lds = lds_lists ? (size_t)kSmallMax * a.K : 0;
+  if (a.n_cfg > 0) hipLaunchKernelGGL(search_small_kernel, dim3(a.n_cfg), dim3(kSmallBlock), lds, s, a, lds_lists);
   hipLaunchKernelGGL(search_kernel, grid_for(a.n_atoms), dim3(kBlock), 0, s, a);
   const dim3 g((unsigned)((a.n_atoms + kBlock - 1) / kBlock), (unsigned)a.K);
-  hipLaunchKernelGGL(reverse_kernel, g, dim3(kBlock), 0, s, a);
+  hipLaunchKernelGGL(reverse_kernel, g, dim3(kBlock), 0, s, a, lds_lists);
   return hipGetLastError();
 }
 

@@ -15,31 +15,49 @@ namespace {
 constexpr int kBlock = 256;
 
 // Forces (when F is not null) and the per-atom virial sum_p g_p (x) r_p
-// (when wv is not null), W_ab = dE/d eps_ab for r -> (I + eps) r.
+// (when wv is not null), W_ab = dE/d eps_ab for r -> (I + eps) r.  Pairs are
+// taken four at a time so that the four dependent loads g[rev[e]] are in
+// flight together; the sums keep the pair order.
 template <typename T>
 __global__ void gather_kernel(int64_t n_atoms, int stride, const int32_t* __restrict__ count,
                               const int32_t* __restrict__ rev, const T* __restrict__ g,
                               const PairRec<T>* __restrict__ pr, double* __restrict__ F, T* __restrict__ wv) {
+  constexpr int U = 4;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n_atoms) return;
   double fx = 0, fy = 0, fz = 0;
   double w[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
   const int c = count[i];
-  for (int p = 0; p < c; ++p) {
-    const size_t e = (size_t)p * stride + i;
-    const double gx = (double)g[3 * e], gy = (double)g[3 * e + 1], gz = (double)g[3 * e + 2];
-    if (F) {
-      const size_t q = (size_t)rev[e];
-      fx += gx - (double)g[3 * q];
-      fy += gy - (double)g[3 * q + 1];
-      fz += gz - (double)g[3 * q + 2];
+  for (int p0 = 0; p0 < c; p0 += U) {
+    double gx[U], gy[U], gz[U], hx[U], hy[U], hz[U], x[U], y[U], z[U];
+    size_t q[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const size_t e = (size_t)(p0 + u < c ? p0 + u : p0) * stride + i;
+      q[u] = F ? (size_t)rev[e] : e;
+      gx[u] = (double)g[3 * e]; gy[u] = (double)g[3 * e + 1]; gz[u] = (double)g[3 * e + 2];
+      if (wv) {
+        const PairRec<T> r = pr[e];
+        x[u] = (double)r.x; y[u] = (double)r.y; z[u] = (double)r.z;
+      }
     }
-    if (wv) {
-      const PairRec<T> q = pr[e];
-      const double x = (double)q.x, y = (double)q.y, z = (double)q.z;
-      w[0] += gx * x; w[1] += gx * y; w[2] += gx * z;
-      w[3] += gy * x; w[4] += gy * y; w[5] += gy * z;
-      w[6] += gz * x; w[7] += gz * y; w[8] += gz * z;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      hx[u] = (double)g[3 * q[u]]; hy[u] = (double)g[3 * q[u] + 1]; hz[u] = (double)g[3 * q[u] + 2];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (p0 + u >= c) break;
+      if (F) {
+        fx += gx[u] - hx[u];
+        fy += gy[u] - hy[u];
+        fz += gz[u] - hz[u];
+      }
+      if (wv) {
+        w[0] += gx[u] * x[u]; w[1] += gx[u] * y[u]; w[2] += gx[u] * z[u];
+        w[3] += gy[u] * x[u]; w[4] += gy[u] * y[u]; w[5] += gy[u] * z[u];
+        w[6] += gz[u] * x[u]; w[7] += gz[u] * y[u]; w[8] += gz[u] * z[u];
+      }
     }
   }
   if (F) {
@@ -86,19 +104,37 @@ __global__ void __launch_bounds__(kBlock) config_kernel(int n_cfg, const CfgInfo
 }
 
 // b[k][f] = sum over atoms of configuration k of B[perm[f]][atom]; one block
-// per configuration, threads over basis functions.
+// per configuration, each wavefront four basis functions at a time: lanes
+// read consecutive atoms (coalesced) and the 64 partial sums are combined by
+// a butterfly in a fixed order.
 template <typename T>
 __global__ void __launch_bounds__(kBlock) b_kernel(int n_cfg, const CfgInfo* __restrict__ cfg,
                                                    const T* __restrict__ B, int m, int b_stride,
                                                    const int32_t* __restrict__ perm, double* b) {
+  constexpr int U = 4;
+  constexpr int kWaves = kBlock / 64;
   const int k = blockIdx.x;
   if (k >= n_cfg) return;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int64_t a0 = cfg[k].start, a1 = cfg[k].start + cfg[k].n;
-  for (int f = threadIdx.x; f < m; f += blockDim.x) {
-    const T* row = B + (size_t)perm[f] * b_stride;
-    double s = 0.0;
-    for (int64_t i = a0; i < a1; ++i) s += (double)row[i];
-    b[(size_t)k * m + f] = s;
+  for (int f0 = wave * U; f0 < m; f0 += kWaves * U) {
+    const T* row[U];
+    double s[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      row[u] = B + (size_t)perm[f0 + u < m ? f0 + u : f0] * b_stride;
+      s[u] = 0.0;
+    }
+    for (int64_t i = a0 + lane; i < a1; i += 64)
+#pragma unroll
+      for (int u = 0; u < U; ++u) s[u] += (double)row[u][i];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      for (int o = 32; o > 0; o >>= 1) s[u] += __shfl_xor(s[u], o, 64);
+    if (lane == 0)
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (f0 + u < m) b[(size_t)k * m + f0 + u] = s[u];
   }
 }
 
