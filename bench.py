@@ -37,6 +37,27 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+TRAFFIC_MD = os.path.join(ROOT, "profiles", "eval_lev16_batch4096_fp64_hbm.md")
+KERNEL_SRC = os.path.join(ROOT, "paper_2007_08555_amd", "csrc", "generated", "gen_lev16.hip")
+
+
+def measured_traffic():
+    """HBM bytes per launch of the evaluation kernels from the committed
+    FETCH_SIZE / WRITE_SIZE summary, when it was taken on the kernels built
+    here (same generated source); else None."""
+    import hashlib
+    try:
+        fields = dict(line.split(": ", 1) for line in open(TRAFFIC_MD).read().splitlines() if ": " in line
+                      and line.split(": ", 1)[0] in ("traffic_bytes_per_launch", "kernel_source_sha256"))
+        with open(KERNEL_SRC, "rb") as fh:
+            digest = hashlib.sha256(fh.read()).hexdigest()
+    except OSError:
+        return None
+    if fields.get("kernel_source_sha256", "").strip() != digest:
+        return None
+    return float(fields["traffic_bytes_per_launch"])
+
+
 def cpu_baseline(batch, pot_path, budget_s):
     """The FP64 oracle on the host, one thread, over whole configurations of
     the same batch until budget_s seconds have passed."""
@@ -172,8 +193,10 @@ def main():
     ms = {k: float(np.mean(v)) for k, v in ms.items()}
     flops = st["n_pairs"] * (st["flops_pair_fwd"] + st["flops_pair_bwd"]) + st["n_atoms"] * st["flops_atom"]
     achieved = flops / (ms["ms_eval"] * 1e-3) / 1e12
+    traffic = measured_traffic() if (a.precision == "fp64" and a.configs == 4096) else None
     roofline = {"bound": "alu", "achieved": achieved, "peak": PEAK[a.precision], "unit": "TFLOP/s",
-                "frac": achieved / PEAK[a.precision], "traffic": None,
+                "frac": achieved / PEAK[a.precision], "traffic": traffic,
+                "traffic_hbm_TBps": None if traffic is None else traffic / (ms["ms_eval"] * 1e-3) / 1e12,
                 "kernel": "evaluation kernel (moments, contractions, adjoint)",
                 "flops_per_launch": flops, "kernel_ms": ms["ms_eval"],
                 "n_pairs": st["n_pairs"], "phase_ms": ms}

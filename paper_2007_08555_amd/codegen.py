@@ -148,6 +148,25 @@ def emit_pair_forward(s, comp_mode, nus=None, kmap=None):
     return out, ops
 
 
+REVERSE_TEMPLATE = r"""
+// Reverse sweep, pass {pidx}: G = dV/dM for the components of degrees {nus}
+// from the moments they pair with and dV/dg of the graphs they occur in.
+template <typename T>
+__global__ void __launch_bounds__(BLOCK) contract_rev_{tag}_kernel(const mtp::EvalArgs<T> args) {{
+  const int i = blockIdx.x * BLOCK + threadIdx.x;
+  if (i >= args.n_atoms) return;
+  T M[C];
+{load_m}
+{load_dg}
+#define MTP_OUT_G(k_, v_) args.G[(size_t)(k_) * args.stride + i] = (v_)
+#define MTP_FENCE_M() do {{ {fence} }} while (0)
+{body}
+#undef MTP_FENCE_M
+#undef MTP_OUT_G
+}}
+"""
+
+
 MOMENTS_TEMPLATE = r"""
 // Moments pass {pidx}: the components of degrees {nus} of one atom, summed
 // over its pairs and written to args.M.
@@ -275,6 +294,39 @@ def emit_contraction(s):
         # interleaved with the next ones (FP64 then needs no scratch)
         out.append("mtp::opaque(M);")
     return out, ops
+
+
+def emit_reverse_pass(s, ks):
+    """Reverse sweep restricted to the components ks: G[k] = sum over graph
+    terms holding M[k] of dV/dg times the product of the other factors.
+    Returns the lines and the sets of M components and graphs it reads."""
+    contrib = defaultdict(lambda: defaultdict(list))
+    for g, terms in enumerate(s.terms):
+        for coef, idx in terms:
+            for k in set(idx):
+                cnt = idx.count(k)
+                rest = list(idx)
+                rest.remove(k)
+                contrib[k][g].append((coef * cnt, rest))
+    out, m_used, g_used = [], set(), set()
+    for k in ks:
+        if not contrib[k]:
+            out.append(f"MTP_OUT_G({k}, T(0));")
+            continue
+        parts = []
+        for g, lst in sorted(contrib[k].items()):
+            g_used.add(g)
+            inner = []
+            for c, rest in lst:
+                m_used.update(rest)
+                expr = _prod([f"M[{q}]" for q in rest])
+                if c != 1:
+                    expr = f"{_const(c)} * {expr}" if rest else _const(c)
+                inner.append(expr)
+            parts.append(f"dg{g} * (" + " + ".join(inner) + ")")
+        out.append(f"MTP_OUT_G({k}, " + " + ".join(parts) + ");")
+        out.append("MTP_FENCE_M();")
+    return out, sorted(m_used), sorted(g_used)
 
 
 def emit_pair_backward(s, nus=None, gmap=None, nmu=None):
@@ -691,20 +743,7 @@ __global__ void __launch_bounds__(BLOCK) contract_fwd_kernel(const mtp::EvalArgs
   args.site[i] = V;
 }}
 
-// Reverse sweep: G = dV/dM from M and dV/dg.
-template <typename T>
-__global__ void __launch_bounds__(BLOCK) contract_rev_kernel(const mtp::EvalArgs<T> args) {{
-  const int i = blockIdx.x * BLOCK + threadIdx.x;
-  if (i >= args.n_atoms) return;
-  T M[C];
-#pragma unroll
-  for (int k = 0; k < C; ++k) M[k] = args.M[(size_t)k * args.stride + i];
-{load_dg}
-#define MTP_OUT_G(k_, v_) args.G[(size_t)(k_) * args.stride + i] = (v_)
-{contraction_rev}
-#undef MTP_OUT_G
-}}
-
+{contract_rev_kernels}
 // The same contraction code on dual numbers M + dM e: the tangents of G and of
 // every B_alpha along the moment tangent dM (forward mode over the reverse
 // sweep).  Writes dG and a_k B_alpha + dB_alpha.
@@ -762,7 +801,11 @@ hipError_t launch_t(const void* a, bool reuse_moments, hipStream_t s) {{
     }}
   }}
   hipLaunchKernelGGL((contract_fwd_kernel<T, WANT_B>), grid, dim3(BLOCK), 0, s, args);
-  hipLaunchKernelGGL((contract_rev_kernel<T>), grid, dim3(BLOCK), 0, s, args);
+  if constexpr (sizeof(T) == 8) {{
+{launch_rev_f64}
+  }} else {{
+{launch_rev_f32}
+  }}
   if constexpr (sizeof(T) == 8) {{
 {launch_f64}
   }} else {{
@@ -803,6 +846,7 @@ extern const mtp::BasisVariant {ns}_variant = {{
 
 
 ADJ_BUDGET_F64 = 90   # components per FP64 adjoint pass
+REV_GROUPS_F64 = [(0, 1), (2,), (3, 4), (5, 6)]   # degree groups of the FP64 reverse sweep
 
 
 def generate(lev_max, block=64):
@@ -812,6 +856,26 @@ def generate(lev_max, block=64):
     # moments passes: FP64 accumulators of all 130 components of level 16 do
     # not fit the register file next to the pair's temporaries, so FP64 sums
     # the degrees in two groups (each pass recomputes r and f_mu)
+    # reverse sweep passes by degree groups: each pass holds only the moments
+    # and dV/dg its components need
+    rev_src, rev_launch = [], {}
+    comp_nu = {k: nu for (mu, nu, abc), k in s.comp.items()}
+    for prec, groups in (("f32", [tuple(range(s.nu_max + 1))]), ("f64", REV_GROUPS_F64)):
+        lines = []
+        groups = [tuple(n for n in grp if n <= s.nu_max) for grp in groups]
+        groups = [grp for grp in groups if any(comp_nu[k] in grp for k in range(s.C))]
+        for pidx, grp in enumerate(groups):
+            tag = f"{prec}_p{pidx}"
+            ks = [k for k in range(s.C) if comp_nu[k] in grp]
+            body, m_used, g_used = emit_reverse_pass(s, ks)
+            rev_src.append(REVERSE_TEMPLATE.format(
+                pidx=pidx, nus=list(grp), tag=tag,
+                load_m="\n".join(f"  M[{q}] = args.M[(size_t){q} * args.stride + i];" for q in m_used),
+                load_dg="\n".join(f"  const T dg{g} = args.D[(size_t){g} * args.stride + i];" for g in g_used),
+                fence=" ".join(f'asm volatile("" : "+v"(M[{q}]));' for q in m_used),
+                body="\n".join("  " + l for l in body)))
+            lines.append(f"    hipLaunchKernelGGL((contract_rev_{tag}_kernel<T>), grid, dim3(BLOCK), 0, s, args);")
+        rev_launch[prec] = "\n".join(lines)
     mom_src, mom_launch = [], {}
     for prec, budget in (("f32", 10 ** 9), ("f64", 85)):
         lines = []
@@ -868,7 +932,8 @@ def generate(lev_max, block=64):
         moments_kernels="\n".join(mom_src), launch_mom_f64=mom_launch["f64"], launch_mom_f32=mom_launch["f32"],
         contraction=ind(con, 2),
         contraction_fwd=ind(con[:con.index("MTP_RELOAD_M();")], 2),
-        contraction_rev=ind(con[con.index("MTP_RELOAD_M();") + 1:], 2),
+        contract_rev_kernels="\n".join(rev_src), launch_rev_f64=rev_launch["f64"],
+        launch_rev_f32=rev_launch["f32"],
         store_dg=ind([f"args.D[(size_t){g} * args.stride + i] = dg{g};" for g in range(len(s.terms))], 2),
         load_dg=ind([f"const T dg{g} = args.D[(size_t){g} * args.stride + i];" for g in range(len(s.terms))], 2), adjoint_kernels="\n".join(adj_src),
         launch_f64=launches["f64"], launch_f32=launches["f32"],
