@@ -404,8 +404,9 @@ ADJOINT_TEMPLATE = r"""
 // Adjoint pass {pidx} over the pairs of one atom, components of degrees {nus}:
 // its share of g = dV_i/dr_ij from G, f_mu and df_mu/dr, stored (first pass)
 // or added (later passes) per pair for the force and virial gather.
-template <typename T, bool FIRST>
-__global__ void __launch_bounds__(BLOCK) adjoint_{tag}_kernel(const mtp::EvalArgs<T> args) {{
+template <typename T, bool FIRST, bool LAST>
+__global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2)))
+adjoint_{tag}_kernel(const mtp::EvalArgs<T> args) {{
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* cs = reinterpret_cast<T*>(smem_raw);
   for (int t = threadIdx.x; t < args.n_c; t += blockDim.x) cs[t] = args.c[t];
@@ -423,6 +424,8 @@ __global__ void __launch_bounds__(BLOCK) adjoint_{tag}_kernel(const mtp::EvalArg
   T G[CP];
 #pragma unroll
   for (int k = 0; k < CP; ++k) G[k] = args.G[(size_t)kIdx[k] * args.stride + i];
+  // the last pass also sums the per-atom virial sum_p g_p (x) r_p
+  T w0 = T(0), w1 = T(0), w2 = T(0), w3 = T(0), w4 = T(0), w5 = T(0), w6 = T(0), w7 = T(0), w8 = T(0);
   // pair p + 1 (and its partial g) is loaded while pair p is processed
   T xn = T(0), yn = T(0), zn = T(0), g0n = T(0), g1n = T(0), g2n = T(0);
   int zjn = 0;
@@ -448,15 +451,21 @@ __global__ void __launch_bounds__(BLOCK) adjoint_{tag}_kernel(const mtp::EvalArg
     T f[{nmu}], df[{nmu}];
     mtp::radial<T, {nmu}, true>(cs, (zi * S + zj) * nq, mu_stride, nq, r, rmin, rcut, f, df);
 {body}
-    if (FIRST) {{
-      args.g[3 * e] = gx;
-      args.g[3 * e + 1] = gy;
-      args.g[3 * e + 2] = gz;
-    }} else {{
-      args.g[3 * e] = gp0 + gx;
-      args.g[3 * e + 1] = gp1 + gy;
-      args.g[3 * e + 2] = gp2 + gz;
+    const T tx = FIRST ? gx : gp0 + gx, ty = FIRST ? gy : gp1 + gy, tz = FIRST ? gz : gp2 + gz;
+    args.g[3 * e] = tx;
+    args.g[3 * e + 1] = ty;
+    args.g[3 * e + 2] = tz;
+    if constexpr (LAST) {{
+      w0 += tx * x; w1 += tx * y; w2 += tx * z;
+      w3 += ty * x; w4 += ty * y; w5 += ty * z;
+      w6 += tz * x; w7 += tz * y; w8 += tz * z;
     }}
+  }}
+  if constexpr (LAST) {{
+    T* wv = args.atom_virial + i;
+    const size_t st = args.stride;
+    wv[0] = w0; wv[st] = w1; wv[2 * st] = w2; wv[3 * st] = w3; wv[4 * st] = w4;
+    wv[5 * st] = w5; wv[6 * st] = w6; wv[7 * st] = w7; wv[8 * st] = w8;
   }}
 }}
 """
@@ -907,7 +916,9 @@ def generate(lev_max, block=64):
             adj_src.append(ADJOINT_TEMPLATE.format(pidx=pidx, nus=nus, tag=tag, ncomp=len(comps), nmu=nmu,
                                                    comp_list=", ".join(map(str, comps)),
                                                    body="\n".join(" " * 4 + l for l in body)))
-            lines.append(f"    hipLaunchKernelGGL((adjoint_{tag}_kernel<T, {'true' if pidx == 0 else 'false'}>), "
+            first = "true" if pidx == 0 else "false"
+            last = "true" if pidx == len(passes) - 1 else "false"
+            lines.append(f"    hipLaunchKernelGGL((adjoint_{tag}_kernel<T, {first}, {last}>), "
                          f"grid, dim3(BLOCK), smem, s, args);")
         launches[prec] = "\n".join(lines)
     # radial work per pair: distance 6, Chebyshev 3 per term, f_mu 2 per (mu, beta),

@@ -416,8 +416,9 @@ int run_eval(mtp_model* M, const mtp_batch* bt, const mtp_out* out, int precisio
       }
     }
     HIP_TRY(mark(2), "hipEventRecord");
+    // the per-atom virials were summed by the last adjoint pass
     HIP_TRY(gather_forces(fp64, N, stride, M->count.as<int32_t>(), M->rev.as<int32_t>(), M->gpair.p, M->pr.p,
-                          out->forces, out->virial ? M->wv.p : nullptr, s),
+                          out->forces, nullptr, s),
             "force gather");
     HIP_TRY(mark(3), "hipEventRecord");
     HIP_TRY(reduce_configs(fp64, n_cfg, M->cfg.as<CfgInfo>(), stride, M->site.p, out->virial ? M->wv.p : nullptr,
@@ -728,7 +729,7 @@ int mtp_normal_equations(mtp_model* M, const mtp_batch* bt, const double* E_t, c
       }
     }
     HIP_TRY(mtp::gather_forces(fp64, N, stride, M->count.as<int32_t>(), M->rev.as<int32_t>(), M->gpair.p, M->pr.p,
-                               col + K_cfg, M->wv.p, s),
+                               col + K_cfg, nullptr, s),
             "force gather");
     HIP_TRY(mtp::reduce_configs(fp64, K_cfg, M->cfg.as<mtp::CfgInfo>(), stride, M->site.p, M->wv.p, nullptr, m,
                                 stride, M->perm_dev.as<int32_t>(), col, col + K_cfg + 3 * N, nullptr, nullptr, s),

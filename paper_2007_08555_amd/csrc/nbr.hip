@@ -422,14 +422,25 @@ __global__ void reverse_kernel(NbrArgs a, int small_done) {
 // a global table (run_start[i][j]) and reverse_kernel reads them.
 constexpr int kLdsSlots = 128;
 
+// Per-atom LDS records of the small search: FP64 position, FP32 wrapped
+// fractional coordinates u, their integer parts m and the clamped species.
+struct SmallAtoms {
+  double4* x;  // (x, y, z, -)
+  float4* u;   // (u0, u1, u2, -)
+  int4* mz;    // (m0, m1, m2, species)
+};
+
 template <typename Visit>
-__device__ inline void small_candidates(const CfgInfo& c, const double* sp, const float* sf, const int32_t* sm,
-                                        int n, int li, double rc2, Visit&& visit) {
-  const double xi = sp[3 * li], yi = sp[3 * li + 1], zi = sp[3 * li + 2];
+__device__ inline void small_candidates(const CfgInfo& c, const SmallAtoms& sa, int n, int li, double rc2,
+                                        Visit&& visit) {
+  const double4 pi = sa.x[li];
   const double* L = c.L;
   if (!c.pbc) {
+    double4 pn = sa.x[0];
     for (int lj = 0; lj < n; ++lj) {
-      const double dx = sp[3 * lj] - xi, dy = sp[3 * lj + 1] - yi, dz = sp[3 * lj + 2] - zi;
+      const double4 pj = pn;
+      pn = sa.x[lj + 1 < n ? lj + 1 : lj];
+      const double dx = pj.x - pi.x, dy = pj.y - pi.y, dz = pj.z - pi.z;
       const double r2 = dx * dx + dy * dy + dz * dz;
       if (lj != li && r2 < rc2) {
         visit.pair(lj, dx, dy, dz, r2);
@@ -439,18 +450,28 @@ __device__ inline void small_candidates(const CfgInfo& c, const double* sp, cons
     return;
   }
   const float w0 = (float)c.w[0] + 1e-3f, w1 = (float)c.w[1] + 1e-3f, w2 = (float)c.w[2] + 1e-3f;
-  const float fi0 = sf[3 * li], fi1 = sf[3 * li + 1], fi2 = sf[3 * li + 2];
-  const int mi0 = sm[3 * li], mi1 = sm[3 * li + 1], mi2 = sm[3 * li + 2];
+  const float4 ui = sa.u[li];
+  const int4 mi = sa.mz[li];
   if (w0 < 0.5f && w1 < 0.5f && w2 < 0.5f) {
+    // the records of atom lj + 1 are read while lj is tested (LDS latency)
+    float4 un = sa.u[0];
+    int4 mn = sa.mz[0];
+    double4 pn = sa.x[0];
     for (int lj = 0; lj < n; ++lj) {
-      const float s0 = sf[3 * lj] - fi0, s1 = sf[3 * lj + 1] - fi1, s2 = sf[3 * lj + 2] - fi2;
+      const float4 uj = un;
+      const int4 mj = mn;
+      const double4 pj = pn;
+      const int ln = lj + 1 < n ? lj + 1 : lj;
+      un = sa.u[ln];
+      mn = sa.mz[ln];
+      pn = sa.x[ln];
+      const float s0 = uj.x - ui.x, s1 = uj.y - ui.y, s2 = uj.z - ui.z;
       const float r0 = rintf(s0), r1 = rintf(s1), r2f = rintf(s2);
       if (fabsf(s0 - r0) > w0 || fabsf(s1 - r1) > w1 || fabsf(s2 - r2f) > w2) continue;
       // n = n' - m_j + m_i with n' = -rint(u_j - u_i)
-      const int n0 = -(int)r0 + mi0 - sm[3 * lj], n1 = -(int)r1 + mi1 - sm[3 * lj + 1],
-                n2 = -(int)r2f + mi2 - sm[3 * lj + 2];
+      const int n0 = -(int)r0 + mi.x - mj.x, n1 = -(int)r1 + mi.y - mj.y, n2 = -(int)r2f + mi.z - mj.z;
       if (lj == li && n0 == 0 && n1 == 0 && n2 == 0) continue;
-      const double dx = sp[3 * lj] - xi, dy = sp[3 * lj + 1] - yi, dz = sp[3 * lj + 2] - zi;
+      const double dx = pj.x - pi.x, dy = pj.y - pi.y, dz = pj.z - pi.z;
       const double rx = dx + ((double)n0 * L[0] + (double)n1 * L[3] + (double)n2 * L[6]);
       const double ry = dy + ((double)n0 * L[1] + (double)n1 * L[4] + (double)n2 * L[7]);
       const double rz = dz + ((double)n0 * L[2] + (double)n1 * L[5] + (double)n2 * L[8]);
@@ -463,14 +484,17 @@ __device__ inline void small_candidates(const CfgInfo& c, const double* sp, cons
     return;
   }
   for (int lj = 0; lj < n; ++lj) {
-    const float s0 = sf[3 * lj] - fi0, s1 = sf[3 * lj + 1] - fi1, s2 = sf[3 * lj + 2] - fi2;
+    const float4 uj = sa.u[lj];
+    const float s0 = uj.x - ui.x, s1 = uj.y - ui.y, s2 = uj.z - ui.z;
     if (fabsf(s0 - rintf(s0)) > w0 || fabsf(s1 - rintf(s1)) > w1 || fabsf(s2 - rintf(s2)) > w2) continue;
     const int lo0 = -(int)floorf(w0 + s0), hi0 = (int)floorf(w0 - s0);
     const int lo1 = -(int)floorf(w1 + s1), hi1 = (int)floorf(w1 - s1);
     const int lo2 = -(int)floorf(w2 + s2), hi2 = (int)floorf(w2 - s2);
-    const double dx = sp[3 * lj] - xi, dy = sp[3 * lj + 1] - yi, dz = sp[3 * lj + 2] - zi;
+    const double4 pj = sa.x[lj];
+    const double dx = pj.x - pi.x, dy = pj.y - pi.y, dz = pj.z - pi.z;
     // n = n' - m_j + m_i
-    const int o0 = mi0 - sm[3 * lj], o1 = mi1 - sm[3 * lj + 1], o2 = mi2 - sm[3 * lj + 2];
+    const int4 mj = sa.mz[lj];
+    const int o0 = mi.x - mj.x, o1 = mi.y - mj.y, o2 = mi.z - mj.z;
     int k = 0;
     for (int n0 = lo0 + o0; n0 <= hi0 + o0; ++n0)
       for (int n1 = lo1 + o1; n1 <= hi1 + o1; ++n1)
@@ -494,7 +518,7 @@ __device__ inline void small_candidates(const CfgInfo& c, const double* sp, cons
 struct SmallEmit {
   const NbrArgs& a;
   int64_t i, start;
-  const int32_t* sz;
+  const int4* mz;
   int32_t* row;
   int16_t* my_starts;   // global run-start row (null when the LDS lists are used)
   uint8_t* lds_row;     // LDS list of local neighbour indices (null otherwise)
@@ -503,7 +527,7 @@ struct SmallEmit {
   __device__ void pair(int lj, double rx, double ry, double rz, double r2) {
     if (count < a.K) {
       row[count] = (int32_t)(start + lj);
-      store_pair(a, (size_t)count * a.stride + i, rx, ry, rz, sz[lj]);
+      store_pair(a, (size_t)count * a.stride + i, rx, ry, rz, mz[lj].w);
       if (lds_row) lds_row[count] = (uint8_t)lj;
     }
     if (r2 < rmin2) ++below;
@@ -516,37 +540,39 @@ struct SmallEmit {
 };
 
 __global__ void __launch_bounds__(kSmallBlock) search_small_kernel(NbrArgs a, int lds_lists) {
-  __shared__ double sp[3 * kSmallMax];
-  __shared__ float sf[3 * kSmallMax];
-  __shared__ int32_t sm[3 * kSmallMax];
-  __shared__ int32_t sz[kSmallMax];
+  __shared__ double4 sx[kSmallMax];
+  __shared__ float4 su[kSmallMax];
+  __shared__ int4 smz[kSmallMax];
   __shared__ int32_t scount[kSmallMax];
   __shared__ unsigned long long red[5];
-  extern __shared__ uint8_t lists[];   // [kSmallMax][K] when lds_lists
+  extern __shared__ uint8_t lists[];   // [kSmallMax][K + 4] when lds_lists
   const CfgInfo c = a.cfg[blockIdx.x];
   if (!is_small(c)) return;
   const int t = threadIdx.x;
   const int n = c.n;
-  const int KL = a.K;
+  const int KL = a.K + 4;   // row pitch in bytes: rows of consecutive atoms fall in different banks
   if (t < 5) red[t] = 0;
-  for (int q = t; q < 3 * n; q += blockDim.x) sp[q] = a.pos[3 * c.start + q];
   int bad = 0;
   for (int q = t; q < n; q += blockDim.x) {
-    const int z = a.species[c.start + q];
-    if (z < 0 || z >= a.n_species) bad = 1;
-    sz[q] = z < 0 ? 0 : (z >= a.n_species ? a.n_species - 1 : z);
+    const size_t g = (size_t)(c.start + q);
+    const double x = a.pos[3 * g], y = a.pos[3 * g + 1], z = a.pos[3 * g + 2];
+    sx[q] = make_double4(x, y, z, 0.0);
+    const int zs = a.species[g];
+    if (zs < 0 || zs >= a.n_species) bad = 1;
+    int m[3] = {0, 0, 0};
+    float u[3] = {0.f, 0.f, 0.f};
+    if (c.pbc)
+      for (int d = 0; d < 3; ++d) {
+        const double f = x * c.inv[0 * 3 + d] + y * c.inv[1 * 3 + d] + z * c.inv[2 * 3 + d];
+        const double fl = floor(f);
+        u[d] = (float)(f - fl);
+        m[d] = (int32_t)fl;
+      }
+    su[q] = make_float4(u[0], u[1], u[2], 0.f);
+    smz[q] = make_int4(m[0], m[1], m[2], zs < 0 ? 0 : (zs >= a.n_species ? a.n_species - 1 : zs));
   }
   __syncthreads();
-  if (c.pbc)
-    for (int q = t; q < n; q += blockDim.x)
-      for (int d = 0; d < 3; ++d) {
-        const double f = sp[3 * q] * c.inv[0 * 3 + d] + sp[3 * q + 1] * c.inv[1 * 3 + d] +
-                         sp[3 * q + 2] * c.inv[2 * 3 + d];
-        const double fl = floor(f);
-        sf[3 * q + d] = (float)(f - fl);
-        sm[3 * q + d] = (int32_t)fl;
-      }
-  __syncthreads();
+  const SmallAtoms sa{sx, su, smz};
   const double rc2 = a.rcut * a.rcut;
   // global run starts of this configuration: rows of n int16 at the config's atom offset
   int16_t* run_start = a.run_start + (size_t)c.start * kSmallMax;
@@ -554,10 +580,10 @@ __global__ void __launch_bounds__(kSmallBlock) search_small_kernel(NbrArgs a, in
   int count = 0, below = 0;
   if (li < n) {
     const int64_t i = c.start + li;
-    SmallEmit em{a, i, c.start, sz, a.nbr_row + (size_t)i * a.K,
+    SmallEmit em{a, i, c.start, smz, a.nbr_row + (size_t)i * a.K,
                  lds_lists ? nullptr : run_start + (size_t)li * n,
                  lds_lists ? lists + (size_t)li * KL : nullptr, a.rmin * a.rmin};
-    small_candidates(c, sp, sf, sm, n, li, rc2, em);
+    small_candidates(c, sa, n, li, rc2, em);
     count = em.count;
     below = em.below;
     a.count[i] = count < a.K ? count : a.K;
@@ -631,7 +657,7 @@ hipError_t nbr_build(NbrArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(bin_fill_kernel, grid_for(a.n_atoms), dim3(kBlock), 0, s, a);
   hipLaunchKernelGGL(bin_sort_kernel, grid_for(a.n_atoms), dim3(kBlock), 0, s, a);
   const int lds_lists = a.K <= kLdsSlots ? 1 : 0;
-  const size_t lds = lds_lists ? (size_t)kSmallMax * a.K : 0;
+  const size_t lds = lds_lists ? (size_t)kSmallMax * (a.K + 4) : 0;
   if (a.n_cfg > 0) hipLaunchKernelGGL(search_small_kernel, dim3(a.n_cfg), dim3(kSmallBlock), lds, s, a, lds_lists);
   hipLaunchKernelGGL(search_kernel, grid_for(a.n_atoms), dim3(kBlock), 0, s, a);
   const dim3 g((unsigned)((a.n_atoms + kBlock - 1) / kBlock), (unsigned)a.K);
