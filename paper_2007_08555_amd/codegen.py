@@ -570,7 +570,7 @@ LOSS_PAIR_HEAD = r"""
     const mtp::PairRec<T> q = args.pr[e];
     const T x = q.x, y = q.y, z = q.z;
     const int zj = q.zj;
-    const int j = la.nbr_row[(size_t)i * la.K + p];
+    const int j = la.nbr[(size_t)p * args.stride + i];
     // delta r_ij = u_j - u_i + eps r_ij
     const T dx = la.u[3 * (size_t)j] - ux + (e00 * x + e01 * y + e02 * z);
     const T dy = la.u[3 * (size_t)j + 1] - uy + (e10 * x + e11 * y + e12 * z);

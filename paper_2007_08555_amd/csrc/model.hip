@@ -99,7 +99,7 @@ struct mtp_model {
   Buffer ainv, gj_work, gj_flag;
   // workspace
   Buffer cfg, atom_cfg, atom_bin, bin_count, bin_start, bin_atoms, bin_fill, nbins_dev;
-  Buffer count, nbr_row, pr, rev, gpair, Mbuf, Gbuf, Dbuf, site, wv, B, status, run_start;
+  Buffer count, nbr, pr, rev, gpair, Mbuf, Gbuf, Dbuf, site, wv, B, status, run_start;
   int K = 64;  // neighbour capacity per atom, grown on overflow
   Buffer b_tmp, c_tmp;
   int last_stride = 0;
@@ -363,7 +363,7 @@ int run_eval(mtp_model* M, const mtp_batch* bt, const mtp_out* out, int precisio
     const int K = M->K;
     const size_t slots = (size_t)K * stride;
     if (slots >= (size_t)0x7fffffff) return fail(MTP_E_CAPACITY, "neighbour slots exceed 2^31 (split the batch)");
-    NEED(M->nbr_row, sizeof(int32_t) * (size_t)K * (N + 1));
+    NEED(M->nbr, sizeof(int32_t) * slots);
     NEED(M->rev, sizeof(int32_t) * slots);
     NEED(M->pr, (fp64 ? sizeof(PairRec<double>) : sizeof(PairRec<float>)) * slots);
     NEED(M->gpair, tsz * 3 * slots);
@@ -398,7 +398,7 @@ int run_eval(mtp_model* M, const mtp_batch* bt, const mtp_out* out, int precisio
     a.count = M->count.as<int32_t>();
     a.stride = stride;
     a.K = K;
-    a.nbr_row = M->nbr_row.as<int32_t>();
+    a.nbr = M->nbr.as<int32_t>();
     a.pr = M->pr.p;
     a.fp64 = fp64 ? 1 : 0;
     a.rev = M->rev.as<int32_t>();
@@ -663,7 +663,7 @@ int mtp_loss_grad(mtp_model* M, const mtp_batch* bt, const double* E_t, const do
     la.a_atom = M->lo_a.as<T>();
     la.u = M->lo_u.as<T>();
     la.eps_atom = M->lo_eps.as<T>();
-    la.nbr_row = M->nbr_row.as<int>();
+    la.nbr = M->nbr.as<int>();
     la.K = K;
     la.dM = M->lo_dM.as<T>();
     la.dG = M->lo_dG.as<T>();

@@ -136,7 +136,7 @@ struct LossArgs {
   const T* a_atom;     // [n_atoms] a_k = 2 w_e (E_k - E_k^t) of the atom's configuration
   const T* u;          // [n_atoms][3] u_i = -2 w_f (F_i - F_i^t)
   const T* eps_atom;   // [9][stride] eps_k = 2 w_s (W_k - W_k^t) of the atom's configuration
-  const int* nbr_row;  // [n_atoms][K] neighbour home indices
+  const int* nbr;      // [K * stride] neighbour home index of slot p of atom i at p * stride + i
   int K;
   T* dM;               // [C][stride] tangent of the moments along delta r
   T* dG;               // [C][stride] tangent of G = dV/dM

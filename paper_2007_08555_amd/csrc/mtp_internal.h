@@ -49,7 +49,7 @@ struct NbrArgs {
   int32_t* count;        // [n_atoms] neighbours per atom (clamped to K)
   int stride;            // ELL pitch (>= n_atoms)
   int K;                 // ELL slots per atom
-  int32_t* nbr_row;      // [n_atoms][K] neighbour home index, row-major per atom
+  int32_t* nbr;          // [K * stride] neighbour home index of slot p of atom i at p * stride + i
   void* pr;              // [K * stride] PairRec<double> or PairRec<float>
   int fp64;              // pair record type
   int32_t* rev;          // [K * stride] ELL index of the reverse pair

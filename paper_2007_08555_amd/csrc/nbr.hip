@@ -249,7 +249,7 @@ struct Emitter {
       const size_t e = (size_t)count * a.stride + i;
       int zj = a.species[j];
       zj = zj < 0 ? 0 : (zj >= a.n_species ? a.n_species - 1 : zj);
-      a.nbr_row[(size_t)i * a.K + count] = j;
+      a.nbr[e] = j;
       store_pair(a, e, rx, ry, rz, zj);
     }
     if (r2 < rmin2) ++below;
@@ -360,14 +360,14 @@ __global__ void reverse_kernel(NbrArgs a, int small_done) {
   if (i >= a.n_atoms || p >= a.count[i]) return;
   const CfgInfo& c = a.cfg[a.atom_cfg[i]];
   if (!in_cfg(c, i) || (small_done && is_small(c))) return;
-  const size_t e = (size_t)p * a.stride + i;
-  const int32_t* row_i = a.nbr_row + (size_t)i * a.K;
+  const size_t st = (size_t)a.stride;
+  const size_t e = (size_t)p * st + i;
   const int ci = a.count[i];
-  const int32_t j = row_i[p];
+  const int32_t j = a.nbr[e];
   int rank = 0;
-  while (p - rank - 1 >= 0 && row_i[p - rank - 1] == j) ++rank;
+  while (p - rank - 1 >= 0 && a.nbr[(size_t)(p - rank - 1) * st + i] == j) ++rank;
   int after = 0;
-  while (p + after + 1 < ci && row_i[p + after + 1] == j) ++after;
+  while (p + after + 1 < ci && a.nbr[(size_t)(p + after + 1) * st + i] == j) ++after;
   const int k = rank + 1 + after;
   const int cj = a.count[j];
   int q0 = -1;
@@ -376,22 +376,21 @@ __global__ void reverse_kernel(NbrArgs a, int small_done) {
     const int li = (int)(i - c.start), lj = (int)(j - c.start);
     if (lj >= 0 && lj < n) q0 = a.run_start[(size_t)c.start * kSmallMax + (size_t)lj * n + li];
   } else {
-    const int32_t* row_j = a.nbr_row + (size_t)j * a.K;
     int lo = 0;
     if (c.binned) {
-      while (lo < cj && row_j[lo] != (int32_t)i) ++lo;        // one image per atom
+      while (lo < cj && a.nbr[(size_t)lo * st + j] != (int32_t)i) ++lo;   // one image per atom
     } else {
-      int hi = cj;                                             // rows ascend in neighbour index
+      int hi = cj;                                                      // lists ascend in neighbour index
       while (lo < hi) {
         const int mid = (lo + hi) >> 1;
-        if (row_j[mid] < (int32_t)i) lo = mid + 1; else hi = mid;
+        if (a.nbr[(size_t)mid * st + j] < (int32_t)i) lo = mid + 1; else hi = mid;
       }
     }
     q0 = lo;
   }
   const int q = q0 + k - 1 - rank;
-  if (q0 >= 0 && q < cj && a.nbr_row[(size_t)j * a.K + q] == (int32_t)i) {
-    a.rev[e] = (int32_t)((size_t)q * a.stride + j);
+  if (q0 >= 0 && q < cj && a.nbr[(size_t)q * st + j] == (int32_t)i) {
+    a.rev[e] = (int32_t)((size_t)q * st + j);
   } else {
     a.rev[e] = (int32_t)e;
     atomicAdd(&a.status->list_errors, 1ull);
@@ -409,17 +408,19 @@ __global__ void reverse_kernel(NbrArgs a, int small_done) {
 // rejected at once when the nearest integer to u_j - u_i is farther than w_d
 // along some direction, otherwise the images of the box are tested with the
 // exact FP64 pair vector.  When every w_d < 1/2 the box holds at most that
-// nearest integer, and no loop over images is needed.  u_j - u_i changes
-// sign exactly when i and j swap, so the box of (j, i) is the negated box of
-// (i, j).
+// nearest integer ("nearest" cells).  u_j - u_i changes sign exactly when i
+// and j swap, so the box of (j, i) is the negated box of (i, j).
 //
+// With neighbour capacity K <= kLdsSlots the lists are built in LDS first
+// (one byte per slot: the neighbour's index in the configuration); after a
+// barrier a write-out pass forms each slot's pair vector again and stores the
+// pair record, the neighbour index and the reverse index at p * stride + i,
+// so that the threads of a wavefront store consecutive records of one slot.
 // Reverse indices: the r-th of the k images in i's run of j is reversed by
-// entry q0 + k - 1 - r of j's list, q0 the start of j's run of i.  With
-// neighbour capacity K <= kLdsSlots the lists are also kept in LDS as local
-// indices (one byte each) and, after a barrier, every thread finds q0 by a
-// binary search of j's LDS list, so the workgroup issues no global load after
-// its first global store.  With a larger K the search records run starts in
-// a global table (run_start[i][j]) and reverse_kernel reads them.
+// entry q0 + k - 1 - r of j's list, q0 the start of j's run of i, found by a
+// binary search of j's LDS list.  With a larger K the search writes the
+// records directly and records run starts in a global table
+// (run_start[i][j]) that reverse_kernel reads.
 constexpr int kLdsSlots = 128;
 
 // Per-atom LDS records of the small search: FP64 position, FP32 wrapped
@@ -430,16 +431,66 @@ struct SmallAtoms {
   int4* mz;    // (m0, m1, m2, species)
 };
 
+__device__ inline bool nearest_cell(const CfgInfo& c) {
+  return c.pbc && c.w[0] + 1e-3 < 0.5 && c.w[1] + 1e-3 < 0.5 && c.w[2] + 1e-3 < 0.5;
+}
+
+// Images of atom lj within R_cut of atom li in a periodic cell, in box order:
+// visit(rx, ry, rz, r2) for each.  Returns false when the box is empty.
+template <typename F>
+__device__ inline bool box_images(const CfgInfo& c, const SmallAtoms& sa, int li, int lj, double rc2, F&& visit) {
+  const float w0 = (float)c.w[0] + 1e-3f, w1 = (float)c.w[1] + 1e-3f, w2 = (float)c.w[2] + 1e-3f;
+  const float4 ui = sa.u[li], uj = sa.u[lj];
+  const float s0 = uj.x - ui.x, s1 = uj.y - ui.y, s2 = uj.z - ui.z;
+  if (fabsf(s0 - rintf(s0)) > w0 || fabsf(s1 - rintf(s1)) > w1 || fabsf(s2 - rintf(s2)) > w2) return false;
+  const int lo0 = -(int)floorf(w0 + s0), hi0 = (int)floorf(w0 - s0);
+  const int lo1 = -(int)floorf(w1 + s1), hi1 = (int)floorf(w1 - s1);
+  const int lo2 = -(int)floorf(w2 + s2), hi2 = (int)floorf(w2 - s2);
+  const double4 pi = sa.x[li], pj = sa.x[lj];
+  const double dx = pj.x - pi.x, dy = pj.y - pi.y, dz = pj.z - pi.z;
+  // n = n' - m_j + m_i
+  const int4 mi = sa.mz[li], mj = sa.mz[lj];
+  const int o0 = mi.x - mj.x, o1 = mi.y - mj.y, o2 = mi.z - mj.z;
+  const double* L = c.L;
+  for (int n0 = lo0 + o0; n0 <= hi0 + o0; ++n0)
+    for (int n1 = lo1 + o1; n1 <= hi1 + o1; ++n1)
+      for (int n2 = lo2 + o2; n2 <= hi2 + o2; ++n2) {
+        if (lj == li && n0 == 0 && n1 == 0 && n2 == 0) continue;
+        const double sx = (double)n0 * L[0] + (double)n1 * L[3] + (double)n2 * L[6];
+        const double sy = (double)n0 * L[1] + (double)n1 * L[4] + (double)n2 * L[7];
+        const double sz = (double)n0 * L[2] + (double)n1 * L[5] + (double)n2 * L[8];
+        const double rx = dx + sx, ry = dy + sy, rz = dz + sz;
+        const double r2 = rx * rx + ry * ry + rz * rz;
+        if (r2 < rc2) visit(rx, ry, rz, r2);
+      }
+  return true;
+}
+
+// The pair vector of atom lj's nearest image for atom li in a nearest cell.
+__device__ inline void nearest_vector(const CfgInfo& c, const SmallAtoms& sa, int li, int lj, double& rx, double& ry,
+                                      double& rz) {
+  const float4 ui = sa.u[li], uj = sa.u[lj];
+  const int4 mi = sa.mz[li], mj = sa.mz[lj];
+  const double4 pi = sa.x[li], pj = sa.x[lj];
+  // n = n' - m_j + m_i with n' = -rint(u_j - u_i)
+  const int n0 = -(int)rintf(uj.x - ui.x) + mi.x - mj.x;
+  const int n1 = -(int)rintf(uj.y - ui.y) + mi.y - mj.y;
+  const int n2 = -(int)rintf(uj.z - ui.z) + mi.z - mj.z;
+  const double* L = c.L;
+  rx = (pj.x - pi.x) + ((double)n0 * L[0] + (double)n1 * L[3] + (double)n2 * L[6]);
+  ry = (pj.y - pi.y) + ((double)n0 * L[1] + (double)n1 * L[4] + (double)n2 * L[7]);
+  rz = (pj.z - pi.z) + ((double)n0 * L[2] + (double)n1 * L[5] + (double)n2 * L[8]);
+}
+
+// All neighbours of atom li in list order: visit.pair(lj, r, r2) per entry,
+// visit.run_end(lj, k) after the k images of each neighbour.
 template <typename Visit>
 __device__ inline void small_candidates(const CfgInfo& c, const SmallAtoms& sa, int n, int li, double rc2,
                                         Visit&& visit) {
   const double4 pi = sa.x[li];
-  const double* L = c.L;
   if (!c.pbc) {
-    double4 pn = sa.x[0];
     for (int lj = 0; lj < n; ++lj) {
-      const double4 pj = pn;
-      pn = sa.x[lj + 1 < n ? lj + 1 : lj];
+      const double4 pj = sa.x[lj];
       const double dx = pj.x - pi.x, dy = pj.y - pi.y, dz = pj.z - pi.z;
       const double r2 = dx * dx + dy * dy + dz * dz;
       if (lj != li && r2 < rc2) {
@@ -449,92 +500,132 @@ __device__ inline void small_candidates(const CfgInfo& c, const SmallAtoms& sa, 
     }
     return;
   }
-  const float w0 = (float)c.w[0] + 1e-3f, w1 = (float)c.w[1] + 1e-3f, w2 = (float)c.w[2] + 1e-3f;
-  const float4 ui = sa.u[li];
-  const int4 mi = sa.mz[li];
-  if (w0 < 0.5f && w1 < 0.5f && w2 < 0.5f) {
-    // the records of atom lj + 1 are read while lj is tested (LDS latency)
-    float4 un = sa.u[0];
-    int4 mn = sa.mz[0];
-    double4 pn = sa.x[0];
-    for (int lj = 0; lj < n; ++lj) {
-      const float4 uj = un;
-      const int4 mj = mn;
-      const double4 pj = pn;
-      const int ln = lj + 1 < n ? lj + 1 : lj;
-      un = sa.u[ln];
-      mn = sa.mz[ln];
-      pn = sa.x[ln];
-      const float s0 = uj.x - ui.x, s1 = uj.y - ui.y, s2 = uj.z - ui.z;
-      const float r0 = rintf(s0), r1 = rintf(s1), r2f = rintf(s2);
-      if (fabsf(s0 - r0) > w0 || fabsf(s1 - r1) > w1 || fabsf(s2 - r2f) > w2) continue;
-      // n = n' - m_j + m_i with n' = -rint(u_j - u_i)
-      const int n0 = -(int)r0 + mi.x - mj.x, n1 = -(int)r1 + mi.y - mj.y, n2 = -(int)r2f + mi.z - mj.z;
-      if (lj == li && n0 == 0 && n1 == 0 && n2 == 0) continue;
-      const double dx = pj.x - pi.x, dy = pj.y - pi.y, dz = pj.z - pi.z;
-      const double rx = dx + ((double)n0 * L[0] + (double)n1 * L[3] + (double)n2 * L[6]);
-      const double ry = dy + ((double)n0 * L[1] + (double)n1 * L[4] + (double)n2 * L[7]);
-      const double rz = dz + ((double)n0 * L[2] + (double)n1 * L[5] + (double)n2 * L[8]);
-      const double r2 = rx * rx + ry * ry + rz * rz;
-      if (r2 < rc2) {
-        visit.pair(lj, rx, ry, rz, r2);
-        visit.run_end(lj, 1);
-      }
-    }
-    return;
-  }
   for (int lj = 0; lj < n; ++lj) {
-    const float4 uj = sa.u[lj];
-    const float s0 = uj.x - ui.x, s1 = uj.y - ui.y, s2 = uj.z - ui.z;
-    if (fabsf(s0 - rintf(s0)) > w0 || fabsf(s1 - rintf(s1)) > w1 || fabsf(s2 - rintf(s2)) > w2) continue;
-    const int lo0 = -(int)floorf(w0 + s0), hi0 = (int)floorf(w0 - s0);
-    const int lo1 = -(int)floorf(w1 + s1), hi1 = (int)floorf(w1 - s1);
-    const int lo2 = -(int)floorf(w2 + s2), hi2 = (int)floorf(w2 - s2);
-    const double4 pj = sa.x[lj];
-    const double dx = pj.x - pi.x, dy = pj.y - pi.y, dz = pj.z - pi.z;
-    // n = n' - m_j + m_i
-    const int4 mj = sa.mz[lj];
-    const int o0 = mi.x - mj.x, o1 = mi.y - mj.y, o2 = mi.z - mj.z;
     int k = 0;
-    for (int n0 = lo0 + o0; n0 <= hi0 + o0; ++n0)
-      for (int n1 = lo1 + o1; n1 <= hi1 + o1; ++n1)
-        for (int n2 = lo2 + o2; n2 <= hi2 + o2; ++n2) {
-          if (lj == li && n0 == 0 && n1 == 0 && n2 == 0) continue;
-          const double sx = (double)n0 * L[0] + (double)n1 * L[3] + (double)n2 * L[6];
-          const double sy = (double)n0 * L[1] + (double)n1 * L[4] + (double)n2 * L[7];
-          const double sz = (double)n0 * L[2] + (double)n1 * L[5] + (double)n2 * L[8];
-          const double rx = dx + sx, ry = dy + sy, rz = dz + sz;
-          const double r2 = rx * rx + ry * ry + rz * rz;
-          if (r2 < rc2) {
-            visit.pair(lj, rx, ry, rz, r2);
-            ++k;
-          }
-        }
+    box_images(c, sa, li, lj, rc2, [&](double rx, double ry, double rz, double r2) {
+      visit.pair(lj, rx, ry, rz, r2);
+      ++k;
+    });
     if (k > 0) visit.run_end(lj, k);
   }
 }
 
-// Lists, run starts (global table or LDS list) and counters of one atom.
+// Two-phase list of one atom for free clusters and nearest cells: phase A
+// walks all atoms j with the cheap test only (FP64 distance of a cluster, or
+// the FP32 nearest-image box and distance) and records the candidates j in
+// the atom's LDS row; phase B tests only the candidates with the exact FP64 pair vector and
+// rewrites the row in place (kept entries never outrun the candidates).
+// Returns the candidate count (> K means the row overflowed).
+template <typename Visit>
+__device__ inline int small_two_phase(const CfgInfo& c, const SmallAtoms& sa, int n, int li, double rc2, int K,
+                                      uint8_t* row, Visit&& visit) {
+  const double4 pi = sa.x[li];
+  int nc = 0;
+  if (!c.pbc) {
+    for (int lj = 0; lj < n; ++lj) {
+      const double4 pj = sa.x[lj];
+      const double dx = pj.x - pi.x, dy = pj.y - pi.y, dz = pj.z - pi.z;
+      const double r2 = dx * dx + dy * dy + dz * dz;
+      if (lj != li && r2 < rc2) {
+        if (nc < K) row[nc] = (uint8_t)lj;
+        ++nc;
+      }
+    }
+    const int m = nc < K ? nc : K;
+    for (int q = 0; q < m; ++q) {
+      const int lj = row[q];
+      const double4 pj = sa.x[lj];
+      const double dx = pj.x - pi.x, dy = pj.y - pi.y, dz = pj.z - pi.z;
+      visit.pair(lj, dx, dy, dz, dx * dx + dy * dy + dz * dz);
+    }
+    return nc;
+  }
+  const float w0 = (float)c.w[0] + 1e-3f, w1 = (float)c.w[1] + 1e-3f, w2 = (float)c.w[2] + 1e-3f;
+  const float4 ui = sa.u[li];
+  // FP32 estimate of the nearest-image distance, with a margin far above its
+  // rounding error, so that nearly every candidate is a neighbour
+  float Lf[9];
+  for (int t = 0; t < 9; ++t) Lf[t] = (float)c.L[t];
+  const float rcm = (float)sqrt(rc2) + 1e-3f, rcm2 = rcm * rcm;
+  for (int lj = 0; lj < n; ++lj) {
+    const float4 uj = sa.u[lj];
+    const float s0 = uj.x - ui.x, s1 = uj.y - ui.y, s2 = uj.z - ui.z;
+    const float f0 = s0 - rintf(s0), f1 = s1 - rintf(s1), f2 = s2 - rintf(s2);
+    // the atom's own nearest image is itself (n = 0) and no other image is in range
+    if (lj == li || fabsf(f0) > w0 || fabsf(f1) > w1 || fabsf(f2) > w2) continue;
+    const float x = f0 * Lf[0] + f1 * Lf[3] + f2 * Lf[6];
+    const float y = f0 * Lf[1] + f1 * Lf[4] + f2 * Lf[7];
+    const float z = f0 * Lf[2] + f1 * Lf[5] + f2 * Lf[8];
+    if (x * x + y * y + z * z > rcm2) continue;
+    if (nc < K) row[nc] = (uint8_t)lj;
+    ++nc;
+  }
+  const int m = nc < K ? nc : K;
+  for (int q = 0; q < m; ++q) {
+    const int lj = row[q];
+    double rx, ry, rz;
+    nearest_vector(c, sa, li, lj, rx, ry, rz);
+    const double r2 = rx * rx + ry * ry + rz * rz;
+    if (r2 < rc2) visit.pair(lj, rx, ry, rz, r2);
+  }
+  return nc;
+}
+
+// LDS list of one atom: local neighbour index per slot, counters.
+struct LdsCollect {
+  uint8_t* row;
+  int K;
+  double rmin2;
+  int count = 0, below = 0;
+  __device__ void pair(int lj, double, double, double, double r2) {
+    if (count < K) row[count] = (uint8_t)lj;
+    if (r2 < rmin2) ++below;
+    ++count;
+  }
+  __device__ void run_end(int, int) {}
+};
+
+// LDS list plus direct records of one atom (periodic cells with several
+// images per neighbour, whose write-out would have to enumerate boxes again).
+struct LdsAndRecords {
+  const NbrArgs& a;
+  int64_t i, start;
+  const int4* mz;
+  uint8_t* row;
+  double rmin2;
+  int count = 0, below = 0;
+  __device__ void pair(int lj, double rx, double ry, double rz, double r2) {
+    if (count < a.K) {
+      const size_t e = (size_t)count * a.stride + i;
+      a.nbr[e] = (int32_t)(start + lj);
+      store_pair(a, e, rx, ry, rz, mz[lj].w);
+      row[count] = (uint8_t)lj;
+    }
+    if (r2 < rmin2) ++below;
+    ++count;
+  }
+  __device__ void run_end(int, int) {}
+};
+
+// Direct lists (K > kLdsSlots): records, neighbour indices and run starts.
 struct SmallEmit {
   const NbrArgs& a;
   int64_t i, start;
   const int4* mz;
-  int32_t* row;
-  int16_t* my_starts;   // global run-start row (null when the LDS lists are used)
-  uint8_t* lds_row;     // LDS list of local neighbour indices (null otherwise)
+  int16_t* my_starts;
   double rmin2;
   int count = 0, below = 0, before = 0;
   __device__ void pair(int lj, double rx, double ry, double rz, double r2) {
     if (count < a.K) {
-      row[count] = (int32_t)(start + lj);
-      store_pair(a, (size_t)count * a.stride + i, rx, ry, rz, mz[lj].w);
-      if (lds_row) lds_row[count] = (uint8_t)lj;
+      const size_t e = (size_t)count * a.stride + i;
+      a.nbr[e] = (int32_t)(start + lj);
+      store_pair(a, e, rx, ry, rz, mz[lj].w);
     }
     if (r2 < rmin2) ++below;
     ++count;
   }
   __device__ void run_end(int lj, int) {
-    if (my_starts && before < a.K) my_starts[lj] = (int16_t)before;
+    if (before < a.K) my_starts[lj] = (int16_t)before;
     before = count;
   }
 };
@@ -574,18 +665,36 @@ __global__ void __launch_bounds__(kSmallBlock) search_small_kernel(NbrArgs a, in
   __syncthreads();
   const SmallAtoms sa{sx, su, smz};
   const double rc2 = a.rcut * a.rcut;
-  // global run starts of this configuration: rows of n int16 at the config's atom offset
+  const double rmin2 = a.rmin * a.rmin;
+  const bool nearest = nearest_cell(c);
+  // global run starts (direct lists): rows of n int16 at the config's atom offset
   int16_t* run_start = a.run_start + (size_t)c.start * kSmallMax;
   const int li = t;
   int count = 0, below = 0;
   if (li < n) {
     const int64_t i = c.start + li;
-    SmallEmit em{a, i, c.start, smz, a.nbr_row + (size_t)i * a.K,
-                 lds_lists ? nullptr : run_start + (size_t)li * n,
-                 lds_lists ? lists + (size_t)li * KL : nullptr, a.rmin * a.rmin};
-    small_candidates(c, sa, n, li, rc2, em);
-    count = em.count;
-    below = em.below;
+    if (lds_lists) {
+      uint8_t* row = lists + (size_t)li * KL;
+      LdsCollect col{row, a.K, rmin2};
+      if (!c.pbc || nearest) {
+        const int nc = small_two_phase(c, sa, n, li, rc2, a.K, row, col);
+        // a candidate overflow is reported like a neighbour overflow (the
+        // call is repeated with capacity for every candidate)
+        if (nc > a.K && col.count <= a.K) col.count = nc;
+        count = col.count;
+        below = col.below;
+      } else {
+        LdsAndRecords em{a, i, c.start, smz, row, rmin2};
+        small_candidates(c, sa, n, li, rc2, em);
+        count = em.count;
+        below = em.below;
+      }
+    } else {
+      SmallEmit em{a, i, c.start, smz, run_start + (size_t)li * n, rmin2};
+      small_candidates(c, sa, n, li, rc2, em);
+      count = em.count;
+      below = em.below;
+    }
     a.count[i] = count < a.K ? count : a.K;
     scount[li] = count < a.K ? count : a.K;
   }
@@ -604,15 +713,33 @@ __global__ void __launch_bounds__(kSmallBlock) search_small_kernel(NbrArgs a, in
     if (red[4]) atomicAdd(&a.status->bad_species, red[4]);
   }
   if (!lds_lists || li >= n || red[2]) return;   // on overflow the call is repeated with more slots
+  // write-out: slot by slot, consecutive atoms store consecutive records
+  // (cells with several images per neighbour stored theirs in the search)
   const int64_t i = c.start + li;
   const uint8_t* mine = lists + (size_t)li * KL;
   const int ci = scount[li];
+  const bool records = !c.pbc || nearest;
   unsigned long long errs = 0;
-  int p = 0;
-  while (p < ci) {
+  for (int p = 0; p < ci; ++p) {
     const int lj = mine[p];
-    int k = 1;
-    while (p + k < ci && mine[p + k] == lj) ++k;
+    int r = 0, k = 1;
+    const size_t e = (size_t)p * a.stride + i;
+    const int64_t j = c.start + lj;
+    if (records) {
+      double rx, ry, rz;
+      if (!c.pbc) {
+        const double4 pi = sx[li], pj = sx[lj];
+        rx = pj.x - pi.x; ry = pj.y - pi.y; rz = pj.z - pi.z;
+      } else {
+        nearest_vector(c, sa, li, lj, rx, ry, rz);
+      }
+      store_pair(a, e, rx, ry, rz, smz[lj].w);
+      a.nbr[e] = (int32_t)j;
+    } else {
+      // rank of this image in the run of lj, and the run length
+      while (p - r - 1 >= 0 && mine[p - r - 1] == lj) ++r;
+      while (p - r + k < ci && mine[p - r + k] == lj) ++k;
+    }
     // start of the run of li in lj's list (ascending local indices)
     const uint8_t* other = lists + (size_t)lj * KL;
     const int cj = scount[lj];
@@ -621,18 +748,13 @@ __global__ void __launch_bounds__(kSmallBlock) search_small_kernel(NbrArgs a, in
       const int mid = (lo + hi) >> 1;
       if ((int)other[mid] < li) lo = mid + 1; else hi = mid;
     }
-    const int64_t j = c.start + lj;
-    for (int r = 0; r < k; ++r) {
-      const size_t e = (size_t)(p + r) * a.stride + i;
-      const int q = lo + k - 1 - r;
-      if (q < cj && other[q] == (uint8_t)li) {
-        a.rev[e] = (int32_t)((size_t)q * a.stride + j);
-      } else {
-        a.rev[e] = (int32_t)e;
-        ++errs;
-      }
+    const int q = lo + k - 1 - r;
+    if (q < cj && other[q] == (uint8_t)li) {
+      a.rev[e] = (int32_t)((size_t)q * a.stride + j);
+    } else {
+      a.rev[e] = (int32_t)e;
+      ++errs;
     }
-    p += k;
   }
   if (errs) atomicAdd(&a.status->list_errors, errs);
 }

@@ -64,7 +64,10 @@ class Potential:
     def __del__(self):
         h = getattr(self, "_h", None)
         if h is not None and h.value:
-            lib().mtp_free(h)
+            try:
+                lib().mtp_free(h)
+            except Exception:   # interpreter shutdown: the process releases everything
+                pass
             self._h = None
 
     # parameters -------------------------------------------------------
