@@ -873,6 +873,8 @@ def generate(lev_max, block=64):
         lines = []
         groups = [tuple(n for n in grp if n <= s.nu_max) for grp in groups]
         groups = [grp for grp in groups if any(comp_nu[k] in grp for k in range(s.C))]
+        covered = {n for grp in groups for n in grp}
+        groups += [(n,) for n in sorted(set(comp_nu.values()) - covered)]   # higher levels: one pass per degree
         for pidx, grp in enumerate(groups):
             tag = f"{prec}_p{pidx}"
             ks = [k for k in range(s.C) if comp_nu[k] in grp]
