@@ -135,6 +135,12 @@ def main():
         log(f"calibration copy: {a.calib_copy_mib} MiB read, {a.calib_copy_mib} MiB written")
         del src, dst
 
+    # the library's autotuner picks the FP64 pass split for this batch
+    t_at = time.perf_counter()
+    chosen, sched_ms = P.autotune(B, precision=a.precision, repeats=3)
+    log(f"autotune: schedule {chosen} of {len(sched_ms)} ({', '.join(f'{t:.3f}' for t in sched_ms)} ms "
+        f"evaluation kernels), {time.perf_counter() - t_at:.2f} s")
+
     def step():
         out = P.eval(B, precision=a.precision, forces=True, virial=True, energy=True, b=True, stream=stream)
         out["gamma"], out["argmax"] = P.grade_from_b(out["b"], stream=stream)
@@ -209,7 +215,7 @@ def main():
                                    f"{n_atoms} atoms, 1-3 of 3 species, MTP level 16, N_Q 8, R_cut 5 A; "
                                    f"E, F, stress and the extrapolation grade per configuration",
                        "precision": a.precision, "level": 16, "atoms": n_atoms, "configs": a.configs,
-                       "graph_replay": not a.no_graph},
+                       "graph_replay": not a.no_graph, "schedule": chosen, "schedule_ms": sched_ms},
             "roofline": roofline, "eager_ms_per_step": dt_eager * 1e3}
 
     if not a.no_extras:

@@ -82,6 +82,8 @@ typedef struct {
   int32_t n_c;          /* |c| = n_mu * n_species^2 * n_q */
   double r_min;         /* Angstrom */
   double r_cut;         /* Angstrom */
+  int32_t n_schedules;  /* FP64 schedules of the evaluation kernels (mtp_set_schedule) */
+  int32_t reserved;
 } mtp_info;
 
 /*
@@ -199,6 +201,26 @@ int mtp_normal_equations(mtp_model* model, const mtp_batch* batch, const double*
  * `stream`.
  */
 int mtp_solve_normal(mtp_model* model, const double* H_dev, const double* g_dev, double* xi_dev, void* stream);
+
+/*
+ * Schedules of the evaluation kernels.  Level by level the FP64 kernels are
+ * compiled in several schedules: different cuts of the per-atom work
+ * (moments, reverse sweep, adjoint) into passes that fit the register file,
+ * trading recomputation per pair against wavefronts per SIMD.  All compute
+ * the same quantities (they differ only in summation order).  FP32 has one
+ * schedule.
+ *
+ * mtp_set_schedule selects one (MTP_E_ARG for an index outside
+ * 0 .. schedules - 1).  mtp_autotune builds the lists of `batch`, times each
+ * schedule's evaluation kernels `repeats` times with HIP events on `stream`
+ * (after one untimed launch), keeps the fastest for `precision` and returns
+ * its index in *chosen (may be NULL); ms_out[k] (k < n_out, may be NULL)
+ * receives the mean time of schedule k in milliseconds.  Synchronises
+ * `stream`.
+ */
+int mtp_set_schedule(mtp_model* model, int precision, int schedule);
+int mtp_autotune(mtp_model* model, const mtp_batch* batch, int precision, int repeats, float* ms_out, int n_out,
+                 int* chosen, void* stream);
 
 /*
  * Device-side counters of the last mtp_eval on this model: pairs closer than

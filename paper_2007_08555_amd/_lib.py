@@ -37,7 +37,8 @@ class mtp_out(ctypes.Structure):
 class mtp_info(ctypes.Structure):
     _fields_ = [("level", ctypes.c_int32), ("m", ctypes.c_int32), ("n_mu", ctypes.c_int32),
                 ("n_species", ctypes.c_int32), ("n_q", ctypes.c_int32), ("n_c", ctypes.c_int32),
-                ("r_min", ctypes.c_double), ("r_cut", ctypes.c_double)]
+                ("r_min", ctypes.c_double), ("r_cut", ctypes.c_double), ("n_schedules", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class mtp_stats(ctypes.Structure):
@@ -65,6 +66,9 @@ _SIGNATURES = {
                                             ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_int,
                                             ctypes.c_int, _P, _P, _P, _P]),
     "mtp_solve_normal": (ctypes.c_int, [_P, _P, _P, _P, _P]),
+    "mtp_set_schedule": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int]),
+    "mtp_autotune": (ctypes.c_int, [_P, ctypes.POINTER(mtp_batch), ctypes.c_int, ctypes.c_int, _P, ctypes.c_int,
+                                    ctypes.POINTER(ctypes.c_int), _P]),
     "mtp_set_timing": (ctypes.c_int, [_P, ctypes.c_int]),
     "mtp_get_stats": (ctypes.c_int, [_P, ctypes.POINTER(mtp_stats)]),
     "mtp_free": (None, [_P]),

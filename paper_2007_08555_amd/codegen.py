@@ -797,39 +797,28 @@ hipError_t launch_loss(int precision, const void* a, const void* l, hipStream_t 
 }}
 
 template <typename T, bool COMP, bool WANT_B>
-hipError_t launch_t(const void* a, bool reuse_moments, hipStream_t s) {{
+hipError_t launch_t(const void* a, bool reuse_moments, int schedule, hipStream_t s) {{
   const auto& args = *static_cast<const mtp::EvalArgs<T>*>(a);
   if (args.n_atoms <= 0) return hipSuccess;
   const dim3 grid((args.n_atoms + BLOCK - 1) / BLOCK);
   const size_t smem = (size_t)args.n_c * sizeof(T);
-  if (!reuse_moments) {{
-    if constexpr (sizeof(T) == 8) {{
-{launch_mom_f64}
-    }} else {{
-{launch_mom_f32}
-    }}
-  }}
-  hipLaunchKernelGGL((contract_fwd_kernel<T, WANT_B>), grid, dim3(BLOCK), 0, s, args);
-  if constexpr (sizeof(T) == 8) {{
-{launch_rev_f64}
-  }} else {{
-{launch_rev_f32}
-  }}
-  if constexpr (sizeof(T) == 8) {{
-{launch_f64}
-  }} else {{
-{launch_f32}
-  }}
+{launch_body}
   return hipGetLastError();
 }}
 
-hipError_t launch(int precision, unsigned flags, const void* a, hipStream_t s) {{
+hipError_t launch(int precision, unsigned flags, int schedule, const void* a, hipStream_t s) {{
   const bool want_b = (flags & mtp::kEvalWantB) != 0;
   const bool reuse = (flags & mtp::kEvalReuseMoments) != 0;
   switch (precision) {{
-    case 0: return want_b ? launch_t<double, false, true>(a, reuse, s) : launch_t<double, false, false>(a, reuse, s);
-    case 1: return want_b ? launch_t<float, false, true>(a, reuse, s) : launch_t<float, false, false>(a, reuse, s);
-    case 2: return want_b ? launch_t<float, true, true>(a, reuse, s) : launch_t<float, true, false>(a, reuse, s);
+    case 0:
+      return want_b ? launch_t<double, false, true>(a, reuse, schedule, s)
+                    : launch_t<double, false, false>(a, reuse, schedule, s);
+    case 1:
+      return want_b ? launch_t<float, false, true>(a, reuse, schedule, s)
+                    : launch_t<float, false, false>(a, reuse, schedule, s);
+    case 2:
+      return want_b ? launch_t<float, true, true>(a, reuse, schedule, s)
+                    : launch_t<float, true, false>(a, reuse, schedule, s);
   }}
   return hipErrorInvalidValue;
 }}
@@ -849,13 +838,22 @@ const int kFuncFactors[] = {{ {func_factors} }};
 extern const mtp::BasisVariant {ns}_variant = {{
   "{ns}", {level}, {n_moments}, {ns}::kMoments, {ngraphs}, {ns}::kGraphKeyOffsets, {ns}::kGraphKeys,
   {m}, {ns}::kFuncOffsets, {ns}::kFuncFactors, {C}, {n_mu}, {nu_max},
-  {flops_pair_fwd}, {flops_pair_bwd}, {flops_atom}, {ns}::launch, {ns}::launch_loss, {ns}::BLOCK }};
+  {flops_pair_fwd}, {flops_pair_bwd}, {flops_atom}, {ns}::launch, {ns}::launch_loss, {ns}::BLOCK, {n_sched} }};
 #endif
 """
 
 
-ADJ_BUDGET_F64 = 90   # components per FP64 adjoint pass
-REV_GROUPS_F64 = [(0, 1), (2,), (3, 4), (5, 6)]   # degree groups of the FP64 reverse sweep
+# FP64 schedules: how the per-atom work is cut into passes that fit the
+# register file (moments and adjoint: components per pass; reverse sweep:
+# degree groups).  Fewer passes recompute less per pair; more passes need
+# fewer registers per wavefront and so run more wavefronts per SIMD.  The
+# library times them on the caller's batch (mtp_autotune) and keeps the
+# fastest; schedule 0 is the default.
+SCHEDULES_F64 = [
+    {"mom": 85, "rev": [(0, 1), (2,), (3, 4), (5, 6)], "adj": 90},
+    {"mom": 50, "rev": [(0,), (1,), (2,), (3,), (4,), (5,), (6,)], "adj": 50},
+]
+SCHEDULE_F32 = {"mom": 10 ** 9, "rev": [tuple(range(64))], "adj": 10 ** 9}
 
 
 def generate(lev_max, block=64):
@@ -865,64 +863,72 @@ def generate(lev_max, block=64):
     # moments passes: FP64 accumulators of all 130 components of level 16 do
     # not fit the register file next to the pair's temporaries, so FP64 sums
     # the degrees in two groups (each pass recomputes r and f_mu)
-    # reverse sweep passes by degree groups: each pass holds only the moments
-    # and dV/dg its components need
-    rev_src, rev_launch = [], {}
     comp_nu = {k: nu for (mu, nu, abc), k in s.comp.items()}
-    for prec, groups in (("f32", [tuple(range(s.nu_max + 1))]), ("f64", REV_GROUPS_F64)):
-        lines = []
-        groups = [tuple(n for n in grp if n <= s.nu_max) for grp in groups]
+    con, ops_c = emit_contraction(s)
+    bwd, ops_b = emit_pair_backward(s)
+    loss_src, loss_launch = emit_loss_kernels(s, budget=45)
+    kern_src, sched_launch = [], {}
+    plans = [("f32", 0, SCHEDULE_F32)] + [("f64", k, sch) for k, sch in enumerate(SCHEDULES_F64)]
+    for prec, sidx, sch in plans:
+        mom_lines, rev_lines, adj_lines = [], [], []
+        # moments passes: each recomputes r and f_mu for the degrees it sums
+        for pidx, (nus, comps) in enumerate(adjoint_passes(s, sch["mom"])):
+            tag = f"{prec}s{sidx}_p{pidx}"
+            kmap = {k: j for j, k in enumerate(comps)}
+            body, _ = emit_pair_forward(s, comp_mode=True, nus=set(nus), kmap=kmap)
+            nmu = 1 + max(mu for (mu, nu, abc), k in s.comp.items() if nu in nus)
+            kern_src.append(MOMENTS_TEMPLATE.format(pidx=pidx, nus=nus, tag=tag, ncomp=len(comps), nmu=nmu,
+                                                    comp_list=", ".join(map(str, comps)),
+                                                    body="\n".join(" " * 4 + l for l in body)))
+            mom_lines.append(f"hipLaunchKernelGGL((moments_{tag}_kernel<T, COMP>), grid, dim3(BLOCK), smem, s, args);")
+        # reverse sweep passes by degree groups: each pass holds only the
+        # moments and dV/dg its components need
+        groups = [tuple(n for n in grp if n <= s.nu_max) for grp in sch["rev"]]
         groups = [grp for grp in groups if any(comp_nu[k] in grp for k in range(s.C))]
         covered = {n for grp in groups for n in grp}
         groups += [(n,) for n in sorted(set(comp_nu.values()) - covered)]   # higher levels: one pass per degree
         for pidx, grp in enumerate(groups):
-            tag = f"{prec}_p{pidx}"
+            tag = f"{prec}s{sidx}_p{pidx}"
             ks = [k for k in range(s.C) if comp_nu[k] in grp]
             body, m_used, g_used = emit_reverse_pass(s, ks)
-            rev_src.append(REVERSE_TEMPLATE.format(
+            kern_src.append(REVERSE_TEMPLATE.format(
                 pidx=pidx, nus=list(grp), tag=tag,
                 load_m="\n".join(f"  M[{q}] = args.M[(size_t){q} * args.stride + i];" for q in m_used),
                 load_dg="\n".join(f"  const T dg{g} = args.D[(size_t){g} * args.stride + i];" for g in g_used),
                 fence=" ".join(f'asm volatile("" : "+v"(M[{q}]));' for q in m_used),
                 body="\n".join("  " + l for l in body)))
-            lines.append(f"    hipLaunchKernelGGL((contract_rev_{tag}_kernel<T>), grid, dim3(BLOCK), 0, s, args);")
-        rev_launch[prec] = "\n".join(lines)
-    mom_src, mom_launch = [], {}
-    for prec, budget in (("f32", 10 ** 9), ("f64", 85)):
-        lines = []
-        for pidx, (nus, comps) in enumerate(adjoint_passes(s, budget)):
-            tag = f"{prec}_p{pidx}"
-            kmap = {k: j for j, k in enumerate(comps)}
-            body, _ = emit_pair_forward(s, comp_mode=True, nus=set(nus), kmap=kmap)
-            nmu = 1 + max(mu for (mu, nu, abc), k in s.comp.items() if nu in nus)
-            mom_src.append(MOMENTS_TEMPLATE.format(pidx=pidx, nus=nus, tag=tag, ncomp=len(comps), nmu=nmu,
-                                                   comp_list=", ".join(map(str, comps)),
-                                                   body="\n".join(" " * 4 + l for l in body)))
-            lines.append(f"      hipLaunchKernelGGL((moments_{tag}_kernel<T, COMP>), grid, dim3(BLOCK), smem, s, args);")
-        mom_launch[prec] = "\n".join(lines)
-    con, ops_c = emit_contraction(s)
-    bwd, ops_b = emit_pair_backward(s)
-    loss_src, loss_launch = emit_loss_kernels(s, budget=45)
-    adj_src, launches = [], {}
-    for prec, budget in (("f32", 10 ** 9), ("f64", ADJ_BUDGET_F64)):
-        lines = []
-        passes = adjoint_passes(s, budget)
+            rev_lines.append(f"hipLaunchKernelGGL((contract_rev_{tag}_kernel<T>), grid, dim3(BLOCK), 0, s, args);")
+        # adjoint passes
+        passes = adjoint_passes(s, sch["adj"])
         for pidx, (nus, comps) in enumerate(passes):
-            tag = f"{prec}_p{pidx}"
+            tag = f"{prec}s{sidx}_p{pidx}"
             gmap = {k: j for j, k in enumerate(comps)}
             nmu = 1 + max(mu for (mu, nu, abc), k in s.comp.items() if nu in nus)
             body, _ = emit_pair_backward(s, nus=nus, gmap=gmap, nmu=nmu)
             import re as _re
             used = {int(v) for line in body for v in _re.findall(r"G\[(\d+)\]", line)}
             assert used <= set(range(len(comps))), "adjoint pass reads a component outside its range"
-            adj_src.append(ADJOINT_TEMPLATE.format(pidx=pidx, nus=nus, tag=tag, ncomp=len(comps), nmu=nmu,
-                                                   comp_list=", ".join(map(str, comps)),
-                                                   body="\n".join(" " * 4 + l for l in body)))
+            kern_src.append(ADJOINT_TEMPLATE.format(pidx=pidx, nus=nus, tag=tag, ncomp=len(comps), nmu=nmu,
+                                                    comp_list=", ".join(map(str, comps)),
+                                                    body="\n".join(" " * 4 + l for l in body)))
             first = "true" if pidx == 0 else "false"
             last = "true" if pidx == len(passes) - 1 else "false"
-            lines.append(f"    hipLaunchKernelGGL((adjoint_{tag}_kernel<T, {first}, {last}>), "
-                         f"grid, dim3(BLOCK), smem, s, args);")
-        launches[prec] = "\n".join(lines)
+            adj_lines.append(f"hipLaunchKernelGGL((adjoint_{tag}_kernel<T, {first}, {last}>), "
+                             f"grid, dim3(BLOCK), smem, s, args);")
+        body = (["if (!reuse_moments) {"] + ["  " + l for l in mom_lines] + ["}"] +
+                ["hipLaunchKernelGGL((contract_fwd_kernel<T, WANT_B>), grid, dim3(BLOCK), 0, s, args);"] +
+                rev_lines + adj_lines)
+        sched_launch[(prec, sidx)] = body
+    f64_cases = []
+    for k in range(len(SCHEDULES_F64)):
+        f64_cases.append(f"      case {k}: {{")
+        f64_cases += ["        " + l for l in sched_launch[("f64", k)]]
+        f64_cases.append("      } break;")
+    launch_body = "\n".join(
+        ["  if constexpr (sizeof(T) == 8) {", "    switch (schedule) {"] + f64_cases +
+        ["      default: return hipErrorInvalidValue;", "    }", "  } else {",
+         "    if (schedule != 0) return hipErrorInvalidValue;"] +
+        ["    " + l for l in sched_launch[("f32", 0)]] + ["  }"])
     # radial work per pair: distance 6, Chebyshev 3 per term, f_mu 2 per (mu, beta),
     # derivative pass adds dT and df
     nq = 8
@@ -942,14 +948,12 @@ def generate(lev_max, block=64):
     src = KERNEL_TEMPLATE.format(
         level=lev_max, m=len(s.funcs), ngraphs=len(s.keys), C=s.C, n_mu=s.n_mu, nu_max=s.nu_max,
         block=block, ns=ns,
-        moments_kernels="\n".join(mom_src), launch_mom_f64=mom_launch["f64"], launch_mom_f32=mom_launch["f32"],
+        moments_kernels="\n".join(kern_src), launch_body=launch_body,
         contraction=ind(con, 2),
         contraction_fwd=ind(con[:con.index("MTP_RELOAD_M();")], 2),
-        contract_rev_kernels="\n".join(rev_src), launch_rev_f64=rev_launch["f64"],
-        launch_rev_f32=rev_launch["f32"],
+        contract_rev_kernels="",
         store_dg=ind([f"args.D[(size_t){g} * args.stride + i] = dg{g};" for g in range(len(s.terms))], 2),
-        load_dg=ind([f"const T dg{g} = args.D[(size_t){g} * args.stride + i];" for g in range(len(s.terms))], 2), adjoint_kernels="\n".join(adj_src),
-        launch_f64=launches["f64"], launch_f32=launches["f32"],
+        adjoint_kernels="", n_sched=len(SCHEDULES_F64),
         loss_kernels=loss_src, launch_loss=loss_launch, creduce=CREDUCE_TEMPLATE.format(),
         moments=", ".join(f"{mu}, {nu}" for mu, nu in s.moments),
         n_moments=len(s.moments),

@@ -101,6 +101,7 @@ struct mtp_model {
   Buffer cfg, atom_cfg, atom_bin, bin_count, bin_start, bin_atoms, bin_fill, nbins_dev;
   Buffer count, nbr, pr, rev, gpair, Mbuf, Gbuf, Dbuf, site, wv, B, status, run_start;
   int K = 64;  // neighbour capacity per atom, grown on overflow
+  int schedule64 = 0;  // FP64 pass split of the evaluation kernels (mtp_autotune)
   Buffer b_tmp, c_tmp;
   int last_stride = 0;
   // loss gradient
@@ -409,10 +410,12 @@ int run_eval(mtp_model* M, const mtp_batch* bt, const mtp_out* out, int precisio
     if (N > 0) {
       if (fp64) {
         auto ea = make_args<double>(M, N, stride, bt->species, want_b);
-        HIP_TRY(M->var->launch_eval(precision, want_b ? kEvalWantB : 0u, &ea, s), "evaluation kernels");
+        HIP_TRY(M->var->launch_eval(precision, want_b ? kEvalWantB : 0u, fp64 ? M->schedule64 : 0, &ea, s),
+                "evaluation kernels");
       } else {
         auto ea = make_args<float>(M, N, stride, bt->species, want_b);
-        HIP_TRY(M->var->launch_eval(precision, want_b ? kEvalWantB : 0u, &ea, s), "evaluation kernels");
+        HIP_TRY(M->var->launch_eval(precision, want_b ? kEvalWantB : 0u, fp64 ? M->schedule64 : 0, &ea, s),
+                "evaluation kernels");
       }
     }
     HIP_TRY(mark(2), "hipEventRecord");
@@ -483,6 +486,8 @@ int mtp_model_info(const mtp_model* M, mtp_info* info) {
   info->n_c = M->n_c;
   info->r_min = M->rmin;
   info->r_cut = M->rcut;
+  info->n_schedules = M->var->n_schedules;
+  info->reserved = 0;
   return MTP_OK;
 }
 
@@ -721,11 +726,13 @@ int mtp_normal_equations(mtp_model* M, const mtp_batch* bt, const double* E_t, c
       if (fp64) {
         auto ea = make_args<double>(M, N, stride, bt->species, false);
         ea.xi = M->fit_eye.as<double>() + row;
-        HIP_TRY(M->var->launch_eval(precision, mtp::kEvalReuseMoments, &ea, s), "evaluation kernels");
+        HIP_TRY(M->var->launch_eval(precision, mtp::kEvalReuseMoments, fp64 ? M->schedule64 : 0, &ea, s),
+                "evaluation kernels");
       } else {
         auto ea = make_args<float>(M, N, stride, bt->species, false);
         ea.xi = M->fit_eye.as<float>() + row;
-        HIP_TRY(M->var->launch_eval(precision, mtp::kEvalReuseMoments, &ea, s), "evaluation kernels");
+        HIP_TRY(M->var->launch_eval(precision, mtp::kEvalReuseMoments, fp64 ? M->schedule64 : 0, &ea, s),
+                "evaluation kernels");
       }
     }
     HIP_TRY(mtp::gather_forces(fp64, N, stride, M->count.as<int32_t>(), M->rev.as<int32_t>(), M->gpair.p, M->pr.p,
@@ -780,6 +787,70 @@ int mtp_status(mtp_model* M, void* stream, int64_t* n_below_rmin, int64_t* n_lis
   if (st.bad_offsets) return fail(MTP_E_ARG, "last evaluation: atom_offsets must be non-decreasing from 0 to n_atoms");
   if (st.bad_species) return fail(MTP_E_ARG, "last evaluation: species index outside [0, species_count)");
   if (st.overflow) return fail(MTP_E_CAPACITY, "last evaluation: an atom had more neighbours than the workspace holds");
+  return MTP_OK;
+}
+
+int mtp_set_schedule(mtp_model* M, int precision, int schedule) {
+  g_err.clear();
+  if (!M) return fail(MTP_E_ARG, "mtp_set_schedule: null model");
+  const int n = precision == MTP_FP64 ? M->var->n_schedules : 1;
+  if (precision < MTP_FP64 || precision > MTP_FP32_COMPENSATED || schedule < 0 || schedule >= n)
+    return fail(MTP_E_ARG, "mtp_set_schedule: no such schedule for this precision");
+  if (precision == MTP_FP64) M->schedule64 = schedule;
+  return MTP_OK;
+}
+
+int mtp_autotune(mtp_model* M, const mtp_batch* bt, int precision, int repeats, float* ms_out, int n_out,
+                 int* chosen, void* stream) {
+  g_err.clear();
+  if (!M || !bt) return fail(MTP_E_ARG, "mtp_autotune: null argument");
+  if (precision < MTP_FP64 || precision > MTP_FP32_COMPENSATED) return fail(MTP_E_ARG, "mtp_autotune: bad precision");
+  if (repeats < 1) return fail(MTP_E_ARG, "mtp_autotune: repeats must be positive");
+  HIP_TRY(hipSetDevice(M->device), "hipSetDevice");
+  hipStream_t s = (hipStream_t)stream;
+  // neighbour lists and workspace for this batch
+  mtp_out none{};
+  int rc = run_eval(M, bt, &none, precision, s);
+  if (rc != MTP_OK) return rc;
+  const bool fp64 = precision == MTP_FP64;
+  const int n = fp64 ? M->var->n_schedules : 1;
+  const int64_t N = bt->n_atoms;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIP_TRY(hipEventCreate(&e0), "hipEventCreate");
+  HIP_TRY(hipEventCreate(&e1), "hipEventCreate");
+  int best = 0;
+  float best_ms = 0.f;
+  hipError_t err = hipSuccess;
+  for (int k = 0; k < n && err == hipSuccess; ++k) {
+    float ms = 0.f;
+    if (N > 0) {
+      auto run = [&]() -> hipError_t {
+        if (fp64) {
+          auto ea = make_args<double>(M, N, M->last_stride, bt->species, false);
+          return M->var->launch_eval(precision, 0u, k, &ea, s);
+        }
+        auto ea = make_args<float>(M, N, M->last_stride, bt->species, false);
+        return M->var->launch_eval(precision, 0u, k, &ea, s);
+      };
+      err = run();                                   // first launch not timed
+      if (err == hipSuccess) err = hipEventRecord(e0, s);
+      for (int r = 0; r < repeats && err == hipSuccess; ++r) err = run();
+      if (err == hipSuccess) err = hipEventRecord(e1, s);
+      if (err == hipSuccess) err = hipEventSynchronize(e1);
+      if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+      ms /= (float)repeats;
+    }
+    if (ms_out && k < n_out) ms_out[k] = ms;
+    if (k == 0 || ms < best_ms) {
+      best = k;
+      best_ms = ms;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (err != hipSuccess) return hip_fail(err, "mtp_autotune");
+  if (fp64) M->schedule64 = best;
+  if (chosen) *chosen = best;
   return MTP_OK;
 }
 

@@ -27,10 +27,12 @@ struct BasisVariant {
   double flops_pair_bwd;         // per pair, adjoint
   double flops_atom;             // per atom, contraction forward + reverse
   // precision: 0 = FP64, 1 = FP32, 2 = FP32 with compensated moment sums
-  hipError_t (*launch_eval)(int precision, unsigned flags, const void* args, hipStream_t stream);
+  // schedule: index of the FP64 pass split (0 .. n_schedules - 1; FP32 has only 0)
+  hipError_t (*launch_eval)(int precision, unsigned flags, int schedule, const void* args, hipStream_t stream);
   // loss-gradient kernels after an evaluation that left M and G in place
   hipError_t (*launch_loss)(int precision, const void* eval_args, const void* loss_args, hipStream_t stream);
   int block;                     // atoms per workgroup of the per-atom kernels
+  int n_schedules;               // FP64 schedules compiled (pass splits)
 };
 
 extern const BasisVariant* const kVariants[];

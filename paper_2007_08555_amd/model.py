@@ -60,6 +60,7 @@ class Potential:
         self.level, self.m, self.n_mu = info.level, info.m, info.n_mu
         self.n_species, self.n_q, self.n_c = info.n_species, info.n_q, info.n_c
         self.r_min, self.r_cut = info.r_min, info.r_cut
+        self.n_schedules = info.n_schedules
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -161,6 +162,21 @@ class Potential:
         xi = self.solve_normal(H, g, stream=stream)
         self.set_params(xi=xi.cpu().numpy())
         return xi
+
+    def set_schedule(self, schedule, precision="fp64"):
+        """Selects the pass split of the evaluation kernels (mtp_set_schedule)."""
+        check(lib().mtp_set_schedule(self._h, _lib.PRECISIONS[precision], int(schedule)), "mtp_set_schedule")
+
+    def autotune(self, batch: Batch, precision="fp64", repeats=3, stream=None):
+        """Times every schedule on `batch` and keeps the fastest
+        (mtp_autotune).  Returns (chosen index, [ms per schedule])."""
+        ms = (ctypes.c_float * 16)()
+        chosen = ctypes.c_int(-1)
+        bs = batch.c_struct()
+        check(lib().mtp_autotune(self._h, ctypes.byref(bs), _lib.PRECISIONS[precision], int(repeats), ms, 16,
+                                 ctypes.byref(chosen), _stream(stream)), "mtp_autotune")
+        n = 1 if precision != "fp64" else self.n_schedules
+        return chosen.value, [float(ms[k]) for k in range(n)]
 
     def outputs(self, batch: Batch, forces=True, virial=True, site=False, b=False, energy=True):
         """Preallocated output tensors for eval_async (dict as returned by eval)."""

@@ -1,0 +1,46 @@
+"""Schedules of the evaluation kernels and the autotuner: every FP64
+schedule matches the FP64 oracle, the autotuner's choice is one of them and
+is the schedule used afterwards."""
+import numpy as np
+import pytest
+
+import synth
+from gpu_common import errors, gpu_batch, log, oracle_batch, pot_path
+from oracle.potential import read_potential
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = {"energy_per_atom": 1e-11, "site": 1e-11, "force": 1e-10, "virial": 1e-9, "b_rel": 1e-11}
+
+
+def test_every_schedule_matches_the_oracle_and_autotune_picks_one():
+    import torch
+    from paper_2007_08555_amd import Batch, Potential
+    from paper_2007_08555_amd._lib import MTPError
+    P = Potential(pot_path("lev16_s3"))
+    assert P.n_schedules >= 2
+    batch = synth.mixed_batch(seed=41, n_configs=24, n_min=8, n_max=96, n_species_model=3)
+    o = oracle_batch(read_potential(pot_path("lev16_s3")), batch)
+    results = []
+    for k in range(P.n_schedules):
+        P.set_schedule(k)
+        g = gpu_batch(P, batch, "fp64")
+        rep = errors(batch, g, o)
+        log(f"[schedule {k}] {rep}")
+        for key, v in TOL64.items():
+            assert rep[key] <= v, (k, key, rep[key])
+        results.append(g)
+    chosen, ms = P.autotune(Batch.from_arrays(batch), precision="fp64", repeats=2)
+    log(f"[autotune] chosen {chosen}, ms per schedule {ms}")
+    assert 0 <= chosen < P.n_schedules and len(ms) == P.n_schedules and all(t > 0 for t in ms)
+    assert ms[chosen] == min(ms)
+    g = gpu_batch(P, batch, "fp64")
+    for key in ("energy", "forces", "virial"):
+        assert np.array_equal(g[key], results[chosen][key])
+    with pytest.raises(MTPError):
+        P.set_schedule(P.n_schedules)
+    with pytest.raises(MTPError):
+        P.set_schedule(1, precision="fp32")
+    chosen32, ms32 = P.autotune(Batch.from_arrays(batch), precision="fp32")
+    assert chosen32 == 0 and len(ms32) == 1
+    torch.cuda.synchronize()
