@@ -167,6 +167,77 @@ __global__ void __launch_bounds__(BLOCK) contract_rev_{tag}_kernel(const mtp::Ev
 """
 
 
+TGRAPH_TEMPLATE = r"""
+// Loss path, graph pass {pidx}: values and tangents (along dM) of the
+// connected graphs {graphs}, from the moments they use.
+template <typename R>
+__global__ void __launch_bounds__(BLOCK) tgraph_{tag}_kernel(const mtp::EvalArgs<R> args, const mtp::LossArgs<R> la) {{
+  using T = mtp::Dual<R>;
+  const int i = blockIdx.x * BLOCK + threadIdx.x;
+  if (i >= args.n_atoms) return;
+  T M[C];
+{load_m}
+{body}
+{store_g}
+}}
+"""
+
+TBASIS_TEMPLATE = r"""
+// Loss path: basis functions, V and dV/dg on dual numbers from the graph
+// values and tangents; writes a_k B_alpha + tangent of B_alpha and dV/dg.
+template <typename R>
+__global__ void __launch_bounds__(BLOCK) tbasis_kernel(const mtp::EvalArgs<R> args, const mtp::LossArgs<R> la) {{
+  using T = mtp::Dual<R>;
+  const int i = blockIdx.x * BLOCK + threadIdx.x;
+  if (i >= args.n_atoms) return;
+  const R* __restrict__ xi = args.xi;
+  const R aw = la.a_atom[i];
+{load_g}
+#define MTP_OUT_B(a_, v_) la.xi_terms[(size_t)(a_) * args.stride + i] = aw * (v_).v + (v_).d
+{body}
+#undef MTP_OUT_B
+{store_dg}
+  (void)V;
+}}
+"""
+
+TREV_TEMPLATE = r"""
+// Loss path, reverse pass {pidx}: tangent of G = dV/dM for the components of
+// degrees {nus}, from the moments they pair with and dV/dg on dual numbers.
+template <typename R>
+__global__ void __launch_bounds__(BLOCK) trev_{tag}_kernel(const mtp::EvalArgs<R> args, const mtp::LossArgs<R> la) {{
+  using T = mtp::Dual<R>;
+  const int i = blockIdx.x * BLOCK + threadIdx.x;
+  if (i >= args.n_atoms) return;
+  T M[C];
+{load_m}
+{load_dg}
+#define MTP_OUT_G(k_, v_) la.dG[(size_t)(k_) * args.stride + i] = (v_).d
+#define MTP_FENCE_M() do {{ {fence} }} while (0)
+{body}
+#undef MTP_FENCE_M
+#undef MTP_OUT_G
+}}
+"""
+
+
+def graph_groups(s, budget):
+    """Connected graphs grouped (in order of their first moment component)
+    so that each group reads at most `budget` moment components."""
+    sets = [set(k for c, idx in t for k in idx) for t in s.terms]
+    order = sorted(range(len(sets)), key=lambda g: (min(sets[g]) if sets[g] else 0, len(sets[g]), g))
+    out, cur, used = [], [], set()
+    for g in order:
+        if cur and len(used | sets[g]) > budget:
+            out.append(cur)
+            cur, used = [], set()
+        cur.append(g)
+        used |= sets[g]
+    if cur:
+        out.append(cur)
+    return out
+
+
 MOMENTS_TEMPLATE = r"""
 // Moments pass {pidx}: the components of degrees {nus} of one atom, summed
 // over its pairs and written to args.M.
@@ -753,29 +824,6 @@ __global__ void __launch_bounds__(BLOCK) contract_fwd_kernel(const mtp::EvalArgs
 }}
 
 {contract_rev_kernels}
-// The same contraction code on dual numbers M + dM e: the tangents of G and of
-// every B_alpha along the moment tangent dM (forward mode over the reverse
-// sweep).  Writes dG and a_k B_alpha + dB_alpha.
-template <typename R>
-__global__ void __launch_bounds__(BLOCK) tangent_contract_kernel(const mtp::EvalArgs<R> args,
-                                                                 const mtp::LossArgs<R> la) {{
-  using T = mtp::Dual<R>;
-  const int i = blockIdx.x * BLOCK + threadIdx.x;
-  if (i >= args.n_atoms) return;
-  const R* __restrict__ xi = args.xi;
-  const R aw = la.a_atom[i];
-  T M[C];
-#pragma unroll
-  for (int k = 0; k < C; ++k) M[k] = T(args.M[(size_t)k * args.stride + i], la.dM[(size_t)k * args.stride + i]);
-#define MTP_OUT_B(a_, v_) la.xi_terms[(size_t)(a_) * args.stride + i] = aw * (v_).v + (v_).d
-#define MTP_OUT_G(k_, v_) la.dG[(size_t)(k_) * args.stride + i] = (v_).d
-#define MTP_RELOAD_M() mtp::opaque(M)
-{contraction}
-#undef MTP_RELOAD_M
-#undef MTP_OUT_B
-#undef MTP_OUT_G
-  (void)V;
-}}
 
 {adjoint_kernels}
 {loss_kernels}
@@ -919,6 +967,59 @@ def generate(lev_max, block=64):
                 ["hipLaunchKernelGGL((contract_fwd_kernel<T, WANT_B>), grid, dim3(BLOCK), 0, s, args);"] +
                 rev_lines + adj_lines)
         sched_launch[(prec, sidx)] = body
+    # loss path: the contraction on dual numbers, split into graph passes,
+    # the basis step and reverse passes (dual values need twice the registers)
+    fwd_lines = con[:con.index("MTP_RELOAD_M();")]
+    vpos = fwd_lines.index("T V = T(0);")
+    basis_lines = fwd_lines[vpos:]
+    ng = len(s.terms)
+    tgraph_budget, trev_groups = 40, [(n,) for n in range(s.nu_max + 1)]
+    tkern, tlaunch = [], []
+    for pidx, graphs in enumerate(graph_groups(s, tgraph_budget)):
+        tag = f"p{pidx}"
+        body, m_used = [], set()
+        for g in graphs:
+            body.append(f"T g{g} = T(0);")
+            for coef, idx in s.terms[g]:
+                m_used.update(idx)
+                expr = _prod([f"M[{k}]" for k in idx])
+                if coef != 1:
+                    expr = f"{_const(coef)} * {expr}"
+                body.append(f"g{g} += {expr};")
+        tkern.append(TGRAPH_TEMPLATE.format(
+            pidx=pidx, graphs=graphs, tag=tag,
+            load_m="\n".join(f"  M[{q}] = T(args.M[(size_t){q} * args.stride + i], la.dM[(size_t){q} * args.stride + i]);"
+                             for q in sorted(m_used)),
+            body="\n".join("  " + l for l in body),
+            store_g="\n".join(f"  la.gd[(size_t){g} * args.stride + i] = g{g}.v; "
+                               f"la.gd[(size_t){ng + g} * args.stride + i] = g{g}.d;" for g in graphs)))
+        tlaunch.append(f"  hipLaunchKernelGGL((tgraph_{tag}_kernel<T>), grid, dim3(BLOCK), 0, s, args, la);")
+    tkern.append(TBASIS_TEMPLATE.format(
+        load_g="\n".join(f"  const T g{g}(la.gd[(size_t){g} * args.stride + i], la.gd[(size_t){ng + g} * args.stride + i]);"
+                         for g in range(ng)),
+        body="\n".join("  " + l for l in basis_lines),
+        store_dg="\n".join(f"  la.gd[(size_t){g} * args.stride + i] = dg{g}.v; "
+                            f"la.gd[(size_t){ng + g} * args.stride + i] = dg{g}.d;" for g in range(ng))))
+    tlaunch.append("  hipLaunchKernelGGL((tbasis_kernel<T>), grid, dim3(BLOCK), 0, s, args, la);")
+    for pidx, grp in enumerate(trev_groups):
+        ks = [k for k in range(s.C) if comp_nu[k] in grp]
+        if not ks:
+            continue
+        tag = f"p{pidx}"
+        body, m_used, g_used = emit_reverse_pass(s, ks)
+        tkern.append(TREV_TEMPLATE.format(
+            pidx=pidx, nus=list(grp), tag=tag,
+            load_m="\n".join(f"  M[{q}] = T(args.M[(size_t){q} * args.stride + i], la.dM[(size_t){q} * args.stride + i]);"
+                             for q in m_used),
+            load_dg="\n".join(f"  const T dg{g}(la.gd[(size_t){g} * args.stride + i], la.gd[(size_t){ng + g} * args.stride + i]);"
+                              for g in g_used),
+            fence=" ".join(f'asm volatile("" : "+v"(M[{q}].v), "+v"(M[{q}].d));' for q in m_used),
+            body="\n".join("  " + l for l in body)))
+        tlaunch.append(f"  hipLaunchKernelGGL((trev_{tag}_kernel<T>), grid, dim3(BLOCK), 0, s, args, la);")
+    old_launch = "  hipLaunchKernelGGL((tangent_contract_kernel<T>), grid, dim3(BLOCK), 0, s, args, la);"
+    assert old_launch in loss_launch
+    loss_launch = loss_launch.replace(old_launch, "\n".join(tlaunch))
+    loss_src = loss_src + "\n" + "\n".join(tkern)
     f64_cases = []
     for k in range(len(SCHEDULES_F64)):
         f64_cases.append(f"      case {k}: {{")

@@ -105,7 +105,7 @@ struct mtp_model {
   Buffer b_tmp, c_tmp;
   int last_stride = 0;
   // loss gradient
-  Buffer lo_E, lo_F, lo_W, lo_a, lo_u, lo_eps, lo_dM, lo_dG, lo_xit, lo_pa, lo_pb, lo_cpart;
+  Buffer lo_E, lo_F, lo_W, lo_a, lo_u, lo_eps, lo_dM, lo_dG, lo_xit, lo_pa, lo_pb, lo_cpart, lo_gd;
   Buffer lo_acfg, lo_wfcfg, lo_epscfg, lo_losscfg, lo_lossatom;
   // normal equations
   Buffer fit_J, fit_w, fit_P, fit_eye, fit_D, fit_W2, fit_inv, fit_flag;
@@ -630,6 +630,7 @@ int mtp_loss_grad(mtp_model* M, const mtp_batch* bt, const double* E_t, const do
   HIP_TRY(M->lo_eps.ensure(tsz * 9 * stride), "hipMalloc");
   HIP_TRY(M->lo_dM.ensure(tsz * (size_t)C * stride), "hipMalloc");
   HIP_TRY(M->lo_dG.ensure(tsz * (size_t)C * stride), "hipMalloc");
+  HIP_TRY(M->lo_gd.ensure(tsz * 2 * (size_t)M->var->n_graphs * stride), "hipMalloc");
   HIP_TRY(M->lo_xit.ensure(tsz * (size_t)M->m * stride), "hipMalloc");
   HIP_TRY(M->lo_pa.ensure(tsz * (size_t)M->n_mu * K * stride), "hipMalloc");
   HIP_TRY(M->lo_pb.ensure(tsz * (size_t)M->n_mu * K * stride), "hipMalloc");
@@ -672,6 +673,7 @@ int mtp_loss_grad(mtp_model* M, const mtp_batch* bt, const double* E_t, const do
     la.K = K;
     la.dM = M->lo_dM.as<T>();
     la.dG = M->lo_dG.as<T>();
+    la.gd = M->lo_gd.as<T>();
     la.xi_terms = M->lo_xit.as<T>();
     la.pa = M->lo_pa.as<T>();
     la.pb = M->lo_pb.as<T>();

@@ -141,6 +141,7 @@ struct LossArgs {
   T* dM;               // [C][stride] tangent of the moments along delta r
   T* dG;               // [C][stride] tangent of G = dV/dM
   T* xi_terms;         // [m][stride] a B_alpha + tangent of B_alpha
+  T* gd;               // [2 n_graphs][stride] graph values and tangents, then dV/dg and its tangent
   T* pa;               // [NMU][K * stride] per pair: coefficient of Q_beta
   T* pb;               // [NMU][K * stride] per pair: coefficient of dQ_beta/dr
   double* cpart;       // [blocks][n_c] partial sums of dL/dc per workgroup
