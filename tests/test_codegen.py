@@ -1,0 +1,34 @@
+"""Host checks of the kernel generator: every schedule's passes cover each
+moment component exactly once (moments, reverse sweep, adjoint), the graph
+groups of the loss path cover each connected graph once, and every kernel a
+launcher names is defined."""
+import re
+
+import pytest
+
+from paper_2007_08555_amd import codegen
+
+
+@pytest.mark.parametrize("level", [8, 12, 16])
+def test_passes_partition_the_components(level):
+    s = codegen.Schedule(level)
+    comp_nu = {k: nu for (mu, nu, abc), k in s.comp.items()}
+    for sch in [codegen.SCHEDULE_F32] + codegen.SCHEDULES_F64:
+        for key in ("mom", "adj"):
+            seen = [k for _, comps in codegen.adjoint_passes(s, sch[key]) for k in comps]
+            assert sorted(seen) == list(range(s.C))
+        groups = [tuple(n for n in g if n <= s.nu_max) for g in sch["rev"]]
+        covered = [n for g in groups for n in g if any(comp_nu[k] == n for k in range(s.C))]
+        assert len(covered) == len(set(covered))
+    groups = codegen.graph_groups(s, 40)
+    assert sorted(g for grp in groups for g in grp) == list(range(len(s.terms)))
+
+
+@pytest.mark.parametrize("level", [8, 16])
+def test_launched_kernels_are_defined(level):
+    src, _ = codegen.generate(level)
+    launched = set(re.findall(r"hipLaunchKernelGGL\(\((\w+)<", src))
+    defined = set(re.findall(r"(\w+_kernel)\(const mtp::EvalArgs", src))
+    assert launched and launched <= defined, launched - defined
+    # one case per FP64 schedule in the evaluation launcher
+    assert src.count("      case ") >= len(codegen.SCHEDULES_F64)

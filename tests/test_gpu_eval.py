@@ -104,3 +104,30 @@ def test_bad_offsets_are_rejected(potentials):
     b["atom_offsets"] = np.array([0, 100], np.int64)
     with pytest.raises(MTPError, match="atom_offsets"):
         gpu_batch(P, b, "fp32")
+
+
+@pytest.mark.parametrize("spacing", [1.95, 1.55])
+def test_dense_cells_grow_the_neighbour_capacity(potentials, spacing):
+    # simple cubic cells denser than any physical structure: about 70 and 140
+    # neighbours per atom, beyond the default capacity of 64 slots (the second
+    # also beyond the 128 slots kept in LDS by the small-configuration search)
+    rng = np.random.default_rng(5)
+    n = 4
+    g = np.arange(n, dtype=np.float64)
+    pos = np.stack(np.meshgrid(g, g, g, indexing="ij"), -1).reshape(-1, 3) * spacing
+    pos += rng.normal(0, 0.02, pos.shape)
+    cell = np.eye(3) * n * spacing
+    species = rng.integers(0, 2, len(pos)).astype(np.int32)
+    b = synth._batch([(pos, species, cell, True), (pos[:20] * 1.0, species[:20], cell, False)])
+    P, op = potentials("lev12_s2")
+    g_ = gpu_batch(P, b, "fp64")
+    st = P.stats()
+    o = oracle_batch(op, b)
+    rep = errors(b, g_, o)
+    log(f"[dense-{spacing}] errors {rep}")
+    assert P.status()["list_errors"] == 0
+    # pairs far inside R_min give forces of 1e4 eV/A: FP64 bounds relative to the scales
+    assert rep["site"] <= 1e-13 * rep["site_scale"] and rep["force"] <= 1e-13 * rep["force_scale"]
+    assert rep["b_rel"] <= 1e-11
+    log(f"[dense-{spacing}] max neighbours {st['max_neighbours']}")
+    assert st["max_neighbours"] > (128 if spacing < 1.7 else 64)
