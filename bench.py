@@ -38,7 +38,7 @@ def log(*a):
 
 
 TRAFFIC_MD = os.path.join(ROOT, "profiles", "eval_lev16_batch4096_fp64_hbm.md")
-KERNEL_SRC = os.path.join(ROOT, "paper_2007_08555_amd", "csrc", "generated", "gen_lev16.hip")
+KERNEL_SRC = os.path.join(ROOT, "paper_2007_08555_amd", "csrc", "generated", "gen_lev16.inc")
 
 
 def measured_traffic():
@@ -56,6 +56,45 @@ def measured_traffic():
     if fields.get("kernel_source_sha256", "").strip() != digest:
         return None
     return float(fields["traffic_bytes_per_launch"])
+
+
+def training_extras(P, pot_path, precision):
+    """The training-side rows on a batch shaped like the paper's training
+    sets (1024 configurations of 32-128 atoms, three species): loss and
+    gradient in all parameters (mtp_loss_grad), and the normal equations in
+    xi with their solve (mtp_normal_equations, mtp_solve_normal).  Targets
+    come from the same potential with xi scaled by 1.1 plus N(0, 1e-3^2)
+    noise."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2007_08555_amd import Batch
+    tb = synth.mixed_batch(seed=4, n_configs=1024, n_min=32, n_max=128, n_species_model=3)
+    n_atoms = int(tb["n_atoms"].sum())
+    B = Batch.from_arrays(tb, "cuda:0")
+    c, xi = P.get_params()
+    P.set_params(xi=xi * 1.1)
+    ref = P.eval(B, precision="fp64", forces=True, virial=True)
+    P.set_params(xi=xi)
+    g = torch.Generator(device="cuda:0").manual_seed(0)
+    noise = lambda t: t + 1e-3 * torch.randn(t.shape, generator=g, device=t.device, dtype=t.dtype)
+    Et, Ft, Wt = noise(ref["energy"]), noise(ref["forces"]), noise(ref["virial"])
+    res = {"workload": f"1024 configurations, 32-128 atoms ({n_atoms} atoms), 3 species, level 16, FP64",
+           "atoms": n_atoms}
+    for name, fn in (("loss_grad", lambda: P.loss_grad(B, Et, Ft, Wt, precision="fp64")),
+                     ("normal_equations", lambda: P.solve_normal(*P.normal_equations(B, Et, Ft, Wt)[:2]))):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        reps = 3
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        res[name] = {"ms_per_call": dt * 1e3, "atom_evals_per_s": n_atoms / dt}
+    res["normal_equations"]["note"] = f"m = {P.m} evaluations with xi = e_alpha, Gram product and solve"
+    return res
 
 
 def cpu_baseline(batch, pot_path, budget_s):
@@ -249,6 +288,8 @@ def main():
         tb = (time.perf_counter() - t0) / 10
         line["bcc16000"] = {"value": 16000 / tb, "unit": "atom-evals/s", "ms_per_step": tb * 1e3}
         log(f"bcc16000: {16000 / tb:.4g} atom-evals/s")
+        line["training"] = training_extras(P, pot_path, a.precision)
+        log(f"training: {line['training']}")
         line["cpu_baseline"] = cpu_baseline(batch, pot_path, a.cpu_seconds)
         log(f"cpu baseline: {line['cpu_baseline']}")
     print(json.dumps(line), flush=True)

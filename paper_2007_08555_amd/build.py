@@ -13,6 +13,7 @@ from __future__ import annotations
 import argparse
 import concurrent.futures as cf
 import hashlib
+import re
 import os
 import shutil
 import subprocess
@@ -43,7 +44,12 @@ HEADERS = ["mtp_device.h", "mtp_internal.h", "mtp_variant.h"]
 def _hash(path, extra):
     h = hashlib.sha256()
     with open(path, "rb") as fh:
-        h.update(fh.read())
+        text = fh.read()
+    h.update(text)
+    # a generated part includes the level's kernel body
+    for inc in re.findall(rb'#include "(gen_lev\d+\.inc)"', text):
+        with open(os.path.join(os.path.dirname(path), inc.decode()), "rb") as fh:
+            h.update(fh.read())
     for hd in HEADERS:
         with open(os.path.join(CSRC, hd), "rb") as fh:
             h.update(fh.read())
@@ -79,7 +85,13 @@ def build(levels=None, jobs=None, verbose=True):
     jobs = jobs or min(8, os.cpu_count() or 4)
     objs = []
     # largest generated kernels first so they overlap with the small files
-    sources.sort(key=lambda p: -os.path.getsize(p))
+    def cost(p):   # compile the parts of the largest bases first
+        size = os.path.getsize(p)
+        with open(p, "rb") as fh:
+            for inc in re.findall(rb'#include "(gen_lev\d+\.inc)"', fh.read()):
+                size += os.path.getsize(os.path.join(os.path.dirname(p), inc.decode()))
+        return -size
+    sources.sort(key=cost)
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
         for obj, dt, msg in ex.map(_compile, sources):
             objs.append(obj)

@@ -805,6 +805,7 @@ constexpr int BLOCK = {block};
 
 __device__ __forceinline__ int clamp_species(int z, int S) {{ return z < 0 ? 0 : (z >= S ? S - 1 : z); }}
 
+#if MTP_PART == 1 || MTP_PART == 2
 {moments_kernels}
 // Forward contractions of one atom's moments: graph values, V, optional B,
 // and dV/dg of every connected graph g (to args.D).
@@ -823,9 +824,9 @@ __global__ void __launch_bounds__(BLOCK) contract_fwd_kernel(const mtp::EvalArgs
   args.site[i] = V;
 }}
 
-{contract_rev_kernels}
+#endif  // parts 1, 2
 
-{adjoint_kernels}
+#if MTP_PART == 3
 {loss_kernels}
 {creduce}
 
@@ -839,36 +840,68 @@ hipError_t launch_loss_t(const void* a, const void* l, hipStream_t s) {{
 {launch_loss}
   return hipGetLastError();
 }}
+#endif  // part 3
 
-hipError_t launch_loss(int precision, const void* a, const void* l, hipStream_t s) {{
-  return precision == 0 ? launch_loss_t<double>(a, l, s) : launch_loss_t<float>(a, l, s);
-}}
-
+#if MTP_PART == 1 || MTP_PART == 2
 template <typename T, bool COMP, bool WANT_B>
 hipError_t launch_t(const void* a, bool reuse_moments, int schedule, hipStream_t s) {{
   const auto& args = *static_cast<const mtp::EvalArgs<T>*>(a);
   if (args.n_atoms <= 0) return hipSuccess;
   const dim3 grid((args.n_atoms + BLOCK - 1) / BLOCK);
   const size_t smem = (size_t)args.n_c * sizeof(T);
-{launch_body}
+#if MTP_PART == 1
+{launch_body64}
+#else
+{launch_body32}
+#endif
   return hipGetLastError();
 }}
+#endif  // parts 1, 2
 
-hipError_t launch(int precision, unsigned flags, int schedule, const void* a, hipStream_t s) {{
+}}  // namespace {ns}
+}}  // namespace
+
+// Entry points of the parts (compiled as separate translation units).
+namespace mtp_gen_{ns} {{
+hipError_t eval64(unsigned flags, int schedule, const void* a, hipStream_t s);
+hipError_t eval32(int precision, unsigned flags, int schedule, const void* a, hipStream_t s);
+hipError_t loss(int precision, const void* a, const void* l, hipStream_t s);
+#if MTP_PART == 1
+hipError_t eval64(unsigned flags, int schedule, const void* a, hipStream_t s) {{
+  using namespace {ns};
   const bool want_b = (flags & mtp::kEvalWantB) != 0;
   const bool reuse = (flags & mtp::kEvalReuseMoments) != 0;
-  switch (precision) {{
-    case 0:
-      return want_b ? launch_t<double, false, true>(a, reuse, schedule, s)
-                    : launch_t<double, false, false>(a, reuse, schedule, s);
-    case 1:
-      return want_b ? launch_t<float, false, true>(a, reuse, schedule, s)
-                    : launch_t<float, false, false>(a, reuse, schedule, s);
-    case 2:
-      return want_b ? launch_t<float, true, true>(a, reuse, schedule, s)
-                    : launch_t<float, true, false>(a, reuse, schedule, s);
-  }}
+  return want_b ? launch_t<double, false, true>(a, reuse, schedule, s)
+                : launch_t<double, false, false>(a, reuse, schedule, s);
+}}
+#elif MTP_PART == 2
+hipError_t eval32(int precision, unsigned flags, int schedule, const void* a, hipStream_t s) {{
+  using namespace {ns};
+  const bool want_b = (flags & mtp::kEvalWantB) != 0;
+  const bool reuse = (flags & mtp::kEvalReuseMoments) != 0;
+  if (precision == 2)
+    return want_b ? launch_t<float, true, true>(a, reuse, schedule, s) : launch_t<float, true, false>(a, reuse, schedule, s);
+  return want_b ? launch_t<float, false, true>(a, reuse, schedule, s) : launch_t<float, false, false>(a, reuse, schedule, s);
+}}
+#elif MTP_PART == 3
+hipError_t loss(int precision, const void* a, const void* l, hipStream_t s) {{
+  using namespace {ns};
+  return precision == 0 ? launch_loss_t<double>(a, l, s) : launch_loss_t<float>(a, l, s);
+}}
+#endif
+}}  // namespace mtp_gen_{ns}
+
+#if MTP_PART == 0
+namespace {{
+namespace {ns} {{
+hipError_t launch(int precision, unsigned flags, int schedule, const void* a, hipStream_t s) {{
+  if (precision == 0) return mtp_gen_{ns}::eval64(flags, schedule, a, s);
+  if (precision == 1 || precision == 2) return mtp_gen_{ns}::eval32(precision, flags, schedule, a, s);
   return hipErrorInvalidValue;
+}}
+
+hipError_t launch_loss(int precision, const void* a, const void* l, hipStream_t s) {{
+  return mtp_gen_{ns}::loss(precision, a, l, s);
 }}
 
 const int kMoments[] = {{ {moments} }};
@@ -888,6 +921,7 @@ extern const mtp::BasisVariant {ns}_variant = {{
   {m}, {ns}::kFuncOffsets, {ns}::kFuncFactors, {C}, {n_mu}, {nu_max},
   {flops_pair_fwd}, {flops_pair_bwd}, {flops_atom}, {ns}::launch, {ns}::launch_loss, {ns}::BLOCK, {n_sched} }};
 #endif
+#endif  // part 0
 """
 
 
@@ -915,7 +949,7 @@ def generate(lev_max, block=64):
     con, ops_c = emit_contraction(s)
     bwd, ops_b = emit_pair_backward(s)
     loss_src, loss_launch = emit_loss_kernels(s, budget=45)
-    kern_src, sched_launch = [], {}
+    kern_src, sched_launch = {"f32": [], "f64": []}, {}
     plans = [("f32", 0, SCHEDULE_F32)] + [("f64", k, sch) for k, sch in enumerate(SCHEDULES_F64)]
     for prec, sidx, sch in plans:
         mom_lines, rev_lines, adj_lines = [], [], []
@@ -925,7 +959,7 @@ def generate(lev_max, block=64):
             kmap = {k: j for j, k in enumerate(comps)}
             body, _ = emit_pair_forward(s, comp_mode=True, nus=set(nus), kmap=kmap)
             nmu = 1 + max(mu for (mu, nu, abc), k in s.comp.items() if nu in nus)
-            kern_src.append(MOMENTS_TEMPLATE.format(pidx=pidx, nus=nus, tag=tag, ncomp=len(comps), nmu=nmu,
+            kern_src[prec].append(MOMENTS_TEMPLATE.format(pidx=pidx, nus=nus, tag=tag, ncomp=len(comps), nmu=nmu,
                                                     comp_list=", ".join(map(str, comps)),
                                                     body="\n".join(" " * 4 + l for l in body)))
             mom_lines.append(f"hipLaunchKernelGGL((moments_{tag}_kernel<T, COMP>), grid, dim3(BLOCK), smem, s, args);")
@@ -939,7 +973,7 @@ def generate(lev_max, block=64):
             tag = f"{prec}s{sidx}_p{pidx}"
             ks = [k for k in range(s.C) if comp_nu[k] in grp]
             body, m_used, g_used = emit_reverse_pass(s, ks)
-            kern_src.append(REVERSE_TEMPLATE.format(
+            kern_src[prec].append(REVERSE_TEMPLATE.format(
                 pidx=pidx, nus=list(grp), tag=tag,
                 load_m="\n".join(f"  M[{q}] = args.M[(size_t){q} * args.stride + i];" for q in m_used),
                 load_dg="\n".join(f"  const T dg{g} = args.D[(size_t){g} * args.stride + i];" for g in g_used),
@@ -956,7 +990,7 @@ def generate(lev_max, block=64):
             import re as _re
             used = {int(v) for line in body for v in _re.findall(r"G\[(\d+)\]", line)}
             assert used <= set(range(len(comps))), "adjoint pass reads a component outside its range"
-            kern_src.append(ADJOINT_TEMPLATE.format(pidx=pidx, nus=nus, tag=tag, ncomp=len(comps), nmu=nmu,
+            kern_src[prec].append(ADJOINT_TEMPLATE.format(pidx=pidx, nus=nus, tag=tag, ncomp=len(comps), nmu=nmu,
                                                     comp_list=", ".join(map(str, comps)),
                                                     body="\n".join(" " * 4 + l for l in body)))
             first = "true" if pidx == 0 else "false"
@@ -1022,14 +1056,13 @@ def generate(lev_max, block=64):
     loss_src = loss_src + "\n" + "\n".join(tkern)
     f64_cases = []
     for k in range(len(SCHEDULES_F64)):
-        f64_cases.append(f"      case {k}: {{")
-        f64_cases += ["        " + l for l in sched_launch[("f64", k)]]
-        f64_cases.append("      } break;")
-    launch_body = "\n".join(
-        ["  if constexpr (sizeof(T) == 8) {", "    switch (schedule) {"] + f64_cases +
-        ["      default: return hipErrorInvalidValue;", "    }", "  } else {",
-         "    if (schedule != 0) return hipErrorInvalidValue;"] +
-        ["    " + l for l in sched_launch[("f32", 0)]] + ["  }"])
+        f64_cases.append(f"    case {k}: {{")
+        f64_cases += ["      " + l for l in sched_launch[("f64", k)]]
+        f64_cases.append("    } break;")
+    launch_body64 = "\n".join(["  switch (schedule) {"] + f64_cases +
+                               ["    default: return hipErrorInvalidValue;", "  }"])
+    launch_body32 = "\n".join(["  if (schedule != 0) return hipErrorInvalidValue;"] +
+                               ["  " + l for l in sched_launch[("f32", 0)]])
     # radial work per pair: distance 6, Chebyshev 3 per term, f_mu 2 per (mu, beta),
     # derivative pass adds dT and df
     nq = 8
@@ -1049,7 +1082,8 @@ def generate(lev_max, block=64):
     src = KERNEL_TEMPLATE.format(
         level=lev_max, m=len(s.funcs), ngraphs=len(s.keys), C=s.C, n_mu=s.n_mu, nu_max=s.nu_max,
         block=block, ns=ns,
-        moments_kernels="\n".join(kern_src), launch_body=launch_body,
+        moments_kernels="\n".join(["#if MTP_PART == 1"] + kern_src["f64"] + ["#else"] + kern_src["f32"] + ["#endif"]),
+        launch_body64=launch_body64, launch_body32=launch_body32,
         contraction=ind(con, 2),
         contraction_fwd=ind(con[:con.index("MTP_RELOAD_M();")], 2),
         contract_rev_kernels="",
@@ -1073,18 +1107,32 @@ def generate(lev_max, block=64):
 LEVELS = (2, 4, 6, 8, 10, 12, 14, 16)
 
 
+PARTS = (("", 0), ("_eval64", 1), ("_eval32", 2), ("_loss", 3))
+
+
 def write_all(outdir, levels=LEVELS):
+    """Writes, per level, the generated kernels (gen_levL.inc) and four
+    translation units that compile its parts (the table entry and launchers;
+    FP64 evaluation; FP32 evaluation; loss gradient), so that the parts of a
+    large basis compile in parallel."""
     os.makedirs(outdir, exist_ok=True)
     metas = {}
     files = []
+
+    def put(path, text):
+        old = open(path).read() if os.path.exists(path) else None
+        if old != text:
+            with open(path, "w") as fh:
+                fh.write(text)
+
     for L in levels:
         src, meta = generate(L)
-        path = os.path.join(outdir, f"gen_lev{L}.hip")
-        old = open(path).read() if os.path.exists(path) else None
-        if old != src:
-            with open(path, "w") as fh:
-                fh.write(src)
-        files.append(path)
+        put(os.path.join(outdir, f"gen_lev{L}.inc"), src)
+        for suffix, part in PARTS:
+            path = os.path.join(outdir, f"gen_lev{L}{suffix}.hip")
+            put(path, f"// Part {part} of the generated kernels of level {L}.\n#define MTP_PART {part}\n"
+                      f'#include "gen_lev{L}.inc"\n')
+            files.append(path)
         metas[f"lev{L}"] = meta
     reg = ["// Generated: the table of compiled bases.", '#include "mtp_variant.h"', ""]
     reg += [f"extern const mtp::BasisVariant lev{L}_variant;" for L in levels]

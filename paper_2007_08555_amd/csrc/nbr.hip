@@ -712,9 +712,13 @@ __global__ void __launch_bounds__(kSmallBlock) search_small_kernel(NbrArgs a, in
     if (red[3]) atomicAdd(&a.status->below_rmin, red[3]);
     if (red[4]) atomicAdd(&a.status->bad_species, red[4]);
   }
-  if (!lds_lists || li >= n || red[2]) return;   // on overflow the call is repeated with more slots
-  // write-out: slot by slot, consecutive atoms store consecutive records
-  // (cells with several images per neighbour stored theirs in the search)
+  // Write-out, also when an atom overflowed its K slots (the call is then
+  // repeated with more slots, but the kernels that follow in this attempt
+  // read the first K slots of every list, which must hold valid records and
+  // reverse indices).  Slot by slot, consecutive atoms store consecutive
+  // records (cells with several images per neighbour stored theirs in the
+  // search).
+  if (!lds_lists || li >= n) return;
   const int64_t i = c.start + li;
   const uint8_t* mine = lists + (size_t)li * KL;
   const int ci = scount[li];
@@ -773,6 +777,8 @@ hipError_t nbr_build(NbrArgs& a, hipStream_t s) {
     hipLaunchKernelGGL(cfg_prepare_kernel, grid_for(a.n_cfg), dim3(kBlock), 0, s, a);
   if (a.n_atoms == 0) return hipGetLastError();
   hipLaunchKernelGGL(atom_cfg_kernel, grid_for(a.n_atoms), dim3(kBlock), 0, s, a);
+  // every atom's count is written by this call (atoms of an invalid range keep 0)
+  hipLaunchKernelGGL(zero_kernel, grid_for(a.n_atoms), dim3(kBlock), 0, s, a.count, a.n_atoms);
   hipLaunchKernelGGL(zero_kernel, grid_for(a.n_atoms + 1), dim3(kBlock), 0, s, a.bin_count, a.n_atoms + 1);
   hipLaunchKernelGGL(bin_count_kernel, grid_for(a.n_atoms), dim3(kBlock), 0, s, a);
   if (a.n_cfg > 0) hipLaunchKernelGGL(bin_scan_kernel, dim3(a.n_cfg), dim3(256), 0, s, a);
