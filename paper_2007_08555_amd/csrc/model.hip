@@ -98,7 +98,7 @@ struct mtp_model {
   bool has_active = false;
   Buffer ainv, gj_work, gj_flag;
   // workspace
-  Buffer cfg, atom_cfg, atom_bin, bin_count, bin_start, bin_atoms, bin_fill, nbins_dev;
+  Buffer cfg, cfg_order, atom_cfg, atom_bin, bin_count, bin_start, bin_atoms, bin_fill, nbins_dev;
   Buffer count, nbr, pr, rev, gpair, Mbuf, Gbuf, Dbuf, site, wv, B, status, run_start;
   int K = 64;  // neighbour capacity per atom, grown on overflow
   int schedule64 = 0;  // FP64 pass split of the evaluation kernels (mtp_autotune)
@@ -354,6 +354,7 @@ int run_eval(mtp_model* M, const mtp_batch* bt, const mtp_out* out, int precisio
   NEED(M->status, sizeof(Status));
   if (n_cfg == 0) return MTP_OK;
   NEED(M->cfg, sizeof(CfgInfo) * n_cfg);
+  NEED(M->cfg_order, sizeof(int32_t) * n_cfg);
   for (Buffer* b : {&M->atom_cfg, &M->atom_bin, &M->bin_count, &M->bin_start, &M->bin_fill, &M->bin_atoms,
                     &M->count})
     NEED(*b, sizeof(int32_t) * (N + 1));
@@ -390,6 +391,7 @@ int run_eval(mtp_model* M, const mtp_batch* bt, const mtp_out* out, int precisio
     a.rmin = M->rmin;
     a.n_species = M->S;
     a.cfg = M->cfg.as<CfgInfo>();
+    a.cfg_order = M->cfg_order.as<int32_t>();
     a.atom_cfg = M->atom_cfg.as<int32_t>();
     a.atom_bin = M->atom_bin.as<int32_t>();
     a.bin_count = M->bin_count.as<int32_t>();

@@ -103,6 +103,32 @@ __global__ void cfg_prepare_kernel(NbrArgs a) {
   a.cfg[k] = c;
 }
 
+// Launch order of the small-configuration search: largest configurations
+// first (a counting sort by atom count; the order among equal counts does
+// not matter, each configuration is searched by one workgroup), so that the
+// longest workgroups do not start last.
+__global__ void __launch_bounds__(1024) cfg_order_kernel(NbrArgs a) {
+  constexpr int kBins = kSmallMax + 2;   // counts 0..kSmallMax, then larger ones
+  __shared__ int hist[kBins], base[kBins];
+  for (int b = threadIdx.x; b < kBins; b += blockDim.x) hist[b] = 0;
+  __syncthreads();
+  auto bin_of_cfg = [&](int k) {
+    const int n = a.cfg[k].n;
+    return n > kSmallMax ? kBins - 1 : kSmallMax - n;   // descending counts, large boxes last
+  };
+  for (int k = threadIdx.x; k < a.n_cfg; k += blockDim.x) atomicAdd(&hist[bin_of_cfg(k)], 1);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int acc = 0;
+    for (int b = 0; b < kBins; ++b) {
+      base[b] = acc;
+      acc += hist[b];
+    }
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < a.n_cfg; k += blockDim.x) a.cfg_order[atomicAdd(&base[bin_of_cfg(k)], 1)] = k;
+}
+
 __global__ void atom_cfg_kernel(NbrArgs a) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= a.n_atoms) return;
@@ -637,7 +663,7 @@ __global__ void __launch_bounds__(kSmallBlock) search_small_kernel(NbrArgs a, in
   __shared__ int32_t scount[kSmallMax];
   __shared__ unsigned long long red[5];
   extern __shared__ uint8_t lists[];   // [kSmallMax][K + 4] when lds_lists
-  const CfgInfo c = a.cfg[blockIdx.x];
+  const CfgInfo c = a.cfg[a.cfg_order[blockIdx.x]];
   if (!is_small(c)) return;
   const int t = threadIdx.x;
   const int n = c.n;
@@ -786,7 +812,10 @@ hipError_t nbr_build(NbrArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(bin_sort_kernel, grid_for(a.n_atoms), dim3(kBlock), 0, s, a);
   const int lds_lists = a.K <= kLdsSlots ? 1 : 0;
   const size_t lds = lds_lists ? (size_t)kSmallMax * (a.K + 4) : 0;
-  if (a.n_cfg > 0) hipLaunchKernelGGL(search_small_kernel, dim3(a.n_cfg), dim3(kSmallBlock), lds, s, a, lds_lists);
+  if (a.n_cfg > 0) {
+    hipLaunchKernelGGL(cfg_order_kernel, dim3(1), dim3(1024), 0, s, a);
+    hipLaunchKernelGGL(search_small_kernel, dim3(a.n_cfg), dim3(kSmallBlock), lds, s, a, lds_lists);
+  }
   hipLaunchKernelGGL(search_kernel, grid_for(a.n_atoms), dim3(kBlock), 0, s, a);
   const dim3 g((unsigned)((a.n_atoms + kBlock - 1) / kBlock), (unsigned)a.K);
   hipLaunchKernelGGL(reverse_kernel, g, dim3(kBlock), 0, s, a, lds_lists);
