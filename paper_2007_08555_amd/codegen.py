@@ -241,7 +241,7 @@ def graph_groups(s, budget):
 MOMENTS_TEMPLATE = r"""
 // Moments pass {pidx}: the components of degrees {nus} of one atom, summed
 // over its pairs and written to args.M.
-template <typename T, bool COMP>
+template <typename T, bool COMP, int NQ>
 __global__ void __launch_bounds__(BLOCK) moments_{tag}_kernel(const mtp::EvalArgs<T> args) {{
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* cs = reinterpret_cast<T*>(smem_raw);
@@ -282,7 +282,7 @@ __global__ void __launch_bounds__(BLOCK) moments_{tag}_kernel(const mtp::EvalArg
     }}
     const T r = sqrt(x * x + y * y + z * z);
     T f[NMP], df[NMP];
-    mtp::radial<T, NMP, false>(cs, (zi * S + zj) * nq, mu_stride, nq, r, rmin, rcut, f, df);
+    mtp::radial<T, NMP, false, NQ>(cs, (zi * S + zj) * nq, mu_stride, nq, r, rmin, rcut, f, df);
 {body}
   }}
   if constexpr (COMP) {{
@@ -475,7 +475,7 @@ ADJOINT_TEMPLATE = r"""
 // Adjoint pass {pidx} over the pairs of one atom, components of degrees {nus}:
 // its share of g = dV_i/dr_ij from G, f_mu and df_mu/dr, stored (first pass)
 // or added (later passes) per pair for the force and virial gather.
-template <typename T, bool FIRST, bool LAST>
+template <typename T, bool FIRST, bool LAST, int NQ>
 __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2)))
 adjoint_{tag}_kernel(const mtp::EvalArgs<T> args) {{
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -520,7 +520,7 @@ adjoint_{tag}_kernel(const mtp::EvalArgs<T> args) {{
     const T r = sqrt(x * x + y * y + z * z);
     const T inv_r = T(1) / r;
     T f[{nmu}], df[{nmu}];
-    mtp::radial<T, {nmu}, true>(cs, (zi * S + zj) * nq, mu_stride, nq, r, rmin, rcut, f, df);
+    mtp::radial<T, {nmu}, true, NQ>(cs, (zi * S + zj) * nq, mu_stride, nq, r, rmin, rcut, f, df);
 {body}
     const T tx = FIRST ? gx : gp0 + gx, ty = FIRST ? gy : gp1 + gy, tz = FIRST ? gz : gp2 + gz;
     args.g[3 * e] = tx;
@@ -843,7 +843,7 @@ hipError_t launch_loss_t(const void* a, const void* l, hipStream_t s) {{
 #endif  // part 3
 
 #if MTP_PART == 1 || MTP_PART == 2
-template <typename T, bool COMP, bool WANT_B>
+template <typename T, bool COMP, bool WANT_B, int NQ>
 hipError_t launch_t(const void* a, bool reuse_moments, int schedule, hipStream_t s) {{
   const auto& args = *static_cast<const mtp::EvalArgs<T>*>(a);
   if (args.n_atoms <= 0) return hipSuccess;
@@ -871,17 +871,29 @@ hipError_t eval64(unsigned flags, int schedule, const void* a, hipStream_t s) {{
   using namespace {ns};
   const bool want_b = (flags & mtp::kEvalWantB) != 0;
   const bool reuse = (flags & mtp::kEvalReuseMoments) != 0;
-  return want_b ? launch_t<double, false, true>(a, reuse, schedule, s)
-                : launch_t<double, false, false>(a, reuse, schedule, s);
+  // the pair kernels come with the radial basis size 8 fixed (unrolled) and
+  // with a run-time size
+  if (static_cast<const mtp::EvalArgs<double>*>(a)->nq == 8)
+    return want_b ? launch_t<double, false, true, 8>(a, reuse, schedule, s)
+                  : launch_t<double, false, false, 8>(a, reuse, schedule, s);
+  return want_b ? launch_t<double, false, true, 0>(a, reuse, schedule, s)
+                : launch_t<double, false, false, 0>(a, reuse, schedule, s);
 }}
 #elif MTP_PART == 2
 hipError_t eval32(int precision, unsigned flags, int schedule, const void* a, hipStream_t s) {{
   using namespace {ns};
   const bool want_b = (flags & mtp::kEvalWantB) != 0;
   const bool reuse = (flags & mtp::kEvalReuseMoments) != 0;
+  if (static_cast<const mtp::EvalArgs<float>*>(a)->nq == 8) {{
+    if (precision == 2)
+      return want_b ? launch_t<float, true, true, 8>(a, reuse, schedule, s)
+                    : launch_t<float, true, false, 8>(a, reuse, schedule, s);
+    return want_b ? launch_t<float, false, true, 8>(a, reuse, schedule, s)
+                  : launch_t<float, false, false, 8>(a, reuse, schedule, s);
+  }}
   if (precision == 2)
-    return want_b ? launch_t<float, true, true>(a, reuse, schedule, s) : launch_t<float, true, false>(a, reuse, schedule, s);
-  return want_b ? launch_t<float, false, true>(a, reuse, schedule, s) : launch_t<float, false, false>(a, reuse, schedule, s);
+    return want_b ? launch_t<float, true, true, 0>(a, reuse, schedule, s) : launch_t<float, true, false, 0>(a, reuse, schedule, s);
+  return want_b ? launch_t<float, false, true, 0>(a, reuse, schedule, s) : launch_t<float, false, false, 0>(a, reuse, schedule, s);
 }}
 #elif MTP_PART == 3
 hipError_t loss(int precision, const void* a, const void* l, hipStream_t s) {{
@@ -962,7 +974,8 @@ def generate(lev_max, block=64):
             kern_src[prec].append(MOMENTS_TEMPLATE.format(pidx=pidx, nus=nus, tag=tag, ncomp=len(comps), nmu=nmu,
                                                     comp_list=", ".join(map(str, comps)),
                                                     body="\n".join(" " * 4 + l for l in body)))
-            mom_lines.append(f"hipLaunchKernelGGL((moments_{tag}_kernel<T, COMP>), grid, dim3(BLOCK), smem, s, args);")
+            # (the moments passes measured no faster with the unrolled radial basis)
+            mom_lines.append(f"hipLaunchKernelGGL((moments_{tag}_kernel<T, COMP, 0>), grid, dim3(BLOCK), smem, s, args);")
         # reverse sweep passes by degree groups: each pass holds only the
         # moments and dV/dg its components need
         groups = [tuple(n for n in grp if n <= s.nu_max) for grp in sch["rev"]]
@@ -995,7 +1008,7 @@ def generate(lev_max, block=64):
                                                     body="\n".join(" " * 4 + l for l in body)))
             first = "true" if pidx == 0 else "false"
             last = "true" if pidx == len(passes) - 1 else "false"
-            adj_lines.append(f"hipLaunchKernelGGL((adjoint_{tag}_kernel<T, {first}, {last}>), "
+            adj_lines.append(f"hipLaunchKernelGGL((adjoint_{tag}_kernel<T, {first}, {last}, NQ>), "
                              f"grid, dim3(BLOCK), smem, s, args);")
         body = (["if (!reuse_moments) {"] + ["  " + l for l in mom_lines] + ["}"] +
                 ["hipLaunchKernelGGL((contract_fwd_kernel<T, WANT_B>), grid, dim3(BLOCK), 0, s, args);"] +

@@ -56,9 +56,12 @@ struct EvalArgs {
 // f_mu and, when DERIV, df_mu/dr for the NMU radial functions of one pair.
 // cs points at c staged in LDS; base = ((0 * S + zi) * S + zj) * nq and the
 // stride between consecutive mu is S * S * nq.
-template <typename T, int NMU, bool DERIV>
+// NQ > 0 fixes the radial basis size at compile time (nq is then ignored
+// and the recurrence is unrolled); NQ = 0 takes nq at run time.
+template <typename T, int NMU, bool DERIV, int NQ = 0>
 __device__ __forceinline__ void radial(const T* __restrict__ cs, int base, int mu_stride, int nq,
                                        T r, T rmin, T rcut, T (&f)[NMU], T (&df)[NMU]) {
+  if constexpr (NQ > 0) nq = NQ;
   const T span_inv = T(1) / (rcut - rmin);
   const T x = (T(2) * r - rmin - rcut) * span_inv;
   const T dxdr = T(2) * span_inv;
@@ -71,7 +74,8 @@ __device__ __forceinline__ void radial(const T* __restrict__ cs, int base, int m
   }
   T t_prev = T(1), t_cur = x;                     // T_0, T_1
   T d_prev = T(0), d_cur = T(1);                  // dT_0/dx, dT_1/dx
-  for (int b = 1; b < nq; ++b) {
+#pragma unroll
+  for (int b = 1; b < (NQ > 0 ? NQ : nq); ++b) {
 #pragma unroll
     for (int mu = 0; mu < NMU; ++mu) {
       const T cb = cs[base + mu * mu_stride + b];
