@@ -58,7 +58,22 @@ def measured_traffic():
     return float(fields["traffic_bytes_per_launch"])
 
 
-def training_extras(P, pot_path, precision):
+def training_level20():
+    """The training workload at its own basis, level 20 (1024 configurations
+    of 32-128 atoms, three species, targets from the reference potential
+    plus noise), when the library was built with level 20."""
+    from paper_2007_08555_amd import Potential
+    from paper_2007_08555_amd._lib import MTPError
+    pdir = os.path.join(ROOT, "tests", "golden", "potentials")
+    try:
+        P = Potential(os.path.join(pdir, "lev20_s3.mtp"))
+    except MTPError:
+        return {"note": "level 20 is not compiled into this build (MTP_EXTRA_LEVELS=20 adds it)"}
+    return training_extras(P, os.path.join(pdir, "lev20_s3.mtp"), "fp64",
+                           ref_path=os.path.join(pdir, "lev20_s3_ref.mtp"))
+
+
+def training_extras(P, pot_path, precision, ref_path=None):
     """The training-side rows on a batch shaped like the paper's training
     sets (1024 configurations of 32-128 atoms, three species): loss and
     gradient in all parameters (mtp_loss_grad), and the normal equations in
@@ -73,14 +88,18 @@ def training_extras(P, pot_path, precision):
     tb = synth.mixed_batch(seed=4, n_configs=1024, n_min=32, n_max=128, n_species_model=3)
     n_atoms = int(tb["n_atoms"].sum())
     B = Batch.from_arrays(tb, "cuda:0")
-    c, xi = P.get_params()
-    P.set_params(xi=xi * 1.1)
-    ref = P.eval(B, precision="fp64", forces=True, virial=True)
-    P.set_params(xi=xi)
+    if ref_path is None:
+        c, xi = P.get_params()
+        P.set_params(xi=xi * 1.1)
+        ref = P.eval(B, precision="fp64", forces=True, virial=True)
+        P.set_params(xi=xi)
+    else:
+        from paper_2007_08555_amd import Potential
+        ref = Potential(ref_path).eval(B, precision="fp64", forces=True, virial=True)
     g = torch.Generator(device="cuda:0").manual_seed(0)
     noise = lambda t: t + 1e-3 * torch.randn(t.shape, generator=g, device=t.device, dtype=t.dtype)
     Et, Ft, Wt = noise(ref["energy"]), noise(ref["forces"]), noise(ref["virial"])
-    res = {"workload": f"1024 configurations, 32-128 atoms ({n_atoms} atoms), 3 species, level 16, FP64",
+    res = {"workload": f"1024 configurations, 32-128 atoms ({n_atoms} atoms), 3 species, level {P.level}, FP64",
            "atoms": n_atoms}
     for name, fn in (("loss_grad", lambda: P.loss_grad(B, Et, Ft, Wt, precision="fp64")),
                      ("normal_equations", lambda: P.solve_normal(*P.normal_equations(B, Et, Ft, Wt)[:2]))):
@@ -95,6 +114,51 @@ def training_extras(P, pot_path, precision):
         res[name] = {"ms_per_call": dt * 1e3, "atom_evals_per_s": n_atoms / dt}
     res["normal_equations"]["note"] = f"m = {P.m} evaluations with xi = e_alpha, Gram product and solve"
     return res
+
+
+_POOL = {}
+
+
+def _pool_init(sample, pot_path):
+    from threadpoolctl import threadpool_limits
+
+    from oracle.potential import read_potential
+    _POOL["limits"] = threadpool_limits(limits=1)   # one thread per worker process
+    _POOL["sample"], _POOL["pot"] = sample, read_potential(pot_path)
+
+
+def _pool_eval(k):
+    import synth
+    from oracle import mtp as omtp
+    omtp.evaluate(_POOL["pot"], *synth.config_of(_POOL["sample"], k))
+    return int(_POOL["sample"]["n_atoms"][k])
+
+
+def cpu_baseline_pool(batch, pot_path, rate1, budget_s):
+    """The same oracle in one single-threaded worker process per host core
+    (at most 16), over whole configurations from the start of the batch,
+    sized for about budget_s seconds of wall time."""
+    import concurrent.futures as cf
+    import multiprocessing as mp
+
+    import synth
+    cores = min(16, len(os.sched_getaffinity(0)))
+    target = rate1 * cores * budget_s
+    n_cfg, atoms = 0, 0
+    while n_cfg < len(batch["n_atoms"]) and atoms < target:
+        atoms += int(batch["n_atoms"][n_cfg])
+        n_cfg += 1
+    sample = synth.subset(batch, list(range(n_cfg)))
+    # fresh interpreters (spawn): the workers never touch the GPU
+    with cf.ProcessPoolExecutor(max_workers=cores, mp_context=mp.get_context("spawn"),
+                                initializer=_pool_init, initargs=(sample, pot_path)) as ex:
+        list(ex.map(abs, range(4 * cores)))   # start every worker
+        t0 = time.perf_counter()
+        done = sum(ex.map(_pool_eval, range(n_cfg), chunksize=2))
+        dt = time.perf_counter() - t0
+    return {"value": done / dt, "unit": "atom-evals/s", "cores": cores, "kind": "oracle",
+            "sample": f"first {n_cfg} configurations ({done} atoms) of the benchmark batch, E+F+virial in FP64, "
+                      f"{dt:.1f} s on {cores} worker processes of one thread each"}
 
 
 def cpu_baseline(batch, pot_path, budget_s):
@@ -274,24 +338,47 @@ def main():
                          "note": "one mtp_eval call per configuration on the first configurations of the batch"}
         line["batched_over_plain"] = value / (atoms_p / tp)
         log(f"plain: {atoms_p / tp:.4g} atom-evals/s")
-        # the single 16 000-atom bcc box (two species)
+        # the 16 000-atom bcc box (two species) as 100 MD-style steps: before
+        # each step after the first every coordinate moves by N(0, 0.002^2) A,
+        # then neighbour lists, E, F and virial; FP32 (the workload's precision)
+        # and FP64
         box = synth.bcc_alloy(seed=0)
         P2 = Potential(os.path.join(ROOT, "tests", "golden", "potentials", "lev16_s2.mtp"), device=0)
         Bb = Batch.from_arrays(box, "cuda:0")
-        for _ in range(2):
-            P2.eval(Bb, precision=a.precision, stream=stream)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(10):
-            P2.eval(Bb, precision=a.precision, stream=stream)
-        torch.cuda.synchronize()
-        tb = (time.perf_counter() - t0) / 10
-        line["bcc16000"] = {"value": 16000 / tb, "unit": "atom-evals/s", "ms_per_step": tb * 1e3}
-        log(f"bcc16000: {16000 / tb:.4g} atom-evals/s")
+        nb = int(box["n_atoms"][0])
+        jit = torch.as_tensor(np.stack(list(synth.md_jitter(1, nb, 99))), device="cuda:0")
+        pos0 = Bb.pos.clone()
+        line["bcc16000"] = {"workload": f"{nb}-atom periodic bcc box, 2 species, level 16, 100 MD-style steps "
+                                        f"(jitter N(0, 0.002^2) A per step, lists rebuilt every step)"}
+        for prec in ("fp32", "fp64"):
+            for _ in range(2):
+                P2.eval(Bb, precision=prec, stream=stream)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for t in range(100):
+                if t:
+                    Bb.pos.add_(jit[t - 1])
+                P2.eval(Bb, precision=prec, stream=stream)
+            torch.cuda.synchronize()
+            tb = (time.perf_counter() - t0) / 100
+            Bb.pos.copy_(pos0)
+            P2.set_timing(True)
+            P2.eval(Bb, precision=prec, stream=stream)
+            st2 = P2.stats()
+            P2.set_timing(False)
+            line["bcc16000"][prec] = {"value": nb / tb, "unit": "atom-evals/s", "ms_per_step": tb * 1e3,
+                                      "phase_ms": {k: st2[k] for k in ("ms_neighbours", "ms_eval", "ms_forces",
+                                                                        "ms_reduce")}}
+            log(f"bcc16000 {prec}: {nb / tb:.4g} atom-evals/s, {tb * 1e3:.3f} ms/step")
         line["training"] = training_extras(P, pot_path, a.precision)
         log(f"training: {line['training']}")
+        line["training_level20"] = training_level20()
+        log(f"training, level 20: {line['training_level20']}")
         line["cpu_baseline"] = cpu_baseline(batch, pot_path, a.cpu_seconds)
         log(f"cpu baseline: {line['cpu_baseline']}")
+        line["cpu_baseline"]["all_cores"] = cpu_baseline_pool(batch, pot_path, line["cpu_baseline"]["value"],
+                                                              a.cpu_seconds)
+        log(f"cpu baseline, all cores: {line['cpu_baseline']['all_cores']}")
     print(json.dumps(line), flush=True)
 
 

@@ -79,7 +79,12 @@ def build(levels=None, jobs=None, verbose=True):
     if not os.path.exists(HIPCC):
         raise RuntimeError(f"hipcc not found at {HIPCC}")
     os.makedirs(BUILD, exist_ok=True)
-    gen_files, _ = codegen.write_all(GEN, levels=levels or codegen.LEVELS)
+    if levels is None:
+        # MTP_EXTRA_LEVELS (e.g. "18,20") adds larger bases, whose kernels
+        # take minutes to compile (level 20: about 10 minutes per part)
+        extra = [int(v) for v in os.environ.get("MTP_EXTRA_LEVELS", "").replace(",", " ").split()]
+        levels = tuple(sorted(set(codegen.LEVELS) | set(extra)))
+    gen_files, _ = codegen.write_all(GEN, levels=levels)
     sources = [os.path.join(CSRC, f) for f in sorted(os.listdir(CSRC)) if f.endswith(".hip")]
     sources += [f for f in gen_files if f.endswith((".hip", ".cpp"))]
     jobs = jobs or min(8, os.cpu_count() or 4)

@@ -1,0 +1,64 @@
+"""Level 20 (the training workload's basis: 460 functions, 295 moment
+components), when the library was built with it (MTP_EXTRA_LEVELS=20):
+evaluation and the loss gradient against the FP64 oracle, with targets from
+a seeded reference potential plus N(0, 1e-3^2) noise."""
+import numpy as np
+import pytest
+
+import synth
+from gpu_common import errors, gpu_batch, log, oracle_batch, pot_path
+from oracle import loss as ol
+from oracle import mtp as omtp
+from oracle.potential import read_potential
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = {"energy_per_atom": 1e-11, "site": 1e-11, "force": 1e-10, "virial": 1e-9, "b_rel": 1e-11}
+
+
+@pytest.fixture(scope="module")
+def lev20():
+    from paper_2007_08555_amd import Potential
+    from paper_2007_08555_amd._lib import MTPError
+    try:
+        return Potential(pot_path("lev20_s3"))
+    except MTPError as e:
+        pytest.skip(f"level 20 is not compiled into this library ({e})")
+
+
+def test_level20_evaluation(lev20):
+    pot = read_potential(pot_path("lev20_s3"))
+    batch = synth.mixed_batch(seed=51, n_configs=6, n_min=8, n_max=32, n_species_model=3)
+    g = gpu_batch(lev20, batch, "fp64")
+    rep = errors(batch, g, oracle_batch(pot, batch))
+    log(f"[lev20 fp64] {rep}")
+    for k, v in TOL64.items():
+        assert rep[k] <= v, (k, rep[k])
+
+
+def test_level20_loss_gradient(lev20):
+    from paper_2007_08555_amd import Batch
+    pot = read_potential(pot_path("lev20_s3"))
+    ref = read_potential(pot_path("lev20_s3_ref"))
+    batch = synth.mixed_batch(seed=52, n_configs=4, n_min=8, n_max=20, n_species_model=3)
+    rng = np.random.default_rng(6)
+    E, F, W = [], [], []
+    for k in range(len(batch["n_atoms"])):
+        r = omtp.evaluate(ref, *synth.config_of(batch, k))
+        E.append(r["energy"] + rng.normal(0, 1e-3))
+        F.append(r["forces"] + rng.normal(0, 1e-3, r["forces"].shape))
+        W.append(r["virial"] + rng.normal(0, 1e-3, (3, 3)))
+    tg = {"energy": np.array(E), "forces": np.concatenate(F), "virial": np.array(W)}
+    w = dict(w_e=1.0, w_f=0.01, w_s=0.001, scaling="vibrations")
+    loss, grad = lev20.loss_grad(Batch.from_arrays(batch), tg["energy"], tg["forces"], tg["virial"],
+                                 precision="fp64", **w)
+    loss, grad = loss.item(), grad.cpu().numpy()
+    L_o = ol.loss(pot, batch, tg, **w)
+    m, nc = len(pot["xi"]), pot["c"].size
+    idx = sorted(set(rng.choice(m, size=12, replace=False).tolist()) |
+                 set((m + rng.choice(nc, size=12, replace=False)).tolist()))
+    g_o = ol.loss_grad(pot, batch, tg, indices=idx, **w)
+    err = np.abs(grad[idx] - g_o) / np.abs(g_o).max()
+    log(f"[lev20 loss] gpu {loss:.10e} oracle {L_o:.10e}; grad max rel err {err.max():.3e}")
+    assert abs(loss - L_o) <= 1e-10 * abs(L_o)
+    assert err.max() <= 1e-8
