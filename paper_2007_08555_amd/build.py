@@ -38,7 +38,43 @@ FLAGS = [
     "-I", CSRC, "-I", os.path.join(ROOT, "include"),
     "-Wno-unused-result",
 ]
-HEADERS = ["mtp_device.h", "mtp_internal.h", "mtp_variant.h"]
+
+
+_PART_IF = re.compile(rb"#(el)?if\s+(MTP_PART\s*==\s*\d+(\s*\|\|\s*MTP_PART\s*==\s*\d+)*)\s*$")
+
+
+def _part_text(text, part):
+    """The lines of a generated kernel file that part `part` compiles: the
+    sections under `#if MTP_PART == a || ...` / `#elif` / `#else` are kept
+    only where they select `part`; every other line (other conditionals
+    included) is kept."""
+    out, stack = [], []   # stack entries: [is_part_if, active, taken]
+    for line in text.split(b"\n"):
+        t = line.strip()
+        m = _PART_IF.match(t)
+        if m and not m.group(1):
+            hit = part in [int(v) for v in re.findall(rb"\d+", m.group(2))]
+            stack.append([True, hit, hit])
+            continue
+        if stack and stack[-1][0]:
+            if m and m.group(1):
+                hit = part in [int(v) for v in re.findall(rb"\d+", m.group(2))]
+                stack[-1][1] = hit and not stack[-1][2]
+                stack[-1][2] |= hit
+                continue
+            if t.startswith(b"#else"):
+                stack[-1][1] = not stack[-1][2]
+                stack[-1][2] = True
+                continue
+        if t.startswith((b"#if", b"#ifdef", b"#ifndef")):
+            stack.append([False, True, True])
+        elif t.startswith(b"#endif"):
+            top = stack.pop()
+            if top[0]:
+                continue
+        if all(e[1] for e in stack):
+            out.append(line)
+    return b"\n".join(out)
 
 
 def _hash(path, extra):
@@ -46,17 +82,41 @@ def _hash(path, extra):
     with open(path, "rb") as fh:
         text = fh.read()
     h.update(text)
-    # a generated part includes the level's kernel body
+    # a generated part includes the level's kernel file, of which it compiles
+    # only its own sections: a change elsewhere in that file keeps its object
+    m = re.search(rb"#define MTP_PART (\d+)", text)
+    scanned = text
     for inc in re.findall(rb'#include "(gen_lev\d+\.inc)"', text):
         with open(os.path.join(os.path.dirname(path), inc.decode()), "rb") as fh:
+            body = fh.read()
+        part = _part_text(body, int(m.group(1))) if m else body
+        h.update(part)
+        scanned += part
+    # the project headers the file includes, directly or through others
+    for dep in _includes(scanned):
+        with open(dep, "rb") as fh:
             h.update(fh.read())
-    for hd in HEADERS:
-        with open(os.path.join(CSRC, hd), "rb") as fh:
-            h.update(fh.read())
-    with open(os.path.join(ROOT, "include", "mtp.h"), "rb") as fh:
-        h.update(fh.read())
     h.update(" ".join(extra).encode())
     return h.hexdigest()[:16]
+
+
+def _includes(text):
+    """Paths of the project headers reachable from `text` by #include "..."
+    (the generated kernel files themselves excluded), in a fixed order."""
+    found, todo = [], [text]
+    while todo:
+        for name in re.findall(rb'#include "([^"]+)"', todo.pop()):
+            name = name.decode()
+            if name.startswith("gen_lev"):
+                continue
+            for d in (CSRC, os.path.join(ROOT, "include")):
+                path = os.path.join(d, name)
+                if os.path.exists(path) and path not in found:
+                    found.append(path)
+                    with open(path, "rb") as fh:
+                        todo.append(fh.read())
+                    break
+    return sorted(found)
 
 
 def _compile(src):

@@ -152,7 +152,7 @@ REVERSE_TEMPLATE = r"""
 // Reverse sweep, pass {pidx}: G = dV/dM for the components of degrees {nus}
 // from the moments they pair with and dV/dg of the graphs they occur in.
 template <typename T>
-__global__ void __launch_bounds__(BLOCK) contract_rev_{tag}_kernel(const mtp::EvalArgs<T> args) {{
+__global__ void __launch_bounds__(BLOCK){attr} contract_rev_{tag}_kernel(const mtp::EvalArgs<T> args) {{
   const int i = blockIdx.x * BLOCK + threadIdx.x;
   if (i >= args.n_atoms) return;
   T M[C];
@@ -944,6 +944,7 @@ extern const mtp::BasisVariant {ns}_variant = {{
 # library times them on the caller's batch (mtp_autotune) and keeps the
 # fastest; schedule 0 is the default.
 SCHEDULES_F64 = [
+    {"mom": 85, "rev": [(0, 1, 2), (3, 4), (5, 6)], "adj": 90},
     {"mom": 85, "rev": [(0, 1), (2,), (3, 4), (5, 6)], "adj": 90},
     {"mom": 50, "rev": [(0,), (1,), (2,), (3,), (4,), (5,), (6,)], "adj": 50},
 ]
@@ -988,6 +989,9 @@ def generate(lev_max, block=64):
             body, m_used, g_used = emit_reverse_pass(s, ks)
             kern_src[prec].append(REVERSE_TEMPLATE.format(
                 pidx=pidx, nus=list(grp), tag=tag,
+                # FP64 passes: two wavefronts per SIMD (a pass just above 256
+                # registers spills a few words rather than halving occupancy)
+                attr=" __attribute__((amdgpu_waves_per_eu(2)))" if prec == "f64" else "",
                 load_m="\n".join(f"  M[{q}] = args.M[(size_t){q} * args.stride + i];" for q in m_used),
                 load_dg="\n".join(f"  const T dg{g} = args.D[(size_t){g} * args.stride + i];" for g in g_used),
                 fence=" ".join(f'asm volatile("" : "+v"(M[{q}]));' for q in m_used),

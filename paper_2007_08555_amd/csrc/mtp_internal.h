@@ -27,6 +27,7 @@ struct Status {
   unsigned long long bad_species; // species index outside [0, n_species)
   unsigned long long n_pairs;     // total neighbour pairs of the last search
   unsigned long long overflow;    // atoms with more neighbours than the ELL capacity
+  unsigned long long n_binned;    // atoms of binned configurations (entries of NbrArgs::binned)
 };
 
 struct NbrArgs {
@@ -47,6 +48,7 @@ struct NbrArgs {
   int32_t* bin_start;    // [n_atoms + 1]
   int32_t* bin_atoms;    // [n_atoms] atoms sorted by bin, then index
   int32_t* bin_fill;     // [n_atoms + 1] scratch cursor
+  int32_t* binned;       // [n_atoms] atoms of binned configurations, in no particular order
   int32_t* count;        // [n_atoms] neighbours per atom (clamped to K)
   int stride;            // ELL pitch (>= n_atoms)
   int K;                 // ELL slots per atom

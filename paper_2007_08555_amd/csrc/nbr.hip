@@ -196,6 +196,7 @@ __global__ void bin_count_kernel(NbrArgs a) {
   const int64_t flat = c.bin0 + ((int64_t)b.x * c.nb[1] + b.y) * c.nb[2] + b.z;
   a.atom_bin[i] = (int32_t)flat;
   atomicAdd(&a.bin_count[flat], 1);
+  a.binned[atomicAdd(&a.status->n_binned, 1ull)] = (int32_t)i;
 }
 
 // Exclusive scan of the bin counts of one binned configuration (one block
@@ -264,6 +265,19 @@ __global__ void bin_sort_kernel(NbrArgs a) {
   }
 }
 
+// Pair vector to the nearest image of atom j in a binned configuration (at
+// most one image lies within R_cut): n = -rint(d . L^-1), r = d + n . L.
+__device__ inline void binned_vector(const CfgInfo& c, double dx, double dy, double dz, double& rx, double& ry,
+                                     double& rz) {
+  const double* L = c.L;
+  const double* inv = c.inv;
+  double n[3];
+  for (int d = 0; d < 3; ++d) n[d] = -rint(dx * inv[0 * 3 + d] + dy * inv[1 * 3 + d] + dz * inv[2 * 3 + d]);
+  rx = dx + (n[0] * L[0] + n[1] * L[3] + n[2] * L[6]);
+  ry = dy + (n[0] * L[1] + n[1] * L[4] + n[2] * L[7]);
+  rz = dz + (n[0] * L[2] + n[1] * L[5] + n[2] * L[8]);
+}
+
 struct Emitter {
   NbrArgs& a;
   int64_t i;
@@ -297,7 +311,8 @@ __global__ void __launch_bounds__(kBlock) search_kernel(NbrArgs a) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   // atoms of small configurations are searched by search_small_kernel; every
   // lane stays to the end for the wavefront reductions
-  const bool active = i < a.n_atoms && !(is_small(a.cfg[a.atom_cfg[i]]) && in_cfg(a.cfg[a.atom_cfg[i]], i));
+  const bool active = i < a.n_atoms && !((is_small(a.cfg[a.atom_cfg[i]]) || a.cfg[a.atom_cfg[i]].binned) &&
+                                         in_cfg(a.cfg[a.atom_cfg[i]], i));
   Emitter emit{a, i, 0, a.rmin * a.rmin, 0};
   int bad = 0;
   if (active) {
@@ -333,30 +348,6 @@ __global__ void __launch_bounds__(kBlock) search_kernel(NbrArgs a) {
               if (r2 < rc2) emit((int32_t)j, rx, ry, rz, r2);
             }
       }
-    } else {
-      const int3 b = bin_of(c, xi, yi, zi);
-      for (int ox = -1; ox <= 1; ++ox)
-        for (int oy = -1; oy <= 1; ++oy)
-          for (int oz = -1; oz <= 1; ++oz) {
-            const int bx = (b.x + ox + c.nb[0]) % c.nb[0];
-            const int by = (b.y + oy + c.nb[1]) % c.nb[1];
-            const int bz = (b.z + oz + c.nb[2]) % c.nb[2];
-            const int64_t flat = c.bin0 + ((int64_t)bx * c.nb[1] + by) * c.nb[2] + bz;
-            const int32_t s0 = a.bin_start[flat], s1 = a.bin_start[flat + 1];
-            for (int32_t t = s0; t < s1; ++t) {
-              const int32_t j = a.bin_atoms[t];
-              if (j == i) continue;
-              const double dx = a.pos[3 * j] - xi, dy = a.pos[3 * j + 1] - yi, dz = a.pos[3 * j + 2] - zi;
-              double n[3];
-              for (int d = 0; d < 3; ++d)
-                n[d] = -rint(dx * inv[0 * 3 + d] + dy * inv[1 * 3 + d] + dz * inv[2 * 3 + d]);
-              const double rx = dx + (n[0] * L[0] + n[1] * L[3] + n[2] * L[6]);
-              const double ry = dy + (n[0] * L[1] + n[1] * L[4] + n[2] * L[7]);
-              const double rz = dz + (n[0] * L[2] + n[1] * L[5] + n[2] * L[8]);
-              const double r2 = rx * rx + ry * ry + rz * rz;
-              if (r2 < rc2) emit(j, rx, ry, rz, r2);
-            }
-          }
     }
   }
   a.count[i] = emit.count < a.K ? emit.count : a.K;
@@ -373,6 +364,127 @@ __global__ void __launch_bounds__(kBlock) search_kernel(NbrArgs a) {
     if (over) atomicAdd(&a.status->overflow, (unsigned long long)over);
     if (below) atomicAdd(&a.status->below_rmin, (unsigned long long)below);
     if (nbad) atomicAdd(&a.status->bad_species, (unsigned long long)nbad);
+  }
+}
+
+// Binned configurations, one wavefront per atom.  The candidates are the
+// atoms of the 27 bins around the atom's bin, bins in the order
+// (ox, oy, oz) = -1..1 and atoms of a bin in ascending index.  Lane s < 27
+// loads the range of bin s, a scan over the lanes numbers the candidates, and
+// each round tests 64 consecutive candidates, one per lane; a ballot ranks
+// the neighbours found, so the list keeps the candidate order.  A fixed grid
+// walks the atoms listed in a.binned (their number is in the status), and
+// each workgroup adds its counts to the status once.  All cross-lane
+// operations run with every lane active.
+constexpr int kBinnedBlocks = 256;
+constexpr int kBinnedBlock = 1024;
+
+__global__ void __launch_bounds__(kBinnedBlock) search_binned_kernel(NbrArgs a) {
+  const int lane = threadIdx.x & 63;
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int64_t n_waves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  const int64_t n_binned = (int64_t)a.status->n_binned;
+  const double rc2 = a.rcut * a.rcut, rmin2 = a.rmin * a.rmin;
+  int pairs = 0, cmax = 0, over = 0, nbad = 0, below = 0;
+  for (int64_t k = wave; k < n_binned; k += n_waves) {
+    const int64_t i = a.binned[k];
+    const CfgInfo& c = a.cfg[a.atom_cfg[i]];
+    const double xi = a.pos[3 * i], yi = a.pos[3 * i + 1], zi = a.pos[3 * i + 2];
+    const int3 b = bin_of(c, xi, yi, zi);
+    int start = 0, size = 0;
+    if (lane < 27) {
+      const int ox = lane / 9 - 1, oy = (lane / 3) % 3 - 1, oz = lane % 3 - 1;
+      const int bx = (b.x + ox + c.nb[0]) % c.nb[0];
+      const int by = (b.y + oy + c.nb[1]) % c.nb[1];
+      const int bz = (b.z + oz + c.nb[2]) % c.nb[2];
+      const int64_t flat = c.bin0 + ((int64_t)bx * c.nb[1] + by) * c.nb[2] + bz;
+      start = a.bin_start[flat];
+      size = a.bin_start[flat + 1] - start;
+    }
+    int incl = size;   // inclusive scan over lanes 0..26 (lanes above hold 0)
+    for (int o = 1; o < 32; o <<= 1) {
+      const int v = __shfl_up(incl, o, 64);
+      if (lane >= o) incl += v;
+    }
+    const int total = __shfl(incl, 26, 64);
+    const int excl = incl - size;
+    int count = 0;
+    for (int base = 0; base < total; base += 64) {
+      const int cand = base + lane;
+      // first bin s with incl_s > cand: it holds candidate cand
+      int lo = 0, hi = 27;
+      for (int it = 0; it < 5; ++it) {
+        const int mid = (lo + hi) >> 1;
+        const int v = __shfl(incl, mid < 26 ? mid : 26, 64);
+        if (lo < hi) {
+          if (v > cand) hi = mid; else lo = mid + 1;
+        }
+      }
+      const int sb = lo < 26 ? lo : 26;
+      const int st = __shfl(start, sb, 64), ex = __shfl(excl, sb, 64);
+      bool hit = false;
+      int32_t j = -1;
+      double rx = 0.0, ry = 0.0, rz = 0.0, r2 = 0.0;
+      if (cand < total) {
+        j = a.bin_atoms[st + (cand - ex)];
+        if (j != (int32_t)i) {
+          const double dx = a.pos[3 * j] - xi, dy = a.pos[3 * j + 1] - yi, dz = a.pos[3 * j + 2] - zi;
+          binned_vector(c, dx, dy, dz, rx, ry, rz);
+          r2 = rx * rx + ry * ry + rz * rz;
+          hit = r2 < rc2;
+        }
+      }
+      const unsigned long long mask = __ballot(hit);
+      const int slot = count + __popcll(mask & ((1ull << lane) - 1ull));
+      if (hit && slot < a.K) {
+        const size_t e = (size_t)slot * a.stride + i;
+        int zj = a.species[j];
+        zj = zj < 0 ? 0 : (zj >= a.n_species ? a.n_species - 1 : zj);
+        a.nbr[e] = j;
+        store_pair(a, e, rx, ry, rz, zj);
+      }
+      if (hit && r2 < rmin2) ++below;
+      count += __popcll(mask);
+    }
+    if (lane == 0) {
+      a.count[i] = count < a.K ? count : a.K;
+      if (a.species[i] < 0 || a.species[i] >= a.n_species) ++nbad;
+    }
+    pairs += count;
+    cmax = count > cmax ? count : cmax;
+    if (count > a.K) ++over;
+  }
+  below = wave_sum(below);
+  nbad = wave_sum(nbad);
+  // per-wavefront counts (uniform across the lanes) summed over the workgroup
+  constexpr int kWaves = kBinnedBlock / 64;
+  __shared__ int part[5][kWaves];
+  const int w = threadIdx.x >> 6;
+  if (lane == 0) {
+    part[0][w] = pairs;
+    part[1][w] = cmax;
+    part[2][w] = over;
+    part[3][w] = below;
+    part[4][w] = nbad;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long tp = 0, to = 0, tb = 0, tn = 0;
+    int tm = 0;
+    for (int q = 0; q < kWaves; ++q) {
+      tp += part[0][q];
+      tm = part[1][q] > tm ? part[1][q] : tm;
+      to += part[2][q];
+      tb += part[3][q];
+      tn += part[4][q];
+    }
+    if (tp || tn) {
+      atomicMax(&a.status->max_count, (unsigned long long)tm);
+      atomicAdd(&a.status->n_pairs, tp);
+      if (to) atomicAdd(&a.status->overflow, to);
+      if (tb) atomicAdd(&a.status->below_rmin, tb);
+      if (tn) atomicAdd(&a.status->bad_species, tn);
+    }
   }
 }
 
@@ -724,12 +836,16 @@ __global__ void __launch_bounds__(kSmallBlock) search_small_kernel(NbrArgs a, in
     a.count[i] = count < a.K ? count : a.K;
     scount[li] = count < a.K ? count : a.K;
   }
-  const int over = count > a.K ? 1 : 0;
-  atomicMax(&red[0], (unsigned long long)count);
-  atomicAdd(&red[1], (unsigned long long)count);
-  if (over) atomicAdd(&red[2], 1ull);
-  if (below) atomicAdd(&red[3], (unsigned long long)below);
-  if (bad) atomicAdd(&red[4], 1ull);
+  // counts summed over the wavefront first: one LDS atomic per wavefront
+  const int wmax = wave_max(count), wsum = wave_sum(count), wover = wave_sum(count > a.K ? 1 : 0);
+  const int wbelow = wave_sum(below), wbad = wave_sum(bad);
+  if ((t & 63) == 0) {
+    atomicMax(&red[0], (unsigned long long)wmax);
+    atomicAdd(&red[1], (unsigned long long)wsum);
+    if (wover) atomicAdd(&red[2], (unsigned long long)wover);
+    if (wbelow) atomicAdd(&red[3], (unsigned long long)wbelow);
+    if (wbad) atomicAdd(&red[4], (unsigned long long)wbad);
+  }
   __syncthreads();  // LDS lists and counts of the whole configuration are complete
   if (t == 0) {
     atomicMax(&a.status->max_count, red[0]);
@@ -817,6 +933,7 @@ hipError_t nbr_build(NbrArgs& a, hipStream_t s) {
     hipLaunchKernelGGL(search_small_kernel, dim3(a.n_cfg), dim3(kSmallBlock), lds, s, a, lds_lists);
   }
   hipLaunchKernelGGL(search_kernel, grid_for(a.n_atoms), dim3(kBlock), 0, s, a);
+  hipLaunchKernelGGL(search_binned_kernel, dim3(kBinnedBlocks), dim3(kBinnedBlock), 0, s, a);
   const dim3 g((unsigned)((a.n_atoms + kBlock - 1) / kBlock), (unsigned)a.K);
   hipLaunchKernelGGL(reverse_kernel, g, dim3(kBlock), 0, s, a, lds_lists);
   return hipGetLastError();

@@ -81,12 +81,38 @@ __global__ void __launch_bounds__(kBlock) config_kernel(int n_cfg, const CfgInfo
   const int64_t a0 = cfg[k].start, a1 = cfg[k].start + cfg[k].n;
   double acc[10];
   for (int t = 0; t < 10; ++t) acc[t] = 0.0;
-  for (int64_t i = a0 + threadIdx.x; i < a1; i += blockDim.x) {
-    const double v = (double)site[i];
-    acc[0] += v;
-    if (site_out) site_out[i] = v;
-    if (wv)
-      for (int t = 0; t < 9; ++t) acc[1 + t] += (double)wv[(size_t)t * stride + i];
+  // A large configuration is one block: U atoms per thread in flight.  Either
+  // loop adds the atoms i, i + blockDim, i + 2 blockDim, ... in order.
+  constexpr int U = 4;
+  if (a1 - a0 <= (int64_t)U * blockDim.x) {
+    for (int64_t i = a0 + threadIdx.x; i < a1; i += blockDim.x) {
+      const double v = (double)site[i];
+      acc[0] += v;
+      if (site_out) site_out[i] = v;
+      if (wv)
+        for (int t = 0; t < 9; ++t) acc[1 + t] += (double)wv[(size_t)t * stride + i];
+    }
+  } else {
+    for (int64_t i0 = a0 + threadIdx.x; i0 < a1; i0 += (int64_t)U * blockDim.x) {
+      double v[U], w[U][9];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int64_t i = i0 + (int64_t)u * blockDim.x;
+        const int64_t ic = i < a1 ? i : i0;
+        v[u] = (double)site[ic];
+        if (wv)
+          for (int t = 0; t < 9; ++t) w[u][t] = (double)wv[(size_t)t * stride + ic];
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int64_t i = i0 + (int64_t)u * blockDim.x;
+        if (i >= a1) break;
+        acc[0] += v[u];
+        if (site_out) site_out[i] = v[u];
+        if (wv)
+          for (int t = 0; t < 9; ++t) acc[1 + t] += w[u][t];
+      }
+    }
   }
   __shared__ double red[10][kBlock];
   for (int t = 0; t < 10; ++t) red[t][threadIdx.x] = acc[t];
