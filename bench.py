@@ -78,8 +78,8 @@ def training_extras(P, pot_path, precision, ref_path=None):
     sets (1024 configurations of 32-128 atoms, three species): loss and
     gradient in all parameters (mtp_loss_grad), and the normal equations in
     xi with their solve (mtp_normal_equations, mtp_solve_normal).  Targets
-    come from the same potential with xi scaled by 1.1 plus N(0, 1e-3^2)
-    noise."""
+    are E, F and virial of the reference potential at ref_path (by default
+    the same potential with xi scaled by 1.1) plus N(0, 1e-3^2) noise."""
     import numpy as np
     import torch
 
