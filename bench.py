@@ -161,6 +161,17 @@ def cpu_baseline_pool(batch, pot_path, rate1, budget_s):
                       f"{dt:.1f} s on {cores} worker processes of one thread each"}
 
 
+def host_cpu():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(batch, pot_path, budget_s):
     """The FP64 oracle on the host, one thread, over whole configurations of
     the same batch until budget_s seconds have passed."""
@@ -181,6 +192,7 @@ def cpu_baseline(batch, pot_path, budget_s):
                 break
     dt = time.perf_counter() - t0
     return {"value": atoms / dt, "unit": "atom-evals/s", "cores": 1, "kind": "oracle",
+            "host": f"{host_cpu()}, os.cpu_count() = {os.cpu_count()}",
             "sample": f"first {done} configurations ({atoms} atoms) of the benchmark batch, "
                       f"E+F+virial in FP64, {dt:.1f} s on one host thread"}
 
@@ -189,7 +201,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "fp32c"])
     ap.add_argument("--configs", type=int, default=4096)
     ap.add_argument("--plain-configs", type=int, default=256)
@@ -259,6 +271,7 @@ def main():
     dt_eager = (time.perf_counter() - t0) / a.steps
     log(f"batched, eager calls: {dt_eager * 1e3:.3f} ms/step")
     dt = dt_eager
+    replay_ms = None
     if not a.no_graph:
         # the same step captured once in a HIP graph and replayed
         out = P.outputs(B, b=True)
@@ -281,12 +294,22 @@ def main():
             graph.replay()
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / a.steps
+        # the same replays one by one between HIP events: median and minimum
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2 * a.steps)]
+        for k in range(a.steps):
+            ev[2 * k].record()
+            graph.replay()
+            ev[2 * k + 1].record()
+        torch.cuda.synchronize()
+        per = np.array([ev[2 * k].elapsed_time(ev[2 * k + 1]) for k in range(a.steps)])
+        replay_ms = {"median": float(np.median(per)), "min": float(per.min()), "max": float(per.max())}
         P.status()   # raises if a replay met a capacity or input problem
         ref = step()
         torch.cuda.synchronize()
         if not (torch.equal(ref["energy"], out["energy"]) and torch.equal(ref["gamma"], gamma)):
             raise RuntimeError("graph replay differs from the eager step")
-        log(f"batched, graph replay: {dt * 1e3:.3f} ms/step (gamma max {gamma.max().item():.3g})")
+        log(f"batched, graph replay: {dt * 1e3:.3f} ms/step (gamma max {gamma.max().item():.3g}); "
+            f"single replays {replay_ms}")
     value = n_atoms / dt
     log(f"batched: {dt * 1e3:.3f} ms/step, {value:.4g} atom-evals/s")
 
@@ -319,7 +342,8 @@ def main():
                                    f"E, F, stress and the extrapolation grade per configuration",
                        "precision": a.precision, "level": 16, "atoms": n_atoms, "configs": a.configs,
                        "graph_replay": not a.no_graph, "schedule": chosen, "schedule_ms": sched_ms},
-            "roofline": roofline, "eager_ms_per_step": dt_eager * 1e3}
+            "roofline": roofline, "eager_ms_per_step": dt_eager * 1e3,
+            "replay_ms_per_step": replay_ms}
 
     if not a.no_extras:
         # the plain path: one configuration per call, same configurations

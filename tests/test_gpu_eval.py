@@ -131,3 +131,40 @@ def test_dense_cells_grow_the_neighbour_capacity(potentials, spacing):
     assert rep["b_rel"] <= 1e-11
     log(f"[dense-{spacing}] max neighbours {st['max_neighbours']}")
     assert st["max_neighbours"] > (128 if spacing < 1.7 else 64)
+
+
+def _every_search_path():
+    """One batch that takes every neighbour-search path: two cell-list
+    boxes (2662 atoms each, bins of width >= R_cut, at different atom
+    offsets), a 300-atom cluster and a 288-atom thin periodic cell (one
+    workgroup per configuration is for at most 256 atoms; the thin cell
+    needs several images per neighbour), and small clusters and cells."""
+    rng = np.random.default_rng(21)
+    cfgs = []
+    small = synth.mixed_batch(seed=22, n_configs=6, n_min=8, n_max=64, n_species_model=2)
+    for k in range(3):
+        cfgs.append(synth.config_of(small, k))
+    for seed in (23, 24):
+        ideal, cell = synth.cubic_box("bcc", 11, 3.2)
+        pos, _ = synth.displace(rng, ideal, cell, True, 0.1, 2.0)
+        cfgs.append((pos, rng.integers(0, 2, len(pos)).astype(np.int32), cell, 1))
+        if seed == 23:
+            cfgs.append(synth.config_of(small, 3))
+    ideal, cell = synth.cubic_box("fcc", 6, 3.9)
+    centre = cell.sum(axis=0) / 2
+    near = np.argsort(np.linalg.norm(ideal - centre, axis=1))[:300]
+    pos, _ = synth.displace(rng, ideal[near], np.zeros((3, 3)), False, 0.1, 2.0)
+    cfgs.append((pos, rng.integers(0, 2, 300).astype(np.int32), np.zeros((3, 3)), 0))
+    ucell, basis = synth.unit_cell("fcc", 2.75)
+    pos, cell = synth.supercell(ucell, basis, (2, 6, 6))
+    pos, _ = synth.displace(rng, pos, cell, True, 0.1, 2.0)
+    cfgs.append((pos, rng.integers(0, 2, len(pos)).astype(np.int32), cell, 1))
+    for k in range(4, 6):
+        cfgs.append(synth.config_of(small, k))
+    return synth._batch(cfgs)
+
+
+def test_every_search_path_in_one_batch(potentials):
+    b = _every_search_path()
+    assert b["n_atoms"].max() > 2048 and (b["n_atoms"] > 256).sum() >= 4
+    _check("lev12_s2", b, "fp64", potentials, TOL64, "search paths")
