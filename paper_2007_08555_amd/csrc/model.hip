@@ -423,8 +423,7 @@ int run_eval(mtp_model* M, const mtp_batch* bt, const mtp_out* out, int precisio
     }
     HIP_TRY(mark(2), "hipEventRecord");
     // the per-atom virials were summed by the last adjoint pass
-    HIP_TRY(gather_forces(fp64, N, stride, M->count.as<int32_t>(), M->rev.as<int32_t>(), M->gpair.p, M->pr.p,
-                          out->forces, nullptr, s),
+    HIP_TRY(gather_forces(fp64, N, stride, M->count.as<int32_t>(), M->rev.as<int32_t>(), M->gpair.p, out->forces, s),
             "force gather");
     HIP_TRY(mark(3), "hipEventRecord");
     HIP_TRY(reduce_configs(fp64, n_cfg, M->cfg.as<CfgInfo>(), stride, M->site.p, out->virial ? M->wv.p : nullptr,
@@ -740,8 +739,8 @@ int mtp_normal_equations(mtp_model* M, const mtp_batch* bt, const double* E_t, c
                 "evaluation kernels");
       }
     }
-    HIP_TRY(mtp::gather_forces(fp64, N, stride, M->count.as<int32_t>(), M->rev.as<int32_t>(), M->gpair.p, M->pr.p,
-                               col + K_cfg, nullptr, s),
+    HIP_TRY(mtp::gather_forces(fp64, N, stride, M->count.as<int32_t>(), M->rev.as<int32_t>(), M->gpair.p,
+                               col + K_cfg, s),
             "force gather");
     HIP_TRY(mtp::reduce_configs(fp64, K_cfg, M->cfg.as<mtp::CfgInfo>(), stride, M->site.p, M->wv.p, nullptr, m,
                                 stride, M->perm_dev.as<int32_t>(), col, col + K_cfg + 3 * N, nullptr, nullptr, s),

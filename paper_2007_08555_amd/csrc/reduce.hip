@@ -14,59 +14,46 @@ namespace {
 
 constexpr int kBlock = 256;
 
-// Forces (when F is not null) and the per-atom virial sum_p g_p (x) r_p
-// (when wv is not null), W_ab = dE/d eps_ab for r -> (I + eps) r.  Pairs are
-// taken four at a time so that the four dependent loads g[rev[e]] are in
-// flight together; the sums keep the pair order.
+// Forces F_i = sum over slots p of (g_p - g_rev(p)), summed in FP64 in slot
+// order.  Pairs are taken eight at a time so that the eight dependent loads
+// g[rev[e]] are in flight together.  (The per-atom virials are summed by the
+// last adjoint pass.)
 template <typename T>
-__global__ void gather_kernel(int64_t n_atoms, int stride, const int32_t* __restrict__ count,
-                              const int32_t* __restrict__ rev, const T* __restrict__ g,
-                              const PairRec<T>* __restrict__ pr, double* __restrict__ F, T* __restrict__ wv) {
-  constexpr int U = 4;
+__global__ void __launch_bounds__(kBlock) gather_kernel(int64_t n_atoms, int stride,
+                                                        const int32_t* __restrict__ count,
+                                                        const int32_t* __restrict__ rev,
+                                                        const T* __restrict__ g, double* __restrict__ F) {
+  constexpr int U = 8;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n_atoms) return;
   double fx = 0, fy = 0, fz = 0;
-  double w[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
   const int c = count[i];
   for (int p0 = 0; p0 < c; p0 += U) {
-    double gx[U], gy[U], gz[U], hx[U], hy[U], hz[U], x[U], y[U], z[U];
+    double gx[U], gy[U], gz[U], hx[U], hy[U], hz[U];
     size_t q[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const size_t e = (size_t)(p0 + u < c ? p0 + u : p0) * stride + i;
-      q[u] = F ? (size_t)rev[e] : e;
+      q[u] = (size_t)rev[e];
       gx[u] = (double)g[3 * e]; gy[u] = (double)g[3 * e + 1]; gz[u] = (double)g[3 * e + 2];
-      if (wv) {
-        const PairRec<T> r = pr[e];
-        x[u] = (double)r.x; y[u] = (double)r.y; z[u] = (double)r.z;
-      }
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       hx[u] = (double)g[3 * q[u]]; hy[u] = (double)g[3 * q[u] + 1]; hz[u] = (double)g[3 * q[u] + 2];
     }
+    // a select, not a branch: the loads above stay unconditional and issue
+    // together (slots past the count were loaded at a clamped index)
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      if (p0 + u >= c) break;
-      if (F) {
-        fx += gx[u] - hx[u];
-        fy += gy[u] - hy[u];
-        fz += gz[u] - hz[u];
-      }
-      if (wv) {
-        w[0] += gx[u] * x[u]; w[1] += gx[u] * y[u]; w[2] += gx[u] * z[u];
-        w[3] += gy[u] * x[u]; w[4] += gy[u] * y[u]; w[5] += gy[u] * z[u];
-        w[6] += gz[u] * x[u]; w[7] += gz[u] * y[u]; w[8] += gz[u] * z[u];
-      }
+      const bool ok = p0 + u < c;
+      fx = ok ? fx + (gx[u] - hx[u]) : fx;
+      fy = ok ? fy + (gy[u] - hy[u]) : fy;
+      fz = ok ? fz + (gz[u] - hz[u]) : fz;
     }
   }
-  if (F) {
-    F[3 * i] = fx;
-    F[3 * i + 1] = fy;
-    F[3 * i + 2] = fz;
-  }
-  if (wv)
-    for (int t = 0; t < 9; ++t) wv[(size_t)t * stride + i] = (T)w[t];
+  F[3 * i] = fx;
+  F[3 * i + 1] = fy;
+  F[3 * i + 2] = fz;
 }
 
 // One block per configuration.  Sums are formed in FP64 in a fixed order
@@ -167,16 +154,15 @@ __global__ void __launch_bounds__(kBlock) b_kernel(int n_cfg, const CfgInfo* __r
 }  // namespace
 
 hipError_t gather_forces(int fp64, int64_t n_atoms, int stride, const int32_t* count,
-                         const int32_t* rev, const void* gp, const void* pr, double* forces,
-                         void* atom_virial, hipStream_t s) {
-  if (n_atoms == 0 || (!forces && !atom_virial)) return hipSuccess;
+                         const int32_t* rev, const void* gp, double* forces, hipStream_t s) {
+  if (n_atoms == 0 || !forces) return hipSuccess;
   const dim3 g((unsigned)((n_atoms + kBlock - 1) / kBlock));
   if (fp64)
     hipLaunchKernelGGL(gather_kernel<double>, g, dim3(kBlock), 0, s, n_atoms, stride, count, rev,
-                       (const double*)gp, (const PairRec<double>*)pr, forces, (double*)atom_virial);
+                       (const double*)gp, forces);
   else
     hipLaunchKernelGGL(gather_kernel<float>, g, dim3(kBlock), 0, s, n_atoms, stride, count, rev,
-                       (const float*)gp, (const PairRec<float>*)pr, forces, (float*)atom_virial);
+                       (const float*)gp, forces);
   return hipGetLastError();
 }
 
