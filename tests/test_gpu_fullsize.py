@@ -105,3 +105,35 @@ def test_bcc16000_sampled_atoms(precision):
         assert e_err <= 1e-11 and f_err <= 1e-10
     else:
         assert e_err <= 1e-6 and f_err <= 1e-5 * fscale
+
+
+def test_fcc256k_precision_study():
+    """The 256 000-atom disordered fcc alloy (40^3 cells, a = 3.6 A, sigma =
+    0.2 A, three species) at level 16, the compiled basis closest to the
+    precision study's: FP64 against the oracle on two sampled atoms, then
+    FP32 and FP32 compensated against FP64 over the whole box (energy per
+    atom within 1e-6 eV; forces within 1e-5 of the largest force, the FP32
+    bound of the other parity tests)."""
+    from paper_2007_08555_amd import Batch, Potential
+    box = synth.fcc_alloy(seed=0)
+    N = int(box["n_atoms"][0])
+    P = Potential(pot_path("lev16_s3"))
+    B = Batch.from_arrays(box, "cuda:0")
+    out = {p: P.eval(B, precision=p, site=True) for p in ("fp64", "fp32", "fp32c")}
+    res = {p: {k: v.cpu().numpy() for k, v in o.items()} for p, o in out.items()}
+    pot = read_potential(pot_path("lev16_s3"))
+    atoms = np.sort(np.random.default_rng(5).choice(N, size=2, replace=False))
+    v_o, f_o = omtp.evaluate_sampled(pot, *synth.config_of(box, 0), atoms, atoms)
+    r64 = res["fp64"]
+    e_err = np.abs(r64["site"][atoms] - v_o).max()
+    f_err = np.abs(r64["forces"][atoms] - f_o).max()
+    log(f"[fcc256k fp64] atoms {atoms.tolist()}: site error {e_err:.3e} eV, force error {f_err:.3e} eV/A")
+    assert e_err <= 1e-11 and f_err <= 1e-10
+    fscale = np.abs(r64["forces"]).max()
+    for p in ("fp32", "fp32c"):
+        de = abs(float(res[p]["energy"][0]) - float(r64["energy"][0])) / N
+        df = np.abs(res[p]["forces"] - r64["forces"]).max()
+        ds = np.abs(res[p]["site"] - r64["site"]).max()
+        log(f"[fcc256k {p}] energy per atom {de:.3e} eV, largest site error {ds:.3e} eV, "
+            f"largest force error {df:.3e} eV/A (largest force {fscale:.3g})")
+        assert de <= 1e-6 and df <= 1e-5 * fscale
