@@ -16,8 +16,10 @@ calibrated potential tests/golden/potentials/lev16_s3.mtp).
 
 Prints one JSON line.  Besides the contract fields it reports the roofline
 of the evaluation kernels, the plain one-configuration-per-call path on the
-same configurations, the single 16 000-atom bcc box, and the FP64 CPU
-oracle timed on a bounded sample of the same workload.
+same configurations, the 16 000-atom bcc box as 100 MD-style steps, the
+256 000-atom alloy in FP64, FP32 and compensated FP32, the training workload
+(loss gradient and normal equations), and the FP64 CPU oracle timed on a
+bounded sample of the same workload (one thread and one process per core).
 """
 import argparse
 import json

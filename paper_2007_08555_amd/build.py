@@ -5,8 +5,10 @@
 Steps: generate one evaluation kernel per compiled basis level
 (codegen.py), compile every .hip source with hipcc for gfx950, link
 paper_2007_08555_amd/libmtp.so.  Object files go to
-paper_2007_08555_amd/_build/ and are reused when their source, the shared
-headers and the flags are unchanged.
+paper_2007_08555_amd/_build/ and are reused while their source (for a part of
+a generated kernel file: the sections that part compiles), the project
+headers it includes and the flags are unchanged.  MTP_EXTRA_LEVELS (e.g.
+"20") adds basis levels to the default ones.
 """
 from __future__ import annotations
 

@@ -307,10 +307,15 @@ __device__ inline int wave_max(int v) {
   return v;
 }
 
+// One thread per atom of the configurations that are neither small nor
+// binned (large clusters, large cells too thin for three bins): brute force
+// over the configuration's atoms and, in a periodic cell, over the box of
+// images that can reach R_cut.
 __global__ void __launch_bounds__(kBlock) search_kernel(NbrArgs a) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  // atoms of small configurations are searched by search_small_kernel; every
-  // lane stays to the end for the wavefront reductions
+  // atoms of small configurations are searched by search_small_kernel, those
+  // of binned ones by search_binned_kernel; every lane stays to the end for
+  // the wavefront reductions
   const bool active = i < a.n_atoms && !((is_small(a.cfg[a.atom_cfg[i]]) || a.cfg[a.atom_cfg[i]].binned) &&
                                          in_cfg(a.cfg[a.atom_cfg[i]], i));
   Emitter emit{a, i, 0, a.rmin * a.rmin, 0};
@@ -322,9 +327,7 @@ __global__ void __launch_bounds__(kBlock) search_kernel(NbrArgs a) {
     const double xi = a.pos[3 * i], yi = a.pos[3 * i + 1], zi = a.pos[3 * i + 2];
     const double rc2 = a.rcut * a.rcut;
     const double* L = c.L;
-    const double* inv = c.inv;
-    (void)inv;
-    if (!c.binned) {
+    {
       const int64_t j0 = c.start, j1 = c.start + c.n;
       for (int64_t j = j0; j < j1; ++j) {
         const double dx = a.pos[3 * j] - xi, dy = a.pos[3 * j + 1] - yi, dz = a.pos[3 * j + 2] - zi;
