@@ -137,3 +137,31 @@ def test_fcc256k_precision_study():
         log(f"[fcc256k {p}] energy per atom {de:.3e} eV, largest site error {ds:.3e} eV, "
             f"largest force error {df:.3e} eV/A (largest force {fscale:.3g})")
         assert de <= 1e-6 and df <= 1e-5 * fscale
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp32c"])
+def test_batched_workload_full_size_fp32(precision):
+    """The batched workload in FP32 (plain and compensated moment sums),
+    sampled configurations against the oracle: energy per atom within 1e-6 eV,
+    forces within 1e-5 of the configuration's largest force (the FP32 bound of
+    the other parity tests), b within 1e-5 relative."""
+    from paper_2007_08555_amd import Batch, Potential
+    batch = synth.mixed_batch(seed=0, n_configs=4096, n_min=8, n_max=256, n_species_model=3)
+    K = len(batch["n_atoms"])
+    P = Potential(pot_path("lev16_s3"))
+    out = P.eval(Batch.from_arrays(batch, "cuda:0"), precision=precision, b=True)
+    E, F, b = (out[k].cpu().numpy() for k in ("energy", "forces", "b"))
+    offs = batch["atom_offsets"]
+    pot = read_potential(pot_path("lev16_s3"))
+    sample = np.sort(np.random.default_rng(8).choice(K, size=8, replace=False))
+    worst_e = worst_f = worst_b = 0.0
+    for k in sample:
+        r = omtp.evaluate(pot, *synth.config_of(batch, int(k)))
+        n = int(batch["n_atoms"][k])
+        fo = r["forces"]
+        worst_e = max(worst_e, abs(E[k] - r["energy"]) / n)
+        worst_f = max(worst_f, np.abs(F[offs[k]:offs[k + 1]] - fo).max() / max(np.abs(fo).max(), 1.0))
+        worst_b = max(worst_b, np.abs(b[k] - r["b"]).max() / np.abs(r["b"]).max())
+    log(f"[full batch {precision}] configurations {sample.tolist()}: energy per atom {worst_e:.3e} eV, "
+        f"force error / largest force {worst_f:.3e}, b {worst_b:.3e}")
+    assert worst_e <= 1e-6 and worst_f <= 1e-5 and worst_b <= 1e-5
