@@ -433,6 +433,30 @@ def main():
                                       "phase_ms": {k: st2[k] for k in ("ms_neighbours", "ms_eval", "ms_forces",
                                                                         "ms_reduce")}}
             log(f"bcc16000 {prec}: {nb / tb:.4g} atom-evals/s, {tb * 1e3:.3f} ms/step")
+        # the same steps with a 0.3 A Verlet skin: lists built out to
+        # R_cut + 0.3 A and reused while no atom moved more than 0.15 A
+        for prec in ("fp32", "fp64"):
+            P3 = Potential(os.path.join(ROOT, "tests", "golden", "potentials", "lev16_s2.mtp"), device=0)
+            P3.set_skin(0.3)
+            for _ in range(2):
+                P3.eval(Bb, precision=prec, stream=stream)
+            torch.cuda.synchronize()
+            reused = 0
+            t0 = time.perf_counter()
+            for t in range(100):
+                if t:
+                    Bb.pos.add_(jit[t - 1])
+                P3.eval(Bb, precision=prec, stream=stream)
+                reused += P3.stats()["lists_reused"]
+            torch.cuda.synchronize()
+            tb = (time.perf_counter() - t0) / 100
+            Bb.pos.copy_(pos0)
+            line["bcc16000"][prec + "_skin0.3"] = {"value": nb / tb, "unit": "atom-evals/s", "ms_per_step": tb * 1e3,
+                                                   "lists_reused_steps": reused,
+                                                   "list_builds": P3.stats()["list_builds"]}
+            log(f"bcc16000 {prec}, skin 0.3 A: {nb / tb:.4g} atom-evals/s, {tb * 1e3:.3f} ms/step, "
+                f"lists reused on {reused} of 100 steps")
+            del P3
         line["precision_study"] = precision_study(stream)
         log(f"precision study: {line['precision_study']}")
         line["training"] = training_extras(P, pot_path, a.precision)

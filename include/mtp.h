@@ -246,7 +246,26 @@ typedef struct {
   float ms_eval;            /* evaluation kernels (moments, contractions, adjoint) */
   float ms_forces;          /* force gather */
   float ms_reduce;          /* per-configuration sums */
+  int32_t lists_reused;     /* 1 if the last mtp_eval refreshed the lists of an earlier call (skin) */
+  int32_t list_builds;      /* neighbour-list builds since the skin was last set */
 } mtp_stats;
+
+/*
+ * Verlet skin for repeated evaluation of one batch whose atoms move a
+ * little between calls (MD steps).  With skin > 0 (Angstrom, at most R_cut),
+ * mtp_eval builds the neighbour lists out to R_cut + skin and later calls
+ * on the same batch arrays (the same device pointers and sizes) reuse them
+ * while every atom is within skin / 2 of its position at the build: the
+ * pair vectors are then recomputed from the positions, pairs beyond R_cut
+ * contributing nothing, and the results are those of a fresh search up to
+ * rounding.  Moving more than skin / 2, or a different batch, rebuilds.  The
+ * cells, species and pbc flags of a batch must not change in place while its
+ * lists are reused (set the skin again to discard them).  The check costs
+ * one extra synchronisation per call; mtp_eval_async ignores the skin and
+ * always searches.  skin = 0 (the default) searches on every call.
+ * MTP_E_ARG outside [0, R_cut].
+ */
+int mtp_set_skin(mtp_model* model, double skin);
 
 /* Turns HIP-event timing of the phases of mtp_eval on (enable = 1) or off.
  * Events are recorded on the stream of each call. */

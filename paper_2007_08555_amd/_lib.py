@@ -45,7 +45,8 @@ class mtp_stats(ctypes.Structure):
     _fields_ = [("n_atoms", ctypes.c_int64), ("n_pairs", ctypes.c_int64), ("max_neighbours", ctypes.c_int32),
                 ("level", ctypes.c_int32), ("flops_pair_fwd", ctypes.c_double), ("flops_pair_bwd", ctypes.c_double),
                 ("flops_atom", ctypes.c_double), ("ms_neighbours", ctypes.c_float), ("ms_eval", ctypes.c_float),
-                ("ms_forces", ctypes.c_float), ("ms_reduce", ctypes.c_float)]
+                ("ms_forces", ctypes.c_float), ("ms_reduce", ctypes.c_float), ("lists_reused", ctypes.c_int32),
+                ("list_builds", ctypes.c_int32)]
 
 
 _P = ctypes.c_void_p
@@ -71,6 +72,7 @@ _SIGNATURES = {
                                     ctypes.POINTER(ctypes.c_int), _P]),
     "mtp_set_timing": (ctypes.c_int, [_P, ctypes.c_int]),
     "mtp_get_stats": (ctypes.c_int, [_P, ctypes.POINTER(mtp_stats)]),
+    "mtp_set_skin": (ctypes.c_int, [_P, ctypes.c_double]),
     "mtp_free": (None, [_P]),
     "mtp_last_error": (ctypes.c_char_p, []),
 }

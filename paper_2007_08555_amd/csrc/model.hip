@@ -102,6 +102,15 @@ struct mtp_model {
   Buffer count, nbr, pr, rev, gpair, Mbuf, Gbuf, Dbuf, site, wv, B, status, run_start;
   int K = 64;  // neighbour capacity per atom, grown on overflow
   int schedule64 = 0;  // FP64 pass split of the evaluation kernels (mtp_autotune)
+  // Verlet skin (mtp_set_skin): lists of the last build, reused while the
+  // batch's arrays are the same and no atom moved more than skin / 2
+  double skin = 0.0;
+  bool lists_valid = false;
+  const void* built_for[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  int64_t built_atoms = -1;
+  int built_cfgs = -1, built_K = 0;
+  Buffer xbuild, img, disp;
+  int32_t lists_reused = 0, list_builds = 0;
   Buffer b_tmp, c_tmp;
   int last_stride = 0;
   // loss gradient
@@ -375,8 +384,31 @@ int run_eval(mtp_model* M, const mtp_batch* bt, const mtp_out* out, int precisio
     NEED(M->site, tsz * stride);
     NEED(M->wv, tsz * 9 * stride);
     if (want_b) NEED(M->B, tsz * (size_t)M->m * stride);
+    const bool use_skin = M->skin > 0.0 && !async;
+    if (use_skin) {
+      NEED(M->xbuild, sizeof(double) * 3 * (size_t)(N + 1));
+      NEED(M->img, sizeof(short4) * slots);
+      NEED(M->disp, sizeof(unsigned long long));
+    }
 #undef NEED
 
+    // lists of an earlier call on the same arrays, if no atom has moved more
+    // than skin / 2 since they were built (one extra synchronisation)
+    bool reuse = false;
+    if (use_skin && M->lists_valid && M->built_atoms == N && M->built_cfgs == n_cfg && M->built_K == K &&
+        M->built_for[0] == bt->pos && M->built_for[1] == bt->atom_offsets && M->built_for[2] == bt->species &&
+        M->built_for[3] == bt->cell && M->built_for[4] == bt->pbc) {
+      HIP_TRY(zero_words((int32_t*)M->disp.p, 2, s), "displacement reset");
+      HIP_TRY(max_displacement(bt->pos, M->xbuild.as<double>(), N, M->disp.as<unsigned long long>(), s),
+              "displacement check");
+      unsigned long long bits = 0;
+      HIP_TRY(hipMemcpyAsync(&bits, M->disp.p, sizeof(bits), hipMemcpyDeviceToHost, s), "hipMemcpyAsync");
+      HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
+      double d2;
+      std::memcpy(&d2, &bits, sizeof(d2));
+      reuse = d2 <= 0.25 * M->skin * M->skin;
+    }
+    if (!reuse) M->lists_valid = false;
     HIP_TRY(mark(0), "hipEventRecord");
     HIP_TRY(zero_words((int32_t*)M->status.p, sizeof(Status) / sizeof(int32_t), s), "status reset");
     NbrArgs a{};
@@ -408,7 +440,20 @@ int run_eval(mtp_model* M, const mtp_batch* bt, const mtp_out* out, int precisio
     a.rev = M->rev.as<int32_t>();
     a.run_start = M->run_start.as<int16_t>();
     a.status = M->status.as<Status>();
-    HIP_TRY(nbr_build(a, s), "neighbour search");
+    if (reuse) {
+      HIP_TRY(refresh_pairs(a, M->img.as<short4>(), s), "pair refresh");
+    } else if (use_skin) {
+      // lists out to R_cut + skin; records of pairs beyond R_cut made neutral
+      a.rcut = M->rcut + M->skin;
+      HIP_TRY(nbr_build(a, s), "neighbour search");
+      HIP_TRY(pair_images(a, M->img.as<short4>(), s), "pair images");
+      a.rcut = M->rcut;
+      HIP_TRY(refresh_pairs(a, M->img.as<short4>(), s), "pair refresh");
+      HIP_TRY(hipMemcpyAsync(M->xbuild.p, bt->pos, sizeof(double) * 3 * (size_t)N, hipMemcpyDeviceToDevice, s),
+              "hipMemcpyAsync");
+    } else {
+      HIP_TRY(nbr_build(a, s), "neighbour search");
+    }
     HIP_TRY(mark(1), "hipEventRecord");
     if (N > 0) {
       if (fp64) {
@@ -442,10 +487,25 @@ int run_eval(mtp_model* M, const mtp_batch* bt, const mtp_out* out, int precisio
       M->K = (int)((st.max_count + 7) / 8 * 8);
       continue;
     }
+    M->lists_reused = reuse ? 1 : 0;
+    if (use_skin && !reuse) {
+      M->lists_valid = true;
+      M->built_for[0] = bt->pos;
+      M->built_for[1] = bt->atom_offsets;
+      M->built_for[2] = bt->species;
+      M->built_for[3] = bt->cell;
+      M->built_for[4] = bt->pbc;
+      M->built_atoms = N;
+      M->built_cfgs = n_cfg;
+      M->built_K = K;
+      ++M->list_builds;
+    }
     M->last_atoms = N;
     M->last_stride = stride;
-    M->last_pairs = (int64_t)st.n_pairs;
-    M->last_max_nb = (int32_t)st.max_count;
+    if (!reuse) {   // a reuse keeps the pair count and largest list of its build
+      M->last_pairs = (int64_t)st.n_pairs;
+      M->last_max_nb = (int32_t)st.max_count;
+    }
     M->timed = M->timing;
     return MTP_OK;
   }
@@ -861,6 +921,16 @@ int mtp_autotune(mtp_model* M, const mtp_batch* bt, int precision, int repeats, 
   return MTP_OK;
 }
 
+int mtp_set_skin(mtp_model* M, double skin) {
+  g_err.clear();
+  if (!M) return fail(MTP_E_ARG, "mtp_set_skin: null model");
+  if (!(skin >= 0.0) || !(skin <= M->rcut)) return fail(MTP_E_ARG, "mtp_set_skin: skin must be in [0, R_cut]");
+  M->skin = skin;
+  M->lists_valid = false;
+  M->list_builds = 0;
+  return MTP_OK;
+}
+
 int mtp_set_timing(mtp_model* M, int enable) {
   if (!M) return fail(MTP_E_ARG, "mtp_set_timing: null model");
   HIP_TRY(hipSetDevice(M->device), "hipSetDevice");
@@ -880,6 +950,8 @@ int mtp_get_stats(mtp_model* M, mtp_stats* st) {
   st->flops_pair_fwd = M->var->flops_pair_fwd;
   st->flops_pair_bwd = M->var->flops_pair_bwd;
   st->flops_atom = M->var->flops_atom;
+  st->lists_reused = M->lists_reused;
+  st->list_builds = M->list_builds;
   st->ms_neighbours = st->ms_eval = st->ms_forces = st->ms_reduce = -1.0f;
   if (M->timed) {
     HIP_TRY(hipEventSynchronize(M->ev[4]), "hipEventSynchronize");

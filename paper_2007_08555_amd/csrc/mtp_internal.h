@@ -64,6 +64,21 @@ struct NbrArgs {
 // fill the ELL lists up to K slots (counting overflow), reverse indices.
 hipError_t nbr_build(NbrArgs& a, hipStream_t s);
 
+// Verlet skin (lists built with R_cut + skin and reused while every atom
+// stays within skin / 2 of its position at the build).
+// Largest squared displacement |x_i - x_build_i|^2 over the atoms, as the
+// bits of a non-negative double in *out (which must start at zero).
+hipError_t max_displacement(const double* pos, const double* xbuild, int64_t n_atoms,
+                            unsigned long long* out, hipStream_t s);
+// After a build: the image shift n of every stored pair (r = x_j - x_i + n.L),
+// as int16 triples in img [K * stride] (entry 3 unused).
+hipError_t pair_images(const NbrArgs& a, short4* img, hipStream_t s);
+// Pair records of every stored pair recomputed from the positions and img,
+// the same expression as the search; a pair at or beyond R_cut = a.rcut gets
+// the record (R_cut, 0, 0), whose radial factor (R_cut - r)^2 and its
+// derivative vanish, so it adds exactly nothing.  Counts pairs below R_min.
+hipError_t refresh_pairs(const NbrArgs& a, const short4* img, hipStream_t s);
+
 // Sets n 32-bit words to zero with a kernel (capturable, unlike memset nodes).
 hipError_t zero_words(int32_t* p, int64_t n, hipStream_t s);
 

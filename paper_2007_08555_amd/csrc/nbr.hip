@@ -908,12 +908,120 @@ __global__ void __launch_bounds__(kSmallBlock) search_small_kernel(NbrArgs a, in
   if (errs) atomicAdd(&a.status->list_errors, errs);
 }
 
+// ---------------------------------------------------------------------------
+// Verlet skin: lists built with R_cut + skin are reused while every atom stays
+// within skin / 2 of its position at the build (then no pair that was beyond
+// R_cut + skin can have come within R_cut).  The records are refreshed from
+// the positions on every reuse.
+
+__global__ void __launch_bounds__(kBlock) max_disp_kernel(const double* __restrict__ pos,
+                                                          const double* __restrict__ xb, int64_t n,
+                                                          unsigned long long* out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double d2 = 0.0;
+  if (i < n) {
+    const double dx = pos[3 * i] - xb[3 * i], dy = pos[3 * i + 1] - xb[3 * i + 1], dz = pos[3 * i + 2] - xb[3 * i + 2];
+    d2 = dx * dx + dy * dy + dz * dz;
+  }
+  for (int o = 32; o > 0; o >>= 1) d2 = fmax(d2, __shfl_xor(d2, o, 64));
+  __shared__ double part[kBlock / 64];
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = d2;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double m = part[0];
+    for (int w = 1; w < kBlock / 64; ++w) m = fmax(m, part[w]);
+    // non-negative doubles order like their bit patterns
+    if (m > 0.0) atomicMax(out, (unsigned long long)__double_as_longlong(m));
+  }
+}
+
+// Image shift of slot p of atom i: n = rint((r - (x_j - x_i)) . L^-1).
+__global__ void pair_images_kernel(NbrArgs a, short4* img) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int p = blockIdx.y;
+  if (i >= a.n_atoms || p >= a.count[i]) return;
+  const CfgInfo& c = a.cfg[a.atom_cfg[i]];
+  const size_t e = (size_t)p * a.stride + i;
+  const int32_t j = a.nbr[e];
+  double rx, ry, rz;
+  if (a.fp64) {
+    const PairRec<double> q = ((const PairRec<double>*)a.pr)[e];
+    rx = q.x; ry = q.y; rz = q.z;
+  } else {
+    const PairRec<float> q = ((const PairRec<float>*)a.pr)[e];
+    rx = q.x; ry = q.y; rz = q.z;
+  }
+  const double sx = rx - (a.pos[3 * j] - a.pos[3 * i]);
+  const double sy = ry - (a.pos[3 * j + 1] - a.pos[3 * i + 1]);
+  const double sz = rz - (a.pos[3 * j + 2] - a.pos[3 * i + 2]);
+  int n[3] = {0, 0, 0};
+  bool bad = false;
+  if (c.pbc)
+    for (int d = 0; d < 3; ++d) {
+      const double v = rint(sx * c.inv[0 * 3 + d] + sy * c.inv[1 * 3 + d] + sz * c.inv[2 * 3 + d]);
+      bad = bad || !(fabs(v) <= 32767.0);
+      n[d] = bad ? 0 : (int)v;
+    }
+  if (bad) atomicAdd(&a.status->list_errors, 1ull);
+  img[e] = make_short4((short)n[0], (short)n[1], (short)n[2], 0);
+}
+
+__global__ void refresh_pairs_kernel(NbrArgs a, const short4* __restrict__ img) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int p = blockIdx.y;
+  int below = 0;
+  if (i < a.n_atoms && p < a.count[i]) {
+    const CfgInfo& c = a.cfg[a.atom_cfg[i]];
+    const size_t e = (size_t)p * a.stride + i;
+    const int32_t j = a.nbr[e];
+    const short4 n = img[e];
+    const double* L = c.L;
+    const double dx = a.pos[3 * j] - a.pos[3 * i], dy = a.pos[3 * j + 1] - a.pos[3 * i + 1],
+                 dz = a.pos[3 * j + 2] - a.pos[3 * i + 2];
+    const double sx = (double)n.x * L[0] + (double)n.y * L[3] + (double)n.z * L[6];
+    const double sy = (double)n.x * L[1] + (double)n.y * L[4] + (double)n.z * L[7];
+    const double sz = (double)n.x * L[2] + (double)n.y * L[5] + (double)n.z * L[8];
+    const double rx = dx + sx, ry = dy + sy, rz = dz + sz;
+    const double r2 = rx * rx + ry * ry + rz * rz;
+    int zj = a.species[j];
+    zj = zj < 0 ? 0 : (zj >= a.n_species ? a.n_species - 1 : zj);
+    if (r2 < a.rcut * a.rcut) {
+      store_pair(a, e, rx, ry, rz, zj);
+      if (r2 < a.rmin * a.rmin) below = 1;
+    } else {
+      store_pair(a, e, a.rcut, 0.0, 0.0, zj);
+    }
+  }
+  below = wave_sum(below);
+  if ((threadIdx.x & 63) == 0 && below) atomicAdd(&a.status->below_rmin, (unsigned long long)below);
+}
+
 inline dim3 grid_for(int64_t n) { return dim3((unsigned)((n + kBlock - 1) / kBlock)); }
 
 }  // namespace
 
 hipError_t zero_words(int32_t* p, int64_t n, hipStream_t s) {
   if (n > 0) hipLaunchKernelGGL(zero_kernel, grid_for(n), dim3(kBlock), 0, s, p, n);
+  return hipGetLastError();
+}
+
+hipError_t max_displacement(const double* pos, const double* xbuild, int64_t n_atoms,
+                            unsigned long long* out, hipStream_t s) {
+  if (n_atoms > 0) hipLaunchKernelGGL(max_disp_kernel, grid_for(n_atoms), dim3(kBlock), 0, s, pos, xbuild, n_atoms, out);
+  return hipGetLastError();
+}
+
+hipError_t pair_images(const NbrArgs& a, short4* img, hipStream_t s) {
+  if (a.n_atoms == 0 || a.K == 0) return hipSuccess;
+  const dim3 g((unsigned)((a.n_atoms + kBlock - 1) / kBlock), (unsigned)a.K);
+  hipLaunchKernelGGL(pair_images_kernel, g, dim3(kBlock), 0, s, a, img);
+  return hipGetLastError();
+}
+
+hipError_t refresh_pairs(const NbrArgs& a, const short4* img, hipStream_t s) {
+  if (a.n_atoms == 0 || a.K == 0) return hipSuccess;
+  const dim3 g((unsigned)((a.n_atoms + kBlock - 1) / kBlock), (unsigned)a.K);
+  hipLaunchKernelGGL(refresh_pairs_kernel, g, dim3(kBlock), 0, s, a, img);
   return hipGetLastError();
 }
 

@@ -206,6 +206,10 @@ class Potential:
                                    _stream(stream)), "mtp_eval_async")
         return out
 
+    def set_skin(self, skin):
+        """Verlet skin in Angstrom (mtp_set_skin); 0 searches on every call."""
+        check(lib().mtp_set_skin(self._h, float(skin)), "mtp_set_skin")
+
     def set_timing(self, enable=True):
         check(lib().mtp_set_timing(self._h, 1 if enable else 0), "mtp_set_timing")
 

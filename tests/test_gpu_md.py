@@ -81,3 +81,43 @@ def test_md_steps_bcc16000(precision):
             assert e_err <= 1e-11 and f_err <= 1e-10
         else:
             assert e_mean <= 1e-6 and e_err <= 5e-6 and f_err <= 1e-5
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_md_steps_with_verlet_skin(precision):
+    """The same 100 steps with a 0.3 A Verlet skin (mtp_set_skin): the lists
+    are built once out to R_cut + 0.3 A and reused while no atom has moved
+    more than 0.15 A; every reused step equals a search on every step (a
+    second potential without skin on the same positions) up to the rounding
+    of the summation order, and the last step matches the oracle."""
+    import torch
+    from paper_2007_08555_amd import Batch, Potential
+    box, jitter, at, atoms = trajectory()
+    P = Potential(pot_path("lev16_s2"))
+    P.set_skin(0.3)
+    Q = Potential(pot_path("lev16_s2"))
+    B = Batch.from_arrays(box, "cuda:0")
+    reused, worst = 0, {"energy": 0.0, "forces": 0.0, "virial": 0.0}
+    for t in range(N_STEPS):
+        if t > 0:
+            B.pos.add_(torch.as_tensor(jitter[t - 1], device="cuda:0"))
+        out = P.eval(B, precision=precision, site=True)
+        reused += P.stats()["lists_reused"]
+        if t % 11 == 0 or t == N_STEPS - 1:
+            ref = Q.eval(B, precision=precision, site=True)
+            for k in worst:
+                d = (out[k] - ref[k]).abs().max().item() / max(ref[k].abs().max().item(), 1e-300)
+                worst[k] = max(worst[k], d)
+    st = P.stats()
+    log(f"[md skin {precision}] list builds {st['list_builds']}, reused on {reused} of {N_STEPS} steps; "
+        f"largest relative difference to a search on every step {worst}")
+    assert st["list_builds"] >= 1 and reused >= N_STEPS - st["list_builds"] - 1
+    tol = 1e-12 if precision == "fp64" else 1e-5
+    assert max(worst.values()) <= tol
+    if precision == "fp64":
+        v_o, f_o = oracle_at(N_STEPS - 1)
+        e_err = np.abs(out["site"].cpu().numpy()[atoms] - v_o).max()
+        f_err = np.abs(out["forces"].cpu().numpy()[atoms[:N_FORCES]] - f_o).max()
+        log(f"[md skin fp64 step {N_STEPS - 1}] site error {e_err:.3e} eV, force error {f_err:.3e} eV/A")
+        assert e_err <= 1e-11 and f_err <= 1e-10
+    P.status()
