@@ -121,11 +121,11 @@ def _includes(text):
     return sorted(found)
 
 
-def _compile(src):
+def _compile(src, force=False):
     base = os.path.splitext(os.path.basename(src))[0]
     tag = _hash(src, FLAGS)
     obj = os.path.join(BUILD, f"{base}.{tag}.o")
-    if os.path.exists(obj):
+    if os.path.exists(obj) and not force:
         return obj, 0.0, "cached"
     t0 = time.time()
     lang = ["-x", "hip"] if src.endswith((".hip", ".cpp")) else []
@@ -137,7 +137,9 @@ def _compile(src):
     return obj, time.time() - t0, res.stderr.strip()
 
 
-def build(levels=None, jobs=None, verbose=True):
+def build(levels=None, jobs=None, verbose=True, force=False):
+    """Generates, compiles (every source when force, else the changed ones)
+    and links the library; returns its path."""
     if not os.path.exists(HIPCC):
         raise RuntimeError(f"hipcc not found at {HIPCC}")
     os.makedirs(BUILD, exist_ok=True)
@@ -160,7 +162,7 @@ def build(levels=None, jobs=None, verbose=True):
         return -size
     sources.sort(key=cost)
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
-        for obj, dt, msg in ex.map(_compile, sources):
+        for obj, dt, msg in ex.map(lambda src: _compile(src, force), sources):
             objs.append(obj)
             if verbose and dt:
                 print(f"  compiled {os.path.basename(obj)} in {dt:.1f} s", flush=True)
@@ -170,10 +172,13 @@ def build(levels=None, jobs=None, verbose=True):
     if res.returncode != 0:
         raise RuntimeError(f"link failed:\n{res.stderr[-4000:]}")
     os.replace(tmp, LIB)
-    # drop stale objects of earlier source versions
+    # drop stale objects of earlier versions of these sources (objects of
+    # sources not in this build, such as levels added by MTP_EXTRA_LEVELS
+    # another time, are kept)
     keep = set(os.path.basename(o) for o in objs)
+    bases = set(f.split(".")[0] for f in keep)
     for f in os.listdir(BUILD):
-        if f.endswith(".o") and f not in keep:
+        if f.endswith(".o") and f not in keep and f.split(".")[0] in bases:
             os.remove(os.path.join(BUILD, f))
     if verbose:
         print(f"built {LIB}", flush=True)
@@ -184,9 +189,10 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--jobs", type=int, default=None)
     ap.add_argument("--levels", type=str, default=None)
+    ap.add_argument("--force", action="store_true", help="compile every source, ignoring cached objects")
     a = ap.parse_args()
     levels = tuple(int(x) for x in a.levels.split(",")) if a.levels else None
-    build(levels=levels, jobs=a.jobs)
+    build(levels=levels, jobs=a.jobs, force=a.force)
 
 
 if __name__ == "__main__":
