@@ -232,6 +232,27 @@ int mtp_autotune(mtp_model* model, const mtp_batch* batch, int precision, int re
  */
 int mtp_status(mtp_model* model, void* stream, int64_t* n_below_rmin, int64_t* n_list_errors);
 
+/*
+ * MaxVol selection of an active set (section 2.3: the step of Goreinov et
+ * al. behind the query strategy) from a pool of descriptor rows: pool_dev
+ * (device, [n_pool][m] FP64, file basis order, e.g. b of candidate
+ * configurations from mtp_eval).  rows_dev (device, [m] int32): with
+ * init = 1 it holds the starting rows (distinct pool indices), with
+ * init = 0 the library picks them (the pivot rows of Gaussian elimination
+ * with partial pivoting of the column-equilibrated pool, ascending).  Then,
+ * while the largest |c_ij| of C = pool A^{-1}, A = pool[rows], exceeds
+ * 1 + delta (lowest i, then j, on ties) and fewer than max_swaps swaps were
+ * made (max_swaps < 0: 100 m), rows[j] becomes i; |det A| grows by |c_ij|
+ * each time.  On return rows_dev holds the selection in position order and
+ * *n_swaps (host, may be NULL) the number of swaps.  C is updated by rank-one
+ * steps and recomputed from A^{-1} every 32 swaps and before stopping.  It
+ * synchronises `stream` once per swap; the model's active set is not
+ * changed (pass pool[rows] to mtp_set_active_set).  MTP_E_ARG for a pool
+ * of fewer than m rows, invalid starting rows or a singular selection.
+ */
+int mtp_maxvol(mtp_model* model, int32_t n_pool, const double* pool_dev, int32_t* rows_dev, int init,
+               double delta, int32_t max_swaps, int32_t* n_swaps, void* stream);
+
 /* Counters and device timings of the last mtp_eval on a model. */
 typedef struct {
   int64_t n_atoms;          /* atoms of the last batch */

@@ -44,14 +44,15 @@ def initial_rows(B_pool):
     return np.sort(perm[:m])
 
 
-def maxvol(B_pool, delta=1e-3, max_swaps=None):
+def maxvol(B_pool, delta=1e-3, max_swaps=None, start=None):
     """Row indices of a dominant m x m submatrix of B_pool and the swap count.
 
     Each step replaces row j of A by pool row i at the largest |C_ij| of
-    C = B_pool A^{-1}; |det A| grows by that factor every step."""
+    C = B_pool A^{-1}; |det A| grows by that factor every step.  start: the
+    starting rows (default: initial_rows)."""
     B = np.asarray(B_pool, dtype=np.float64)
     K, m = B.shape
-    rows = list(initial_rows(B))
+    rows = list(initial_rows(B)) if start is None else [int(r) for r in start]
     if max_swaps is None:
         max_swaps = 100 * m
     swaps = 0

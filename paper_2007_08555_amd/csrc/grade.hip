@@ -153,4 +153,10 @@ hipError_t grade_rows(int n, int m, const double* b, const double* Ainv, double*
   return hipGetLastError();
 }
 
+hipError_t row_maxima(int n, int m, const double* c, double* gamma, int32_t* argmax, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(maxabs_kernel, dim3((n + 3) / 4), dim3(64, 4), 0, s, n, m, c, gamma, argmax);
+  return hipGetLastError();
+}
+
 }  // namespace mtp

@@ -110,6 +110,8 @@ struct mtp_model {
   int64_t built_atoms = -1;
   int built_cfgs = -1, built_K = 0;
   Buffer xbuild, img, disp;
+  // MaxVol selection (mtp_maxvol)
+  Buffer mv_W, mv_perm, mv_C, mv_max, mv_arg, mv_col, mv_row, mv_pick, mv_gj, mv_inv, mv_flag;
   int32_t lists_reused = 0, list_builds = 0;
   Buffer b_tmp, c_tmp;
   int last_stride = 0;
@@ -623,6 +625,95 @@ int mtp_set_active_set(mtp_model* M, const double* A_dev, void* stream) {
     return fail(MTP_E_ARG, "mtp_set_active_set: A is numerically singular");
   }
   M->has_active = true;
+  return MTP_OK;
+}
+
+int mtp_maxvol(mtp_model* M, int32_t n_pool, const double* pool_dev, int32_t* rows_dev, int init, double delta,
+               int32_t max_swaps, int32_t* n_swaps, void* stream) {
+  using namespace mtp;
+  g_err.clear();
+  if (!M || !pool_dev || !rows_dev) return fail(MTP_E_ARG, "mtp_maxvol: null argument");
+  const int m = M->m, K = n_pool;
+  if (K < m) return fail(MTP_E_ARG, "mtp_maxvol: the pool has fewer rows than the basis size");
+  if (!(delta >= 0.0)) return fail(MTP_E_ARG, "mtp_maxvol: delta must be non-negative");
+  if ((int64_t)K * m >= 0x7fffffffLL) return fail(MTP_E_CAPACITY, "mtp_maxvol: pool too large");
+  if (max_swaps < 0) max_swaps = 100 * m;
+  HIP_TRY(hipSetDevice(M->device), "hipSetDevice");
+  hipStream_t s = (hipStream_t)stream;
+  const size_t km = (size_t)K * m;
+  HIP_TRY(M->mv_C.ensure(sizeof(double) * km), "hipMalloc");
+  HIP_TRY(M->mv_max.ensure(sizeof(double) * K), "hipMalloc");
+  HIP_TRY(M->mv_arg.ensure(sizeof(int32_t) * K), "hipMalloc");
+  HIP_TRY(M->mv_col.ensure(sizeof(double) * K), "hipMalloc");
+  HIP_TRY(M->mv_row.ensure(sizeof(double) * m), "hipMalloc");
+  HIP_TRY(M->mv_pick.ensure(sizeof(MaxvolPick)), "hipMalloc");
+  HIP_TRY(M->mv_gj.ensure(sizeof(double) * 2 * (size_t)m * m), "hipMalloc");
+  HIP_TRY(M->mv_inv.ensure(sizeof(double) * (size_t)m * m), "hipMalloc");
+  HIP_TRY(M->mv_flag.ensure(sizeof(int)), "hipMalloc");
+  auto read_flag = [&](int& v) -> hipError_t {
+    hipError_t e = hipMemcpyAsync(&v, M->mv_flag.p, sizeof(int), hipMemcpyDeviceToHost, s);
+    return e == hipSuccess ? hipStreamSynchronize(s) : e;
+  };
+  int flag = 0;
+  if (init) {
+    // the caller's starting rows: distinct pool indices
+    std::vector<int32_t> r(m);
+    HIP_TRY(hipMemcpyAsync(r.data(), rows_dev, sizeof(int32_t) * m, hipMemcpyDeviceToHost, s), "hipMemcpyAsync");
+    HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
+    std::vector<int32_t> sorted(r);
+    std::sort(sorted.begin(), sorted.end());
+    for (int t = 0; t < m; ++t)
+      if (sorted[t] < 0 || sorted[t] >= K || (t > 0 && sorted[t] == sorted[t - 1]))
+        return fail(MTP_E_ARG, "mtp_maxvol: starting rows must be distinct indices into the pool");
+  } else {
+    HIP_TRY(M->mv_W.ensure(sizeof(double) * km), "hipMalloc");
+    HIP_TRY(M->mv_perm.ensure(sizeof(int32_t) * K), "hipMalloc");
+    HIP_TRY(hipMemcpyAsync(M->mv_W.p, pool_dev, sizeof(double) * km, hipMemcpyDeviceToDevice, s), "hipMemcpyAsync");
+    HIP_TRY(maxvol_pivot_rows(K, m, M->mv_W.as<double>(), M->mv_perm.as<int32_t>(), rows_dev, M->mv_flag.as<int>(), s),
+            "pivot rows");
+    HIP_TRY(read_flag(flag), "pivot rows");
+    if (flag) return fail(MTP_E_ARG, "mtp_maxvol: the pool has rank below the basis size");
+  }
+  double* C = M->mv_C.as<double>();
+  // A^{-1} of the selected rows and C = pool A^{-1} from scratch, with row maxima
+  auto refresh = [&]() -> int {
+    HIP_TRY(maxvol_gather(m, pool_dev, rows_dev, M->mv_gj.as<double>(), s), "gather");
+    HIP_TRY(gauss_jordan_inverse(m, M->mv_gj.as<double>(), M->mv_inv.as<double>(), M->mv_flag.as<int>(), s),
+            "Gauss-Jordan");
+    HIP_TRY(read_flag(flag), "Gauss-Jordan");
+    if (flag) return fail(MTP_E_ARG, "mtp_maxvol: the selected rows are numerically singular");
+    HIP_TRY(grade_rows(K, m, pool_dev, M->mv_inv.as<double>(), M->mv_max.as<double>(), M->mv_arg.as<int32_t>(), C,
+                       s),
+            "C = pool A^-1");
+    return MTP_OK;
+  };
+  constexpr int kRefresh = 32;   // swaps between recomputations of C
+  int rc = refresh();
+  if (rc != MTP_OK) return rc;
+  int swaps = 0, since = 0;
+  MaxvolPick* pick_dev = M->mv_pick.as<MaxvolPick>();
+  for (;;) {
+    MaxvolPick pk{};
+    HIP_TRY(maxvol_pick(K, M->mv_max.as<double>(), M->mv_arg.as<int32_t>(), pick_dev, s), "pick");
+    HIP_TRY(hipMemcpyAsync(&pk, pick_dev, sizeof(pk), hipMemcpyDeviceToHost, s), "hipMemcpyAsync");
+    HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
+    if (!(pk.value > 1.0 + delta)) {
+      if (since == 0) break;               // a freshly computed C: converged
+      if ((rc = refresh()) != MTP_OK) return rc;
+      since = 0;
+      continue;
+    }
+    if (swaps >= max_swaps) break;
+    HIP_TRY(maxvol_swap(K, m, C, pick_dev, M->mv_col.as<double>(), M->mv_row.as<double>(), rows_dev, s), "swap");
+    ++swaps;
+    if (++since >= kRefresh) {
+      if ((rc = refresh()) != MTP_OK) return rc;
+      since = 0;
+    } else {
+      HIP_TRY(row_maxima(K, m, C, M->mv_max.as<double>(), M->mv_arg.as<int32_t>(), s), "row maxima");
+    }
+  }
+  if (n_swaps) *n_swaps = swaps;
   return MTP_OK;
 }
 

@@ -147,10 +147,28 @@ hipError_t loss_finish(int fp64, int n_cfg, int64_t N, int stride, int m, int n_
                        const double* loss_cfg, const double* loss_atom, const void* xi_terms, const int32_t* perm,
                        const double* cpart, double* loss, double* grad, hipStream_t s);
 
+// MaxVol selection (section 2.3): the largest |C_ij| and where it is.
+struct MaxvolPick {
+  double value;
+  int32_t i, j;
+};
+// Pivot rows of Gaussian elimination with partial pivoting of W [K][m]
+// (columns equilibrated first; W and perm [K] are overwritten), ascending.
+hipError_t maxvol_pivot_rows(int K, int m, double* W, int32_t* perm, int32_t* rows, int* singular, hipStream_t s);
+// [A | I] [m][2m] with A = pool[rows].
+hipError_t maxvol_gather(int m, const double* pool, const int32_t* rows, double* W, hipStream_t s);
+// Largest entry over the per-row maxima (lowest row on ties).
+hipError_t maxvol_pick(int K, const double* rowmax, const int32_t* rowarg, MaxvolPick* out, hipStream_t s);
+// Rank-one update of C [K][m] for the swap in *pick; rows[pick->j] = pick->i.
+hipError_t maxvol_swap(int K, int m, double* C, const MaxvolPick* pick, double* colj, double* rowi, int32_t* rows,
+                       hipStream_t s);
+
 // Dense FP64 helpers of the grade.
 hipError_t gauss_jordan_inverse(int m, double* work /*[m][2m]*/, double* inv, int* singular,
                                 hipStream_t s);
 hipError_t grade_rows(int n, int m, const double* b, const double* Ainv, double* gamma,
                       int32_t* argmax, double* c, hipStream_t s);
+// Per row of c [n][m]: max |c| and its first index.
+hipError_t row_maxima(int n, int m, const double* c, double* gamma, int32_t* argmax, hipStream_t s);
 
 }  // namespace mtp

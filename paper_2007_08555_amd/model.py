@@ -240,6 +240,21 @@ class Potential:
               "mtp_grade_from_b")
         return (gamma, arg, c) if want_c else (gamma, arg)
 
+    def maxvol(self, pool, rows=None, delta=1e-3, max_swaps=-1, stream=None):
+        """MaxVol selection of m rows of pool [K, m] (FP64, file order) by
+        mtp_maxvol; rows = starting rows, or None for the pivot rows of
+        Gaussian elimination.  Returns (rows int32 [m] on the device, swaps)."""
+        pool = torch.as_tensor(pool, dtype=torch.float64).to(self.device).contiguous()
+        K = int(pool.shape[0])
+        if rows is None:
+            r = torch.zeros(self.m, dtype=torch.int32, device=self.device)
+        else:
+            r = torch.as_tensor(rows, dtype=torch.int32).to(self.device).clone().contiguous()
+        n = ctypes.c_int32()
+        check(lib().mtp_maxvol(self._h, K, _ptr(pool), _ptr(r), 0 if rows is None else 1, float(delta),
+                               int(max_swaps), ctypes.byref(n), _stream(stream)), "mtp_maxvol")
+        return r, n.value
+
     def grade(self, batch: Batch, precision="fp32", stream=None):
         gamma = torch.empty(batch.n_configs, dtype=torch.float64, device=self.device)
         arg = torch.empty(batch.n_configs, dtype=torch.int32, device=self.device)
