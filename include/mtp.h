@@ -253,6 +253,20 @@ int mtp_status(mtp_model* model, void* stream, int64_t* n_below_rmin, int64_t* n
 int mtp_maxvol(mtp_model* model, int32_t n_pool, const double* pool_dev, int32_t* rows_dev, int init,
                double delta, int32_t max_swaps, int32_t* n_swaps, void* stream);
 
+/*
+ * One half step of velocity Verlet for the molecular dynamics in which the
+ * active learning of section 2.3 runs: vel += (dt/2) F / m for every atom
+ * and, when drift != 0, then pos += dt vel.  Device arrays: species [n]
+ * int32, pos [n][3] and vel [n][3] FP64 (Angstrom, Angstrom/fs, updated in
+ * place), forces [n][3] FP64 (eV/A, from mtp_eval); mass_host [S] in atomic
+ * mass units; dt in fs.  A step is kick+drift, mtp_eval at the new
+ * positions, kick.  Asynchronous on `stream`, except that a call with
+ * masses different from the previous call's first synchronises it to copy
+ * them to the device.
+ */
+int mtp_md_kick(mtp_model* model, int64_t n_atoms, const int32_t* species_dev, double* pos_dev, double* vel_dev,
+                const double* forces_dev, const double* mass_host, double dt_fs, int drift, void* stream);
+
 /* Counters and device timings of the last mtp_eval on a model. */
 typedef struct {
   int64_t n_atoms;          /* atoms of the last batch */

@@ -73,6 +73,7 @@ _SIGNATURES = {
     "mtp_set_timing": (ctypes.c_int, [_P, ctypes.c_int]),
     "mtp_get_stats": (ctypes.c_int, [_P, ctypes.POINTER(mtp_stats)]),
     "mtp_set_skin": (ctypes.c_int, [_P, ctypes.c_double]),
+    "mtp_md_kick": (ctypes.c_int, [_P, ctypes.c_int64, _P, _P, _P, _P, _P, ctypes.c_double, ctypes.c_int, _P]),
     "mtp_maxvol": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, ctypes.c_int, ctypes.c_double, ctypes.c_int32,
                                   ctypes.POINTER(ctypes.c_int32), _P]),
     "mtp_free": (None, [_P]),

@@ -112,6 +112,9 @@ struct mtp_model {
   Buffer xbuild, img, disp;
   // MaxVol selection (mtp_maxvol)
   Buffer mv_W, mv_perm, mv_C, mv_max, mv_arg, mv_col, mv_row, mv_pick, mv_gj, mv_inv, mv_flag;
+  // MD (mtp_md_kick): inverse masses per species
+  Buffer md_inv_mass;
+  std::vector<double> md_masses;   // the masses md_inv_mass holds
   int32_t lists_reused = 0, list_builds = 0;
   Buffer b_tmp, c_tmp;
   int last_stride = 0;
@@ -625,6 +628,33 @@ int mtp_set_active_set(mtp_model* M, const double* A_dev, void* stream) {
     return fail(MTP_E_ARG, "mtp_set_active_set: A is numerically singular");
   }
   M->has_active = true;
+  return MTP_OK;
+}
+
+int mtp_md_kick(mtp_model* M, int64_t n_atoms, const int32_t* species_dev, double* pos_dev, double* vel_dev,
+                const double* forces_dev, const double* mass_host, double dt_fs, int drift, void* stream) {
+  g_err.clear();
+  if (!M || n_atoms < 0 || !mass_host) return fail(MTP_E_ARG, "mtp_md_kick: bad argument");
+  if (n_atoms > 0 && (!species_dev || !vel_dev || !forces_dev || (drift && !pos_dev)))
+    return fail(MTP_E_ARG, "mtp_md_kick: null array");
+  const int S = M->S;
+  std::vector<double> inv(S);
+  for (int z = 0; z < S; ++z) {
+    if (!(mass_host[z] > 0.0)) return fail(MTP_E_ARG, "mtp_md_kick: masses must be positive");
+    inv[z] = 1.0 / mass_host[z];
+  }
+  HIP_TRY(hipSetDevice(M->device), "hipSetDevice");
+  hipStream_t s = (hipStream_t)stream;
+  if (M->md_masses != std::vector<double>(mass_host, mass_host + S)) {
+    // new masses: a synchronous copy (the host vector is gone after return)
+    HIP_TRY(M->md_inv_mass.ensure(sizeof(double) * S), "hipMalloc");
+    HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
+    HIP_TRY(hipMemcpy(M->md_inv_mass.p, inv.data(), sizeof(double) * S, hipMemcpyHostToDevice), "hipMemcpy");
+    M->md_masses.assign(mass_host, mass_host + S);
+  }
+  HIP_TRY(mtp::md_kick(n_atoms, species_dev, S, M->md_inv_mass.as<double>(), pos_dev, vel_dev, forces_dev, dt_fs,
+                       drift, s),
+          "kick");
   return MTP_OK;
 }
 

@@ -163,6 +163,11 @@ hipError_t maxvol_pick(int K, const double* rowmax, const int32_t* rowarg, Maxvo
 hipError_t maxvol_swap(int K, int m, double* C, const MaxvolPick* pick, double* colj, double* rowi, int32_t* rows,
                        hipStream_t s);
 
+// Velocity Verlet: v += (dt/2) F/m (masses per species, 1/m in amu^-1 on
+// the device); with drift also x += dt v.
+hipError_t md_kick(int64_t n, const int32_t* species, int S, const double* inv_mass, double* pos, double* vel,
+                   const double* F, double dt, int drift, hipStream_t s);
+
 // Dense FP64 helpers of the grade.
 hipError_t gauss_jordan_inverse(int m, double* work /*[m][2m]*/, double* inv, int* singular,
                                 hipStream_t s);
