@@ -53,13 +53,19 @@ __global__ void fit_rows_kernel(int n_cfg, int64_t N, int64_t R, const CfgInfo* 
 }
 
 // Partial Gram products P[s] = Ja^T diag(w) Ja over the rows of split s, for
-// the output tiles (ta, tb) with ta <= tb.  Ja is column-major [n][R].
-__global__ void __launch_bounds__(kTile * kTile) gram_kernel(int n, int64_t R, int64_t rows_per_split,
-                                                          const double* __restrict__ Ja,
-                                                          const double* __restrict__ w, double* __restrict__ P) {
+// the output tiles (ta, tb) with ta <= tb, on the FP64 matrix cores: one
+// wavefront per tile pair and split.  Rows are staged kRows at a time in LDS
+// (coalesced along the rows of the column-major Ja [n][R]); each
+// v_mfma_f64_16x16x4 takes four of them, lane l supplying
+// w[r] Ja[ta*16 + l%16][r] and Ja[tb*16 + l%16][r] for r = r0 + l/16, and
+// lane l holds entry (4j + l/16, l%16) of the tile in slot j.
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+__global__ void __launch_bounds__(64) gram_kernel(int n, int64_t R, int64_t rows_per_split,
+                                                  const double* __restrict__ Ja, const double* __restrict__ w,
+                                                  double* __restrict__ P) {
   __shared__ double sa[kTile][kRows + 1];
   __shared__ double sb[kTile][kRows + 1];
-  __shared__ double sw[kRows];
   // tile pair of this workgroup: blockIdx.x enumerates ta <= tb row by row
   const int nt = (n + kTile - 1) / kTile;
   int ta = 0, rem = blockIdx.x;
@@ -68,29 +74,30 @@ __global__ void __launch_bounds__(kTile * kTile) gram_kernel(int n, int64_t R, i
     ++ta;
   }
   const int tb = ta + rem;
-  const int t = threadIdx.x;
-  const int a = t / kTile, b = t % kTile;
+  const int l = threadIdx.x;
   const int64_t r0 = (int64_t)blockIdx.y * rows_per_split;
   const int64_t r1 = min(R, r0 + rows_per_split);
-  double acc = 0.0;
+  v4d acc = {0.0, 0.0, 0.0, 0.0};
   for (int64_t rb = r0; rb < r1; rb += kRows) {
-    // stage kRows rows of the two 16-column blocks (coalesced along rows)
-    for (int e = t; e < kTile * kRows; e += blockDim.x) {
+    for (int e = l; e < kTile * kRows; e += 64) {
       const int col = e / kRows, rr = e % kRows;
       const int64_t row = rb + rr;
       const bool in = row < r1;
       const int ca = ta * kTile + col, cb = tb * kTile + col;
-      sa[col][rr] = (in && ca < n) ? Ja[(size_t)ca * R + row] : 0.0;
+      sa[col][rr] = (in && ca < n) ? Ja[(size_t)ca * R + row] * w[row] : 0.0;
       sb[col][rr] = (in && cb < n) ? Ja[(size_t)cb * R + row] : 0.0;
-      if (col == 0) sw[rr] = in ? w[row] : 0.0;
     }
     __syncthreads();
-#pragma unroll 8
-    for (int rr = 0; rr < kRows; ++rr) acc = fma(sa[a][rr] * sw[rr], sb[b][rr], acc);
+#pragma unroll 4
+    for (int k0 = 0; k0 < kRows; k0 += 4)
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(sa[l & 15][k0 + (l >> 4)], sb[l & 15][k0 + (l >> 4)], acc, 0, 0, 0);
     __syncthreads();
   }
-  const int ca = ta * kTile + a, cb = tb * kTile + b;
-  if (ca < n && cb < n) P[(size_t)blockIdx.y * n * n + (size_t)ca * n + cb] = acc;
+  const int cb = tb * kTile + (l & 15);
+  for (int j = 0; j < 4; ++j) {
+    const int ca = ta * kTile + 4 * j + (l >> 4);
+    if (ca < n && cb < n) P[(size_t)blockIdx.y * n * n + (size_t)ca * n + cb] = acc[j];
+  }
 }
 
 // Sum of the partials in split order (deterministic); H [m][m], g [m], yy.
@@ -165,7 +172,7 @@ hipError_t gram(int n, int64_t R, const double* Ja, const double* w, double* P, 
   const int nt = (n + kTile - 1) / kTile;
   const int pairs = nt * (nt + 1) / 2;
   const int64_t per = (R + splits - 1) / splits;
-  hipLaunchKernelGGL(gram_kernel, dim3(pairs, splits), dim3(kTile * kTile), 0, s, n, R, per, Ja, w, P);
+  hipLaunchKernelGGL(gram_kernel, dim3(pairs, splits), dim3(64), 0, s, n, R, per, Ja, w, P);
   hipLaunchKernelGGL(gram_reduce_kernel, dim3((n * n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, n, splits, P,
                      accumulate, H, g, yy);
   return hipGetLastError();

@@ -94,26 +94,32 @@ __global__ void __launch_bounds__(kGJBlock) gj_kernel(int m, double* W, double* 
   }
 }
 
-// c = b A^{-1} with 16 x 16 output tiles staged through LDS; then per row the
-// max |c| and its first index.
-constexpr int kT = 16;
+// c = b A^{-1} on the FP64 matrix cores: one wavefront per 16 x 16 tile of c;
+// each v_mfma_f64_16x16x4 takes four k, lane l supplying b[row0 + l%16][k]
+// and A^{-1}[k][col0 + l%16] for k = k0 + l/16 (zero past m), and lane l
+// holds c[row0 + 4j + l/16][col0 + l%16] in slot j.  Then, per row, the max |c|
+// and its first index.
+typedef double v4d __attribute__((ext_vector_type(4)));
 
-__global__ void __launch_bounds__(kT * kT) gemm_kernel(int n, int m, const double* __restrict__ b,
-                                                      const double* __restrict__ A, double* __restrict__ c) {
-  __shared__ double sb[kT][kT + 1];
-  __shared__ double sa[kT][kT + 1];
-  const int tx = threadIdx.x % kT, ty = threadIdx.x / kT;
-  const int row = blockIdx.y * kT + ty, col = blockIdx.x * kT + tx;
-  double acc = 0;
-  for (int k0 = 0; k0 < m; k0 += kT) {
-    sb[ty][tx] = (row < n && k0 + tx < m) ? b[(size_t)row * m + k0 + tx] : 0.0;
-    sa[ty][tx] = (k0 + ty < m && col < m) ? A[(size_t)(k0 + ty) * m + col] : 0.0;
-    __syncthreads();
-#pragma unroll
-    for (int k = 0; k < kT; ++k) acc = fma(sb[ty][k], sa[k][tx], acc);
-    __syncthreads();
+__global__ void __launch_bounds__(256) gemm_kernel(int n, int m, const double* __restrict__ b,
+                                                   const double* __restrict__ A, double* __restrict__ c) {
+  const int l = threadIdx.x & 63;
+  const int tiles_m = (m + 15) / 16;
+  const int tile = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int row0 = (tile / tiles_m) * 16, col0 = (tile % tiles_m) * 16;
+  if (row0 >= n) return;   // the whole wavefront
+  const int ar = row0 + (l & 15), bc = col0 + (l & 15), kk = l >> 4;
+  v4d acc = {0.0, 0.0, 0.0, 0.0};
+  for (int k0 = 0; k0 < m; k0 += 4) {
+    const int k = k0 + kk;
+    const double x = (ar < n && k < m) ? b[(size_t)ar * m + k] : 0.0;
+    const double y = (k < m && bc < m) ? A[(size_t)k * m + bc] : 0.0;
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(x, y, acc, 0, 0, 0);
   }
-  if (row < n && col < m) c[(size_t)row * m + col] = acc;
+  for (int j = 0; j < 4; ++j) {
+    const int r = row0 + 4 * j + kk;
+    if (r < n && bc < m) c[(size_t)r * m + bc] = acc[j];
+  }
 }
 
 __global__ void maxabs_kernel(int n, int m, const double* __restrict__ c, double* gamma, int32_t* arg) {
@@ -147,8 +153,8 @@ hipError_t gauss_jordan_inverse(int m, double* work, double* inv, int* singular,
 hipError_t grade_rows(int n, int m, const double* b, const double* Ainv, double* gamma, int32_t* argmax,
                       double* c, hipStream_t s) {
   if (n == 0) return hipSuccess;
-  const dim3 g((m + kT - 1) / kT, (n + kT - 1) / kT);
-  hipLaunchKernelGGL(gemm_kernel, g, dim3(kT * kT), 0, s, n, m, b, Ainv, c);
+  const int tiles = ((n + 15) / 16) * ((m + 15) / 16);
+  hipLaunchKernelGGL(gemm_kernel, dim3((tiles + 3) / 4), dim3(256), 0, s, n, m, b, Ainv, c);
   hipLaunchKernelGGL(maxabs_kernel, dim3((n + 3) / 4), dim3(64, 4), 0, s, n, m, c, gamma, argmax);
   return hipGetLastError();
 }
