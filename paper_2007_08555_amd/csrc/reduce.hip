@@ -56,49 +56,36 @@ __global__ void __launch_bounds__(kBlock) gather_kernel(int64_t n_atoms, int str
   F[3 * i + 2] = fz;
 }
 
-// One block per configuration.  Sums are formed in FP64 in a fixed order
-// (per-thread strided partial sums, then a tree over the block).
-template <typename T>
-__global__ void __launch_bounds__(kBlock) config_kernel(int n_cfg, const CfgInfo* __restrict__ cfg,
-                                                        int stride, const T* __restrict__ site,
-                                                        const T* __restrict__ wv, double* energy,
-                                                        double* virial, double* site_out) {
-  const int k = blockIdx.x;
-  if (k >= n_cfg) return;
+// FP64 sums of a configuration's site energies and per-atom virials in a
+// fixed order: per thread the atoms i, i + blockDim, i + 2 blockDim, ...,
+// then a tree over the block;
+// U atoms per thread are loaded together (U > 1 for large configurations:
+// the loads of one block then overlap).
+template <typename T, int U>
+__device__ __forceinline__ void config_sums(int k, const CfgInfo* __restrict__ cfg, int stride,
+                                            const T* __restrict__ site, const T* __restrict__ wv, double* energy,
+                                            double* virial, double* site_out) {
   const int64_t a0 = cfg[k].start, a1 = cfg[k].start + cfg[k].n;
   double acc[10];
   for (int t = 0; t < 10; ++t) acc[t] = 0.0;
-  // A large configuration is one block: U atoms per thread in flight.  Either
-  // loop adds the atoms i, i + blockDim, i + 2 blockDim, ... in order.
-  constexpr int U = 4;
-  if (a1 - a0 <= (int64_t)U * blockDim.x) {
-    for (int64_t i = a0 + threadIdx.x; i < a1; i += blockDim.x) {
-      const double v = (double)site[i];
-      acc[0] += v;
-      if (site_out) site_out[i] = v;
+  for (int64_t i0 = a0 + threadIdx.x; i0 < a1; i0 += (int64_t)U * blockDim.x) {
+    double v[U], w[U][9];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t i = i0 + (int64_t)u * blockDim.x;
+      const int64_t ic = i < a1 ? i : i0;
+      v[u] = (double)site[ic];
       if (wv)
-        for (int t = 0; t < 9; ++t) acc[1 + t] += (double)wv[(size_t)t * stride + i];
+        for (int t = 0; t < 9; ++t) w[u][t] = (double)wv[(size_t)t * stride + ic];
     }
-  } else {
-    for (int64_t i0 = a0 + threadIdx.x; i0 < a1; i0 += (int64_t)U * blockDim.x) {
-      double v[U], w[U][9];
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int64_t i = i0 + (int64_t)u * blockDim.x;
-        const int64_t ic = i < a1 ? i : i0;
-        v[u] = (double)site[ic];
-        if (wv)
-          for (int t = 0; t < 9; ++t) w[u][t] = (double)wv[(size_t)t * stride + ic];
-      }
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int64_t i = i0 + (int64_t)u * blockDim.x;
-        if (i >= a1) break;
-        acc[0] += v[u];
-        if (site_out) site_out[i] = v[u];
-        if (wv)
-          for (int t = 0; t < 9; ++t) acc[1 + t] += w[u][t];
-      }
+    for (int u = 0; u < U; ++u) {
+      const int64_t i = i0 + (int64_t)u * blockDim.x;
+      if (i >= a1) break;
+      acc[0] += v[u];
+      if (site_out) site_out[i] = v[u];
+      if (wv)
+        for (int t = 0; t < 9; ++t) acc[1 + t] += w[u][t];
     }
   }
   __shared__ double red[10][kBlock];
@@ -114,6 +101,29 @@ __global__ void __launch_bounds__(kBlock) config_kernel(int n_cfg, const CfgInfo
     if (virial && wv)
       for (int t = 0; t < 9; ++t) virial[9 * k + t] = red[1 + t][0];
   }
+}
+
+// One block per configuration; configurations above kLargeCfg atoms are left
+// to config_large_kernel (one atom per thread keeps this kernel's registers,
+// and so its occupancy over many small configurations, low).
+constexpr int kLargeCfg = 4 * kBlock;
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) config_kernel(int n_cfg, const CfgInfo* __restrict__ cfg, int stride,
+                                                        const T* __restrict__ site, const T* __restrict__ wv,
+                                                        double* energy, double* virial, double* site_out) {
+  const int k = blockIdx.x;
+  if (k >= n_cfg || cfg[k].n > kLargeCfg) return;
+  config_sums<T, 1>(k, cfg, stride, site, wv, energy, virial, site_out);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) config_large_kernel(int n_cfg, const CfgInfo* __restrict__ cfg, int stride,
+                                                              const T* __restrict__ site, const T* __restrict__ wv,
+                                                              double* energy, double* virial, double* site_out) {
+  const int k = blockIdx.x;
+  if (k >= n_cfg || cfg[k].n <= kLargeCfg) return;
+  config_sums<T, 4>(k, cfg, stride, site, wv, energy, virial, site_out);
 }
 
 // b[k][f] = sum over atoms of configuration k of B[perm[f]][atom]; one block
@@ -172,12 +182,17 @@ hipError_t reduce_configs(int fp64, int n_cfg, const CfgInfo* offs, int stride, 
                           double* site_out, hipStream_t s) {
   if (n_cfg == 0) return hipSuccess;
   if (energy || virial || site_out) {
-    if (fp64)
+    if (fp64) {
       hipLaunchKernelGGL(config_kernel<double>, dim3(n_cfg), dim3(kBlock), 0, s, n_cfg, offs, stride,
                          (const double*)site, (const double*)atom_virial, energy, virial, site_out);
-    else
+      hipLaunchKernelGGL(config_large_kernel<double>, dim3(n_cfg), dim3(kBlock), 0, s, n_cfg, offs, stride,
+                         (const double*)site, (const double*)atom_virial, energy, virial, site_out);
+    } else {
       hipLaunchKernelGGL(config_kernel<float>, dim3(n_cfg), dim3(kBlock), 0, s, n_cfg, offs, stride,
                          (const float*)site, (const float*)atom_virial, energy, virial, site_out);
+      hipLaunchKernelGGL(config_large_kernel<float>, dim3(n_cfg), dim3(kBlock), 0, s, n_cfg, offs, stride,
+                         (const float*)site, (const float*)atom_virial, energy, virial, site_out);
+    }
   }
   if (b && B) {
     if (fp64)
