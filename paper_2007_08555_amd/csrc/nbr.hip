@@ -576,35 +576,34 @@ __device__ inline bool nearest_cell(const CfgInfo& c) {
   return c.pbc && c.w[0] + 1e-3 < 0.5 && c.w[1] + 1e-3 < 0.5 && c.w[2] + 1e-3 < 0.5;
 }
 
-// Images of atom lj within R_cut of atom li in a periodic cell, in box order:
-// visit(rx, ry, rz, r2) for each.  Returns false when the box is empty.
-template <typename F>
-__device__ inline bool box_images(const CfgInfo& c, const SmallAtoms& sa, int li, int lj, double rc2, F&& visit) {
+// Image box of atom lj for atom li in a periodic cell: the n with
+// |s_d + n'_d| <= w_d (n = n' - m_j + m_i), bounds in FP32 with a margin
+// (membership is decided by the exact FP64 distance test).  Returns false
+// when no image can lie within R_cut.
+struct ImageBox {
+  int lo0, lo1, lo2, hi0, hi1, hi2;
+  double dx, dy, dz;   // x_j - x_i
+};
+
+__device__ inline bool box_may_hit(const CfgInfo& c, float4 ui, float4 uj) {
+  const float w0 = (float)c.w[0] + 1e-3f, w1 = (float)c.w[1] + 1e-3f, w2 = (float)c.w[2] + 1e-3f;
+  const float s0 = uj.x - ui.x, s1 = uj.y - ui.y, s2 = uj.z - ui.z;
+  return !(fabsf(s0 - rintf(s0)) > w0 || fabsf(s1 - rintf(s1)) > w1 || fabsf(s2 - rintf(s2)) > w2);
+}
+
+__device__ inline ImageBox image_box_of(const CfgInfo& c, const SmallAtoms& sa, int li, int lj) {
   const float w0 = (float)c.w[0] + 1e-3f, w1 = (float)c.w[1] + 1e-3f, w2 = (float)c.w[2] + 1e-3f;
   const float4 ui = sa.u[li], uj = sa.u[lj];
   const float s0 = uj.x - ui.x, s1 = uj.y - ui.y, s2 = uj.z - ui.z;
-  if (fabsf(s0 - rintf(s0)) > w0 || fabsf(s1 - rintf(s1)) > w1 || fabsf(s2 - rintf(s2)) > w2) return false;
-  const int lo0 = -(int)floorf(w0 + s0), hi0 = (int)floorf(w0 - s0);
-  const int lo1 = -(int)floorf(w1 + s1), hi1 = (int)floorf(w1 - s1);
-  const int lo2 = -(int)floorf(w2 + s2), hi2 = (int)floorf(w2 - s2);
-  const double4 pi = sa.x[li], pj = sa.x[lj];
-  const double dx = pj.x - pi.x, dy = pj.y - pi.y, dz = pj.z - pi.z;
-  // n = n' - m_j + m_i
   const int4 mi = sa.mz[li], mj = sa.mz[lj];
   const int o0 = mi.x - mj.x, o1 = mi.y - mj.y, o2 = mi.z - mj.z;
-  const double* L = c.L;
-  for (int n0 = lo0 + o0; n0 <= hi0 + o0; ++n0)
-    for (int n1 = lo1 + o1; n1 <= hi1 + o1; ++n1)
-      for (int n2 = lo2 + o2; n2 <= hi2 + o2; ++n2) {
-        if (lj == li && n0 == 0 && n1 == 0 && n2 == 0) continue;
-        const double sx = (double)n0 * L[0] + (double)n1 * L[3] + (double)n2 * L[6];
-        const double sy = (double)n0 * L[1] + (double)n1 * L[4] + (double)n2 * L[7];
-        const double sz = (double)n0 * L[2] + (double)n1 * L[5] + (double)n2 * L[8];
-        const double rx = dx + sx, ry = dy + sy, rz = dz + sz;
-        const double r2 = rx * rx + ry * ry + rz * rz;
-        if (r2 < rc2) visit(rx, ry, rz, r2);
-      }
-  return true;
+  const double4 pi = sa.x[li], pj = sa.x[lj];
+  ImageBox q;
+  q.lo0 = -(int)floorf(w0 + s0) + o0; q.hi0 = (int)floorf(w0 - s0) + o0;
+  q.lo1 = -(int)floorf(w1 + s1) + o1; q.hi1 = (int)floorf(w1 - s1) + o1;
+  q.lo2 = -(int)floorf(w2 + s2) + o2; q.hi2 = (int)floorf(w2 - s2) + o2;
+  q.dx = pj.x - pi.x; q.dy = pj.y - pi.y; q.dz = pj.z - pi.z;
+  return q;
 }
 
 // The pair vector of atom lj's nearest image for atom li in a nearest cell.
@@ -641,13 +640,67 @@ __device__ inline void small_candidates(const CfgInfo& c, const SmallAtoms& sa, 
     }
     return;
   }
-  for (int lj = 0; lj < n; ++lj) {
-    int k = 0;
-    box_images(c, sa, li, lj, rc2, [&](double rx, double ry, double rz, double r2) {
-      visit.pair(lj, rx, ry, rz, r2);
-      ++k;
-    });
-    if (k > 0) visit.run_end(lj, k);
+  // Periodic cell.  Most atoms have no image within reach (an empty box) and
+  // the others a few, differently many per lane; looping over each atom's
+  // box in step would keep the wavefront for the largest box of every atom.
+  // Instead phase A marks, in a bit mask over the configuration's atoms, the
+  // atoms whose box may hold an image (all lanes test the same atom, LDS
+  // broadcasts), and phase B walks the marked atoms' images as one flat
+  // sequence per lane: one image per iteration, the next marked atom taken
+  // when a box is exhausted, so lanes stay busy until their own last image.
+  const float4 ui = sa.u[li];
+  uint64_t m0 = 0, m1 = 0, m2 = 0, m3 = 0;   // n <= 256 atoms
+#pragma unroll
+  for (int wi = 0; wi < 4; ++wi) {
+    uint64_t bits = 0;
+    const int top = n - 64 * wi < 64 ? n - 64 * wi : 64;
+    for (int bi = 0; bi < top; ++bi)
+      if (box_may_hit(c, ui, sa.u[64 * wi + bi])) bits |= 1ull << bi;
+    if (wi == 0) m0 = bits; else if (wi == 1) m1 = bits; else if (wi == 2) m2 = bits; else m3 = bits;
+  }
+  const double* L = c.L;
+  ImageBox q{0, 0, 0, -1, 0, 0, 0.0, 0.0, 0.0};
+  int lj = -1, k = 0, wbase = 0, n0 = 0, n1 = 0, n2 = 0;
+  while (true) {
+    if (n0 > q.hi0) {   // box exhausted: the next marked atom with a non-empty box
+      if (k > 0) visit.run_end(lj, k);
+      k = 0;
+      bool found = false;
+      while (true) {
+        while (m0 == 0 && wbase < 192) {
+          m0 = m1; m1 = m2; m2 = m3; m3 = 0;
+          wbase += 64;
+        }
+        if (m0 == 0) break;
+        lj = wbase + __builtin_ctzll(m0);
+        m0 &= m0 - 1;
+        q = image_box_of(c, sa, li, lj);
+        if (q.lo0 <= q.hi0 && q.lo1 <= q.hi1 && q.lo2 <= q.hi2) {
+          found = true;
+          break;
+        }
+      }
+      if (!found) break;
+      n0 = q.lo0; n1 = q.lo1; n2 = q.lo2;
+    }
+    if (!(lj == li && n0 == 0 && n1 == 0 && n2 == 0)) {
+      const double sx = (double)n0 * L[0] + (double)n1 * L[3] + (double)n2 * L[6];
+      const double sy = (double)n0 * L[1] + (double)n1 * L[4] + (double)n2 * L[7];
+      const double sz = (double)n0 * L[2] + (double)n1 * L[5] + (double)n2 * L[8];
+      const double rx = q.dx + sx, ry = q.dy + sy, rz = q.dz + sz;
+      const double r2 = rx * rx + ry * ry + rz * rz;
+      if (r2 < rc2) {
+        visit.pair(lj, rx, ry, rz, r2);
+        ++k;
+      }
+    }
+    if (++n2 > q.hi2) {
+      n2 = q.lo2;
+      if (++n1 > q.hi1) {
+        n1 = q.lo1;
+        ++n0;
+      }
+    }
   }
 }
 
