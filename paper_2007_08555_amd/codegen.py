@@ -474,7 +474,9 @@ def adjoint_passes(s, budget):
 ADJOINT_TEMPLATE = r"""
 // Adjoint pass {pidx} over the pairs of one atom, components of degrees {nus}:
 // its share of g = dV_i/dr_ij from G, f_mu and df_mu/dr, stored (first pass)
-// or added (later passes) per pair for the force and virial gather.
+// or added (later passes) per pair for the force and virial gather; the
+// last pass also sums the atom's own share of its force, sum_p g_p, in FP64,
+// so that the gather only has to fetch the reverse pairs' g.
 template <typename T, bool FIRST, bool LAST, int NQ>
 __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2)))
 adjoint_{tag}_kernel(const mtp::EvalArgs<T> args) {{
@@ -495,7 +497,8 @@ adjoint_{tag}_kernel(const mtp::EvalArgs<T> args) {{
   T G[CP];
 #pragma unroll
   for (int k = 0; k < CP; ++k) G[k] = args.G[(size_t)kIdx[k] * args.stride + i];
-  // the last pass also sums the per-atom virial sum_p g_p (x) r_p
+  // the last pass also sums the per-atom virial sum_p g_p (x) r_p and sum_p g_p
+  double o0 = 0.0, o1 = 0.0, o2 = 0.0;
   T w0 = T(0), w1 = T(0), w2 = T(0), w3 = T(0), w4 = T(0), w5 = T(0), w6 = T(0), w7 = T(0), w8 = T(0);
   // pair p + 1 (and its partial g) is loaded while pair p is processed
   T xn = T(0), yn = T(0), zn = T(0), g0n = T(0), g1n = T(0), g2n = T(0);
@@ -530,6 +533,7 @@ adjoint_{tag}_kernel(const mtp::EvalArgs<T> args) {{
       w0 += tx * x; w1 += tx * y; w2 += tx * z;
       w3 += ty * x; w4 += ty * y; w5 += ty * z;
       w6 += tz * x; w7 += tz * y; w8 += tz * z;
+      o0 += (double)tx; o1 += (double)ty; o2 += (double)tz;
     }}
   }}
   if constexpr (LAST) {{
@@ -537,6 +541,8 @@ adjoint_{tag}_kernel(const mtp::EvalArgs<T> args) {{
     const size_t st = args.stride;
     wv[0] = w0; wv[st] = w1; wv[2 * st] = w2; wv[3 * st] = w3; wv[4 * st] = w4;
     wv[5 * st] = w5; wv[6 * st] = w6; wv[7 * st] = w7; wv[8 * st] = w8;
+    double* ow = args.own + i;
+    ow[0] = o0; ow[st] = o1; ow[2 * st] = o2;
   }}
 }}
 """

@@ -99,7 +99,7 @@ struct mtp_model {
   Buffer ainv, gj_work, gj_flag;
   // workspace
   Buffer cfg, cfg_order, atom_cfg, atom_bin, bin_count, bin_start, bin_atoms, bin_fill, binned, nbins_dev;
-  Buffer count, nbr, pr, rev, gpair, Mbuf, Gbuf, Dbuf, site, wv, B, status, run_start;
+  Buffer count, nbr, pr, rev, gpair, own, Mbuf, Gbuf, Dbuf, site, wv, B, status, run_start;
   int K = 64;  // neighbour capacity per atom, grown on overflow
   int schedule64 = 0;  // FP64 pass split of the evaluation kernels (mtp_autotune)
   // Verlet skin (mtp_set_skin): lists of the last build, reused while the
@@ -329,6 +329,7 @@ mtp::EvalArgs<T> make_args(mtp_model* M, int64_t n_atoms, int stride, const int3
   a.D = M->Dbuf.as<T>();
   a.g = M->gpair.as<T>();
   a.atom_virial = M->wv.as<T>();
+  a.own = M->own.as<double>();
   a.B = want_b ? M->B.as<T>() : nullptr;
   a.b_stride = stride;
   return a;
@@ -383,6 +384,7 @@ int run_eval(mtp_model* M, const mtp_batch* bt, const mtp_out* out, int precisio
     NEED(M->rev, sizeof(int32_t) * slots);
     NEED(M->pr, (fp64 ? sizeof(PairRec<double>) : sizeof(PairRec<float>)) * slots);
     NEED(M->gpair, tsz * 3 * slots);
+    NEED(M->own, sizeof(double) * 3 * (size_t)stride);
     NEED(M->Gbuf, tsz * (size_t)M->var->C * stride);
     NEED(M->Mbuf, tsz * (size_t)M->var->C * stride);
     NEED(M->Dbuf, tsz * (size_t)M->var->n_graphs * stride);
@@ -473,7 +475,8 @@ int run_eval(mtp_model* M, const mtp_batch* bt, const mtp_out* out, int precisio
     }
     HIP_TRY(mark(2), "hipEventRecord");
     // the per-atom virials were summed by the last adjoint pass
-    HIP_TRY(gather_forces(fp64, N, stride, M->count.as<int32_t>(), M->rev.as<int32_t>(), M->gpair.p, out->forces, s),
+    HIP_TRY(gather_forces(fp64, N, stride, M->count.as<int32_t>(), M->rev.as<int32_t>(), M->gpair.p,
+                          M->own.as<double>(), out->forces, s),
             "force gather");
     HIP_TRY(mark(3), "hipEventRecord");
     HIP_TRY(reduce_configs(fp64, n_cfg, M->cfg.as<CfgInfo>(), stride, M->site.p, out->virial ? M->wv.p : nullptr,
@@ -921,7 +924,7 @@ int mtp_normal_equations(mtp_model* M, const mtp_batch* bt, const double* E_t, c
       }
     }
     HIP_TRY(mtp::gather_forces(fp64, N, stride, M->count.as<int32_t>(), M->rev.as<int32_t>(), M->gpair.p,
-                               col + K_cfg, s),
+                               M->own.as<double>(), col + K_cfg, s),
             "force gather");
     HIP_TRY(mtp::reduce_configs(fp64, K_cfg, M->cfg.as<mtp::CfgInfo>(), stride, M->site.p, M->wv.p, nullptr, m,
                                 stride, M->perm_dev.as<int32_t>(), col, col + K_cfg + 3 * N, nullptr, nullptr, s),

@@ -48,6 +48,7 @@ struct EvalArgs {
   T* G;                  // [C][stride] dV_i / dM (moment components)
   T* g;                  // [K * stride][3] dV_i / dr_ij, packed per pair
   T* atom_virial;        // [9][stride]  sum_j g_a r_b
+  double* own;          // [3][stride]  sum_j g_ij in FP64 (the atom's own share of its force)
   T* D;                  // [n_graphs][stride] dV_i / dg for every connected graph g
   T* B;                  // [m][b_stride] optional basis values
   int b_stride;

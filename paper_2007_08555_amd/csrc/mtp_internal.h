@@ -82,10 +82,11 @@ hipError_t refresh_pairs(const NbrArgs& a, const short4* img, hipStream_t s);
 // Sets n 32-bit words to zero with a kernel (capturable, unlike memset nodes).
 hipError_t zero_words(int32_t* p, int64_t n, hipStream_t s);
 
-// Forces F_i = sum over slots (g_p - g_rev(p)); g packed [K * stride][3];
+// Forces F_i = own_i - sum over slots g_rev(p), own_i = sum_p g_p summed by
+// the last adjoint pass ([3][stride], FP64); g packed [K * stride][3];
 // nothing is launched when forces is null.
 hipError_t gather_forces(int fp64, int64_t n_atoms, int stride, const int32_t* count,
-                         const int32_t* rev, const void* g, double* forces, hipStream_t s);
+                         const int32_t* rev, const void* g, const double* own, double* forces, hipStream_t s);
 
 // Per-configuration sums of site energies, virials and B (kernel order ->
 // file order through perm, which maps file index -> kernel index), over the

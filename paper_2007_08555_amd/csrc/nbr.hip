@@ -32,6 +32,7 @@ constexpr int kBlock = 256;
 constexpr int kBinnedMinAtoms = 2048;
 constexpr int kSmallMax = 256;    // configurations searched by one workgroup from LDS
 constexpr int kSmallBlock = 256;
+constexpr int kWriteGroup = 4;   // list entries written together by the small search
 
 __device__ inline bool is_small(const CfgInfo& c) { return !c.binned && c.n <= kSmallMax; }
 
@@ -588,7 +589,26 @@ struct ImageBox {
 __device__ inline bool box_may_hit(const CfgInfo& c, float4 ui, float4 uj) {
   const float w0 = (float)c.w[0] + 1e-3f, w1 = (float)c.w[1] + 1e-3f, w2 = (float)c.w[2] + 1e-3f;
   const float s0 = uj.x - ui.x, s1 = uj.y - ui.y, s2 = uj.z - ui.z;
-  return !(fabsf(s0 - rintf(s0)) > w0 || fabsf(s1 - rintf(s1)) > w1 || fabsf(s2 - rintf(s2)) > w2);
+  // bitwise, not short-circuit: all three components are tested without branches
+  return !((fabsf(s0 - rintf(s0)) > w0) | (fabsf(s1 - rintf(s1)) > w1) | (fabsf(s2 - rintf(s2)) > w2));
+}
+
+// f(j, rec[j]) for j = 0..n-1 in order, the LDS records loaded kSweep at a
+// time before any is used, so that their latencies overlap (one load in
+// flight per candidate leaves the loop waiting on LDS).  Indices past n are
+// clamped for the loads and skipped for f.
+constexpr int kSweep = 8;
+
+template <typename T, typename F>
+__device__ inline void lds_sweep(const T* rec, int n, F&& f) {
+  for (int j0 = 0; j0 < n; j0 += kSweep) {
+    T v[kSweep];
+#pragma unroll
+    for (int u = 0; u < kSweep; ++u) v[u] = rec[j0 + u < n ? j0 + u : n - 1];
+#pragma unroll
+    for (int u = 0; u < kSweep; ++u)
+      if (j0 + u < n) f(j0 + u, v[u]);
+  }
 }
 
 __device__ inline ImageBox image_box_of(const CfgInfo& c, const SmallAtoms& sa, int li, int lj) {
@@ -654,8 +674,9 @@ __device__ inline void small_candidates(const CfgInfo& c, const SmallAtoms& sa, 
   for (int wi = 0; wi < 4; ++wi) {
     uint64_t bits = 0;
     const int top = n - 64 * wi < 64 ? n - 64 * wi : 64;
-    for (int bi = 0; bi < top; ++bi)
-      if (box_may_hit(c, ui, sa.u[64 * wi + bi])) bits |= 1ull << bi;
+    lds_sweep(sa.u + 64 * wi, top, [&](int bi, float4 uj) {
+      if (box_may_hit(c, ui, uj)) bits |= 1ull << bi;
+    });
     if (wi == 0) m0 = bits; else if (wi == 1) m1 = bits; else if (wi == 2) m2 = bits; else m3 = bits;
   }
   const double* L = c.L;
@@ -716,15 +737,14 @@ __device__ inline int small_two_phase(const CfgInfo& c, const SmallAtoms& sa, in
   const double4 pi = sa.x[li];
   int nc = 0;
   if (!c.pbc) {
-    for (int lj = 0; lj < n; ++lj) {
-      const double4 pj = sa.x[lj];
+    lds_sweep(sa.x, n, [&](int lj, double4 pj) {
       const double dx = pj.x - pi.x, dy = pj.y - pi.y, dz = pj.z - pi.z;
       const double r2 = dx * dx + dy * dy + dz * dz;
-      if (lj != li && r2 < rc2) {
+      if ((lj != li) & (r2 < rc2)) {
         if (nc < K) row[nc] = (uint8_t)lj;
         ++nc;
       }
-    }
+    });
     const int m = nc < K ? nc : K;
     for (int q = 0; q < m; ++q) {
       const int lj = row[q];
@@ -741,19 +761,20 @@ __device__ inline int small_two_phase(const CfgInfo& c, const SmallAtoms& sa, in
   float Lf[9];
   for (int t = 0; t < 9; ++t) Lf[t] = (float)c.L[t];
   const float rcm = (float)sqrt(rc2) + 1e-3f, rcm2 = rcm * rcm;
-  for (int lj = 0; lj < n; ++lj) {
-    const float4 uj = sa.u[lj];
+  lds_sweep(sa.u, n, [&](int lj, float4 uj) {
     const float s0 = uj.x - ui.x, s1 = uj.y - ui.y, s2 = uj.z - ui.z;
     const float f0 = s0 - rintf(s0), f1 = s1 - rintf(s1), f2 = s2 - rintf(s2);
-    // the atom's own nearest image is itself (n = 0) and no other image is in range
-    if (lj == li || fabsf(f0) > w0 || fabsf(f1) > w1 || fabsf(f2) > w2) continue;
     const float x = f0 * Lf[0] + f1 * Lf[3] + f2 * Lf[6];
     const float y = f0 * Lf[1] + f1 * Lf[4] + f2 * Lf[7];
     const float z = f0 * Lf[2] + f1 * Lf[5] + f2 * Lf[8];
-    if (x * x + y * y + z * z > rcm2) continue;
-    if (nc < K) row[nc] = (uint8_t)lj;
-    ++nc;
-  }
+    // the atom's own nearest image is itself (n = 0) and no other image is in range
+    const bool skip = (lj == li) | (fabsf(f0) > w0) | (fabsf(f1) > w1) | (fabsf(f2) > w2) |
+                      (x * x + y * y + z * z > rcm2);
+    if (!skip) {
+      if (nc < K) row[nc] = (uint8_t)lj;
+      ++nc;
+    }
+  });
   const int m = nc < K ? nc : K;
   for (int q = 0; q < m; ++q) {
     const int lj = row[q];
@@ -922,40 +943,77 @@ __global__ void __launch_bounds__(kSmallBlock) search_small_kernel(NbrArgs a, in
   const int ci = scount[li];
   const bool records = !c.pbc || nearest;
   unsigned long long errs = 0;
-  for (int p = 0; p < ci; ++p) {
-    const int lj = mine[p];
-    int r = 0, k = 1;
-    const size_t e = (size_t)p * a.stride + i;
-    const int64_t j = c.start + lj;
-    if (records) {
-      double rx, ry, rz;
-      if (!c.pbc) {
-        const double4 pi = sx[li], pj = sx[lj];
-        rx = pj.x - pi.x; ry = pj.y - pi.y; rz = pj.z - pi.z;
+  // kWriteGroup entries at a time, their binary searches in lockstep so that
+  // the dependent LDS loads of different entries overlap
+  constexpr int G = kWriteGroup;
+  for (int p0 = 0; p0 < ci; p0 += G) {
+    int ljv[G], lo[G], hi[G], rr[G], kk[G];
+#pragma unroll
+    for (int u = 0; u < G; ++u) ljv[u] = mine[p0 + u < ci ? p0 + u : ci - 1];
+#pragma unroll
+    for (int u = 0; u < G; ++u) {
+      lo[u] = 0;
+      hi[u] = scount[ljv[u]];
+      rr[u] = 0;
+      kk[u] = 1;
+    }
+#pragma unroll
+    for (int u = 0; u < G; ++u) {
+      const int p = p0 + u;
+      if (p >= ci) continue;
+      const int lj = ljv[u];
+      const size_t e = (size_t)p * a.stride + i;
+      if (records) {
+        double rx, ry, rz;
+        if (!c.pbc) {
+          const double4 pi = sx[li], pj = sx[lj];
+          rx = pj.x - pi.x; ry = pj.y - pi.y; rz = pj.z - pi.z;
+        } else {
+          nearest_vector(c, sa, li, lj, rx, ry, rz);
+        }
+        store_pair(a, e, rx, ry, rz, smz[lj].w);
+        a.nbr[e] = (int32_t)(c.start + lj);
       } else {
-        nearest_vector(c, sa, li, lj, rx, ry, rz);
+        // rank of this image in the run of lj, and the run length
+        int r = 0, k = 1;
+        while (p - r - 1 >= 0 && mine[p - r - 1] == lj) ++r;
+        while (p - r + k < ci && mine[p - r + k] == lj) ++k;
+        rr[u] = r;
+        kk[u] = k;
       }
-      store_pair(a, e, rx, ry, rz, smz[lj].w);
-      a.nbr[e] = (int32_t)j;
-    } else {
-      // rank of this image in the run of lj, and the run length
-      while (p - r - 1 >= 0 && mine[p - r - 1] == lj) ++r;
-      while (p - r + k < ci && mine[p - r + k] == lj) ++k;
     }
-    // start of the run of li in lj's list (ascending local indices)
-    const uint8_t* other = lists + (size_t)lj * KL;
-    const int cj = scount[lj];
-    int lo = 0, hi = cj;
-    while (lo < hi) {
-      const int mid = (lo + hi) >> 1;
-      if ((int)other[mid] < li) lo = mid + 1; else hi = mid;
+    // start of the run of li in each lj's list (ascending local indices);
+    // mid <= count <= K stays inside the row of K + 4 bytes
+    while (true) {
+      bool more = false;
+#pragma unroll
+      for (int u = 0; u < G; ++u) more |= lo[u] < hi[u];
+      if (!more) break;
+      int v[G];
+#pragma unroll
+      for (int u = 0; u < G; ++u) v[u] = lists[(size_t)ljv[u] * KL + ((lo[u] + hi[u]) >> 1)];
+#pragma unroll
+      for (int u = 0; u < G; ++u)
+        if (lo[u] < hi[u]) {
+          const int mid = (lo[u] + hi[u]) >> 1;
+          if (v[u] < li) lo[u] = mid + 1; else hi[u] = mid;
+        }
     }
-    const int q = lo + k - 1 - r;
-    if (q < cj && other[q] == (uint8_t)li) {
-      a.rev[e] = (int32_t)((size_t)q * a.stride + j);
-    } else {
-      a.rev[e] = (int32_t)e;
-      ++errs;
+#pragma unroll
+    for (int u = 0; u < G; ++u) {
+      const int p = p0 + u;
+      if (p >= ci) continue;
+      const int lj = ljv[u];
+      const size_t e = (size_t)p * a.stride + i;
+      const int64_t j = c.start + lj;
+      const int cj = scount[lj];
+      const int q = lo[u] + kk[u] - 1 - rr[u];
+      if (q < cj && lists[(size_t)lj * KL + q] == (uint8_t)li) {
+        a.rev[e] = (int32_t)((size_t)q * a.stride + j);
+      } else {
+        a.rev[e] = (int32_t)e;
+        ++errs;
+      }
     }
   }
   if (errs) atomicAdd(&a.status->list_errors, errs);

@@ -14,29 +14,28 @@ namespace {
 
 constexpr int kBlock = 256;
 
-// Forces F_i = sum over slots p of (g_p - g_rev(p)), summed in FP64 in slot
-// order.  Pairs are taken eight at a time so that the eight dependent loads
-// g[rev[e]] are in flight together.  (The per-atom virials are summed by the
-// last adjoint pass.)
+// Forces F_i = sum over slots p of (g_p - g_rev(p)): the first sum was taken
+// in FP64 by the last adjoint pass (own, [3][stride]), so only the reverse
+// pairs' g is fetched here, subtracted in FP64 in slot order.  Pairs are
+// taken eight at a time so that the eight dependent loads g[rev[e]] are in
+// flight together.  (The per-atom virials are summed by the last adjoint
+// pass as well.)
 template <typename T>
 __global__ void __launch_bounds__(kBlock) gather_kernel(int64_t n_atoms, int stride,
                                                         const int32_t* __restrict__ count,
                                                         const int32_t* __restrict__ rev,
-                                                        const T* __restrict__ g, double* __restrict__ F) {
+                                                        const T* __restrict__ g, const double* __restrict__ own,
+                                                        double* __restrict__ F) {
   constexpr int U = 8;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n_atoms) return;
-  double fx = 0, fy = 0, fz = 0;
+  double fx = own[i], fy = own[stride + i], fz = own[2 * (size_t)stride + i];
   const int c = count[i];
   for (int p0 = 0; p0 < c; p0 += U) {
-    double gx[U], gy[U], gz[U], hx[U], hy[U], hz[U];
+    double hx[U], hy[U], hz[U];
     size_t q[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const size_t e = (size_t)(p0 + u < c ? p0 + u : p0) * stride + i;
-      q[u] = (size_t)rev[e];
-      gx[u] = (double)g[3 * e]; gy[u] = (double)g[3 * e + 1]; gz[u] = (double)g[3 * e + 2];
-    }
+    for (int u = 0; u < U; ++u) q[u] = (size_t)rev[(size_t)(p0 + u < c ? p0 + u : p0) * stride + i];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       hx[u] = (double)g[3 * q[u]]; hy[u] = (double)g[3 * q[u] + 1]; hz[u] = (double)g[3 * q[u] + 2];
@@ -46,9 +45,9 @@ __global__ void __launch_bounds__(kBlock) gather_kernel(int64_t n_atoms, int str
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const bool ok = p0 + u < c;
-      fx = ok ? fx + (gx[u] - hx[u]) : fx;
-      fy = ok ? fy + (gy[u] - hy[u]) : fy;
-      fz = ok ? fz + (gz[u] - hz[u]) : fz;
+      fx = ok ? fx - hx[u] : fx;
+      fy = ok ? fy - hy[u] : fy;
+      fz = ok ? fz - hz[u] : fz;
     }
   }
   F[3 * i] = fx;
@@ -164,15 +163,15 @@ __global__ void __launch_bounds__(kBlock) b_kernel(int n_cfg, const CfgInfo* __r
 }  // namespace
 
 hipError_t gather_forces(int fp64, int64_t n_atoms, int stride, const int32_t* count,
-                         const int32_t* rev, const void* gp, double* forces, hipStream_t s) {
+                         const int32_t* rev, const void* gp, const double* own, double* forces, hipStream_t s) {
   if (n_atoms == 0 || !forces) return hipSuccess;
   const dim3 g((unsigned)((n_atoms + kBlock - 1) / kBlock));
   if (fp64)
     hipLaunchKernelGGL(gather_kernel<double>, g, dim3(kBlock), 0, s, n_atoms, stride, count, rev,
-                       (const double*)gp, forces);
+                       (const double*)gp, own, forces);
   else
     hipLaunchKernelGGL(gather_kernel<float>, g, dim3(kBlock), 0, s, n_atoms, stride, count, rev,
-                       (const float*)gp, forces);
+                       (const float*)gp, own, forces);
   return hipGetLastError();
 }
 
