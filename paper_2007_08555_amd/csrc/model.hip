@@ -369,7 +369,7 @@ int run_eval(mtp_model* M, const mtp_batch* bt, const mtp_out* out, int precisio
   NEED(M->status, sizeof(Status));
   if (n_cfg == 0) return MTP_OK;
   NEED(M->cfg, sizeof(CfgInfo) * n_cfg);
-  NEED(M->cfg_order, sizeof(int32_t) * n_cfg);
+  NEED(M->cfg_order, sizeof(int32_t) * (n_cfg + 4));   // the order, then four class counts
   for (Buffer* b : {&M->atom_cfg, &M->atom_bin, &M->bin_count, &M->bin_start, &M->bin_fill, &M->bin_atoms,
                     &M->binned, &M->count})
     NEED(*b, sizeof(int32_t) * (N + 1));

@@ -41,7 +41,8 @@ struct NbrArgs {
   double rcut, rmin;
   int n_species;
   CfgInfo* cfg;          // [n_cfg]
-  int32_t* cfg_order;    // [n_cfg] launch order of the small-configuration search
+  int32_t* cfg_order;    // [n_cfg + 4] launch order of the small-configuration search, then the
+                         // numbers of small configurations of 1, 2, 3 and 4 wavefronts
   int32_t* atom_cfg;     // [n_atoms]
   int32_t* atom_bin;     // [n_atoms] global bin index (binned configs only)
   int32_t* bin_count;    // [n_atoms + 1]  bins of a binned config sit at its atom offset

@@ -106,8 +106,10 @@ __global__ void cfg_prepare_kernel(NbrArgs a) {
 
 // Launch order of the small-configuration search: largest configurations
 // first (a counting sort by atom count; the order among equal counts does
-// not matter, each configuration is searched by one workgroup), so that the
-// longest workgroups do not start last.
+// not matter), so that the longest workgroups do not start last.  After the
+// n_cfg positions, the numbers of small configurations that take 1, 2, 3
+// and 4 wavefronts (1-64, 65-128, 129-192 and 193-256 atoms), from which
+// every workgroup finds its bundle (bundle_slot).
 __global__ void __launch_bounds__(1024) cfg_order_kernel(NbrArgs a) {
   constexpr int kBins = kSmallMax + 2;   // counts 0..kSmallMax, then larger ones
   __shared__ int hist[kBins], base[kBins];
@@ -125,6 +127,9 @@ __global__ void __launch_bounds__(1024) cfg_order_kernel(NbrArgs a) {
       base[b] = acc;
       acc += hist[b];
     }
+    int cls[4] = {0, 0, 0, 0};
+    for (int n = 1; n <= kSmallMax; ++n) cls[(n - 1) >> 6] += hist[kSmallMax - n];
+    for (int w = 0; w < 4; ++w) a.cfg_order[a.n_cfg + w] = cls[w];
   }
   __syncthreads();
   for (int k = threadIdx.x; k < a.n_cfg; k += blockDim.x) a.cfg_order[atomicAdd(&base[bin_of_cfg(k)], 1)] = k;
@@ -845,6 +850,68 @@ struct SmallEmit {
   }
 };
 
+// A workgroup of the small search takes a bundle of configurations, each on
+// whole wavefronts of its own (ceil(n / 64) of them, atom li on lane li % 64
+// of its (li / 64)-th wavefront), so that few of the workgroup's four
+// wavefronts idle and more of them share the CU.  Bundles, from the class
+// counts after cfg_order (configurations in descending size, so the classes
+// are contiguous there): each 4-wavefront configuration alone; each
+// 3-wavefront one with a 1-wavefront one while they last; 2-wavefront ones in
+// pairs, an odd one left over with up to two 1-wavefront ones; the remaining
+// 1-wavefront ones in fours.  Workgroups past the last bundle find none.
+struct SmallSlot {
+  int pos;     // position of the wavefront's configuration in cfg_order, -1: idle
+  int wave0;   // the configuration's first wavefront in the workgroup
+};
+
+__device__ inline SmallSlot bundle_slot(const NbrArgs& a, int b, int wave) {
+  const int* cls = a.cfg_order + a.n_cfg;
+  const int c1 = cls[0], c2 = cls[1], c3 = cls[2], c4 = cls[3];
+  const int s3 = c4, s2 = c4 + c3, s1 = c4 + c3 + c2;   // first positions of the classes
+  const int u1a = c3 < c1 ? c3 : c1;                     // 1-wavefront ones beside 3-wavefront ones
+  const int p2 = c2 >> 1, odd2 = c2 & 1;
+  const int u1b = odd2 ? (c1 - u1a < 2 ? c1 - u1a : 2) : 0;   // beside the odd 2-wavefront one
+  int pos[4] = {-1, -1, -1, -1}, nw[4] = {0, 0, 0, 0};
+  if (b < c4) {
+    pos[0] = b;
+    nw[0] = 4;
+  } else if (b - c4 < c3) {
+    const int q = b - c4;
+    pos[0] = s3 + q;
+    nw[0] = 3;
+    if (q < u1a) {
+      pos[1] = s1 + q;
+      nw[1] = 1;
+    }
+  } else if (b - c4 - c3 < p2) {
+    const int q = b - c4 - c3;
+    pos[0] = s2 + 2 * q;
+    pos[1] = s2 + 2 * q + 1;
+    nw[0] = nw[1] = 2;
+  } else if (b - c4 - c3 - p2 < odd2) {
+    pos[0] = s2 + c2 - 1;
+    nw[0] = 2;
+    for (int t = 0; t < u1b; ++t) {
+      pos[1 + t] = s1 + u1a + t;
+      nw[1 + t] = 1;
+    }
+  } else {
+    const int q = u1a + u1b + 4 * (b - c4 - c3 - p2 - odd2);
+    for (int t = 0; t < 4; ++t)
+      if (q + t < c1) {
+        pos[t] = s1 + q + t;
+        nw[t] = 1;
+      }
+  }
+  int w0 = 0;
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    if (pos[m] >= 0 && wave >= w0 && wave < w0 + nw[m]) return SmallSlot{pos[m], w0};
+    w0 += nw[m];
+  }
+  return SmallSlot{-1, 0};
+}
+
 __global__ void __launch_bounds__(kSmallBlock) search_small_kernel(NbrArgs a, int lds_lists) {
   __shared__ double4 sx[kSmallMax];
   __shared__ float4 su[kSmallMax];
@@ -852,17 +919,27 @@ __global__ void __launch_bounds__(kSmallBlock) search_small_kernel(NbrArgs a, in
   __shared__ int32_t scount[kSmallMax];
   __shared__ unsigned long long red[5];
   extern __shared__ uint8_t lists[];   // [kSmallMax][K + 4] when lds_lists
-  const CfgInfo c = a.cfg[a.cfg_order[blockIdx.x]];
-  if (!is_small(c)) return;
   const int t = threadIdx.x;
-  const int n = c.n;
-  const int KL = a.K + 4;   // row pitch in bytes: rows of consecutive atoms fall in different banks
   if (t < 5) red[t] = 0;
+  // this wavefront's configuration in the workgroup's bundle (none: an idle wavefront)
+  const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
+  const SmallSlot slot = bundle_slot(a, blockIdx.x, wave);
+  CfgInfo c{};
+  if (slot.pos >= 0) c = a.cfg[a.cfg_order[slot.pos]];
+  const int n = c.n;
+  const int base = 64 * slot.wave0;   // LDS index of the configuration's first atom
+  const int li = slot.pos >= 0 ? 64 * (wave - slot.wave0) + (t & 63) : kSmallMax;
+  double4* const sxc = sx + base;
+  float4* const suc = su + base;
+  int4* const smzc = smz + base;
+  int32_t* const scc = scount + base;
+  const int KL = a.K + 4;   // row pitch in bytes: rows of consecutive atoms fall in different banks
+  uint8_t* const lc = lists + (size_t)base * KL;
   int bad = 0;
-  for (int q = t; q < n; q += blockDim.x) {
-    const size_t g = (size_t)(c.start + q);
+  if (li < n) {
+    const size_t g = (size_t)(c.start + li);
     const double x = a.pos[3 * g], y = a.pos[3 * g + 1], z = a.pos[3 * g + 2];
-    sx[q] = make_double4(x, y, z, 0.0);
+    sxc[li] = make_double4(x, y, z, 0.0);
     const int zs = a.species[g];
     if (zs < 0 || zs >= a.n_species) bad = 1;
     int m[3] = {0, 0, 0};
@@ -874,22 +951,21 @@ __global__ void __launch_bounds__(kSmallBlock) search_small_kernel(NbrArgs a, in
         u[d] = (float)(f - fl);
         m[d] = (int32_t)fl;
       }
-    su[q] = make_float4(u[0], u[1], u[2], 0.f);
-    smz[q] = make_int4(m[0], m[1], m[2], zs < 0 ? 0 : (zs >= a.n_species ? a.n_species - 1 : zs));
+    suc[li] = make_float4(u[0], u[1], u[2], 0.f);
+    smzc[li] = make_int4(m[0], m[1], m[2], zs < 0 ? 0 : (zs >= a.n_species ? a.n_species - 1 : zs));
   }
   __syncthreads();
-  const SmallAtoms sa{sx, su, smz};
+  const SmallAtoms sa{sxc, suc, smzc};
   const double rc2 = a.rcut * a.rcut;
   const double rmin2 = a.rmin * a.rmin;
   const bool nearest = nearest_cell(c);
   // global run starts (direct lists): rows of n int16 at the config's atom offset
   int16_t* run_start = a.run_start + (size_t)c.start * kSmallMax;
-  const int li = t;
   int count = 0, below = 0;
   if (li < n) {
     const int64_t i = c.start + li;
     if (lds_lists) {
-      uint8_t* row = lists + (size_t)li * KL;
+      uint8_t* row = lc + (size_t)li * KL;
       LdsCollect col{row, a.K, rmin2};
       if (!c.pbc || nearest) {
         const int nc = small_two_phase(c, sa, n, li, rc2, a.K, row, col);
@@ -899,19 +975,19 @@ __global__ void __launch_bounds__(kSmallBlock) search_small_kernel(NbrArgs a, in
         count = col.count;
         below = col.below;
       } else {
-        LdsAndRecords em{a, i, c.start, smz, row, rmin2};
+        LdsAndRecords em{a, i, c.start, smzc, row, rmin2};
         small_candidates(c, sa, n, li, rc2, em);
         count = em.count;
         below = em.below;
       }
     } else {
-      SmallEmit em{a, i, c.start, smz, run_start + (size_t)li * n, rmin2};
+      SmallEmit em{a, i, c.start, smzc, run_start + (size_t)li * n, rmin2};
       small_candidates(c, sa, n, li, rc2, em);
       count = em.count;
       below = em.below;
     }
     a.count[i] = count < a.K ? count : a.K;
-    scount[li] = count < a.K ? count : a.K;
+    scc[li] = count < a.K ? count : a.K;
   }
   // counts summed over the wavefront first: one LDS atomic per wavefront
   const int wmax = wave_max(count), wsum = wave_sum(count), wover = wave_sum(count > a.K ? 1 : 0);
@@ -923,7 +999,7 @@ __global__ void __launch_bounds__(kSmallBlock) search_small_kernel(NbrArgs a, in
     if (wbelow) atomicAdd(&red[3], (unsigned long long)wbelow);
     if (wbad) atomicAdd(&red[4], (unsigned long long)wbad);
   }
-  __syncthreads();  // LDS lists and counts of the whole configuration are complete
+  __syncthreads();  // LDS lists and counts of every configuration of the bundle are complete
   if (t == 0) {
     atomicMax(&a.status->max_count, red[0]);
     atomicAdd(&a.status->n_pairs, red[1]);
@@ -939,8 +1015,8 @@ __global__ void __launch_bounds__(kSmallBlock) search_small_kernel(NbrArgs a, in
   // search).
   if (!lds_lists || li >= n) return;
   const int64_t i = c.start + li;
-  const uint8_t* mine = lists + (size_t)li * KL;
-  const int ci = scount[li];
+  const uint8_t* mine = lc + (size_t)li * KL;
+  const int ci = scc[li];
   const bool records = !c.pbc || nearest;
   unsigned long long errs = 0;
   // kWriteGroup entries at a time, their binary searches in lockstep so that
@@ -953,7 +1029,7 @@ __global__ void __launch_bounds__(kSmallBlock) search_small_kernel(NbrArgs a, in
 #pragma unroll
     for (int u = 0; u < G; ++u) {
       lo[u] = 0;
-      hi[u] = scount[ljv[u]];
+      hi[u] = scc[ljv[u]];
       rr[u] = 0;
       kk[u] = 1;
     }
@@ -966,12 +1042,12 @@ __global__ void __launch_bounds__(kSmallBlock) search_small_kernel(NbrArgs a, in
       if (records) {
         double rx, ry, rz;
         if (!c.pbc) {
-          const double4 pi = sx[li], pj = sx[lj];
+          const double4 pi = sxc[li], pj = sxc[lj];
           rx = pj.x - pi.x; ry = pj.y - pi.y; rz = pj.z - pi.z;
         } else {
           nearest_vector(c, sa, li, lj, rx, ry, rz);
         }
-        store_pair(a, e, rx, ry, rz, smz[lj].w);
+        store_pair(a, e, rx, ry, rz, smzc[lj].w);
         a.nbr[e] = (int32_t)(c.start + lj);
       } else {
         // rank of this image in the run of lj, and the run length
@@ -991,7 +1067,7 @@ __global__ void __launch_bounds__(kSmallBlock) search_small_kernel(NbrArgs a, in
       if (!more) break;
       int v[G];
 #pragma unroll
-      for (int u = 0; u < G; ++u) v[u] = lists[(size_t)ljv[u] * KL + ((lo[u] + hi[u]) >> 1)];
+      for (int u = 0; u < G; ++u) v[u] = lc[(size_t)ljv[u] * KL + ((lo[u] + hi[u]) >> 1)];
 #pragma unroll
       for (int u = 0; u < G; ++u)
         if (lo[u] < hi[u]) {
@@ -1006,9 +1082,9 @@ __global__ void __launch_bounds__(kSmallBlock) search_small_kernel(NbrArgs a, in
       const int lj = ljv[u];
       const size_t e = (size_t)p * a.stride + i;
       const int64_t j = c.start + lj;
-      const int cj = scount[lj];
+      const int cj = scc[lj];
       const int q = lo[u] + kk[u] - 1 - rr[u];
-      if (q < cj && lists[(size_t)lj * KL + q] == (uint8_t)li) {
+      if (q < cj && lc[(size_t)lj * KL + q] == (uint8_t)li) {
         a.rev[e] = (int32_t)((size_t)q * a.stride + j);
       } else {
         a.rev[e] = (int32_t)e;
