@@ -98,7 +98,7 @@ struct mtp_model {
   bool has_active = false;
   Buffer ainv, gj_work, gj_flag;
   // workspace
-  Buffer cfg, cfg_order, atom_cfg, atom_bin, bin_count, bin_start, bin_atoms, bin_fill, binned, nbins_dev;
+  Buffer cfg, cfg_order, atom_cfg, atom_bin, bin_count, bin_start, bin_atoms, bin_fill, binned, large, nbins_dev;
   Buffer count, nbr, pr, rev, gpair, own, Mbuf, Gbuf, Dbuf, site, wv, B, status, run_start;
   int K = 64;  // neighbour capacity per atom, grown on overflow
   int schedule64 = 0;  // FP64 pass split of the evaluation kernels (mtp_autotune)
@@ -371,7 +371,7 @@ int run_eval(mtp_model* M, const mtp_batch* bt, const mtp_out* out, int precisio
   NEED(M->cfg, sizeof(CfgInfo) * n_cfg);
   NEED(M->cfg_order, sizeof(int32_t) * (n_cfg + 4));   // the order, then four class counts
   for (Buffer* b : {&M->atom_cfg, &M->atom_bin, &M->bin_count, &M->bin_start, &M->bin_fill, &M->bin_atoms,
-                    &M->binned, &M->count})
+                    &M->binned, &M->large, &M->count})
     NEED(*b, sizeof(int32_t) * (N + 1));
   const int stride = (int)((N + 63) / 64 * 64);
   const bool want_b = out->b != nullptr;
@@ -437,6 +437,7 @@ int run_eval(mtp_model* M, const mtp_batch* bt, const mtp_out* out, int precisio
     a.bin_start = M->bin_start.as<int32_t>();
     a.bin_fill = M->bin_fill.as<int32_t>();
     a.binned = M->binned.as<int32_t>();
+    a.large = M->large.as<int32_t>();
     a.bin_atoms = M->bin_atoms.as<int32_t>();
     a.count = M->count.as<int32_t>();
     a.stride = stride;

@@ -28,6 +28,7 @@ struct Status {
   unsigned long long n_pairs;     // total neighbour pairs of the last search
   unsigned long long overflow;    // atoms with more neighbours than the ELL capacity
   unsigned long long n_binned;    // atoms of binned configurations (entries of NbrArgs::binned)
+  unsigned long long n_large;     // atoms of configurations above the small-search size (NbrArgs::large)
 };
 
 struct NbrArgs {
@@ -50,6 +51,7 @@ struct NbrArgs {
   int32_t* bin_atoms;    // [n_atoms] atoms sorted by bin, then index
   int32_t* bin_fill;     // [n_atoms + 1] scratch cursor
   int32_t* binned;       // [n_atoms] atoms of binned configurations, in no particular order
+  int32_t* large;        // [n_atoms] atoms of configurations that are not small, in no particular order
   int32_t* count;        // [n_atoms] neighbours per atom (clamped to K)
   int stride;            // ELL pitch (>= n_atoms)
   int K;                 // ELL slots per atom

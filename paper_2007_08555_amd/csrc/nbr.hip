@@ -190,10 +190,24 @@ __device__ inline void image_box(const CfgInfo& c, double dx, double dy, double 
   }
 }
 
+// Bins of the binned configurations; also lists the atoms of every
+// configuration that is not small (the reverse pass needs only those when the
+// small search kept its lists in LDS), one atomic per wavefront.
 __global__ void bin_count_kernel(NbrArgs a) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  const CfgInfo* cp = i < a.n_atoms ? &a.cfg[a.atom_cfg[i]] : nullptr;
+  const bool big = cp && in_cfg(*cp, i) && !is_small(*cp);
+  const unsigned long long m = __ballot(big);
+  if (m) {
+    const int leader = __ffsll((long long)m) - 1;
+    unsigned long long first = 0;
+    if (lane == leader) first = atomicAdd(&a.status->n_large, (unsigned long long)__popcll(m));
+    first = __shfl(first, leader, 64);
+    if (big) a.large[first + __popcll(m & ((1ull << lane) - 1ull))] = (int32_t)i;
+  }
   if (i >= a.n_atoms) return;
-  const CfgInfo& c = a.cfg[a.atom_cfg[i]];
+  const CfgInfo& c = *cp;
   if (!c.binned || !in_cfg(c, i)) {
     a.atom_bin[i] = -1;
     return;
@@ -501,10 +515,8 @@ __global__ void __launch_bounds__(kBinnedBlock) search_binned_kernel(NbrArgs a) 
 // for the rule.  The run of j around slot p gives r (entries of j before p)
 // and k; the start of i's run in j's list comes from the run-start table of
 // the small search, else from a search of j's list.
-__global__ void reverse_kernel(NbrArgs a, int small_done) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int p = blockIdx.y;
-  if (i >= a.n_atoms || p >= a.count[i]) return;
+__device__ inline void reverse_entry(const NbrArgs& a, int64_t i, int p, int small_done) {
+  if (p >= a.count[i]) return;
   const CfgInfo& c = a.cfg[a.atom_cfg[i]];
   if (!in_cfg(c, i) || (small_done && is_small(c))) return;
   const size_t st = (size_t)a.stride;
@@ -542,6 +554,24 @@ __global__ void reverse_kernel(NbrArgs a, int small_done) {
     a.rev[e] = (int32_t)e;
     atomicAdd(&a.status->list_errors, 1ull);
   }
+}
+
+// Every atom, slot p = blockIdx.y (direct lists: small configurations too).
+__global__ void reverse_kernel(NbrArgs a, int small_done) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < a.n_atoms) reverse_entry(a, i, blockIdx.y, small_done);
+}
+
+// Only the atoms listed in a.large (the small search wrote its own reverse
+// indices): entry k = blockIdx.x * blockDim.x + threadIdx.x of the list, slot
+// p = blockIdx.y.  The grid covers every atom; workgroups past the list's
+// length (all of them when every configuration is small) leave after one
+// scalar load.
+__global__ void reverse_large_kernel(NbrArgs a) {
+  const int64_t n = (int64_t)a.status->n_large;
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if ((int64_t)blockIdx.x * blockDim.x >= n || k >= n) return;
+  reverse_entry(a, a.large[k], blockIdx.y, 1);
 }
 
 // Whole search of one small configuration in one workgroup.  Positions,
@@ -1233,7 +1263,10 @@ hipError_t nbr_build(NbrArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(search_kernel, grid_for(a.n_atoms), dim3(kBlock), 0, s, a);
   hipLaunchKernelGGL(search_binned_kernel, dim3(kBinnedBlocks), dim3(kBinnedBlock), 0, s, a);
   const dim3 g((unsigned)((a.n_atoms + kBlock - 1) / kBlock), (unsigned)a.K);
-  hipLaunchKernelGGL(reverse_kernel, g, dim3(kBlock), 0, s, a, lds_lists);
+  if (lds_lists)
+    hipLaunchKernelGGL(reverse_large_kernel, g, dim3(kBlock), 0, s, a);
+  else
+    hipLaunchKernelGGL(reverse_kernel, g, dim3(kBlock), 0, s, a, lds_lists);
   return hipGetLastError();
 }
 
