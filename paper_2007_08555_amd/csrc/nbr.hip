@@ -113,7 +113,8 @@ __global__ void cfg_prepare_kernel(NbrArgs a) {
 __global__ void __launch_bounds__(1024) cfg_order_kernel(NbrArgs a) {
   constexpr int kBins = kSmallMax + 2;   // counts 0..kSmallMax, then larger ones
   __shared__ int hist[kBins], base[kBins];
-  for (int b = threadIdx.x; b < kBins; b += blockDim.x) hist[b] = 0;
+  const int t = threadIdx.x;   // blockDim.x >= kBins
+  if (t < kBins) hist[t] = 0;
   __syncthreads();
   auto bin_of_cfg = [&](int k) {
     const int n = a.cfg[k].n;
@@ -121,16 +122,23 @@ __global__ void __launch_bounds__(1024) cfg_order_kernel(NbrArgs a) {
   };
   for (int k = threadIdx.x; k < a.n_cfg; k += blockDim.x) atomicAdd(&hist[bin_of_cfg(k)], 1);
   __syncthreads();
-  if (threadIdx.x == 0) {
-    int acc = 0;
-    for (int b = 0; b < kBins; ++b) {
-      base[b] = acc;
-      acc += hist[b];
-    }
-    int cls[4] = {0, 0, 0, 0};
-    for (int n = 1; n <= kSmallMax; ++n) cls[(n - 1) >> 6] += hist[kSmallMax - n];
-    for (int w = 0; w < 4; ++w) a.cfg_order[a.n_cfg + w] = cls[w];
+  // inclusive scan of the bins (in base), then exclusive starts
+  if (t < kBins) base[t] = hist[t];
+  __syncthreads();
+  for (int off = 1; off < kBins; off <<= 1) {
+    const int v = t < kBins && t >= off ? base[t - off] : 0;
+    __syncthreads();
+    if (t < kBins) base[t] += v;
+    __syncthreads();
   }
+  // configurations of w + 1 wavefronts: n in [64 w + 1, 64 w + 64], bins
+  // kSmallMax - n in [192 - 64 w, 255 - 64 w]
+  if (t < 4) {
+    const int hi = 255 - 64 * t, lo = 191 - 64 * t;
+    a.cfg_order[a.n_cfg + t] = base[hi] - (lo >= 0 ? base[lo] : 0);
+  }
+  __syncthreads();
+  if (t < kBins) base[t] -= hist[t];
   __syncthreads();
   for (int k = threadIdx.x; k < a.n_cfg; k += blockDim.x) a.cfg_order[atomicAdd(&base[bin_of_cfg(k)], 1)] = k;
 }
@@ -563,15 +571,16 @@ __global__ void reverse_kernel(NbrArgs a, int small_done) {
 }
 
 // Only the atoms listed in a.large (the small search wrote its own reverse
-// indices): entry k = blockIdx.x * blockDim.x + threadIdx.x of the list, slot
-// p = blockIdx.y.  The grid covers every atom; workgroups past the list's
-// length (all of them when every configuration is small) leave after one
-// scalar load.
+// indices): entries k = blockIdx.x * blockDim.x + threadIdx.x + multiples of
+// the grid's width of the list, slot p = blockIdx.y.  The grid is as wide as
+// the atoms up to kReverseBlocks workgroups; workgroups past the list's length
+// (all of them when every configuration is small) leave after one scalar load.
+constexpr int kReverseBlocks = 256;
+
 __global__ void reverse_large_kernel(NbrArgs a) {
   const int64_t n = (int64_t)a.status->n_large;
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if ((int64_t)blockIdx.x * blockDim.x >= n || k >= n) return;
-  reverse_entry(a, a.large[k], blockIdx.y, 1);
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x)
+    reverse_entry(a, a.large[k], blockIdx.y, 1);
 }
 
 // Whole search of one small configuration in one workgroup.  Positions,
@@ -1264,7 +1273,8 @@ hipError_t nbr_build(NbrArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(search_binned_kernel, dim3(kBinnedBlocks), dim3(kBinnedBlock), 0, s, a);
   const dim3 g((unsigned)((a.n_atoms + kBlock - 1) / kBlock), (unsigned)a.K);
   if (lds_lists)
-    hipLaunchKernelGGL(reverse_large_kernel, g, dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL(reverse_large_kernel, dim3(g.x < kReverseBlocks ? g.x : kReverseBlocks, g.y), dim3(kBlock), 0,
+                       s, a);
   else
     hipLaunchKernelGGL(reverse_kernel, g, dim3(kBlock), 0, s, a, lds_lists);
   return hipGetLastError();
