@@ -168,3 +168,41 @@ def test_every_search_path_in_one_batch(potentials):
     b = _every_search_path()
     assert b["n_atoms"].max() > 2048 and (b["n_atoms"] > 256).sum() >= 4
     _check("lev12_s2", b, "fp64", potentials, TOL64, "search paths")
+
+
+def _bundle_boundaries():
+    """Clusters and periodic cells of every size at the small search's
+    wavefront boundaries (1..4 wavefronts of 64 atoms), empty configurations
+    among them, in a seeded shuffled order."""
+    sizes = [1, 2, 63, 64, 65, 127, 128, 129, 191, 192, 193, 255, 256]
+    cfgs = []
+    for t, n in enumerate(sizes):
+        kinds = {}
+        for seed in range(100 + 10 * t, 110 + 10 * t):
+            cand = synth.mixed_batch(seed=seed, n_configs=4, n_min=n, n_max=n, n_species_model=2)
+            for k in range(4):
+                kinds.setdefault(int(cand["pbc"][k]), synth.config_of(cand, k))
+            if len(kinds) == 2:
+                break
+        assert len(kinds) == 2, n
+        cfgs += [kinds[0], kinds[1]]
+    empty = (np.zeros((0, 3)), np.zeros(0, np.int32), np.zeros((3, 3)), 0)
+    cfgs += [empty, empty, empty]
+    order = np.random.default_rng(7).permutation(len(cfgs))
+    return synth._batch([cfgs[k] for k in order])
+
+
+def test_search_bundles_at_wavefront_boundaries(potentials):
+    """The small search packs configurations into workgroups by wavefront
+    count; every size class and class boundary against the oracle, and the
+    batched results equal to each configuration evaluated on its own."""
+    b = _bundle_boundaries()
+    g, _ = _check("lev12_s2", b, "fp64", potentials, TOL64, "bundles")
+    P, _ = potentials("lev12_s2")
+    off = b["atom_offsets"]
+    for k in np.random.default_rng(8).choice(len(b["n_atoms"]), size=8, replace=False):
+        one = synth._batch([synth.config_of(b, int(k))])
+        s = gpu_batch(P, one, "fp64")
+        assert s["energy"][0] == g["energy"][k]
+        np.testing.assert_array_equal(s["forces"], g["forces"][off[k]:off[k + 1]])
+        np.testing.assert_array_equal(s["b"][0], g["b"][k])
