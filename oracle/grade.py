@@ -66,3 +66,33 @@ def maxvol(B_pool, delta=1e-3, max_swaps=None, start=None):
         rows[j] = int(i)
         swaps += 1
     return np.array(rows, dtype=np.int64), swaps
+
+
+def theta_rows(pot, batch, indices=None, h=1e-30):
+    """Rows of the nonlinear grade: dE_k/dtheta for every configuration k of
+    the batch, theta = [xi, c.ravel()] (section 2.3: the matrix B built from
+    the derivatives of the energy in all parameters, linearised at the current
+    theta; its xi part is b).  Columns are the flat theta indices requested
+    (all when None).  Each column is one complex-step evaluation (Squire and
+    Trapp, 1998): dE_k/dtheta_p = Im E_k(theta + i h e_p) / h, exact to
+    rounding since E is real-analytic in theta."""
+    from . import mtp
+    import synth
+    m = len(pot["xi"])
+    nc = pot["c"].size
+    idx = list(range(m + nc)) if indices is None else list(indices)
+    K = len(batch["n_atoms"])
+    R = np.zeros((K, len(idx)))
+    for t, p in enumerate(idx):
+        q = dict(pot)
+        xi = pot["xi"].astype(np.complex128)
+        c = pot["c"].astype(np.complex128).ravel()
+        if p < m:
+            xi[p] += 1j * h
+        else:
+            c[p - m] += 1j * h
+        q["xi"] = xi
+        q["c"] = c.reshape(pot["c"].shape)
+        for k in range(K):
+            R[k, t] = np.imag(mtp.evaluate(q, *synth.config_of(batch, k))["energy"]) / h
+    return R

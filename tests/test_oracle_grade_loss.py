@@ -164,3 +164,30 @@ def test_error_report_definitions():
     assert np.isclose(rep["force"]["max"], 3.0)
     # stress: only the periodic config, |sigma|^2 / 9 = 3 / 9
     assert np.isclose(rep["stress"]["rmse"], np.sqrt(3 / 9))
+
+
+def test_theta_rows_xi_part_is_b_and_c_part_matches_finite_differences():
+    """Rows dE_k/dtheta of the nonlinear grade: E is linear in xi, so the xi
+    columns are b exactly; the c columns against central differences of E."""
+    pot = make_pot(level=8, S=2)
+    b = synth.mixed_batch(seed=11, n_configs=3, n_min=6, n_max=14, n_species_model=2)
+    m, nc = len(pot["xi"]), pot["c"].size
+    idx = list(range(m)) + [m, m + 3, m + nc // 2, m + nc - 1]
+    R = og.theta_rows(pot, b, indices=idx)
+    for k in range(3):
+        ref = mtp.evaluate(pot, *synth.config_of(b, k))
+        np.testing.assert_allclose(R[k, :m], ref["b"], rtol=1e-12, atol=1e-12 * np.abs(ref["b"]).max())
+        # Euler: E is homogeneous of degree 1 in xi
+        assert abs(R[k, :m] @ pot["xi"] - ref["energy"]) <= 1e-12 * max(1.0, abs(ref["energy"]))
+    theta = np.concatenate([pot["xi"], pot["c"].ravel()])
+    for t, p in enumerate(idx[m:], start=m):
+        h = 1e-6 * max(1.0, abs(theta[p]))
+        E = []
+        for sgn in (1, -1):
+            th = theta.copy()
+            th[p] += sgn * h
+            q = dict(pot, xi=th[:m], c=th[m:].reshape(pot["c"].shape))
+            E.append(np.array([mtp.evaluate(q, *synth.config_of(b, k))["energy"] for k in range(3)]))
+        fd = (E[0] - E[1]) / (2 * h)
+        np.testing.assert_allclose(R[:, t], fd, rtol=1e-6, atol=1e-7 * max(1.0, np.abs(fd).max()))
+        assert np.abs(R[:, t]).max() > 0   # the sampled c entries are used by these species pairs
