@@ -156,6 +156,42 @@ int mtp_grade(mtp_model* model, const mtp_batch* batch, double* gamma_dev, int32
               int precision, void* stream);
 
 /*
+ * Rows of the nonlinear grade of section 2.3: the matrix B generalised from
+ * b = dE/dxi to the derivatives of each configuration's energy in all
+ * parameters theta = (xi, c), at the current theta.  rows_dev (device,
+ * [n_configs][m + n_c] FP64, caller-owned): columns 0..m-1 are b_k (file
+ * basis order), columns m.. are dE_k/dc in the layout of c,
+ * [n_mu][S][S][N_Q].  Runs the evaluation and the loss-gradient kernels with
+ * unit energy weights and no force or stress terms.  precision FP64 or FP32
+ * (FP32 kernels, FP64 sums).  MTP_E_ARG for an empty batch; errors of
+ * mtp_eval otherwise.  Synchronises `stream` (as mtp_eval does).
+ */
+int mtp_theta_rows(mtp_model* model, const mtp_batch* batch, int precision, double* rows_dev, void* stream);
+
+/*
+ * Active set of the nonlinear grade: A (device, [n_cols][n_cols] FP64, row j =
+ * the theta row of active configuration j restricted to n_cols columns that
+ * the caller chose, 1 <= n_cols <= m + n_c).  The full rows are never of full
+ * rank: scaling c_mu by lambda and every xi_alpha by lambda^-k (k the number
+ * of moments of radial function mu in basis function alpha) leaves E
+ * unchanged, one linear relation among the columns per mu, so some c columns
+ * must be left out.  Inverted and kept like the linear active set
+ * (mtp_set_active_set), independently of it.  MTP_E_ARG for n_cols out of
+ * range or a numerically singular A.  Synchronises `stream`.
+ */
+int mtp_set_active_set_theta(mtp_model* model, int32_t n_cols, const double* A_dev, void* stream);
+
+/*
+ * Nonlinear grade of section 2.3 for theta rows restricted to the active
+ * set's columns (device, [n][n_cols] FP64): c = row A^{-1}, gamma =
+ * max_j |c_j|, argmax as in mtp_grade_from_b.  gamma_dev [n] FP64,
+ * argmax_dev [n] int32.  MTP_E_STATE without an active set
+ * (mtp_set_active_set_theta).
+ */
+int mtp_grade_theta(mtp_model* model, int32_t n, const double* rows_dev, double* gamma_dev,
+                    int32_t* argmax_dev, void* stream);
+
+/*
  * Training loss of section 2.2 (eq. Fitting; weighting `scaling` = molecules,
  * structures (eq. train-structures) or vibrations (eq. train-vibrations)) and
  * its gradient with respect to theta = {xi, c}.  Targets (device, FP64):

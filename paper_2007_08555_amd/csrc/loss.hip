@@ -10,6 +10,9 @@
 // the stress term through the one along the strain eps.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
+#include "mtp_device.h"
 #include "mtp_internal.h"
 
 namespace mtp {
@@ -101,6 +104,71 @@ __global__ void grad_c_kernel(int n_blocks, int n_c, const double* cpart, double
   grad[t] = v;
 }
 
+// Rows of the nonlinear grade (section 2.3): dE_k/dtheta of every
+// configuration.  With a_i = 1, u = 0 and eps = 0 the loss kernels differentiate
+// S = sum_k E_k and leave, per pair, the coefficients pa_mu and pb_mu of
+// Q_beta and dQ_beta/dr in dV_i/dc; summed per configuration (not per
+// workgroup) they give dE_k/dc.  The xi part of the row is b_k.
+template <typename T>
+__global__ void unit_weights_kernel(int64_t N, int64_t n_eps, T* a_atom, T* u, T* eps_atom) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < N) a_atom[t] = T(1);
+  if (t < 3 * N) u[t] = T(0);
+  if (t < n_eps) eps_atom[t] = T(0);
+}
+
+// One workgroup per configuration; threads over its atoms and their pairs,
+// the c entries summed in LDS.
+template <typename T>
+__global__ void __launch_bounds__(kBlock) c_rows_kernel(const ThetaRowArgs a, const PairRec<T>* __restrict__ pr,
+                                                        const T* __restrict__ pa, const T* __restrict__ pb) {
+  extern __shared__ double acc[];   // [n_c]
+  const int k = blockIdx.x;
+  for (int t = threadIdx.x; t < a.n_c; t += blockDim.x) acc[t] = 0.0;
+  __syncthreads();
+  const int64_t a0 = a.cfg[k].start, a1 = a0 + a.cfg[k].n;
+  const size_t n_slots = (size_t)a.K * a.stride;
+  const double span_inv = 1.0 / (a.rcut - a.rmin), dxdr = 2.0 * span_inv;
+  const int S = a.n_species, nq = a.nq;
+  for (int64_t i = a0 + threadIdx.x; i < a1; i += blockDim.x) {
+    int zi = a.species[i];
+    zi = zi < 0 ? 0 : (zi >= S ? S - 1 : zi);
+    const int cnt = a.count[i];
+    for (int p = 0; p < cnt; ++p) {
+      const size_t e = (size_t)p * a.stride + i;
+      const PairRec<T> q = pr[e];
+      const int zj = q.zj;
+      const double x = q.x, y = q.y, z = q.z;
+      const double r = sqrt(x * x + y * y + z * z);
+      const double sc = a.rcut - r;
+      const double xq = (2.0 * r - a.rmin - a.rcut) * span_inv;
+      // Chebyshev T_b(xq) and dT_b/dxq by their three-term recurrences
+      double t0 = 1.0, t1 = xq, d0 = 0.0, d1 = 1.0;
+      for (int b = 0; b < nq; ++b) {
+        const double tb = b == 0 ? t0 : t1, db = b == 0 ? d0 : d1;
+        const double Q = tb * sc * sc, dQ = db * dxdr * sc * sc - 2.0 * tb * sc;
+        for (int mu = 0; mu < a.n_mu; ++mu) {
+          const double v = (double)pa[(size_t)mu * n_slots + e] * Q + (double)pb[(size_t)mu * n_slots + e] * dQ;
+          atomicAdd(&acc[((mu * S + zi) * S + zj) * nq + b], v);
+        }
+        if (b >= 1) {
+          const double t2 = 2.0 * xq * t1 - t0, d2 = 2.0 * t1 + 2.0 * xq * d1 - d0;
+          t0 = t1; t1 = t2; d0 = d1; d1 = d2;
+        }
+      }
+    }
+  }
+  __syncthreads();
+  double* row = a.rows + (size_t)k * (a.m + a.n_c);
+  for (int t = threadIdx.x; t < a.n_c; t += blockDim.x) row[a.m + t] = acc[t];
+}
+
+__global__ void copy_b_kernel(int n_cfg, int m, int n_c, const double* __restrict__ b, double* rows) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)n_cfg * m) return;
+  rows[(t / m) * (m + n_c) + t % m] = b[t];
+}
+
 }  // namespace
 
 hipError_t loss_residuals(LossResidualArgs& r, int fp64, void* a_atom, void* u, void* eps_atom, hipStream_t s) {
@@ -135,6 +203,38 @@ hipError_t loss_finish(int fp64, int n_cfg, int64_t N, int stride, int m, int n_
     hipError_t e = hipMemsetAsync(grad, 0, sizeof(double) * (m + n_c), s);
     if (e != hipSuccess) return e;
   }
+  return hipGetLastError();
+}
+
+
+hipError_t theta_rows_prepare(int fp64, int64_t N, int stride, void* a_atom, void* u, void* eps_atom, hipStream_t s) {
+  const int64_t n_eps = 9 * (int64_t)stride;
+  const int64_t n = std::max(3 * N, n_eps);
+  if (n == 0) return hipSuccess;
+  const dim3 g((unsigned)((n + kBlock - 1) / kBlock));
+  if (fp64)
+    hipLaunchKernelGGL(unit_weights_kernel<double>, g, dim3(kBlock), 0, s, N, n_eps, (double*)a_atom, (double*)u,
+                       (double*)eps_atom);
+  else
+    hipLaunchKernelGGL(unit_weights_kernel<float>, g, dim3(kBlock), 0, s, N, n_eps, (float*)a_atom, (float*)u,
+                       (float*)eps_atom);
+  return hipGetLastError();
+}
+
+hipError_t theta_rows_finish(int fp64, const ThetaRowArgs& a, const void* pr, const void* pa, const void* pb,
+                             const double* b, hipStream_t s) {
+  if (a.n_cfg == 0) return hipSuccess;
+  const size_t lds = sizeof(double) * (size_t)a.n_c;
+  if (fp64)
+    hipLaunchKernelGGL(c_rows_kernel<double>, dim3(a.n_cfg), dim3(kBlock), lds, s, a, (const PairRec<double>*)pr,
+                       (const double*)pa, (const double*)pb);
+  else
+    hipLaunchKernelGGL(c_rows_kernel<float>, dim3(a.n_cfg), dim3(kBlock), lds, s, a, (const PairRec<float>*)pr,
+                       (const float*)pa, (const float*)pb);
+  const int64_t nb = (int64_t)a.n_cfg * a.m;
+  if (nb > 0)
+    hipLaunchKernelGGL(copy_b_kernel, dim3((unsigned)((nb + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, a.n_cfg, a.m,
+                       a.n_c, b, a.rows);
   return hipGetLastError();
 }
 

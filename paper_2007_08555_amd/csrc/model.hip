@@ -97,6 +97,9 @@ struct mtp_model {
   // active set
   bool has_active = false;
   Buffer ainv, gj_work, gj_flag;
+  bool has_active_theta = false;   // active set of rows dE/dtheta (nonlinear grade)
+  int theta_cols = 0;              // its row length
+  Buffer ainv_theta, th_b;
   // workspace
   Buffer cfg, cfg_order, atom_cfg, atom_bin, bin_count, bin_start, bin_atoms, bin_fill, binned, large, nbins_dev;
   Buffer count, nbr, pr, rev, gpair, own, Mbuf, Gbuf, Dbuf, site, wv, B, status, run_start;
@@ -603,35 +606,146 @@ int mtp_eval_async(mtp_model* M, const mtp_batch* bt, const mtp_out* out, int pr
   return run_eval(M, bt, out, precision, (hipStream_t)stream, true);
 }
 
-int mtp_set_active_set(mtp_model* M, const double* A_dev, void* stream) {
-  g_err.clear();
-  if (!M || !A_dev) return fail(MTP_E_ARG, "mtp_set_active_set: null argument");
-  HIP_TRY(hipSetDevice(M->device), "hipSetDevice");
-  hipStream_t s = (hipStream_t)stream;
-  const int m = M->m;
-  // [A | I] in file column order; b rows handed to the grade are in file order too
-  std::vector<double> A((size_t)m * m), W((size_t)m * 2 * m, 0.0);
-  HIP_TRY(hipMemcpyAsync(A.data(), A_dev, sizeof(double) * m * m, hipMemcpyDeviceToHost, s), "hipMemcpyAsync");
+// inv = A^-1 of an n x n active-set matrix A (device, row-major, file order)
+// by the Gauss-Jordan kernel; MTP_E_ARG when A is numerically singular.
+static int invert_active(mtp_model* M, const double* A_dev, int n, Buffer& inv, const char* who, hipStream_t s) {
+  // [A | I]
+  std::vector<double> A((size_t)n * n), W((size_t)n * 2 * n, 0.0);
+  HIP_TRY(hipMemcpyAsync(A.data(), A_dev, sizeof(double) * n * n, hipMemcpyDeviceToHost, s), "hipMemcpyAsync");
   HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
-  for (int r = 0; r < m; ++r) {
-    std::copy(A.begin() + (size_t)r * m, A.begin() + (size_t)(r + 1) * m, W.begin() + (size_t)r * 2 * m);
-    W[(size_t)r * 2 * m + m + r] = 1.0;
+  for (int r = 0; r < n; ++r) {
+    std::copy(A.begin() + (size_t)r * n, A.begin() + (size_t)(r + 1) * n, W.begin() + (size_t)r * 2 * n);
+    W[(size_t)r * 2 * n + n + r] = 1.0;
   }
   HIP_TRY(M->gj_work.ensure(sizeof(double) * W.size()), "hipMalloc");
-  HIP_TRY(M->ainv.ensure(sizeof(double) * (size_t)m * m), "hipMalloc");
+  HIP_TRY(inv.ensure(sizeof(double) * (size_t)n * n), "hipMalloc");
   HIP_TRY(M->gj_flag.ensure(sizeof(int)), "hipMalloc");
   HIP_TRY(hipMemcpyAsync(M->gj_work.p, W.data(), sizeof(double) * W.size(), hipMemcpyHostToDevice, s),
           "hipMemcpyAsync");
-  HIP_TRY(mtp::gauss_jordan_inverse(m, M->gj_work.as<double>(), M->ainv.as<double>(), M->gj_flag.as<int>(), s),
+  HIP_TRY(mtp::gauss_jordan_inverse(n, M->gj_work.as<double>(), inv.as<double>(), M->gj_flag.as<int>(), s),
           "Gauss-Jordan");
   int singular = 0;
   HIP_TRY(hipMemcpyAsync(&singular, M->gj_flag.p, sizeof(int), hipMemcpyDeviceToHost, s), "hipMemcpyAsync");
   HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
-  if (singular) {
-    M->has_active = false;
-    return fail(MTP_E_ARG, "mtp_set_active_set: A is numerically singular");
-  }
-  M->has_active = true;
+  if (singular) return fail(MTP_E_ARG, std::string(who) + ": A is numerically singular");
+  return MTP_OK;
+}
+
+int mtp_set_active_set(mtp_model* M, const double* A_dev, void* stream) {
+  g_err.clear();
+  if (!M || !A_dev) return fail(MTP_E_ARG, "mtp_set_active_set: null argument");
+  HIP_TRY(hipSetDevice(M->device), "hipSetDevice");
+  // b rows handed to the grade are in file order, like the columns of A
+  const int rc = invert_active(M, A_dev, M->m, M->ainv, "mtp_set_active_set", (hipStream_t)stream);
+  M->has_active = rc == MTP_OK;
+  return rc;
+}
+
+int mtp_set_active_set_theta(mtp_model* M, int32_t n_cols, const double* A_dev, void* stream) {
+  g_err.clear();
+  if (!M || !A_dev) return fail(MTP_E_ARG, "mtp_set_active_set_theta: null argument");
+  if (n_cols < 1 || n_cols > M->m + M->n_c)
+    return fail(MTP_E_ARG, "mtp_set_active_set_theta: n_cols must be in [1, m + n_c]");
+  HIP_TRY(hipSetDevice(M->device), "hipSetDevice");
+  M->has_active_theta = false;
+  const int rc = invert_active(M, A_dev, n_cols, M->ainv_theta, "mtp_set_active_set_theta", (hipStream_t)stream);
+  M->has_active_theta = rc == MTP_OK;
+  M->theta_cols = rc == MTP_OK ? n_cols : 0;
+  return rc;
+}
+
+int mtp_grade_theta(mtp_model* M, int32_t n, const double* rows_dev, double* gamma_dev, int32_t* argmax_dev,
+                    void* stream) {
+  g_err.clear();
+  if (!M || n < 0 || (n > 0 && (!rows_dev || !gamma_dev || !argmax_dev)))
+    return fail(MTP_E_ARG, "mtp_grade_theta: bad argument");
+  if (!M->has_active_theta)
+    return fail(MTP_E_STATE, "mtp_grade_theta: no active set (call mtp_set_active_set_theta)");
+  HIP_TRY(hipSetDevice(M->device), "hipSetDevice");
+  hipStream_t s = (hipStream_t)stream;
+  const int nt = M->theta_cols;
+  HIP_TRY(M->c_tmp.ensure(sizeof(double) * (size_t)std::max(1, n) * nt), "hipMalloc");
+  HIP_TRY(mtp::grade_rows(n, nt, rows_dev, M->ainv_theta.as<double>(), gamma_dev, argmax_dev, M->c_tmp.as<double>(),
+                          s),
+          "grade");
+  return MTP_OK;
+}
+
+int mtp_theta_rows(mtp_model* M, const mtp_batch* bt, int precision, double* rows_dev, void* stream) {
+  g_err.clear();
+  if (!M || !bt || !rows_dev) return fail(MTP_E_ARG, "mtp_theta_rows: null argument");
+  if (precision != MTP_FP64 && precision != MTP_FP32) return fail(MTP_E_ARG, "mtp_theta_rows: precision must be FP64 or FP32");
+  HIP_TRY(hipSetDevice(M->device), "hipSetDevice");
+  hipStream_t s = (hipStream_t)stream;
+  const int K_cfg = bt->n_configs;
+  const int64_t N = bt->n_atoms;
+  if (K_cfg <= 0) return fail(MTP_E_ARG, "mtp_theta_rows: empty batch");
+  HIP_TRY(M->lo_E.ensure(sizeof(double) * K_cfg), "hipMalloc");
+  HIP_TRY(M->lo_W.ensure(sizeof(double) * 9 * K_cfg), "hipMalloc");
+  HIP_TRY(M->lo_F.ensure(sizeof(double) * 3 * (N + 1)), "hipMalloc");
+  HIP_TRY(M->th_b.ensure(sizeof(double) * (size_t)K_cfg * M->m), "hipMalloc");
+  mtp_out o{};
+  o.energy = M->lo_E.as<double>();
+  o.forces = M->lo_F.as<double>();
+  o.virial = M->lo_W.as<double>();
+  o.b = M->th_b.as<double>();
+  int rc = run_eval(M, bt, &o, precision, s);
+  if (rc != MTP_OK) return rc;
+  const bool fp64 = precision == MTP_FP64;
+  const size_t tsz = fp64 ? sizeof(double) : sizeof(float);
+  const int stride = M->last_stride;
+  const int K = M->K;
+  const int C = M->var->C;
+  const int block = M->var->block;
+  const int n_blocks = (int)((N + block - 1) / block);
+  HIP_TRY(M->lo_a.ensure(tsz * (N + 1)), "hipMalloc");
+  HIP_TRY(M->lo_u.ensure(tsz * 3 * (N + 1)), "hipMalloc");
+  HIP_TRY(M->lo_eps.ensure(tsz * 9 * stride), "hipMalloc");
+  HIP_TRY(M->lo_dM.ensure(tsz * (size_t)C * stride), "hipMalloc");
+  HIP_TRY(M->lo_dG.ensure(tsz * (size_t)C * stride), "hipMalloc");
+  HIP_TRY(M->lo_gd.ensure(tsz * 2 * (size_t)M->var->n_graphs * stride), "hipMalloc");
+  HIP_TRY(M->lo_xit.ensure(tsz * (size_t)M->m * stride), "hipMalloc");
+  HIP_TRY(M->lo_pa.ensure(tsz * (size_t)M->n_mu * K * stride), "hipMalloc");
+  HIP_TRY(M->lo_pb.ensure(tsz * (size_t)M->n_mu * K * stride), "hipMalloc");
+  HIP_TRY(M->lo_cpart.ensure(sizeof(double) * (size_t)std::max(1, n_blocks) * M->n_c), "hipMalloc");
+  HIP_TRY(mtp::theta_rows_prepare(fp64, N, stride, M->lo_a.p, M->lo_u.p, M->lo_eps.p, s), "unit weights");
+  auto launch = [&](auto* tag) -> int {
+    using T = std::remove_pointer_t<decltype(tag)>;
+    auto ea = make_args<T>(M, N, stride, bt->species, false);
+    mtp::LossArgs<T> la;
+    la.a_atom = M->lo_a.as<T>();
+    la.u = M->lo_u.as<T>();
+    la.eps_atom = M->lo_eps.as<T>();
+    la.nbr = M->nbr.as<int>();
+    la.K = K;
+    la.dM = M->lo_dM.as<T>();
+    la.dG = M->lo_dG.as<T>();
+    la.gd = M->lo_gd.as<T>();
+    la.xi_terms = M->lo_xit.as<T>();
+    la.pa = M->lo_pa.as<T>();
+    la.pb = M->lo_pb.as<T>();
+    la.cpart = M->lo_cpart.as<double>();
+    HIP_TRY(M->var->launch_loss(precision, &ea, &la, s), "loss-gradient kernels");
+    return MTP_OK;
+  };
+  rc = fp64 ? launch((double*)nullptr) : launch((float*)nullptr);
+  if (rc != MTP_OK) return rc;
+  mtp::ThetaRowArgs ta{};
+  ta.n_cfg = K_cfg;
+  ta.cfg = M->cfg.as<mtp::CfgInfo>();
+  ta.stride = stride;
+  ta.K = K;
+  ta.count = M->count.as<int32_t>();
+  ta.species = bt->species;
+  ta.n_mu = M->n_mu;
+  ta.n_species = M->S;
+  ta.nq = M->nq;
+  ta.rmin = M->rmin;
+  ta.rcut = M->rcut;
+  ta.m = M->m;
+  ta.n_c = M->n_c;
+  ta.rows = rows_dev;
+  HIP_TRY(mtp::theta_rows_finish(fp64, ta, M->pr.p, M->lo_pa.p, M->lo_pb.p, M->th_b.as<double>(), s), "theta rows");
   return MTP_OK;
 }
 

@@ -146,6 +146,25 @@ struct LossResidualArgs {
   double* loss_cfg;   // [n_cfg]
   double* loss_atom;  // [N]
 };
+// Rows dE_k/dtheta of the nonlinear grade (loss.hip): theta_rows_prepare sets
+// a = 1, u = 0, eps = 0 for the loss kernels; theta_rows_finish sums their
+// per-pair c coefficients per configuration into rows[k][m + t] and copies
+// b_k (file order) into rows[k][0 .. m).
+struct ThetaRowArgs {
+  int n_cfg;
+  const CfgInfo* cfg;
+  int stride, K;
+  const int32_t* count;
+  const int32_t* species;
+  int n_mu, n_species, nq;
+  double rmin, rcut;
+  int m, n_c;
+  double* rows;   // [n_cfg][m + n_c]
+};
+hipError_t theta_rows_prepare(int fp64, int64_t N, int stride, void* a_atom, void* u, void* eps_atom, hipStream_t s);
+hipError_t theta_rows_finish(int fp64, const ThetaRowArgs& a, const void* pr, const void* pa, const void* pb,
+                             const double* b, hipStream_t s);
+
 hipError_t loss_residuals(LossResidualArgs& r, int fp64, void* a_atom, void* u, void* eps_atom, hipStream_t s);
 hipError_t loss_finish(int fp64, int n_cfg, int64_t N, int stride, int m, int n_c, int n_blocks,
                        const double* loss_cfg, const double* loss_atom, const void* xi_terms, const int32_t* perm,

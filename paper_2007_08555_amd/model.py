@@ -240,6 +240,33 @@ class Potential:
               "mtp_grade_from_b")
         return (gamma, arg, c) if want_c else (gamma, arg)
 
+    # nonlinear grade: rows dE/dtheta over theta = (xi, c) ------------------
+    def theta_rows(self, batch: Batch, precision="fp64", stream=None):
+        """dE_k/dtheta [K, m + n_c] FP64 on the device (mtp_theta_rows)."""
+        rows = torch.empty((batch.n_configs, self.m + self.n_c), dtype=torch.float64, device=self.device)
+        bs = batch.c_struct()
+        check(lib().mtp_theta_rows(self._h, ctypes.byref(bs), _lib.PRECISIONS[precision], _ptr(rows),
+                                   _stream(stream)), "mtp_theta_rows")
+        return rows
+
+    def set_active_set_theta(self, A, stream=None):
+        """A [n, n]: theta rows of the active configurations restricted to n
+        chosen columns (mtp_set_active_set_theta)."""
+        A = torch.as_tensor(A, dtype=torch.float64).to(self.device).contiguous()
+        n = int(A.shape[0])
+        if A.dim() != 2 or tuple(A.shape) != (n, n) or not 1 <= n <= self.m + self.n_c:
+            raise ValueError(f"active set must be square with at most {self.m + self.n_c} columns")
+        check(lib().mtp_set_active_set_theta(self._h, n, _ptr(A), _stream(stream)), "mtp_set_active_set_theta")
+
+    def grade_theta(self, rows, stream=None):
+        rows = torch.as_tensor(rows, dtype=torch.float64).to(self.device).contiguous()
+        n = int(rows.shape[0])
+        gamma = torch.empty(n, dtype=torch.float64, device=self.device)
+        arg = torch.empty(n, dtype=torch.int32, device=self.device)
+        check(lib().mtp_grade_theta(self._h, n, _ptr(rows), _ptr(gamma), _ptr(arg), _stream(stream)),
+              "mtp_grade_theta")
+        return gamma, arg
+
     def maxvol(self, pool, rows=None, delta=1e-3, max_swaps=-1, stream=None):
         """MaxVol selection of m rows of pool [K, m] (FP64, file order) by
         mtp_maxvol; rows = starting rows, or None for the pivot rows of

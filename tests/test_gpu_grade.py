@@ -79,3 +79,58 @@ def test_singular_active_set_is_rejected(setup):
         P2.set_active_set(bad)
     with pytest.raises(MTPError, match="active set"):
         P2.grade_from_b(A[:2])
+
+
+def test_theta_rows_match_the_oracle():
+    """Rows dE_k/dtheta of the nonlinear grade (mtp_theta_rows) against the
+    oracle's complex-step rows: every xi column and a sample of c columns."""
+    from paper_2007_08555_amd import Batch, Potential
+    P = Potential(pot_path("lev12_s2"))
+    pot = read_potential(pot_path("lev12_s2"))
+    batch = synth.mixed_batch(seed=21, n_configs=4, n_min=8, n_max=20, n_species_model=2)
+    m, nc = len(pot["xi"]), pot["c"].size
+    idx = list(range(m)) + list(range(m, m + nc, 6)) + [m + nc - 1]
+    log(f"[theta rows] configs 4 atoms {int(batch['n_atoms'].sum())} columns {len(idx)} of {m + nc}")
+    R = P.theta_rows(Batch.from_arrays(batch), precision="fp64").cpu().numpy()
+    assert R.shape == (4, m + nc)
+    Ro = og.theta_rows(pot, batch, indices=idx)
+    scale = np.maximum(np.abs(Ro).max(axis=0), 1e-300)
+    err = np.abs(R[:, idx] - Ro) / scale
+    log(f"[theta rows] max error relative to each column's scale {err.max():.3e}")
+    assert err.max() <= 1e-10
+    assert np.abs(Ro[:, m:]).max() > 0
+    R32 = P.theta_rows(Batch.from_arrays(batch), precision="fp32").cpu().numpy()
+    err32 = np.abs(R32[:, idx] - Ro) / scale
+    log(f"[theta rows] FP32 kernels: {err32.max():.3e}")
+    assert err32.max() <= 1e-4
+
+
+def test_nonlinear_grade_matches_the_oracle():
+    """gamma over theta rows (oracle rows, restricted to independent columns
+    chosen by pivoted QR: the full rows are rank-deficient by one relation per
+    radial function) against an active set chosen by pivoted elimination: the
+    oracle's grade on the same rows, and grade one with argmax = own index on
+    the active rows themselves."""
+    import scipy.linalg
+    from paper_2007_08555_amd import Potential
+    P = Potential(pot_path("lev8_s1"))
+    pot = read_potential(pot_path("lev8_s1"))
+    batch = synth.mixed_batch(seed=22, n_configs=48, n_min=8, n_max=24, n_species_model=1)
+    R = og.theta_rows(pot, batch)
+    Rs = R / np.abs(R).max(axis=0).clip(1e-300)
+    _q, rr, piv = scipy.linalg.qr(Rs, pivoting=True)
+    rank = int((np.abs(np.diag(rr)) > 1e-10 * abs(rr[0, 0])).sum())
+    cols = np.sort(piv[:rank])
+    Rc = R[:, cols]
+    rows = og.initial_rows(Rc)
+    A = Rc[rows]
+    P.set_active_set_theta(A)
+    gam, arg = P.grade_theta(Rc)
+    gam_o, arg_o, c_o = og.grade(Rc, A)
+    g = gam.cpu().numpy()
+    log(f"[nonlinear grade] {R.shape[1]} theta columns, rank {rank}, gamma {g.min():.3g}..{g.max():.3g}")
+    assert rank < R.shape[1]
+    assert np.allclose(g, gam_o, rtol=1e-8)
+    ga, aa = P.grade_theta(A)
+    assert np.allclose(ga.cpu().numpy(), 1.0, atol=1e-8)
+    assert np.array_equal(aa.cpu().numpy(), np.arange(rank))
