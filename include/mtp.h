@@ -290,6 +290,16 @@ int mtp_maxvol(mtp_model* model, int32_t n_pool, const double* pool_dev, int32_t
                double delta, int32_t max_swaps, int32_t* n_swaps, void* stream);
 
 /*
+ * mtp_maxvol for the nonlinear grade: the pool holds theta rows (from
+ * mtp_theta_rows) restricted to n_cols columns of the caller's choice
+ * (device, [n_pool][n_cols] FP64, 1 <= n_cols <= m + n_c), and n_cols rows
+ * are selected (rows_dev [n_cols] int32).  Same algorithm, ties, errors and
+ * synchronisation as mtp_maxvol; pass pool[rows] to mtp_set_active_set_theta.
+ */
+int mtp_maxvol_theta(mtp_model* model, int32_t n_cols, int32_t n_pool, const double* pool_dev, int32_t* rows_dev,
+                     int init, double delta, int32_t max_swaps, int32_t* n_swaps, void* stream);
+
+/*
  * One half step of velocity Verlet for the molecular dynamics in which the
  * active learning of section 2.3 runs: vel += (dt/2) F / m for every atom
  * and, when drift != 0, then pos += dt vel.  Device arrays: species [n]

@@ -776,15 +776,16 @@ int mtp_md_kick(mtp_model* M, int64_t n_atoms, const int32_t* species_dev, doubl
   return MTP_OK;
 }
 
-int mtp_maxvol(mtp_model* M, int32_t n_pool, const double* pool_dev, int32_t* rows_dev, int init, double delta,
-               int32_t max_swaps, int32_t* n_swaps, void* stream) {
+// MaxVol over a pool of rows of length m (the basis size for b rows, or the
+// caller's column count for theta rows); `who` names the entry point in errors.
+static int maxvol_rows(mtp_model* M, const std::string& who, int m, int32_t n_pool, const double* pool_dev,
+                       int32_t* rows_dev, int init, double delta, int32_t max_swaps, int32_t* n_swaps, void* stream) {
   using namespace mtp;
-  g_err.clear();
-  if (!M || !pool_dev || !rows_dev) return fail(MTP_E_ARG, "mtp_maxvol: null argument");
-  const int m = M->m, K = n_pool;
-  if (K < m) return fail(MTP_E_ARG, "mtp_maxvol: the pool has fewer rows than the basis size");
-  if (!(delta >= 0.0)) return fail(MTP_E_ARG, "mtp_maxvol: delta must be non-negative");
-  if ((int64_t)K * m >= 0x7fffffffLL) return fail(MTP_E_CAPACITY, "mtp_maxvol: pool too large");
+  if (!M || !pool_dev || !rows_dev) return fail(MTP_E_ARG, who + ": null argument");
+  const int K = n_pool;
+  if (K < m) return fail(MTP_E_ARG, who + ": the pool has fewer rows than the basis size");
+  if (!(delta >= 0.0)) return fail(MTP_E_ARG, who + ": delta must be non-negative");
+  if ((int64_t)K * m >= 0x7fffffffLL) return fail(MTP_E_CAPACITY, who + ": pool too large");
   if (max_swaps < 0) max_swaps = 100 * m;
   HIP_TRY(hipSetDevice(M->device), "hipSetDevice");
   hipStream_t s = (hipStream_t)stream;
@@ -812,7 +813,7 @@ int mtp_maxvol(mtp_model* M, int32_t n_pool, const double* pool_dev, int32_t* ro
     std::sort(sorted.begin(), sorted.end());
     for (int t = 0; t < m; ++t)
       if (sorted[t] < 0 || sorted[t] >= K || (t > 0 && sorted[t] == sorted[t - 1]))
-        return fail(MTP_E_ARG, "mtp_maxvol: starting rows must be distinct indices into the pool");
+        return fail(MTP_E_ARG, who + ": starting rows must be distinct indices into the pool");
   } else {
     HIP_TRY(M->mv_W.ensure(sizeof(double) * km), "hipMalloc");
     HIP_TRY(M->mv_perm.ensure(sizeof(int32_t) * K), "hipMalloc");
@@ -820,7 +821,7 @@ int mtp_maxvol(mtp_model* M, int32_t n_pool, const double* pool_dev, int32_t* ro
     HIP_TRY(maxvol_pivot_rows(K, m, M->mv_W.as<double>(), M->mv_perm.as<int32_t>(), rows_dev, M->mv_flag.as<int>(), s),
             "pivot rows");
     HIP_TRY(read_flag(flag), "pivot rows");
-    if (flag) return fail(MTP_E_ARG, "mtp_maxvol: the pool has rank below the basis size");
+    if (flag) return fail(MTP_E_ARG, who + ": the pool has rank below the basis size");
   }
   double* C = M->mv_C.as<double>();
   // A^{-1} of the selected rows and C = pool A^{-1} from scratch, with row maxima
@@ -829,7 +830,7 @@ int mtp_maxvol(mtp_model* M, int32_t n_pool, const double* pool_dev, int32_t* ro
     HIP_TRY(gauss_jordan_inverse(m, M->mv_gj.as<double>(), M->mv_inv.as<double>(), M->mv_flag.as<int>(), s),
             "Gauss-Jordan");
     HIP_TRY(read_flag(flag), "Gauss-Jordan");
-    if (flag) return fail(MTP_E_ARG, "mtp_maxvol: the selected rows are numerically singular");
+    if (flag) return fail(MTP_E_ARG, who + ": the selected rows are numerically singular");
     HIP_TRY(grade_rows(K, m, pool_dev, M->mv_inv.as<double>(), M->mv_max.as<double>(), M->mv_arg.as<int32_t>(), C,
                        s),
             "C = pool A^-1");
@@ -863,6 +864,23 @@ int mtp_maxvol(mtp_model* M, int32_t n_pool, const double* pool_dev, int32_t* ro
   }
   if (n_swaps) *n_swaps = swaps;
   return MTP_OK;
+}
+
+int mtp_maxvol(mtp_model* M, int32_t n_pool, const double* pool_dev, int32_t* rows_dev, int init, double delta,
+               int32_t max_swaps, int32_t* n_swaps, void* stream) {
+  g_err.clear();
+  if (!M) return fail(MTP_E_ARG, "mtp_maxvol: null argument");
+  return maxvol_rows(M, "mtp_maxvol", M->m, n_pool, pool_dev, rows_dev, init, delta, max_swaps, n_swaps, stream);
+}
+
+int mtp_maxvol_theta(mtp_model* M, int32_t n_cols, int32_t n_pool, const double* pool_dev, int32_t* rows_dev,
+                     int init, double delta, int32_t max_swaps, int32_t* n_swaps, void* stream) {
+  g_err.clear();
+  if (!M) return fail(MTP_E_ARG, "mtp_maxvol_theta: null argument");
+  if (n_cols < 1 || n_cols > M->m + M->n_c)
+    return fail(MTP_E_ARG, "mtp_maxvol_theta: n_cols must be in [1, m + n_c]");
+  return maxvol_rows(M, "mtp_maxvol_theta", n_cols, n_pool, pool_dev, rows_dev, init, delta, max_swaps, n_swaps,
+                     stream);
 }
 
 int mtp_grade_from_b(mtp_model* M, int32_t n, const double* b_dev, double* gamma_dev, int32_t* argmax_dev,

@@ -267,6 +267,21 @@ class Potential:
               "mtp_grade_theta")
         return gamma, arg
 
+    def maxvol_theta(self, pool, rows=None, delta=1e-3, max_swaps=-1, stream=None):
+        """MaxVol selection of n rows of a pool of theta rows restricted to n
+        columns ([K, n] FP64) by mtp_maxvol_theta; as maxvol otherwise."""
+        pool = torch.as_tensor(pool, dtype=torch.float64).to(self.device).contiguous()
+        K, n_cols = int(pool.shape[0]), int(pool.shape[1])
+        if rows is None:
+            r = torch.zeros(n_cols, dtype=torch.int32, device=self.device)
+        else:
+            r = torch.as_tensor(rows, dtype=torch.int32).to(self.device).clone().contiguous()
+        n = ctypes.c_int32()
+        check(lib().mtp_maxvol_theta(self._h, n_cols, K, _ptr(pool), _ptr(r), 0 if rows is None else 1,
+                                     float(delta), int(max_swaps), ctypes.byref(n), _stream(stream)),
+              "mtp_maxvol_theta")
+        return r, n.value
+
     def maxvol(self, pool, rows=None, delta=1e-3, max_swaps=-1, stream=None):
         """MaxVol selection of m rows of pool [K, m] (FP64, file order) by
         mtp_maxvol; rows = starting rows, or None for the pivot rows of

@@ -134,3 +134,12 @@ def test_nonlinear_grade_matches_the_oracle():
     ga, aa = P.grade_theta(A)
     assert np.allclose(ga.cpu().numpy(), 1.0, atol=1e-8)
     assert np.array_equal(aa.cpu().numpy(), np.arange(rank))
+    # MaxVol over the theta pool: the same swaps and final rows as the oracle's
+    sel, swaps = P.maxvol_theta(Rc)
+    sel_o, swaps_o = og.maxvol(Rc)
+    log(f"[nonlinear maxvol] swaps gpu {swaps} oracle {swaps_o}")
+    assert swaps == swaps_o
+    assert np.array_equal(sel.cpu().numpy(), np.asarray(sel_o))
+    P.set_active_set_theta(Rc[sel.cpu().numpy()])
+    g3, _ = P.grade_theta(Rc)
+    assert g3.max().item() <= 1.0 + 1e-3 + 1e-9
