@@ -191,3 +191,24 @@ def test_theta_rows_xi_part_is_b_and_c_part_matches_finite_differences():
         fd = (E[0] - E[1]) / (2 * h)
         np.testing.assert_allclose(R[:, t], fd, rtol=1e-6, atol=1e-7 * max(1.0, np.abs(fd).max()))
         assert np.abs(R[:, t]).max() > 0   # the sampled c entries are used by these species pairs
+
+
+def test_fire_step_special_cases():
+    """The FIRE oracle: from rest it is a plain Euler step with the force; a
+    velocity against the force is zeroed and the step shrinks; the mixing
+    keeps |v| along a force parallel to v."""
+    from oracle import relax as orx
+    acc = orx.EV_PER_A_AMU_IN_A_PER_FS2
+    prm = dict(dt_max=5.0, n_min=1, f_inc=1.1, f_dec=0.5, alpha_start=0.1, f_alpha=0.99)
+    x = np.zeros((2, 3)); F = np.array([[1.0, 0, 0], [0, -2.0, 0]]); m = np.array([2.0, 4.0])
+    x1, v1, st = orx.fire_step(x, np.zeros((2, 3)), F, m, (0.5, 0.1, 0), **prm)
+    np.testing.assert_allclose(v1, 0.5 * acc * F / m[:, None], rtol=1e-15)
+    np.testing.assert_allclose(x1, 0.5 * v1, rtol=1e-15)
+    assert st == (0.5, 0.1, 1)
+    x2, v2, st2 = orx.fire_step(x, -F, F, m, (0.5, 0.05, 7), **prm)
+    assert st2 == (0.25, 0.1, 0)
+    np.testing.assert_allclose(v2, 0.25 * acc * F / m[:, None], rtol=1e-15)
+    v = np.array([[2.0, 0, 0]]); f = np.array([[3.0, 0, 0]])
+    _x, v3, st3 = orx.fire_step(np.zeros((1, 3)), v, f, np.array([1e30]), (1.0, 0.1, 5), **prm)
+    np.testing.assert_allclose(v3, v, rtol=1e-12)     # mixing along v keeps |v| (the kick is ~0)
+    assert st3[0] == 1.1 and abs(st3[1] - 0.099) < 1e-15 and st3[2] == 6
