@@ -313,6 +313,27 @@ int mtp_maxvol_theta(mtp_model* model, int32_t n_cols, int32_t n_pool, const dou
 int mtp_md_kick(mtp_model* model, int64_t n_atoms, const int32_t* species_dev, double* pos_dev, double* vel_dev,
                 const double* forces_dev, const double* mass_host, double dt_fs, int drift, void* stream);
 
+/*
+ * One step of FIRE relaxation (the relaxations of the active-learning
+ * scheme of section 2.3 run to a minimum of the potential; FIRE is the method
+ * of Bitzek et al., Phys. Rev. Lett. 97, 170201 (2006)), every configuration
+ * of a batch independently: with P = F . v over the configuration, if P >= 0
+ * v <- (1 - alpha) v + alpha |v| F/|F| and, after more than n_min such steps
+ * in a row, dt <- min(f_inc dt, dt_max), alpha <- f_alpha alpha; if P < 0,
+ * v <- 0, dt <- f_dec dt, alpha <- alpha_start.  Then v += dt F / m and
+ * pos += dt v.  Device arrays: atom_offsets [n_configs + 1] int64, species
+ * [n_atoms] int32, pos and vel [n_atoms][3] FP64 (updated in place), forces
+ * [n_atoms][3] FP64 (eV/A, from mtp_eval at pos), state [n_configs][4] FP64
+ * (dt in fs, alpha, the count of steps with P >= 0, unused; the caller sets
+ * dt0, alpha_start, 0 before the first step).  mass_host [S] amu;
+ * params_host = {dt_max, n_min, f_inc, f_dec, alpha_start, f_alpha}.
+ * MTP_E_ARG for null arrays or parameters out of range.  Asynchronous on
+ * `stream` except for new masses, as mtp_md_kick.
+ */
+int mtp_fire_step(mtp_model* model, int32_t n_configs, const int64_t* atom_offsets_dev, int64_t n_atoms,
+                  const int32_t* species_dev, double* pos_dev, double* vel_dev, const double* forces_dev,
+                  const double* mass_host, double* state_dev, const double* params_host, void* stream);
+
 /* Counters and device timings of the last mtp_eval on a model. */
 typedef struct {
   int64_t n_atoms;          /* atoms of the last batch */

@@ -749,30 +749,65 @@ int mtp_theta_rows(mtp_model* M, const mtp_batch* bt, int precision, double* row
   return MTP_OK;
 }
 
+// Inverse masses per species on the device, uploaded when they change (a
+// synchronous copy: the host array is the caller's).
+static int upload_masses(mtp_model* M, const double* mass_host, const std::string& who, hipStream_t s) {
+  const int S = M->S;
+  std::vector<double> inv(S);
+  for (int z = 0; z < S; ++z) {
+    if (!(mass_host[z] > 0.0)) return fail(MTP_E_ARG, who + ": masses must be positive");
+    inv[z] = 1.0 / mass_host[z];
+  }
+  if (M->md_masses != std::vector<double>(mass_host, mass_host + S)) {
+    HIP_TRY(M->md_inv_mass.ensure(sizeof(double) * S), "hipMalloc");
+    HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
+    HIP_TRY(hipMemcpy(M->md_inv_mass.p, inv.data(), sizeof(double) * S, hipMemcpyHostToDevice), "hipMemcpy");
+    M->md_masses.assign(mass_host, mass_host + S);
+  }
+  return MTP_OK;
+}
+
 int mtp_md_kick(mtp_model* M, int64_t n_atoms, const int32_t* species_dev, double* pos_dev, double* vel_dev,
                 const double* forces_dev, const double* mass_host, double dt_fs, int drift, void* stream) {
   g_err.clear();
   if (!M || n_atoms < 0 || !mass_host) return fail(MTP_E_ARG, "mtp_md_kick: bad argument");
   if (n_atoms > 0 && (!species_dev || !vel_dev || !forces_dev || (drift && !pos_dev)))
     return fail(MTP_E_ARG, "mtp_md_kick: null array");
-  const int S = M->S;
-  std::vector<double> inv(S);
-  for (int z = 0; z < S; ++z) {
-    if (!(mass_host[z] > 0.0)) return fail(MTP_E_ARG, "mtp_md_kick: masses must be positive");
-    inv[z] = 1.0 / mass_host[z];
-  }
   HIP_TRY(hipSetDevice(M->device), "hipSetDevice");
   hipStream_t s = (hipStream_t)stream;
-  if (M->md_masses != std::vector<double>(mass_host, mass_host + S)) {
-    // new masses: a synchronous copy (the host vector is gone after return)
-    HIP_TRY(M->md_inv_mass.ensure(sizeof(double) * S), "hipMalloc");
-    HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
-    HIP_TRY(hipMemcpy(M->md_inv_mass.p, inv.data(), sizeof(double) * S, hipMemcpyHostToDevice), "hipMemcpy");
-    M->md_masses.assign(mass_host, mass_host + S);
-  }
-  HIP_TRY(mtp::md_kick(n_atoms, species_dev, S, M->md_inv_mass.as<double>(), pos_dev, vel_dev, forces_dev, dt_fs,
+  const int rc = upload_masses(M, mass_host, "mtp_md_kick", s);
+  if (rc != MTP_OK) return rc;
+  HIP_TRY(mtp::md_kick(n_atoms, species_dev, M->S, M->md_inv_mass.as<double>(), pos_dev, vel_dev, forces_dev, dt_fs,
                        drift, s),
           "kick");
+  return MTP_OK;
+}
+
+int mtp_fire_step(mtp_model* M, int32_t n_configs, const int64_t* offsets_dev, int64_t n_atoms,
+                  const int32_t* species_dev, double* pos_dev, double* vel_dev, const double* forces_dev,
+                  const double* mass_host, double* state_dev, const double* params_host, void* stream) {
+  g_err.clear();
+  if (!M || n_configs < 0 || n_atoms < 0 || !mass_host || !params_host) return fail(MTP_E_ARG, "mtp_fire_step: bad argument");
+  if (n_configs > 0 && (!offsets_dev || !state_dev || (n_atoms > 0 && (!species_dev || !pos_dev || !vel_dev ||
+                                                                       !forces_dev))))
+    return fail(MTP_E_ARG, "mtp_fire_step: null array");
+  mtp::FireParams fp;
+  fp.dt_max = params_host[0];
+  fp.n_min = params_host[1];
+  fp.f_inc = params_host[2];
+  fp.f_dec = params_host[3];
+  fp.alpha_start = params_host[4];
+  fp.f_alpha = params_host[5];
+  if (!(fp.dt_max > 0 && fp.n_min >= 0 && fp.f_inc >= 1 && fp.f_dec > 0 && fp.f_dec <= 1 && fp.alpha_start >= 0 &&
+        fp.alpha_start <= 1 && fp.f_alpha > 0 && fp.f_alpha <= 1))
+    return fail(MTP_E_ARG, "mtp_fire_step: parameters out of range");
+  HIP_TRY(hipSetDevice(M->device), "hipSetDevice");
+  hipStream_t s = (hipStream_t)stream;
+  const int rc = upload_masses(M, mass_host, "mtp_fire_step", s);
+  if (rc != MTP_OK) return rc;
+  HIP_TRY(mtp::md_fire(n_configs, n_atoms, offsets_dev, species_dev, M->S, M->md_inv_mass.as<double>(), pos_dev,
+                       vel_dev, forces_dev, state_dev, fp, s),
+          "FIRE step");
   return MTP_OK;
 }
 

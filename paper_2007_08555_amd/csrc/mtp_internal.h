@@ -188,6 +188,14 @@ hipError_t maxvol_swap(int K, int m, double* C, const MaxvolPick* pick, double* 
 
 // Velocity Verlet: v += (dt/2) F/m (masses per species, 1/m in amu^-1 on
 // the device); with drift also x += dt v.
+// FIRE relaxation step per configuration (md.hip); state [n_cfg][4].
+struct FireParams {
+  double dt_max, f_inc, f_dec, alpha_start, f_alpha;
+  double n_min;
+};
+hipError_t md_fire(int n_cfg, int64_t n_atoms, const int64_t* offsets, const int32_t* species, int S,
+                   const double* inv_mass, double* pos, double* vel, const double* F, double* state,
+                   const FireParams& fp, hipStream_t s);
 hipError_t md_kick(int64_t n, const int32_t* species, int S, const double* inv_mass, double* pos, double* vel,
                    const double* F, double dt, int drift, hipStream_t s);
 
