@@ -334,6 +334,17 @@ int mtp_fire_step(mtp_model* model, int32_t n_configs, const int64_t* atom_offse
                   const int32_t* species_dev, double* pos_dev, double* vel_dev, const double* forces_dev,
                   const double* mass_host, double* state_dev, const double* params_host, void* stream);
 
+/*
+ * Kinetic energy of every configuration for the MD of section 2.3:
+ * ekin_dev[k] = sum over its atoms of m |v|^2 / 2 in eV (device [n_configs]
+ * FP64), summed in a fixed order.  atom_offsets [n_configs + 1] int64,
+ * species [n_atoms] int32, vel [n_atoms][3] FP64 (Angstrom/fs), mass_host [S]
+ * amu.  Asynchronous on `stream` except for new masses, as mtp_md_kick.
+ */
+int mtp_kinetic_energy(mtp_model* model, int32_t n_configs, const int64_t* atom_offsets_dev, int64_t n_atoms,
+                       const int32_t* species_dev, const double* vel_dev, const double* mass_host, double* ekin_dev,
+                       void* stream);
+
 /* Counters and device timings of the last mtp_eval on a model. */
 typedef struct {
   int64_t n_atoms;          /* atoms of the last batch */

@@ -63,6 +63,7 @@ _SIGNATURES = {
     "mtp_theta_rows": (ctypes.c_int, [_P, ctypes.POINTER(mtp_batch), ctypes.c_int, _P, _P]),
     "mtp_set_active_set_theta": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P]),
     "mtp_grade_theta": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, _P, _P]),
+    "mtp_kinetic_energy": (ctypes.c_int, [_P, ctypes.c_int32, _P, ctypes.c_int64, _P, _P, _P, _P, _P]),
     "mtp_fire_step": (ctypes.c_int, [_P, ctypes.c_int32, _P, ctypes.c_int64, _P, _P, _P, _P, _P, _P, _P, _P]),
     "mtp_maxvol_theta": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, _P, _P, ctypes.c_int, ctypes.c_double,
                                         ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), _P]),

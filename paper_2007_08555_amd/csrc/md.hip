@@ -112,6 +112,35 @@ __global__ void __launch_bounds__(kMDBlock) fire_kernel(int n_cfg, int64_t n_ato
   }
 }
 
+// Kinetic energy sum_i m_i |v_i|^2 / 2 (eV) of every configuration, one
+// workgroup each, summed in a fixed order (per thread strided, then a tree).
+__global__ void __launch_bounds__(kMDBlock) kinetic_kernel(int n_cfg, int64_t n_atoms,
+                                                           const int64_t* __restrict__ offsets,
+                                                           const int32_t* __restrict__ species, int S,
+                                                           const double* __restrict__ inv_mass,
+                                                           const double* __restrict__ vel, double* ekin) {
+  __shared__ double red[kMDBlock];
+  const int k = blockIdx.x;
+  const int t = threadIdx.x;
+  int64_t a0 = offsets[k], a1 = offsets[k + 1];
+  a0 = a0 < 0 ? 0 : (a0 > n_atoms ? n_atoms : a0);
+  a1 = a1 < a0 ? a0 : (a1 > n_atoms ? n_atoms : a1);
+  double e = 0.0;
+  for (int64_t i = a0 + t; i < a1; i += blockDim.x) {
+    int z = species[i];
+    z = z < 0 ? 0 : (z >= S ? S - 1 : z);
+    const double vx = vel[3 * i], vy = vel[3 * i + 1], vz = vel[3 * i + 2];
+    e += 0.5 / (kAccel * inv_mass[z]) * (vx * vx + vy * vy + vz * vz);
+  }
+  red[t] = e;
+  __syncthreads();
+  for (int h = kMDBlock / 2; h > 0; h >>= 1) {
+    if (t < h) red[t] += red[t + h];
+    __syncthreads();
+  }
+  if (t == 0) ekin[k] = red[0];
+}
+
 }  // namespace
 
 hipError_t md_kick(int64_t n, const int32_t* species, int S, const double* inv_mass, double* pos, double* vel,
@@ -119,6 +148,14 @@ hipError_t md_kick(int64_t n, const int32_t* species, int S, const double* inv_m
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(kick_kernel, dim3((unsigned)((n + kMDBlock - 1) / kMDBlock)), dim3(kMDBlock), 0, s, n, species,
                      S, inv_mass, pos, vel, F, dt, drift);
+  return hipGetLastError();
+}
+
+hipError_t md_kinetic(int n_cfg, int64_t n_atoms, const int64_t* offsets, const int32_t* species, int S,
+                      const double* inv_mass, const double* vel, double* ekin, hipStream_t s) {
+  if (n_cfg == 0) return hipSuccess;
+  hipLaunchKernelGGL(kinetic_kernel, dim3(n_cfg), dim3(kMDBlock), 0, s, n_cfg, n_atoms, offsets, species, S, inv_mass,
+                     vel, ekin);
   return hipGetLastError();
 }
 

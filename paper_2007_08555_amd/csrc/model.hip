@@ -783,6 +783,23 @@ int mtp_md_kick(mtp_model* M, int64_t n_atoms, const int32_t* species_dev, doubl
   return MTP_OK;
 }
 
+int mtp_kinetic_energy(mtp_model* M, int32_t n_configs, const int64_t* offsets_dev, int64_t n_atoms,
+                       const int32_t* species_dev, const double* vel_dev, const double* mass_host, double* ekin_dev,
+                       void* stream) {
+  g_err.clear();
+  if (!M || n_configs < 0 || n_atoms < 0 || !mass_host) return fail(MTP_E_ARG, "mtp_kinetic_energy: bad argument");
+  if (n_configs > 0 && (!offsets_dev || !ekin_dev || (n_atoms > 0 && (!species_dev || !vel_dev))))
+    return fail(MTP_E_ARG, "mtp_kinetic_energy: null array");
+  HIP_TRY(hipSetDevice(M->device), "hipSetDevice");
+  hipStream_t s = (hipStream_t)stream;
+  const int rc = upload_masses(M, mass_host, "mtp_kinetic_energy", s);
+  if (rc != MTP_OK) return rc;
+  HIP_TRY(mtp::md_kinetic(n_configs, n_atoms, offsets_dev, species_dev, M->S, M->md_inv_mass.as<double>(), vel_dev,
+                          ekin_dev, s),
+          "kinetic energy");
+  return MTP_OK;
+}
+
 int mtp_fire_step(mtp_model* M, int32_t n_configs, const int64_t* offsets_dev, int64_t n_atoms,
                   const int32_t* species_dev, double* pos_dev, double* vel_dev, const double* forces_dev,
                   const double* mass_host, double* state_dev, const double* params_host, void* stream) {

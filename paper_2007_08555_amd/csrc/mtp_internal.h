@@ -188,6 +188,9 @@ hipError_t maxvol_swap(int K, int m, double* C, const MaxvolPick* pick, double* 
 
 // Velocity Verlet: v += (dt/2) F/m (masses per species, 1/m in amu^-1 on
 // the device); with drift also x += dt v.
+// Kinetic energy per configuration (md.hip), eV.
+hipError_t md_kinetic(int n_cfg, int64_t n_atoms, const int64_t* offsets, const int32_t* species, int S,
+                      const double* inv_mass, const double* vel, double* ekin, hipStream_t s);
 // FIRE relaxation step per configuration (md.hip); state [n_cfg][4].
 struct FireParams {
   double dt_max, f_inc, f_dec, alpha_start, f_alpha;

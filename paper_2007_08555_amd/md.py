@@ -35,6 +35,19 @@ def kick(P: Potential, batch: Batch, vel, forces, masses, dt, drift, stream=None
           "mtp_md_kick")
 
 
+def kinetic_energy(P: Potential, batch: Batch, vel, masses, stream=None):
+    """Kinetic energy [K] (eV) of every configuration (mtp_kinetic_energy)."""
+    m = np.ascontiguousarray(np.asarray(masses, dtype=np.float64))
+    if m.size != P.n_species:
+        raise ValueError("one mass per species")
+    out = torch.empty(batch.n_configs, dtype=torch.float64, device=vel.device)
+    check(lib().mtp_kinetic_energy(P._h, batch.n_configs, batch.atom_offsets.data_ptr(), batch.n_atoms,
+                                   batch.species.data_ptr(), vel.data_ptr(), m.ctypes.data_as(ctypes.c_void_p),
+                                   out.data_ptr(), _stream(stream)),
+          "mtp_kinetic_energy")
+    return out
+
+
 def run(P: Potential, batch: Batch, vel, masses, dt=1.0, n_steps=100, precision="fp64", skin=0.3,
         gamma_select=None, gamma_break=None):
     """n_steps of velocity Verlet on `batch` (positions updated in place) with
@@ -45,12 +58,7 @@ def run(P: Potential, batch: Batch, vel, masses, dt=1.0, n_steps=100, precision=
     "stopped_at": the step at which gamma exceeded gamma_break, or None}."""
     P.set_skin(skin)
     grade = gamma_select is not None or gamma_break is not None
-    mass_atom = torch.as_tensor(np.asarray(masses, dtype=np.float64), device=vel.device)[batch.species.long()]
-    cfg_of_atom = torch.repeat_interleave(torch.arange(batch.n_configs, device=vel.device),
-                                          batch.atom_offsets.diff())
-    # 1/2 m v^2 in eV: amu A^2 / fs^2 = 103.6427 eV
-    ekin = lambda: torch.zeros(batch.n_configs, dtype=torch.float64, device=vel.device).index_add_(
-        0, cfg_of_atom, 0.5 * 103.642696562 * mass_atom * (vel * vel).sum(dim=1))
+    ekin = lambda: kinetic_energy(P, batch, vel, masses)
     energies, kinetic, gammas, selected, stopped = [], [], [], [], None
 
     def evaluate(step):

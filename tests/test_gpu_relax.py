@@ -98,3 +98,22 @@ def test_relax_driver_follows_the_oracle():
     assert res["steps"] == 4
     np.testing.assert_allclose(res["energy"][:4, 0], E, rtol=1e-12)
     np.testing.assert_allclose(B.pos.cpu().numpy(), x, rtol=0, atol=1e-10)
+
+
+def test_kinetic_energy_per_configuration():
+    """mtp_kinetic_energy against sum m |v|^2 / 2 in eV per configuration
+    (1 amu A^2/fs^2 = 103.642696562 eV), empty configurations included."""
+    import torch
+    from paper_2007_08555_amd import Batch, Potential, md
+    P = Potential(pot_path("lev12_s2"))
+    b = _batch_arrays([7, 0, 300, 1], seed=9)
+    B = Batch.from_arrays(b)
+    v = np.random.default_rng(10).normal(0, 0.02, (b["n_atoms"].sum(), 3))
+    masses = np.array([26.98, 58.69])
+    e = md.kinetic_energy(P, B, torch.as_tensor(v, device="cuda").contiguous(), masses).cpu().numpy()
+    off = b["atom_offsets"]
+    m = masses[b["species"]]
+    ref = np.array([0.5 * np.sum(m[off[k]:off[k + 1], None] * v[off[k]:off[k + 1]] ** 2) / orx.EV_PER_A_AMU_IN_A_PER_FS2
+                    for k in range(len(b["n_atoms"]))])
+    np.testing.assert_allclose(e, ref, rtol=1e-13)
+    assert e[1] == 0.0
