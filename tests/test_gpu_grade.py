@@ -81,15 +81,19 @@ def test_singular_active_set_is_rejected(setup):
         P2.grade_from_b(A[:2])
 
 
-def test_theta_rows_match_the_oracle():
+@pytest.mark.parametrize("name,n_species,step", [("lev12_s2", 2, 6), ("lev16_s3", 3, 17)])
+def test_theta_rows_match_the_oracle(name, n_species, step):
     """Rows dE_k/dtheta of the nonlinear grade (mtp_theta_rows) against the
-    oracle's complex-step rows: every xi column and a sample of c columns."""
+    oracle's complex-step rows: every xi column and a sample of c columns
+    (every species pair at level 16 with three species)."""
     from paper_2007_08555_amd import Batch, Potential
-    P = Potential(pot_path("lev12_s2"))
-    pot = read_potential(pot_path("lev12_s2"))
-    batch = synth.mixed_batch(seed=21, n_configs=4, n_min=8, n_max=20, n_species_model=2)
+    P = Potential(pot_path(name))
+    pot = read_potential(pot_path(name))
+    batch = synth.mixed_batch(seed=21, n_configs=4, n_min=8, n_max=20, n_species_model=n_species)
     m, nc = len(pot["xi"]), pot["c"].size
-    idx = list(range(m)) + list(range(m, m + nc, 6)) + [m + nc - 1]
+    # every xi column at level 12; at level 16 a few (the xi part is b, checked
+    # against the oracle by the grade tests above)
+    idx = (list(range(m)) if m <= 40 else [0, m // 2, m - 1]) + list(range(m, m + nc, step)) + [m + nc - 1]
     log(f"[theta rows] configs 4 atoms {int(batch['n_atoms'].sum())} columns {len(idx)} of {m + nc}")
     R = P.theta_rows(Batch.from_arrays(batch), precision="fp64").cpu().numpy()
     assert R.shape == (4, m + nc)
@@ -98,7 +102,8 @@ def test_theta_rows_match_the_oracle():
     err = np.abs(R[:, idx] - Ro) / scale
     log(f"[theta rows] max error relative to each column's scale {err.max():.3e}")
     assert err.max() <= 1e-10
-    assert np.abs(Ro[:, m:]).max() > 0
+    c_cols = [t for t, q in enumerate(idx) if q >= m]
+    assert np.abs(Ro[:, c_cols]).max() > 0
     R32 = P.theta_rows(Batch.from_arrays(batch), precision="fp32").cpu().numpy()
     err32 = np.abs(R32[:, idx] - Ro) / scale
     log(f"[theta rows] FP32 kernels: {err32.max():.3e}")
