@@ -769,11 +769,12 @@ __device__ inline void small_candidates(const CfgInfo& c, const SmallAtoms& sa, 
   }
 }
 
-// Two-phase list of one atom for free clusters and nearest cells: phase A
-// walks all atoms j with the cheap test only (FP64 distance of a cluster, or
-// the FP32 nearest-image box and distance) and records the candidates j in
-// the atom's LDS row; phase B tests only the candidates with the exact FP64 pair vector and
-// rewrites the row in place (kept entries never outrun the candidates).
+// Two-phase list of one atom for nearest cells: phase A walks all atoms j
+// with the cheap test only (the FP32 nearest-image box and distance) and
+// records the candidates j in the atom's LDS row; phase B tests only the
+// candidates with the exact FP64 pair vector and rewrites the row in place
+// (kept entries never outrun the candidates).  A free cluster's test is the
+// exact FP64 distance, so its walk hands the neighbours to visit directly.
 // Returns the candidate count (> K means the row overflowed).
 template <typename Visit>
 __device__ inline int small_two_phase(const CfgInfo& c, const SmallAtoms& sa, int n, int li, double rc2, int K,
@@ -781,21 +782,16 @@ __device__ inline int small_two_phase(const CfgInfo& c, const SmallAtoms& sa, in
   const double4 pi = sa.x[li];
   int nc = 0;
   if (!c.pbc) {
+    // a cluster's cheap test is already the exact one: the candidates are the
+    // neighbours, handed to visit in order (no second phase)
     lds_sweep(sa.x, n, [&](int lj, double4 pj) {
       const double dx = pj.x - pi.x, dy = pj.y - pi.y, dz = pj.z - pi.z;
       const double r2 = dx * dx + dy * dy + dz * dz;
       if ((lj != li) & (r2 < rc2)) {
-        if (nc < K) row[nc] = (uint8_t)lj;
+        visit.pair(lj, dx, dy, dz, r2);
         ++nc;
       }
     });
-    const int m = nc < K ? nc : K;
-    for (int q = 0; q < m; ++q) {
-      const int lj = row[q];
-      const double4 pj = sa.x[lj];
-      const double dx = pj.x - pi.x, dy = pj.y - pi.y, dz = pj.z - pi.z;
-      visit.pair(lj, dx, dy, dz, dx * dx + dy * dy + dz * dz);
-    }
     return nc;
   }
   const float w0 = (float)c.w[0] + 1e-3f, w1 = (float)c.w[1] + 1e-3f, w2 = (float)c.w[2] + 1e-3f;
