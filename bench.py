@@ -118,6 +118,68 @@ def training_extras(P, pot_path, precision, ref_path=None):
     return res
 
 
+def active_learning_extras(P, batch):
+    """The selection and relaxation rows on the benchmark batch: MaxVol over
+    its descriptor rows b (mtp_maxvol), the rows dE/dtheta over xi and c
+    (mtp_theta_rows), MaxVol and the grade over those rows restricted to
+    independent columns (mtp_maxvol_theta, mtp_grade_theta; the columns are
+    chosen on the host by pivoted QR, outside the timings), and one FIRE step
+    of every configuration (mtp_fire_step).  Each entry reports its error
+    instead of a time if the call fails."""
+    import numpy as np
+    import scipy.linalg
+    import torch
+
+    from paper_2007_08555_amd import Batch, md
+    B = Batch.from_arrays(batch, "cuda:0")
+    K, N = B.n_configs, B.n_atoms
+    res = {"workload": f"the benchmark batch: {K} configurations, {N} atoms, level {P.level}, FP64"}
+
+    def timed(fn, reps=3):
+        out = fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            out = fn()
+        torch.cuda.synchronize()
+        return out, (time.perf_counter() - t0) / reps * 1e3
+
+    out = P.eval(B, precision="fp64", forces=True, virial=False, b=True)
+    try:
+        (_rows, swaps), ms = timed(lambda: P.maxvol(out["b"]), reps=1)
+        res["maxvol_b"] = {"ms_per_call": ms, "swaps": swaps, "pool": [K, P.m]}
+    except Exception as e:   # noqa: BLE001 - reported in the JSON line
+        res["maxvol_b"] = {"error": str(e)}
+    try:
+        R, ms = timed(lambda: P.theta_rows(B))
+        res["theta_rows"] = {"ms_per_call": ms, "configs_per_s": K / ms * 1e3, "atom_evals_per_s": N / ms * 1e3,
+                             "columns": P.m + P.n_c}
+        Rh = R.cpu().numpy()
+        Rs = Rh / np.maximum(np.abs(Rh).max(axis=0), 1e-300)
+        _q, rr, piv = scipy.linalg.qr(Rs, pivoting=True, mode="economic")
+        rank = int((np.abs(np.diag(rr)) > 1e-10 * abs(rr[0, 0])).sum())
+        cols = torch.as_tensor(np.sort(piv[:rank]), device=R.device)
+        Rc = R[:, cols].contiguous()
+        (sel, swaps_t), ms = timed(lambda: P.maxvol_theta(Rc), reps=1)
+        res["maxvol_theta"] = {"ms_per_call": ms, "swaps": swaps_t, "pool": [K, rank]}
+        P.set_active_set_theta(Rc[sel.long()])
+        _, ms = timed(lambda: P.grade_theta(Rc))
+        res["grade_theta"] = {"ms_per_call": ms, "configs_per_s": K / ms * 1e3}
+    except Exception as e:   # noqa: BLE001
+        res["theta_error"] = str(e)
+    try:
+        vel = torch.zeros((N, 3), dtype=torch.float64, device=B.pos.device)
+        state = md.fire_state(B)
+        pos0 = B.pos.clone()
+        masses = np.full(P.n_species, 50.0)
+        _, ms = timed(lambda: md.fire_step(P, B, vel, out["forces"], masses, state), reps=10)
+        B.pos.copy_(pos0)
+        res["fire_step"] = {"ms_per_call": ms, "atoms_per_s": N / ms * 1e3}
+    except Exception as e:   # noqa: BLE001
+        res["fire_step"] = {"error": str(e)}
+    return res
+
+
 def precision_study(stream):
     """The 256 000-atom disordered fcc alloy (40^3 cells, a = 3.6 A, sigma =
     0.2 A, three species) at level 16: throughput of FP64, FP32 and FP32
@@ -461,6 +523,8 @@ def main():
         log(f"precision study: {line['precision_study']}")
         line["training"] = training_extras(P, pot_path, a.precision)
         log(f"training: {line['training']}")
+        line["active_learning"] = active_learning_extras(P, batch)
+        log(f"active learning and relaxation: {line['active_learning']}")
         line["training_level20"] = training_level20()
         log(f"training, level 20: {line['training_level20']}")
         line["cpu_baseline"] = cpu_baseline(batch, pot_path, a.cpu_seconds)
