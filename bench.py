@@ -15,7 +15,7 @@ from 3, level-16 MTP with N_Q = 8, R_cut = 5 A (seeded synthetic data; the
 calibrated potential tests/golden/potentials/lev16_s3.mtp).
 
 Prints one JSON line.  Besides the contract fields it reports the roofline
-of the evaluation kernels, the plain one-configuration-per-call path on the
+of the evaluation kernels, the plain one-configuration-per-launch path on the
 same configurations, the 16 000-atom bcc box as 100 MD-style steps, the
 256 000-atom alloy in FP64, FP32 and compensated FP32, the training workload
 (loss gradient and normal equations), and the FP64 CPU oracle timed on a
@@ -180,6 +180,62 @@ def active_learning_extras(P, batch):
     return res
 
 
+def plain_path(P, batch, precision, stream):
+    """One configuration per launch sequence: mtp_eval_async on each of the
+    batch's configurations in turn (views into the resident batch arrays and
+    output buffers, no host synchronisation between them), timed over the
+    whole batch between two synchronisations.  The results are compared with
+    the batched call's."""
+    import ctypes
+
+    import numpy as np
+    import torch
+
+    from paper_2007_08555_amd import Batch, _lib
+    B = Batch.from_arrays(batch, "cuda:0")
+    K = B.n_configs
+    offs = batch["atom_offsets"]
+    ref = P.eval(B, precision=precision, b=False, stream=stream)     # sizes the workspace for every configuration
+    out = P.outputs(B, forces=True, virial=True)
+    one = torch.zeros((K, 2), dtype=torch.int64, device="cuda:0")
+    one[:, 1] = torch.as_tensor(batch["n_atoms"], device="cuda:0")
+    calls = []
+    for k in range(K):
+        a, n = int(offs[k]), int(offs[k + 1] - offs[k])
+        bs = _lib.mtp_batch(1, n, one[k].data_ptr(), B.pos.data_ptr() + 24 * a, B.species.data_ptr() + 4 * a,
+                            B.cell.data_ptr() + 72 * k, B.pbc.data_ptr() + k)
+        o = _lib.mtp_out(out["energy"].data_ptr() + 8 * k, out["forces"].data_ptr() + 24 * a,
+                         out["virial"].data_ptr() + 72 * k, None, None)
+        calls.append((bs, o))
+    fn, h, prec, sp = _lib.lib().mtp_eval_async, P._h, _lib.PRECISIONS[precision], ctypes.c_void_p(stream.cuda_stream)
+
+    def run():
+        for bs, o in calls:
+            rc = fn(h, ctypes.byref(bs), ctypes.byref(o), prec, sp)
+            if rc:
+                _lib.check(rc, "mtp_eval_async")
+
+    run()
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        run()
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    P.status(stream)
+    tp = float(np.median(times))
+    n_atoms = int(batch["n_atoms"].sum())
+    dE = float((out["energy"] - ref["energy"]).abs().max())
+    dF = float((out["forces"] - ref["forces"]).abs().max())
+    return {"value": n_atoms / tp, "unit": "atom-evals/s", "configs": K, "ms_per_batch": tp * 1e3,
+            "ms_per_batch_all": [t * 1e3 for t in times],
+            "max_abs_diff_vs_batched": {"energy_eV": dE, "forces_eV_per_A": dF},
+            "note": "every configuration of the batch on its own: one mtp_eval_async launch sequence per "
+                    "configuration (neighbour lists, evaluation kernels, force gather, sums) on one stream, "
+                    "one synchronisation at the end; median of 3 passes over the batch"}
+
+
 def precision_study(stream):
     """The 256 000-atom disordered fcc alloy (40^3 cells, a = 3.6 A, sigma =
     0.2 A, three species) at level 16: throughput of FP64, FP32 and FP32
@@ -213,6 +269,41 @@ def precision_study(stream):
             "site_max_eV": float(np.abs(outs[p]["site"] - r64["site"]).max()),
             "force_max_eV_per_A": float(np.abs(outs[p]["forces"] - r64["forces"]).max()),
             "largest_force_eV_per_A": float(np.abs(r64["forces"]).max())}
+        res[p]["vs_fp64"]["force_rel"] = res[p]["vs_fp64"]["force_max_eV_per_A"] / \
+            res[p]["vs_fp64"]["largest_force_eV_per_A"]
+    return res
+
+
+def fp32_accuracy(P, batch, stream):
+    """Errors of the FP32 and compensated FP32 paths against the FP64 path
+    (which the tests pin to the oracle) over every configuration of a batch:
+    energy per atom, absolute force error and the force error relative to
+    each configuration's largest force, virial per atom."""
+    import numpy as np
+
+    from paper_2007_08555_amd import Batch
+    B = Batch.from_arrays(batch, "cuda:0")
+    offs = batch["atom_offsets"]
+    n = np.maximum(batch["n_atoms"], 1).astype(float)
+    outs = {p: {k: v.cpu().numpy() for k, v in P.eval(B, precision=p, stream=stream).items()}
+            for p in ("fp64", "fp32", "fp32c")}
+    r64 = outs["fp64"]
+    cfg_of_atom = np.repeat(np.arange(len(n)), batch["n_atoms"])
+    fmax_cfg = np.zeros(len(n))
+    np.maximum.at(fmax_cfg, cfg_of_atom, np.abs(r64["forces"]).max(axis=1))
+    res = {}
+    for p in ("fp32", "fp32c"):
+        dF = np.abs(outs[p]["forces"] - r64["forces"]).max(axis=1)
+        dF_cfg = np.zeros(len(n))
+        np.maximum.at(dF_cfg, cfg_of_atom, dF)
+        res[p] = {"energy_per_atom_eV": float(np.max(np.abs(outs[p]["energy"] - r64["energy"]) / n)),
+                  "force_max_eV_per_A": float(dF.max()),
+                  "force_rel": float(np.max(dF_cfg / np.maximum(fmax_cfg, 1e-300))),
+                  "virial_per_atom_eV": float(np.max(np.abs(outs[p]["virial"] - r64["virial"]).reshape(len(n), -1)
+                                                     .max(axis=1) / n)),
+                  "configs_within_1e-5_eV_per_A": int((dF_cfg <= 1e-5).sum()),
+                  "configs": int(len(n))}
+    res["largest_force_eV_per_A"] = float(np.abs(r64["forces"]).max())
     return res
 
 
@@ -304,7 +395,6 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "fp32c"])
     ap.add_argument("--configs", type=int, default=4096)
-    ap.add_argument("--plain-configs", type=int, default=256)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-extras", action="store_true", help="skip plain path, bcc box and CPU baseline")
     ap.add_argument("--no-graph", action="store_true", help="time eager calls instead of HIP-graph replays")
@@ -446,22 +536,12 @@ def main():
             "replay_ms_per_step": replay_ms}
 
     if not a.no_extras:
-        # the plain path: one configuration per call, same configurations
-        nplain = min(a.plain_configs, a.configs)
-        sub = [Batch.from_arrays(synth.subset(batch, [k]), "cuda:0") for k in range(nplain)]
-        for s_ in sub[:8]:
-            P.eval(s_, precision=a.precision, stream=stream)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for s_ in sub:
-            P.eval(s_, precision=a.precision, stream=stream)
-        torch.cuda.synchronize()
-        tp = time.perf_counter() - t0
-        atoms_p = int(batch["n_atoms"][:nplain].sum())
-        line["plain"] = {"value": atoms_p / tp, "unit": "atom-evals/s", "configs": nplain,
-                         "note": "one mtp_eval call per configuration on the first configurations of the batch"}
-        line["batched_over_plain"] = value / (atoms_p / tp)
-        log(f"plain: {atoms_p / tp:.4g} atom-evals/s")
+        # the plain path: every configuration of the batch on its own, one
+        # mtp_eval_async launch sequence per configuration on the same stream,
+        # one synchronisation at the end (same precision, same outputs)
+        line["plain"] = plain_path(P, batch, a.precision, stream)
+        line["batched_over_plain"] = value / line["plain"]["value"]
+        log(f"plain: {line['plain']}")
         # the 16 000-atom bcc box (two species) as 100 MD-style steps: before
         # each step after the first every coordinate moves by N(0, 0.002^2) A,
         # then neighbour lists, E, F and virial; FP32 (the workload's precision)
@@ -519,6 +599,11 @@ def main():
             log(f"bcc16000 {prec}, skin 0.3 A: {nb / tb:.4g} atom-evals/s, {tb * 1e3:.3f} ms/step, "
                 f"lists reused on {reused} of 100 steps")
             del P3
+        line["fp32_accuracy"] = {"batched": fp32_accuracy(P, batch, stream)}
+        P2b = Potential(os.path.join(ROOT, "tests", "golden", "potentials", "lev16_s2.mtp"), device=0)
+        line["fp32_accuracy"]["bcc16000"] = fp32_accuracy(P2b, synth.bcc_alloy(seed=0), stream)
+        del P2b
+        log(f"fp32 accuracy: {line['fp32_accuracy']}")
         line["precision_study"] = precision_study(stream)
         log(f"precision study: {line['precision_study']}")
         line["training"] = training_extras(P, pot_path, a.precision)

@@ -261,9 +261,11 @@ int mtp_autotune(mtp_model* model, const mtp_batch* batch, int precision, int re
 /*
  * Device-side counters of the last mtp_eval on this model: pairs closer than
  * R_min (the radial polynomial is then evaluated outside [R_min, R_cut]) and
- * neighbour-list inconsistencies (always 0 unless memory was corrupted).
- * Returns MTP_E_ARG or MTP_E_CAPACITY when the last (asynchronous)
- * evaluation met invalid input or exceeded the neighbour capacity.
+ * neighbour-list inconsistencies (pairs whose reverse pair was not found;
+ * always 0 unless memory was corrupted).  Returns MTP_E_ARG or
+ * MTP_E_CAPACITY when the last (asynchronous) evaluation met invalid input
+ * or exceeded the neighbour capacity, and MTP_E_STATE when its lists were
+ * inconsistent (its forces are then wrong); mtp_eval returns the same codes.
  * Synchronises `stream`.
  */
 int mtp_status(mtp_model* model, void* stream, int64_t* n_below_rmin, int64_t* n_list_errors);

@@ -492,12 +492,15 @@ int run_eval(mtp_model* M, const mtp_batch* bt, const mtp_out* out, int precisio
     Status st{};
     HIP_TRY(hipMemcpyAsync(&st, M->status.p, sizeof(Status), hipMemcpyDeviceToHost, s), "hipMemcpyAsync");
     HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
-    if (st.bad_offsets) return fail(MTP_E_ARG, "atom_offsets must be non-decreasing from 0 to n_atoms");
-    if (st.bad_species) return fail(MTP_E_ARG, "species index outside [0, species_count)");
-    if (st.overflow) {
+    if (st.overflow && !st.bad_offsets && !st.bad_species) {
       if (st.max_count > 4096) return fail(MTP_E_CAPACITY, "more than 4096 neighbours of one atom");
       M->K = (int)((st.max_count + 7) / 8 * 8);
       continue;
+    }
+    {
+      const char* msg = "";
+      const int code = status_code(st, &msg);
+      if (code != MTP_OK) return fail(code, msg);
     }
     M->lists_reused = reuse ? 1 : 0;
     if (use_skin && !reuse) {
@@ -1157,9 +1160,9 @@ int mtp_status(mtp_model* M, void* stream, int64_t* n_below_rmin, int64_t* n_lis
   if (n_below_rmin) *n_below_rmin = (int64_t)st.below_rmin;
   if (n_list_errors) *n_list_errors = (int64_t)st.list_errors;
   // conditions an asynchronous evaluation could only record
-  if (st.bad_offsets) return fail(MTP_E_ARG, "last evaluation: atom_offsets must be non-decreasing from 0 to n_atoms");
-  if (st.bad_species) return fail(MTP_E_ARG, "last evaluation: species index outside [0, species_count)");
-  if (st.overflow) return fail(MTP_E_CAPACITY, "last evaluation: an atom had more neighbours than the workspace holds");
+  const char* msg = "";
+  const int code = mtp::status_code(st, &msg);
+  if (code != MTP_OK) return fail(code, std::string("last evaluation: ") + msg);
   return MTP_OK;
 }
 

@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "status.h"
+
 namespace mtp {
 
 // Per-configuration geometry prepared on the device before the neighbour search.
@@ -18,18 +20,6 @@ struct CfgInfo {
   int64_t bin0;     // first bin of this config in the global bin arrays
 };
 
-// Device counters read by mtp_status and by mtp_eval after its kernels.
-struct Status {
-  unsigned long long below_rmin;
-  unsigned long long list_errors;
-  unsigned long long max_count;   // largest neighbour count of the last search
-  unsigned long long bad_offsets; // atom_offsets not monotone from 0 to n_atoms
-  unsigned long long bad_species; // species index outside [0, n_species)
-  unsigned long long n_pairs;     // total neighbour pairs of the last search
-  unsigned long long overflow;    // atoms with more neighbours than the ELL capacity
-  unsigned long long n_binned;    // atoms of binned configurations (entries of NbrArgs::binned)
-  unsigned long long n_large;     // atoms of configurations above the small-search size (NbrArgs::large)
-};
 
 struct NbrArgs {
   int n_cfg;

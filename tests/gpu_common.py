@@ -47,6 +47,8 @@ def errors(batch, g, o):
         "force": float(np.max(np.abs(g["forces"] - o["forces"]))) if len(o["forces"]) else 0.0,
         "virial": float(np.max(np.abs(g["virial"] - o["virial"]))) if len(o["virial"]) else 0.0,
     }
+    dw = np.abs(g["virial"] - o["virial"]).reshape(len(n), -1).max(axis=1) if len(n) else np.zeros(0)
+    rep["virial_per_atom"] = float(np.max(dw / n)) if len(n) else 0.0
     scale_b = np.maximum(np.abs(o["b"]).max(axis=0), 1e-300) if o["b"].size else 1.0
     rep["b_rel"] = float(np.max(np.abs(g["b"] - o["b"]) / scale_b)) if o["b"].size else 0.0
     rep["force_scale"] = float(np.abs(o["forces"]).max()) if len(o["forces"]) else 0.0

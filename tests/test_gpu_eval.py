@@ -12,12 +12,32 @@ pytestmark = pytest.mark.gpu
 # FP64 kernels against the FP64 oracle: only summation order differs.
 TOL64 = {"energy_per_atom": 1e-11, "site": 1e-11, "force": 1e-10, "virial": 1e-9, "b_rel": 1e-11}
 # FP32 kernels on the calibrated potentials (site energies O(1) eV, forces up
-# to ~20 eV/A): energy per atom within 1e-6 eV; forces within 1e-5 of the
-# largest force.  A force is a sum of per-pair gradients that cancel, each
-# carrying a relative FP32 rounding error of tens of unit roundoffs
-# (2^-24 ~ 6e-8), which bounds FP32 forces near 1e-6..1e-5 relative.  The
-# absolute 1e-5 eV/A bound is met by the FP64 path.
-TOL32 = {"energy_per_atom": 1e-6, "force_rel": 1e-5}
+# to ~20 eV/A) are held to the stated absolute bounds: energy per atom
+# 1e-6 eV and force 1e-5 eV/A, plus bounds derived from them for the other
+# outputs: the virial per atom within R_cut x 1e-5 eV/A = 5e-5 eV (a virial
+# term is a pair gradient times a pair vector of length below R_cut) and the
+# descriptor sums b within 1e-5 relative.  Where FP32 arithmetic cannot meet
+# them the test records an expected failure with the measured errors (a force
+# is a sum of per-pair gradients that cancel, each carrying a relative FP32
+# rounding of tens of unit roundoffs); a guard at FP32's own rounding level
+# (forces within 1e-5 of the largest force, every site energy within 1e-5 eV)
+# is asserted in every case.
+ABS32 = {"energy_per_atom": 1e-6, "force": 1e-5, "virial_per_atom": 5e-5, "b_rel": 1e-5}
+GUARD32 = {"energy_per_atom": 1e-6, "force_rel": 1e-5, "site": 1e-5, "b_rel": 2e-5}
+# workloads on which FP32 misses the absolute force bound (measured maxima in
+# the expected-failure message)
+KNOWN_FP32_MISS = {"mixed-l12", "mixed-l16"}
+
+
+def check_fp32(rep, label, known=KNOWN_FP32_MISS):
+    """Guard, then the stated absolute bounds (an expected failure, with the
+    numbers, for workloads known to miss them)."""
+    for k, v in GUARD32.items():
+        assert rep[k] <= v, (label, k, rep[k], v)
+    miss = {k: rep[k] for k, v in ABS32.items() if rep[k] > v}
+    if miss and label in known:
+        pytest.xfail(f"{label}: FP32 misses the absolute bounds {ABS32}: measured {miss}")
+    assert not miss, (label, miss)
 
 
 @pytest.fixture(scope="module")
@@ -43,6 +63,9 @@ def _check(name, batch, precision, potentials, tol, label):
     st = P.status()
     assert st["list_errors"] == 0
     rep["force_rel"] = rep["force"] / max(rep["force_scale"], 1e-300)
+    if tol is None:
+        check_fp32(rep, label)
+        return g, o
     for k, v in tol.items():
         assert rep[k] <= v, (k, rep[k], v)
     return g, o
@@ -51,19 +74,19 @@ def _check(name, batch, precision, potentials, tol, label):
 @pytest.mark.parametrize("precision", ["fp64", "fp32", "fp32c"])
 def test_fcc108_level8(potentials, precision):
     b = synth.fcc108(seed=0)
-    _check("lev8_s1", b, precision, potentials, TOL64 if precision == "fp64" else TOL32, "fcc108")
+    _check("lev8_s1", b, precision, potentials, TOL64 if precision == "fp64" else None, "fcc108")
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32", "fp32c"])
 def test_mixed_level12(potentials, precision):
     b = synth.mixed_batch(seed=3, n_configs=24, n_min=8, n_max=48, n_species_model=2)
-    _check("lev12_s2", b, precision, potentials, TOL64 if precision == "fp64" else TOL32, "mixed-l12")
+    _check("lev12_s2", b, precision, potentials, TOL64 if precision == "fp64" else None, "mixed-l12")
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32", "fp32c"])
 def test_mixed_level16(potentials, precision):
     b = synth.mixed_batch(seed=4, n_configs=12, n_min=8, n_max=96, n_species_model=3)
-    _check("lev16_s3", b, precision, potentials, TOL64 if precision == "fp64" else TOL32, "mixed-l16")
+    _check("lev16_s3", b, precision, potentials, TOL64 if precision == "fp64" else None, "mixed-l16")
 
 
 def test_edge_cases(potentials):
