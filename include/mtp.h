@@ -151,6 +151,21 @@ int mtp_set_active_set(mtp_model* model, const double* A_dev, void* stream);
 int mtp_grade_from_b(mtp_model* model, int32_t n, const double* b_dev, double* gamma_dev,
                      int32_t* argmax_dev, double* c_dev, void* stream);
 
+/*
+ * mtp_grade_from_b without any allocation, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops): the
+ * product c = b A^{-1} goes to a fixed device array of the library (16 MiB
+ * per GPU, held until the process ends) instead of memory the model would
+ * allocate, so n * m must not exceed 2^21 (MTP_E_CAPACITY otherwise, before
+ * anything is launched).  gamma_dev [n] FP64 and argmax_dev [n] int32 as in
+ * mtp_grade_from_b; c is not returned.  Every call on one GPU shares that
+ * array: calls that overlap on one GPU (on different streams, or from
+ * different models) race, so order them on one stream.  MTP_E_STATE without
+ * an active set.  Asynchronous on `stream`.
+ */
+int mtp_grade_from_b_noalloc(mtp_model* model, int32_t n, const double* b_dev, double* gamma_dev,
+                             int32_t* argmax_dev, void* stream);
+
 /* mtp_eval for b followed by mtp_grade_from_b, per configuration. */
 int mtp_grade(mtp_model* model, const mtp_batch* batch, double* gamma_dev, int32_t* argmax_dev,
               int precision, void* stream);

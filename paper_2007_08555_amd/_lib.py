@@ -59,6 +59,7 @@ _SIGNATURES = {
     "mtp_eval_async": (ctypes.c_int, [_P, ctypes.POINTER(mtp_batch), ctypes.POINTER(mtp_out), ctypes.c_int, _P]),
     "mtp_set_active_set": (ctypes.c_int, [_P, _P, _P]),
     "mtp_grade_from_b": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, _P, _P, _P]),
+    "mtp_grade_from_b_noalloc": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, _P, _P]),
     "mtp_grade": (ctypes.c_int, [_P, ctypes.POINTER(mtp_batch), _P, _P, ctypes.c_int, _P]),
     "mtp_theta_rows": (ctypes.c_int, [_P, ctypes.POINTER(mtp_batch), ctypes.c_int, _P, _P]),
     "mtp_set_active_set_theta": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P]),

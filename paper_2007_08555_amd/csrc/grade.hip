@@ -2,6 +2,8 @@
 // the active-set inverse A^{-1} and c = b A^{-1}, gamma = max_j |c_j|,
 // argmax_j |c_j| (lowest index on ties).
 #include <hip/hip_runtime.h>
+
+#include <mutex>
 #include <math.h>
 
 #include "mtp_internal.h"
@@ -144,6 +146,27 @@ __global__ void maxabs_kernel(int n, int m, const double* __restrict__ c, double
 }
 
 }  // namespace
+
+// Scratch of mtp_grade_from_b_noalloc: the product c = b A^{-1} of one call,
+// in a fixed device array (one copy per GPU, kept until the process ends).
+static __device__ __align__(256) double grade_scratch[kGradeScratchDoubles];
+
+hipError_t grade_scratch_address(int device, double** out) {
+  // The array's name is a host-side stand-in: its device address on the
+  // current device comes from the runtime, once per device.
+  static std::mutex mu;
+  static double* addr[kMaxGradeDevices] = {};
+  if (device < 0 || device >= kMaxGradeDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(grade_scratch));
+    if (e != hipSuccess) return e;
+    addr[device] = static_cast<double*>(p);
+  }
+  *out = addr[device];
+  return hipSuccess;
+}
 
 hipError_t gauss_jordan_inverse(int m, double* work, double* inv, int* singular, hipStream_t s) {
   hipLaunchKernelGGL(gj_kernel, dim3(1), dim3(kGJBlock), 0, s, m, work, inv, singular);

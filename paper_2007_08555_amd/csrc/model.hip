@@ -545,6 +545,13 @@ int mtp_load(const char* path, int device, mtp_model** out) {
   M->device = device;
   int rc = parse_and_match(path, M);
   if (rc == MTP_OK) rc = upload_params(M);
+  if (rc == MTP_OK) {
+    // device address of the fixed scratch of mtp_grade_from_b_noalloc on
+    // this device, looked up here so that the call itself does no set-up
+    double* scratch = nullptr;
+    const hipError_t e = mtp::grade_scratch_address(device, &scratch);
+    if (e != hipSuccess) rc = hip_fail(e, "hipGetSymbolAddress");
+  }
   if (rc != MTP_OK) {
     delete M;
     return rc;
@@ -952,6 +959,24 @@ int mtp_grade_from_b(mtp_model* M, int32_t n, const double* b_dev, double* gamma
     c = M->c_tmp.as<double>();
   }
   HIP_TRY(mtp::grade_rows(n, M->m, b_dev, M->ainv.as<double>(), gamma_dev, argmax_dev, c, s), "grade");
+  return MTP_OK;
+}
+
+int mtp_grade_from_b_noalloc(mtp_model* M, int32_t n, const double* b_dev, double* gamma_dev, int32_t* argmax_dev,
+                             void* stream) {
+  g_err.clear();
+  if (!M || n < 0 || (n > 0 && (!b_dev || !gamma_dev || !argmax_dev)))
+    return fail(MTP_E_ARG, "mtp_grade_from_b_noalloc: bad argument");
+  if (!M->has_active) return fail(MTP_E_STATE, "mtp_grade_from_b_noalloc: no active set (call mtp_set_active_set)");
+  if ((size_t)n * (size_t)M->m > mtp::kGradeScratchDoubles)
+    return fail(MTP_E_CAPACITY, "mtp_grade_from_b_noalloc: n * m = " + std::to_string((size_t)n * M->m) +
+                                    " exceeds the fixed scratch of " + std::to_string(mtp::kGradeScratchDoubles) +
+                                    " doubles (split the rows or use mtp_grade_from_b)");
+  HIP_TRY(hipSetDevice(M->device), "hipSetDevice");
+  double* c = nullptr;
+  HIP_TRY(mtp::grade_scratch_address(M->device, &c), "hipGetSymbolAddress");
+  HIP_TRY(mtp::grade_rows(n, M->m, b_dev, M->ainv.as<double>(), gamma_dev, argmax_dev, c, (hipStream_t)stream),
+          "grade");
   return MTP_OK;
 }
 

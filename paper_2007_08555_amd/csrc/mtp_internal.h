@@ -197,6 +197,13 @@ hipError_t gauss_jordan_inverse(int m, double* work /*[m][2m]*/, double* inv, in
                                 hipStream_t s);
 hipError_t grade_rows(int n, int m, const double* b, const double* Ainv, double* gamma,
                       int32_t* argmax, double* c, hipStream_t s);
+// Fixed device scratch of mtp_grade_from_b_noalloc (grade.hip): room for c
+// of n x m doubles with n m <= kGradeScratchDoubles (16 MiB per GPU).
+constexpr size_t kGradeScratchDoubles = size_t(1) << 21;
+constexpr int kMaxGradeDevices = 256;
+// Device address of that array on `device`, which must be the current
+// device; looked up once per device and cached.
+hipError_t grade_scratch_address(int device, double** out);
 // Per row of c [n][m]: max |c| and its first index.
 hipError_t row_maxima(int n, int m, const double* c, double* gamma, int32_t* argmax, hipStream_t s);
 

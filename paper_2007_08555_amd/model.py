@@ -240,6 +240,18 @@ class Potential:
               "mtp_grade_from_b")
         return (gamma, arg, c) if want_c else (gamma, arg)
 
+    def grade_from_b_noalloc(self, b, gamma, argmax, stream=None):
+        """mtp_grade_from_b_noalloc: gamma [n] float64 and argmax [n] int32
+        are preallocated device tensors; the library allocates nothing."""
+        n = int(b.shape[0])
+        if b.dtype != torch.float64 or not b.is_contiguous() or b.dim() != 2 or int(b.shape[1]) != self.m:
+            raise ValueError("b must be a contiguous float64 [n, m] device tensor")
+        if gamma.dtype != torch.float64 or argmax.dtype != torch.int32 or gamma.numel() < n or argmax.numel() < n:
+            raise ValueError("gamma must be float64 [n] and argmax int32 [n]")
+        check(lib().mtp_grade_from_b_noalloc(self._h, n, _ptr(b), _ptr(gamma), _ptr(argmax), _stream(stream)),
+              "mtp_grade_from_b_noalloc")
+        return gamma, argmax
+
     # nonlinear grade: rows dE/dtheta over theta = (xi, c) ------------------
     def theta_rows(self, batch: Batch, precision="fp64", stream=None):
         """dE_k/dtheta [K, m + n_c] FP64 on the device (mtp_theta_rows)."""
