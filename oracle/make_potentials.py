@@ -35,6 +35,7 @@ SPECS = {
     "lev16_s3": (16, 3, 8, 2.0, 5.0, 103, ("mixed", 1, 64, 8, 256)),
     "lev20_s3": (20, 3, 8, 2.0, 5.0, 104, ("mixed", 2, 64, 32, 128)),
     "lev20_s3_ref": (20, 3, 8, 2.0, 5.0, 105, ("mixed", 2, 64, 32, 128)),
+    "lev24_s3": (24, 3, 8, 2.0, 5.0, 106, ("fcc_alloy", 128)),
 }
 
 
@@ -45,6 +46,8 @@ def calibration_B(pot, calib, max_atoms=2048):
         b = synth.fcc108(seed=0)
     elif calib[0] == "bcc_alloy":
         b = synth.bcc_alloy(seed=0)
+    elif calib[0] == "fcc_alloy":
+        b = synth.fcc_alloy(seed=0)
     elif calib[0] == "mixed":
         _, seed, n_cfg, n_min, n_max = calib
         b = synth.mixed_batch(seed=seed, n_configs=n_cfg, n_min=n_min, n_max=n_max,
@@ -52,7 +55,7 @@ def calibration_B(pot, calib, max_atoms=2048):
     else:
         raise ValueError(calib)
     total = int(b["n_atoms"].sum())
-    budget = min(total, calib[1] if calib[0] == "bcc_alloy" else max_atoms)
+    budget = min(total, calib[1] if calib[0] in ("bcc_alloy", "fcc_alloy") else max_atoms)
     take = np.sort(rng.choice(total, size=budget, replace=False)) if budget < total else np.arange(total)
     offs = b["atom_offsets"]
     for k in range(len(b["n_atoms"])):
@@ -60,8 +63,10 @@ def calibration_B(pot, calib, max_atoms=2048):
         if len(sel) == 0:
             continue
         pos, sp, cell, pbc = synth.config_of(b, k)
-        for s in range(0, len(sel), 256):
-            _, B, _ = mtp._eval_centers(pot, pos, sp, cell, pbc, sel[s:s + 256], want_grad=False)
+        # full 3^nu tensors: fewer centres per call at high levels
+        step = 256 if pot["level"] <= 20 else 8
+        for s in range(0, len(sel), step):
+            _, B, _ = mtp._eval_centers(pot, pos, sp, cell, pbc, sel[s:s + step], want_grad=False)
             rows.append(B)
     return np.concatenate(rows)
 

@@ -59,29 +59,40 @@ def key_level(key):
     return sum(level_of(mu, nu) for mu, nu in labels)
 
 
-def _stub_matchings(deg):
-    """Every loopless multigraph with the given degree sequence, by pairing
-    the first open stub with a stub of a later vertex (with repetition)."""
+def _multigraphs(deg):
+    """Every loopless multigraph with the given degree sequence (as a dense
+    multiplicity matrix), each exactly once: the first vertex with open
+    degree spreads all of it over later vertices, one multiplicity per
+    later vertex, bounded by their open degrees."""
     n = len(deg)
     adj = [[0] * n for _ in range(n)]
     rem = list(deg)
+
+    def spread(a, b, left):
+        # give vertex a's remaining `left` edges to vertices b, b+1, ...
+        if left == 0:
+            yield from rec()
+            return
+        if b >= n:
+            return
+        if sum(rem[c] for c in range(b, n)) < left:
+            return
+        for k in range(min(left, rem[b]), -1, -1):
+            rem[b] -= k
+            adj[a][b] = adj[b][a] = k
+            yield from spread(a, b + 1, left - k)
+            rem[b] += k
+            adj[a][b] = adj[b][a] = 0
 
     def rec():
         a = next((v for v in range(n) if rem[v] > 0), None)
         if a is None:
             yield [row[:] for row in adj]
             return
-        for b in range(a + 1, n):
-            if rem[b] > 0:
-                rem[a] -= 1
-                rem[b] -= 1
-                adj[a][b] += 1
-                adj[b][a] += 1
-                yield from rec()
-                adj[a][b] -= 1
-                adj[b][a] -= 1
-                rem[a] += 1
-                rem[b] += 1
+        left = rem[a]
+        rem[a] = 0
+        yield from spread(a, a + 1, left)
+        rem[a] = left
 
     yield from rec()
 
@@ -98,6 +109,30 @@ def _connected(adj):
     return len(seen) == n
 
 
+def _label_multisets(types, n, budget):
+    """Non-decreasing n-tuples of vertex types whose levels sum to at most
+    budget (types sorted by (mu, nu), so a type's level grows with nu within
+    one mu and the scan over later types can stop per mu)."""
+    lev = [level_of(*t) for t in types]
+    cheapest = min(lev)
+    out = []
+
+    def rec(start, chosen, total):
+        if len(chosen) == n:
+            out.append(tuple(chosen))
+            return
+        left = n - len(chosen) - 1
+        for t in range(start, len(types)):
+            if total + lev[t] + left * cheapest > budget:
+                continue
+            chosen.append(types[t])
+            rec(t, chosen, total + lev[t])
+            chosen.pop()
+
+    rec(0, [], 0)
+    return out
+
+
 @lru_cache(maxsize=None)
 def contractions(lev_max):
     """Canonical keys of all connected contractions with level <= lev_max,
@@ -110,18 +145,11 @@ def contractions(lev_max):
                           if level_of(mu, nu) <= lev_max)
     n = 2
     while 4 * n - 2 <= lev_max:      # n vertices need >= n-1 edges: level >= 4n - 2
-        for labels in itertools.combinations_with_replacement(vertex_types, n):
-            if sum(level_of(*l) for l in labels) > lev_max:
-                continue
+        for labels in _label_multisets(vertex_types, n, lev_max):
             deg = [nu for _, nu in labels]
             if sum(deg) % 2:
                 continue
-            seen = set()
-            for adj in _stub_matchings(deg):
-                t = tuple(map(tuple, adj))
-                if t in seen:
-                    continue
-                seen.add(t)
+            for adj in _multigraphs(deg):
                 if _connected(adj):
                     keys.add(canonical(list(labels), adj))
         n += 1

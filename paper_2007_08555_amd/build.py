@@ -8,7 +8,8 @@ paper_2007_08555_amd/libmtp.so.  Object files go to
 paper_2007_08555_amd/_build/ and are reused while their source (for a part of
 a generated kernel file: the sections that part compiles), the project
 headers it includes and the flags are unchanged.  MTP_EXTRA_LEVELS (e.g.
-"20") adds basis levels to the default ones.
+"18") adds basis levels to the default ones (2-16 straight-line, 20 and 24
+table-driven).
 """
 from __future__ import annotations
 
@@ -144,10 +145,10 @@ def build(levels=None, jobs=None, verbose=True, force=False):
         raise RuntimeError(f"hipcc not found at {HIPCC}")
     os.makedirs(BUILD, exist_ok=True)
     if levels is None:
-        # MTP_EXTRA_LEVELS (e.g. "18,20") adds larger bases, whose kernels
-        # take minutes to compile (level 20: about 10 minutes per part)
+        # the straight-line bases (levels 2-16) and the table-driven ones
+        # (20, 24); MTP_EXTRA_LEVELS (e.g. "18") adds more
         extra = [int(v) for v in os.environ.get("MTP_EXTRA_LEVELS", "").replace(",", " ").split()]
-        levels = tuple(sorted(set(codegen.LEVELS) | set(extra)))
+        levels = tuple(sorted(set(codegen.LEVELS) | set(codegen.TABLE_LEVELS) | set(extra)))
     gen_files, _ = codegen.write_all(GEN, levels=levels)
     sources = [os.path.join(CSRC, f) for f in sorted(os.listdir(CSRC)) if f.endswith(".hip")]
     sources += [f for f in gen_files if f.endswith((".hip", ".cpp"))]

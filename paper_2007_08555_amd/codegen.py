@@ -60,22 +60,28 @@ class Schedule:
         self.terms = [self._terms(labels, edges) for labels, edges in self.graphs]
 
     def _terms(self, labels, edges):
+        """Sum over the index assignments of a graph as weighted products of
+        components: edges are taken one at a time, each spreading its k
+        contracted index pairs over the axes (composition (kx, ky, kz) with
+        weight k! / (kx! ky! kz!)) and adding them to both endpoints' counts;
+        assignments that reach the same per-vertex counts are merged."""
         if not edges:
             (mu, nu), = labels
             return [(1, (self.comp[(mu, 0, (0, 0, 0))],))]
-        per_edge = []
+        states = {tuple((0, 0, 0) for _ in labels): 1}
         for u, v, k in edges:
-            per_edge.append([(u, v, abc, multinomial(*abc)) for abc in components(k)])
+            spread = [(abc, multinomial(*abc)) for abc in components(k)]
+            nxt = defaultdict(int)
+            for st, coef in states.items():
+                for abc, w in spread:
+                    cnt = list(st)
+                    cnt[u] = tuple(x + y for x, y in zip(cnt[u], abc))
+                    cnt[v] = tuple(x + y for x, y in zip(cnt[v], abc))
+                    nxt[tuple(cnt)] += coef * w
+            states = nxt
         acc = defaultdict(int)
-        for choice in itertools.product(*per_edge):
-            cnt = [[0, 0, 0] for _ in labels]
-            coef = 1
-            for u, v, abc, w in choice:
-                for t in range(3):
-                    cnt[u][t] += abc[t]
-                    cnt[v][t] += abc[t]
-                coef *= w
-            idx = tuple(sorted(self.comp[(mu, nu, tuple(cnt[x]))] for x, (mu, nu) in enumerate(labels)))
+        for cnt, coef in states.items():
+            idx = tuple(sorted(self.comp[(mu, nu, cnt[x])] for x, (mu, nu) in enumerate(labels)))
             acc[idx] += coef
         return sorted((c, idx) for idx, c in acc.items())
 
@@ -471,6 +477,71 @@ def adjoint_passes(s, budget):
     return [(p, sorted(k for nu in p for k in per_nu[nu])) for p in passes]
 
 
+FUSED_TEMPLATE = r"""
+// Moments, contractions and reverse sweep of one atom in one kernel: all C
+// moment components summed in registers over the atom's pairs (and written
+// out only when STORE_M, for the loss and normal-equation paths that reread
+// them), then the graph values, B, V, dV/dg and G = dV/dM (written out for
+// the adjoint passes).  Up to 512 registers per lane (VGPRs and AGPRs), one
+// wavefront per SIMD.
+template <typename T, bool WANT_B, bool STORE_M, int NQ>
+__global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(1, 1)))
+fused_{tag}_kernel(const mtp::EvalArgs<T> args) {{
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* cs = reinterpret_cast<T*>(smem_raw);
+  for (int t = threadIdx.x; t < args.n_c; t += blockDim.x) cs[t] = args.c[t];
+  __syncthreads();
+  const int i = blockIdx.x * BLOCK + threadIdx.x;
+  if (i >= args.n_atoms) return;
+  const int S = args.n_species;
+  const int nq = args.nq;
+  const int mu_stride = S * S * nq;
+  const int zi = clamp_species(args.species[i], S);
+  const int cnt = args.nbr_count[i];
+  const T rmin = args.rmin, rcut = args.rcut;
+  constexpr bool COMP = false;
+  T M[C];
+  T Mlo[1];
+  (void)Mlo;
+#pragma unroll
+  for (int k = 0; k < C; ++k) M[k] = T(0);
+  T xn = T(0), yn = T(0), zn = T(0);
+  int zjn = 0;
+  if (cnt > 0) {{
+    const mtp::PairRec<T> q = args.pr[i];
+    xn = q.x; yn = q.y; zn = q.z; zjn = q.zj;
+  }}
+#pragma unroll 1
+  for (int p = 0; p < cnt; ++p) {{
+    const T x = xn, y = yn, z = zn;
+    const int zj = zjn;
+    if (p + 1 < cnt) {{
+      const size_t en = (size_t)(p + 1) * args.stride + i;
+      const mtp::PairRec<T> q = args.pr[en];
+      xn = q.x; yn = q.y; zn = q.z; zjn = q.zj;
+    }}
+    const T r = sqrt(x * x + y * y + z * z);
+    T f[NMU], df[NMU];
+    mtp::radial<T, NMU, false, NQ>(cs, (zi * S + zj) * nq, mu_stride, nq, r, rmin, rcut, f, df);
+{moments}
+  }}
+  if constexpr (STORE_M) {{
+#pragma unroll
+    for (int k = 0; k < C; ++k) args.M[(size_t)k * args.stride + i] = M[k];
+  }}
+  const T* __restrict__ xi = args.xi;
+#define MTP_OUT_B(a_, v_) do {{ if (WANT_B) args.B[(size_t)(a_) * args.b_stride + i] = (v_); }} while (0)
+#define MTP_OUT_G(k_, v_) args.G[(size_t)(k_) * args.stride + i] = (v_)
+#define MTP_RELOAD_M() mtp::opaque(M)
+{contraction}
+#undef MTP_RELOAD_M
+#undef MTP_OUT_G
+#undef MTP_OUT_B
+  args.site[i] = V;
+}}
+"""
+
+
 ADJOINT_TEMPLATE = r"""
 // Adjoint pass {pidx} over the pairs of one atom, components of degrees {nus}:
 // its share of g = dV_i/dr_ij from G, f_mu and df_mu/dr, stored (first pass)
@@ -850,8 +921,9 @@ hipError_t launch_loss_t(const void* a, const void* l, hipStream_t s) {{
 
 #if MTP_PART == 1 || MTP_PART == 2
 template <typename T, bool COMP, bool WANT_B, int NQ>
-hipError_t launch_t(const void* a, bool reuse_moments, int schedule, hipStream_t s) {{
+hipError_t launch_t(const void* a, bool reuse_moments, bool store_moments, int schedule, hipStream_t s) {{
   const auto& args = *static_cast<const mtp::EvalArgs<T>*>(a);
+  (void)store_moments;
   if (args.n_atoms <= 0) return hipSuccess;
   const dim3 grid((args.n_atoms + BLOCK - 1) / BLOCK);
   const size_t smem = (size_t)args.n_c * sizeof(T);
@@ -877,29 +949,31 @@ hipError_t eval64(unsigned flags, int schedule, const void* a, hipStream_t s) {{
   using namespace {ns};
   const bool want_b = (flags & mtp::kEvalWantB) != 0;
   const bool reuse = (flags & mtp::kEvalReuseMoments) != 0;
+  const bool store = (flags & mtp::kEvalStoreMoments) != 0;
   // the pair kernels come with the radial basis size 8 fixed (unrolled) and
   // with a run-time size
   if (static_cast<const mtp::EvalArgs<double>*>(a)->nq == 8)
-    return want_b ? launch_t<double, false, true, 8>(a, reuse, schedule, s)
-                  : launch_t<double, false, false, 8>(a, reuse, schedule, s);
-  return want_b ? launch_t<double, false, true, 0>(a, reuse, schedule, s)
-                : launch_t<double, false, false, 0>(a, reuse, schedule, s);
+    return want_b ? launch_t<double, false, true, 8>(a, reuse, store, schedule, s)
+                  : launch_t<double, false, false, 8>(a, reuse, store, schedule, s);
+  return want_b ? launch_t<double, false, true, 0>(a, reuse, store, schedule, s)
+                : launch_t<double, false, false, 0>(a, reuse, store, schedule, s);
 }}
 #elif MTP_PART == 2
 hipError_t eval32(int precision, unsigned flags, int schedule, const void* a, hipStream_t s) {{
   using namespace {ns};
   const bool want_b = (flags & mtp::kEvalWantB) != 0;
   const bool reuse = (flags & mtp::kEvalReuseMoments) != 0;
+  const bool store = (flags & mtp::kEvalStoreMoments) != 0;
   if (static_cast<const mtp::EvalArgs<float>*>(a)->nq == 8) {{
     if (precision == 2)
-      return want_b ? launch_t<float, true, true, 8>(a, reuse, schedule, s)
-                    : launch_t<float, true, false, 8>(a, reuse, schedule, s);
-    return want_b ? launch_t<float, false, true, 8>(a, reuse, schedule, s)
-                  : launch_t<float, false, false, 8>(a, reuse, schedule, s);
+      return want_b ? launch_t<float, true, true, 8>(a, reuse, store, schedule, s)
+                    : launch_t<float, true, false, 8>(a, reuse, store, schedule, s);
+    return want_b ? launch_t<float, false, true, 8>(a, reuse, store, schedule, s)
+                  : launch_t<float, false, false, 8>(a, reuse, store, schedule, s);
   }}
   if (precision == 2)
-    return want_b ? launch_t<float, true, true, 0>(a, reuse, schedule, s) : launch_t<float, true, false, 0>(a, reuse, schedule, s);
-  return want_b ? launch_t<float, false, true, 0>(a, reuse, schedule, s) : launch_t<float, false, false, 0>(a, reuse, schedule, s);
+    return want_b ? launch_t<float, true, true, 0>(a, reuse, store, schedule, s) : launch_t<float, true, false, 0>(a, reuse, store, schedule, s);
+  return want_b ? launch_t<float, false, true, 0>(a, reuse, store, schedule, s) : launch_t<float, false, false, 0>(a, reuse, store, schedule, s);
 }}
 #elif MTP_PART == 3
 hipError_t loss(int precision, const void* a, const void* l, hipStream_t s) {{
@@ -953,6 +1027,9 @@ SCHEDULES_F64 = [
     {"mom": 85, "rev": [(0, 1, 2), (3, 4), (5, 6)], "adj": 90},
     {"mom": 85, "rev": [(0, 1), (2,), (3, 4), (5, 6)], "adj": 90},
     {"mom": 50, "rev": [(0,), (1,), (2,), (3,), (4,), (5,), (6,)], "adj": 50},
+    # moments, contractions and reverse sweep in one kernel (M, dV/dg never
+    # leave the registers), then the adjoint passes
+    {"fused": True, "adj": 90},
 ]
 SCHEDULE_F32 = {"mom": 10 ** 9, "rev": [tuple(range(64))], "adj": 10 ** 9}
 
@@ -972,6 +1049,35 @@ def generate(lev_max, block=64):
     plans = [("f32", 0, SCHEDULE_F32)] + [("f64", k, sch) for k, sch in enumerate(SCHEDULES_F64)]
     for prec, sidx, sch in plans:
         mom_lines, rev_lines, adj_lines = [], [], []
+        if sch.get("fused"):
+            tag = f"{prec}s{sidx}"
+            kern_src[prec].append(FUSED_TEMPLATE.format(
+                tag=tag, moments="\n".join(" " * 4 + l for l in fwd), contraction="\n".join("  " + l for l in con)))
+            passes = adjoint_passes(s, sch["adj"])
+            for pidx, (nus, comps) in enumerate(passes):
+                ptag = f"{prec}s{sidx}_p{pidx}"
+                gmap = {k: j for j, k in enumerate(comps)}
+                nmu = 1 + max(mu for (mu, nu, abc), k in s.comp.items() if nu in nus)
+                body, _ = emit_pair_backward(s, nus=nus, gmap=gmap, nmu=nmu)
+                kern_src[prec].append(ADJOINT_TEMPLATE.format(pidx=pidx, nus=nus, tag=ptag, ncomp=len(comps), nmu=nmu,
+                                                              comp_list=", ".join(map(str, comps)),
+                                                              body="\n".join(" " * 4 + l for l in body)))
+                first = "true" if pidx == 0 else "false"
+                last = "true" if pidx == len(passes) - 1 else "false"
+                adj_lines.append(f"hipLaunchKernelGGL((adjoint_{ptag}_kernel<T, {first}, {last}, NQ>), "
+                                 f"grid, dim3(BLOCK), smem, s, args);")
+            # the reread of stored moments (normal equations) runs the
+            # contraction of schedule 0 from them
+            body = (["if (reuse_moments) {",
+                     "  hipLaunchKernelGGL((contract_fwd_kernel<T, WANT_B>), grid, dim3(BLOCK), 0, s, args);"] +
+                    ["  " + l for l in sched_launch[(prec, 0)] if l.startswith("hipLaunchKernelGGL((contract_rev_")] +
+                    ["} else if (store_moments) {",
+                     f"  hipLaunchKernelGGL((fused_{tag}_kernel<T, WANT_B, true, NQ>), grid, dim3(BLOCK), smem, s, args);",
+                     "} else {",
+                     f"  hipLaunchKernelGGL((fused_{tag}_kernel<T, WANT_B, false, NQ>), grid, dim3(BLOCK), smem, s, args);",
+                     "}"] + adj_lines)
+            sched_launch[(prec, sidx)] = body
+            continue
         # moments passes: each recomputes r and f_mu for the degrees it sums
         for pidx, (nus, comps) in enumerate(adjoint_passes(s, sch["mom"])):
             tag = f"{prec}s{sidx}_p{pidx}"
@@ -1127,7 +1233,331 @@ def generate(lev_max, block=64):
     return src, meta
 
 
+# --------------------------------------------------------------------------
+# Table-driven bases (levels whose straight-line contraction is too large to
+# compile): the per-pair passes stay generated code, the contraction walks
+# per-graph tries of component indices (csrc/contract_table.h).
+# --------------------------------------------------------------------------
+
+def build_tries(s):
+    """Per graph, the trie of its terms' sorted factor tuples.  Returns
+    (nodes [k, c0, c1] with children [c0, c1) or, at a leaf, c0 = its weight's
+    index), the weights, the roots per depth {D: [(graph, r0, r1)]}."""
+    nodes, coefs, roots = [], [], defaultdict(list)
+    for g, terms in enumerate(s.terms):
+        depth = len(terms[0][1])
+        assert all(len(idx) == depth for _, idx in terms)
+        tree = {}
+        for coef, idx in terms:
+            cur = tree
+            for k in idx[:-1]:
+                cur = cur.setdefault(k, {})
+            assert idx[-1] not in cur
+            cur[idx[-1]] = coef
+
+        def place(d, level):
+            r0 = len(nodes)
+            items = sorted(d.items())
+            nodes.extend([k, 0, 0] for k, _ in items)
+            for t, (_, v) in enumerate(items):
+                if level == depth:
+                    coefs.append(v)
+                    nodes[r0 + t][1] = len(coefs) - 1
+                else:
+                    nodes[r0 + t][1], nodes[r0 + t][2] = place(v, level + 1)
+            return r0, r0 + len(items)
+
+        r0, r1 = place(tree, 1)
+        roots[depth].append((g, r0, r1))
+    return nodes, coefs, dict(roots)
+
+
+def contraction_flops(s):
+    """Algorithmic flops of the contraction forward and reverse per atom as
+    emit_contraction counts them (products of the terms, basis products,
+    dV/dg, then every component's share of the reverse), without emitting
+    the code."""
+    ops = 0
+    for terms in s.terms:
+        ops += sum(len(idx) + (1 if coef != 1 else 0) for coef, idx in terms)
+    for fn in s.funcs:
+        ops += len(fn) - 1 + 2
+        counts = defaultdict(int)
+        for g in fn:
+            counts[g] += 1
+        for g, n in counts.items():
+            ops += (len(fn) - 1) + 1 + (1 if n > 1 else 0)
+    contrib = defaultdict(lambda: defaultdict(int))
+    for g, terms in enumerate(s.terms):
+        for coef, idx in terms:
+            for k in set(idx):
+                cnt = idx.count(k)
+                rest = len(idx) - 1
+                contrib[k][g] += (1 if coef * cnt != 1 and rest else 0) + max(rest - 1, 0) + 1
+    for k in contrib:
+        for g in contrib[k]:
+            ops += contrib[k][g] + 1
+    return ops
+
+
+TABLE_TEMPLATE = r"""// Generated by paper_2007_08555_amd/codegen.py for the MTP basis of level {level}
+// ({m} basis functions, {ngraphs} connected contractions, {C} moment components;
+// {nnodes} trie nodes).  Table-driven contraction; do not edit.
+#include "mtp_device.h"
+#include "mtp_variant.h"
+#if MTP_PART >= 1
+#include "contract_table.h"
+#endif
+
+namespace {{
+namespace {ns} {{
+
+constexpr int C = {C};
+constexpr int NMU = {n_mu};
+constexpr int BLOCK = 64;
+
+__device__ __forceinline__ int clamp_species(int z, int S) {{ return z < 0 ? 0 : (z >= S ? S - 1 : z); }}
+
+#if MTP_PART >= 1
+// trie nodes (k, c0, c1, 0), leaf weights, roots (graph, r0, r1, 0) by depth,
+// basis functions as lists of graphs
+__device__ const int kNode[] __attribute__((aligned(16))) = {{ {node_data} }};
+__device__ const double kCoef[] = {{ {coef_data} }};
+__device__ const int kRoots[] __attribute__((aligned(16))) = {{ {root_data} }};
+__device__ const int kFOff[] = {{ {foff_data} }};
+__device__ const int kFFac[] = {{ {ffac_data} }};
+
+struct Tab {{
+  static constexpr int kGraphs = {ngraphs};
+  static constexpr int kC = C;
+  static constexpr int kM = {m};
+  static constexpr int kDepth = {depth};
+  static constexpr int kMaxFactors = {qmax};
+  __device__ static const int4* node() {{ return reinterpret_cast<const int4*>(kNode); }}
+  __device__ static const double* coef() {{ return kCoef; }}
+  __device__ static const int4* roots() {{ return reinterpret_cast<const int4*>(kRoots); }}
+  __device__ static int root_begin(int d) {{
+    constexpr int b[] = {{ {root_begin} }};
+    return b[d];
+  }}
+  __device__ static const int* func_off() {{ return kFOff; }}
+  __device__ static const int* func_fac() {{ return kFFac; }}
+}};
+#endif
+
+#if MTP_PART == 1 || MTP_PART == 2
+#if MTP_PART == 1
+{kernels64}
+#else
+{kernels32}
+#endif
+
+template <typename T, bool COMP, bool WANT_B, int NQ>
+hipError_t launch_t(const void* a, bool reuse_moments, bool store_moments, int schedule, hipStream_t s) {{
+  const auto& args = *static_cast<const mtp::EvalArgs<T>*>(a);
+  (void)store_moments;   // the moments always go through memory here
+  if (schedule != 0) return hipErrorInvalidValue;
+  if (args.n_atoms <= 0) return hipSuccess;
+  const dim3 grid((args.n_atoms + BLOCK - 1) / BLOCK);
+  const size_t smem = (size_t)args.n_c * sizeof(T);
+#if MTP_PART == 1
+{launch64}
+#else
+{launch32}
+#endif
+  return hipGetLastError();
+}}
+#endif  // parts 1, 2
+
+#if MTP_PART == 3
+{loss_kernels}
+{creduce}
+
+template <typename T>
+hipError_t launch_loss_t(const void* a, const void* l, hipStream_t s) {{
+  const auto& args = *static_cast<const mtp::EvalArgs<T>*>(a);
+  const auto& la = *static_cast<const mtp::LossArgs<T>*>(l);
+  if (args.n_atoms <= 0) return hipSuccess;
+  const dim3 grid((args.n_atoms + BLOCK - 1) / BLOCK);
+  const size_t smem = (size_t)args.n_c * sizeof(T);
+{launch_loss}
+  return hipGetLastError();
+}}
+#endif  // part 3
+
+}}  // namespace {ns}
+}}  // namespace
+
+namespace mtp_gen_{ns} {{
+hipError_t eval64(unsigned flags, int schedule, const void* a, hipStream_t s);
+hipError_t eval32(int precision, unsigned flags, int schedule, const void* a, hipStream_t s);
+hipError_t loss(int precision, const void* a, const void* l, hipStream_t s);
+#if MTP_PART == 1
+hipError_t eval64(unsigned flags, int schedule, const void* a, hipStream_t s) {{
+  using namespace {ns};
+  const bool want_b = (flags & mtp::kEvalWantB) != 0;
+  const bool reuse = (flags & mtp::kEvalReuseMoments) != 0;
+  const bool store = (flags & mtp::kEvalStoreMoments) != 0;
+  if (static_cast<const mtp::EvalArgs<double>*>(a)->nq == 8)
+    return want_b ? launch_t<double, false, true, 8>(a, reuse, store, schedule, s)
+                  : launch_t<double, false, false, 8>(a, reuse, store, schedule, s);
+  return want_b ? launch_t<double, false, true, 0>(a, reuse, store, schedule, s)
+                : launch_t<double, false, false, 0>(a, reuse, store, schedule, s);
+}}
+#elif MTP_PART == 2
+hipError_t eval32(int precision, unsigned flags, int schedule, const void* a, hipStream_t s) {{
+  using namespace {ns};
+  const bool want_b = (flags & mtp::kEvalWantB) != 0;
+  const bool reuse = (flags & mtp::kEvalReuseMoments) != 0;
+  const bool store = (flags & mtp::kEvalStoreMoments) != 0;
+  if (precision == 2)
+    return want_b ? launch_t<float, true, true, 0>(a, reuse, store, schedule, s) : launch_t<float, true, false, 0>(a, reuse, store, schedule, s);
+  return want_b ? launch_t<float, false, true, 0>(a, reuse, store, schedule, s) : launch_t<float, false, false, 0>(a, reuse, store, schedule, s);
+}}
+#elif MTP_PART == 3
+hipError_t loss(int precision, const void* a, const void* l, hipStream_t s) {{
+  using namespace {ns};
+  return precision == 0 ? launch_loss_t<double>(a, l, s) : launch_loss_t<float>(a, l, s);
+}}
+#endif
+}}  // namespace mtp_gen_{ns}
+
+#if MTP_PART == 0
+namespace {{
+namespace {ns} {{
+hipError_t launch(int precision, unsigned flags, int schedule, const void* a, hipStream_t s) {{
+  if (precision == 0) return mtp_gen_{ns}::eval64(flags, schedule, a, s);
+  if (precision == 1 || precision == 2) return mtp_gen_{ns}::eval32(precision, flags, schedule, a, s);
+  return hipErrorInvalidValue;
+}}
+
+{launch_loss_entry}
+
+const int kMoments[] = {{ {moments} }};
+const int kGraphKeyOffsets[] = {{ {graph_offsets} }};
+const int kGraphKeys[] = {{ {graph_keys} }};
+const int kFuncOffsets[] = {{ {func_offsets} }};
+const int kFuncFactors[] = {{ {func_factors} }};
+
+}}  // namespace {ns}
+}}  // namespace
+
+#if !defined(__HIP_DEVICE_COMPILE__)
+extern const mtp::BasisVariant {ns}_variant = {{
+  "{ns}", {level}, {n_moments}, {ns}::kMoments, {ngraphs}, {ns}::kGraphKeyOffsets, {ns}::kGraphKeys,
+  {m}, {ns}::kFuncOffsets, {ns}::kFuncFactors, {C}, {n_mu}, {nu_max},
+  {flops_pair_fwd}, {flops_pair_bwd}, {flops_atom}, {ns}::launch, {loss_ptr}, {ns}::BLOCK, 1 }};
+#endif
+#endif  // part 0
+"""
+
+# pass splits of the table-driven bases: FP64 and FP32 components per pass
+SCHEDULE_TABLE = {"f64": {"mom": 85, "adj": 90}, "f32": {"mom": 120, "adj": 120}}
+# the loss gradient is compiled for table-driven levels up to this one
+TABLE_LOSS_MAX_LEVEL = 20
+
+
+def _pair_pass_kernels(s, prec, sidx, sch):
+    """Moments and adjoint pass kernels of one schedule and their launches."""
+    src, mom_lines, adj_lines = [], [], []
+    for pidx, (nus, comps) in enumerate(adjoint_passes(s, sch["mom"])):
+        tag = f"{prec}s{sidx}_p{pidx}"
+        kmap = {k: j for j, k in enumerate(comps)}
+        body, _ = emit_pair_forward(s, comp_mode=True, nus=set(nus), kmap=kmap)
+        nmu = 1 + max(mu for (mu, nu, abc), k in s.comp.items() if nu in nus)
+        src.append(MOMENTS_TEMPLATE.format(pidx=pidx, nus=nus, tag=tag, ncomp=len(comps), nmu=nmu,
+                                           comp_list=", ".join(map(str, comps)),
+                                           body="\n".join(" " * 4 + l for l in body)))
+        mom_lines.append(f"hipLaunchKernelGGL((moments_{tag}_kernel<T, COMP, 0>), grid, dim3(BLOCK), smem, s, args);")
+    passes = adjoint_passes(s, sch["adj"])
+    for pidx, (nus, comps) in enumerate(passes):
+        tag = f"{prec}s{sidx}_p{pidx}"
+        gmap = {k: j for j, k in enumerate(comps)}
+        nmu = 1 + max(mu for (mu, nu, abc), k in s.comp.items() if nu in nus)
+        body, _ = emit_pair_backward(s, nus=nus, gmap=gmap, nmu=nmu)
+        src.append(ADJOINT_TEMPLATE.format(pidx=pidx, nus=nus, tag=tag, ncomp=len(comps), nmu=nmu,
+                                           comp_list=", ".join(map(str, comps)),
+                                           body="\n".join(" " * 4 + l for l in body)))
+        first = "true" if pidx == 0 else "false"
+        last = "true" if pidx == len(passes) - 1 else "false"
+        adj_lines.append(f"hipLaunchKernelGGL((adjoint_{tag}_kernel<T, {first}, {last}, NQ>), "
+                         f"grid, dim3(BLOCK), smem, s, args);")
+    return src, mom_lines, adj_lines
+
+
+def generate_table(lev_max):
+    """Source of a table-driven basis (same entry points and table entry as
+    generate())."""
+    s = Schedule(lev_max)
+    ns = f"lev{lev_max}"
+    nodes, coefs, roots = build_tries(s)
+    depth = max(roots)
+    qmax = max(len(f) for f in s.funcs)
+    root_list, root_begin = [], [0, 0]
+    for d in range(1, depth + 1):
+        for g, r0, r1 in roots.get(d, []):
+            root_list += [g, r0, r1, 0]
+        root_begin.append(len(root_list) // 4)
+    parts = {}
+    for prec in ("f64", "f32"):
+        src, mom, adj = _pair_pass_kernels(s, prec, 0, SCHEDULE_TABLE[prec])
+        launch = (["if (!reuse_moments) {"] + ["  " + l for l in mom] + ["}"] +
+                  ["hipLaunchKernelGGL((mtp::contract_table_kernel<T, WANT_B, Tab>), grid, dim3(BLOCK), 0, s, args);"] +
+                  adj)
+        parts[prec] = ("\n".join(src), "\n".join("  " + l for l in launch))
+    with_loss = lev_max <= TABLE_LOSS_MAX_LEVEL
+    if with_loss:
+        loss_src, loss_launch = emit_loss_kernels(s, budget=45)
+        old = "  hipLaunchKernelGGL((tangent_contract_kernel<T>), grid, dim3(BLOCK), 0, s, args, la);"
+        assert old in loss_launch
+        loss_launch = loss_launch.replace(
+            old, "  hipLaunchKernelGGL((mtp::contract_table_loss_kernel<T, Tab>), grid, dim3(BLOCK), 0, s, args, la);")
+        creduce = CREDUCE_TEMPLATE.format()
+        loss_entry = (f"hipError_t launch_loss(int precision, const void* a, const void* l, hipStream_t s) {{\n"
+                      f"  return mtp_gen_{ns}::loss(precision, a, l, s);\n}}")
+        loss_ptr = f"{ns}::launch_loss"
+    else:
+        loss_src, loss_launch, creduce, loss_entry, loss_ptr = "", "  return hipErrorNotSupported;", "", "", "nullptr"
+    _, ops_f = emit_pair_forward(s, comp_mode=True)
+    _, ops_b = emit_pair_backward(s)
+    ops_c = contraction_flops(s)
+    nq = 8
+    rad_f = 6 + 3 * (nq - 2) + 2 * s.n_mu * nq + 2 * s.n_mu
+    rad_b = rad_f + 5 * (nq - 2) + 2 * s.n_mu * nq + 4 * s.n_mu + 2
+    graph_keys, graph_offsets = [], [0]
+    for k in s.keys:
+        graph_keys += list(k)
+        graph_offsets.append(len(graph_keys))
+    func_factors, func_offsets = [], [0]
+    for f in s.funcs:
+        func_factors += list(f)
+        func_offsets.append(len(func_factors))
+    join = lambda v: ", ".join(map(str, v))
+    src = TABLE_TEMPLATE.format(
+        level=lev_max, m=len(s.funcs), ngraphs=len(s.keys), C=s.C, n_mu=s.n_mu, nu_max=s.nu_max, ns=ns,
+        nnodes=len(nodes), depth=depth, qmax=qmax,
+        node_data=join(v for nd in nodes for v in (nd[0], nd[1], nd[2], 0)),
+        coef_data=", ".join(repr(float(c)) for c in coefs),
+        root_data=join(root_list), root_begin=join(root_begin),
+        foff_data=join(func_offsets), ffac_data=join(func_factors),
+        kernels64=parts["f64"][0], kernels32=parts["f32"][0], launch64=parts["f64"][1], launch32=parts["f32"][1],
+        loss_kernels=loss_src, creduce=creduce, launch_loss=loss_launch, launch_loss_entry=loss_entry,
+        loss_ptr=loss_ptr,
+        moments=", ".join(f"{mu}, {nu}" for mu, nu in s.moments), n_moments=len(s.moments),
+        graph_offsets=join(graph_offsets), graph_keys=join(graph_keys),
+        func_offsets=join(func_offsets), func_factors=join(func_factors),
+        flops_pair_fwd=float(ops_f + rad_f), flops_pair_bwd=float(ops_b + rad_b + 1), flops_atom=float(ops_c))
+    assert all(float(c) == c for c in coefs), "a term weight is not exact in FP64"
+    meta = s.metadata()
+    meta.update({"flops_pair_fwd": ops_f + rad_f, "flops_pair_bwd": ops_b + rad_b + 1,
+                 "flops_atom_contraction": ops_c, "flops_counted_for_nq": nq, "table": True,
+                 "trie_nodes": len(nodes), "loss": with_loss})
+    return src, meta
+
+
 LEVELS = (2, 4, 6, 8, 10, 12, 14, 16)
+# bases compiled with the table-driven contraction
+TABLE_LEVELS = (20, 24)
 
 
 PARTS = (("", 0), ("_eval64", 1), ("_eval32", 2), ("_loss", 3))
@@ -1149,7 +1579,7 @@ def write_all(outdir, levels=LEVELS):
                 fh.write(text)
 
     for L in levels:
-        src, meta = generate(L)
+        src, meta = generate_table(L) if L in TABLE_LEVELS else generate(L)
         put(os.path.join(outdir, f"gen_lev{L}.inc"), src)
         for suffix, part in PARTS:
             path = os.path.join(outdir, f"gen_lev{L}{suffix}.hip")

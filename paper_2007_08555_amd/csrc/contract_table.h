@@ -1,0 +1,204 @@
+// Table-driven contraction of the moments of one atom (paper, section 2.1:
+// eqs. V_MTP and MTPbasisLevel8, the connected contractions and their
+// products), used for the bases whose straight-line kernels would be too
+// large to compile (levels 20 and 24).
+//
+// A connected contraction is a sum over index assignments of products of
+// symmetric moment components; the terms of one graph all have one factor
+// per vertex.  Sorting each term's factors and sharing common prefixes gives
+// a trie per graph: a node holds a component index k, an inner node the
+// range of its children, a leaf (depth D = number of vertices) the term's
+// integer weight.  With T(n) the value below node n (the weight at a leaf,
+// else the sum over children c of M[k_c] T(c)), the graph value is
+// T(root), and its derivative in M[k] is the sum over nodes n with k_n = k
+// of P(n) T(n), P(n) the product of M over n's strict ancestors.  One walk
+// in order gives the value; a second walk with P carried down and T
+// returned up accumulates dV/dM = sum_g dV/dg dg/dM.
+//
+// One thread per atom; the tables are read by every lane at the same index,
+// so the node loads are uniform across the wavefront.  M, G, the graph
+// values and dV/dg are [rows][stride] columns of the atom (Mi = M + i).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "mtp_device.h"
+
+namespace mtp {
+
+// A term weight (an integer, exact in FP64) in the arithmetic type.
+template <typename T>
+__device__ __forceinline__ T from_coef(double c);
+template <>
+__device__ __forceinline__ float from_coef<float>(double c) { return static_cast<float>(c); }
+template <>
+__device__ __forceinline__ double from_coef<double>(double c) { return c; }
+template <>
+__device__ __forceinline__ Dual<double> from_coef<Dual<double>>(double c) { return Dual<double>(c); }
+template <>
+__device__ __forceinline__ Dual<float> from_coef<Dual<float>>(double c) { return Dual<float>(static_cast<float>(c)); }
+
+// Value below the nodes [a, b) at depth L of a graph with D vertices.
+template <typename T, int L, int D, typename Tab, typename MLoad>
+__device__ T trie_value(int a, int b, const MLoad& mload) {
+  T s = T(0);
+  for (int n = a; n < b; ++n) {
+    const int4 nd = Tab::node()[n];
+    const T m = mload(nd.x);
+    if constexpr (L == D) {
+      s += from_coef<T>(Tab::coef()[nd.y]) * m;
+    } else {
+      s += m * trie_value<T, L + 1, D, Tab>(nd.y, nd.z, mload);
+    }
+  }
+  return s;
+}
+
+// As trie_value, and adds P(n) T(n) to the adjoint of M[k_n] for every node
+// (P = dV/dg times the product of the ancestors' moments).
+template <typename T, int L, int D, typename Tab, typename MLoad, typename GAdd>
+__device__ T trie_reverse(int a, int b, T P, const MLoad& mload, const GAdd& gadd) {
+  T s = T(0);
+  for (int n = a; n < b; ++n) {
+    const int4 nd = Tab::node()[n];
+    const T m = mload(nd.x);
+    T sub;
+    if constexpr (L == D) {
+      sub = from_coef<T>(Tab::coef()[nd.y]);
+    } else {
+      sub = trie_reverse<T, L + 1, D, Tab>(nd.y, nd.z, P * m, mload, gadd);
+    }
+    gadd(nd.x, P * sub);
+    s += m * sub;
+  }
+  return s;
+}
+
+// Graph values of every graph with D vertices (roots listed per depth).
+template <typename T, int D, typename Tab, typename MLoad, typename VStore>
+__device__ __forceinline__ void graphs_forward(const MLoad& mload, const VStore& vstore) {
+  if constexpr (D <= Tab::kDepth) {
+    for (int r = Tab::root_begin(D); r < Tab::root_begin(D + 1); ++r) {
+      const int4 e = Tab::roots()[r];
+      vstore(e.x, trie_value<T, 1, D, Tab>(e.y, e.z, mload));
+    }
+    graphs_forward<T, D + 1, Tab>(mload, vstore);
+  }
+}
+
+template <typename T, int D, typename Tab, typename MLoad, typename DgLoad, typename GAdd>
+__device__ __forceinline__ void graphs_reverse(const MLoad& mload, const DgLoad& dgload, const GAdd& gadd) {
+  if constexpr (D <= Tab::kDepth) {
+    for (int r = Tab::root_begin(D); r < Tab::root_begin(D + 1); ++r) {
+      const int4 e = Tab::roots()[r];
+      (void)trie_reverse<T, 1, D, Tab>(e.y, e.z, dgload(e.x), mload, gadd);
+    }
+    graphs_reverse<T, D + 1, Tab>(mload, dgload, gadd);
+  }
+}
+
+// Basis functions B_alpha = product of graph values (eq. MTPbasisLevel8 and
+// its generalisation), V = sum_alpha xi_alpha B_alpha, and dV/dg added to
+// the graphs' adjoints: for each function, prefix products times suffix
+// products give the product of the other factors.  bout(alpha, B) receives
+// every B.
+template <typename T, typename Tab, typename XiLoad, typename VLoad, typename DgAdd, typename BOut>
+__device__ __forceinline__ T basis_products(const XiLoad& xiload, const VLoad& vload, const DgAdd& dgadd,
+                                            const BOut& bout) {
+  constexpr int Q = Tab::kMaxFactors;
+  T V = T(0);
+  for (int a = 0; a < Tab::kM; ++a) {
+    const int f0 = Tab::func_off()[a];
+    const int q = Tab::func_off()[a + 1] - f0;
+    int g[Q];
+    T v[Q];
+#pragma unroll
+    for (int j = 0; j < Q; ++j) {
+      g[j] = j < q ? Tab::func_fac()[f0 + j] : 0;
+      v[j] = j < q ? vload(g[j]) : T(1);
+    }
+    T pre[Q + 1];
+    pre[0] = T(1);
+#pragma unroll
+    for (int j = 0; j < Q; ++j) pre[j + 1] = pre[j] * v[j];
+    const T B = pre[Q];
+    const T x = xiload(a);
+    V += x * B;
+    bout(a, B);
+    T suf = T(1);
+#pragma unroll
+    for (int j = Q - 1; j >= 0; --j) {
+      if (j < q) dgadd(g[j], x * (pre[j] * suf));
+      suf = suf * v[j];
+    }
+  }
+  return V;
+}
+
+// Forward contraction, basis products and reverse sweep of one atom per
+// thread: graph values to the upper half of D, B (when wanted), V to site,
+// dV/dg to the lower half of D, G = dV/dM.
+template <typename T, bool WANT_B, typename Tab>
+__global__ void __launch_bounds__(64) contract_table_kernel(const EvalArgs<T> args) {
+  const int i = blockIdx.x * 64 + threadIdx.x;
+  if (i >= args.n_atoms) return;
+  const size_t st = args.stride;
+  const T* Mi = args.M + i;
+  T* Gi = args.G + i;
+  T* Dg = args.D + i;
+  T* Dv = args.D + (size_t)Tab::kGraphs * st + i;
+  const auto mload = [&](int k) { return Mi[(size_t)k * st]; };
+  graphs_forward<T, 1, Tab>(mload, [&](int g, T v) { Dv[(size_t)g * st] = v; });
+  for (int g = 0; g < Tab::kGraphs; ++g) Dg[(size_t)g * st] = T(0);
+  const T V = basis_products<T, Tab>(
+      [&](int a) { return args.xi[a]; }, [&](int g) { return Dv[(size_t)g * st]; },
+      [&](int g, T v) { Dg[(size_t)g * st] += v; },
+      [&](int a, T B) {
+        if (WANT_B) args.B[(size_t)a * args.b_stride + i] = B;
+      });
+  args.site[i] = V;
+  for (int k = 0; k < Tab::kC; ++k) Gi[(size_t)k * st] = T(0);
+  graphs_reverse<T, 1, Tab>(mload, [&](int g) { return Dg[(size_t)g * st]; },
+                            [&](int k, T v) { Gi[(size_t)k * st] += v; });
+}
+
+// The same on dual numbers for the loss gradient: moments carry their
+// tangent along the displacement field (la.dM), so the forward walk gives
+// graph values and tangents, the products give a B_alpha + tangent of
+// B_alpha per atom (the xi part of the gradient) and dV/dg with its tangent,
+// and the reverse walk the tangent of G (la.dG).  la.gd holds four blocks of
+// n_graphs rows: values, their tangents, dV/dg, its tangent.
+template <typename R, typename Tab>
+__global__ void __launch_bounds__(64) contract_table_loss_kernel(const EvalArgs<R> args, const LossArgs<R> la) {
+  using T = Dual<R>;
+  const int i = blockIdx.x * 64 + threadIdx.x;
+  if (i >= args.n_atoms) return;
+  const size_t st = args.stride;
+  const size_t ng = Tab::kGraphs;
+  const R* Mi = args.M + i;
+  const R* dMi = la.dM + i;
+  R* gd = la.gd + i;
+  R* dGi = la.dG + i;
+  const R aw = la.a_atom[i];
+  const auto mload = [&](int k) { return T(Mi[(size_t)k * st], dMi[(size_t)k * st]); };
+  graphs_forward<T, 1, Tab>(mload, [&](int g, T v) {
+    gd[(size_t)g * st] = v.v;
+    gd[(ng + g) * st] = v.d;
+  });
+  for (size_t g = 0; g < ng; ++g) {
+    gd[(2 * ng + g) * st] = R(0);
+    gd[(3 * ng + g) * st] = R(0);
+  }
+  (void)basis_products<T, Tab>(
+      [&](int a) { return T(args.xi[a]); },
+      [&](int g) { return T(gd[(size_t)g * st], gd[(ng + g) * st]); },
+      [&](int g, T v) {
+        gd[(2 * ng + g) * st] += v.v;
+        gd[(3 * ng + g) * st] += v.d;
+      },
+      [&](int a, T B) { la.xi_terms[(size_t)a * st + i] = aw * B.v + B.d; });
+  for (int k = 0; k < Tab::kC; ++k) dGi[(size_t)k * st] = R(0);
+  graphs_reverse<T, 1, Tab>(mload, [&](int g) { return T(gd[(2 * ng + g) * st], gd[(3 * ng + g) * st]); },
+                            [&](int k, T v) { dGi[(size_t)k * st] += v.d; });
+}
+
+}  // namespace mtp

@@ -342,7 +342,7 @@ mtp::EvalArgs<T> make_args(mtp_model* M, int64_t n_atoms, int stride, const int3
 // one host synchronisation at the end to read the status (and a second pass
 // if an atom had more neighbours than the current capacity).
 int run_eval(mtp_model* M, const mtp_batch* bt, const mtp_out* out, int precision, hipStream_t s,
-             bool async = false) {
+             bool async = false, bool store_moments = false) {
   using namespace mtp;
   const int64_t N = bt->n_atoms;
   const int n_cfg = bt->n_configs;
@@ -390,7 +390,8 @@ int run_eval(mtp_model* M, const mtp_batch* bt, const mtp_out* out, int precisio
     NEED(M->own, sizeof(double) * 3 * (size_t)stride);
     NEED(M->Gbuf, tsz * (size_t)M->var->C * stride);
     NEED(M->Mbuf, tsz * (size_t)M->var->C * stride);
-    NEED(M->Dbuf, tsz * (size_t)M->var->n_graphs * stride);
+    // dV/dg per graph, then (table-driven bases) the graph values
+    NEED(M->Dbuf, tsz * 2 * (size_t)M->var->n_graphs * stride);
     NEED(M->site, tsz * stride);
     NEED(M->wv, tsz * 9 * stride);
     if (want_b) NEED(M->B, tsz * (size_t)M->m * stride);
@@ -467,14 +468,13 @@ int run_eval(mtp_model* M, const mtp_batch* bt, const mtp_out* out, int precisio
     }
     HIP_TRY(mark(1), "hipEventRecord");
     if (N > 0) {
+      const unsigned flags = (want_b ? kEvalWantB : 0u) | (store_moments ? kEvalStoreMoments : 0u);
       if (fp64) {
         auto ea = make_args<double>(M, N, stride, bt->species, want_b);
-        HIP_TRY(M->var->launch_eval(precision, want_b ? kEvalWantB : 0u, fp64 ? M->schedule64 : 0, &ea, s),
-                "evaluation kernels");
+        HIP_TRY(M->var->launch_eval(precision, flags, M->schedule64, &ea, s), "evaluation kernels");
       } else {
         auto ea = make_args<float>(M, N, stride, bt->species, want_b);
-        HIP_TRY(M->var->launch_eval(precision, want_b ? kEvalWantB : 0u, fp64 ? M->schedule64 : 0, &ea, s),
-                "evaluation kernels");
+        HIP_TRY(M->var->launch_eval(precision, flags, 0, &ea, s), "evaluation kernels");
       }
     }
     HIP_TRY(mark(2), "hipEventRecord");
@@ -690,6 +690,9 @@ int mtp_theta_rows(mtp_model* M, const mtp_batch* bt, int precision, double* row
   const int K_cfg = bt->n_configs;
   const int64_t N = bt->n_atoms;
   if (K_cfg <= 0) return fail(MTP_E_ARG, "mtp_theta_rows: empty batch");
+  if (!M->var->launch_loss)
+    return fail(MTP_E_BASIS, "mtp_theta_rows: the loss-gradient kernels are not compiled for level " +
+                                 std::to_string(M->level));
   HIP_TRY(M->lo_E.ensure(sizeof(double) * K_cfg), "hipMalloc");
   HIP_TRY(M->lo_W.ensure(sizeof(double) * 9 * K_cfg), "hipMalloc");
   HIP_TRY(M->lo_F.ensure(sizeof(double) * 3 * (N + 1)), "hipMalloc");
@@ -699,7 +702,7 @@ int mtp_theta_rows(mtp_model* M, const mtp_batch* bt, int precision, double* row
   o.forces = M->lo_F.as<double>();
   o.virial = M->lo_W.as<double>();
   o.b = M->th_b.as<double>();
-  int rc = run_eval(M, bt, &o, precision, s);
+  int rc = run_eval(M, bt, &o, precision, s, false, true);   // the loss kernels reread M
   if (rc != MTP_OK) return rc;
   const bool fp64 = precision == MTP_FP64;
   const size_t tsz = fp64 ? sizeof(double) : sizeof(float);
@@ -713,7 +716,7 @@ int mtp_theta_rows(mtp_model* M, const mtp_batch* bt, int precision, double* row
   HIP_TRY(M->lo_eps.ensure(tsz * 9 * stride), "hipMalloc");
   HIP_TRY(M->lo_dM.ensure(tsz * (size_t)C * stride), "hipMalloc");
   HIP_TRY(M->lo_dG.ensure(tsz * (size_t)C * stride), "hipMalloc");
-  HIP_TRY(M->lo_gd.ensure(tsz * 2 * (size_t)M->var->n_graphs * stride), "hipMalloc");
+  HIP_TRY(M->lo_gd.ensure(tsz * 4 * (size_t)M->var->n_graphs * stride), "hipMalloc");
   HIP_TRY(M->lo_xit.ensure(tsz * (size_t)M->m * stride), "hipMalloc");
   HIP_TRY(M->lo_pa.ensure(tsz * (size_t)M->n_mu * K * stride), "hipMalloc");
   HIP_TRY(M->lo_pb.ensure(tsz * (size_t)M->n_mu * K * stride), "hipMalloc");
@@ -1003,6 +1006,8 @@ int mtp_loss_grad(mtp_model* M, const mtp_batch* bt, const double* E_t, const do
   if (scaling < MTP_SCALE_MOLECULES || scaling > MTP_SCALE_VIBRATIONS) return fail(MTP_E_ARG, "mtp_loss_grad: bad scaling");
   if (precision != MTP_FP64 && precision != MTP_FP32) return fail(MTP_E_ARG, "mtp_loss_grad: precision must be FP64 or FP32");
   if (!(w_e >= 0 && w_f >= 0 && w_s >= 0)) return fail(MTP_E_ARG, "mtp_loss_grad: weights must be non-negative");
+  if (!M->var->launch_loss)
+    return fail(MTP_E_BASIS, "mtp_loss_grad: the loss gradient is not compiled for level " + std::to_string(M->level));
   HIP_TRY(hipSetDevice(M->device), "hipSetDevice");
   hipStream_t s = (hipStream_t)stream;
   const int K_cfg = bt->n_configs;
@@ -1015,7 +1020,7 @@ int mtp_loss_grad(mtp_model* M, const mtp_batch* bt, const double* E_t, const do
   o.energy = M->lo_E.as<double>();
   o.forces = M->lo_F.as<double>();
   o.virial = M->lo_W.as<double>();
-  int rc = run_eval(M, bt, &o, precision, s);
+  int rc = run_eval(M, bt, &o, precision, s, false, true);   // the loss kernels reread M
   if (rc != MTP_OK) return rc;
   const bool fp64 = precision == MTP_FP64;
   const size_t tsz = fp64 ? sizeof(double) : sizeof(float);
@@ -1029,7 +1034,7 @@ int mtp_loss_grad(mtp_model* M, const mtp_batch* bt, const double* E_t, const do
   HIP_TRY(M->lo_eps.ensure(tsz * 9 * stride), "hipMalloc");
   HIP_TRY(M->lo_dM.ensure(tsz * (size_t)C * stride), "hipMalloc");
   HIP_TRY(M->lo_dG.ensure(tsz * (size_t)C * stride), "hipMalloc");
-  HIP_TRY(M->lo_gd.ensure(tsz * 2 * (size_t)M->var->n_graphs * stride), "hipMalloc");
+  HIP_TRY(M->lo_gd.ensure(tsz * 4 * (size_t)M->var->n_graphs * stride), "hipMalloc");
   HIP_TRY(M->lo_xit.ensure(tsz * (size_t)M->m * stride), "hipMalloc");
   HIP_TRY(M->lo_pa.ensure(tsz * (size_t)M->n_mu * K * stride), "hipMalloc");
   HIP_TRY(M->lo_pb.ensure(tsz * (size_t)M->n_mu * K * stride), "hipMalloc");
@@ -1105,7 +1110,7 @@ int mtp_normal_equations(mtp_model* M, const mtp_batch* bt, const double* E_t, c
   hipStream_t s = (hipStream_t)stream;
   // neighbour lists and moments at the current c (nothing written out)
   mtp_out none{};
-  int rc = run_eval(M, bt, &none, precision, s);
+  int rc = run_eval(M, bt, &none, precision, s, false, true);   // the columns reuse M
   if (rc != MTP_OK) return rc;
   const bool fp64 = precision == MTP_FP64;
   const size_t tsz = fp64 ? sizeof(double) : sizeof(float);

@@ -6,8 +6,10 @@
 namespace mtp {
 
 // Flags of launch_eval: also write every B_alpha; keep the moments already in
-// args.M (same pairs and radial coefficients) instead of recomputing them.
-enum : unsigned { kEvalWantB = 1u, kEvalReuseMoments = 2u };
+// args.M (same pairs and radial coefficients) instead of recomputing them;
+// leave the moments in args.M (schedules that keep them in registers skip
+// that store otherwise) for a later reuse or for the loss kernels.
+enum : unsigned { kEvalWantB = 1u, kEvalReuseMoments = 2u, kEvalStoreMoments = 4u };
 
 struct BasisVariant {
   const char* name;

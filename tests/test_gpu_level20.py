@@ -1,7 +1,7 @@
 """Level 20 (the training workload's basis: 460 functions, 295 moment
-components), when the library was built with it (MTP_EXTRA_LEVELS=20):
-evaluation and the loss gradient against the FP64 oracle, with targets from
-a seeded reference potential plus N(0, 1e-3^2) noise."""
+components; table-driven contraction): evaluation and the loss gradient
+against the FP64 oracle, with targets from a seeded reference potential plus
+N(0, 1e-3^2) noise."""
 import numpy as np
 import pytest
 
@@ -19,11 +19,7 @@ TOL64 = {"energy_per_atom": 1e-11, "site": 1e-11, "force": 1e-10, "virial": 1e-9
 @pytest.fixture(scope="module")
 def lev20():
     from paper_2007_08555_amd import Potential
-    from paper_2007_08555_amd._lib import MTPError
-    try:
-        return Potential(pot_path("lev20_s3"))
-    except MTPError as e:
-        pytest.skip(f"level 20 is not compiled into this library ({e})")
+    return Potential(pot_path("lev20_s3"))
 
 
 def test_level20_evaluation(lev20):

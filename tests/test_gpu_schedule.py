@@ -44,3 +44,29 @@ def test_every_schedule_matches_the_oracle_and_autotune_picks_one():
     chosen32, ms32 = P.autotune(Batch.from_arrays(batch), precision="fp32")
     assert chosen32 == 0 and len(ms32) == 1
     torch.cuda.synchronize()
+
+
+def test_every_schedule_feeds_the_loss_and_normal_equations():
+    """The loss gradient and the normal equations reread the moments the
+    evaluation leaves in memory: every schedule, including the one that keeps
+    them in registers, must give the same results as schedule 0."""
+    from paper_2007_08555_amd import Batch, Potential
+    P = Potential(pot_path("lev16_s3"))
+    batch = synth.mixed_batch(seed=43, n_configs=8, n_min=8, n_max=40, n_species_model=3)
+    B = Batch.from_arrays(batch)
+    P.set_schedule(0)
+    ref = P.eval(B, precision="fp64")
+    rng = np.random.default_rng(2)
+    Et = ref["energy"].cpu().numpy() + rng.normal(0, 1e-3, len(batch["n_atoms"]))
+    Ft = ref["forces"].cpu().numpy() + rng.normal(0, 1e-3, ref["forces"].shape)
+    Wt = ref["virial"].cpu().numpy() + rng.normal(0, 1e-3, ref["virial"].shape)
+    out = {}
+    for k in range(P.n_schedules):
+        P.set_schedule(k)
+        loss, grad = P.loss_grad(B, Et, Ft, Wt, precision="fp64")
+        H, g, yy = P.normal_equations(B, Et, Ft, Wt)
+        out[k] = [t.cpu().numpy() for t in (loss, grad, H, g, yy)]
+        log(f"[schedule {k}] loss {out[k][0][0]:.12e}")
+    for k in range(1, P.n_schedules):
+        for a, b in zip(out[k], out[0]):
+            assert np.allclose(a, b, rtol=1e-11, atol=1e-11 * np.abs(b).max()), k
