@@ -69,8 +69,8 @@ def training_level20():
     pdir = os.path.join(ROOT, "tests", "golden", "potentials")
     try:
         P = Potential(os.path.join(pdir, "lev20_s3.mtp"))
-    except MTPError:
-        return {"note": "level 20 is not compiled into this build (MTP_EXTRA_LEVELS=20 adds it)"}
+    except MTPError as e:
+        return {"error": str(e)}
     return training_extras(P, os.path.join(pdir, "lev20_s3.mtp"), "fp64",
                            ref_path=os.path.join(pdir, "lev20_s3_ref.mtp"))
 
@@ -236,30 +236,37 @@ def plain_path(P, batch, precision, stream):
                     "one synchronisation at the end; median of 3 passes over the batch"}
 
 
-def precision_study(stream):
+def precision_study(stream, level=24):
     """The 256 000-atom disordered fcc alloy (40^3 cells, a = 3.6 A, sigma =
-    0.2 A, three species) at level 16: throughput of FP64, FP32 and FP32
-    with compensated moment sums, and the FP32 errors against the FP64 path
-    (which the tests pin to the oracle) over every atom."""
+    0.2 A, three species) at the given level (24: the workload's own basis,
+    table-driven contraction; 16: the headline's basis): throughput of FP64,
+    FP32 and FP32 with compensated moment sums, the FP32 errors against the
+    FP64 path (which the tests pin to the oracle) over every atom, and the
+    FP64 oracle's own rate on a few site energies of the same box."""
     import numpy as np
     import torch
+    from threadpoolctl import threadpool_limits
 
     import synth
+    from oracle import mtp as omtp
+    from oracle.potential import read_potential
     from paper_2007_08555_amd import Batch, Potential
     box = synth.fcc_alloy(seed=0)
     N = int(box["n_atoms"][0])
-    P = Potential(os.path.join(ROOT, "tests", "golden", "potentials", "lev16_s3.mtp"), device=0)
+    path = os.path.join(ROOT, "tests", "golden", "potentials", f"lev{level}_s3.mtp")
+    P = Potential(path, device=0)
     B = Batch.from_arrays(box, "cuda:0")
-    res, outs = {"workload": f"{N}-atom periodic disordered fcc alloy, 3 species, level 16 (E, F, virial)"}, {}
+    res, outs = {"workload": f"{N}-atom periodic disordered fcc alloy, 3 species, level {level} (E, F, virial)"}, {}
+    reps = 5 if level <= 16 else 2
     for p in ("fp64", "fp32", "fp32c"):
-        for _ in range(2):
+        for _ in range(2 if level <= 16 else 1):
             P.eval(B, precision=p, stream=stream)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for _ in range(5):
+        for _ in range(reps):
             out = P.eval(B, precision=p, site=True, stream=stream)
         torch.cuda.synchronize()
-        dt = (time.perf_counter() - t0) / 5
+        dt = (time.perf_counter() - t0) / reps
         outs[p] = {k: v.cpu().numpy() for k, v in out.items()}
         res[p] = {"value": N / dt, "unit": "atom-evals/s", "ms_per_step": dt * 1e3}
     r64 = outs["fp64"]
@@ -268,9 +275,22 @@ def precision_study(stream):
             "energy_per_atom_eV": abs(float(outs[p]["energy"][0]) - float(r64["energy"][0])) / N,
             "site_max_eV": float(np.abs(outs[p]["site"] - r64["site"]).max()),
             "force_max_eV_per_A": float(np.abs(outs[p]["forces"] - r64["forces"]).max()),
+            "virial_per_atom_eV": float(np.abs(outs[p]["virial"] - r64["virial"]).max()) / N,
             "largest_force_eV_per_A": float(np.abs(r64["forces"]).max())}
         res[p]["vs_fp64"]["force_rel"] = res[p]["vs_fp64"]["force_max_eV_per_A"] / \
             res[p]["vs_fp64"]["largest_force_eV_per_A"]
+    if level > 16:
+        # the oracle on one host thread: site energies of a few seeded atoms
+        pot = read_potential(path)
+        atoms = np.sort(np.random.default_rng(1).choice(N, size=8, replace=False))
+        with threadpool_limits(limits=1):
+            t0 = time.perf_counter()
+            site, _ = omtp.evaluate_sampled(pot, *synth.config_of(box, 0), atoms, [], chunk=8)
+            dt = time.perf_counter() - t0
+        res["oracle"] = {"value": len(atoms) / dt, "unit": "site energies/s", "cores": 1,
+                         "sample": f"site energies of {len(atoms)} seeded atoms of the box (no forces), FP64, "
+                                   f"{dt:.1f} s on one host thread",
+                         "site_max_abs_diff_vs_gpu_fp64_eV": float(np.abs(site - r64["site"][atoms]).max())}
     return res
 
 
@@ -398,6 +418,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-extras", action="store_true", help="skip plain path, bcc box and CPU baseline")
     ap.add_argument("--no-graph", action="store_true", help="time eager calls instead of HIP-graph replays")
+    ap.add_argument("--schedule", type=int, default=-1,
+                    help="FP64 schedule of the evaluation kernels (default: the autotuner's choice)")
     ap.add_argument("--batch-cache", default="",
                     help="npz file holding the generated batch (written if missing, read if present)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -443,6 +465,9 @@ def main():
     # the library's autotuner picks the FP64 pass split for this batch
     t_at = time.perf_counter()
     chosen, sched_ms = P.autotune(B, precision=a.precision, repeats=3)
+    if a.schedule >= 0:
+        P.set_schedule(a.schedule, precision=a.precision)
+        chosen = a.schedule
     log(f"autotune: schedule {chosen} of {len(sched_ms)} ({', '.join(f'{t:.3f}' for t in sched_ms)} ms "
         f"evaluation kernels), {time.perf_counter() - t_at:.2f} s")
 
@@ -604,8 +629,10 @@ def main():
         line["fp32_accuracy"]["bcc16000"] = fp32_accuracy(P2b, synth.bcc_alloy(seed=0), stream)
         del P2b
         log(f"fp32 accuracy: {line['fp32_accuracy']}")
-        line["precision_study"] = precision_study(stream)
+        line["precision_study"] = precision_study(stream, level=24)
         log(f"precision study: {line['precision_study']}")
+        line["precision_study_level16"] = precision_study(stream, level=16)
+        log(f"precision study, level 16: {line['precision_study_level16']}")
         line["training"] = training_extras(P, pot_path, a.precision)
         log(f"training: {line['training']}")
         line["active_learning"] = active_learning_extras(P, batch)

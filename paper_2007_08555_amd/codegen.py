@@ -246,18 +246,26 @@ def graph_groups(s, budget):
 
 MOMENTS_TEMPLATE = r"""
 // Moments pass {pidx}: the components of degrees {nus} of one atom, summed
-// over its pairs and written to args.M.
+// over its pairs and written to args.M; {split} thread(s) per atom, each over
+// every {split}-th pair, partial sums combined across those lanes.
 template <typename T, bool COMP, int NQ>
-__global__ void __launch_bounds__(BLOCK) moments_{tag}_kernel(const mtp::EvalArgs<T> args) {{
+__global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2)))
+moments_{tag}_kernel(const mtp::EvalArgs<T> args) {{
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* cs = reinterpret_cast<T*>(smem_raw);
-  for (int t = threadIdx.x; t < args.n_c; t += blockDim.x) cs[t] = args.c[t];
+  for (int t = threadIdx.x; t < args.n_c; t += blockDim.x) cs[t + t / args.nq] = args.c[t];
   __syncthreads();
-  const int i = blockIdx.x * BLOCK + threadIdx.x;
+  constexpr int SPLIT = {split};
+  const int tid = blockIdx.x * BLOCK + threadIdx.x;
+  const int i = tid / SPLIT;
+  const int h = tid - i * SPLIT;
   if (i >= args.n_atoms) return;
   const int S = args.n_species;
   const int nq = args.nq;
-  const int mu_stride = S * S * nq;
+  // c in LDS with one pad slot after every (z_i, z_j) block of N_Q values, so
+  // that lanes of different species pairs read different banks
+  const int nqp = nq + 1;
+  const int mu_stride = S * S * nqp;
   const int zi = clamp_species(args.species[i], S);
   const int cnt = args.nbr_count[i];
   const T rmin = args.rmin, rcut = args.rcut;
@@ -270,31 +278,42 @@ __global__ void __launch_bounds__(BLOCK) moments_{tag}_kernel(const mtp::EvalArg
   for (int k = 0; k < CP; ++k) M[k] = T(0);
 #pragma unroll
   for (int k = 0; k < (COMP ? CP : 1); ++k) Mlo[k] = T(0);
-  // pair p + 1 is loaded while pair p is processed
+  // pair p + SPLIT is loaded while pair p is processed
   T xn = T(0), yn = T(0), zn = T(0);
   int zjn = 0;
-  if (cnt > 0) {{
-    const mtp::PairRec<T> q = args.pr[i];
+  if (h < cnt) {{
+    const mtp::PairRec<T> q = args.pr[(size_t)h * args.stride + i];
     xn = q.x; yn = q.y; zn = q.z; zjn = q.zj;
   }}
 #pragma unroll 1
-  for (int p = 0; p < cnt; ++p) {{
+  for (int p = h; p < cnt; p += SPLIT) {{
     const T x = xn, y = yn, z = zn;
     const int zj = zjn;
-    if (p + 1 < cnt) {{
-      const size_t en = (size_t)(p + 1) * args.stride + i;
+    if (p + SPLIT < cnt) {{
+      const size_t en = (size_t)(p + SPLIT) * args.stride + i;
       const mtp::PairRec<T> q = args.pr[en];
       xn = q.x; yn = q.y; zn = q.z; zjn = q.zj;
     }}
     const T r = sqrt(x * x + y * y + z * z);
     T f[NMP], df[NMP];
-    mtp::radial<T, NMP, false, NQ>(cs, (zi * S + zj) * nq, mu_stride, nq, r, rmin, rcut, f, df);
+    mtp::radial<T, NMP, false, NQ>(cs, (zi * S + zj) * nqp, mu_stride, nq, r, rmin, rcut, f, df);
 {body}
   }}
   if constexpr (COMP) {{
 #pragma unroll
     for (int k = 0; k < CP; ++k) M[k] += Mlo[k];
   }}
+  if constexpr (SPLIT > 1) {{
+    // one component at a time (the empty asm ties each sum to the next
+    // component), so that the lane moves of all components are not in
+    // flight at once
+#pragma unroll
+    for (int k = 0; k < CP; ++k) {{
+      M[k] = mtp::group_sum<SPLIT>(M[k]);
+      if (k + 1 < CP) asm volatile("" : "+v"(M[k]), "+v"(M[k + 1]));
+    }}
+  }}
+  if (h != 0) return;
 #pragma unroll
   for (int k = 0; k < CP; ++k) args.M[(size_t)kIdx[k] * args.stride + i] = M[k];
 }}
@@ -306,6 +325,9 @@ def emit_contraction(s):
     out = []
     ops = 0
     # forward: graph values
+    # (each graph value is handed out as soon as it is complete: the
+    # per-configuration descriptor sums b are formed from them by the
+    # reduction kernels)
     for g, terms in enumerate(s.terms):
         out.append(f"T g{g} = T(0);")
         for coef, idx in terms:
@@ -315,6 +337,7 @@ def emit_contraction(s):
                 expr = f"{_const(coef)} * {expr}"
             out.append(f"g{g} += {expr};")
             ops += len(idx) + (1 if coef != 1 else 0)
+        out.append(f"MTP_OUT_GV({g}, g{g});")
     # basis functions and V
     out.append("T V = T(0);")
     for a, fn in enumerate(s.funcs):
@@ -460,6 +483,11 @@ def emit_pair_backward(s, nus=None, gmap=None, nmu=None):
     return out, ops
 
 
+def _grid(split):
+    """Launch grid of a per-pair pass with `split` threads per atom."""
+    return "grid" if split == 1 else f"dim3((args.n_atoms * {split} + BLOCK - 1) / BLOCK)"
+
+
 def adjoint_passes(s, budget):
     """Degrees grouped into passes of at most `budget` components (a degree
     is never split); one pass when everything fits."""
@@ -489,13 +517,16 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(1, 1
 fused_{tag}_kernel(const mtp::EvalArgs<T> args) {{
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* cs = reinterpret_cast<T*>(smem_raw);
-  for (int t = threadIdx.x; t < args.n_c; t += blockDim.x) cs[t] = args.c[t];
+  for (int t = threadIdx.x; t < args.n_c; t += blockDim.x) cs[t + t / args.nq] = args.c[t];
   __syncthreads();
   const int i = blockIdx.x * BLOCK + threadIdx.x;
   if (i >= args.n_atoms) return;
   const int S = args.n_species;
   const int nq = args.nq;
-  const int mu_stride = S * S * nq;
+  // c in LDS with one pad slot after every (z_i, z_j) block of N_Q values, so
+  // that lanes of different species pairs read different banks
+  const int nqp = nq + 1;
+  const int mu_stride = S * S * nqp;
   const int zi = clamp_species(args.species[i], S);
   const int cnt = args.nbr_count[i];
   const T rmin = args.rmin, rcut = args.rcut;
@@ -522,7 +553,7 @@ fused_{tag}_kernel(const mtp::EvalArgs<T> args) {{
     }}
     const T r = sqrt(x * x + y * y + z * z);
     T f[NMU], df[NMU];
-    mtp::radial<T, NMU, false, NQ>(cs, (zi * S + zj) * nq, mu_stride, nq, r, rmin, rcut, f, df);
+    mtp::radial<T, NMU, false, NQ>(cs, (zi * S + zj) * nqp, mu_stride, nq, r, rmin, rcut, f, df);
 {moments}
   }}
   if constexpr (STORE_M) {{
@@ -530,13 +561,21 @@ fused_{tag}_kernel(const mtp::EvalArgs<T> args) {{
     for (int k = 0; k < C; ++k) args.M[(size_t)k * args.stride + i] = M[k];
   }}
   const T* __restrict__ xi = args.xi;
-#define MTP_OUT_B(a_, v_) do {{ if (WANT_B) args.B[(size_t)(a_) * args.b_stride + i] = (v_); }} while (0)
-#define MTP_OUT_G(k_, v_) args.G[(size_t)(k_) * args.stride + i] = (v_)
+  // outputs in row order through running pointers (graph values g = 0, 1,
+  // ...; G for k = 0, 1, ...), so that no per-row address stays live
+  T* gvp = WANT_B ? args.B + i : nullptr;
+  const size_t gvst = args.b_stride;
+  T* gp = args.G + i;
+  const size_t gst = args.stride;
+#define MTP_OUT_GV(g_, v_) do {{ if (WANT_B) {{ *gvp = (v_); gvp += gvst; }} }} while (0)
+#define MTP_OUT_B(a_, v_) do {{ }} while (0)
+#define MTP_OUT_G(k_, v_) do {{ *gp = (v_); gp += gst; }} while (0)
 #define MTP_RELOAD_M() mtp::opaque(M)
 {contraction}
 #undef MTP_RELOAD_M
 #undef MTP_OUT_G
 #undef MTP_OUT_B
+#undef MTP_OUT_GV
   args.site[i] = V;
 }}
 """
@@ -547,19 +586,27 @@ ADJOINT_TEMPLATE = r"""
 // its share of g = dV_i/dr_ij from G, f_mu and df_mu/dr, stored (first pass)
 // or added (later passes) per pair for the force and virial gather; the
 // last pass also sums the atom's own share of its force, sum_p g_p, in FP64,
-// so that the gather only has to fetch the reverse pairs' g.
+// so that the gather only has to fetch the reverse pairs' g.  {split}
+// thread(s) per atom, each over every {split}-th pair (the per-atom sums are
+// combined across those lanes).
 template <typename T, bool FIRST, bool LAST, int NQ>
 __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2)))
 adjoint_{tag}_kernel(const mtp::EvalArgs<T> args) {{
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* cs = reinterpret_cast<T*>(smem_raw);
-  for (int t = threadIdx.x; t < args.n_c; t += blockDim.x) cs[t] = args.c[t];
+  for (int t = threadIdx.x; t < args.n_c; t += blockDim.x) cs[t + t / args.nq] = args.c[t];
   __syncthreads();
-  const int i = blockIdx.x * BLOCK + threadIdx.x;
+  constexpr int SPLIT = {split};
+  const int tid = blockIdx.x * BLOCK + threadIdx.x;
+  const int i = tid / SPLIT;
+  const int h = tid - i * SPLIT;
   if (i >= args.n_atoms) return;
   const int S = args.n_species;
   const int nq = args.nq;
-  const int mu_stride = S * S * nq;
+  // c in LDS with one pad slot after every (z_i, z_j) block of N_Q values, so
+  // that lanes of different species pairs read different banks
+  const int nqp = nq + 1;
+  const int mu_stride = S * S * nqp;
   const int zi = clamp_species(args.species[i], S);
   const int cnt = args.nbr_count[i];
   const T rmin = args.rmin, rcut = args.rcut;
@@ -571,22 +618,23 @@ adjoint_{tag}_kernel(const mtp::EvalArgs<T> args) {{
   // the last pass also sums the per-atom virial sum_p g_p (x) r_p and sum_p g_p
   double o0 = 0.0, o1 = 0.0, o2 = 0.0;
   T w0 = T(0), w1 = T(0), w2 = T(0), w3 = T(0), w4 = T(0), w5 = T(0), w6 = T(0), w7 = T(0), w8 = T(0);
-  // pair p + 1 (and its partial g) is loaded while pair p is processed
+  // pair p + SPLIT (and its partial g) is loaded while pair p is processed
   T xn = T(0), yn = T(0), zn = T(0), g0n = T(0), g1n = T(0), g2n = T(0);
   int zjn = 0;
-  if (cnt > 0) {{
-    const mtp::PairRec<T> q = args.pr[i];
+  if (h < cnt) {{
+    const size_t e0 = (size_t)h * args.stride + i;
+    const mtp::PairRec<T> q = args.pr[e0];
     xn = q.x; yn = q.y; zn = q.z; zjn = q.zj;
-    if (!FIRST) {{ g0n = args.g[3 * (size_t)i]; g1n = args.g[3 * (size_t)i + 1]; g2n = args.g[3 * (size_t)i + 2]; }}
+    if (!FIRST) {{ g0n = args.g[3 * e0]; g1n = args.g[3 * e0 + 1]; g2n = args.g[3 * e0 + 2]; }}
   }}
 #pragma unroll 1
-  for (int p = 0; p < cnt; ++p) {{
+  for (int p = h; p < cnt; p += SPLIT) {{
     const size_t e = (size_t)p * args.stride + i;
     const T x = xn, y = yn, z = zn;
     const int zj = zjn;
     const T gp0 = g0n, gp1 = g1n, gp2 = g2n;
-    if (p + 1 < cnt) {{
-      const size_t en = e + args.stride;
+    if (p + SPLIT < cnt) {{
+      const size_t en = e + (size_t)SPLIT * args.stride;
       const mtp::PairRec<T> q = args.pr[en];
       xn = q.x; yn = q.y; zn = q.z; zjn = q.zj;
       if (!FIRST) {{ g0n = args.g[3 * en]; g1n = args.g[3 * en + 1]; g2n = args.g[3 * en + 2]; }}
@@ -594,7 +642,7 @@ adjoint_{tag}_kernel(const mtp::EvalArgs<T> args) {{
     const T r = sqrt(x * x + y * y + z * z);
     const T inv_r = T(1) / r;
     T f[{nmu}], df[{nmu}];
-    mtp::radial<T, {nmu}, true, NQ>(cs, (zi * S + zj) * nq, mu_stride, nq, r, rmin, rcut, f, df);
+    mtp::radial<T, {nmu}, true, NQ>(cs, (zi * S + zj) * nqp, mu_stride, nq, r, rmin, rcut, f, df);
 {body}
     const T tx = FIRST ? gx : gp0 + gx, ty = FIRST ? gy : gp1 + gy, tz = FIRST ? gz : gp2 + gz;
     args.g[3 * e] = tx;
@@ -607,7 +655,13 @@ adjoint_{tag}_kernel(const mtp::EvalArgs<T> args) {{
       o0 += (double)tx; o1 += (double)ty; o2 += (double)tz;
     }}
   }}
-  if constexpr (LAST) {{
+  if constexpr (LAST && SPLIT > 1) {{
+    w0 = mtp::group_sum<SPLIT>(w0); w1 = mtp::group_sum<SPLIT>(w1); w2 = mtp::group_sum<SPLIT>(w2);
+    w3 = mtp::group_sum<SPLIT>(w3); w4 = mtp::group_sum<SPLIT>(w4); w5 = mtp::group_sum<SPLIT>(w5);
+    w6 = mtp::group_sum<SPLIT>(w6); w7 = mtp::group_sum<SPLIT>(w7); w8 = mtp::group_sum<SPLIT>(w8);
+    o0 = mtp::group_sum<SPLIT>(o0); o1 = mtp::group_sum<SPLIT>(o1); o2 = mtp::group_sum<SPLIT>(o2);
+  }}
+  if (LAST && h == 0) {{
     T* wv = args.atom_virial + i;
     const size_t st = args.stride;
     wv[0] = w0; wv[st] = w1; wv[2 * st] = w2; wv[3 * st] = w3; wv[4 * st] = w4;
@@ -696,13 +750,16 @@ def pass_mus(s, nus):
 LOSS_PASS_HEAD = r"""
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* cs = reinterpret_cast<T*>(smem_raw);
-  for (int t = threadIdx.x; t < args.n_c; t += blockDim.x) cs[t] = args.c[t];
+  for (int t = threadIdx.x; t < args.n_c; t += blockDim.x) cs[t + t / args.nq] = args.c[t];
   __syncthreads();
   const int i = blockIdx.x * BLOCK + threadIdx.x;
   if (i >= args.n_atoms) return;
   const int S = args.n_species;
   const int nq = args.nq;
-  const int mu_stride = S * S * nq;
+  // c in LDS with one pad slot after every (z_i, z_j) block of N_Q values, so
+  // that lanes of different species pairs read different banks
+  const int nqp = nq + 1;
+  const int mu_stride = S * S * nqp;
   const int zi = clamp_species(args.species[i], S);
   const int cnt = args.nbr_count[i];
   const T rmin = args.rmin, rcut = args.rcut;
@@ -726,7 +783,7 @@ LOSS_PAIR_HEAD = r"""
     const T r = sqrt(x * x + y * y + z * z);
     const T inv_r = T(1) / r;
     T f[NMU], df[NMU];
-    mtp::radial<T, NMU, true>(cs, (zi * S + zj) * nq, mu_stride, nq, r, rmin, rcut, f, df);
+    mtp::radial<T, NMU, true>(cs, (zi * S + zj) * nqp, mu_stride, nq, r, rmin, rcut, f, df);
 """
 
 
@@ -884,8 +941,9 @@ __device__ __forceinline__ int clamp_species(int z, int S) {{ return z < 0 ? 0 :
 
 #if MTP_PART == 1 || MTP_PART == 2
 {moments_kernels}
-// Forward contractions of one atom's moments: graph values, V, optional B,
-// and dV/dg of every connected graph g (to args.D).
+// Forward contractions of one atom's moments: graph values (to args.B when
+// the descriptor sums are wanted), V, and dV/dg of every connected graph g
+// (to args.D).
 template <typename T, bool WANT_B>
 __global__ void __launch_bounds__(BLOCK) contract_fwd_kernel(const mtp::EvalArgs<T> args) {{
   const int i = blockIdx.x * BLOCK + threadIdx.x;
@@ -894,9 +952,11 @@ __global__ void __launch_bounds__(BLOCK) contract_fwd_kernel(const mtp::EvalArgs
   T M[C];
 #pragma unroll
   for (int k = 0; k < C; ++k) M[k] = args.M[(size_t)k * args.stride + i];
-#define MTP_OUT_B(a_, v_) do {{ if (WANT_B) args.B[(size_t)(a_) * args.b_stride + i] = (v_); }} while (0)
+#define MTP_OUT_GV(g_, v_) do {{ if (WANT_B) args.B[(size_t)(g_) * args.b_stride + i] = (v_); }} while (0)
+#define MTP_OUT_B(a_, v_) do {{ }} while (0)
 {contraction_fwd}
 #undef MTP_OUT_B
+#undef MTP_OUT_GV
 {store_dg}
   args.site[i] = V;
 }}
@@ -913,7 +973,7 @@ hipError_t launch_loss_t(const void* a, const void* l, hipStream_t s) {{
   const auto& la = *static_cast<const mtp::LossArgs<T>*>(l);
   if (args.n_atoms <= 0) return hipSuccess;
   const dim3 grid((args.n_atoms + BLOCK - 1) / BLOCK);
-  const size_t smem = (size_t)args.n_c * sizeof(T);
+  const size_t smem = (size_t)(args.n_c + args.n_c / args.nq) * sizeof(T);   // c, padded
 {launch_loss}
   return hipGetLastError();
 }}
@@ -926,7 +986,7 @@ hipError_t launch_t(const void* a, bool reuse_moments, bool store_moments, int s
   (void)store_moments;
   if (args.n_atoms <= 0) return hipSuccess;
   const dim3 grid((args.n_atoms + BLOCK - 1) / BLOCK);
-  const size_t smem = (size_t)args.n_c * sizeof(T);
+  const size_t smem = (size_t)(args.n_c + args.n_c / args.nq) * sizeof(T);   // c, padded
 #if MTP_PART == 1
 {launch_body64}
 #else
@@ -1030,6 +1090,12 @@ SCHEDULES_F64 = [
     # moments, contractions and reverse sweep in one kernel (M, dV/dg never
     # leave the registers), then the adjoint passes
     {"fused": True, "adj": 90},
+    # schedule 0 with two and four threads per atom in the moments and adjoint
+    # passes (each over every second / fourth pair): more wavefronts in flight
+    {"mom": 85, "rev": [(0, 1, 2), (3, 4), (5, 6)], "adj": 90, "split": 2},
+    {"mom": 85, "rev": [(0, 1, 2), (3, 4), (5, 6)], "adj": 90, "split": 4},
+    # the fused schedule with two threads per atom in its adjoint passes
+    {"fused": True, "adj": 90, "split": 2},
 ]
 SCHEDULE_F32 = {"mom": 10 ** 9, "rev": [tuple(range(64))], "adj": 10 ** 9}
 
@@ -1059,13 +1125,13 @@ def generate(lev_max, block=64):
                 gmap = {k: j for j, k in enumerate(comps)}
                 nmu = 1 + max(mu for (mu, nu, abc), k in s.comp.items() if nu in nus)
                 body, _ = emit_pair_backward(s, nus=nus, gmap=gmap, nmu=nmu)
-                kern_src[prec].append(ADJOINT_TEMPLATE.format(pidx=pidx, nus=nus, tag=ptag, ncomp=len(comps), nmu=nmu,
+                kern_src[prec].append(ADJOINT_TEMPLATE.format(split=sch.get("split", 1), pidx=pidx, nus=nus, tag=ptag, ncomp=len(comps), nmu=nmu,
                                                               comp_list=", ".join(map(str, comps)),
                                                               body="\n".join(" " * 4 + l for l in body)))
                 first = "true" if pidx == 0 else "false"
                 last = "true" if pidx == len(passes) - 1 else "false"
                 adj_lines.append(f"hipLaunchKernelGGL((adjoint_{ptag}_kernel<T, {first}, {last}, NQ>), "
-                                 f"grid, dim3(BLOCK), smem, s, args);")
+                                 f"{_grid(sch.get('split', 1))}, dim3(BLOCK), smem, s, args);")
             # the reread of stored moments (normal equations) runs the
             # contraction of schedule 0 from them
             body = (["if (reuse_moments) {",
@@ -1084,11 +1150,11 @@ def generate(lev_max, block=64):
             kmap = {k: j for j, k in enumerate(comps)}
             body, _ = emit_pair_forward(s, comp_mode=True, nus=set(nus), kmap=kmap)
             nmu = 1 + max(mu for (mu, nu, abc), k in s.comp.items() if nu in nus)
-            kern_src[prec].append(MOMENTS_TEMPLATE.format(pidx=pidx, nus=nus, tag=tag, ncomp=len(comps), nmu=nmu,
+            kern_src[prec].append(MOMENTS_TEMPLATE.format(split=sch.get("split", 1), pidx=pidx, nus=nus, tag=tag, ncomp=len(comps), nmu=nmu,
                                                     comp_list=", ".join(map(str, comps)),
                                                     body="\n".join(" " * 4 + l for l in body)))
             # (the moments passes measured no faster with the unrolled radial basis)
-            mom_lines.append(f"hipLaunchKernelGGL((moments_{tag}_kernel<T, COMP, 0>), grid, dim3(BLOCK), smem, s, args);")
+            mom_lines.append(f"hipLaunchKernelGGL((moments_{tag}_kernel<T, COMP, 0>), {_grid(sch.get('split', 1))}, dim3(BLOCK), smem, s, args);")
         # reverse sweep passes by degree groups: each pass holds only the
         # moments and dV/dg its components need
         groups = [tuple(n for n in grp if n <= s.nu_max) for grp in sch["rev"]]
@@ -1119,13 +1185,13 @@ def generate(lev_max, block=64):
             import re as _re
             used = {int(v) for line in body for v in _re.findall(r"G\[(\d+)\]", line)}
             assert used <= set(range(len(comps))), "adjoint pass reads a component outside its range"
-            kern_src[prec].append(ADJOINT_TEMPLATE.format(pidx=pidx, nus=nus, tag=tag, ncomp=len(comps), nmu=nmu,
+            kern_src[prec].append(ADJOINT_TEMPLATE.format(split=sch.get("split", 1), pidx=pidx, nus=nus, tag=tag, ncomp=len(comps), nmu=nmu,
                                                     comp_list=", ".join(map(str, comps)),
                                                     body="\n".join(" " * 4 + l for l in body)))
             first = "true" if pidx == 0 else "false"
             last = "true" if pidx == len(passes) - 1 else "false"
             adj_lines.append(f"hipLaunchKernelGGL((adjoint_{tag}_kernel<T, {first}, {last}, NQ>), "
-                             f"grid, dim3(BLOCK), smem, s, args);")
+                             f"{_grid(sch.get('split', 1))}, dim3(BLOCK), smem, s, args);")
         body = (["if (!reuse_moments) {"] + ["  " + l for l in mom_lines] + ["}"] +
                 ["hipLaunchKernelGGL((contract_fwd_kernel<T, WANT_B>), grid, dim3(BLOCK), 0, s, args);"] +
                 rev_lines + adj_lines)
@@ -1359,7 +1425,7 @@ hipError_t launch_t(const void* a, bool reuse_moments, bool store_moments, int s
   if (schedule != 0) return hipErrorInvalidValue;
   if (args.n_atoms <= 0) return hipSuccess;
   const dim3 grid((args.n_atoms + BLOCK - 1) / BLOCK);
-  const size_t smem = (size_t)args.n_c * sizeof(T);
+  const size_t smem = (size_t)(args.n_c + args.n_c / args.nq) * sizeof(T);   // c, padded
 #if MTP_PART == 1
 {launch64}
 #else
@@ -1379,7 +1445,7 @@ hipError_t launch_loss_t(const void* a, const void* l, hipStream_t s) {{
   const auto& la = *static_cast<const mtp::LossArgs<T>*>(l);
   if (args.n_atoms <= 0) return hipSuccess;
   const dim3 grid((args.n_atoms + BLOCK - 1) / BLOCK);
-  const size_t smem = (size_t)args.n_c * sizeof(T);
+  const size_t smem = (size_t)(args.n_c + args.n_c / args.nq) * sizeof(T);   // c, padded
 {launch_loss}
   return hipGetLastError();
 }}
@@ -1465,23 +1531,23 @@ def _pair_pass_kernels(s, prec, sidx, sch):
         kmap = {k: j for j, k in enumerate(comps)}
         body, _ = emit_pair_forward(s, comp_mode=True, nus=set(nus), kmap=kmap)
         nmu = 1 + max(mu for (mu, nu, abc), k in s.comp.items() if nu in nus)
-        src.append(MOMENTS_TEMPLATE.format(pidx=pidx, nus=nus, tag=tag, ncomp=len(comps), nmu=nmu,
+        src.append(MOMENTS_TEMPLATE.format(split=sch.get("split", 1), pidx=pidx, nus=nus, tag=tag, ncomp=len(comps), nmu=nmu,
                                            comp_list=", ".join(map(str, comps)),
                                            body="\n".join(" " * 4 + l for l in body)))
-        mom_lines.append(f"hipLaunchKernelGGL((moments_{tag}_kernel<T, COMP, 0>), grid, dim3(BLOCK), smem, s, args);")
+        mom_lines.append(f"hipLaunchKernelGGL((moments_{tag}_kernel<T, COMP, 0>), {_grid(sch.get('split', 1))}, dim3(BLOCK), smem, s, args);")
     passes = adjoint_passes(s, sch["adj"])
     for pidx, (nus, comps) in enumerate(passes):
         tag = f"{prec}s{sidx}_p{pidx}"
         gmap = {k: j for j, k in enumerate(comps)}
         nmu = 1 + max(mu for (mu, nu, abc), k in s.comp.items() if nu in nus)
         body, _ = emit_pair_backward(s, nus=nus, gmap=gmap, nmu=nmu)
-        src.append(ADJOINT_TEMPLATE.format(pidx=pidx, nus=nus, tag=tag, ncomp=len(comps), nmu=nmu,
+        src.append(ADJOINT_TEMPLATE.format(split=sch.get("split", 1), pidx=pidx, nus=nus, tag=tag, ncomp=len(comps), nmu=nmu,
                                            comp_list=", ".join(map(str, comps)),
                                            body="\n".join(" " * 4 + l for l in body)))
         first = "true" if pidx == 0 else "false"
         last = "true" if pidx == len(passes) - 1 else "false"
         adj_lines.append(f"hipLaunchKernelGGL((adjoint_{tag}_kernel<T, {first}, {last}, NQ>), "
-                         f"grid, dim3(BLOCK), smem, s, args);")
+                         f"{_grid(sch.get('split', 1))}, dim3(BLOCK), smem, s, args);")
     return src, mom_lines, adj_lines
 
 

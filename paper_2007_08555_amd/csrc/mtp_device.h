@@ -50,7 +50,8 @@ struct EvalArgs {
   T* atom_virial;        // [9][stride]  sum_j g_a r_b
   double* own;          // [3][stride]  sum_j g_ij in FP64 (the atom's own share of its force)
   T* D;                  // [n_graphs][stride] dV_i / dg for every connected graph g
-  T* B;                  // [m][b_stride] optional basis values
+  T* B;                  // [n_graphs][b_stride] optional graph values (the basis
+                         // functions B_alpha are their products)
   int b_stride;
 };
 
@@ -98,6 +99,28 @@ __device__ __forceinline__ void radial(const T* __restrict__ cs, int base, int m
     f[mu] = acc[mu] * s2;
     if (DERIV) df[mu] = dacc[mu] * dxdr * s2 - T(2) * s * acc[mu];
   }
+}
+
+// Sum over aligned groups of SPLIT consecutive lanes (SPLIT = 1, 2 or 4):
+// DPP quad permutations [1,0,3,2] then [2,3,0,1], each a lane-to-lane move
+// of the 32-bit halves inside a quad of lanes (every lane of a group ends
+// with the group's sum, formed in the same order).
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp_move(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+template <int SPLIT, typename T>
+__device__ __forceinline__ T group_sum(T v) {
+  static_assert(SPLIT == 1 || SPLIT == 2 || SPLIT == 4, "groups of 1, 2 or 4 lanes");
+  if constexpr (SPLIT >= 2) v = v + dpp_move<0xB1>(v);
+  if constexpr (SPLIT >= 4) v = v + dpp_move<0x4E>(v);
+  return v;
 }
 
 // Makes the values of a register array opaque to the optimiser (an empty asm
