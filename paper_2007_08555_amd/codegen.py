@@ -325,9 +325,6 @@ def emit_contraction(s):
     out = []
     ops = 0
     # forward: graph values
-    # (each graph value is handed out as soon as it is complete: the
-    # per-configuration descriptor sums b are formed from them by the
-    # reduction kernels)
     for g, terms in enumerate(s.terms):
         out.append(f"T g{g} = T(0);")
         for coef, idx in terms:
@@ -337,7 +334,6 @@ def emit_contraction(s):
                 expr = f"{_const(coef)} * {expr}"
             out.append(f"g{g} += {expr};")
             ops += len(idx) + (1 if coef != 1 else 0)
-        out.append(f"MTP_OUT_GV({g}, g{g});")
     # basis functions and V
     out.append("T V = T(0);")
     for a, fn in enumerate(s.funcs):
@@ -561,21 +557,13 @@ fused_{tag}_kernel(const mtp::EvalArgs<T> args) {{
     for (int k = 0; k < C; ++k) args.M[(size_t)k * args.stride + i] = M[k];
   }}
   const T* __restrict__ xi = args.xi;
-  // outputs in row order through running pointers (graph values g = 0, 1,
-  // ...; G for k = 0, 1, ...), so that no per-row address stays live
-  T* gvp = WANT_B ? args.B + i : nullptr;
-  const size_t gvst = args.b_stride;
-  T* gp = args.G + i;
-  const size_t gst = args.stride;
-#define MTP_OUT_GV(g_, v_) do {{ if (WANT_B) {{ *gvp = (v_); gvp += gvst; }} }} while (0)
-#define MTP_OUT_B(a_, v_) do {{ }} while (0)
-#define MTP_OUT_G(k_, v_) do {{ *gp = (v_); gp += gst; }} while (0)
+#define MTP_OUT_B(a_, v_) do {{ if (WANT_B) args.B[(size_t)(a_) * args.b_stride + i] = (v_); }} while (0)
+#define MTP_OUT_G(k_, v_) args.G[(size_t)(k_) * args.stride + i] = (v_)
 #define MTP_RELOAD_M() mtp::opaque(M)
 {contraction}
 #undef MTP_RELOAD_M
 #undef MTP_OUT_G
 #undef MTP_OUT_B
-#undef MTP_OUT_GV
   args.site[i] = V;
 }}
 """
@@ -941,9 +929,8 @@ __device__ __forceinline__ int clamp_species(int z, int S) {{ return z < 0 ? 0 :
 
 #if MTP_PART == 1 || MTP_PART == 2
 {moments_kernels}
-// Forward contractions of one atom's moments: graph values (to args.B when
-// the descriptor sums are wanted), V, and dV/dg of every connected graph g
-// (to args.D).
+// Forward contractions of one atom's moments: graph values, V, optional B,
+// and dV/dg of every connected graph g (to args.D).
 template <typename T, bool WANT_B>
 __global__ void __launch_bounds__(BLOCK) contract_fwd_kernel(const mtp::EvalArgs<T> args) {{
   const int i = blockIdx.x * BLOCK + threadIdx.x;
@@ -952,11 +939,9 @@ __global__ void __launch_bounds__(BLOCK) contract_fwd_kernel(const mtp::EvalArgs
   T M[C];
 #pragma unroll
   for (int k = 0; k < C; ++k) M[k] = args.M[(size_t)k * args.stride + i];
-#define MTP_OUT_GV(g_, v_) do {{ if (WANT_B) args.B[(size_t)(g_) * args.b_stride + i] = (v_); }} while (0)
-#define MTP_OUT_B(a_, v_) do {{ }} while (0)
+#define MTP_OUT_B(a_, v_) do {{ if (WANT_B) args.B[(size_t)(a_) * args.b_stride + i] = (v_); }} while (0)
 {contraction_fwd}
 #undef MTP_OUT_B
-#undef MTP_OUT_GV
 {store_dg}
   args.site[i] = V;
 }}

@@ -135,9 +135,8 @@ __device__ __forceinline__ T basis_products(const XiLoad& xiload, const VLoad& v
 }
 
 // Forward contraction, basis products and reverse sweep of one atom per
-// thread: graph values to the upper half of D (and to args.B when the
-// descriptor sums are wanted), V to site, dV/dg to the lower half of D,
-// G = dV/dM.
+// thread: graph values to the upper half of D, B (when wanted), V to site,
+// dV/dg to the lower half of D, G = dV/dM.
 template <typename T, bool WANT_B, typename Tab>
 __global__ void __launch_bounds__(64) contract_table_kernel(const EvalArgs<T> args) {
   const int i = blockIdx.x * 64 + threadIdx.x;
@@ -148,14 +147,14 @@ __global__ void __launch_bounds__(64) contract_table_kernel(const EvalArgs<T> ar
   T* Dg = args.D + i;
   T* Dv = args.D + (size_t)Tab::kGraphs * st + i;
   const auto mload = [&](int k) { return Mi[(size_t)k * st]; };
-  graphs_forward<T, 1, Tab>(mload, [&](int g, T v) {
-    Dv[(size_t)g * st] = v;
-    if (WANT_B) args.B[(size_t)g * args.b_stride + i] = v;
-  });
+  graphs_forward<T, 1, Tab>(mload, [&](int g, T v) { Dv[(size_t)g * st] = v; });
   for (int g = 0; g < Tab::kGraphs; ++g) Dg[(size_t)g * st] = T(0);
   const T V = basis_products<T, Tab>(
       [&](int a) { return args.xi[a]; }, [&](int g) { return Dv[(size_t)g * st]; },
-      [&](int g, T v) { Dg[(size_t)g * st] += v; }, [&](int, T) {});
+      [&](int g, T v) { Dg[(size_t)g * st] += v; },
+      [&](int a, T B) {
+        if (WANT_B) args.B[(size_t)a * args.b_stride + i] = B;
+      });
   args.site[i] = V;
   for (int k = 0; k < Tab::kC; ++k) Gi[(size_t)k * st] = T(0);
   graphs_reverse<T, 1, Tab>(mload, [&](int g) { return Dg[(size_t)g * st]; },

@@ -11,89 +11,114 @@
 namespace mtp {
 namespace {
 
-constexpr int kGJBlock = 1024;
+constexpr int kGJBlock = 256;
 
 // Gauss-Jordan elimination with partial pivoting on [A | I] (row-major,
-// m x 2m) in one workgroup; the right half ends as A^{-1}.  Columns of A
-// are equilibrated first (A D, then D (AD)^{-1} = A^{-1}).
-__global__ void __launch_bounds__(kGJBlock) gj_kernel(int m, double* W, double* inv, int* singular) {
+// m x 2m); the right half ends as A^{-1}.  Columns of A are equilibrated
+// first (A D, then D (AD)^{-1} = A^{-1}; D is kept in inv's first row until
+// the end).  One launch per column for the scaling, two per step (pivot
+// search, row swap and normalisation in one workgroup; elimination from
+// every other row over the whole grid), two at the end.  A pivot at
+// rounding level sets *singular, after which the later kernels return at
+// once.
+
+__global__ void __launch_bounds__(kGJBlock) gj_scale_kernel(int m, double* W, double* inv, int* singular) {
+  __shared__ double red[kGJBlock];
+  const int col = blockIdx.x, t = threadIdx.x;
+  const int n2 = 2 * m;
+  if (col == 0 && t == 0) *singular = 0;
+  double mx = 0.0;
+  for (int r = t; r < m; r += blockDim.x) mx = fmax(mx, fabs(W[(size_t)r * n2 + col]));
+  red[t] = mx;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if (t < w) red[t] = fmax(red[t], red[t + w]);
+    __syncthreads();
+  }
+  const double d = red[0] > 0 ? 1.0 / red[0] : 1.0;
+  if (t == 0) inv[col] = d;
+  for (int r = t; r < m; r += blockDim.x) W[(size_t)r * n2 + col] *= d;
+}
+
+// Step k: pivot = largest |W[r][k]| for r >= k (lowest row on ties), rows
+// k and pivot swapped, row k divided by the pivot.
+__global__ void __launch_bounds__(kGJBlock) gj_pivot_kernel(int m, int k, double* W, int* singular) {
   __shared__ double s_val[kGJBlock];
   __shared__ int s_idx[kGJBlock];
-  __shared__ double s_piv;
-  __shared__ int s_prow;
+  __shared__ int s_stop;
   const int t = threadIdx.x;
   const int n2 = 2 * m;
-  // column scales D = 1 / max |A_col|, stored in inv's first row as scratch
-  for (int col = t; col < m; col += blockDim.x) {
-    double mx = 0;
-    for (int r = 0; r < m; ++r) mx = fmax(mx, fabs(W[(size_t)r * n2 + col]));
-    const double d = mx > 0 ? 1.0 / mx : 1.0;
-    inv[col] = d;
-    for (int r = 0; r < m; ++r) W[(size_t)r * n2 + col] *= d;
-  }
+  if (t == 0) s_stop = *singular;
   __syncthreads();
-  if (t == 0) *singular = 0;
-  for (int k = 0; k < m; ++k) {
-    // pivot: largest |W[r][k]| for r >= k, lowest row on ties
-    double best = -1;
-    int bi = k;
-    for (int r = k + t; r < m; r += blockDim.x) {
-      const double v = fabs(W[(size_t)r * n2 + k]);
-      if (v > best) { best = v; bi = r; }
-    }
-    s_val[t] = best;
-    s_idx[t] = bi;
-    __syncthreads();
-    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
-      if (t < w) {
-        const double v = s_val[t + w];
-        const int ix = s_idx[t + w];
-        if (v > s_val[t] || (v == s_val[t] && ix < s_idx[t])) { s_val[t] = v; s_idx[t] = ix; }
-      }
-      __syncthreads();
-    }
-    if (t == 0) {
-      s_prow = s_idx[0];
-      // columns are scaled to max |entry| = 1: a pivot at rounding level
-      // means A is numerically singular
-      if (!(s_val[0] > 1e-13)) *singular = 1;
-    }
-    __syncthreads();
-    const int pr = s_prow;
-    if (pr != k)
-      for (int col = t; col < n2; col += blockDim.x) {
-        const double a = W[(size_t)k * n2 + col];
-        W[(size_t)k * n2 + col] = W[(size_t)pr * n2 + col];
-        W[(size_t)pr * n2 + col] = a;
-      }
-    __syncthreads();
-    if (t == 0) s_piv = W[(size_t)k * n2 + k];
-    __syncthreads();
-    const double ip = 1.0 / s_piv;
-    for (int col = t; col < n2; col += blockDim.x) W[(size_t)k * n2 + col] *= ip;
-    __syncthreads();
-    // eliminate column k from every other row
-    for (int idx = t; idx < m * n2; idx += blockDim.x) {
-      const int r = idx / n2, col = idx % n2;
-      if (r == k || col == k) continue;
-      const double f = W[(size_t)r * n2 + k];
-      if (f != 0.0) W[(size_t)r * n2 + col] -= f * W[(size_t)k * n2 + col];
-    }
-    __syncthreads();
-    for (int r = t; r < m; r += blockDim.x)
-      if (r != k) W[(size_t)r * n2 + k] = 0.0;
-    __syncthreads();
+  if (s_stop) return;
+  double best = -1;
+  int bi = k;
+  for (int r = k + t; r < m; r += blockDim.x) {
+    const double v = fabs(W[(size_t)r * n2 + k]);
+    if (v > best) { best = v; bi = r; }
   }
-  // A^{-1} = D (AD)^{-1}: scale row r of the right half by D[r]
-  for (int idx = t; idx < m * m; idx += blockDim.x) {
-    const int r = idx / m, col = idx % m;
-    W[(size_t)r * n2 + m + col] *= inv[r];
-  }
+  s_val[t] = best;
+  s_idx[t] = bi;
   __syncthreads();
-  for (int idx = t; idx < m * m; idx += blockDim.x) {
-    const int r = idx / m, col = idx % m;
-    inv[idx] = W[(size_t)r * n2 + m + col];
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if (t < w) {
+      const double v = s_val[t + w];
+      const int ix = s_idx[t + w];
+      if (v > s_val[t] || (v == s_val[t] && ix < s_idx[t])) { s_val[t] = v; s_idx[t] = ix; }
+    }
+    __syncthreads();
   }
+  // columns are scaled to max |entry| = 1: a pivot at rounding level means
+  // A is numerically singular
+  if (!(s_val[0] > 1e-13)) {
+    if (t == 0) *singular = 1;
+    return;
+  }
+  const int pr = s_idx[0];
+  if (pr != k)
+    for (int col = t; col < n2; col += blockDim.x) {
+      const double a = W[(size_t)k * n2 + col];
+      W[(size_t)k * n2 + col] = W[(size_t)pr * n2 + col];
+      W[(size_t)pr * n2 + col] = a;
+    }
+  __syncthreads();
+  const double ip = 1.0 / W[(size_t)k * n2 + k];
+  __syncthreads();
+  for (int col = t; col < n2; col += blockDim.x) W[(size_t)k * n2 + col] *= ip;
+}
+
+// Step k: column k eliminated from every other row (one wavefront per row,
+// lanes over the columns; the row's factor is read before any lane writes).
+__global__ void __launch_bounds__(kGJBlock) gj_eliminate_kernel(int m, int k, double* W, const int* singular) {
+  if (*singular) return;
+  const int n2 = 2 * m;
+  const int lane = threadIdx.x & 63;
+  const int r = blockIdx.x * (kGJBlock / 64) + (threadIdx.x >> 6);
+  if (r >= m || r == k) return;
+  double* row = W + (size_t)r * n2;
+  const double* prow = W + (size_t)k * n2;
+  const double f = row[k];
+  if (f != 0.0)
+    for (int col = lane; col < n2; col += 64)
+      if (col != k) row[col] -= f * prow[col];
+  if (lane == 0) row[k] = 0.0;
+}
+
+// A^{-1} = D (AD)^{-1}: row r of the right half scaled by D[r], then copied.
+__global__ void gj_unscale_kernel(int m, double* W, const double* inv, const int* singular) {
+  if (*singular) return;
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)m * m) return;
+  const int r = (int)(idx / m), col = (int)(idx % m);
+  W[(size_t)r * 2 * m + m + col] *= inv[r];
+}
+
+__global__ void gj_copy_kernel(int m, const double* W, double* inv, const int* singular) {
+  if (*singular) return;
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)m * m) return;
+  const int r = (int)(idx / m), col = (int)(idx % m);
+  inv[idx] = W[(size_t)r * 2 * m + m + col];
 }
 
 // c = b A^{-1} on the FP64 matrix cores: one wavefront per 16 x 16 tile of c;
@@ -169,7 +194,16 @@ hipError_t grade_scratch_address(int device, double** out) {
 }
 
 hipError_t gauss_jordan_inverse(int m, double* work, double* inv, int* singular, hipStream_t s) {
-  hipLaunchKernelGGL(gj_kernel, dim3(1), dim3(kGJBlock), 0, s, m, work, inv, singular);
+  if (m <= 0) return hipSuccess;
+  hipLaunchKernelGGL(gj_scale_kernel, dim3(m), dim3(kGJBlock), 0, s, m, work, inv, singular);
+  const unsigned row_blocks = (unsigned)((m + kGJBlock / 64 - 1) / (kGJBlock / 64));
+  for (int k = 0; k < m; ++k) {
+    hipLaunchKernelGGL(gj_pivot_kernel, dim3(1), dim3(kGJBlock), 0, s, m, k, work, singular);
+    hipLaunchKernelGGL(gj_eliminate_kernel, dim3(row_blocks), dim3(kGJBlock), 0, s, m, k, work, singular);
+  }
+  const unsigned blocks = (unsigned)(((int64_t)m * m + 255) / 256);
+  hipLaunchKernelGGL(gj_unscale_kernel, dim3(blocks), dim3(256), 0, s, m, work, inv, singular);
+  hipLaunchKernelGGL(gj_copy_kernel, dim3(blocks), dim3(256), 0, s, m, work, inv, singular);
   return hipGetLastError();
 }
 

@@ -15,72 +15,93 @@ namespace {
 constexpr int kMVBlock = 256;
 
 // Starting rows: Gaussian elimination with partial pivoting of the pool with
-// every column scaled to max |entry| = 1, in one workgroup.  W [K][m] is
-// overwritten; perm [K] holds the current row order.  Step t takes the first
-// row, in the current order, of largest |W| in column t among positions
-// t..K-1, swaps it into position t and eliminates column t below it.  The m
-// pivot rows are returned in ascending order.  A zero pivot sets *singular.
-__global__ void __launch_bounds__(kMVBlock) pivot_rows_kernel(int K, int m, double* W, int32_t* perm,
-                                                              int32_t* rows, int* singular) {
-  const int tid = threadIdx.x;
+// every column scaled to max |entry| = 1.  W [K][m] is overwritten; perm [K]
+// holds the current row order.  Step t takes the first row, in the current
+// order, of largest |W| in column t among positions t..K-1, swaps it into
+// position t and eliminates column t below it.  The m pivot rows are
+// returned in ascending order.  A zero pivot sets *singular, after which
+// every later kernel of the elimination returns at once.  One launch per
+// column for the scaling, then two per step (pivot search in one workgroup,
+// elimination over the whole grid).
+
+// perm = identity and column t scaled by 1 / max |W[:, t]| (one block per column).
+__global__ void __launch_bounds__(kMVBlock) pr_scale_kernel(int K, int m, double* W, int32_t* perm, int* singular) {
+  __shared__ double red[kMVBlock];
+  const int col = blockIdx.x, tid = threadIdx.x;
+  if (col == 0) {
+    for (int r = tid; r < K; r += blockDim.x) perm[r] = r;
+    if (tid == 0) *singular = 0;
+  }
+  double mx = 0.0;
+  for (int r = tid; r < K; r += blockDim.x) mx = fmax(mx, fabs(W[(size_t)r * m + col]));
+  red[tid] = mx;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if (tid < w) red[tid] = fmax(red[tid], red[tid + w]);
+    __syncthreads();
+  }
+  mx = red[0];
+  if (mx > 0.0)
+    for (int r = tid; r < K; r += blockDim.x) W[(size_t)r * m + col] /= mx;
+}
+
+// Step t, pivot: largest |W[perm[p]][t]| over positions p >= t, the first one
+// on ties, swapped into position t.
+__global__ void __launch_bounds__(kMVBlock) pr_pivot_kernel(int K, int m, int t, const double* W, int32_t* perm,
+                                                            int* singular) {
   __shared__ double bv[kMVBlock];
   __shared__ int bi[kMVBlock];
-  __shared__ int fail;
-  if (tid == 0) fail = 0;
-  for (int r = tid; r < K; r += blockDim.x) perm[r] = r;
-  for (int k = tid; k < m; k += blockDim.x) {
-    double mx = 0.0;
-    for (int r = 0; r < K; ++r) mx = fmax(mx, fabs(W[(size_t)r * m + k]));
-    if (mx > 0.0)
-      for (int r = 0; r < K; ++r) W[(size_t)r * m + k] /= mx;
+  if (*singular) return;
+  const int tid = threadIdx.x;
+  double best = -1.0;
+  int bp = K;
+  for (int p = t + tid; p < K; p += blockDim.x) {
+    const double v = fabs(W[(size_t)perm[p] * m + t]);
+    if (v > best) { best = v; bp = p; }
   }
+  bv[tid] = best;
+  bi[tid] = bp;
   __syncthreads();
-  for (int t = 0; t < m; ++t) {
-    // pivot: largest |W[perm[p]][t]| over positions p >= t, first one on ties
-    double best = -1.0;
-    int bp = K;
-    for (int p = t + tid; p < K; p += blockDim.x) {
-      const double v = fabs(W[(size_t)perm[p] * m + t]);
-      if (v > best) { best = v; bp = p; }
-    }
-    bv[tid] = best;
-    bi[tid] = bp;
-    __syncthreads();
-    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
-      if (tid < w) {
-        const double ov = bv[tid + w];
-        const int op = bi[tid + w];
-        if (ov > bv[tid] || (ov == bv[tid] && op < bi[tid])) { bv[tid] = ov; bi[tid] = op; }
-      }
-      __syncthreads();
-    }
-    if (tid == 0) {
-      if (!(bv[0] > 0.0)) {
-        fail = 1;
-      } else {
-        const int p = bi[0];
-        const int tmp = perm[t];
-        perm[t] = perm[p];
-        perm[p] = tmp;
-      }
-    }
-    __syncthreads();
-    if (fail) break;
-    // eliminate column t from the rows below position t
-    const double* prow = W + (size_t)perm[t] * m;
-    const double piv = prow[t];
-    const int nr = K - t - 1, nc = m - t - 1;
-    for (int64_t q = tid; q < (int64_t)nr * nc; q += blockDim.x) {
-      const int r = t + 1 + (int)(q / nc), k = t + 1 + (int)(q % nc);
-      double* row = W + (size_t)perm[r] * m;
-      row[k] -= (row[t] / piv) * prow[k];
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if (tid < w) {
+      const double ov = bv[tid + w];
+      const int op = bi[tid + w];
+      if (ov > bv[tid] || (ov == bv[tid] && op < bi[tid])) { bv[tid] = ov; bi[tid] = op; }
     }
     __syncthreads();
   }
-  if (tid == 0) *singular = fail;
-  if (fail) return;
-  // the pivot rows in ascending order (they are distinct): rank by counting
-  for (int t = tid; t < m; t += blockDim.x) {
+  if (tid == 0) {
+    if (!(bv[0] > 0.0)) {
+      *singular = 1;
+    } else {
+      const int p = bi[0];
+      const int tmp = perm[t];
+      perm[t] = perm[p];
+      perm[p] = tmp;
+    }
+  }
+}
+
+// Step t, elimination of column t from the rows at positions t+1..K-1: one
+// wavefront per row, lanes over the columns right of t.
+__global__ void __launch_bounds__(kMVBlock) pr_eliminate_kernel(int K, int m, int t, double* W,
+                                                                const int32_t* __restrict__ perm,
+                                                                const int* singular) {
+  if (*singular) return;
+  const int lane = threadIdx.x & 63;
+  const int r = t + 1 + blockIdx.x * (kMVBlock / 64) + (threadIdx.x >> 6);
+  if (r >= K) return;
+  const double* prow = W + (size_t)perm[t] * m;
+  double* row = W + (size_t)perm[r] * m;
+  const double l = row[t] / prow[t];
+  for (int k = t + 1 + lane; k < m; k += 64) row[k] -= l * prow[k];
+}
+
+// The pivot rows in ascending order (they are distinct): rank by counting.
+__global__ void __launch_bounds__(kMVBlock) pr_rank_kernel(int m, const int32_t* __restrict__ perm, int32_t* rows,
+                                                           const int* singular) {
+  if (*singular) return;
+  for (int t = threadIdx.x; t < m; t += blockDim.x) {
     const int v = perm[t];
     int rank = 0;
     for (int u = 0; u < m; ++u) rank += perm[u] < v ? 1 : 0;
@@ -149,7 +170,15 @@ __global__ void swap_update_kernel(int K, int m, double* C, const MaxvolPick* pi
 }  // namespace
 
 hipError_t maxvol_pivot_rows(int K, int m, double* W, int32_t* perm, int32_t* rows, int* singular, hipStream_t s) {
-  hipLaunchKernelGGL(pivot_rows_kernel, dim3(1), dim3(kMVBlock), 0, s, K, m, W, perm, rows, singular);
+  hipLaunchKernelGGL(pr_scale_kernel, dim3(m), dim3(kMVBlock), 0, s, K, m, W, perm, singular);
+  for (int t = 0; t < m; ++t) {
+    hipLaunchKernelGGL(pr_pivot_kernel, dim3(1), dim3(kMVBlock), 0, s, K, m, t, W, perm, singular);
+    const int rows_below = K - t - 1;
+    if (rows_below > 0)
+      hipLaunchKernelGGL(pr_eliminate_kernel, dim3((rows_below + kMVBlock / 64 - 1) / (kMVBlock / 64)),
+                         dim3(kMVBlock), 0, s, K, m, t, W, perm, singular);
+  }
+  hipLaunchKernelGGL(pr_rank_kernel, dim3(1), dim3(kMVBlock), 0, s, m, perm, rows, singular);
   return hipGetLastError();
 }
 

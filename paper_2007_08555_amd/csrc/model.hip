@@ -94,7 +94,6 @@ struct mtp_model {
   std::vector<int> perm;      // file basis index -> kernel basis index
   std::vector<double> c, xi;  // file order
   Buffer c64, c32, xi64, xi32, perm_dev;
-  Buffer fn_off, fn_fac;   // the compiled basis' functions as lists of graphs (kernel order)
   // active set
   bool has_active = false;
   Buffer ainv, gj_work, gj_flag;
@@ -155,12 +154,6 @@ int upload_params(mtp_model* M) {
   HIP_TRY(hipMemcpy(M->xi32.p, x32.data(), sizeof(float) * M->m, hipMemcpyHostToDevice), "hipMemcpy");
   HIP_TRY(M->perm_dev.ensure(sizeof(int32_t) * M->m), "hipMalloc");
   HIP_TRY(hipMemcpy(M->perm_dev.p, M->perm.data(), sizeof(int32_t) * M->m, hipMemcpyHostToDevice), "hipMemcpy");
-  const int n_fac = M->var->func_offsets[M->m];
-  HIP_TRY(M->fn_off.ensure(sizeof(int32_t) * (M->m + 1)), "hipMalloc");
-  HIP_TRY(M->fn_fac.ensure(sizeof(int32_t) * std::max(1, n_fac)), "hipMalloc");
-  HIP_TRY(hipMemcpy(M->fn_off.p, M->var->func_offsets, sizeof(int32_t) * (M->m + 1), hipMemcpyHostToDevice),
-          "hipMemcpy");
-  HIP_TRY(hipMemcpy(M->fn_fac.p, M->var->func_factors, sizeof(int32_t) * n_fac, hipMemcpyHostToDevice), "hipMemcpy");
   return MTP_OK;
 }
 
@@ -401,7 +394,7 @@ int run_eval(mtp_model* M, const mtp_batch* bt, const mtp_out* out, int precisio
     NEED(M->Dbuf, tsz * 2 * (size_t)M->var->n_graphs * stride);
     NEED(M->site, tsz * stride);
     NEED(M->wv, tsz * 9 * stride);
-    if (want_b) NEED(M->B, tsz * (size_t)M->var->n_graphs * stride);   // graph values
+    if (want_b) NEED(M->B, tsz * (size_t)M->m * stride);
     const bool use_skin = M->skin > 0.0 && !async;
     if (use_skin) {
       NEED(M->xbuild, sizeof(double) * 3 * (size_t)(N + 1));
@@ -491,8 +484,8 @@ int run_eval(mtp_model* M, const mtp_batch* bt, const mtp_out* out, int precisio
             "force gather");
     HIP_TRY(mark(3), "hipEventRecord");
     HIP_TRY(reduce_configs(fp64, n_cfg, M->cfg.as<CfgInfo>(), stride, M->site.p, out->virial ? M->wv.p : nullptr,
-                           want_b ? M->B.p : nullptr, M->m, stride, M->fn_off.as<int32_t>(), M->fn_fac.as<int32_t>(),
-                           M->perm_dev.as<int32_t>(), out->energy, out->virial, out->b, out->site_energy, s),
+                           want_b ? M->B.p : nullptr, M->m, stride, M->perm_dev.as<int32_t>(), out->energy,
+                           out->virial, out->b, out->site_energy, s),
             "reductions");
     HIP_TRY(mark(4), "hipEventRecord");
     if (async) return MTP_OK;  // the caller reads the status later (mtp_status)
@@ -1152,8 +1145,7 @@ int mtp_normal_equations(mtp_model* M, const mtp_batch* bt, const double* E_t, c
                                M->own.as<double>(), col + K_cfg, s),
             "force gather");
     HIP_TRY(mtp::reduce_configs(fp64, K_cfg, M->cfg.as<mtp::CfgInfo>(), stride, M->site.p, M->wv.p, nullptr, m,
-                                stride, nullptr, nullptr, M->perm_dev.as<int32_t>(), col, col + K_cfg + 3 * N,
-                                nullptr, nullptr, s),
+                                stride, M->perm_dev.as<int32_t>(), col, col + K_cfg + 3 * N, nullptr, nullptr, s),
             "reductions");
   }
   HIP_TRY(mtp::fit_rows(K_cfg, N, R, M->cfg.as<mtp::CfgInfo>(), M->atom_cfg.as<int32_t>(), w_e, w_f, w_s, scaling,

@@ -50,8 +50,7 @@ struct EvalArgs {
   T* atom_virial;        // [9][stride]  sum_j g_a r_b
   double* own;          // [3][stride]  sum_j g_ij in FP64 (the atom's own share of its force)
   T* D;                  // [n_graphs][stride] dV_i / dg for every connected graph g
-  T* B;                  // [n_graphs][b_stride] optional graph values (the basis
-                         // functions B_alpha are their products)
+  T* B;                  // [m][b_stride] optional basis values
   int b_stride;
 };
 

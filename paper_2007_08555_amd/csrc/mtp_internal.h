@@ -81,15 +81,13 @@ hipError_t zero_words(int32_t* p, int64_t n, hipStream_t s);
 hipError_t gather_forces(int fp64, int64_t n_atoms, int stride, const int32_t* count,
                          const int32_t* rev, const void* g, const double* own, double* forces, hipStream_t s);
 
-// Per-configuration sums of site energies, virials and the basis functions
-// B_alpha, each the product of its graphs' values gv [n_graphs][gv_stride]
-// (fn_off [m + 1] / fn_fac: the factors of each function in kernel order;
-// kernel order -> file order through perm, which maps file index -> kernel
-// index), over the validated atom ranges of cfg.
+// Per-configuration sums of site energies, virials and B (kernel order ->
+// file order through perm, which maps file index -> kernel index), over the
+// validated atom ranges of cfg.
 hipError_t reduce_configs(int fp64, int n_cfg, const CfgInfo* cfg, int stride,
-                          const void* site, const void* atom_virial, const void* gv, int m,
-                          int gv_stride, const int32_t* fn_off, const int32_t* fn_fac, const int32_t* perm,
-                          double* energy, double* virial, double* b, double* site_out, hipStream_t s);
+                          const void* site, const void* atom_virial, const void* B, int m,
+                          int b_stride, const int32_t* perm, double* energy, double* virial,
+                          double* b, double* site_out, hipStream_t s);
 
 // Normal equations in xi (fit.hip).  Ja is column-major [m + 1][R]: columns
 // 0..m-1 the Jacobian, column m the targets.

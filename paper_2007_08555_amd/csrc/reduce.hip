@@ -125,18 +125,13 @@ __global__ void __launch_bounds__(kBlock) config_large_kernel(int n_cfg, const C
   config_sums<T, 4>(k, cfg, stride, site, wv, energy, virial, site_out);
 }
 
-// b[k][f] = sum over atoms i of configuration k of B_alpha(i), alpha =
-// perm[f], B_alpha the product of its connected graphs' values (eq.
-// matrix-B with B_alpha as in eq. MTPbasisLevel8); gv [n_graphs][gv_stride]
-// holds every atom's graph values.  One block per configuration, each
-// wavefront four basis functions at a time: lanes take consecutive atoms
-// (coalesced rows) and form the products in FP64, and the 64 partial sums
-// are combined by a butterfly in a fixed order.
+// b[k][f] = sum over atoms of configuration k of B[perm[f]][atom]; one block
+// per configuration, each wavefront four basis functions at a time: lanes
+// read consecutive atoms (coalesced) and the 64 partial sums are combined by
+// a butterfly in a fixed order.
 template <typename T>
 __global__ void __launch_bounds__(kBlock) b_kernel(int n_cfg, const CfgInfo* __restrict__ cfg,
-                                                   const T* __restrict__ gv, int m, int gv_stride,
-                                                   const int32_t* __restrict__ fn_off,
-                                                   const int32_t* __restrict__ fn_fac,
+                                                   const T* __restrict__ B, int m, int b_stride,
                                                    const int32_t* __restrict__ perm, double* b) {
   constexpr int U = 4;
   constexpr int kWaves = kBlock / 64;
@@ -145,22 +140,16 @@ __global__ void __launch_bounds__(kBlock) b_kernel(int n_cfg, const CfgInfo* __r
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int64_t a0 = cfg[k].start, a1 = cfg[k].start + cfg[k].n;
   for (int f0 = wave * U; f0 < m; f0 += kWaves * U) {
-    int q0[U], q1[U];
+    const T* row[U];
     double s[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int a = perm[f0 + u < m ? f0 + u : f0];
-      q0[u] = fn_off[a];
-      q1[u] = f0 + u < m ? fn_off[a + 1] : q0[u];
+      row[u] = B + (size_t)perm[f0 + u < m ? f0 + u : f0] * b_stride;
       s[u] = 0.0;
     }
     for (int64_t i = a0 + lane; i < a1; i += 64)
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        double p = 1.0;
-        for (int t = q0[u]; t < q1[u]; ++t) p *= (double)gv[(size_t)fn_fac[t] * gv_stride + i];
-        s[u] += q1[u] > q0[u] ? p : 0.0;
-      }
+      for (int u = 0; u < U; ++u) s[u] += (double)row[u][i];
 #pragma unroll
     for (int u = 0; u < U; ++u)
       for (int o = 32; o > 0; o >>= 1) s[u] += __shfl_xor(s[u], o, 64);
@@ -187,8 +176,8 @@ hipError_t gather_forces(int fp64, int64_t n_atoms, int stride, const int32_t* c
 }
 
 hipError_t reduce_configs(int fp64, int n_cfg, const CfgInfo* offs, int stride, const void* site,
-                          const void* atom_virial, const void* gv, int m, int gv_stride, const int32_t* fn_off,
-                          const int32_t* fn_fac, const int32_t* perm, double* energy, double* virial, double* b,
+                          const void* atom_virial, const void* B, int m, int b_stride,
+                          const int32_t* perm, double* energy, double* virial, double* b,
                           double* site_out, hipStream_t s) {
   if (n_cfg == 0) return hipSuccess;
   if (energy || virial || site_out) {
@@ -204,13 +193,13 @@ hipError_t reduce_configs(int fp64, int n_cfg, const CfgInfo* offs, int stride, 
                          (const float*)site, (const float*)atom_virial, energy, virial, site_out);
     }
   }
-  if (b && gv) {
+  if (b && B) {
     if (fp64)
       hipLaunchKernelGGL(b_kernel<double>, dim3(n_cfg), dim3(kBlock), 0, s, n_cfg, offs,
-                         (const double*)gv, m, gv_stride, fn_off, fn_fac, perm, b);
+                         (const double*)B, m, b_stride, perm, b);
     else
       hipLaunchKernelGGL(b_kernel<float>, dim3(n_cfg), dim3(kBlock), 0, s, n_cfg, offs,
-                         (const float*)gv, m, gv_stride, fn_off, fn_fac, perm, b);
+                         (const float*)B, m, b_stride, perm, b);
   }
   return hipGetLastError();
 }

@@ -52,3 +52,31 @@ def test_loss_gradient_matches_oracle(name, scaling):
         f"(scale {scale:.3e})")
     assert abs(loss - L_o) <= 1e-10 * abs(L_o)
     assert err.max() <= 1e-8
+
+
+def test_loss_gradient_on_a_training_shaped_batch():
+    """The training workload's shape (configurations of 32-128 atoms, three
+    species, level 16): about 1500 atoms over many workgroups, so the
+    per-workgroup partial sums of dL/dc and their final reduction are
+    compared with the oracle too (on a sample of gradient entries)."""
+    from paper_2007_08555_amd import Batch, Potential
+    pot = read_potential(pot_path("lev16_s3"))
+    batch = synth.mixed_batch(seed=29, n_configs=20, n_min=32, n_max=110, n_species_model=3)
+    n_atoms = int(batch["n_atoms"].sum())
+    log(f"[loss training-shaped] {len(batch['n_atoms'])} configurations, {n_atoms} atoms")
+    assert n_atoms > 20 * 64
+    tg = make_targets(pot, batch, seed=5)
+    w = dict(w_e=1.0, w_f=0.01, w_s=0.001, scaling="vibrations")
+    P = Potential(pot_path("lev16_s3"))
+    loss, grad = P.loss_grad(Batch.from_arrays(batch), tg["energy"], tg["forces"], tg["virial"], precision="fp64", **w)
+    loss, grad = loss.item(), grad.cpu().numpy()
+    L_o = ol.loss(pot, batch, tg, **w)
+    m, nc = len(pot["xi"]), pot["c"].size
+    rng = np.random.default_rng(4)
+    idx = sorted(set(rng.choice(m, size=3, replace=False).tolist()) |
+                 set((m + rng.choice(nc, size=3, replace=False)).tolist()))
+    g_o = ol.loss_grad(pot, batch, tg, indices=idx, **w)
+    err = np.abs(grad[idx] - g_o) / np.abs(g_o).max()
+    log(f"[loss training-shaped] loss gpu {loss:.10e} oracle {L_o:.10e}; grad entries {idx}: max rel err {err.max():.3e}")
+    assert abs(loss - L_o) <= 1e-10 * abs(L_o)
+    assert err.max() <= 1e-8
