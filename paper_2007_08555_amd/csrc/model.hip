@@ -104,7 +104,8 @@ struct mtp_model {
   Buffer cfg, cfg_order, atom_cfg, atom_bin, bin_count, bin_start, bin_atoms, bin_fill, binned, large, nbins_dev;
   Buffer count, nbr, pr, rev, gpair, own, Mbuf, Gbuf, Dbuf, site, wv, B, status, run_start;
   int K = 64;  // neighbour capacity per atom, grown on overflow
-  int schedule64 = 0;  // FP64 pass split of the evaluation kernels (mtp_autotune)
+  int schedule64 = 0;    // FP64 pass split of the evaluation kernels (mtp_autotune)
+  int schedule64_b = 0;  // the same for evaluations that also write the basis values (descriptor sums)
   // Verlet skin (mtp_set_skin): lists of the last build, reused while the
   // batch's arrays are the same and no atom moved more than skin / 2
   double skin = 0.0;
@@ -471,7 +472,8 @@ int run_eval(mtp_model* M, const mtp_batch* bt, const mtp_out* out, int precisio
       const unsigned flags = (want_b ? kEvalWantB : 0u) | (store_moments ? kEvalStoreMoments : 0u);
       if (fp64) {
         auto ea = make_args<double>(M, N, stride, bt->species, want_b);
-        HIP_TRY(M->var->launch_eval(precision, flags, M->schedule64, &ea, s), "evaluation kernels");
+        HIP_TRY(M->var->launch_eval(precision, flags, want_b ? M->schedule64_b : M->schedule64, &ea, s),
+                "evaluation kernels");
       } else {
         auto ea = make_args<float>(M, N, stride, bt->species, want_b);
         HIP_TRY(M->var->launch_eval(precision, flags, 0, &ea, s), "evaluation kernels");
@@ -1202,7 +1204,7 @@ int mtp_set_schedule(mtp_model* M, int precision, int schedule) {
   const int n = precision == MTP_FP64 ? M->var->n_schedules : 1;
   if (precision < MTP_FP64 || precision > MTP_FP32_COMPENSATED || schedule < 0 || schedule >= n)
     return fail(MTP_E_ARG, "mtp_set_schedule: no such schedule for this precision");
-  if (precision == MTP_FP64) M->schedule64 = schedule;
+  if (precision == MTP_FP64) M->schedule64 = M->schedule64_b = schedule;
   return MTP_OK;
 }
 
@@ -1225,22 +1227,31 @@ int mtp_autotune(mtp_model* M, const mtp_batch* bt, int precision, int repeats, 
   HIP_TRY(hipEventCreate(&e0), "hipEventCreate");
   HIP_TRY(hipEventCreate(&e1), "hipEventCreate");
   hipError_t err = hipSuccess;
-  auto run = [&](int k) -> hipError_t {
+  // the basis values of the descriptor sums, written by evaluations that want b
+  {
+    const size_t tsz = fp64 ? sizeof(double) : sizeof(float);
+    HIP_TRY(M->B.ensure(tsz * (size_t)M->m * M->last_stride), "hipMalloc");
+  }
+  // slot k < n: schedule k without the basis values, n + k: with them
+  auto run = [&](int slot) -> hipError_t {
+    const int k = slot % n;
+    const bool want_b = slot >= n;
+    const unsigned flags = want_b ? mtp::kEvalWantB : 0u;
     if (fp64) {
-      auto ea = make_args<double>(M, N, M->last_stride, bt->species, false);
-      return M->var->launch_eval(precision, 0u, k, &ea, s);
+      auto ea = make_args<double>(M, N, M->last_stride, bt->species, want_b);
+      return M->var->launch_eval(precision, flags, k, &ea, s);
     }
-    auto ea = make_args<float>(M, N, M->last_stride, bt->species, false);
-    return M->var->launch_eval(precision, 0u, k, &ea, s);
+    auto ea = make_args<float>(M, N, M->last_stride, bt->species, want_b);
+    return M->var->launch_eval(precision, flags, k, &ea, s);
   };
   // Every schedule is launched once untimed, then the schedules are timed in
   // interleaved rounds and each keeps its fastest round, so that clock ramps
   // and the position in the sequence do not favour one of them.
-  std::vector<float> best_of(n, 0.f);
+  std::vector<float> best_of(2 * n, 0.f);
   if (N > 0) {
-    for (int k = 0; k < n && err == hipSuccess; ++k) err = run(k);
+    for (int k = 0; k < 2 * n && err == hipSuccess; ++k) err = run(k);
     for (int r = 0; r < repeats && err == hipSuccess; ++r)
-      for (int k = 0; k < n && err == hipSuccess; ++k) {
+      for (int k = 0; k < 2 * n && err == hipSuccess; ++k) {
         float ms = 0.f;
         err = hipEventRecord(e0, s);
         if (err == hipSuccess) err = run(k);
@@ -1250,15 +1261,19 @@ int mtp_autotune(mtp_model* M, const mtp_batch* bt, int precision, int repeats, 
         if (r == 0 || ms < best_of[k]) best_of[k] = ms;
       }
   }
-  int best = 0;
-  for (int k = 0; k < n; ++k) {
+  int best = 0, best_b = n;
+  for (int k = 0; k < 2 * n; ++k) {
     if (ms_out && k < n_out) ms_out[k] = best_of[k];
-    if (best_of[k] < best_of[best]) best = k;
+    if (k < n && best_of[k] < best_of[best]) best = k;
+    if (k >= n && best_of[k] < best_of[best_b]) best_b = k;
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (err != hipSuccess) return hip_fail(err, "mtp_autotune");
-  if (fp64) M->schedule64 = best;
+  if (fp64) {
+    M->schedule64 = best;
+    M->schedule64_b = best_b - n;
+  }
   if (chosen) *chosen = best;
   return MTP_OK;
 }

@@ -167,16 +167,22 @@ class Potential:
         """Selects the pass split of the evaluation kernels (mtp_set_schedule)."""
         check(lib().mtp_set_schedule(self._h, _lib.PRECISIONS[precision], int(schedule)), "mtp_set_schedule")
 
-    def autotune(self, batch: Batch, precision="fp64", repeats=3, stream=None):
-        """Times every schedule on `batch` and keeps the fastest
-        (mtp_autotune).  Returns (chosen index, [ms per schedule])."""
-        ms = (ctypes.c_float * 16)()
+    def autotune(self, batch: Batch, precision="fp64", repeats=3, stream=None, with_b=False):
+        """Times every schedule on `batch` and keeps the fastest, without and
+        with the per-atom basis values of the descriptor sums (mtp_autotune).
+        Returns (chosen index, [ms per schedule]); with_b=True returns the
+        schedule and times of evaluations that write the basis values."""
+        ms = (ctypes.c_float * 64)()
         chosen = ctypes.c_int(-1)
         bs = batch.c_struct()
-        check(lib().mtp_autotune(self._h, ctypes.byref(bs), _lib.PRECISIONS[precision], int(repeats), ms, 16,
+        check(lib().mtp_autotune(self._h, ctypes.byref(bs), _lib.PRECISIONS[precision], int(repeats), ms, 64,
                                  ctypes.byref(chosen), _stream(stream)), "mtp_autotune")
         n = 1 if precision != "fp64" else self.n_schedules
-        return chosen.value, [float(ms[k]) for k in range(n)]
+        times = [float(ms[k]) for k in range(2 * n)]
+        if with_b:
+            t_b = times[n:]
+            return int(min(range(n), key=lambda k: t_b[k])), t_b
+        return chosen.value, times[:n]
 
     def outputs(self, batch: Batch, forces=True, virial=True, site=False, b=False, energy=True):
         """Preallocated output tensors for eval_async (dict as returned by eval)."""
