@@ -258,7 +258,7 @@ def precision_study(stream, level=24):
     B = Batch.from_arrays(box, "cuda:0")
     res, outs = {"workload": f"{N}-atom periodic disordered fcc alloy, 3 species, level {level} (E, F, virial)"}, {}
     reps = 5 if level <= 16 else 2
-    for p in ("fp64", "fp32", "fp32c"):
+    for p in ("fp64", "fp32", "fp32c", "mixed"):
         for _ in range(2 if level <= 16 else 1):
             P.eval(B, precision=p, stream=stream)
         torch.cuda.synchronize()
@@ -270,7 +270,7 @@ def precision_study(stream, level=24):
         outs[p] = {k: v.cpu().numpy() for k, v in out.items()}
         res[p] = {"value": N / dt, "unit": "atom-evals/s", "ms_per_step": dt * 1e3}
     r64 = outs["fp64"]
-    for p in ("fp32", "fp32c"):
+    for p in ("fp32", "fp32c", "mixed"):
         res[p]["vs_fp64"] = {
             "energy_per_atom_eV": abs(float(outs[p]["energy"][0]) - float(r64["energy"][0])) / N,
             "site_max_eV": float(np.abs(outs[p]["site"] - r64["site"]).max()),
@@ -295,24 +295,35 @@ def precision_study(stream, level=24):
 
 
 def fp32_accuracy(P, batch, stream):
-    """Errors of the FP32 and compensated FP32 paths against the FP64 path
-    (which the tests pin to the oracle) over every configuration of a batch:
-    energy per atom, absolute force error and the force error relative to
-    each configuration's largest force, virial per atom."""
+    """Errors of the FP32, compensated FP32 and mixed paths against the FP64
+    path (which the tests pin to the oracle) over every configuration of a
+    batch: energy per atom, absolute force error and the force error relative
+    to each configuration's largest force, virial per atom; and each
+    precision's time per evaluation (eager calls, each with its host
+    synchronisation)."""
     import numpy as np
+    import torch
 
     from paper_2007_08555_amd import Batch
     B = Batch.from_arrays(batch, "cuda:0")
-    offs = batch["atom_offsets"]
     n = np.maximum(batch["n_atoms"], 1).astype(float)
-    outs = {p: {k: v.cpu().numpy() for k, v in P.eval(B, precision=p, stream=stream).items()}
-            for p in ("fp64", "fp32", "fp32c")}
+    precs = ("fp64", "fp32", "fp32c", "mixed")
+    outs, ms = {}, {}
+    for p in precs:
+        P.eval(B, precision=p, stream=stream)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(5):
+            out = P.eval(B, precision=p, stream=stream)
+        torch.cuda.synchronize()
+        ms[p] = (time.perf_counter() - t0) / 5 * 1e3
+        outs[p] = {k: v.cpu().numpy() for k, v in out.items()}
     r64 = outs["fp64"]
     cfg_of_atom = np.repeat(np.arange(len(n)), batch["n_atoms"])
     fmax_cfg = np.zeros(len(n))
     np.maximum.at(fmax_cfg, cfg_of_atom, np.abs(r64["forces"]).max(axis=1))
-    res = {}
-    for p in ("fp32", "fp32c"):
+    res = {"eager_ms_per_eval": ms}
+    for p in ("fp32", "fp32c", "mixed"):
         dF = np.abs(outs[p]["forces"] - r64["forces"]).max(axis=1)
         dF_cfg = np.zeros(len(n))
         np.maximum.at(dF_cfg, cfg_of_atom, dF)
@@ -581,7 +592,7 @@ def main():
         torch.zeros_like(pos0).add_(jit[0])   # the first elementwise add loads its kernel (tens of ms)
         line["bcc16000"] = {"workload": f"{nb}-atom periodic bcc box, 2 species, level 16, 100 MD-style steps "
                                         f"(jitter N(0, 0.002^2) A per step, lists rebuilt every step)"}
-        for prec in ("fp32", "fp64"):
+        for prec in ("fp32", "mixed", "fp64"):
             for _ in range(2):
                 P2.eval(Bb, precision=prec, stream=stream)
             torch.cuda.synchronize()

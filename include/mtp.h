@@ -39,7 +39,13 @@ enum {
 typedef enum {
   MTP_FP64 = 0,              /* everything in FP64 */
   MTP_FP32 = 1,              /* pair vectors rounded from FP64 to FP32, FP32 arithmetic */
-  MTP_FP32_COMPENSATED = 2   /* as MTP_FP32, moments summed with an error-free TwoSum */
+  MTP_FP32_COMPENSATED = 2,  /* as MTP_FP32, moments summed with an error-free TwoSum */
+  MTP_MIXED = 3              /* moments M_{mu,nu} in FP32 from the FP64 pair
+                                vectors (rounded per pair), stored in FP32;
+                                contractions, dV/dM, the adjoint (g = dV/dr),
+                                forces, virials, site energies and b in FP64.
+                                Evaluation only (mtp_eval, mtp_eval_async,
+                                mtp_grade) */
 } mtp_precision;
 
 /* Loss weightings of section 2.2: eq. Fitting as written, eq.
@@ -259,7 +265,9 @@ int mtp_solve_normal(mtp_model* model, const double* H_dev, const double* g_dev,
  * (moments, reverse sweep, adjoint) into passes that fit the register file,
  * trading recomputation per pair against wavefronts per SIMD.  All compute
  * the same quantities (they differ only in summation order).  FP32 has one
- * schedule.
+ * schedule; the FP64 part of MTP_MIXED follows the FP64 schedules (with the
+ * contraction passes of schedule 0 for the fused ones, as for any evaluation
+ * from stored moments).
  *
  * mtp_set_schedule selects one for every evaluation (MTP_E_ARG for an index
  * outside 0 .. schedules - 1).  mtp_autotune builds the lists of `batch`,

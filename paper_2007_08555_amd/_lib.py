@@ -15,8 +15,8 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libmtp.so")
 HEADER = os.path.join(os.path.dirname(PKG), "include", "mtp.h")
 
-MTP_FP64, MTP_FP32, MTP_FP32_COMPENSATED = 0, 1, 2
-PRECISIONS = {"fp64": MTP_FP64, "fp32": MTP_FP32, "fp32c": MTP_FP32_COMPENSATED}
+MTP_FP64, MTP_FP32, MTP_FP32_COMPENSATED, MTP_MIXED = 0, 1, 2, 3
+PRECISIONS = {"fp64": MTP_FP64, "fp32": MTP_FP32, "fp32c": MTP_FP32_COMPENSATED, "mixed": MTP_MIXED}
 MTP_SCALE_MOLECULES, MTP_SCALE_STRUCTURES, MTP_SCALE_VIBRATIONS = 0, 1, 2
 SCALINGS = {"molecules": 0, "structures": 1, "vibrations": 2}
 ERRORS = {0: "MTP_OK", -1: "MTP_E_ARG", -2: "MTP_E_FILE", -3: "MTP_E_HIP",

@@ -248,9 +248,8 @@ MOMENTS_TEMPLATE = r"""
 // Moments pass {pidx}: the components of degrees {nus} of one atom, summed
 // over its pairs and written to args.M; {split} thread(s) per atom, each over
 // every {split}-th pair, partial sums combined across those lanes.
-template <typename T, bool COMP, int NQ>
-__global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2)))
-moments_{tag}_kernel(const mtp::EvalArgs<T> args) {{
+template <typename T, bool COMP, int NQ, bool PR64>
+__device__ __forceinline__ void moments_{tag}_body(const mtp::EvalArgs<T>& args) {{
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* cs = reinterpret_cast<T*>(smem_raw);
   for (int t = threadIdx.x; t < args.n_c; t += blockDim.x) cs[t + t / args.nq] = args.c[t];
@@ -279,24 +278,30 @@ moments_{tag}_kernel(const mtp::EvalArgs<T> args) {{
 #pragma unroll
   for (int k = 0; k < (COMP ? CP : 1); ++k) Mlo[k] = T(0);
   // pair p + SPLIT is loaded while pair p is processed
-  T xn = T(0), yn = T(0), zn = T(0);
+  T xn = T(0), yn = T(0), zn = T(0), un = T(0), sn = T(0);
   int zjn = 0;
   if (h < cnt) {{
-    const mtp::PairRec<T> q = args.pr[(size_t)h * args.stride + i];
-    xn = q.x; yn = q.y; zn = q.z; zjn = q.zj;
+    const mtp::PairVec<T> q = mtp::load_pair<T, PR64>(args, (size_t)h * args.stride + i);
+    xn = q.x; yn = q.y; zn = q.z; un = q.u; sn = q.s; zjn = q.zj;
   }}
 #pragma unroll 1
   for (int p = h; p < cnt; p += SPLIT) {{
-    const T x = xn, y = yn, z = zn;
+    const T x = xn, y = yn, z = zn, u = un, sc = sn;
     const int zj = zjn;
     if (p + SPLIT < cnt) {{
       const size_t en = (size_t)(p + SPLIT) * args.stride + i;
-      const mtp::PairRec<T> q = args.pr[en];
-      xn = q.x; yn = q.y; zn = q.z; zjn = q.zj;
+      const mtp::PairVec<T> q = mtp::load_pair<T, PR64>(args, en);
+      xn = q.x; yn = q.y; zn = q.z; un = q.u; sn = q.s; zjn = q.zj;
     }}
-    const T r = sqrt(x * x + y * y + z * z);
     T f[NMP], df[NMP];
-    mtp::radial<T, NMP, false, NQ>(cs, (zi * S + zj) * nqp, mu_stride, nq, r, rmin, rcut, f, df);
+    if constexpr (PR64) {{
+      // radial arguments formed in FP64 (load_pair)
+      mtp::radial_us<T, NMP, false, NQ>(cs, (zi * S + zj) * nqp, mu_stride, nq, u, sc, T(0), f, df);
+    }} else {{
+      (void)u; (void)sc;
+      const T r = sqrt(x * x + y * y + z * z);
+      mtp::radial<T, NMP, false, NQ>(cs, (zi * S + zj) * nqp, mu_stride, nq, r, rmin, rcut, f, df);
+    }}
 {body}
   }}
   if constexpr (COMP) {{
@@ -316,6 +321,20 @@ moments_{tag}_kernel(const mtp::EvalArgs<T> args) {{
   if (h != 0) return;
 #pragma unroll
   for (int k = 0; k < CP; ++k) args.M[(size_t)kIdx[k] * args.stride + i] = M[k];
+}}
+
+template <typename T, int NQ, bool PR64>
+__global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2)))
+moments_{tag}_kernel(const mtp::EvalArgs<T> args) {{
+  moments_{tag}_body<T, false, NQ, PR64>(args);
+}}
+
+// compensated sums hold two registers per component: one wavefront per SIMD
+// (the register file of two would spill)
+template <typename T, int NQ, bool PR64>
+__global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(1)))
+moments_{tag}_ckernel(const mtp::EvalArgs<T> args) {{
+  moments_{tag}_body<T, true, NQ, PR64>(args);
 }}
 """
 
@@ -937,8 +956,13 @@ __global__ void __launch_bounds__(BLOCK) contract_fwd_kernel(const mtp::EvalArgs
   if (i >= args.n_atoms) return;
   const T* __restrict__ xi = args.xi;
   T M[C];
+  if (args.M32) {{   // mixed precision: FP32 moments, widened
 #pragma unroll
-  for (int k = 0; k < C; ++k) M[k] = args.M[(size_t)k * args.stride + i];
+    for (int k = 0; k < C; ++k) M[k] = static_cast<T>(args.M32[(size_t)k * args.stride + i]);
+  }} else {{
+#pragma unroll
+    for (int k = 0; k < C; ++k) M[k] = args.M[(size_t)k * args.stride + i];
+  }}
 #define MTP_OUT_B(a_, v_) do {{ if (WANT_B) args.B[(size_t)(a_) * args.b_stride + i] = (v_); }} while (0)
 {contraction_fwd}
 #undef MTP_OUT_B
@@ -965,10 +989,14 @@ hipError_t launch_loss_t(const void* a, const void* l, hipStream_t s) {{
 #endif  // part 3
 
 #if MTP_PART == 1 || MTP_PART == 2
-template <typename T, bool COMP, bool WANT_B, int NQ>
-hipError_t launch_t(const void* a, bool reuse_moments, bool store_moments, int schedule, hipStream_t s) {{
+template <typename T, bool COMP, bool WANT_B, int NQ, bool PR64 = false>
+hipError_t launch_t(const void* a, unsigned flags, int schedule, hipStream_t s) {{
   const auto& args = *static_cast<const mtp::EvalArgs<T>*>(a);
+  const bool reuse_moments = (flags & mtp::kEvalReuseMoments) != 0;
+  const bool store_moments = (flags & mtp::kEvalStoreMoments) != 0;
+  const bool moments_only = (flags & mtp::kEvalMomentsOnly) != 0;
   (void)store_moments;
+  (void)moments_only;
   if (args.n_atoms <= 0) return hipSuccess;
   const dim3 grid((args.n_atoms + BLOCK - 1) / BLOCK);
   const size_t smem = (size_t)(args.n_c + args.n_c / args.nq) * sizeof(T);   // c, padded
@@ -993,32 +1021,31 @@ hipError_t loss(int precision, const void* a, const void* l, hipStream_t s);
 hipError_t eval64(unsigned flags, int schedule, const void* a, hipStream_t s) {{
   using namespace {ns};
   const bool want_b = (flags & mtp::kEvalWantB) != 0;
-  const bool reuse = (flags & mtp::kEvalReuseMoments) != 0;
-  const bool store = (flags & mtp::kEvalStoreMoments) != 0;
   // the pair kernels come with the radial basis size 8 fixed (unrolled) and
   // with a run-time size
   if (static_cast<const mtp::EvalArgs<double>*>(a)->nq == 8)
-    return want_b ? launch_t<double, false, true, 8>(a, reuse, store, schedule, s)
-                  : launch_t<double, false, false, 8>(a, reuse, store, schedule, s);
-  return want_b ? launch_t<double, false, true, 0>(a, reuse, store, schedule, s)
-                : launch_t<double, false, false, 0>(a, reuse, store, schedule, s);
+    return want_b ? launch_t<double, false, true, 8>(a, flags, schedule, s)
+                  : launch_t<double, false, false, 8>(a, flags, schedule, s);
+  return want_b ? launch_t<double, false, true, 0>(a, flags, schedule, s)
+                : launch_t<double, false, false, 0>(a, flags, schedule, s);
 }}
 #elif MTP_PART == 2
 hipError_t eval32(int precision, unsigned flags, int schedule, const void* a, hipStream_t s) {{
   using namespace {ns};
   const bool want_b = (flags & mtp::kEvalWantB) != 0;
-  const bool reuse = (flags & mtp::kEvalReuseMoments) != 0;
-  const bool store = (flags & mtp::kEvalStoreMoments) != 0;
+  if (precision == 3)   // mixed precision: FP32 moments from the FP64 pair records
+    return (flags & mtp::kEvalMomentsOnly) ? launch_t<float, false, false, 0, true>(a, flags, schedule, s)
+                                           : hipErrorInvalidValue;
   if (static_cast<const mtp::EvalArgs<float>*>(a)->nq == 8) {{
     if (precision == 2)
-      return want_b ? launch_t<float, true, true, 8>(a, reuse, store, schedule, s)
-                    : launch_t<float, true, false, 8>(a, reuse, store, schedule, s);
-    return want_b ? launch_t<float, false, true, 8>(a, reuse, store, schedule, s)
-                  : launch_t<float, false, false, 8>(a, reuse, store, schedule, s);
+      return want_b ? launch_t<float, true, true, 8>(a, flags, schedule, s)
+                    : launch_t<float, true, false, 8>(a, flags, schedule, s);
+    return want_b ? launch_t<float, false, true, 8>(a, flags, schedule, s)
+                  : launch_t<float, false, false, 8>(a, flags, schedule, s);
   }}
   if (precision == 2)
-    return want_b ? launch_t<float, true, true, 0>(a, reuse, store, schedule, s) : launch_t<float, true, false, 0>(a, reuse, store, schedule, s);
-  return want_b ? launch_t<float, false, true, 0>(a, reuse, store, schedule, s) : launch_t<float, false, false, 0>(a, reuse, store, schedule, s);
+    return want_b ? launch_t<float, true, true, 0>(a, flags, schedule, s) : launch_t<float, true, false, 0>(a, flags, schedule, s);
+  return want_b ? launch_t<float, false, true, 0>(a, flags, schedule, s) : launch_t<float, false, false, 0>(a, flags, schedule, s);
 }}
 #elif MTP_PART == 3
 hipError_t loss(int precision, const void* a, const void* l, hipStream_t s) {{
@@ -1033,7 +1060,7 @@ namespace {{
 namespace {ns} {{
 hipError_t launch(int precision, unsigned flags, int schedule, const void* a, hipStream_t s) {{
   if (precision == 0) return mtp_gen_{ns}::eval64(flags, schedule, a, s);
-  if (precision == 1 || precision == 2) return mtp_gen_{ns}::eval32(precision, flags, schedule, a, s);
+  if (precision >= 1 && precision <= 3) return mtp_gen_{ns}::eval32(precision, flags, schedule, a, s);
   return hipErrorInvalidValue;
 }}
 
@@ -1119,9 +1146,11 @@ def generate(lev_max, block=64):
                                  f"{_grid(sch.get('split', 1))}, dim3(BLOCK), smem, s, args);")
             # the reread of stored moments (normal equations) runs the
             # contraction of schedule 0 from them
-            body = (["if (reuse_moments) {",
+            rev0 = [l for l in sched_launch[(prec, 0)] if l.startswith("hipLaunchKernelGGL((contract_rev_")]
+            body = (["if (moments_only) return hipErrorInvalidValue;   // the moments stay in registers",
+                     "if (reuse_moments) {",
                      "  hipLaunchKernelGGL((contract_fwd_kernel<T, WANT_B>), grid, dim3(BLOCK), 0, s, args);"] +
-                    ["  " + l for l in sched_launch[(prec, 0)] if l.startswith("hipLaunchKernelGGL((contract_rev_")] +
+                    ["  " + l for l in rev0] +
                     ["} else if (store_moments) {",
                      f"  hipLaunchKernelGGL((fused_{tag}_kernel<T, WANT_B, true, NQ>), grid, dim3(BLOCK), smem, s, args);",
                      "} else {",
@@ -1139,7 +1168,7 @@ def generate(lev_max, block=64):
                                                     comp_list=", ".join(map(str, comps)),
                                                     body="\n".join(" " * 4 + l for l in body)))
             # (the moments passes measured no faster with the unrolled radial basis)
-            mom_lines.append(f"hipLaunchKernelGGL((moments_{tag}_kernel<T, COMP, 0>), {_grid(sch.get('split', 1))}, dim3(BLOCK), smem, s, args);")
+            mom_lines.append(_moments_launch(tag, sch.get('split', 1)))
         # reverse sweep passes by degree groups: each pass holds only the
         # moments and dV/dg its components need
         groups = [tuple(n for n in grp if n <= s.nu_max) for grp in sch["rev"]]
@@ -1155,7 +1184,10 @@ def generate(lev_max, block=64):
                 # FP64 passes: two wavefronts per SIMD (a pass just above 256
                 # registers spills a few words rather than halving occupancy)
                 attr=" __attribute__((amdgpu_waves_per_eu(2)))" if prec == "f64" else "",
-                load_m="\n".join(f"  M[{q}] = args.M[(size_t){q} * args.stride + i];" for q in m_used),
+                load_m="\n".join(["  if (args.M32) {  // mixed precision: FP32 moments, widened"] +
+                                 [f"    M[{q}] = static_cast<T>(args.M32[(size_t){q} * args.stride + i]);" for q in m_used] +
+                                 ["  } else {"] +
+                                 [f"    M[{q}] = args.M[(size_t){q} * args.stride + i];" for q in m_used] + ["  }"]),
                 load_dg="\n".join(f"  const T dg{g} = args.D[(size_t){g} * args.stride + i];" for g in g_used),
                 fence=" ".join(f'asm volatile("" : "+v"(M[{q}]));' for q in m_used),
                 body="\n".join("  " + l for l in body)))
@@ -1178,7 +1210,8 @@ def generate(lev_max, block=64):
             adj_lines.append(f"hipLaunchKernelGGL((adjoint_{tag}_kernel<T, {first}, {last}, NQ>), "
                              f"{_grid(sch.get('split', 1))}, dim3(BLOCK), smem, s, args);")
         body = (["if (!reuse_moments) {"] + ["  " + l for l in mom_lines] + ["}"] +
-                ["hipLaunchKernelGGL((contract_fwd_kernel<T, WANT_B>), grid, dim3(BLOCK), 0, s, args);"] +
+                ["if (moments_only) return hipGetLastError();",
+                 "hipLaunchKernelGGL((contract_fwd_kernel<T, WANT_B>), grid, dim3(BLOCK), 0, s, args);"] +
                 rev_lines + adj_lines)
         sched_launch[(prec, sidx)] = body
     # loss path: the contraction on dual numbers, split into graph passes,
@@ -1403,10 +1436,11 @@ struct Tab {{
 {kernels32}
 #endif
 
-template <typename T, bool COMP, bool WANT_B, int NQ>
-hipError_t launch_t(const void* a, bool reuse_moments, bool store_moments, int schedule, hipStream_t s) {{
+template <typename T, bool COMP, bool WANT_B, int NQ, bool PR64 = false>
+hipError_t launch_t(const void* a, unsigned flags, int schedule, hipStream_t s) {{
   const auto& args = *static_cast<const mtp::EvalArgs<T>*>(a);
-  (void)store_moments;   // the moments always go through memory here
+  const bool reuse_moments = (flags & mtp::kEvalReuseMoments) != 0;   // the moments always go through memory
+  const bool moments_only = (flags & mtp::kEvalMomentsOnly) != 0;
   if (schedule != 0) return hipErrorInvalidValue;
   if (args.n_atoms <= 0) return hipSuccess;
   const dim3 grid((args.n_atoms + BLOCK - 1) / BLOCK);
@@ -1447,23 +1481,22 @@ hipError_t loss(int precision, const void* a, const void* l, hipStream_t s);
 hipError_t eval64(unsigned flags, int schedule, const void* a, hipStream_t s) {{
   using namespace {ns};
   const bool want_b = (flags & mtp::kEvalWantB) != 0;
-  const bool reuse = (flags & mtp::kEvalReuseMoments) != 0;
-  const bool store = (flags & mtp::kEvalStoreMoments) != 0;
   if (static_cast<const mtp::EvalArgs<double>*>(a)->nq == 8)
-    return want_b ? launch_t<double, false, true, 8>(a, reuse, store, schedule, s)
-                  : launch_t<double, false, false, 8>(a, reuse, store, schedule, s);
-  return want_b ? launch_t<double, false, true, 0>(a, reuse, store, schedule, s)
-                : launch_t<double, false, false, 0>(a, reuse, store, schedule, s);
+    return want_b ? launch_t<double, false, true, 8>(a, flags, schedule, s)
+                  : launch_t<double, false, false, 8>(a, flags, schedule, s);
+  return want_b ? launch_t<double, false, true, 0>(a, flags, schedule, s)
+                : launch_t<double, false, false, 0>(a, flags, schedule, s);
 }}
 #elif MTP_PART == 2
 hipError_t eval32(int precision, unsigned flags, int schedule, const void* a, hipStream_t s) {{
   using namespace {ns};
   const bool want_b = (flags & mtp::kEvalWantB) != 0;
-  const bool reuse = (flags & mtp::kEvalReuseMoments) != 0;
-  const bool store = (flags & mtp::kEvalStoreMoments) != 0;
+  if (precision == 3)   // mixed precision: FP32 moments from the FP64 pair records
+    return (flags & mtp::kEvalMomentsOnly) ? launch_t<float, false, false, 0, true>(a, flags, schedule, s)
+                                           : hipErrorInvalidValue;
   if (precision == 2)
-    return want_b ? launch_t<float, true, true, 0>(a, reuse, store, schedule, s) : launch_t<float, true, false, 0>(a, reuse, store, schedule, s);
-  return want_b ? launch_t<float, false, true, 0>(a, reuse, store, schedule, s) : launch_t<float, false, false, 0>(a, reuse, store, schedule, s);
+    return want_b ? launch_t<float, true, true, 0>(a, flags, schedule, s) : launch_t<float, true, false, 0>(a, flags, schedule, s);
+  return want_b ? launch_t<float, false, true, 0>(a, flags, schedule, s) : launch_t<float, false, false, 0>(a, flags, schedule, s);
 }}
 #elif MTP_PART == 3
 hipError_t loss(int precision, const void* a, const void* l, hipStream_t s) {{
@@ -1478,7 +1511,7 @@ namespace {{
 namespace {ns} {{
 hipError_t launch(int precision, unsigned flags, int schedule, const void* a, hipStream_t s) {{
   if (precision == 0) return mtp_gen_{ns}::eval64(flags, schedule, a, s);
-  if (precision == 1 || precision == 2) return mtp_gen_{ns}::eval32(precision, flags, schedule, a, s);
+  if (precision >= 1 && precision <= 3) return mtp_gen_{ns}::eval32(precision, flags, schedule, a, s);
   return hipErrorInvalidValue;
 }}
 
@@ -1508,6 +1541,13 @@ SCHEDULE_TABLE = {"f64": {"mom": 85, "adj": 90}, "f32": {"mom": 120, "adj": 120}
 TABLE_LOSS_MAX_LEVEL = 20
 
 
+def _moments_launch(tag, split):
+    """Launch of one moments pass: the compensated kernel when COMP."""
+    grid = _grid(split)
+    return (f"if constexpr (COMP) {{ hipLaunchKernelGGL((moments_{tag}_ckernel<T, 0, PR64>), {grid}, dim3(BLOCK), smem, s, args); }} "
+            f"else {{ hipLaunchKernelGGL((moments_{tag}_kernel<T, 0, PR64>), {grid}, dim3(BLOCK), smem, s, args); }}")
+
+
 def _pair_pass_kernels(s, prec, sidx, sch):
     """Moments and adjoint pass kernels of one schedule and their launches."""
     src, mom_lines, adj_lines = [], [], []
@@ -1519,7 +1559,7 @@ def _pair_pass_kernels(s, prec, sidx, sch):
         src.append(MOMENTS_TEMPLATE.format(split=sch.get("split", 1), pidx=pidx, nus=nus, tag=tag, ncomp=len(comps), nmu=nmu,
                                            comp_list=", ".join(map(str, comps)),
                                            body="\n".join(" " * 4 + l for l in body)))
-        mom_lines.append(f"hipLaunchKernelGGL((moments_{tag}_kernel<T, COMP, 0>), {_grid(sch.get('split', 1))}, dim3(BLOCK), smem, s, args);")
+        mom_lines.append(_moments_launch(tag, sch.get('split', 1)))
     passes = adjoint_passes(s, sch["adj"])
     for pidx, (nus, comps) in enumerate(passes):
         tag = f"{prec}s{sidx}_p{pidx}"
@@ -1553,7 +1593,8 @@ def generate_table(lev_max):
     for prec in ("f64", "f32"):
         src, mom, adj = _pair_pass_kernels(s, prec, 0, SCHEDULE_TABLE[prec])
         launch = (["if (!reuse_moments) {"] + ["  " + l for l in mom] + ["}"] +
-                  ["hipLaunchKernelGGL((mtp::contract_table_kernel<T, WANT_B, Tab>), grid, dim3(BLOCK), 0, s, args);"] +
+                  ["if (moments_only) return hipGetLastError();",
+                   "hipLaunchKernelGGL((mtp::contract_table_kernel<T, WANT_B, Tab>), grid, dim3(BLOCK), 0, s, args);"] +
                   adj)
         parts[prec] = ("\n".join(src), "\n".join("  " + l for l in launch))
     with_loss = lev_max <= TABLE_LOSS_MAX_LEVEL

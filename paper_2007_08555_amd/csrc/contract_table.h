@@ -146,7 +146,9 @@ __global__ void __launch_bounds__(64) contract_table_kernel(const EvalArgs<T> ar
   T* Gi = args.G + i;
   T* Dg = args.D + i;
   T* Dv = args.D + (size_t)Tab::kGraphs * st + i;
-  const auto mload = [&](int k) { return Mi[(size_t)k * st]; };
+  // (mixed precision: FP32 moments, widened)
+  const float* M32i = args.M32 ? args.M32 + i : nullptr;
+  const auto mload = [&](int k) { return M32i ? static_cast<T>(M32i[(size_t)k * st]) : Mi[(size_t)k * st]; };
   graphs_forward<T, 1, Tab>(mload, [&](int g, T v) { Dv[(size_t)g * st] = v; });
   for (int g = 0; g < Tab::kGraphs; ++g) Dg[(size_t)g * st] = T(0);
   const T V = basis_products<T, Tab>(

@@ -322,8 +322,12 @@ mtp::EvalArgs<T> make_args(mtp_model* M, int64_t n_atoms, int stride, const int3
   a.n_c = M->n_c;
   a.rmin = (T)M->rmin;
   a.rcut = (T)M->rcut;
+  a.rmin64 = M->rmin;
+  a.rcut64 = M->rcut;
   a.nbr_count = M->count.as<int>();
   a.pr = M->pr.as<mtp::PairRec<T>>();
+  a.pr64 = nullptr;
+  a.M32 = nullptr;
   a.species = species;
   a.c = std::is_same<T, double>::value ? (const T*)M->c64.p : (const T*)M->c32.p;
   a.xi = std::is_same<T, double>::value ? (const T*)M->xi64.p : (const T*)M->xi32.p;
@@ -347,7 +351,10 @@ int run_eval(mtp_model* M, const mtp_batch* bt, const mtp_out* out, int precisio
   using namespace mtp;
   const int64_t N = bt->n_atoms;
   const int n_cfg = bt->n_configs;
-  const bool fp64 = precision == MTP_FP64;
+  // the mixed-precision path computes the moments in FP32 (from FP64 pair
+  // records) and everything else in FP64
+  const bool mixed = precision == MTP_MIXED;
+  const bool fp64 = precision == MTP_FP64 || mixed;
   const size_t tsz = fp64 ? sizeof(double) : sizeof(float);
   M->timed = false;
   M->last_stream = s;
@@ -470,7 +477,20 @@ int run_eval(mtp_model* M, const mtp_batch* bt, const mtp_out* out, int precisio
     HIP_TRY(mark(1), "hipEventRecord");
     if (N > 0) {
       const unsigned flags = (want_b ? kEvalWantB : 0u) | (store_moments ? kEvalStoreMoments : 0u);
-      if (fp64) {
+      if (mixed) {
+        // FP32 moments from the FP64 pair records into M (as floats), then
+        // the FP64 contractions (reading them widened) and adjoint passes
+        auto em = make_args<float>(M, N, stride, bt->species, false);
+        em.pr = nullptr;
+        em.pr64 = M->pr.as<PairRec<double>>();
+        HIP_TRY(M->var->launch_eval(MTP_MIXED, kEvalMomentsOnly, 0, &em, s), "moment kernels");
+        auto ea = make_args<double>(M, N, stride, bt->species, want_b);
+        ea.M = nullptr;
+        ea.M32 = M->Mbuf.as<float>();
+        HIP_TRY(M->var->launch_eval(MTP_FP64, flags | kEvalReuseMoments, want_b ? M->schedule64_b : M->schedule64,
+                                    &ea, s),
+                "evaluation kernels");
+      } else if (fp64) {
         auto ea = make_args<double>(M, N, stride, bt->species, want_b);
         HIP_TRY(M->var->launch_eval(precision, flags, want_b ? M->schedule64_b : M->schedule64, &ea, s),
                 "evaluation kernels");
@@ -596,7 +616,7 @@ int mtp_get_params(const mtp_model* M, double* c_host, double* xi_host) {
 int mtp_eval(mtp_model* M, const mtp_batch* bt, const mtp_out* out, int precision, void* stream) {
   g_err.clear();
   if (!M || !bt || !out) return fail(MTP_E_ARG, "mtp_eval: null argument");
-  if (precision < MTP_FP64 || precision > MTP_FP32_COMPENSATED) return fail(MTP_E_ARG, "mtp_eval: bad precision");
+  if (precision < MTP_FP64 || precision > MTP_MIXED) return fail(MTP_E_ARG, "mtp_eval: bad precision");
   if (bt->n_configs < 0 || bt->n_atoms < 0) return fail(MTP_E_ARG, "mtp_eval: negative size");
   if (bt->n_configs > 0 && (!bt->atom_offsets || !bt->cell || !bt->pbc))
     return fail(MTP_E_ARG, "mtp_eval: null batch array");
@@ -608,7 +628,7 @@ int mtp_eval(mtp_model* M, const mtp_batch* bt, const mtp_out* out, int precisio
 int mtp_eval_async(mtp_model* M, const mtp_batch* bt, const mtp_out* out, int precision, void* stream) {
   g_err.clear();
   if (!M || !bt || !out) return fail(MTP_E_ARG, "mtp_eval_async: null argument");
-  if (precision < MTP_FP64 || precision > MTP_FP32_COMPENSATED) return fail(MTP_E_ARG, "mtp_eval_async: bad precision");
+  if (precision < MTP_FP64 || precision > MTP_MIXED) return fail(MTP_E_ARG, "mtp_eval_async: bad precision");
   if (bt->n_configs < 0 || bt->n_atoms < 0) return fail(MTP_E_ARG, "mtp_eval_async: negative size");
   if (bt->n_configs > 0 && (!bt->atom_offsets || !bt->cell || !bt->pbc))
     return fail(MTP_E_ARG, "mtp_eval_async: null batch array");

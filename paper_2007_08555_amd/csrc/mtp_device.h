@@ -38,13 +38,18 @@ struct EvalArgs {
   int n_species;       // S
   int n_c;             // n_mu * S * S * N_Q
   T rmin, rcut;
+  double rmin64, rcut64; // the same in FP64 (radial arguments of the mixed-precision path)
   const int* nbr_count;  // [n_atoms]
   const PairRec<T>* pr;  // [K * stride] pair vectors and neighbour species
+  const PairRec<double>* pr64;  // the same in FP64, read instead of pr by the moments
+                                // passes of the mixed-precision path (else unused)
   const int* species;    // [n_atoms]
   const T* c;            // [n_mu][S][S][N_Q]
   const T* xi;           // [m] in the kernel's basis order
   T* site;               // [n_atoms]   site energies V_i
   T* M;                  // [C][stride] moment components of every atom
+  const float* M32;      // the same in FP32, read instead of M by the contraction
+                         // kernels of the mixed-precision path (else null)
   T* G;                  // [C][stride] dV_i / dM (moment components)
   T* g;                  // [K * stride][3] dV_i / dr_ij, packed per pair
   T* atom_virial;        // [9][stride]  sum_j g_a r_b
@@ -54,19 +59,43 @@ struct EvalArgs {
   int b_stride;
 };
 
+// One pair's vector and neighbour species in the arithmetic type T: from
+// the records of the evaluation's own precision, or (PR64, the moments of
+// the mixed-precision path) from the FP64 records, rounded to T after the
+// radial arguments were formed from them in FP64: the Chebyshev argument u
+// of |r| and s = R_cut - |r| (a distance rounded to FP32 moves an atom by
+// about 1e-7 A, and the steep radial functions turn that into force errors
+// of tens of micro-eV/A; rounding u and s instead keeps them near 1e-6).
+template <typename T>
+struct PairVec {
+  T x, y, z;
+  T u, s;   // (PR64 only) Chebyshev argument and R_cut - |r|
+  int zj;
+};
+template <typename T, bool PR64>
+__device__ __forceinline__ PairVec<T> load_pair(const EvalArgs<T>& a, size_t e) {
+  if constexpr (PR64) {
+    const PairRec<double> q = a.pr64[e];
+    const double r = sqrt(q.x * q.x + q.y * q.y + q.z * q.z);
+    const double span_inv = 1.0 / (a.rcut64 - a.rmin64);
+    const double u = (2.0 * r - a.rmin64 - a.rcut64) * span_inv;
+    return {(T)q.x, (T)q.y, (T)q.z, (T)u, (T)(a.rcut64 - r), q.zj};
+  } else {
+    const PairRec<T> q = a.pr[e];
+    return {q.x, q.y, q.z, T(0), T(0), q.zj};
+  }
+}
+
 // f_mu and, when DERIV, df_mu/dr for the NMU radial functions of one pair.
 // cs points at c staged in LDS; base = ((0 * S + zi) * S + zj) * nq and the
 // stride between consecutive mu is S * S * nq.
 // NQ > 0 fixes the radial basis size at compile time (nq is then ignored
 // and the recurrence is unrolled); NQ = 0 takes nq at run time.
+// radial_us takes the Chebyshev argument x of r, dx/dr and s = R_cut - r.
 template <typename T, int NMU, bool DERIV, int NQ = 0>
-__device__ __forceinline__ void radial(const T* __restrict__ cs, int base, int mu_stride, int nq,
-                                       T r, T rmin, T rcut, T (&f)[NMU], T (&df)[NMU]) {
+__device__ __forceinline__ void radial_us(const T* __restrict__ cs, int base, int mu_stride, int nq,
+                                          T x, T s, T dxdr, T (&f)[NMU], T (&df)[NMU]) {
   if constexpr (NQ > 0) nq = NQ;
-  const T span_inv = T(1) / (rcut - rmin);
-  const T x = (T(2) * r - rmin - rcut) * span_inv;
-  const T dxdr = T(2) * span_inv;
-  const T s = rcut - r;
   T acc[NMU], dacc[NMU];
 #pragma unroll
   for (int mu = 0; mu < NMU; ++mu) {
@@ -98,6 +127,15 @@ __device__ __forceinline__ void radial(const T* __restrict__ cs, int base, int m
     f[mu] = acc[mu] * s2;
     if (DERIV) df[mu] = dacc[mu] * dxdr * s2 - T(2) * s * acc[mu];
   }
+}
+
+template <typename T, int NMU, bool DERIV, int NQ = 0>
+__device__ __forceinline__ void radial(const T* __restrict__ cs, int base, int mu_stride, int nq,
+                                       T r, T rmin, T rcut, T (&f)[NMU], T (&df)[NMU]) {
+  const T span_inv = T(1) / (rcut - rmin);
+  const T x = (T(2) * r - rmin - rcut) * span_inv;
+  const T dxdr = T(2) * span_inv;
+  radial_us<T, NMU, DERIV, NQ>(cs, base, mu_stride, nq, x, rcut - r, dxdr, f, df);
 }
 
 // Sum over aligned groups of SPLIT consecutive lanes (SPLIT = 1, 2 or 4):

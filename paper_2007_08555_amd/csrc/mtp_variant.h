@@ -6,10 +6,17 @@
 namespace mtp {
 
 // Flags of launch_eval: also write every B_alpha; keep the moments already in
-// args.M (same pairs and radial coefficients) instead of recomputing them;
-// leave the moments in args.M (schedules that keep them in registers skip
-// that store otherwise) for a later reuse or for the loss kernels.
-enum : unsigned { kEvalWantB = 1u, kEvalReuseMoments = 2u, kEvalStoreMoments = 4u };
+// args.M (or args.M32; same pairs and radial coefficients) instead of
+// recomputing them; leave the moments in args.M (schedules that keep them in
+// registers skip that store otherwise) for a later reuse or for the loss
+// kernels; compute the moments only (the first half of the mixed-precision
+// path).
+enum : unsigned {
+  kEvalWantB = 1u,
+  kEvalReuseMoments = 2u,
+  kEvalStoreMoments = 4u,
+  kEvalMomentsOnly = 8u
+};
 
 struct BasisVariant {
   const char* name;
@@ -28,7 +35,9 @@ struct BasisVariant {
   double flops_pair_fwd;         // algorithmic flops per pair (N_Q = 8), forward
   double flops_pair_bwd;         // per pair, adjoint
   double flops_atom;             // per atom, contraction forward + reverse
-  // precision: 0 = FP64, 1 = FP32, 2 = FP32 with compensated moment sums
+  // precision: 0 = FP64, 1 = FP32, 2 = FP32 with compensated moment sums,
+  // 3 = FP32 moments from the FP64 pair records (args.pr64), with
+  // kEvalMomentsOnly: the first half of the mixed-precision path
   // schedule: index of the FP64 pass split (0 .. n_schedules - 1; FP32 has only 0)
   hipError_t (*launch_eval)(int precision, unsigned flags, int schedule, const void* args, hipStream_t stream);
   // loss-gradient kernels after an evaluation that left M and G in place

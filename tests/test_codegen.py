@@ -32,7 +32,7 @@ def test_launched_kernels_are_defined(level):
     src, _ = codegen.generate(level)
     src = src.replace("mtp::contract_table", "contract_table")
     launched = set(re.findall(r"hipLaunchKernelGGL\(\((\w+)<", src))
-    defined = set(re.findall(r"(\w+_kernel)\(const mtp::EvalArgs", src))
+    defined = set(re.findall(r"(\w+_c?kernel)\(const mtp::EvalArgs", src))
     assert launched and launched <= defined, launched - defined
     # one case per FP64 schedule in the evaluation launcher
     assert len(re.findall(r"\n\s*case \d+: \{", src)) == len(codegen.SCHEDULES_F64)
@@ -42,7 +42,7 @@ def test_launched_kernels_are_defined(level):
 def test_table_level_launches(level):
     src, meta = codegen.generate_table(level)
     launched = set(re.findall(r"hipLaunchKernelGGL\(\((?:mtp::)?(\w+)<", src))
-    defined = set(re.findall(r"(\w+_kernel)\(const mtp::EvalArgs", src))
+    defined = set(re.findall(r"(\w+_c?kernel)\(const mtp::EvalArgs", src))
     defined |= {"contract_table_kernel", "contract_table_loss_kernel"}   # csrc/contract_table.h
     assert launched and launched <= defined, launched - defined
     assert meta["table"] and meta["loss"] and meta["trie_nodes"] > 0

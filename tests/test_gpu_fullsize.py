@@ -135,13 +135,14 @@ def test_fcc256k_fp64_sampled_atoms():
     assert e_err <= 1e-11 and f_err <= 1e-10
 
 
-@pytest.mark.parametrize("precision", ["fp32", "fp32c"])
+@pytest.mark.parametrize("precision", ["fp32", "fp32c", "mixed"])
 def test_fcc256k_fp32_against_fp64(precision):
-    """FP32 and FP32 with compensated moment sums against FP64 over the whole
-    alloy box: the guard at FP32's rounding level (forces within 1e-5 of the
-    largest force), then the stated absolute bounds (energy per atom 1e-6 eV,
-    force 1e-5 eV/A), which FP32 misses here: the box has forces of hundreds
-    of eV/A (atoms pushed towards R_min) and the FP32 error scales with them."""
+    """FP32, FP32 with compensated moment sums and the mixed path (FP32
+    moments, the rest in FP64) against FP64 over the whole alloy box: the
+    guard at FP32's rounding level (forces within 1e-5 of the largest force),
+    then the stated absolute bounds (energy per atom 1e-6 eV, force 1e-5
+    eV/A), which all three miss here: the box has forces of hundreds of eV/A
+    (atoms pushed towards R_min) and the FP32 error scales with them."""
     box, res = _fcc256k(["fp64", precision])
     N = int(box["n_atoms"][0])
     r64, r32 = res["fp64"], res[precision]
@@ -153,14 +154,14 @@ def test_fcc256k_fp32_against_fp64(precision):
         f"largest force error {df:.3e} eV/A (largest force {fscale:.3g})")
     assert de <= 1e-6 and df <= 1e-5 * fscale and ds <= 1e-3
     if df > 1e-5:
-        pytest.xfail(f"fcc256k {precision}: FP32 force error {df:.3e} eV/A exceeds 1e-5 eV/A "
+        pytest.xfail(f"fcc256k {precision}: force error {df:.3e} eV/A exceeds 1e-5 eV/A "
                      f"(largest force {fscale:.3g} eV/A)")
 
 
-@pytest.mark.parametrize("precision", ["fp32", "fp32c"])
+@pytest.mark.parametrize("precision", ["fp32", "fp32c", "mixed"])
 def test_batched_workload_full_size_fp32(precision):
-    """The batched workload in FP32 (plain and compensated moment sums),
-    sampled configurations against the oracle.  Guard at FP32's rounding
+    """The batched workload in FP32 (plain and compensated moment sums) and
+    on the mixed path, sampled configurations against the oracle.  Guard at FP32's rounding
     level: energy per atom within 1e-6 eV, forces within 1e-5 of the
     configuration's largest force, b within 2e-5 relative.  Then the stated
     absolute bounds (force 1e-5 eV/A, virial per atom 5e-5 eV): an expected
@@ -191,5 +192,5 @@ def test_batched_workload_full_size_fp32(precision):
     assert worst["e"] <= 1e-6 and worst["f_rel"] <= 1e-5 and worst["b"] <= 2e-5
     miss = {k: worst[k] for k, v in (("f", 1e-5), ("w", 5e-5)) if worst[k] > v}
     if miss:
-        pytest.xfail(f"full batch {precision}: FP32 misses the absolute bounds (force 1e-5 eV/A, "
+        pytest.xfail(f"full batch {precision}: misses the absolute bounds (force 1e-5 eV/A, "
                      f"virial per atom 5e-5 eV): measured {miss}")

@@ -4,7 +4,8 @@ evaluation against the FP64 oracle on small configurations, then on sampled
 atoms of the 256 000-atom disordered fcc alloy (40^3 cells, a = 3.6 A,
 sigma = 0.2 A, three species), and FP32 / compensated FP32 against FP64 over
 the whole box, held to the stated absolute bounds (an expected failure, with
-the numbers, where FP32 misses them)."""
+the numbers, where FP32 misses them); the same for the mixed-precision path
+(FP32 moments, everything else in FP64)."""
 import numpy as np
 import pytest
 
@@ -71,7 +72,7 @@ def test_level24_alloy_box_sampled_atoms(lev24):
     assert np.abs(F.sum(axis=0)).max() <= 1e-9 * np.abs(F).max() * np.sqrt(N)
 
 
-@pytest.mark.parametrize("precision", ["fp32", "fp32c"])
+@pytest.mark.parametrize("precision", ["fp32", "fp32c", "mixed"])
 def test_level24_alloy_box_fp32(lev24, precision):
     P, _ = lev24
     box, res = _box_results(P, ["fp64", precision])
