@@ -31,25 +31,27 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "atom-evals/s (E+F+stress) MTP lev16; batched vs plain at force err ≤1e-5 eV/Å"
-PEAK = {"fp64": 78.6, "fp32": 157.3, "fp32c": 157.3}   # TFLOP/s, MI355X vector FP64 / FP32
-DTYPE = {"fp64": "f64", "fp32": "f32", "fp32c": "f32"}
+# TFLOP/s, MI355X vector FP64 / FP32 (the mixed path does all but the moments in FP64)
+PEAK = {"fp64": 78.6, "fp32": 157.3, "fp32c": 157.3, "mixed": 78.6}
+DTYPE = {"fp64": "f64", "fp32": "f32", "fp32c": "f32", "mixed": "f64 (moments f32)"}
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-TRAFFIC_MD = os.path.join(ROOT, "profiles", "eval_lev16_batch4096_fp64_hbm.md")
+TRAFFIC_MD = os.path.join(ROOT, "profiles", "eval_lev16_batch4096_fp64_s{}_hbm.md")
 KERNEL_SRC = os.path.join(ROOT, "paper_2007_08555_amd", "csrc", "generated", "gen_lev16.inc")
 
 
-def measured_traffic():
-    """HBM bytes per launch of the evaluation kernels from the committed
-    FETCH_SIZE / WRITE_SIZE summary, when it was taken on the kernels built
-    here (same generated source); else None."""
+def measured_traffic(schedule):
+    """HBM bytes per launch of the evaluation kernels of one FP64 schedule
+    from the committed FETCH_SIZE / WRITE_SIZE summary, when it was taken on
+    the kernels built here (same generated source); else None."""
     import hashlib
     try:
-        fields = dict(line.split(": ", 1) for line in open(TRAFFIC_MD).read().splitlines() if ": " in line
+        fields = dict(line.split(": ", 1) for line in open(TRAFFIC_MD.format(schedule)).read().splitlines()
+                      if ": " in line
                       and line.split(": ", 1)[0] in ("traffic_bytes_per_launch", "kernel_source_sha256"))
         with open(KERNEL_SRC, "rb") as fh:
             digest = hashlib.sha256(fh.read()).hexdigest()
@@ -424,7 +426,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "fp32c"])
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "fp32c", "mixed"])
     ap.add_argument("--configs", type=int, default=4096)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-extras", action="store_true", help="skip plain path, bcc box and CPU baseline")
@@ -476,9 +478,11 @@ def main():
     # the library's autotuner picks the FP64 pass split for this batch
     t_at = time.perf_counter()
     # the step writes the basis values of the descriptor sums (for the grade)
-    chosen, sched_ms = P.autotune(B, precision=a.precision, repeats=3, with_b=True)
+    # (the mixed path runs all but its moments with the FP64 schedules)
+    tune_precision = "fp64" if a.precision == "mixed" else a.precision
+    chosen, sched_ms = P.autotune(B, precision=tune_precision, repeats=3, with_b=True)
     if a.schedule >= 0:
-        P.set_schedule(a.schedule, precision=a.precision)
+        P.set_schedule(a.schedule, precision=tune_precision)
         chosen = a.schedule
     log(f"autotune: schedule {chosen} of {len(sched_ms)} ({', '.join(f'{t:.3f}' for t in sched_ms)} ms "
         f"evaluation kernels), {time.perf_counter() - t_at:.2f} s")
@@ -552,7 +556,7 @@ def main():
     ms = {k: float(np.mean(v)) for k, v in ms.items()}
     flops = st["n_pairs"] * (st["flops_pair_fwd"] + st["flops_pair_bwd"]) + st["n_atoms"] * st["flops_atom"]
     achieved = flops / (ms["ms_eval"] * 1e-3) / 1e12
-    traffic = measured_traffic() if (a.precision == "fp64" and a.configs == 4096) else None
+    traffic = measured_traffic(chosen) if (a.precision == "fp64" and a.configs == 4096) else None
     roofline = {"bound": "alu", "achieved": achieved, "peak": PEAK[a.precision], "unit": "TFLOP/s",
                 "frac": achieved / PEAK[a.precision], "traffic": traffic,
                 "traffic_hbm_TBps": None if traffic is None else traffic / (ms["ms_eval"] * 1e-3) / 1e12,
