@@ -1594,7 +1594,14 @@ def generate_table(lev_max):
         src, mom, adj = _pair_pass_kernels(s, prec, 0, SCHEDULE_TABLE[prec])
         launch = (["if (!reuse_moments) {"] + ["  " + l for l in mom] + ["}"] +
                   ["if (moments_only) return hipGetLastError();",
-                   "hipLaunchKernelGGL((mtp::contract_table_kernel<T, WANT_B, Tab>), grid, dim3(BLOCK), 0, s, args);"] +
+                   "if (args.M32) {   // mixed precision: FP32 moments",
+                   "  if constexpr (std::is_same<T, double>::value)",
+                   "    hipLaunchKernelGGL((mtp::contract_table_kernel<T, WANT_B, Tab, true>), grid, dim3(BLOCK), 0, s, args);",
+                   "  else",
+                   "    return hipErrorInvalidValue;",
+                   "} else {",
+                   "  hipLaunchKernelGGL((mtp::contract_table_kernel<T, WANT_B, Tab>), grid, dim3(BLOCK), 0, s, args);",
+                   "}"] +
                   adj)
         parts[prec] = ("\n".join(src), "\n".join("  " + l for l in launch))
     with_loss = lev_max <= TABLE_LOSS_MAX_LEVEL

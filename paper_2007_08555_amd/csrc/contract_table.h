@@ -21,6 +21,8 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "mtp_device.h"
 
 namespace mtp {
@@ -137,18 +139,24 @@ __device__ __forceinline__ T basis_products(const XiLoad& xiload, const VLoad& v
 // Forward contraction, basis products and reverse sweep of one atom per
 // thread: graph values to the upper half of D, B (when wanted), V to site,
 // dV/dg to the lower half of D, G = dV/dM.
-template <typename T, bool WANT_B, typename Tab>
+// M32: the moments are read from args.M32 (FP32, the mixed-precision path)
+// and widened.
+template <typename T, bool WANT_B, typename Tab, bool M32 = false>
 __global__ void __launch_bounds__(64) contract_table_kernel(const EvalArgs<T> args) {
   const int i = blockIdx.x * 64 + threadIdx.x;
   if (i >= args.n_atoms) return;
   const size_t st = args.stride;
   const T* Mi = args.M + i;
+  const float* M32i = args.M32 + i;
   T* Gi = args.G + i;
   T* Dg = args.D + i;
   T* Dv = args.D + (size_t)Tab::kGraphs * st + i;
-  // (mixed precision: FP32 moments, widened)
-  const float* M32i = args.M32 ? args.M32 + i : nullptr;
-  const auto mload = [&](int k) { return M32i ? static_cast<T>(M32i[(size_t)k * st]) : Mi[(size_t)k * st]; };
+  const auto mload = [&](int k) {
+    if constexpr (M32)
+      return static_cast<T>(M32i[(size_t)k * st]);
+    else
+      return Mi[(size_t)k * st];
+  };
   graphs_forward<T, 1, Tab>(mload, [&](int g, T v) { Dv[(size_t)g * st] = v; });
   for (int g = 0; g < Tab::kGraphs; ++g) Dg[(size_t)g * st] = T(0);
   const T V = basis_products<T, Tab>(
