@@ -386,11 +386,12 @@ int run_eval(mtp_model* M, const mtp_batch* bt, const mtp_out* out, int precisio
     NEED(*b, sizeof(int32_t) * (N + 1));
   const int stride = (int)((N + 63) / 64 * 64);
   const bool want_b = out->b != nullptr;
-  NEED(M->run_start, sizeof(int16_t) * 256 * (size_t)(N + 1));
   for (int attempt = 0; attempt < 2; ++attempt) {
     const int K = M->K;
     const size_t slots = (size_t)K * stride;
     if (slots >= (size_t)0x7fffffff) return fail(MTP_E_CAPACITY, "neighbour slots exceed 2^31 (split the batch)");
+    // run starts of the small-configuration search: only for lists too long for LDS
+    if (K > kLdsListSlots) NEED(M->run_start, sizeof(int16_t) * 256 * (size_t)(N + 1));
     NEED(M->nbr, sizeof(int32_t) * slots);
     NEED(M->rev, sizeof(int32_t) * slots);
     NEED(M->pr, (fp64 ? sizeof(PairRec<double>) : sizeof(PairRec<float>)) * slots);
@@ -458,7 +459,7 @@ int run_eval(mtp_model* M, const mtp_batch* bt, const mtp_out* out, int precisio
     a.pr = M->pr.p;
     a.fp64 = fp64 ? 1 : 0;
     a.rev = M->rev.as<int32_t>();
-    a.run_start = M->run_start.as<int16_t>();
+    a.run_start = K > kLdsListSlots ? M->run_start.as<int16_t>() : nullptr;
     a.status = M->status.as<Status>();
     if (reuse) {
       HIP_TRY(refresh_pairs(a, M->img.as<short4>(), s), "pair refresh");

@@ -21,6 +21,10 @@ struct CfgInfo {
 };
 
 
+// Neighbour capacity up to which the small-configuration search builds its
+// lists in LDS (above it, it writes them directly and needs run_start).
+constexpr int kLdsListSlots = 128;
+
 struct NbrArgs {
   int n_cfg;
   int64_t n_atoms;
@@ -49,7 +53,8 @@ struct NbrArgs {
   void* pr;              // [K * stride] PairRec<double> or PairRec<float>
   int fp64;              // pair record type
   int32_t* rev;          // [K * stride] ELL index of the reverse pair
-  int16_t* run_start;    // [n_atoms][256] scratch of the small-configuration search
+  int16_t* run_start;    // [n_atoms][256] scratch of the small-configuration search when
+                         // K > kLdsListSlots (else unused, may be null)
   Status* status;
 };
 

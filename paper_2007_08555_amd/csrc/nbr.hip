@@ -607,7 +607,7 @@ __global__ void reverse_large_kernel(NbrArgs a) {
 // binary search of j's LDS list.  With a larger K the search writes the
 // records directly and records run starts in a global table
 // (run_start[i][j]) that reverse_kernel reads.
-constexpr int kLdsSlots = 128;
+constexpr int kLdsSlots = kLdsListSlots;
 
 // Per-atom LDS records of the small search: FP64 position, FP32 wrapped
 // fractional coordinates u, their integer parts m and the clamped species.

@@ -80,3 +80,56 @@ def test_loss_gradient_on_a_training_shaped_batch():
     log(f"[loss training-shaped] loss gpu {loss:.10e} oracle {L_o:.10e}; grad entries {idx}: max rel err {err.max():.3e}")
     assert abs(loss - L_o) <= 1e-10 * abs(L_o)
     assert err.max() <= 1e-8
+
+
+def test_loss_gradient_on_the_training_workload():
+    """The training workload itself (1024 configurations of 32-128 atoms,
+    82 106 atoms, level 16), where the oracle is too slow: properties that
+    hold at any size.  (1) The loss of eq. Fitting is a sum over
+    configurations, so the loss and gradient of the batch equal those of its
+    two halves added (this checks the multi-workgroup reduction of dL/dc
+    over the whole batch); (2) the gradient along a random direction d equals
+    the central difference of the loss, (L(theta + h d) - L(theta - h d)) / 2h.
+    Targets are seeded random numbers (no evaluation supplies them)."""
+    from paper_2007_08555_amd import Batch, Potential
+    batch = synth.mixed_batch(seed=4, n_configs=1024, n_min=32, n_max=128, n_species_model=3)
+    K, N = len(batch["n_atoms"]), int(batch["n_atoms"].sum())
+    offs = batch["atom_offsets"]
+    rng = np.random.default_rng(11)
+    E_t = rng.normal(-3.0, 0.5, K) * batch["n_atoms"]
+    F_t = rng.normal(0.0, 1.0, (N, 3))
+    W_t = rng.normal(0.0, 1.0, (K, 3, 3)) * batch["n_atoms"][:, None, None]
+    w = dict(w_e=1.0, w_f=0.01, w_s=0.001, scaling="vibrations", precision="fp64")
+    P = Potential(pot_path("lev16_s3"))
+    log(f"[loss training workload] {K} configurations, {N} atoms")
+    L, g = P.loss_grad(Batch.from_arrays(batch), E_t, F_t, W_t, **w)
+    L, g = L.item(), g.cpu().numpy()
+    # (1) additivity over a split of the configurations
+    h = K // 2
+    parts = []
+    for ks in (range(0, h), range(h, K)):
+        sub = synth._batch([synth.config_of(batch, k) for k in ks])
+        a0, a1 = offs[ks[0]], offs[ks[-1] + 1]
+        Lp, gp = P.loss_grad(Batch.from_arrays(sub), E_t[list(ks)], F_t[a0:a1], W_t[list(ks)], **w)
+        parts.append((Lp.item(), gp.cpu().numpy()))
+    dL = abs(L - parts[0][0] - parts[1][0]) / abs(L)
+    dg = np.abs(g - parts[0][1] - parts[1][1]).max() / np.abs(g).max()
+    log(f"[loss training workload] loss {L:.10e}; halves: loss {dL:.2e}, gradient {dg:.2e} (relative)")
+    assert dL <= 1e-12 and dg <= 1e-10
+    # (2) central difference along a random direction, relative to each entry
+    c0, xi0 = P.get_params()
+    m = len(xi0)
+    d = rng.normal(size=g.shape)
+    d[:m] *= np.abs(xi0)
+    d[m:] *= np.abs(c0.ravel())
+    step = 1e-5
+    vals = []
+    for sgn in (1.0, -1.0):
+        P.set_params(c=(c0.ravel() + sgn * step * d[m:]).reshape(c0.shape), xi=xi0 + sgn * step * d[:m])
+        Ls, _ = P.loss_grad(Batch.from_arrays(batch), E_t, F_t, W_t, **w)
+        vals.append(Ls.item())
+    P.set_params(c=c0, xi=xi0)
+    fd = (vals[0] - vals[1]) / (2 * step)
+    an = float(g @ d)
+    log(f"[loss training workload] directional derivative: gradient {an:.10e}, central difference {fd:.10e}")
+    assert abs(fd - an) <= 1e-6 * abs(an)
