@@ -855,77 +855,88 @@ __global__ void __launch_bounds__(BLOCK) cgrad_p{pidx}_kernel(const mtp::EvalArg
 }}
 """)
         launch.append(f"  hipLaunchKernelGGL((cgrad_p{pidx}_kernel<T>), grid, dim3(BLOCK), smem, s, args, la);")
-    launch.append("  hipLaunchKernelGGL((creduce_kernel<T>), grid, dim3(BLOCK), (size_t)args.n_c * sizeof(double), s, args, la);")
+    launch.append("  hipLaunchKernelGGL((creduce_kernel<T>), grid, dim3(BLOCK), "
+                  "(size_t)(args.n_c + NMU * args.nq * BLOCK) * sizeof(double) + BLOCK * sizeof(int), s, args, la);")
     return "\n".join(src), "\n".join(launch)
 
 
 CREDUCE_TEMPLATE = r"""
 // dL/dc[mu][z_i][z_j][beta] = sum over pairs of species (z_i, z_j) of
 // pa_mu Q_beta(r) + pb_mu dQ_beta/dr: per thread over its pairs for one z_j
-// at a time, then per workgroup in LDS, then per workgroup to cpart.
+// at a time, then per workgroup in a fixed order (for each entry, the
+// threads of that z_i in thread order: bitwise repeatable), then per
+// workgroup to cpart.  LDS: n_c sums, then [NMU * nq][BLOCK] thread values
+// and BLOCK species (creduce_smem).
 template <typename T>
 __global__ void __launch_bounds__(BLOCK) creduce_kernel(const mtp::EvalArgs<T> args, const mtp::LossArgs<T> la) {{
   extern __shared__ __align__(16) unsigned char smem_raw[];
   double* acc_blk = reinterpret_cast<double*>(smem_raw);
+  double* tile = acc_blk + args.n_c;
+  int* zt = reinterpret_cast<int*>(tile + (size_t)NMU * args.nq * BLOCK);
   for (int t = threadIdx.x; t < args.n_c; t += blockDim.x) acc_blk[t] = 0.0;
-  __syncthreads();
   const int i = blockIdx.x * BLOCK + threadIdx.x;
   const int S = args.n_species;
   const int nq = args.nq;
   const size_t n_slots = (size_t)la.K * args.stride;
-  if (i < args.n_atoms) {{
-    const int zi = clamp_species(args.species[i], S);
-    const int cnt = args.nbr_count[i];
-    const T span_inv = T(1) / (args.rcut - args.rmin);
-    for (int zj = 0; zj < S; ++zj) {{
-      T acc[NMU][16];
+  const bool active = i < args.n_atoms;
+  const int zi = active ? clamp_species(args.species[i], S) : -1;
+  const int cnt = active ? args.nbr_count[i] : 0;
+  zt[threadIdx.x] = zi;
+  const T span_inv = T(1) / (args.rcut - args.rmin);
+  for (int zj = 0; zj < S; ++zj) {{
+    T acc[NMU][16];
 #pragma unroll
-      for (int mu = 0; mu < NMU; ++mu)
+    for (int mu = 0; mu < NMU; ++mu)
 #pragma unroll
-        for (int b = 0; b < 16; ++b) acc[mu][b] = T(0);
-      bool any = false;
-      for (int p = 0; p < cnt; ++p) {{
-        const size_t e = (size_t)p * args.stride + i;
-        const mtp::PairRec<T> pq = args.pr[e];
-        if (pq.zj != zj) continue;
-        any = true;
-        const T x = pq.x, y = pq.y, z = pq.z;
-        const T r = sqrt(x * x + y * y + z * z);
-        const T q = (T(2) * r - args.rmin - args.rcut) * span_inv;
-        const T dqdr = T(2) * span_inv;
-        const T sc = args.rcut - r;
-        T pa[NMU], pb[NMU];
+      for (int b = 0; b < 16; ++b) acc[mu][b] = T(0);
+    for (int p = 0; p < cnt; ++p) {{
+      const size_t e = (size_t)p * args.stride + i;
+      const mtp::PairRec<T> pq = args.pr[e];
+      if (pq.zj != zj) continue;
+      const T x = pq.x, y = pq.y, z = pq.z;
+      const T r = sqrt(x * x + y * y + z * z);
+      const T q = (T(2) * r - args.rmin - args.rcut) * span_inv;
+      const T dqdr = T(2) * span_inv;
+      const T sc = args.rcut - r;
+      T pa[NMU], pb[NMU];
 #pragma unroll
-        for (int mu = 0; mu < NMU; ++mu) {{
-          pa[mu] = la.pa[(size_t)mu * n_slots + e];
-          pb[mu] = la.pb[(size_t)mu * n_slots + e];
-        }}
-        T t0 = T(1), t1 = q, d0 = T(0), d1 = T(1);
+      for (int mu = 0; mu < NMU; ++mu) {{
+        pa[mu] = la.pa[(size_t)mu * n_slots + e];
+        pb[mu] = la.pb[(size_t)mu * n_slots + e];
+      }}
+      T t0 = T(1), t1 = q, d0 = T(0), d1 = T(1);
 #pragma unroll
-        for (int b = 0; b < 16; ++b) {{
-          if (b < nq) {{
-            const T tb = b == 0 ? t0 : t1;
-            const T db = b == 0 ? d0 : d1;
-            const T Qb = tb * sc * sc;
-            const T dQb = db * dqdr * sc * sc - T(2) * tb * sc;
+      for (int b = 0; b < 16; ++b) {{
+        if (b < nq) {{
+          const T tb = b == 0 ? t0 : t1;
+          const T db = b == 0 ? d0 : d1;
+          const T Qb = tb * sc * sc;
+          const T dQb = db * dqdr * sc * sc - T(2) * tb * sc;
 #pragma unroll
-            for (int mu = 0; mu < NMU; ++mu) acc[mu][b] += pa[mu] * Qb + pb[mu] * dQb;
-            if (b >= 1) {{
-              const T t2 = T(2) * q * t1 - t0;
-              const T d2 = T(2) * t1 + T(2) * q * d1 - d0;
-              t0 = t1; t1 = t2; d0 = d1; d1 = d2;
-            }}
+          for (int mu = 0; mu < NMU; ++mu) acc[mu][b] += pa[mu] * Qb + pb[mu] * dQb;
+          if (b >= 1) {{
+            const T t2 = T(2) * q * t1 - t0;
+            const T d2 = T(2) * t1 + T(2) * q * d1 - d0;
+            t0 = t1; t1 = t2; d0 = d1; d1 = d2;
           }}
         }}
       }}
-      if (any)
-        for (int mu = 0; mu < NMU; ++mu)
-#pragma unroll
-          for (int b = 0; b < 16; ++b)
-            if (b < nq) atomicAdd(&acc_blk[((mu * S + zi) * S + zj) * nq + b], (double)acc[mu][b]);
     }}
+#pragma unroll
+    for (int mu = 0; mu < NMU; ++mu)
+#pragma unroll
+      for (int b = 0; b < 16; ++b)
+        if (b < nq) tile[(size_t)(mu * nq + b) * BLOCK + threadIdx.x] = (double)acc[mu][b];
+    __syncthreads();
+    for (int t = threadIdx.x; t < NMU * S * nq; t += blockDim.x) {{
+      const int b = t % nq, zz = (t / nq) % S, mu = t / (nq * S);
+      const double* row = tile + (size_t)(mu * nq + b) * BLOCK;
+      double v = 0.0;
+      for (int l = 0; l < BLOCK; ++l) v += zt[l] == zz ? row[l] : 0.0;
+      acc_blk[((mu * S + zz) * S + zj) * nq + b] += v;
+    }}
+    __syncthreads();
   }}
-  __syncthreads();
   for (int t = threadIdx.x; t < args.n_c; t += blockDim.x) la.cpart[(size_t)blockIdx.x * args.n_c + t] = acc_blk[t];
 }}
 """

@@ -74,34 +74,57 @@ __device__ double block_sum(double v) {
   return s;
 }
 
-__global__ void __launch_bounds__(kBlock) loss_total_kernel(int n_cfg, int64_t N, const double* loss_cfg,
-                                                            const double* loss_atom, double* loss) {
+// Two-level sums in a fixed order, spread over the GPU (one workgroup
+// summing a long array waits on its loads one round after another): first
+// kSplit partial sums per output over contiguous chunks, then the partials in
+// chunk order.  kSplit workgroups per output.
+constexpr int kSplit = 32;
+
+// Partial sums of the loss terms: the configuration terms followed by the
+// atom terms, as one array of n_cfg + N values cut into kSplit chunks.
+__global__ void __launch_bounds__(kBlock) loss_part_kernel(int n_cfg, int64_t N, const double* loss_cfg,
+                                                           const double* loss_atom, double* part) {
+  const int64_t total = n_cfg + N;
+  const int64_t chunk = (total + kSplit - 1) / kSplit;
+  const int64_t a0 = blockIdx.x * chunk, a1 = std::min(total, a0 + chunk);
   double v = 0.0;
-  for (int64_t k = threadIdx.x; k < n_cfg; k += blockDim.x) v += loss_cfg[k];
-  for (int64_t i = threadIdx.x; i < N; i += blockDim.x) v += loss_atom[i];
+  for (int64_t t = a0 + threadIdx.x; t < a1; t += blockDim.x) v += t < n_cfg ? loss_cfg[t] : loss_atom[t - n_cfg];
   const double s = block_sum(v);
-  if (threadIdx.x == 0) *loss = s;
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
-// grad_xi[f] = sum over atoms of xi_terms[perm[f]][atom]; one workgroup per f.
+// grad_xi[f] = sum over atoms of xi_terms[perm[f]][atom]: workgroup (f, c)
+// sums chunk c of row f.
 template <typename T>
-__global__ void __launch_bounds__(kBlock) grad_xi_kernel(int64_t N, int stride, const T* xi_terms,
-                                                         const int32_t* perm, double* grad) {
-  const int f = blockIdx.x;
+__global__ void __launch_bounds__(kBlock) grad_xi_part_kernel(int64_t N, int stride, const T* xi_terms,
+                                                              const int32_t* perm, double* part) {
+  const int f = blockIdx.x, c = blockIdx.y;
   const T* row = xi_terms + (size_t)perm[f] * stride;
+  const int64_t chunk = (N + kSplit - 1) / kSplit;
+  const int64_t a0 = c * chunk, a1 = std::min(N, a0 + chunk);
   double v = 0.0;
-  for (int64_t i = threadIdx.x; i < N; i += blockDim.x) v += (double)row[i];
+  for (int64_t i = a0 + threadIdx.x; i < a1; i += blockDim.x) v += (double)row[i];
   const double s = block_sum(v);
-  if (threadIdx.x == 0) grad[f] = s;
+  if (threadIdx.x == 0) part[(size_t)f * kSplit + c] = s;
 }
 
-// grad_c[t] = sum over workgroups of cpart[b][t].
-__global__ void grad_c_kernel(int n_blocks, int n_c, const double* cpart, double* grad) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= n_c) return;
+// out[r] = sum over c of part[r][c] in order, for n rows.
+__global__ void part_sum_kernel(int n, const double* part, double* out) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
   double v = 0.0;
-  for (int b = 0; b < n_blocks; ++b) v += cpart[(size_t)b * n_c + t];
-  grad[t] = v;
+  for (int c = 0; c < kSplit; ++c) v += part[(size_t)r * kSplit + c];
+  out[r] = v;
+}
+
+// grad_c[t] = sum over workgroups b of cpart[b][t], b in order per thread
+// (strided), then a tree over the workgroup: one workgroup per entry t.
+__global__ void __launch_bounds__(kBlock) grad_c_kernel(int n_blocks, int n_c, const double* cpart, double* grad) {
+  const int t = blockIdx.x;
+  double v = 0.0;
+  for (int b = threadIdx.x; b < n_blocks; b += blockDim.x) v += cpart[(size_t)b * n_c + t];
+  const double s = block_sum(v);
+  if (threadIdx.x == 0) grad[t] = s;
 }
 
 // Rows of the nonlinear grade (section 2.3): dE_k/dtheta of every
@@ -188,17 +211,19 @@ hipError_t loss_residuals(LossResidualArgs& r, int fp64, void* a_atom, void* u, 
 
 hipError_t loss_finish(int fp64, int n_cfg, int64_t N, int stride, int m, int n_c, int n_blocks,
                        const double* loss_cfg, const double* loss_atom, const void* xi_terms, const int32_t* perm,
-                       const double* cpart, double* loss, double* grad, hipStream_t s) {
-  hipLaunchKernelGGL(loss_total_kernel, dim3(1), dim3(kBlock), 0, s, n_cfg, N, loss_cfg, loss_atom, loss);
+                       const double* cpart, double* part, double* loss, double* grad, hipStream_t s) {
+  double* part_xi = part + kSplit;
+  hipLaunchKernelGGL(loss_part_kernel, dim3(kSplit), dim3(kBlock), 0, s, n_cfg, N, loss_cfg, loss_atom, part);
+  hipLaunchKernelGGL(part_sum_kernel, dim3(1), dim3(64), 0, s, 1, part, loss);
   if (N > 0) {
     if (fp64)
-      hipLaunchKernelGGL(grad_xi_kernel<double>, dim3(m), dim3(kBlock), 0, s, N, stride, (const double*)xi_terms,
-                         perm, grad);
+      hipLaunchKernelGGL(grad_xi_part_kernel<double>, dim3(m, kSplit), dim3(kBlock), 0, s, N, stride,
+                         (const double*)xi_terms, perm, part_xi);
     else
-      hipLaunchKernelGGL(grad_xi_kernel<float>, dim3(m), dim3(kBlock), 0, s, N, stride, (const float*)xi_terms,
-                         perm, grad);
-    hipLaunchKernelGGL(grad_c_kernel, dim3((n_c + kBlock - 1) / kBlock), dim3(kBlock), 0, s, n_blocks, n_c, cpart,
-                       grad + m);
+      hipLaunchKernelGGL(grad_xi_part_kernel<float>, dim3(m, kSplit), dim3(kBlock), 0, s, N, stride,
+                         (const float*)xi_terms, perm, part_xi);
+    hipLaunchKernelGGL(part_sum_kernel, dim3((m + 63) / 64), dim3(64), 0, s, m, part_xi, grad);
+    hipLaunchKernelGGL(grad_c_kernel, dim3(n_c), dim3(kBlock), 0, s, n_blocks, n_c, cpart, grad + m);
   } else {
     hipError_t e = hipMemsetAsync(grad, 0, sizeof(double) * (m + n_c), s);
     if (e != hipSuccess) return e;
@@ -206,6 +231,7 @@ hipError_t loss_finish(int fp64, int n_cfg, int64_t N, int stride, int m, int n_
   return hipGetLastError();
 }
 
+int loss_finish_scratch_doubles(int m) { return kSplit * (1 + m); }
 
 hipError_t theta_rows_prepare(int fp64, int64_t N, int stride, void* a_atom, void* u, void* eps_atom, hipStream_t s) {
   const int64_t n_eps = 9 * (int64_t)stride;

@@ -123,7 +123,7 @@ struct mtp_model {
   Buffer b_tmp, c_tmp;
   int last_stride = 0;
   // loss gradient
-  Buffer lo_E, lo_F, lo_W, lo_a, lo_u, lo_eps, lo_dM, lo_dG, lo_xit, lo_pa, lo_pb, lo_cpart, lo_gd;
+  Buffer lo_E, lo_F, lo_W, lo_a, lo_u, lo_eps, lo_dM, lo_dG, lo_xit, lo_pa, lo_pb, lo_cpart, lo_gd, lo_part;
   Buffer lo_acfg, lo_wfcfg, lo_epscfg, lo_losscfg, lo_lossatom;
   // normal equations
   Buffer fit_J, fit_w, fit_P, fit_eye, fit_D, fit_W2, fit_inv, fit_flag;
@@ -1110,8 +1110,10 @@ int mtp_loss_grad(mtp_model* M, const mtp_batch* bt, const double* E_t, const do
   };
   rc = fp64 ? fill((double*)nullptr) : fill((float*)nullptr);
   if (rc != MTP_OK) return rc;
+  HIP_TRY(M->lo_part.ensure(sizeof(double) * (size_t)mtp::loss_finish_scratch_doubles(M->m)), "hipMalloc");
   HIP_TRY(mtp::loss_finish(fp64, K_cfg, N, stride, M->m, M->n_c, n_blocks, r.loss_cfg, r.loss_atom, M->lo_xit.p,
-                           M->perm_dev.as<int32_t>(), M->lo_cpart.as<double>(), loss_dev, grad_dev, s),
+                           M->perm_dev.as<int32_t>(), M->lo_cpart.as<double>(), M->lo_part.as<double>(), loss_dev,
+                           grad_dev, s),
           "loss reductions");
   return MTP_OK;
 }

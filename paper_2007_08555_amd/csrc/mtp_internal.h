@@ -161,9 +161,13 @@ hipError_t theta_rows_finish(int fp64, const ThetaRowArgs& a, const void* pr, co
                              const double* b, hipStream_t s);
 
 hipError_t loss_residuals(LossResidualArgs& r, int fp64, void* a_atom, void* u, void* eps_atom, hipStream_t s);
+// Loss and gradient from the per-configuration and per-atom loss terms, the
+// per-atom xi terms and the per-workgroup c partials, all sums in a fixed
+// order; part: loss_finish_scratch_doubles(m) doubles of device scratch.
 hipError_t loss_finish(int fp64, int n_cfg, int64_t N, int stride, int m, int n_c, int n_blocks,
                        const double* loss_cfg, const double* loss_atom, const void* xi_terms, const int32_t* perm,
-                       const double* cpart, double* loss, double* grad, hipStream_t s);
+                       const double* cpart, double* part, double* loss, double* grad, hipStream_t s);
+int loss_finish_scratch_doubles(int m);
 
 // MaxVol selection (section 2.3): the largest |C_ij| and where it is.
 struct MaxvolPick {

@@ -133,3 +133,21 @@ def test_loss_gradient_on_the_training_workload():
     an = float(g @ d)
     log(f"[loss training workload] directional derivative: gradient {an:.10e}, central difference {fd:.10e}")
     assert abs(fd - an) <= 1e-6 * abs(an)
+
+
+def test_loss_gradient_is_bitwise_repeatable():
+    """Every sum of the loss path runs in a fixed order (no floating-point
+    atomics): two calls on the same inputs agree bit for bit."""
+    from paper_2007_08555_amd import Batch, Potential
+    batch = synth.mixed_batch(seed=30, n_configs=64, n_min=32, n_max=128, n_species_model=3)
+    K, N = len(batch["n_atoms"]), int(batch["n_atoms"].sum())
+    rng = np.random.default_rng(12)
+    E_t = rng.normal(-3.0, 0.5, K) * batch["n_atoms"]
+    F_t = rng.normal(0.0, 1.0, (N, 3))
+    W_t = rng.normal(0.0, 1.0, (K, 3, 3))
+    P = Potential(pot_path("lev16_s3"))
+    B = Batch.from_arrays(batch)
+    runs = [P.loss_grad(B, E_t, F_t, W_t, precision="fp64") for _ in range(3)]
+    for L, g in runs[1:]:
+        assert L.item() == runs[0][0].item()
+        assert np.array_equal(g.cpu().numpy(), runs[0][1].cpu().numpy())
