@@ -47,17 +47,17 @@ KERNEL_SRC = os.path.join(ROOT, "paper_2007_08555_amd", "csrc", "generated", "ge
 def measured_traffic(schedule):
     """HBM bytes per launch of the evaluation kernels of one FP64 schedule
     from the committed FETCH_SIZE / WRITE_SIZE summary, when it was taken on
-    the kernels built here (same generated source); else None."""
-    import hashlib
+    the kernels built here (same FP64 evaluation part of the generated
+    source); else None."""
+    from paper_2007_08555_amd.prof import eval_part_digest
     try:
         fields = dict(line.split(": ", 1) for line in open(TRAFFIC_MD.format(schedule)).read().splitlines()
                       if ": " in line
-                      and line.split(": ", 1)[0] in ("traffic_bytes_per_launch", "kernel_source_sha256"))
-        with open(KERNEL_SRC, "rb") as fh:
-            digest = hashlib.sha256(fh.read()).hexdigest()
+                      and line.split(": ", 1)[0] in ("traffic_bytes_per_launch", "kernel_part_sha256"))
+        digest = eval_part_digest(KERNEL_SRC)
     except OSError:
         return None
-    if fields.get("kernel_source_sha256", "").strip() != digest:
+    if fields.get("kernel_part_sha256", "").strip() != digest:
         return None
     return float(fields["traffic_bytes_per_launch"])
 

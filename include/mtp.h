@@ -386,7 +386,8 @@ typedef struct {
   float ms_neighbours;      /* device time of the neighbour search (-1 when timing is off) */
   float ms_eval;            /* evaluation kernels (moments, contractions, adjoint) */
   float ms_forces;          /* force gather */
-  float ms_reduce;          /* per-configuration sums */
+  float ms_reduce;          /* per-configuration sums: they run on a second stream beside
+                               the gather, so this is the time they add after it */
   int32_t lists_reused;     /* 1 if the last mtp_eval refreshed the lists of an earlier call (skin) */
   int32_t list_builds;      /* neighbour-list builds since the skin was last set */
 } mtp_stats;

@@ -133,9 +133,16 @@ struct mtp_model {
   bool timing = false, timed = false;
   hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
   hipStream_t last_stream = nullptr;
+  // the per-configuration sums run beside the force gather: a second stream
+  // forked from and joined back to the caller's stream by two events
+  hipStream_t side = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
   ~mtp_model() {
     for (auto& e : ev)
       if (e) (void)hipEventDestroy(e);
+    if (fork) (void)hipEventDestroy(fork);
+    if (join) (void)hipEventDestroy(join);
+    if (side) (void)hipStreamDestroy(side);
   }
 };
 
@@ -501,15 +508,22 @@ int run_eval(mtp_model* M, const mtp_batch* bt, const mtp_out* out, int precisio
       }
     }
     HIP_TRY(mark(2), "hipEventRecord");
+    // per-configuration sums (site energies, per-atom virials, B) on the
+    // side stream while the force gather runs here: the gather waits on
+    // scattered loads, the sums stream B; both need only the evaluation
+    HIP_TRY(hipEventRecord(M->fork, s), "hipEventRecord");
+    HIP_TRY(hipStreamWaitEvent(M->side, M->fork, 0), "hipStreamWaitEvent");
+    HIP_TRY(reduce_configs(fp64, n_cfg, M->cfg.as<CfgInfo>(), stride, M->site.p, out->virial ? M->wv.p : nullptr,
+                           want_b ? M->B.p : nullptr, M->m, stride, M->perm_dev.as<int32_t>(), out->energy,
+                           out->virial, out->b, out->site_energy, M->side),
+            "reductions");
+    HIP_TRY(hipEventRecord(M->join, M->side), "hipEventRecord");
     // the per-atom virials were summed by the last adjoint pass
     HIP_TRY(gather_forces(fp64, N, stride, M->count.as<int32_t>(), M->rev.as<int32_t>(), M->gpair.p,
                           M->own.as<double>(), out->forces, s),
             "force gather");
     HIP_TRY(mark(3), "hipEventRecord");
-    HIP_TRY(reduce_configs(fp64, n_cfg, M->cfg.as<CfgInfo>(), stride, M->site.p, out->virial ? M->wv.p : nullptr,
-                           want_b ? M->B.p : nullptr, M->m, stride, M->perm_dev.as<int32_t>(), out->energy,
-                           out->virial, out->b, out->site_energy, s),
-            "reductions");
+    HIP_TRY(hipStreamWaitEvent(s, M->join, 0), "hipStreamWaitEvent");
     HIP_TRY(mark(4), "hipEventRecord");
     if (async) return MTP_OK;  // the caller reads the status later (mtp_status)
     Status st{};
@@ -574,6 +588,12 @@ int mtp_load(const char* path, int device, mtp_model** out) {
     double* scratch = nullptr;
     const hipError_t e = mtp::grade_scratch_address(device, &scratch);
     if (e != hipSuccess) rc = hip_fail(e, "hipGetSymbolAddress");
+  }
+  if (rc == MTP_OK) {
+    hipError_t e = hipStreamCreateWithFlags(&M->side, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&M->fork, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&M->join, hipEventDisableTiming);
+    if (e != hipSuccess) rc = hip_fail(e, "side stream");
   }
   if (rc != MTP_OK) {
     delete M;

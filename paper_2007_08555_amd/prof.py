@@ -13,8 +13,9 @@ the one with the largest WRITE_SIZE, and each counter is scaled by
 (CALIB_MIB MiB) / (what it read for that copy).  Kernels whose names match
 KERNEL_REGEX are summed per dispatch round (one launch of each per step).
 The summary ends with two lines that bench.py reads:
-`traffic_bytes_per_launch: <bytes>` and `kernel_source_sha256: <hash of
-SOURCE_FILE>` (the counters only describe the kernels built from that file).
+`traffic_bytes_per_launch: <bytes>` and `kernel_part_sha256: <hash of the
+FP64 evaluation part of SOURCE_FILE>` (the lines that part 1 of the build
+compiles: the counters only describe the kernels built from them).
 """
 import collections
 import csv
@@ -57,6 +58,14 @@ def _per_kernel(path, counter):
     return d, rows
 
 
+def eval_part_digest(source_file):
+    """SHA-256 of the lines of a generated kernel file that the FP64
+    evaluation part of the build compiles."""
+    from .build import _part_text
+    with open(source_file, "rb") as fh:
+        return hashlib.sha256(_part_text(fh.read(), 1)).hexdigest()
+
+
 def traffic(fetch_csv, write_csv, out, cmd_fetch, cmd_write, title, calib_mib, kernel_regex, source_file):
     calib = float(calib_mib) * 2 ** 20
     fetch, frows = _per_kernel(fetch_csv, "FETCH_SIZE")
@@ -87,9 +96,7 @@ def traffic(fetch_csv, write_csv, out, cmd_fetch, cmd_write, title, calib_mib, k
         lines.append(f"| `{_short(n)[:90]}` | {len(fr)} | {r_b / 1e6:.1f} | {w_b / 1e6:.1f} |")
     lines += ["", f"Sum over the matched kernels (one launch each per step): read {tot_r / 1e9:.3f} GB, "
               f"written {tot_w / 1e9:.3f} GB.", ""]
-    with open(source_file, "rb") as fh:
-        digest = hashlib.sha256(fh.read()).hexdigest()
-    lines += [f"traffic_bytes_per_launch: {tot_r + tot_w:.6e}", f"kernel_source_sha256: {digest}"]
+    lines += [f"traffic_bytes_per_launch: {tot_r + tot_w:.6e}", f"kernel_part_sha256: {eval_part_digest(source_file)}"]
     open(out, "w").write("\n".join(lines) + "\n")
 
 
