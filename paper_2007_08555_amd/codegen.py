@@ -855,33 +855,36 @@ __global__ void __launch_bounds__(BLOCK) cgrad_p{pidx}_kernel(const mtp::EvalArg
 }}
 """)
         launch.append(f"  hipLaunchKernelGGL((cgrad_p{pidx}_kernel<T>), grid, dim3(BLOCK), smem, s, args, la);")
-    launch.append("  hipLaunchKernelGGL((creduce_kernel<T>), grid, dim3(BLOCK), "
-                  "(size_t)(args.n_c + NMU * args.nq * BLOCK) * sizeof(double) + BLOCK * sizeof(int), s, args, la);")
+    launch.append("  hipLaunchKernelGGL((creduce_kernel<T>), grid, dim3(BLOCK * kCredSplit), "
+                  "creduce_smem(args.n_c, args.nq), s, args, la);")
     return "\n".join(src), "\n".join(launch)
 
 
 CREDUCE_TEMPLATE = r"""
 // dL/dc[mu][z_i][z_j][beta] = sum over pairs of species (z_i, z_j) of
-// pa_mu Q_beta(r) + pb_mu dQ_beta/dr: per thread over its pairs for one z_j
-// at a time, then per workgroup in a fixed order (for each entry, the
-// threads of that z_i in thread order: bitwise repeatable), then per
-// workgroup to cpart.  LDS: n_c sums, then [NMU * nq][BLOCK] thread values
-// and BLOCK species (creduce_smem).
+// pa_mu Q_beta(r) + pb_mu dQ_beta/dr.  Four lanes per atom, each over every
+// fourth pair in order, for one z_j at a time; the four partial sums are
+// combined by DPP quad moves, then per workgroup in a fixed order (for each
+// entry, the atoms of that z_i in atom order: bitwise repeatable), then per
+// workgroup (BLOCK atoms) to cpart.  LDS: creduce_smem.
+constexpr int kCredSplit = 4;
 template <typename T>
-__global__ void __launch_bounds__(BLOCK) creduce_kernel(const mtp::EvalArgs<T> args, const mtp::LossArgs<T> la) {{
+__global__ void __launch_bounds__(BLOCK * kCredSplit) creduce_kernel(const mtp::EvalArgs<T> args,
+                                                                     const mtp::LossArgs<T> la) {{
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  double* acc_blk = reinterpret_cast<double*>(smem_raw);
-  double* tile = acc_blk + args.n_c;
-  int* zt = reinterpret_cast<int*>(tile + (size_t)NMU * args.nq * BLOCK);
-  for (int t = threadIdx.x; t < args.n_c; t += blockDim.x) acc_blk[t] = 0.0;
-  const int i = blockIdx.x * BLOCK + threadIdx.x;
   const int S = args.n_species;
   const int nq = args.nq;
+  double* acc_blk = reinterpret_cast<double*>(smem_raw);
+  double* tile = acc_blk + args.n_c;
+  int* zt = reinterpret_cast<int*>(tile + (size_t)NMU * nq * BLOCK);
+  for (int t = threadIdx.x; t < args.n_c; t += blockDim.x) acc_blk[t] = 0.0;
+  const int a = threadIdx.x / kCredSplit, h = threadIdx.x % kCredSplit;
+  const int i = blockIdx.x * BLOCK + a;
   const size_t n_slots = (size_t)la.K * args.stride;
   const bool active = i < args.n_atoms;
   const int zi = active ? clamp_species(args.species[i], S) : -1;
   const int cnt = active ? args.nbr_count[i] : 0;
-  zt[threadIdx.x] = zi;
+  if (h == 0) zt[a] = zi;
   const T span_inv = T(1) / (args.rcut - args.rmin);
   for (int zj = 0; zj < S; ++zj) {{
     T acc[NMU][16];
@@ -889,7 +892,7 @@ __global__ void __launch_bounds__(BLOCK) creduce_kernel(const mtp::EvalArgs<T> a
     for (int mu = 0; mu < NMU; ++mu)
 #pragma unroll
       for (int b = 0; b < 16; ++b) acc[mu][b] = T(0);
-    for (int p = 0; p < cnt; ++p) {{
+    for (int p = h; p < cnt; p += kCredSplit) {{
       const size_t e = (size_t)p * args.stride + i;
       const mtp::PairRec<T> pq = args.pr[e];
       if (pq.zj != zj) continue;
@@ -926,7 +929,10 @@ __global__ void __launch_bounds__(BLOCK) creduce_kernel(const mtp::EvalArgs<T> a
     for (int mu = 0; mu < NMU; ++mu)
 #pragma unroll
       for (int b = 0; b < 16; ++b)
-        if (b < nq) tile[(size_t)(mu * nq + b) * BLOCK + threadIdx.x] = (double)acc[mu][b];
+        if (b < nq) {{
+          const double v = mtp::group_sum<kCredSplit>((double)acc[mu][b]);
+          if (h == 0) tile[(size_t)(mu * nq + b) * BLOCK + a] = v;
+        }}
     __syncthreads();
     for (int t = threadIdx.x; t < NMU * S * nq; t += blockDim.x) {{
       const int b = t % nq, zz = (t / nq) % S, mu = t / (nq * S);
@@ -938,6 +944,11 @@ __global__ void __launch_bounds__(BLOCK) creduce_kernel(const mtp::EvalArgs<T> a
     __syncthreads();
   }}
   for (int t = threadIdx.x; t < args.n_c; t += blockDim.x) la.cpart[(size_t)blockIdx.x * args.n_c + t] = acc_blk[t];
+}}
+
+// LDS bytes of creduce_kernel
+inline size_t creduce_smem(int n_c, int nq) {{
+  return (size_t)(n_c + NMU * nq * BLOCK) * sizeof(double) + BLOCK * sizeof(int);
 }}
 """
 
