@@ -27,7 +27,8 @@ def test_traffic_is_calibrated_by_the_copy(tmp_path):
     _write(tmp_path / "f.csv", "FETCH_SIZE", fetch)
     _write(tmp_path / "w.csv", "WRITE_SIZE", write)
     src = tmp_path / "k.hip"
-    src.write_text("kernel source")
+    # the hash covers the lines that the FP64 evaluation part compiles
+    src.write_text("common\n#if MTP_PART == 3\nloss only\n#endif\n#if MTP_PART == 1 || MTP_PART == 2\neval\n#endif\n")
     out = tmp_path / "t.md"
     prof.traffic(str(tmp_path / "f.csv"), str(tmp_path / "w.csv"), str(out), "cmd f", "cmd w", "title", "1",
                  r"lev16::(moments|adjoint)", str(src))
@@ -35,4 +36,4 @@ def test_traffic_is_calibrated_by_the_copy(tmp_path):
     # per launch: moments read 100*2, written 20 (mean); adjoint read 60*2, written 20 (KiB)
     expect = (200 + 20 + 120 + 20) * 1024
     assert abs(float(fields["traffic_bytes_per_launch"]) - expect) <= 1e-6 * expect
-    assert fields["kernel_source_sha256"] == hashlib.sha256(b"kernel source").hexdigest()
+    assert fields["kernel_part_sha256"] == hashlib.sha256(b"common\neval\n").hexdigest()
