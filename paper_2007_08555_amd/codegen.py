@@ -498,6 +498,35 @@ def emit_pair_backward(s, nus=None, gmap=None, nmu=None):
     return out, ops
 
 
+def _nu_bits(nus):
+    return sum(1 << n for n in nus)
+
+
+def _adjoint_launches(tags_nus, split):
+    """Launch lines of the adjoint passes [(tag, degrees)]: a preamble that
+    finds the last pass the caller needs (nu_need, a bit mask of degrees: the
+    later passes would only add zeros) and the degrees nu_run of the passes
+    that run, then the launches, the last one that runs as the final pass
+    (it sums the per-atom virial and own force)."""
+    n = len(tags_nus)
+    pre = [f"constexpr unsigned kAdjNu[{n}] = {{ {', '.join(f'{_nu_bits(nus)}u' for _, nus in tags_nus)} }};",
+           f"int last_adj = {n - 1};",
+           "while (last_adj > 0 && !(nu_need & kAdjNu[last_adj])) --last_adj;",
+           "unsigned nu_run = 0;",
+           "for (int k = 0; k <= last_adj; ++k) nu_run |= kAdjNu[k];",
+           "(void)nu_run;"]
+    grid = _grid(split)
+    adj = []
+    for k, (tag, _) in enumerate(tags_nus):
+        first = "true" if k == 0 else "false"
+        adj.append(f"if (last_adj == {k}) hipLaunchKernelGGL((adjoint_{tag}_kernel<T, {first}, true, NQ>), "
+                   f"{grid}, dim3(BLOCK), smem, s, args);")
+        if k < n - 1:
+            adj.append(f"else if (last_adj > {k}) hipLaunchKernelGGL((adjoint_{tag}_kernel<T, {first}, false, NQ>), "
+                       f"{grid}, dim3(BLOCK), smem, s, args);")
+    return pre, adj
+
+
 def _grid(split):
     """Launch grid of a per-pair pass with `split` threads per atom."""
     return "grid" if split == 1 else f"dim3((args.n_atoms * {split} + BLOCK - 1) / BLOCK)"
@@ -1017,6 +1046,8 @@ hipError_t launch_t(const void* a, unsigned flags, int schedule, hipStream_t s) 
   const bool reuse_moments = (flags & mtp::kEvalReuseMoments) != 0;
   const bool store_moments = (flags & mtp::kEvalStoreMoments) != 0;
   const bool moments_only = (flags & mtp::kEvalMomentsOnly) != 0;
+  // degrees whose adjoint the caller needs (all unless kEvalNuMask)
+  const unsigned nu_need = (flags & mtp::kEvalNuMask) ? (flags >> mtp::kEvalNuShift) : ~0u;
   (void)store_moments;
   (void)moments_only;
   if (args.n_atoms <= 0) return hipSuccess;
@@ -1162,15 +1193,13 @@ def generate(lev_max, block=64):
                 kern_src[prec].append(ADJOINT_TEMPLATE.format(split=sch.get("split", 1), pidx=pidx, nus=nus, tag=ptag, ncomp=len(comps), nmu=nmu,
                                                               comp_list=", ".join(map(str, comps)),
                                                               body="\n".join(" " * 4 + l for l in body)))
-                first = "true" if pidx == 0 else "false"
-                last = "true" if pidx == len(passes) - 1 else "false"
-                adj_lines.append(f"hipLaunchKernelGGL((adjoint_{ptag}_kernel<T, {first}, {last}, NQ>), "
-                                 f"{_grid(sch.get('split', 1))}, dim3(BLOCK), smem, s, args);")
+            pre, adj_lines = _adjoint_launches([(f"{prec}s{sidx}_p{pidx}", nus) for pidx, (nus, _) in enumerate(passes)],
+                                               sch.get("split", 1))
             # the reread of stored moments (normal equations) runs the
             # contraction of schedule 0 from them
-            rev0 = [l for l in sched_launch[(prec, 0)] if l.startswith("hipLaunchKernelGGL((contract_rev_")]
-            body = (["if (moments_only) return hipErrorInvalidValue;   // the moments stay in registers",
-                     "if (reuse_moments) {",
+            rev0 = [l for l in sched_launch[(prec, 0)] if "hipLaunchKernelGGL((contract_rev_" in l]
+            body = (["if (moments_only) return hipErrorInvalidValue;   // the moments stay in registers"] + pre +
+                    ["if (reuse_moments) {",
                      "  hipLaunchKernelGGL((contract_fwd_kernel<T, WANT_B>), grid, dim3(BLOCK), 0, s, args);"] +
                     ["  " + l for l in rev0] +
                     ["} else if (store_moments) {",
@@ -1213,7 +1242,8 @@ def generate(lev_max, block=64):
                 load_dg="\n".join(f"  const T dg{g} = args.D[(size_t){g} * args.stride + i];" for g in g_used),
                 fence=" ".join(f'asm volatile("" : "+v"(M[{q}]));' for q in m_used),
                 body="\n".join("  " + l for l in body)))
-            rev_lines.append(f"hipLaunchKernelGGL((contract_rev_{tag}_kernel<T>), grid, dim3(BLOCK), 0, s, args);")
+            rev_lines.append(f"if (nu_run & {_nu_bits(grp)}u) "
+                             f"hipLaunchKernelGGL((contract_rev_{tag}_kernel<T>), grid, dim3(BLOCK), 0, s, args);")
         # adjoint passes
         passes = adjoint_passes(s, sch["adj"])
         for pidx, (nus, comps) in enumerate(passes):
@@ -1227,13 +1257,11 @@ def generate(lev_max, block=64):
             kern_src[prec].append(ADJOINT_TEMPLATE.format(split=sch.get("split", 1), pidx=pidx, nus=nus, tag=tag, ncomp=len(comps), nmu=nmu,
                                                     comp_list=", ".join(map(str, comps)),
                                                     body="\n".join(" " * 4 + l for l in body)))
-            first = "true" if pidx == 0 else "false"
-            last = "true" if pidx == len(passes) - 1 else "false"
-            adj_lines.append(f"hipLaunchKernelGGL((adjoint_{tag}_kernel<T, {first}, {last}, NQ>), "
-                             f"{_grid(sch.get('split', 1))}, dim3(BLOCK), smem, s, args);")
+        pre, adj_lines = _adjoint_launches([(f"{prec}s{sidx}_p{pidx}", nus) for pidx, (nus, _) in enumerate(passes)],
+                                           sch.get("split", 1))
         body = (["if (!reuse_moments) {"] + ["  " + l for l in mom_lines] + ["}"] +
-                ["if (moments_only) return hipGetLastError();",
-                 "hipLaunchKernelGGL((contract_fwd_kernel<T, WANT_B>), grid, dim3(BLOCK), 0, s, args);"] +
+                ["if (moments_only) return hipGetLastError();"] + pre +
+                ["hipLaunchKernelGGL((contract_fwd_kernel<T, WANT_B>), grid, dim3(BLOCK), 0, s, args);"] +
                 rev_lines + adj_lines)
         sched_launch[(prec, sidx)] = body
     # loss path: the contraction on dual numbers, split into graph passes,
@@ -1463,6 +1491,8 @@ hipError_t launch_t(const void* a, unsigned flags, int schedule, hipStream_t s) 
   const auto& args = *static_cast<const mtp::EvalArgs<T>*>(a);
   const bool reuse_moments = (flags & mtp::kEvalReuseMoments) != 0;   // the moments always go through memory
   const bool moments_only = (flags & mtp::kEvalMomentsOnly) != 0;
+  // degrees whose adjoint the caller needs (all unless kEvalNuMask)
+  const unsigned nu_need = (flags & mtp::kEvalNuMask) ? (flags >> mtp::kEvalNuShift) : ~0u;
   if (schedule != 0) return hipErrorInvalidValue;
   if (args.n_atoms <= 0) return hipSuccess;
   const dim3 grid((args.n_atoms + BLOCK - 1) / BLOCK);
@@ -1591,11 +1621,9 @@ def _pair_pass_kernels(s, prec, sidx, sch):
         src.append(ADJOINT_TEMPLATE.format(split=sch.get("split", 1), pidx=pidx, nus=nus, tag=tag, ncomp=len(comps), nmu=nmu,
                                            comp_list=", ".join(map(str, comps)),
                                            body="\n".join(" " * 4 + l for l in body)))
-        first = "true" if pidx == 0 else "false"
-        last = "true" if pidx == len(passes) - 1 else "false"
-        adj_lines.append(f"hipLaunchKernelGGL((adjoint_{tag}_kernel<T, {first}, {last}, NQ>), "
-                         f"{_grid(sch.get('split', 1))}, dim3(BLOCK), smem, s, args);")
-    return src, mom_lines, adj_lines
+    pre, adj = _adjoint_launches([(f"{prec}s{sidx}_p{pidx}", nus) for pidx, (nus, _) in enumerate(passes)],
+                                 sch.get("split", 1))
+    return src, mom_lines, pre + adj
 
 
 def generate_table(lev_max):

@@ -76,23 +76,36 @@ __device__ T trie_reverse(int a, int b, T P, const MLoad& mload, const GAdd& gad
 }
 
 // Graph values of every graph with D vertices (roots listed per depth).
-template <typename T, int D, typename Tab, typename MLoad, typename VStore>
-__device__ __forceinline__ void graphs_forward(const MLoad& mload, const VStore& vstore) {
+// Graph values of every graph with D vertices (roots listed per depth) for
+// which need(g) holds.
+template <typename T, int D, typename Tab, typename MLoad, typename VStore, typename Need>
+__device__ __forceinline__ void graphs_forward(const MLoad& mload, const VStore& vstore, const Need& need) {
   if constexpr (D <= Tab::kDepth) {
     for (int r = Tab::root_begin(D); r < Tab::root_begin(D + 1); ++r) {
       const int4 e = Tab::roots()[r];
-      vstore(e.x, trie_value<T, 1, D, Tab>(e.y, e.z, mload));
+      if (need(e.x)) vstore(e.x, trie_value<T, 1, D, Tab>(e.y, e.z, mload));
     }
-    graphs_forward<T, D + 1, Tab>(mload, vstore);
+    graphs_forward<T, D + 1, Tab>(mload, vstore, need);
   }
 }
 
+template <typename T, int D, typename Tab, typename MLoad, typename VStore>
+__device__ __forceinline__ void graphs_forward(const MLoad& mload, const VStore& vstore) {
+  graphs_forward<T, D, Tab>(mload, vstore, [](int) { return true; });
+}
+
+// A graph whose dV/dg is exactly zero adds nothing and is skipped (for
+// xi = e_alpha, as in the normal equations, all but alpha's graphs).
 template <typename T, int D, typename Tab, typename MLoad, typename DgLoad, typename GAdd>
 __device__ __forceinline__ void graphs_reverse(const MLoad& mload, const DgLoad& dgload, const GAdd& gadd) {
   if constexpr (D <= Tab::kDepth) {
     for (int r = Tab::root_begin(D); r < Tab::root_begin(D + 1); ++r) {
       const int4 e = Tab::roots()[r];
-      (void)trie_reverse<T, 1, D, Tab>(e.y, e.z, dgload(e.x), mload, gadd);
+      const T P = dgload(e.x);
+      if constexpr (std::is_floating_point<T>::value) {
+        if (P == T(0)) continue;
+      }
+      (void)trie_reverse<T, 1, D, Tab>(e.y, e.z, P, mload, gadd);
     }
     graphs_reverse<T, D + 1, Tab>(mload, dgload, gadd);
   }
@@ -102,13 +115,17 @@ __device__ __forceinline__ void graphs_reverse(const MLoad& mload, const DgLoad&
 // its generalisation), V = sum_alpha xi_alpha B_alpha, and dV/dg added to
 // the graphs' adjoints: for each function, prefix products times suffix
 // products give the product of the other factors.  bout(alpha, B) receives
-// every B.
-template <typename T, typename Tab, typename XiLoad, typename VLoad, typename DgAdd, typename BOut>
+// every B when ALL_B; otherwise functions with xi_alpha exactly zero, which
+// add nothing, are skipped.
+template <typename T, typename Tab, bool ALL_B, typename XiLoad, typename VLoad, typename DgAdd, typename BOut>
 __device__ __forceinline__ T basis_products(const XiLoad& xiload, const VLoad& vload, const DgAdd& dgadd,
                                             const BOut& bout) {
   constexpr int Q = Tab::kMaxFactors;
   T V = T(0);
   for (int a = 0; a < Tab::kM; ++a) {
+    if constexpr (!ALL_B && std::is_floating_point<T>::value) {
+      if (xiload(a) == T(0)) continue;
+    }
     const int f0 = Tab::func_off()[a];
     const int q = Tab::func_off()[a + 1] - f0;
     int g[Q];
@@ -143,6 +160,28 @@ __device__ __forceinline__ T basis_products(const XiLoad& xiload, const VLoad& v
 // and widened.
 template <typename T, bool WANT_B, typename Tab, bool M32 = false>
 __global__ void __launch_bounds__(64) contract_table_kernel(const EvalArgs<T> args) {
+  // graphs that some function with xi_alpha != 0 uses (a bit per graph),
+  // and whether that is all of them
+  __shared__ uint32_t need[(Tab::kGraphs + 31) / 32];
+  __shared__ int n_zero;
+  if constexpr (!WANT_B) {
+    for (int w = threadIdx.x; w < (Tab::kGraphs + 31) / 32; w += 64) need[w] = 0u;
+    if (threadIdx.x == 0) n_zero = 0;
+    __syncthreads();
+    for (int a = threadIdx.x; a < Tab::kM; a += 64)
+      if (args.xi[a] == T(0)) atomicAdd(&n_zero, 1);
+    __syncthreads();
+    if (n_zero > 0) {   // uniform over the workgroup
+      for (int a = threadIdx.x; a < Tab::kM; a += 64)
+        if (args.xi[a] != T(0))
+          for (int t = Tab::func_off()[a]; t < Tab::func_off()[a + 1]; ++t) {
+            const int g = Tab::func_fac()[t];
+            atomicOr(&need[g >> 5], 1u << (g & 31));
+          }
+      __syncthreads();
+    }
+  }
+  const bool need_all = WANT_B || n_zero == 0;
   const int i = blockIdx.x * 64 + threadIdx.x;
   if (i >= args.n_atoms) return;
   const size_t st = args.stride;
@@ -157,9 +196,17 @@ __global__ void __launch_bounds__(64) contract_table_kernel(const EvalArgs<T> ar
     else
       return Mi[(size_t)k * st];
   };
-  graphs_forward<T, 1, Tab>(mload, [&](int g, T v) { Dv[(size_t)g * st] = v; });
+  if constexpr (WANT_B) {
+    graphs_forward<T, 1, Tab>(mload, [&](int g, T v) { Dv[(size_t)g * st] = v; });
+  } else {
+    // only the graphs of functions with xi_alpha != 0 (the others' values
+    // are never read): for xi = e_alpha, as in the normal equations, alpha's
+    const bool all = need_all;
+    graphs_forward<T, 1, Tab>(mload, [&](int g, T v) { Dv[(size_t)g * st] = v; },
+                              [&](int g) { return all || ((need[g >> 5] >> (g & 31)) & 1u); });
+  }
   for (int g = 0; g < Tab::kGraphs; ++g) Dg[(size_t)g * st] = T(0);
-  const T V = basis_products<T, Tab>(
+  const T V = basis_products<T, Tab, WANT_B>(
       [&](int a) { return args.xi[a]; }, [&](int g) { return Dv[(size_t)g * st]; },
       [&](int g, T v) { Dg[(size_t)g * st] += v; },
       [&](int a, T B) {
@@ -198,7 +245,7 @@ __global__ void __launch_bounds__(64) contract_table_loss_kernel(const EvalArgs<
     gd[(2 * ng + g) * st] = R(0);
     gd[(3 * ng + g) * st] = R(0);
   }
-  (void)basis_products<T, Tab>(
+  (void)basis_products<T, Tab, true>(
       [&](int a) { return T(args.xi[a]); },
       [&](int g) { return T(gd[(size_t)g * st], gd[(ng + g) * st]); },
       [&](int g, T v) {

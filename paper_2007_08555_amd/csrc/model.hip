@@ -319,6 +319,27 @@ int parse_and_match(const char* path, mtp_model* M) {
                                std::to_string(gkeys.size()) + " contractions) is not compiled into libmtp");
 }
 
+// Bit mask of the moment degrees nu that each basis function of the
+// variant uses (kernel order): nu of every vertex of its contractions, read
+// from their canonical keys (mu_0, nu_0, ..., mu_{n-1}, nu_{n-1}, then the
+// n(n-1)/2 edge multiplicities).  All bits for a degree above 31.
+std::vector<uint32_t> function_nu_masks(const mtp::BasisVariant* V) {
+  std::vector<uint32_t> gm(V->n_graphs, 0u);
+  for (int g = 0; g < V->n_graphs; ++g) {
+    const int a = V->graph_key_offsets[g], len = V->graph_key_offsets[g + 1] - a;
+    int n = 0;
+    while (2 * n + n * (n - 1) / 2 < len) ++n;
+    for (int v = 0; v < n; ++v) {
+      const int nu = V->graph_keys[a + 2 * v + 1];
+      gm[g] |= nu < 32 ? (1u << nu) : ~0u;
+    }
+  }
+  std::vector<uint32_t> fm(V->m, 0u);
+  for (int f = 0; f < V->m; ++f)
+    for (int t = V->func_offsets[f]; t < V->func_offsets[f + 1]; ++t) fm[f] |= gm[V->func_factors[t]];
+  return fm;
+}
+
 template <typename T>
 mtp::EvalArgs<T> make_args(mtp_model* M, int64_t n_atoms, int stride, const int32_t* species, bool want_b) {
   mtp::EvalArgs<T> a;
@@ -1169,21 +1190,25 @@ int mtp_normal_equations(mtp_model* M, const mtp_batch* bt, const double* E_t, c
   HIP_TRY(M->fit_P.ensure(sizeof(double) * (size_t)splits * n * n), "hipMalloc");
   HIP_TRY(mtp::fill_eye(fp64, m, M->fit_eye.p, s), "identity");
   double* J = M->fit_J.as<double>();
+  // with xi = e_alpha, dV/dM is zero outside the moments of alpha's
+  // contractions: the adjoint passes of other degrees are skipped
+  const std::vector<uint32_t> nu_masks = function_nu_masks(M->var);
   // column alpha: energies, forces and virials of the potential xi = e_alpha
   for (int al = 0; al < m; ++al) {
     double* col = J + (size_t)al * R;
     const size_t row = (size_t)M->perm[al] * m;  // e_alpha in the kernel's basis order
+    const uint32_t nu = nu_masks[M->perm[al]];
+    const unsigned flags = mtp::kEvalReuseMoments |
+                           (nu < (1u << (32 - mtp::kEvalNuShift)) ? (mtp::kEvalNuMask | (nu << mtp::kEvalNuShift)) : 0u);
     if (N > 0) {
       if (fp64) {
         auto ea = make_args<double>(M, N, stride, bt->species, false);
         ea.xi = M->fit_eye.as<double>() + row;
-        HIP_TRY(M->var->launch_eval(precision, mtp::kEvalReuseMoments, fp64 ? M->schedule64 : 0, &ea, s),
-                "evaluation kernels");
+        HIP_TRY(M->var->launch_eval(precision, flags, fp64 ? M->schedule64 : 0, &ea, s), "evaluation kernels");
       } else {
         auto ea = make_args<float>(M, N, stride, bt->species, false);
         ea.xi = M->fit_eye.as<float>() + row;
-        HIP_TRY(M->var->launch_eval(precision, mtp::kEvalReuseMoments, fp64 ? M->schedule64 : 0, &ea, s),
-                "evaluation kernels");
+        HIP_TRY(M->var->launch_eval(precision, flags, fp64 ? M->schedule64 : 0, &ea, s), "evaluation kernels");
       }
     }
     HIP_TRY(mtp::gather_forces(fp64, N, stride, M->count.as<int32_t>(), M->rev.as<int32_t>(), M->gpair.p,

@@ -10,12 +10,18 @@ namespace mtp {
 // recomputing them; leave the moments in args.M (schedules that keep them in
 // registers skip that store otherwise) for a later reuse or for the loss
 // kernels; compute the moments only (the first half of the mixed-precision
-// path).
+// path); with kEvalNuMask, bits kEvalNuShift.. of the flags mark the moment
+// degrees nu whose dV/dM can be nonzero (the rest is known to be zero, as for
+// xi = e_alpha in the normal equations): adjoint passes past the last one
+// holding such a degree, and reverse passes feeding none of those that run,
+// are skipped.
 enum : unsigned {
   kEvalWantB = 1u,
   kEvalReuseMoments = 2u,
   kEvalStoreMoments = 4u,
-  kEvalMomentsOnly = 8u
+  kEvalMomentsOnly = 8u,
+  kEvalNuMask = 16u,
+  kEvalNuShift = 8u
 };
 
 struct BasisVariant {
