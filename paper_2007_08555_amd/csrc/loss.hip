@@ -140,50 +140,66 @@ __global__ void unit_weights_kernel(int64_t N, int64_t n_eps, T* a_atom, T* u, T
   if (t < n_eps) eps_atom[t] = T(0);
 }
 
-// One workgroup per configuration; threads over its atoms and their pairs,
-// the c entries summed in LDS.
+// One workgroup per configuration; threads over its atoms.  One pass per
+// c block (z_i, z_j, mu): each thread sums, in order, the contributions of
+// its atoms of species z_i and their pairs with neighbours of species z_j to
+// the N_Q entries of the block, then the thread sums are added in thread
+// order (no atomics: the rows are bitwise repeatable).  LDS: [nq][kBlock].
 template <typename T>
 __global__ void __launch_bounds__(kBlock) c_rows_kernel(const ThetaRowArgs a, const PairRec<T>* __restrict__ pr,
                                                         const T* __restrict__ pa, const T* __restrict__ pb) {
-  extern __shared__ double acc[];   // [n_c]
+  extern __shared__ double tile[];   // [nq][kBlock]
   const int k = blockIdx.x;
-  for (int t = threadIdx.x; t < a.n_c; t += blockDim.x) acc[t] = 0.0;
-  __syncthreads();
   const int64_t a0 = a.cfg[k].start, a1 = a0 + a.cfg[k].n;
   const size_t n_slots = (size_t)a.K * a.stride;
   const double span_inv = 1.0 / (a.rcut - a.rmin), dxdr = 2.0 * span_inv;
   const int S = a.n_species, nq = a.nq;
-  for (int64_t i = a0 + threadIdx.x; i < a1; i += blockDim.x) {
-    int zi = a.species[i];
-    zi = zi < 0 ? 0 : (zi >= S ? S - 1 : zi);
-    const int cnt = a.count[i];
-    for (int p = 0; p < cnt; ++p) {
-      const size_t e = (size_t)p * a.stride + i;
-      const PairRec<T> q = pr[e];
-      const int zj = q.zj;
-      const double x = q.x, y = q.y, z = q.z;
-      const double r = sqrt(x * x + y * y + z * z);
-      const double sc = a.rcut - r;
-      const double xq = (2.0 * r - a.rmin - a.rcut) * span_inv;
-      // Chebyshev T_b(xq) and dT_b/dxq by their three-term recurrences
-      double t0 = 1.0, t1 = xq, d0 = 0.0, d1 = 1.0;
-      for (int b = 0; b < nq; ++b) {
-        const double tb = b == 0 ? t0 : t1, db = b == 0 ? d0 : d1;
-        const double Q = tb * sc * sc, dQ = db * dxdr * sc * sc - 2.0 * tb * sc;
-        for (int mu = 0; mu < a.n_mu; ++mu) {
-          const double v = (double)pa[(size_t)mu * n_slots + e] * Q + (double)pb[(size_t)mu * n_slots + e] * dQ;
-          atomicAdd(&acc[((mu * S + zi) * S + zj) * nq + b], v);
+  double* row = a.rows + (size_t)k * (a.m + a.n_c) + a.m;
+  for (int zi = 0; zi < S; ++zi)
+    for (int zj = 0; zj < S; ++zj)
+      for (int mu = 0; mu < a.n_mu; ++mu) {
+        double acc[16];
+        for (int b = 0; b < 16; ++b) acc[b] = 0.0;
+        for (int64_t i = a0 + threadIdx.x; i < a1; i += blockDim.x) {
+          int z = a.species[i];
+          z = z < 0 ? 0 : (z >= S ? S - 1 : z);
+          if (z != zi) continue;
+          const int cnt = a.count[i];
+          for (int p = 0; p < cnt; ++p) {
+            const size_t e = (size_t)p * a.stride + i;
+            const PairRec<T> q = pr[e];
+            if (q.zj != zj) continue;
+            const double x = q.x, y = q.y, zz = q.z;
+            const double r = sqrt(x * x + y * y + zz * zz);
+            const double sc = a.rcut - r;
+            const double xq = (2.0 * r - a.rmin - a.rcut) * span_inv;
+            const double va = (double)pa[(size_t)mu * n_slots + e], vb = (double)pb[(size_t)mu * n_slots + e];
+            // Chebyshev T_b(xq) and dT_b/dxq by their three-term recurrences
+            double t0 = 1.0, t1 = xq, d0 = 0.0, d1 = 1.0;
+#pragma unroll
+            for (int b = 0; b < 16; ++b) {
+              if (b < nq) {
+                const double tb = b == 0 ? t0 : t1, db = b == 0 ? d0 : d1;
+                acc[b] += va * (tb * sc * sc) + vb * (db * dxdr * sc * sc - 2.0 * tb * sc);
+                if (b >= 1) {
+                  const double t2 = 2.0 * xq * t1 - t0, d2 = 2.0 * t1 + 2.0 * xq * d1 - d0;
+                  t0 = t1; t1 = t2; d0 = d1; d1 = d2;
+                }
+              }
+            }
+          }
         }
-        if (b >= 1) {
-          const double t2 = 2.0 * xq * t1 - t0, d2 = 2.0 * t1 + 2.0 * xq * d1 - d0;
-          t0 = t1; t1 = t2; d0 = d1; d1 = d2;
+#pragma unroll
+        for (int b = 0; b < 16; ++b)
+          if (b < nq) tile[(size_t)b * kBlock + threadIdx.x] = acc[b];
+        __syncthreads();
+        for (int b = threadIdx.x; b < nq; b += blockDim.x) {
+          double v = 0.0;
+          for (int l = 0; l < kBlock; ++l) v += tile[(size_t)b * kBlock + l];
+          row[((mu * S + zi) * S + zj) * nq + b] = v;
         }
+        __syncthreads();
       }
-    }
-  }
-  __syncthreads();
-  double* row = a.rows + (size_t)k * (a.m + a.n_c);
-  for (int t = threadIdx.x; t < a.n_c; t += blockDim.x) row[a.m + t] = acc[t];
 }
 
 __global__ void copy_b_kernel(int n_cfg, int m, int n_c, const double* __restrict__ b, double* rows) {
@@ -250,7 +266,8 @@ hipError_t theta_rows_prepare(int fp64, int64_t N, int stride, void* a_atom, voi
 hipError_t theta_rows_finish(int fp64, const ThetaRowArgs& a, const void* pr, const void* pa, const void* pb,
                              const double* b, hipStream_t s) {
   if (a.n_cfg == 0) return hipSuccess;
-  const size_t lds = sizeof(double) * (size_t)a.n_c;
+  if (a.nq > 16) return hipErrorInvalidValue;
+  const size_t lds = sizeof(double) * (size_t)a.nq * kBlock;
   if (fp64)
     hipLaunchKernelGGL(c_rows_kernel<double>, dim3(a.n_cfg), dim3(kBlock), lds, s, a, (const PairRec<double>*)pr,
                        (const double*)pa, (const double*)pb);

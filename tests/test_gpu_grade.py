@@ -110,6 +110,20 @@ def test_theta_rows_match_the_oracle(name, n_species, step):
     assert err32.max() <= 1e-4
 
 
+def test_theta_rows_are_bitwise_repeatable():
+    """The c part of the rows is summed per configuration in a fixed order
+    (no floating-point atomics), also for configurations larger than a
+    workgroup: two calls agree bit for bit."""
+    from paper_2007_08555_amd import Batch, Potential
+    P = Potential(pot_path("lev16_s3"))
+    batch = synth.mixed_batch(seed=22, n_configs=16, n_min=200, n_max=400, n_species_model=3)
+    assert batch["n_atoms"].max() > 256
+    B = Batch.from_arrays(batch)
+    R = [P.theta_rows(B, precision="fp64").cpu().numpy() for _ in range(3)]
+    assert np.abs(R[0]).max() > 0
+    assert all(np.array_equal(R[0], r) for r in R[1:])
+
+
 def test_nonlinear_grade_matches_the_oracle():
     """gamma over theta rows (oracle rows, restricted to independent columns
     chosen by pivoted QR: the full rows are rank-deficient by one relation per
