@@ -117,3 +117,65 @@ def test_kinetic_energy_per_configuration():
                     for k in range(len(b["n_atoms"]))])
     np.testing.assert_allclose(e, ref, rtol=1e-13)
     assert e[1] == 0.0
+
+
+def _morse_pair_potential(path):
+    """A level-2 potential, V_i = sum_j f_0(r_ij), whose radial function is
+    the least-squares fit (numpy, on the Chebyshev radial basis) of half a
+    Morse pair potential D[(1 - exp(-a(r - r0)))^2 - 1] with D = 0.3 eV,
+    a = 1.5 / A, r0 = 2.55 A: a pair potential with a minimum at the
+    nearest-neighbour distance of fcc with lattice constant 3.6 A."""
+    from oracle import basis as obasis
+    from oracle import mtp as omtp
+    from oracle.potential import write_potential
+    level, n_q, r_min, r_cut = 2, 8, 2.0, 5.0
+    r = np.linspace(1.8, r_cut, 400)
+    Q, _ = omtp.radial_basis(r, r_min, r_cut, n_q)
+    target = 0.5 * 0.3 * ((1 - np.exp(-1.5 * (r - 2.55))) ** 2 - 1)
+    c = np.linalg.lstsq(Q, target, rcond=None)[0]
+    pot = dict(level=level, n_species=1, n_q=n_q, r_min=r_min, r_cut=r_cut, moments=obasis.moments_used(level),
+               graphs=list(obasis.connected_contractions(level)), basis=list(obasis.basis(level)),
+               c=c.reshape(1, 1, 1, n_q), xi=np.ones(1))
+    write_potential(path, pot)
+    return pot
+
+
+def test_fire_relaxes_a_perturbed_crystal_on_a_pair_potential(tmp_path):
+    """FIRE (md.relax) on a potential with a minimum: a 108-atom fcc box
+    (a = 3.6 A) with every coordinate perturbed by N(0, 0.08^2) A relaxes
+    until the largest force is below 1e-4 eV/A; the oracle confirms the
+    forces at the final positions, and the box returns to the perfect
+    lattice (up to a common translation) and its energy."""
+    import torch
+    from oracle import mtp as omtp
+    from paper_2007_08555_amd import Batch, Potential, md
+    path = str(tmp_path / "morse_lev2.mtp")
+    pot = _morse_pair_potential(path)
+    a = 3.6
+    base = np.array([[0, 0, 0], [0.5, 0.5, 0], [0.5, 0, 0.5], [0, 0.5, 0.5]])
+    ideal = np.array([(np.array([i, j, k]) + b) * a for i in range(3) for j in range(3) for k in range(3)
+                      for b in base])
+    cell = np.eye(3) * 3 * a
+    rng = np.random.default_rng(17)
+    start = ideal + rng.normal(0, 0.08, ideal.shape)
+    batch = synth._batch([(start, np.zeros(len(ideal), np.int32), cell, 1)])
+    P = Potential(path)
+    B = Batch.from_arrays(batch)
+    res = md.relax(P, B, masses=np.array([63.5]), fmax=1e-4, max_steps=4000)
+    final = B.pos.cpu().numpy()
+    log(f"[relax morse] steps {res['steps']}, converged {bool(res['converged'][0])}, "
+        f"fmax {res['fmax'][-1][0]:.2e}, energy {res['energy'][0][0]:.6f} -> {res['energy'][-1][0]:.6f} eV")
+    assert res["converged"][0]
+    f_o = omtp.evaluate(pot, final, np.zeros(len(ideal), np.int32), cell, 1)["forces"]
+    assert np.abs(f_o).max() <= 2e-4
+    # back on the lattice: displacement from the ideal sites is one common
+    # translation (minimum image per atom)
+    d = final - ideal
+    d -= np.round(d / (3 * a)) * (3 * a)
+    shift = d.mean(axis=0)
+    dev = np.abs(d - shift).max()
+    e_ideal = omtp.evaluate(pot, ideal + shift, np.zeros(len(ideal), np.int32), cell, 1)["energy"]
+    log(f"[relax morse] largest deviation from the shifted lattice {dev:.2e} A; energy {res['energy'][-1][0]:.8f}, "
+        f"perfect lattice {e_ideal:.8f} eV")
+    assert dev <= 1e-3
+    assert abs(res["energy"][-1][0] - e_ideal) <= 1e-6 * len(ideal)
