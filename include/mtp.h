@@ -222,12 +222,17 @@ int mtp_grade_theta(mtp_model* model, int32_t n, const double* rows_dev, double*
  * dL/dxi in the file's basis order, then dL/dc in the layout
  * c[mu][z_i][z_j][beta].  The gradient is formed by forward-mode tangents of
  * the moments and of the contraction's reverse sweep (directional
- * derivatives along the force and virial residuals).  precision: MTP_FP64 or
- * MTP_FP32.  Synchronises `stream` once (inside the evaluation).
+ * derivatives along the force and virial residuals).  grad_pos_dev (device,
+ * may be NULL): dL/dx [n_atoms][3] in eV/Angstrom, the gradient in the atomic
+ * positions at fixed cells: -a_k F_i from the energy term plus the
+ * Hessian-vector product of E with the force and stress residuals, formed by
+ * the same tangents and a dual-number pass over the pair gradients.
+ * precision: MTP_FP64 or MTP_FP32.  Synchronises `stream` once (inside the
+ * evaluation).
  */
 int mtp_loss_grad(mtp_model* model, const mtp_batch* batch, const double* E_t, const double* F_t,
                   const double* W_t, double w_e, double w_f, double w_s, int scaling, int precision,
-                  double* loss_dev, double* grad_dev, void* stream);
+                  double* loss_dev, double* grad_dev, double* grad_pos_dev, void* stream);
 
 /*
  * Normal equations of section 2.2, eq. Fitting, in xi at the model's current

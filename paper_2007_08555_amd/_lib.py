@@ -70,7 +70,7 @@ _SIGNATURES = {
                                         ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), _P]),
     "mtp_status": (ctypes.c_int, [_P, _P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]),
     "mtp_loss_grad": (ctypes.c_int, [_P, ctypes.POINTER(mtp_batch), _P, _P, _P, ctypes.c_double, ctypes.c_double,
-                                     ctypes.c_double, ctypes.c_int, ctypes.c_int, _P, _P, _P]),
+                                     ctypes.c_double, ctypes.c_int, ctypes.c_int, _P, _P, _P, _P]),
     "mtp_normal_equations": (ctypes.c_int, [_P, ctypes.POINTER(mtp_batch), _P, _P, _P, ctypes.c_double,
                                             ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_int,
                                             ctypes.c_int, _P, _P, _P, _P]),

@@ -886,7 +886,75 @@ __global__ void __launch_bounds__(BLOCK) cgrad_p{pidx}_kernel(const mtp::EvalArg
         launch.append(f"  hipLaunchKernelGGL((cgrad_p{pidx}_kernel<T>), grid, dim3(BLOCK), smem, s, args, la);")
     launch.append("  hipLaunchKernelGGL((creduce_kernel<T>), grid, dim3(BLOCK * kCredSplit), "
                   "creduce_smem(args.n_c, args.nq), s, args, la);")
+    # the gradient in the positions (when la.hvp is given): the tangent of the
+    # pair gradients along delta r, on dual numbers (twice the registers of
+    # the adjoint: passes of at most 40 components)
+    import re as _re
+    launch.append("  if (la.hvp) {")
+    for pidx, (nus, comps) in enumerate(adjoint_passes(s, 40)):
+        gmap = {k: j for j, k in enumerate(comps)}
+        nmu = 1 + max(mu for (mu, nu, abc), k in s.comp.items() if nu in nus)
+        body, _ = emit_pair_backward(s, nus=nus, gmap=gmap, nmu=nmu)
+        body = [_re.sub(r"\bT\b", "DT", l) for l in body]
+        src.append(TADJ_TEMPLATE.format(
+            pidx=pidx, nus=nus, head=LOSS_PASS_HEAD, ncomp=len(comps), comp_list=", ".join(map(str, comps)),
+            nmu=nmu, body=ind(body, 4), store=TADJ_FIRST if pidx == 0 else TADJ_ADD))
+        launch.append(f"    hipLaunchKernelGGL((tadj_p{pidx}_kernel<T>), grid, dim3(BLOCK), smem, s, args, la);")
+    launch.append("  }")
     return "\n".join(src), "\n".join(launch)
+
+
+TADJ_TEMPLATE = r"""
+// Loss gradient in the positions, pass {pidx} (components of degrees {nus}):
+// per pair, the tangent along delta r of this pass's share of g = dV_i/dr_ij
+// (G with its tangent dG from the loss path, the pair vector with tangent
+// delta r, in dual numbers), stored (first pass, with eps^T g) or added to
+// la.hvp.
+template <typename T>
+__global__ void __launch_bounds__(BLOCK) tadj_p{pidx}_kernel(const mtp::EvalArgs<T> args, const mtp::LossArgs<T> la) {{{head}
+  using DT = mtp::Dual<T>;
+  constexpr int CP = {ncomp};
+  constexpr int kIdx[CP] = {{ {comp_list} }};
+  DT G[CP];
+#pragma unroll
+  for (int k = 0; k < CP; ++k)
+    G[k] = DT(args.G[(size_t)kIdx[k] * args.stride + i], la.dG[(size_t)kIdx[k] * args.stride + i]);
+#pragma unroll 1
+  for (int p = 0; p < cnt; ++p) {{
+    const size_t e = (size_t)p * args.stride + i;
+    const mtp::PairRec<T> q = args.pr[e];
+    const int zj = q.zj;
+    const int j = la.nbr[e];
+    // delta r_ij = u_j - u_i + eps r_ij
+    const T dx = la.u[3 * (size_t)j] - ux + (e00 * q.x + e01 * q.y + e02 * q.z);
+    const T dy = la.u[3 * (size_t)j + 1] - uy + (e10 * q.x + e11 * q.y + e12 * q.z);
+    const T dz = la.u[3 * (size_t)j + 2] - uz + (e20 * q.x + e21 * q.y + e22 * q.z);
+    const DT x = DT(q.x, dx), y = DT(q.y, dy), z = DT(q.z, dz);
+    const DT r = mtp::dsqrt(x * x + y * y + z * z);
+    const DT inv_r = DT(T(1)) / r;
+    DT f[{nmu}], df[{nmu}];
+    mtp::radial<DT, {nmu}, true, 0, T>(cs, (zi * S + zj) * nqp, mu_stride, nq, r, DT(rmin), DT(rcut), f, df);
+{body}
+    T cx = gx.d, cy = gy.d, cz = gz.d;
+{store}
+  }}
+}}
+"""
+
+TADJ_FIRST = r"""    {{
+      // the stress term's explicit dependence on r_ij: eps^T g
+      const T g0 = args.g[3 * e], g1 = args.g[3 * e + 1], g2 = args.g[3 * e + 2];
+      cx += e00 * g0 + e10 * g1 + e20 * g2;
+      cy += e01 * g0 + e11 * g1 + e21 * g2;
+      cz += e02 * g0 + e12 * g1 + e22 * g2;
+    }}
+    la.hvp[3 * e] = cx;
+    la.hvp[3 * e + 1] = cy;
+    la.hvp[3 * e + 2] = cz;""".replace("{{", "{").replace("}}", "}")
+
+TADJ_ADD = r"""    la.hvp[3 * e] += cx;
+    la.hvp[3 * e + 1] += cy;
+    la.hvp[3 * e + 2] += cz;"""
 
 
 CREDUCE_TEMPLATE = r"""

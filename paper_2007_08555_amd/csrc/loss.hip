@@ -208,7 +208,47 @@ __global__ void copy_b_kernel(int n_cfg, int m, int n_c, const double* __restric
   rows[(t / m) * (m + n_c) + t % m] = b[t];
 }
 
+// dL/dx_i = -a_i F_i - (sum over the slots p of atom i of hvp_p - sum of
+// hvp at the reverse slots), in FP64: the energy term (dE_k/dx_i = -F_i)
+// and the derivative of S_u = sum over pairs of g . delta r through the pair
+// vectors (r_ij = x_j - x_i), whose per-pair values the position passes left
+// in hvp.
+template <typename T>
+__global__ void __launch_bounds__(kBlock) grad_pos_kernel(int64_t N, int stride, const int32_t* __restrict__ count,
+                                                          const int32_t* __restrict__ rev, const T* __restrict__ hvp,
+                                                          const T* __restrict__ a_atom, const double* __restrict__ F,
+                                                          double* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const double a = (double)a_atom[i];
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+  const int c = count[i];
+  for (int p = 0; p < c; ++p) {
+    const size_t e = (size_t)p * stride + i;
+    const size_t q = (size_t)rev[e];
+    s0 += (double)hvp[3 * e] - (double)hvp[3 * q];
+    s1 += (double)hvp[3 * e + 1] - (double)hvp[3 * q + 1];
+    s2 += (double)hvp[3 * e + 2] - (double)hvp[3 * q + 2];
+  }
+  out[3 * i] = -a * F[3 * i] - s0;
+  out[3 * i + 1] = -a * F[3 * i + 1] - s1;
+  out[3 * i + 2] = -a * F[3 * i + 2] - s2;
+}
+
 }  // namespace
+
+hipError_t loss_grad_pos(int fp64, int64_t N, int stride, const int32_t* count, const int32_t* rev, const void* hvp,
+                         const void* a_atom, const double* F, double* out, hipStream_t s) {
+  if (N <= 0) return hipSuccess;
+  const dim3 g((unsigned)((N + kBlock - 1) / kBlock));
+  if (fp64)
+    hipLaunchKernelGGL(grad_pos_kernel<double>, g, dim3(kBlock), 0, s, N, stride, count, rev, (const double*)hvp,
+                       (const double*)a_atom, F, out);
+  else
+    hipLaunchKernelGGL(grad_pos_kernel<float>, g, dim3(kBlock), 0, s, N, stride, count, rev, (const float*)hvp,
+                       (const float*)a_atom, F, out);
+  return hipGetLastError();
+}
 
 hipError_t loss_residuals(LossResidualArgs& r, int fp64, void* a_atom, void* u, void* eps_atom, hipStream_t s) {
   if (r.n_cfg > 0)

@@ -123,7 +123,7 @@ struct mtp_model {
   Buffer b_tmp, c_tmp;
   int last_stride = 0;
   // loss gradient
-  Buffer lo_E, lo_F, lo_W, lo_a, lo_u, lo_eps, lo_dM, lo_dG, lo_xit, lo_pa, lo_pb, lo_cpart, lo_gd, lo_part;
+  Buffer lo_E, lo_F, lo_W, lo_a, lo_u, lo_eps, lo_dM, lo_dG, lo_xit, lo_pa, lo_pb, lo_cpart, lo_gd, lo_part, lo_hvp;
   Buffer lo_acfg, lo_wfcfg, lo_epscfg, lo_losscfg, lo_lossatom;
   // normal equations
   Buffer fit_J, fit_w, fit_P, fit_eye, fit_D, fit_W2, fit_inv, fit_flag;
@@ -802,6 +802,7 @@ int mtp_theta_rows(mtp_model* M, const mtp_batch* bt, int precision, double* row
     la.pa = M->lo_pa.as<T>();
     la.pb = M->lo_pb.as<T>();
     la.cpart = M->lo_cpart.as<double>();
+    la.hvp = nullptr;
     HIP_TRY(M->var->launch_loss(precision, &ea, &la, s), "loss-gradient kernels");
     return MTP_OK;
   };
@@ -1063,7 +1064,7 @@ int mtp_grade(mtp_model* M, const mtp_batch* bt, double* gamma_dev, int32_t* arg
 
 int mtp_loss_grad(mtp_model* M, const mtp_batch* bt, const double* E_t, const double* F_t, const double* W_t,
                   double w_e, double w_f, double w_s, int scaling, int precision, double* loss_dev,
-                  double* grad_dev, void* stream) {
+                  double* grad_dev, double* grad_pos_dev, void* stream) {
   g_err.clear();
   if (!M || !bt || !E_t || !F_t || !W_t || !loss_dev || !grad_dev)
     return fail(MTP_E_ARG, "mtp_loss_grad: null argument");
@@ -1108,6 +1109,7 @@ int mtp_loss_grad(mtp_model* M, const mtp_batch* bt, const double* E_t, const do
   HIP_TRY(M->lo_epscfg.ensure(sizeof(double) * 9 * K_cfg), "hipMalloc");
   HIP_TRY(M->lo_losscfg.ensure(sizeof(double) * K_cfg), "hipMalloc");
   HIP_TRY(M->lo_lossatom.ensure(sizeof(double) * (N + 1)), "hipMalloc");
+  if (grad_pos_dev) HIP_TRY(M->lo_hvp.ensure(tsz * 3 * (size_t)K * stride), "hipMalloc");
   mtp::LossResidualArgs r{};
   r.n_cfg = K_cfg;
   r.N = N;
@@ -1146,11 +1148,16 @@ int mtp_loss_grad(mtp_model* M, const mtp_batch* bt, const double* E_t, const do
     la.pa = M->lo_pa.as<T>();
     la.pb = M->lo_pb.as<T>();
     la.cpart = M->lo_cpart.as<double>();
+    la.hvp = grad_pos_dev ? M->lo_hvp.as<T>() : nullptr;
     HIP_TRY(M->var->launch_loss(precision, &ea, &la, s), "loss-gradient kernels");
     return MTP_OK;
   };
   rc = fp64 ? fill((double*)nullptr) : fill((float*)nullptr);
   if (rc != MTP_OK) return rc;
+  if (grad_pos_dev)
+    HIP_TRY(mtp::loss_grad_pos(fp64, N, stride, M->count.as<int32_t>(), M->rev.as<int32_t>(), M->lo_hvp.p, M->lo_a.p,
+                               o.forces, grad_pos_dev, s),
+            "position gradient");
   HIP_TRY(M->lo_part.ensure(sizeof(double) * (size_t)mtp::loss_finish_scratch_doubles(M->m)), "hipMalloc");
   HIP_TRY(mtp::loss_finish(fp64, K_cfg, N, stride, M->m, M->n_c, n_blocks, r.loss_cfg, r.loss_atom, M->lo_xit.p,
                            M->perm_dev.as<int32_t>(), M->lo_cpart.as<double>(), M->lo_part.as<double>(), loss_dev,

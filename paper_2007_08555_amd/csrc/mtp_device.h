@@ -91,9 +91,20 @@ __device__ __forceinline__ PairVec<T> load_pair(const EvalArgs<T>& a, size_t e) 
 // stride between consecutive mu is S * S * nq.
 // NQ > 0 fixes the radial basis size at compile time (nq is then ignored
 // and the recurrence is unrolled); NQ = 0 takes nq at run time.
+// Fused multiply-add of the radial recurrences (overloaded for dual numbers
+// further down).
+__device__ __forceinline__ double fmadd(double a, double b, double c) { return fma(a, b, c); }
+__device__ __forceinline__ float fmadd(float a, float b, float c) { return fmaf(a, b, c); }
+template <typename R>
+struct Dual;
+template <typename R>
+__device__ __forceinline__ Dual<R> fmadd(R a, Dual<R> b, Dual<R> c);
+
 // radial_us takes the Chebyshev argument x of r, dx/dr and s = R_cut - r.
-template <typename T, int NMU, bool DERIV, int NQ = 0>
-__device__ __forceinline__ void radial_us(const T* __restrict__ cs, int base, int mu_stride, int nq,
+// CT: type of the coefficients (the arithmetic type, or its real part when T
+// is a dual number).
+template <typename T, int NMU, bool DERIV, int NQ = 0, typename CT = T>
+__device__ __forceinline__ void radial_us(const CT* __restrict__ cs, int base, int mu_stride, int nq,
                                           T x, T s, T dxdr, T (&f)[NMU], T (&df)[NMU]) {
   if constexpr (NQ > 0) nq = NQ;
   T acc[NMU], dacc[NMU];
@@ -108,9 +119,9 @@ __device__ __forceinline__ void radial_us(const T* __restrict__ cs, int base, in
   for (int b = 1; b < (NQ > 0 ? NQ : nq); ++b) {
 #pragma unroll
     for (int mu = 0; mu < NMU; ++mu) {
-      const T cb = cs[base + mu * mu_stride + b];
-      acc[mu] = fma(cb, t_cur, acc[mu]);
-      if (DERIV) dacc[mu] = fma(cb, d_cur, dacc[mu]);
+      const CT cb = cs[base + mu * mu_stride + b];
+      acc[mu] = fmadd(cb, t_cur, acc[mu]);
+      if (DERIV) dacc[mu] = fmadd(cb, d_cur, dacc[mu]);
     }
     const T t_next = T(2) * x * t_cur - t_prev;
     if (DERIV) {
@@ -129,13 +140,13 @@ __device__ __forceinline__ void radial_us(const T* __restrict__ cs, int base, in
   }
 }
 
-template <typename T, int NMU, bool DERIV, int NQ = 0>
-__device__ __forceinline__ void radial(const T* __restrict__ cs, int base, int mu_stride, int nq,
+template <typename T, int NMU, bool DERIV, int NQ = 0, typename CT = T>
+__device__ __forceinline__ void radial(const CT* __restrict__ cs, int base, int mu_stride, int nq,
                                        T r, T rmin, T rcut, T (&f)[NMU], T (&df)[NMU]) {
   const T span_inv = T(1) / (rcut - rmin);
   const T x = (T(2) * r - rmin - rcut) * span_inv;
   const T dxdr = T(2) * span_inv;
-  radial_us<T, NMU, DERIV, NQ>(cs, base, mu_stride, nq, x, rcut - r, dxdr, f, df);
+  radial_us<T, NMU, DERIV, NQ, CT>(cs, base, mu_stride, nq, x, rcut - r, dxdr, f, df);
 }
 
 // Sum over aligned groups of SPLIT consecutive lanes (SPLIT = 1, 2 or 4):
@@ -187,6 +198,21 @@ template <typename R>
 __device__ __forceinline__ Dual<R> operator*(R a, Dual<R> b) { return Dual<R>(a * b.v, a * b.d); }
 template <typename R>
 __device__ __forceinline__ Dual<R>& operator+=(Dual<R>& a, Dual<R> b) { a.v += b.v; a.d += b.d; return a; }
+template <typename R>
+__device__ __forceinline__ Dual<R> operator-(Dual<R> a, Dual<R> b) { return Dual<R>(a.v - b.v, a.d - b.d); }
+template <typename R>
+__device__ __forceinline__ Dual<R> operator/(Dual<R> a, Dual<R> b) {
+  const R q = a.v / b.v;
+  return Dual<R>(q, (a.d - q * b.d) / b.v);
+}
+template <typename R>
+__device__ __forceinline__ Dual<R> dsqrt(Dual<R> a) {
+  const R r = sqrt(a.v);
+  return Dual<R>(r, a.d / (R(2) * r));
+}
+// a b + c with a real coefficient a (radial coefficients times a dual)
+template <typename R>
+__device__ __forceinline__ Dual<R> fmadd(R a, Dual<R> b, Dual<R> c) { return Dual<R>(fma(a, b.v, c.v), fma(a, b.d, c.d)); }
 
 template <typename R, int N>
 __device__ __forceinline__ void opaque(Dual<R> (&v)[N]) {
@@ -210,6 +236,8 @@ struct LossArgs {
   T* pa;               // [NMU][K * stride] per pair: coefficient of Q_beta
   T* pb;               // [NMU][K * stride] per pair: coefficient of dQ_beta/dr
   double* cpart;       // [blocks][n_c] partial sums of dL/dc per workgroup
+  T* hvp;              // [K * stride][3] per pair: tangent of g = dV_i/dr_ij along delta r plus
+                       // eps^T g (for dL/dx); null when the position gradient is not wanted
 };
 
 // Error-free sum (Knuth's TwoSum): hi + lo carries the accumulated sum.

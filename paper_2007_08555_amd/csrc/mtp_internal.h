@@ -168,6 +168,10 @@ hipError_t loss_finish(int fp64, int n_cfg, int64_t N, int stride, int m, int n_
                        const double* loss_cfg, const double* loss_atom, const void* xi_terms, const int32_t* perm,
                        const double* cpart, double* part, double* loss, double* grad, hipStream_t s);
 int loss_finish_scratch_doubles(int m);
+// dL/dx [N][3] from the forces F of the evaluation, a per atom and the
+// per-pair values hvp of the position passes (see grad_pos_kernel).
+hipError_t loss_grad_pos(int fp64, int64_t N, int stride, const int32_t* count, const int32_t* rev, const void* hvp,
+                         const void* a_atom, const double* F, double* out, hipStream_t s);
 
 // MaxVol selection (section 2.3): the largest |C_ij| and where it is.
 struct MaxvolPick {

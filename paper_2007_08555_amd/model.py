@@ -113,19 +113,21 @@ class Potential:
         return res
 
     def loss_grad(self, batch: Batch, E_t, F_t, W_t, w_e=1.0, w_f=0.01, w_s=0.001, scaling="vibrations",
-                  precision="fp64", stream=None):
+                  precision="fp64", stream=None, pos=False):
         """Loss of eq. Fitting and dL/d(xi, c) (mtp_loss_grad); targets are
-        device or host arrays: E_t [K], F_t [N,3], W_t [K,3,3] (virial, eV)."""
+        device or host arrays: E_t [K], F_t [N,3], W_t [K,3,3] (virial, eV).
+        With pos=True also dL/dx [N,3] (the gradient in the positions)."""
         dev = self.device
         t = lambda a: torch.as_tensor(a, dtype=torch.float64).to(dev).contiguous()
         E_t, F_t, W_t = t(E_t), t(F_t), t(W_t)
         loss = torch.empty(1, dtype=torch.float64, device=dev)
         grad = torch.empty(self.m + self.n_c, dtype=torch.float64, device=dev)
+        gpos = torch.empty((batch.n_atoms, 3), dtype=torch.float64, device=dev) if pos else None
         bs = batch.c_struct()
         check(lib().mtp_loss_grad(self._h, ctypes.byref(bs), _ptr(E_t), _ptr(F_t), _ptr(W_t), float(w_e), float(w_f),
                                   float(w_s), _lib.SCALINGS[scaling], _lib.PRECISIONS[precision], _ptr(loss),
-                                  _ptr(grad), _stream(stream)), "mtp_loss_grad")
-        return loss, grad
+                                  _ptr(grad), _ptr(gpos) if pos else None, _stream(stream)), "mtp_loss_grad")
+        return (loss, grad, gpos) if pos else (loss, grad)
 
     def normal_equations(self, batch: Batch, E_t, F_t, W_t, w_e=1.0, w_f=0.01, w_s=0.001, scaling="vibrations",
                          precision="fp64", out=None, stream=None):
