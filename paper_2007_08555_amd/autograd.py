@@ -66,3 +66,29 @@ class MTPLoss(torch.autograd.Function):
         (grad,) = ctx.saved_tensors
         g = grad * gL.to(torch.float64)
         return g[ctx.m:], g[:ctx.m], None, None, None, None, None, None, None, None, None, None
+
+
+class MTPLossPositions(torch.autograd.Function):
+    """L(positions, c, xi) of eq. Fitting with fixed targets; backward is
+    mtp_loss_grad with its position gradient (dL/dx, dL/dc, dL/dxi).
+
+    forward(pos [N,3] FP64 on the device, c [n_c], xi [m], P, batch, E_t, F_t,
+    W_t, ...) -> L."""
+
+    @staticmethod
+    def forward(ctx, pos, c, xi, P: Potential, batch: Batch, E_t, F_t, W_t, w_e=1.0, w_f=0.01, w_s=0.001,
+                scaling="vibrations", precision="fp64"):
+        _set_theta(P, c, xi)
+        b = Batch(batch.atom_offsets, pos.detach().contiguous(), batch.species, batch.cell, batch.pbc)
+        loss, grad, gpos = P.loss_grad(b, E_t, F_t, W_t, w_e=w_e, w_f=w_f, w_s=w_s, scaling=scaling,
+                                       precision=precision, pos=True)
+        ctx.m = P.m
+        ctx.save_for_backward(grad, gpos)
+        return loss[0]
+
+    @staticmethod
+    def backward(ctx, gL):
+        grad, gpos = ctx.saved_tensors
+        gL = gL.to(torch.float64)
+        g = grad * gL
+        return gpos * gL, g[ctx.m:], g[:ctx.m], None, None, None, None, None, None, None, None, None, None

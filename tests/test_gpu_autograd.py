@@ -81,3 +81,34 @@ def test_loss_gradient_matches_finite_differences():
                     vals.append(MTPLoss.apply(*args, P, B, E_t, F_t, W_t).item())
             fd = (vals[0] - vals[1]) / (2 * hh)
             assert abs(fd - grad[k].item()) <= 1e-6 * max(abs(fd), 1e-6 * grad.abs().max().item()), (which, k)
+
+
+def test_loss_position_gradient_through_autograd():
+    """MTPLossPositions: torch.autograd gives dL/dx from mtp_loss_grad; its
+    product with a random displacement matches the central difference of the
+    loss (same function, shifted positions)."""
+    import torch
+    from paper_2007_08555_amd import Batch, Potential
+    from paper_2007_08555_amd.autograd import MTPLossPositions
+    P = Potential(pot_path("lev12_s2"))
+    batch = synth.mixed_batch(seed=27, n_configs=6, n_min=8, n_max=24, n_species_model=2)
+    B = Batch.from_arrays(batch)
+    K, N = len(batch["n_atoms"]), int(batch["n_atoms"].sum())
+    rng = np.random.default_rng(3)
+    E_t = torch.as_tensor(rng.normal(-3.0, 0.5, K) * batch["n_atoms"], device="cuda")
+    F_t = torch.as_tensor(rng.normal(0.0, 1.0, (N, 3)), device="cuda")
+    W_t = torch.as_tensor(rng.normal(0.0, 1.0, (K, 3, 3)), device="cuda")
+    c0, xi0 = P.get_params()
+    c = torch.as_tensor(c0, device="cuda")
+    xi = torch.as_tensor(xi0, device="cuda")
+    pos = B.pos.clone().requires_grad_(True)
+    L = MTPLossPositions.apply(pos, c, xi, P, B, E_t, F_t, W_t)
+    L.backward()
+    d = torch.as_tensor(rng.normal(size=(N, 3)), device="cuda")
+    h = 1e-6
+    Lp = MTPLossPositions.apply(B.pos + h * d, c, xi, P, B, E_t, F_t, W_t).item()
+    Lm = MTPLossPositions.apply(B.pos - h * d, c, xi, P, B, E_t, F_t, W_t).item()
+    fd = (Lp - Lm) / (2 * h)
+    an = float((pos.grad * d).sum())
+    log(f"[autograd positions] directional derivative {an:.10e}, central difference {fd:.10e}")
+    assert abs(an - fd) <= 1e-6 * abs(an)
