@@ -247,7 +247,10 @@ int mtp_loss_grad(mtp_model* model, const mtp_batch* batch, const double* E_t, c
  * the buffers hold (summing over batches of a training set larger than one
  * batch), with 0 they are overwritten.  J is evaluated in `precision`
  * (MTP_FP64 or MTP_FP32) and held in the model's workspace:
- * 8 (m + 1)(10 n_configs + 3 n_atoms) bytes.  Synchronises `stream` once.
+ * 8 (m + 1)(10 n_configs + 3 n_atoms) bytes, plus two more sets of the
+ * evaluation's per-atom buffers: the columns run on three internal streams
+ * forked from and joined back to `stream`, so the outputs are ready in
+ * `stream` order.  Synchronises `stream` once.
  */
 int mtp_normal_equations(mtp_model* model, const mtp_batch* batch, const double* E_t, const double* F_t,
                          const double* W_t, double w_e, double w_f, double w_s, int scaling, int precision,

@@ -127,6 +127,16 @@ struct mtp_model {
   Buffer lo_acfg, lo_wfcfg, lo_epscfg, lo_losscfg, lo_lossatom;
   // normal equations
   Buffer fit_J, fit_w, fit_P, fit_eye, fit_D, fit_W2, fit_inv, fit_flag;
+  // their columns run on kFitLanes streams at once (forked from and joined
+  // back to the caller's stream); lane 0 writes the evaluation buffers above,
+  // the others their own dV/dM, dV/dg, pair gradients and per-atom sums
+  struct FitLane {
+    hipStream_t s = nullptr;
+    hipEvent_t done = nullptr;
+    Buffer G, D, gpair, own, site, wv;
+  };
+  static constexpr int kFitLanes = 3;
+  FitLane fit_lane[kFitLanes];
   // statistics of the last evaluation
   int64_t last_atoms = 0, last_pairs = 0;
   int32_t last_max_nb = 0;
@@ -143,6 +153,10 @@ struct mtp_model {
     if (fork) (void)hipEventDestroy(fork);
     if (join) (void)hipEventDestroy(join);
     if (side) (void)hipStreamDestroy(side);
+    for (auto& l : fit_lane) {
+      if (l.done) (void)hipEventDestroy(l.done);
+      if (l.s) (void)hipStreamDestroy(l.s);
+    }
   }
 };
 
@@ -1200,8 +1214,37 @@ int mtp_normal_equations(mtp_model* M, const mtp_batch* bt, const double* E_t, c
   // with xi = e_alpha, dV/dM is zero outside the moments of alpha's
   // contractions: the adjoint passes of other degrees are skipped
   const std::vector<uint32_t> nu_masks = function_nu_masks(M->var);
-  // column alpha: energies, forces and virials of the potential xi = e_alpha
+  // the column lanes: streams (made once) and buffers of lanes 1.. (lane 0
+  // has the evaluation's own)
+  const size_t slots = (size_t)M->K * stride;
+  for (int l = 0; l < mtp_model::kFitLanes; ++l) {
+    auto& L = M->fit_lane[l];
+    if (!L.s) {
+      HIP_TRY(hipStreamCreateWithFlags(&L.s, hipStreamNonBlocking), "hipStreamCreateWithFlags");
+      HIP_TRY(hipEventCreateWithFlags(&L.done, hipEventDisableTiming), "hipEventCreateWithFlags");
+    }
+    if (l == 0) continue;
+    HIP_TRY(L.G.ensure(tsz * (size_t)M->var->C * stride), "hipMalloc");
+    HIP_TRY(L.D.ensure(tsz * 2 * (size_t)M->var->n_graphs * stride), "hipMalloc");
+    HIP_TRY(L.gpair.ensure(tsz * 3 * slots), "hipMalloc");
+    HIP_TRY(L.own.ensure(sizeof(double) * 3 * (size_t)stride), "hipMalloc");
+    HIP_TRY(L.site.ensure(tsz * (size_t)stride), "hipMalloc");
+    HIP_TRY(L.wv.ensure(tsz * 9 * (size_t)stride), "hipMalloc");
+  }
+  HIP_TRY(hipEventRecord(M->fork, s), "hipEventRecord");
+  for (auto& L : M->fit_lane) HIP_TRY(hipStreamWaitEvent(L.s, M->fork, 0), "hipStreamWaitEvent");
+  // column alpha on lane alpha mod kFitLanes: energies, forces and virials of
+  // the potential xi = e_alpha (moments, neighbour lists and the identity
+  // rows are only read)
   for (int al = 0; al < m; ++al) {
+    const int l = al % mtp_model::kFitLanes;
+    const auto& L = M->fit_lane[l];
+    void* G = l ? L.G.p : M->Gbuf.p;
+    void* D = l ? L.D.p : M->Dbuf.p;
+    void* gp = l ? L.gpair.p : M->gpair.p;
+    void* site = l ? L.site.p : M->site.p;
+    void* wv = l ? L.wv.p : M->wv.p;
+    double* own = l ? L.own.as<double>() : M->own.as<double>();
     double* col = J + (size_t)al * R;
     const size_t row = (size_t)M->perm[al] * m;  // e_alpha in the kernel's basis order
     const uint32_t nu = nu_masks[M->perm[al]];
@@ -1211,19 +1254,27 @@ int mtp_normal_equations(mtp_model* M, const mtp_batch* bt, const double* E_t, c
       if (fp64) {
         auto ea = make_args<double>(M, N, stride, bt->species, false);
         ea.xi = M->fit_eye.as<double>() + row;
-        HIP_TRY(M->var->launch_eval(precision, flags, fp64 ? M->schedule64 : 0, &ea, s), "evaluation kernels");
+        ea.G = (double*)G; ea.D = (double*)D; ea.g = (double*)gp; ea.site = (double*)site;
+        ea.atom_virial = (double*)wv; ea.own = own;
+        HIP_TRY(M->var->launch_eval(precision, flags, M->schedule64, &ea, L.s), "evaluation kernels");
       } else {
         auto ea = make_args<float>(M, N, stride, bt->species, false);
         ea.xi = M->fit_eye.as<float>() + row;
-        HIP_TRY(M->var->launch_eval(precision, flags, fp64 ? M->schedule64 : 0, &ea, s), "evaluation kernels");
+        ea.G = (float*)G; ea.D = (float*)D; ea.g = (float*)gp; ea.site = (float*)site;
+        ea.atom_virial = (float*)wv; ea.own = own;
+        HIP_TRY(M->var->launch_eval(precision, flags, 0, &ea, L.s), "evaluation kernels");
       }
     }
-    HIP_TRY(mtp::gather_forces(fp64, N, stride, M->count.as<int32_t>(), M->rev.as<int32_t>(), M->gpair.p,
-                               M->own.as<double>(), col + K_cfg, s),
+    HIP_TRY(mtp::gather_forces(fp64, N, stride, M->count.as<int32_t>(), M->rev.as<int32_t>(), gp, own,
+                               col + K_cfg, L.s),
             "force gather");
-    HIP_TRY(mtp::reduce_configs(fp64, K_cfg, M->cfg.as<mtp::CfgInfo>(), stride, M->site.p, M->wv.p, nullptr, m,
-                                stride, M->perm_dev.as<int32_t>(), col, col + K_cfg + 3 * N, nullptr, nullptr, s),
+    HIP_TRY(mtp::reduce_configs(fp64, K_cfg, M->cfg.as<mtp::CfgInfo>(), stride, site, wv, nullptr, m, stride,
+                                M->perm_dev.as<int32_t>(), col, col + K_cfg + 3 * N, nullptr, nullptr, L.s),
             "reductions");
+  }
+  for (auto& L : M->fit_lane) {
+    HIP_TRY(hipEventRecord(L.done, L.s), "hipEventRecord");
+    HIP_TRY(hipStreamWaitEvent(s, L.done, 0), "hipStreamWaitEvent");
   }
   HIP_TRY(mtp::fit_rows(K_cfg, N, R, M->cfg.as<mtp::CfgInfo>(), M->atom_cfg.as<int32_t>(), w_e, w_f, w_s, scaling,
                         E_t, F_t, W_t, M->fit_w.as<double>(), J + (size_t)m * R, s),
