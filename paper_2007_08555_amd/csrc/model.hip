@@ -103,6 +103,8 @@ struct mtp_model {
   // workspace
   Buffer cfg, cfg_order, atom_cfg, atom_bin, bin_count, bin_start, bin_atoms, bin_fill, binned, large, nbins_dev;
   Buffer count, nbr, pr, rev, gpair, own, Mbuf, Gbuf, Dbuf, site, wv, B, status, run_start;
+  Buffer item_start, item_cfg, red_part;   // work items and partials of the per-configuration sums
+  int red_items = 0;                       // reduce_max_items of the last batch
   int K = 64;  // neighbour capacity per atom, grown on overflow
   int schedule64 = 0;    // FP64 pass split of the evaluation kernels (mtp_autotune)
   int schedule64_b = 0;  // the same for evaluations that also write the basis values (descriptor sums)
@@ -133,7 +135,7 @@ struct mtp_model {
   struct FitLane {
     hipStream_t s = nullptr;
     hipEvent_t done = nullptr;
-    Buffer G, D, gpair, own, site, wv;
+    Buffer G, D, gpair, own, site, wv, red_part;
   };
   static constexpr int kFitLanes = 3;
   FitLane fit_lane[kFitLanes];
@@ -446,6 +448,10 @@ int run_eval(mtp_model* M, const mtp_batch* bt, const mtp_out* out, int precisio
     NEED(M->site, tsz * stride);
     NEED(M->wv, tsz * 9 * stride);
     if (want_b) NEED(M->B, tsz * (size_t)M->m * stride);
+    const int red_items = reduce_max_items(n_cfg, N);
+    NEED(M->item_start, sizeof(int32_t) * ((size_t)n_cfg + 1));
+    NEED(M->item_cfg, sizeof(int32_t) * (size_t)red_items);
+    NEED(M->red_part, sizeof(double) * (size_t)red_items * reduce_rows(1, M->m, want_b));
     const bool use_skin = M->skin > 0.0 && !async;
     if (use_skin) {
       NEED(M->xbuild, sizeof(double) * 3 * (size_t)(N + 1));
@@ -518,6 +524,14 @@ int run_eval(mtp_model* M, const mtp_batch* bt, const mtp_out* out, int precisio
       HIP_TRY(nbr_build(a, s), "neighbour search");
     }
     HIP_TRY(mark(1), "hipEventRecord");
+    // work items of the per-configuration sums (they need only the
+    // configurations' ranges) on the side stream, beside the evaluation
+    M->red_items = red_items;
+    HIP_TRY(hipEventRecord(M->fork, s), "hipEventRecord");
+    HIP_TRY(hipStreamWaitEvent(M->side, M->fork, 0), "hipStreamWaitEvent");
+    HIP_TRY(reduce_items(n_cfg, M->cfg.as<CfgInfo>(), red_items, M->item_start.as<int32_t>(),
+                         M->item_cfg.as<int32_t>(), M->side),
+            "reduction items");
     if (N > 0) {
       const unsigned flags = (want_b ? kEvalWantB : 0u) | (store_moments ? kEvalStoreMoments : 0u);
       if (mixed) {
@@ -548,9 +562,11 @@ int run_eval(mtp_model* M, const mtp_batch* bt, const mtp_out* out, int precisio
     // scattered loads, the sums stream B; both need only the evaluation
     HIP_TRY(hipEventRecord(M->fork, s), "hipEventRecord");
     HIP_TRY(hipStreamWaitEvent(M->side, M->fork, 0), "hipStreamWaitEvent");
+    const ReduceItems items{red_items, M->item_start.as<int32_t>(), M->item_cfg.as<int32_t>(),
+                            M->red_part.as<double>()};
     HIP_TRY(reduce_configs(fp64, n_cfg, M->cfg.as<CfgInfo>(), stride, M->site.p, out->virial ? M->wv.p : nullptr,
                            want_b ? M->B.p : nullptr, M->m, stride, M->perm_dev.as<int32_t>(), out->energy,
-                           out->virial, out->b, out->site_energy, M->side),
+                           out->virial, out->b, out->site_energy, items, M->side),
             "reductions");
     HIP_TRY(hipEventRecord(M->join, M->side), "hipEventRecord");
     // the per-atom virials were summed by the last adjoint pass
@@ -1224,6 +1240,7 @@ int mtp_normal_equations(mtp_model* M, const mtp_batch* bt, const double* E_t, c
       HIP_TRY(hipEventCreateWithFlags(&L.done, hipEventDisableTiming), "hipEventCreateWithFlags");
     }
     if (l == 0) continue;
+    HIP_TRY(L.red_part.ensure(sizeof(double) * (size_t)M->red_items * mtp::reduce_rows(1, m, false)), "hipMalloc");
     HIP_TRY(L.G.ensure(tsz * (size_t)M->var->C * stride), "hipMalloc");
     HIP_TRY(L.D.ensure(tsz * 2 * (size_t)M->var->n_graphs * stride), "hipMalloc");
     HIP_TRY(L.gpair.ensure(tsz * 3 * slots), "hipMalloc");
@@ -1268,8 +1285,10 @@ int mtp_normal_equations(mtp_model* M, const mtp_batch* bt, const double* E_t, c
     HIP_TRY(mtp::gather_forces(fp64, N, stride, M->count.as<int32_t>(), M->rev.as<int32_t>(), gp, own,
                                col + K_cfg, L.s),
             "force gather");
+    const mtp::ReduceItems items{M->red_items, M->item_start.as<int32_t>(), M->item_cfg.as<int32_t>(),
+                                 l ? L.red_part.as<double>() : M->red_part.as<double>()};
     HIP_TRY(mtp::reduce_configs(fp64, K_cfg, M->cfg.as<mtp::CfgInfo>(), stride, site, wv, nullptr, m, stride,
-                                M->perm_dev.as<int32_t>(), col, col + K_cfg + 3 * N, nullptr, nullptr, L.s),
+                                M->perm_dev.as<int32_t>(), col, col + K_cfg + 3 * N, nullptr, nullptr, items, L.s),
             "reductions");
   }
   for (auto& L : M->fit_lane) {

@@ -88,11 +88,24 @@ hipError_t gather_forces(int fp64, int64_t n_atoms, int stride, const int32_t* c
 
 // Per-configuration sums of site energies, virials and B (kernel order ->
 // file order through perm, which maps file index -> kernel index), over the
-// validated atom ranges of cfg.
+// validated atom ranges of cfg, as chunked row sums (reduce.hip): the work
+// items come from reduce_items (once per batch, after the search), and
+// partial holds reduce_max_items x reduce_rows doubles (per stream when
+// several reductions run at once).
+struct ReduceItems {
+  int max_items;            // reduce_max_items(n_cfg, n_atoms)
+  const int32_t* item_start;  // [n_cfg + 1]
+  const int32_t* item_cfg;    // [max_items]
+  double* partial;          // [max_items][rows]
+};
+int reduce_max_items(int n_cfg, int64_t n_atoms);
+int reduce_rows(int has_virial, int m, bool b);
+hipError_t reduce_items(int n_cfg, const CfgInfo* cfg, int max_items, int32_t* item_start, int32_t* item_cfg,
+                        hipStream_t s);
 hipError_t reduce_configs(int fp64, int n_cfg, const CfgInfo* cfg, int stride,
                           const void* site, const void* atom_virial, const void* B, int m,
                           int b_stride, const int32_t* perm, double* energy, double* virial,
-                          double* b, double* site_out, hipStream_t s);
+                          double* b, double* site_out, const ReduceItems& items, hipStream_t s);
 
 // Normal equations in xi (fit.hip).  Ja is column-major [m + 1][R]: columns
 // 0..m-1 the Jacobian, column m the targets.

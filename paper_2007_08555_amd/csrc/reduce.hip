@@ -55,109 +55,136 @@ __global__ void __launch_bounds__(kBlock) gather_kernel(int64_t n_atoms, int str
   F[3 * i + 2] = fz;
 }
 
-// FP64 sums of a configuration's site energies and per-atom virials in a
-// fixed order: per thread the atoms i, i + blockDim, i + 2 blockDim, ...,
-// then a tree over the block;
-// U atoms per thread are loaded together (U > 1 for large configurations:
-// the loads of one block then overlap).
-template <typename T, int U>
-__device__ __forceinline__ void config_sums(int k, const CfgInfo* __restrict__ cfg, int stride,
-                                            const T* __restrict__ site, const T* __restrict__ wv, double* energy,
-                                            double* virial, double* site_out) {
-  const int64_t a0 = cfg[k].start, a1 = cfg[k].start + cfg[k].n;
-  double acc[10];
-  for (int t = 0; t < 10; ++t) acc[t] = 0.0;
-  for (int64_t i0 = a0 + threadIdx.x; i0 < a1; i0 += (int64_t)U * blockDim.x) {
-    double v[U], w[U][9];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int64_t i = i0 + (int64_t)u * blockDim.x;
-      const int64_t ic = i < a1 ? i : i0;
-      v[u] = (double)site[ic];
-      if (wv)
-        for (int t = 0; t < 9; ++t) w[u][t] = (double)wv[(size_t)t * stride + ic];
+// Per-configuration sums (site energies -> E_k, per-atom virials -> W_k,
+// basis values -> b_k) as segmented row sums.  Every configuration is cut
+// into chunks of kChunk atoms from its first atom; each chunk is one work
+// item (one workgroup).  A workgroup's wavefronts take U rows at a time, the
+// lanes every 64th atom of the chunk, and the 64 partial sums are combined by
+// a butterfly; a configuration of one chunk writes its sums directly, a
+// larger one writes a partial per chunk that rows_finish_kernel adds in chunk
+// order.  The order of every sum is fixed by the configuration's size alone
+// (bitwise repeatable, and the same for a configuration evaluated alone), and
+// a configuration of any size is spread over ceil(n / kChunk) workgroups.
+constexpr int kChunk = 1024;
+constexpr int kRowWaves = kBlock / 64;
+constexpr int kRowU = 4;
+
+// item_start[k] = first work item of configuration k (n_cfg + 1 entries),
+// item_cfg[item] = its configuration; items past max_items are not recorded
+// (only reachable with invalid atom offsets, which the search reports).
+__global__ void __launch_bounds__(1024) chunk_items_kernel(int n_cfg, const CfgInfo* __restrict__ cfg,
+                                                           int max_items, int32_t* item_start, int32_t* item_cfg) {
+  __shared__ int32_t sc[1024];
+  const int t = threadIdx.x;
+  int base = 0;
+  for (int k0 = 0; k0 < n_cfg; k0 += 1024) {
+    const int k = k0 + t;
+    const int n = k < n_cfg ? cfg[k].n : 0;
+    const int cnt = k < n_cfg ? (n > kChunk ? (n + kChunk - 1) / kChunk : 1) : 0;
+    sc[t] = cnt;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {   // inclusive scan (Hillis-Steele)
+      const int v = t >= off ? sc[t - off] : 0;
+      __syncthreads();
+      sc[t] += v;
+      __syncthreads();
     }
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int64_t i = i0 + (int64_t)u * blockDim.x;
-      if (i >= a1) break;
-      acc[0] += v[u];
-      if (site_out) site_out[i] = v[u];
-      if (wv)
-        for (int t = 0; t < 9; ++t) acc[1 + t] += w[u][t];
+    const int first = base + sc[t] - cnt;
+    if (k < n_cfg) {
+      item_start[k] = first;
+      for (int c = 0; c < cnt && first + c < max_items; ++c) item_cfg[first + c] = k;
     }
-  }
-  __shared__ double red[10][kBlock];
-  for (int t = 0; t < 10; ++t) red[t][threadIdx.x] = acc[t];
-  __syncthreads();
-  for (int w = kBlock / 2; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w)
-      for (int t = 0; t < 10; ++t) red[t][threadIdx.x] += red[t][threadIdx.x + w];
+    base += sc[1023];
     __syncthreads();
   }
-  if (threadIdx.x == 0) {
-    if (energy) energy[k] = red[0][0];
-    if (virial && wv)
-      for (int t = 0; t < 9; ++t) virial[9 * k + t] = red[1 + t][0];
+  if (t == 0) item_start[n_cfg] = base;
+}
+
+// Rows: 0 the site energies, then (has_v) the nine per-atom virial
+// components, then (B) the m basis values in file order (perm).
+struct RowSums {
+  int n_cfg, stride, n_rows, has_v, m, b_stride, max_items;
+  const CfgInfo* cfg;
+  const void* site;
+  const void* wv;
+  const void* B;
+  const int32_t* perm;
+  const int32_t* item_start;
+  const int32_t* item_cfg;
+  double* partial;   // [max_items][n_rows]
+  double *energy, *virial, *b, *site_out;
+};
+
+template <typename T>
+__device__ inline const T* row_ptr(const RowSums& a, int r) {
+  if (r == 0) return (const T*)a.site;
+  if (a.has_v && r <= 9) return (const T*)a.wv + (size_t)(r - 1) * a.stride;
+  return (const T*)a.B + (size_t)a.perm[r - 1 - 9 * a.has_v] * a.b_stride;
+}
+
+__device__ inline void row_out(const RowSums& a, int k, int r, double v) {
+  if (r == 0) {
+    if (a.energy) a.energy[k] = v;
+  } else if (a.has_v && r <= 9) {
+    if (a.virial) a.virial[9 * k + r - 1] = v;
+  } else {
+    a.b[(size_t)k * a.m + r - 1 - 9 * a.has_v] = v;
   }
 }
 
-// One block per configuration; configurations above kLargeCfg atoms are left
-// to config_large_kernel (one atom per thread keeps this kernel's registers,
-// and so its occupancy over many small configurations, low).
-constexpr int kLargeCfg = 4 * kBlock;
-
 template <typename T>
-__global__ void __launch_bounds__(kBlock) config_kernel(int n_cfg, const CfgInfo* __restrict__ cfg, int stride,
-                                                        const T* __restrict__ site, const T* __restrict__ wv,
-                                                        double* energy, double* virial, double* site_out) {
-  const int k = blockIdx.x;
-  if (k >= n_cfg || cfg[k].n > kLargeCfg) return;
-  config_sums<T, 1>(k, cfg, stride, site, wv, energy, virial, site_out);
-}
-
-template <typename T>
-__global__ void __launch_bounds__(kBlock) config_large_kernel(int n_cfg, const CfgInfo* __restrict__ cfg, int stride,
-                                                              const T* __restrict__ site, const T* __restrict__ wv,
-                                                              double* energy, double* virial, double* site_out) {
-  const int k = blockIdx.x;
-  if (k >= n_cfg || cfg[k].n <= kLargeCfg) return;
-  config_sums<T, 4>(k, cfg, stride, site, wv, energy, virial, site_out);
-}
-
-// b[k][f] = sum over atoms of configuration k of B[perm[f]][atom]; one block
-// per configuration, each wavefront four basis functions at a time: lanes
-// read consecutive atoms (coalesced) and the 64 partial sums are combined by
-// a butterfly in a fixed order.
-template <typename T>
-__global__ void __launch_bounds__(kBlock) b_kernel(int n_cfg, const CfgInfo* __restrict__ cfg,
-                                                   const T* __restrict__ B, int m, int b_stride,
-                                                   const int32_t* __restrict__ perm, double* b) {
-  constexpr int U = 4;
-  constexpr int kWaves = kBlock / 64;
-  const int k = blockIdx.x;
-  if (k >= n_cfg) return;
+__global__ void __launch_bounds__(kBlock) rows_kernel(RowSums a) {
+  const int item = blockIdx.x;
+  const int total = a.item_start[a.n_cfg];
+  if (item >= total || item >= a.max_items) return;
+  const int k = a.item_cfg[item];
+  const int first = a.item_start[k], items = a.item_start[k + 1] - first;
+  const int64_t end = a.cfg[k].start + a.cfg[k].n;
+  const int64_t c0 = a.cfg[k].start + (int64_t)(item - first) * kChunk;
+  const int64_t c1 = c0 + kChunk < end ? c0 + kChunk : end;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int64_t a0 = cfg[k].start, a1 = cfg[k].start + cfg[k].n;
-  for (int f0 = wave * U; f0 < m; f0 += kWaves * U) {
-    const T* row[U];
-    double s[U];
+  for (int r0 = wave * kRowU; r0 < a.n_rows; r0 += kRowWaves * kRowU) {
+    const T* row[kRowU];
+    double s[kRowU];
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      row[u] = B + (size_t)perm[f0 + u < m ? f0 + u : f0] * b_stride;
+    for (int u = 0; u < kRowU; ++u) {
+      row[u] = row_ptr<T>(a, r0 + u < a.n_rows ? r0 + u : r0);
       s[u] = 0.0;
     }
-    for (int64_t i = a0 + lane; i < a1; i += 64)
+    for (int64_t i = c0 + lane; i < c1; i += 64) {
+      double v[kRowU];
 #pragma unroll
-      for (int u = 0; u < U; ++u) s[u] += (double)row[u][i];
+      for (int u = 0; u < kRowU; ++u) v[u] = (double)row[u][i];
 #pragma unroll
-    for (int u = 0; u < U; ++u)
+      for (int u = 0; u < kRowU; ++u) s[u] += v[u];
+      if (r0 == 0 && a.site_out) a.site_out[i] = v[0];
+    }
+#pragma unroll
+    for (int u = 0; u < kRowU; ++u)
       for (int o = 32; o > 0; o >>= 1) s[u] += __shfl_xor(s[u], o, 64);
     if (lane == 0)
 #pragma unroll
-      for (int u = 0; u < U; ++u)
-        if (f0 + u < m) b[(size_t)k * m + f0 + u] = s[u];
+      for (int u = 0; u < kRowU; ++u) {
+        if (r0 + u >= a.n_rows) break;
+        if (items == 1)
+          row_out(a, k, r0 + u, s[u]);
+        else
+          a.partial[(size_t)item * a.n_rows + r0 + u] = s[u];
+      }
   }
+}
+
+// Configurations of several chunks: one thread per (configuration, row)
+// adds the chunk partials in chunk order.
+__global__ void __launch_bounds__(kBlock) rows_finish_kernel(RowSums a) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)a.n_cfg * a.n_rows) return;
+  const int k = (int)(t / a.n_rows), r = (int)(t - (int64_t)k * a.n_rows);
+  const int i0 = a.item_start[k], i1 = a.item_start[k + 1];
+  if (i1 - i0 <= 1) return;
+  double v = 0.0;
+  for (int it = i0; it < i1 && it < a.max_items; ++it) v += a.partial[(size_t)it * a.n_rows + r];
+  row_out(a, k, r, v);
 }
 
 }  // namespace
@@ -175,32 +202,53 @@ hipError_t gather_forces(int fp64, int64_t n_atoms, int stride, const int32_t* c
   return hipGetLastError();
 }
 
+int reduce_max_items(int n_cfg, int64_t n_atoms) {
+  return (int)((n_atoms + kChunk - 1) / kChunk) + n_cfg;
+}
+
+int reduce_rows(int has_virial, int m, bool b) { return 1 + (has_virial ? 9 : 0) + (b ? m : 0); }
+
+hipError_t reduce_items(int n_cfg, const CfgInfo* cfg, int max_items, int32_t* item_start, int32_t* item_cfg,
+                        hipStream_t s) {
+  if (n_cfg == 0) return hipSuccess;
+  hipLaunchKernelGGL(chunk_items_kernel, dim3(1), dim3(1024), 0, s, n_cfg, cfg, max_items, item_start, item_cfg);
+  return hipGetLastError();
+}
+
 hipError_t reduce_configs(int fp64, int n_cfg, const CfgInfo* offs, int stride, const void* site,
                           const void* atom_virial, const void* B, int m, int b_stride,
                           const int32_t* perm, double* energy, double* virial, double* b,
-                          double* site_out, hipStream_t s) {
+                          double* site_out, const ReduceItems& it, hipStream_t s) {
   if (n_cfg == 0) return hipSuccess;
-  if (energy || virial || site_out) {
-    if (fp64) {
-      hipLaunchKernelGGL(config_kernel<double>, dim3(n_cfg), dim3(kBlock), 0, s, n_cfg, offs, stride,
-                         (const double*)site, (const double*)atom_virial, energy, virial, site_out);
-      hipLaunchKernelGGL(config_large_kernel<double>, dim3(n_cfg), dim3(kBlock), 0, s, n_cfg, offs, stride,
-                         (const double*)site, (const double*)atom_virial, energy, virial, site_out);
-    } else {
-      hipLaunchKernelGGL(config_kernel<float>, dim3(n_cfg), dim3(kBlock), 0, s, n_cfg, offs, stride,
-                         (const float*)site, (const float*)atom_virial, energy, virial, site_out);
-      hipLaunchKernelGGL(config_large_kernel<float>, dim3(n_cfg), dim3(kBlock), 0, s, n_cfg, offs, stride,
-                         (const float*)site, (const float*)atom_virial, energy, virial, site_out);
-    }
-  }
-  if (b && B) {
-    if (fp64)
-      hipLaunchKernelGGL(b_kernel<double>, dim3(n_cfg), dim3(kBlock), 0, s, n_cfg, offs,
-                         (const double*)B, m, b_stride, perm, b);
-    else
-      hipLaunchKernelGGL(b_kernel<float>, dim3(n_cfg), dim3(kBlock), 0, s, n_cfg, offs,
-                         (const float*)B, m, b_stride, perm, b);
-  }
+  const bool want_b = b && B;
+  const bool has_v = virial && atom_virial;
+  if (!energy && !has_v && !site_out && !want_b) return hipSuccess;
+  RowSums a;
+  a.n_cfg = n_cfg;
+  a.stride = stride;
+  a.has_v = has_v ? 1 : 0;
+  a.m = m;
+  a.n_rows = reduce_rows(a.has_v, m, want_b);
+  a.b_stride = b_stride;
+  a.max_items = it.max_items;
+  a.cfg = offs;
+  a.site = site;
+  a.wv = atom_virial;
+  a.B = B;
+  a.perm = perm;
+  a.item_start = it.item_start;
+  a.item_cfg = it.item_cfg;
+  a.partial = it.partial;
+  a.energy = energy;
+  a.virial = has_v ? virial : nullptr;
+  a.b = want_b ? b : nullptr;
+  a.site_out = site_out;
+  if (fp64)
+    hipLaunchKernelGGL(rows_kernel<double>, dim3(it.max_items), dim3(kBlock), 0, s, a);
+  else
+    hipLaunchKernelGGL(rows_kernel<float>, dim3(it.max_items), dim3(kBlock), 0, s, a);
+  const int64_t fin = (int64_t)n_cfg * a.n_rows;
+  hipLaunchKernelGGL(rows_finish_kernel, dim3((unsigned)((fin + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, a);
   return hipGetLastError();
 }
 
