@@ -506,8 +506,10 @@ def _adjoint_launches(tags_nus, split):
     """Launch lines of the adjoint passes [(tag, degrees)]: a preamble that
     finds the last pass the caller needs (nu_need, a bit mask of degrees: the
     later passes would only add zeros) and the degrees nu_run of the passes
-    that run, then the launches, the last one that runs as the final pass
-    (it sums the per-atom virial and own force)."""
+    that run, then the launches.  The final pass of the split sums the
+    per-atom virial and own force itself; when an earlier pass is the last
+    that runs, those sums follow as a kernel of their own (in the earlier
+    passes they would spill)."""
     n = len(tags_nus)
     pre = [f"constexpr unsigned kAdjNu[{n}] = {{ {', '.join(f'{_nu_bits(nus)}u' for _, nus in tags_nus)} }};",
            f"int last_adj = {n - 1};",
@@ -519,11 +521,14 @@ def _adjoint_launches(tags_nus, split):
     adj = []
     for k, (tag, _) in enumerate(tags_nus):
         first = "true" if k == 0 else "false"
-        adj.append(f"if (last_adj == {k}) hipLaunchKernelGGL((adjoint_{tag}_kernel<T, {first}, true, NQ>), "
-                   f"{grid}, dim3(BLOCK), smem, s, args);")
-        if k < n - 1:
-            adj.append(f"else if (last_adj > {k}) hipLaunchKernelGGL((adjoint_{tag}_kernel<T, {first}, false, NQ>), "
+        if k == n - 1:
+            adj.append(f"if (last_adj == {k}) hipLaunchKernelGGL((adjoint_{tag}_kernel<T, {first}, true, NQ>), "
                        f"{grid}, dim3(BLOCK), smem, s, args);")
+        else:
+            adj.append(f"if (last_adj >= {k}) hipLaunchKernelGGL((adjoint_{tag}_kernel<T, {first}, false, NQ>), "
+                       f"{grid}, dim3(BLOCK), smem, s, args);")
+            adj.append(f"if (last_adj == {k}) hipLaunchKernelGGL((mtp::adjoint_sums_kernel<T>), "
+                       "dim3((args.n_atoms + 255) / 256), dim3(256), 0, s, args);")
     return pre, adj
 
 

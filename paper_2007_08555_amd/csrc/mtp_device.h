@@ -250,4 +250,39 @@ __device__ __forceinline__ void two_sum_acc(T& hi, T& lo, T v) {
   lo += err;
 }
 
+namespace {
+
+// The per-atom sums of the final adjoint pass — the per-atom virial
+// sum_p g_p (x) r_p and the atom's own force share sum_p g_p in FP64 — as a
+// kernel of their own, one thread per atom over its pairs in slot order, for
+// launches whose last pass is an earlier pass of a split (the later passes
+// skipped by a degree mask): folding the twelve sums into that pass would
+// make it spill.
+template <typename T>
+__global__ void __launch_bounds__(256) adjoint_sums_kernel(const EvalArgs<T> args) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= args.n_atoms) return;
+  const int cnt = args.nbr_count[i];
+  double o0 = 0.0, o1 = 0.0, o2 = 0.0;
+  T w0 = T(0), w1 = T(0), w2 = T(0), w3 = T(0), w4 = T(0), w5 = T(0), w6 = T(0), w7 = T(0), w8 = T(0);
+#pragma unroll 4
+  for (int p = 0; p < cnt; ++p) {
+    const size_t e = (size_t)p * args.stride + i;
+    const PairRec<T> q = args.pr[e];
+    const T tx = args.g[3 * e], ty = args.g[3 * e + 1], tz = args.g[3 * e + 2];
+    w0 += tx * q.x; w1 += tx * q.y; w2 += tx * q.z;
+    w3 += ty * q.x; w4 += ty * q.y; w5 += ty * q.z;
+    w6 += tz * q.x; w7 += tz * q.y; w8 += tz * q.z;
+    o0 += (double)tx; o1 += (double)ty; o2 += (double)tz;
+  }
+  T* wv = args.atom_virial + i;
+  const size_t st = args.stride;
+  wv[0] = w0; wv[st] = w1; wv[2 * st] = w2; wv[3 * st] = w3; wv[4 * st] = w4;
+  wv[5 * st] = w5; wv[6 * st] = w6; wv[7 * st] = w7; wv[8 * st] = w8;
+  double* ow = args.own + i;
+  ow[0] = o0; ow[st] = o1; ow[2 * st] = o2;
+}
+
+}  // namespace
+
 }  // namespace mtp
