@@ -19,7 +19,20 @@ constexpr int kBlock = 256;
 // pairs' g is fetched here, subtracted in FP64 in slot order.  Pairs are
 // taken eight at a time so that the eight dependent loads g[rev[e]] are in
 // flight together.  (The per-atom virials are summed by the last adjoint
-// pass as well.)
+// pass as well.)  The reverse pairs of a configuration's atoms lie in the
+// records of that configuration, so consecutive blocks of atoms share cache
+// lines: workgroups are dispatched to the eight XCDs in turn, each with its
+// own L2, and block b takes the atom block xcd_block(b), which keeps runs of
+// consecutive atom blocks on one XCD.
+// Atom block of workgroup b when workgroups go to XCD b % 8 in turn: XCD x
+// takes the contiguous run of q + (x < r) blocks starting at x q + min(x, r)
+// (q = n / 8, r = n % 8): a bijection of [0, n).
+constexpr int kXcds = 8;
+__device__ inline int64_t xcd_block(int64_t b, int64_t n) {
+  const int64_t x = b % kXcds, q = n / kXcds, r = n % kXcds;
+  return x * q + (x < r ? x : r) + b / kXcds;
+}
+
 template <typename T>
 __global__ void __launch_bounds__(kBlock) gather_kernel(int64_t n_atoms, int stride,
                                                         const int32_t* __restrict__ count,
@@ -27,7 +40,7 @@ __global__ void __launch_bounds__(kBlock) gather_kernel(int64_t n_atoms, int str
                                                         const T* __restrict__ g, const double* __restrict__ own,
                                                         double* __restrict__ F) {
   constexpr int U = 8;
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t i = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (i >= n_atoms) return;
   double fx = own[i], fy = own[stride + i], fz = own[2 * (size_t)stride + i];
   const int c = count[i];
