@@ -514,14 +514,14 @@ int run_eval(mtp_model* M, const mtp_batch* bt, const mtp_out* out, int precisio
     } else if (use_skin) {
       // lists out to R_cut + skin; records of pairs beyond R_cut made neutral
       a.rcut = M->rcut + M->skin;
-      HIP_TRY(nbr_build(a, s), "neighbour search");
+      HIP_TRY(nbr_build(a, s, M->side, M->fork, M->join), "neighbour search");
       HIP_TRY(pair_images(a, M->img.as<short4>(), s), "pair images");
       a.rcut = M->rcut;
       HIP_TRY(refresh_pairs(a, M->img.as<short4>(), s), "pair refresh");
       HIP_TRY(hipMemcpyAsync(M->xbuild.p, bt->pos, sizeof(double) * 3 * (size_t)N, hipMemcpyDeviceToDevice, s),
               "hipMemcpyAsync");
     } else {
-      HIP_TRY(nbr_build(a, s), "neighbour search");
+      HIP_TRY(nbr_build(a, s, M->side, M->fork, M->join), "neighbour search");
     }
     HIP_TRY(mark(1), "hipEventRecord");
     // work items of the per-configuration sums (they need only the

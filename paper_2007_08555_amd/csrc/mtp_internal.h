@@ -60,7 +60,10 @@ struct NbrArgs {
 
 // Neighbour search without host synchronisation: prepare configs and bins,
 // fill the ELL lists up to K slots (counting overflow), reverse indices.
-hipError_t nbr_build(NbrArgs& a, hipStream_t s);
+// Under graph capture the large configurations' searches run on `side`
+// (forked from and joined back to s with the two events); the results are
+// complete in s order either way.
+hipError_t nbr_build(NbrArgs& a, hipStream_t s, hipStream_t side, hipEvent_t fork, hipEvent_t join);
 
 // Verlet skin (lists built with R_cut + skin and reused while every atom
 // stays within skin / 2 of its position at the build).

@@ -1247,32 +1247,55 @@ hipError_t refresh_pairs(const NbrArgs& a, const short4* img, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t nbr_build(NbrArgs& a, hipStream_t s) {
+hipError_t nbr_build(NbrArgs& a, hipStream_t s, hipStream_t side, hipEvent_t fork, hipEvent_t join) {
   if (a.n_cfg > 0)
     hipLaunchKernelGGL(cfg_prepare_kernel, grid_for(a.n_cfg), dim3(kBlock), 0, s, a);
   if (a.n_atoms == 0) return hipGetLastError();
   hipLaunchKernelGGL(atom_cfg_kernel, grid_for(a.n_atoms), dim3(kBlock), 0, s, a);
   // every atom's count is written by this call (atoms of an invalid range keep 0)
   hipLaunchKernelGGL(zero_kernel, grid_for(a.n_atoms), dim3(kBlock), 0, s, a.count, a.n_atoms);
-  hipLaunchKernelGGL(zero_kernel, grid_for(a.n_atoms + 1), dim3(kBlock), 0, s, a.bin_count, a.n_atoms + 1);
-  hipLaunchKernelGGL(bin_count_kernel, grid_for(a.n_atoms), dim3(kBlock), 0, s, a);
-  if (a.n_cfg > 0) hipLaunchKernelGGL(bin_scan_kernel, dim3(a.n_cfg), dim3(256), 0, s, a);
-  hipLaunchKernelGGL(bin_fill_kernel, grid_for(a.n_atoms), dim3(kBlock), 0, s, a);
-  hipLaunchKernelGGL(bin_sort_kernel, grid_for(a.n_atoms), dim3(kBlock), 0, s, a);
   const int lds_lists = a.K <= kLdsSlots ? 1 : 0;
   const size_t lds = lds_lists ? (size_t)kSmallMax * (a.K + 4) : 0;
+  // The searches of small and of large configurations write the rows of
+  // disjoint atoms: under graph capture the large ones (bins, cell-list and
+  // direct searches, and with LDS lists their reverse indices) form a branch
+  // on the side stream beside the small-configuration search, joined back
+  // before returning.  Launched eagerly they stay on s: there the two
+  // cross-stream waits cost more (about 30 us) than the overlap saves.
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  hipError_t e = hipStreamIsCapturing(s, &cap);
+  if (e != hipSuccess) return e;
+  const bool branch = cap == hipStreamCaptureStatusActive;
+  if (!branch) side = s;
+  if (branch) {
+    e = hipEventRecord(fork, s);
+    if (e == hipSuccess) e = hipStreamWaitEvent(side, fork, 0);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(zero_kernel, grid_for(a.n_atoms + 1), dim3(kBlock), 0, side, a.bin_count, a.n_atoms + 1);
+  hipLaunchKernelGGL(bin_count_kernel, grid_for(a.n_atoms), dim3(kBlock), 0, side, a);
+  if (a.n_cfg > 0) hipLaunchKernelGGL(bin_scan_kernel, dim3(a.n_cfg), dim3(256), 0, side, a);
+  hipLaunchKernelGGL(bin_fill_kernel, grid_for(a.n_atoms), dim3(kBlock), 0, side, a);
+  hipLaunchKernelGGL(bin_sort_kernel, grid_for(a.n_atoms), dim3(kBlock), 0, side, a);
+  hipLaunchKernelGGL(search_kernel, grid_for(a.n_atoms), dim3(kBlock), 0, side, a);
+  hipLaunchKernelGGL(search_binned_kernel, dim3(kBinnedBlocks), dim3(kBinnedBlock), 0, side, a);
+  const dim3 g((unsigned)((a.n_atoms + kBlock - 1) / kBlock), (unsigned)a.K);
+  if (lds_lists)
+    hipLaunchKernelGGL(reverse_large_kernel, dim3(g.x < kReverseBlocks ? g.x : kReverseBlocks, g.y), dim3(kBlock), 0,
+                       side, a);
+  e = hipGetLastError();
+  if (e == hipSuccess && branch) e = hipEventRecord(join, side);
+  if (e != hipSuccess) return e;
   if (a.n_cfg > 0) {
     hipLaunchKernelGGL(cfg_order_kernel, dim3(1), dim3(1024), 0, s, a);
     hipLaunchKernelGGL(search_small_kernel, dim3(a.n_cfg), dim3(kSmallBlock), lds, s, a, lds_lists);
   }
-  hipLaunchKernelGGL(search_kernel, grid_for(a.n_atoms), dim3(kBlock), 0, s, a);
-  hipLaunchKernelGGL(search_binned_kernel, dim3(kBinnedBlocks), dim3(kBinnedBlock), 0, s, a);
-  const dim3 g((unsigned)((a.n_atoms + kBlock - 1) / kBlock), (unsigned)a.K);
-  if (lds_lists)
-    hipLaunchKernelGGL(reverse_large_kernel, dim3(g.x < kReverseBlocks ? g.x : kReverseBlocks, g.y), dim3(kBlock), 0,
-                       s, a);
-  else
-    hipLaunchKernelGGL(reverse_kernel, g, dim3(kBlock), 0, s, a, lds_lists);
+  if (branch) {
+    e = hipStreamWaitEvent(s, join, 0);
+    if (e != hipSuccess) return e;
+  }
+  // without LDS lists every list's reverse indices come after both searches
+  if (!lds_lists) hipLaunchKernelGGL(reverse_kernel, g, dim3(kBlock), 0, s, a, lds_lists);
   return hipGetLastError();
 }
 
