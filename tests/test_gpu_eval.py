@@ -197,6 +197,32 @@ def test_every_search_path_in_one_batch(potentials):
     _check("lev12_s2", b, "fp64", potentials, TOL64, "search paths")
 
 
+def test_configuration_sums_over_chunks(potentials):
+    """Per-configuration sums are taken over chunks of 1024 atoms, chunk
+    partials added in chunk order: for every configuration above one chunk,
+    E equals the exactly rounded sum of its site energies to 1e-13 relative,
+    and energy, virial and b equal those of the configuration evaluated on
+    its own, bit for bit (the order depends only on its size), in two calls."""
+    import math
+    b = _every_search_path()
+    P, _ = potentials("lev12_s2")
+    g = [gpu_batch(P, b, "fp64") for _ in range(2)]
+    for key in ("energy", "virial", "b", "forces"):
+        np.testing.assert_array_equal(g[0][key], g[1][key])
+    off = b["atom_offsets"]
+    big = [k for k in range(len(b["n_atoms"])) if b["n_atoms"][k] > 1024]
+    assert big
+    for k in big:
+        site = g[0]["site"][off[k]:off[k + 1]]
+        exact = math.fsum(site)
+        assert abs(g[0]["energy"][k] - exact) <= 1e-13 * max(abs(exact), np.abs(site).sum())
+        one = gpu_batch(P, synth._batch([synth.config_of(b, k)]), "fp64")
+        assert one["energy"][0] == g[0]["energy"][k]
+        np.testing.assert_array_equal(one["virial"][0], g[0]["virial"][k])
+        np.testing.assert_array_equal(one["b"][0], g[0]["b"][k])
+    log(f"[chunked sums] {len(big)} configurations above 1024 atoms (largest {int(b['n_atoms'].max())})")
+
+
 def _bundle_boundaries():
     """Clusters and periodic cells of every size at the small search's
     wavefront boundaries (1..4 wavefronts of 64 atoms), empty configurations

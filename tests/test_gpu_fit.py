@@ -127,6 +127,25 @@ def test_accumulation_over_batches():
     assert eH <= 1e-13 and eg <= 1e-13 and ey <= 1e-13
 
 
+def test_normal_equations_are_bitwise_repeatable():
+    """The columns of J run on three streams at once, each with its own
+    buffers; H, g and yy do not depend on how they interleave: two calls
+    agree bit for bit."""
+    from paper_2007_08555_amd import Batch, Potential
+    batch = synth.mixed_batch(seed=34, n_configs=24, n_min=8, n_max=300, n_species_model=3)
+    rng = np.random.default_rng(9)   # arbitrary targets: only repeatability is checked
+    K, N = len(batch["n_atoms"]), int(batch["n_atoms"].sum())
+    tg = {"energy": rng.normal(0, 1, K), "forces": rng.normal(0, 1, (N, 3)), "virial": rng.normal(0, 1, (K, 9))}
+    P = Potential(pot_path("lev16_s3"))
+    B = Batch.from_arrays(batch)
+    runs = [[x.cpu().numpy() for x in P.normal_equations(B, tg["energy"], tg["forces"], tg["virial"])]
+            for _ in range(3)]
+    assert np.abs(runs[0][0]).max() > 0
+    for r in runs[1:]:
+        for a, c in zip(runs[0], r):
+            np.testing.assert_array_equal(a, c)
+
+
 def test_fp32_jacobian():
     from paper_2007_08555_amd import Potential
     pot = read_potential(pot_path("lev12_s2"))
