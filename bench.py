@@ -435,6 +435,9 @@ def main():
                     help="FP64 schedule of the evaluation kernels (default: the autotuner's choice)")
     ap.add_argument("--batch-cache", default="",
                     help="npz file holding the generated batch (written if missing, read if present)")
+    ap.add_argument("--study", type=int, default=0,
+                    help="only the 256 000-atom alloy precision study at this level (16, 20 or 24), "
+                         "printed as one JSON line (for profiling that workload alone)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one plain device copy of this size first (reference for HBM counters)")
     a = ap.parse_args()
@@ -450,6 +453,11 @@ def main():
 
     import synth
     from paper_2007_08555_amd import Batch, Potential
+
+    if a.study:
+        print(json.dumps({"precision_study": precision_study(torch.cuda.current_stream(), level=a.study)}),
+              flush=True)
+        return
 
     pot_path = os.path.join(ROOT, "tests", "golden", "potentials", "lev16_s3.mtp")
     t0 = time.time()
