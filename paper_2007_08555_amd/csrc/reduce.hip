@@ -14,6 +14,15 @@ namespace {
 
 constexpr int kBlock = 256;
 
+// Atom block of workgroup b when workgroups go to XCD b % 8 in turn: XCD x
+// takes the contiguous run of q + (x < r) blocks starting at x q + min(x, r)
+// (q = n / 8, r = n % 8): a bijection of [0, n).
+constexpr int kXcds = 8;
+__device__ inline int64_t xcd_block(int64_t b, int64_t n) {
+  const int64_t x = b % kXcds, q = n / kXcds, r = n % kXcds;
+  return x * q + (x < r ? x : r) + b / kXcds;
+}
+
 // Forces F_i = sum over slots p of (g_p - g_rev(p)): the first sum was taken
 // in FP64 by the last adjoint pass (own, [3][stride]), so only the reverse
 // pairs' g is fetched here, subtracted in FP64 in slot order.  Pairs are
@@ -24,15 +33,6 @@ constexpr int kBlock = 256;
 // lines: workgroups are dispatched to the eight XCDs in turn, each with its
 // own L2, and block b takes the atom block xcd_block(b), which keeps runs of
 // consecutive atom blocks on one XCD.
-// Atom block of workgroup b when workgroups go to XCD b % 8 in turn: XCD x
-// takes the contiguous run of q + (x < r) blocks starting at x q + min(x, r)
-// (q = n / 8, r = n % 8): a bijection of [0, n).
-constexpr int kXcds = 8;
-__device__ inline int64_t xcd_block(int64_t b, int64_t n) {
-  const int64_t x = b % kXcds, q = n / kXcds, r = n % kXcds;
-  return x * q + (x < r ? x : r) + b / kXcds;
-}
-
 template <typename T>
 __global__ void __launch_bounds__(kBlock) gather_kernel(int64_t n_atoms, int stride,
                                                         const int32_t* __restrict__ count,
@@ -71,7 +71,7 @@ __global__ void __launch_bounds__(kBlock) gather_kernel(int64_t n_atoms, int str
 // Per-configuration sums (site energies -> E_k, per-atom virials -> W_k,
 // basis values -> b_k) as segmented row sums.  Every configuration is cut
 // into chunks of kChunk atoms from its first atom; each chunk is one work
-// item (one workgroup).  A workgroup's wavefronts take U rows at a time, the
+// item (one workgroup).  A workgroup's wavefronts take kRowU rows at a time, the
 // lanes every 64th atom of the chunk, and the 64 partial sums are combined by
 // a butterfly; a configuration of one chunk writes its sums directly, a
 // larger one writes a partial per chunk that rows_finish_kernel adds in chunk
