@@ -1655,7 +1655,7 @@ const int kFuncFactors[] = {{ {func_factors} }};
 extern const mtp::BasisVariant {ns}_variant = {{
   "{ns}", {level}, {n_moments}, {ns}::kMoments, {ngraphs}, {ns}::kGraphKeyOffsets, {ns}::kGraphKeys,
   {m}, {ns}::kFuncOffsets, {ns}::kFuncFactors, {C}, {n_mu}, {nu_max},
-  {flops_pair_fwd}, {flops_pair_bwd}, {flops_atom}, {ns}::launch, {loss_ptr}, {ns}::BLOCK, 1 }};
+  {flops_pair_fwd}, {flops_pair_bwd}, {flops_atom}, {ns}::launch, {loss_ptr}, {ns}::BLOCK, 1, {partial_rows} }};
 #endif
 #endif  // part 0
 """
@@ -1664,6 +1664,8 @@ extern const mtp::BasisVariant {ns}_variant = {{
 SCHEDULE_TABLE = {"f64": {"mom": 85, "adj": 90}, "f32": {"mom": 120, "adj": 120}}
 # the loss gradient is compiled for table-driven levels up to this one
 TABLE_LOSS_MAX_LEVEL = 20
+# wavefronts sharing a workgroup's 64 atoms in the split table kernels
+TABLE_WAVES = 4
 
 
 def _moments_launch(tag, split):
@@ -1707,21 +1709,47 @@ def generate_table(lev_max):
     nodes, coefs, roots = build_tries(s)
     depth = max(roots)
     qmax = max(len(f) for f in s.funcs)
+    # each root's share (wavefront) in the split kernels: largest tries first,
+    # each to the wavefront with the fewest nodes so far
+    def trie_size(r0, r1, level, depth_):
+        n = r1 - r0
+        if level < depth_:
+            for t in range(r0, r1):
+                n += trie_size(nodes[t][1], nodes[t][2], level + 1, depth_)
+        return n
+    sizes = {g: trie_size(r0, r1, 1, d) for d, lst in roots.items() for g, r0, r1 in lst}
+    load, share = [0] * TABLE_WAVES, {}
+    for g in sorted(sizes, key=lambda g: (-sizes[g], g)):
+        w = min(range(TABLE_WAVES), key=lambda t: (load[t], t))
+        share[g] = w
+        load[w] += sizes[g]
     root_list, root_begin = [], [0, 0]
     for d in range(1, depth + 1):
         for g, r0, r1 in roots.get(d, []):
-            root_list += [g, r0, r1, 0]
+            root_list += [g, r0, r1, share[g]]
         root_begin.append(len(root_list) // 4)
     parts = {}
     for prec in ("f64", "f32"):
         src, mom, adj = _pair_pass_kernels(s, prec, 0, SCHEDULE_TABLE[prec])
+        W = TABLE_WAVES
+        split_grid = "dim3((args.n_atoms + 63) / 64), dim3(64 * " + str(W) + ")"
         launch = (["if (!reuse_moments) {"] + ["  " + l for l in mom] + ["}"] +
                   ["if (moments_only) return hipGetLastError();",
+                   "// the graphs of a workgroup's atoms shared out among wavefronts (with the",
+                   "// partial rows at hand), except for degree-masked calls (xi = e_alpha: few",
+                   "// graphs, where summing the shares would cost more than it spreads)",
+                   "const bool split = args.Gpart && !(flags & mtp::kEvalNuMask);",
                    "if (args.M32) {   // mixed precision: FP32 moments",
-                   "  if constexpr (std::is_same<T, double>::value)",
-                   "    hipLaunchKernelGGL((mtp::contract_table_kernel<T, WANT_B, Tab, true>), grid, dim3(BLOCK), 0, s, args);",
-                   "  else",
+                   "  if constexpr (std::is_same<T, double>::value) {",
+                   "    if (split)",
+                   f"      hipLaunchKernelGGL((mtp::contract_table_split_kernel<T, WANT_B, Tab, true, {W}>), {split_grid}, 0, s, args);",
+                   "    else",
+                   "      hipLaunchKernelGGL((mtp::contract_table_kernel<T, WANT_B, Tab, true>), grid, dim3(BLOCK), 0, s, args);",
+                   "  } else {",
                    "    return hipErrorInvalidValue;",
+                   "  }",
+                   "} else if (split) {",
+                   f"  hipLaunchKernelGGL((mtp::contract_table_split_kernel<T, WANT_B, Tab, false, {W}>), {split_grid}, 0, s, args);",
                    "} else {",
                    "  hipLaunchKernelGGL((mtp::contract_table_kernel<T, WANT_B, Tab>), grid, dim3(BLOCK), 0, s, args);",
                    "}"] +
@@ -1733,7 +1761,11 @@ def generate_table(lev_max):
         old = "  hipLaunchKernelGGL((tangent_contract_kernel<T>), grid, dim3(BLOCK), 0, s, args, la);"
         assert old in loss_launch
         loss_launch = loss_launch.replace(
-            old, "  hipLaunchKernelGGL((mtp::contract_table_loss_kernel<T, Tab>), grid, dim3(BLOCK), 0, s, args, la);")
+            old, "  if (args.Gpart)\n"
+                 f"    hipLaunchKernelGGL((mtp::contract_table_loss_split_kernel<T, Tab, {TABLE_WAVES}>), "
+                 f"dim3((args.n_atoms + 63) / 64), dim3(64 * {TABLE_WAVES}), 0, s, args, la);\n"
+                 "  else\n"
+                 "    hipLaunchKernelGGL((mtp::contract_table_loss_kernel<T, Tab>), grid, dim3(BLOCK), 0, s, args, la);")
         creduce = CREDUCE_TEMPLATE.format()
         loss_entry = (f"hipError_t launch_loss(int precision, const void* a, const void* l, hipStream_t s) {{\n"
                       f"  return mtp_gen_{ns}::loss(precision, a, l, s);\n}}")
@@ -1765,6 +1797,9 @@ def generate_table(lev_max):
         kernels64=parts["f64"][0], kernels32=parts["f32"][0], launch64=parts["f64"][1], launch32=parts["f32"][1],
         loss_kernels=loss_src, creduce=creduce, launch_loss=loss_launch, launch_loss_entry=loss_entry,
         loss_ptr=loss_ptr,
+        # per atom: (TABLE_WAVES - 1) shares of C + 2 n_graphs rows (the loss kernel's need; the
+        # evaluation uses C + n_graphs of them)
+        partial_rows=(TABLE_WAVES - 1) * (s.C + 2 * len(s.keys)),
         moments=", ".join(f"{mu}, {nu}" for mu, nu in s.moments), n_moments=len(s.moments),
         graph_offsets=join(graph_offsets), graph_keys=join(graph_keys),
         func_offsets=join(func_offsets), func_factors=join(func_factors),

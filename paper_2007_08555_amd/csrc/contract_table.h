@@ -75,40 +75,48 @@ __device__ T trie_reverse(int a, int b, T P, const MLoad& mload, const GAdd& gad
   return s;
 }
 
-// Graph values of every graph with D vertices (roots listed per depth).
-// Graph values of every graph with D vertices (roots listed per depth) for
-// which need(g) holds.
-template <typename T, int D, typename Tab, typename MLoad, typename VStore, typename Need>
-__device__ __forceinline__ void graphs_forward(const MLoad& mload, const VStore& vstore, const Need& need) {
+// Graph values of every graph with D vertices (roots listed per depth) whose
+// root entry e (graph e.x, trie e.y .. e.z, workgroup share e.w) take(e)
+// accepts.
+template <typename T, int D, typename Tab, typename MLoad, typename VStore, typename Take>
+__device__ __forceinline__ void graphs_forward(const MLoad& mload, const VStore& vstore, const Take& take) {
   if constexpr (D <= Tab::kDepth) {
     for (int r = Tab::root_begin(D); r < Tab::root_begin(D + 1); ++r) {
       const int4 e = Tab::roots()[r];
-      if (need(e.x)) vstore(e.x, trie_value<T, 1, D, Tab>(e.y, e.z, mload));
+      if (take(e)) vstore(e.x, trie_value<T, 1, D, Tab>(e.y, e.z, mload));
     }
-    graphs_forward<T, D + 1, Tab>(mload, vstore, need);
+    graphs_forward<T, D + 1, Tab>(mload, vstore, take);
   }
 }
 
 template <typename T, int D, typename Tab, typename MLoad, typename VStore>
 __device__ __forceinline__ void graphs_forward(const MLoad& mload, const VStore& vstore) {
-  graphs_forward<T, D, Tab>(mload, vstore, [](int) { return true; });
+  graphs_forward<T, D, Tab>(mload, vstore, [](const int4&) { return true; });
 }
 
 // A graph whose dV/dg is exactly zero adds nothing and is skipped (for
-// xi = e_alpha, as in the normal equations, all but alpha's graphs).
-template <typename T, int D, typename Tab, typename MLoad, typename DgLoad, typename GAdd>
-__device__ __forceinline__ void graphs_reverse(const MLoad& mload, const DgLoad& dgload, const GAdd& gadd) {
+// xi = e_alpha, as in the normal equations, all but alpha's graphs); only
+// the roots take(e) accepts are walked.
+template <typename T, int D, typename Tab, typename MLoad, typename DgLoad, typename GAdd, typename Take>
+__device__ __forceinline__ void graphs_reverse(const MLoad& mload, const DgLoad& dgload, const GAdd& gadd,
+                                               const Take& take) {
   if constexpr (D <= Tab::kDepth) {
     for (int r = Tab::root_begin(D); r < Tab::root_begin(D + 1); ++r) {
       const int4 e = Tab::roots()[r];
+      if (!take(e)) continue;
       const T P = dgload(e.x);
       if constexpr (std::is_floating_point<T>::value) {
         if (P == T(0)) continue;
       }
       (void)trie_reverse<T, 1, D, Tab>(e.y, e.z, P, mload, gadd);
     }
-    graphs_reverse<T, D + 1, Tab>(mload, dgload, gadd);
+    graphs_reverse<T, D + 1, Tab>(mload, dgload, gadd, take);
   }
+}
+
+template <typename T, int D, typename Tab, typename MLoad, typename DgLoad, typename GAdd>
+__device__ __forceinline__ void graphs_reverse(const MLoad& mload, const DgLoad& dgload, const GAdd& gadd) {
+  graphs_reverse<T, D, Tab>(mload, dgload, gadd, [](const int4&) { return true; });
 }
 
 // Basis functions B_alpha = product of graph values (eq. MTPbasisLevel8 and
@@ -116,13 +124,14 @@ __device__ __forceinline__ void graphs_reverse(const MLoad& mload, const DgLoad&
 // the graphs' adjoints: for each function, prefix products times suffix
 // products give the product of the other factors.  bout(alpha, B) receives
 // every B when ALL_B; otherwise functions with xi_alpha exactly zero, which
-// add nothing, are skipped.
+// add nothing, are skipped.  Only the functions a0, a0 + a_step, ... are
+// formed (a share of a workgroup's wavefronts).
 template <typename T, typename Tab, bool ALL_B, typename XiLoad, typename VLoad, typename DgAdd, typename BOut>
 __device__ __forceinline__ T basis_products(const XiLoad& xiload, const VLoad& vload, const DgAdd& dgadd,
-                                            const BOut& bout) {
+                                            const BOut& bout, int a0 = 0, int a_step = 1) {
   constexpr int Q = Tab::kMaxFactors;
   T V = T(0);
-  for (int a = 0; a < Tab::kM; ++a) {
+  for (int a = a0; a < Tab::kM; a += a_step) {
     if constexpr (!ALL_B && std::is_floating_point<T>::value) {
       if (xiload(a) == T(0)) continue;
     }
@@ -203,7 +212,7 @@ __global__ void __launch_bounds__(64) contract_table_kernel(const EvalArgs<T> ar
     // are never read): for xi = e_alpha, as in the normal equations, alpha's
     const bool all = need_all;
     graphs_forward<T, 1, Tab>(mload, [&](int g, T v) { Dv[(size_t)g * st] = v; },
-                              [&](int g) { return all || ((need[g >> 5] >> (g & 31)) & 1u); });
+                              [&](const int4& e) { return all || ((need[e.x >> 5] >> (e.x & 31)) & 1u); });
   }
   for (int g = 0; g < Tab::kGraphs; ++g) Dg[(size_t)g * st] = T(0);
   const T V = basis_products<T, Tab, WANT_B>(
@@ -216,6 +225,102 @@ __global__ void __launch_bounds__(64) contract_table_kernel(const EvalArgs<T> ar
   for (int k = 0; k < Tab::kC; ++k) Gi[(size_t)k * st] = T(0);
   graphs_reverse<T, 1, Tab>(mload, [&](int g) { return Dg[(size_t)g * st]; },
                             [&](int k, T v) { Gi[(size_t)k * st] += v; });
+}
+
+// The same with the work of a workgroup's 64 atoms shared out among W
+// wavefronts that take the same atoms (lane l of every wavefront is atom
+// l): a batch of some ten thousand atoms gives one thread-per-atom wavefront
+// per SIMD or fewer, too few to cover the latencies of the walks' dependent
+// loads.  Root e goes to wavefront e.w % W (shares balanced by trie size
+// when the tables are generated), function a to wavefront a % W.  Each
+// wavefront writes the values of its graphs, adds the dV/dg of its
+// functions and the dV/dM of its graphs' reverse walks into rows of its own
+// (wavefront 0 into D and G, wavefront w > 0 into rows w - 1 of
+// args.Gpart: C rows for dV/dM, then n_graphs rows for dV/dg), and the
+// shares are added in wavefront order where they are read (bitwise
+// repeatable; a different order of the sums than the one-wavefront kernel).
+template <typename T, bool WANT_B, typename Tab, bool M32, int W>
+__global__ void __launch_bounds__(64 * W) contract_table_split_kernel(const EvalArgs<T> args) {
+  __shared__ uint32_t need[(Tab::kGraphs + 31) / 32];
+  __shared__ int n_zero;
+  __shared__ T vpart[W][64];
+  if constexpr (!WANT_B) {
+    for (int w = threadIdx.x; w < (Tab::kGraphs + 31) / 32; w += 64 * W) need[w] = 0u;
+    if (threadIdx.x == 0) n_zero = 0;
+    __syncthreads();
+    for (int a = threadIdx.x; a < Tab::kM; a += 64 * W)
+      if (args.xi[a] == T(0)) atomicAdd(&n_zero, 1);
+    __syncthreads();
+    if (n_zero > 0) {   // uniform over the workgroup
+      for (int a = threadIdx.x; a < Tab::kM; a += 64 * W)
+        if (args.xi[a] != T(0))
+          for (int t = Tab::func_off()[a]; t < Tab::func_off()[a + 1]; ++t) {
+            const int g = Tab::func_fac()[t];
+            atomicOr(&need[g >> 5], 1u << (g & 31));
+          }
+      __syncthreads();
+    }
+  }
+  const bool need_all = WANT_B || n_zero == 0;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int i = blockIdx.x * 64 + lane;
+  const bool active = i < args.n_atoms;
+  const size_t st = args.stride;
+  const size_t rows = (size_t)Tab::kC + Tab::kGraphs;   // partial rows per wavefront
+  const T* Mi = args.M + i;
+  const float* M32i = args.M32 + i;
+  T* Gi = args.G + i;
+  T* Dg = args.D + i;
+  T* Dv = args.D + (size_t)Tab::kGraphs * st + i;
+  T* Gw = wave == 0 ? Gi : args.Gpart + (size_t)(wave - 1) * rows * st + i;
+  T* Dw = wave == 0 ? Dg : args.Gpart + ((size_t)(wave - 1) * rows + Tab::kC) * st + i;
+  const auto mload = [&](int k) {
+    if constexpr (M32)
+      return static_cast<T>(M32i[(size_t)k * st]);
+    else
+      return Mi[(size_t)k * st];
+  };
+  const auto mine = [&](const int4& e) { return (e.w % W) == wave; };
+  if (active) {
+    for (int k = 0; k < Tab::kC; ++k) Gw[(size_t)k * st] = T(0);
+    for (int g = 0; g < Tab::kGraphs; ++g) Dw[(size_t)g * st] = T(0);
+    const bool all = need_all;
+    graphs_forward<T, 1, Tab>(mload, [&](int g, T v) { Dv[(size_t)g * st] = v; }, [&](const int4& e) {
+      return mine(e) && (all || ((need[e.x >> 5] >> (e.x & 31)) & 1u));
+    });
+  }
+  __syncthreads();   // every graph value written
+  T V = T(0);
+  if (active)
+    V = basis_products<T, Tab, WANT_B>(
+        [&](int a) { return args.xi[a]; }, [&](int g) { return Dv[(size_t)g * st]; },
+        [&](int g, T v) { Dw[(size_t)g * st] += v; },
+        [&](int a, T B) {
+          if (WANT_B) args.B[(size_t)a * args.b_stride + i] = B;
+        },
+        wave, W);
+  vpart[wave][lane] = V;
+  __syncthreads();   // every share of dV/dg and V written
+  if (active) {
+    if (wave == 0) {
+      T s = vpart[0][lane];
+      for (int w = 1; w < W; ++w) s += vpart[w][lane];
+      args.site[i] = s;
+    }
+    const auto dgload = [&](int g) {
+      T d = Dg[(size_t)g * st];
+      for (int w = 1; w < W; ++w) d += args.Gpart[((size_t)(w - 1) * rows + Tab::kC + g) * st + i];
+      return d;
+    };
+    graphs_reverse<T, 1, Tab>(mload, dgload, [&](int k, T v) { Gw[(size_t)k * st] += v; }, mine);
+  }
+  __syncthreads();   // every share of dV/dM written
+  if (active)
+    for (int k = wave; k < Tab::kC; k += W) {
+      T g = Gi[(size_t)k * st];
+      for (int w = 1; w < W; ++w) g += args.Gpart[((size_t)(w - 1) * rows + k) * st + i];
+      Gi[(size_t)k * st] = g;
+    }
 }
 
 // The same on dual numbers for the loss gradient: moments carry their
@@ -256,6 +361,72 @@ __global__ void __launch_bounds__(64) contract_table_loss_kernel(const EvalArgs<
   for (int k = 0; k < Tab::kC; ++k) dGi[(size_t)k * st] = R(0);
   graphs_reverse<T, 1, Tab>(mload, [&](int g) { return T(gd[(2 * ng + g) * st], gd[(3 * ng + g) * st]); },
                             [&](int k, T v) { dGi[(size_t)k * st] += v.d; });
+}
+
+// contract_table_loss_kernel with the work shared out among W wavefronts as
+// in contract_table_split_kernel: each wavefront's share of dV/dg and its
+// tangent, and of the tangent of G, in rows of its own (wavefront w > 0:
+// rows w - 1 of args.Gpart, C rows for dG, then 2 n_graphs rows for dV/dg
+// and its tangent), added in wavefront order where they are read.
+template <typename R, typename Tab, int W>
+__global__ void __launch_bounds__(64 * W) contract_table_loss_split_kernel(const EvalArgs<R> args,
+                                                                          const LossArgs<R> la) {
+  using T = Dual<R>;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int i = blockIdx.x * 64 + lane;
+  const bool active = i < args.n_atoms;
+  const size_t st = args.stride;
+  const size_t ng = Tab::kGraphs;
+  const size_t rows = (size_t)Tab::kC + 2 * ng;
+  const R* Mi = args.M + i;
+  const R* dMi = la.dM + i;
+  R* gd = la.gd + i;
+  R* dGi = la.dG + i;
+  R* dGw = wave == 0 ? dGi : args.Gpart + (size_t)(wave - 1) * rows * st + i;
+  // dV/dg and its tangent of this wavefront's functions
+  R* Dw = wave == 0 ? gd + 2 * ng * st : args.Gpart + ((size_t)(wave - 1) * rows + Tab::kC) * st + i;
+  const auto mload = [&](int k) { return T(Mi[(size_t)k * st], dMi[(size_t)k * st]); };
+  const auto mine = [&](const int4& e) { return (e.w % W) == wave; };
+  if (active) {
+    for (int k = 0; k < Tab::kC; ++k) dGw[(size_t)k * st] = R(0);
+    for (size_t g = 0; g < 2 * ng; ++g) Dw[g * st] = R(0);
+    graphs_forward<T, 1, Tab>(mload, [&](int g, T v) {
+      gd[(size_t)g * st] = v.v;
+      gd[(ng + g) * st] = v.d;
+    }, mine);
+  }
+  __syncthreads();   // every graph value and tangent written
+  if (active) {
+    const R aw = la.a_atom[i];
+    (void)basis_products<T, Tab, true>(
+        [&](int a) { return T(args.xi[a]); },
+        [&](int g) { return T(gd[(size_t)g * st], gd[(ng + g) * st]); },
+        [&](int g, T v) {
+          Dw[(size_t)g * st] += v.v;
+          Dw[(ng + g) * st] += v.d;
+        },
+        [&](int a, T B) { la.xi_terms[(size_t)a * st + i] = aw * B.v + B.d; }, wave, W);
+  }
+  __syncthreads();   // every share of dV/dg written
+  if (active) {
+    const auto dgload = [&](int g) {
+      R v = gd[(2 * ng + g) * st], d = gd[(3 * ng + g) * st];
+      for (int w = 1; w < W; ++w) {
+        const R* p = args.Gpart + ((size_t)(w - 1) * rows + Tab::kC) * st + i;
+        v += p[(size_t)g * st];
+        d += p[(ng + g) * st];
+      }
+      return T(v, d);
+    };
+    graphs_reverse<T, 1, Tab>(mload, dgload, [&](int k, T v) { dGw[(size_t)k * st] += v.d; }, mine);
+  }
+  __syncthreads();   // every share of dG written
+  if (active)
+    for (int k = wave; k < Tab::kC; k += W) {
+      R g = dGi[(size_t)k * st];
+      for (int w = 1; w < W; ++w) g += args.Gpart[((size_t)(w - 1) * rows + k) * st + i];
+      dGi[(size_t)k * st] = g;
+    }
 }
 
 }  // namespace mtp

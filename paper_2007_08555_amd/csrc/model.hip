@@ -102,7 +102,7 @@ struct mtp_model {
   Buffer ainv_theta, th_b;
   // workspace
   Buffer cfg, cfg_order, atom_cfg, atom_bin, bin_count, bin_start, bin_atoms, bin_fill, binned, large, nbins_dev;
-  Buffer count, nbr, pr, rev, gpair, own, Mbuf, Gbuf, Dbuf, site, wv, B, status, run_start;
+  Buffer count, nbr, pr, rev, gpair, own, Mbuf, Gbuf, Dbuf, Gpart, site, wv, B, status, run_start;
   Buffer item_start, item_cfg, red_part;   // work items and partials of the per-configuration sums
   int red_items = 0;                       // reduce_max_items of the last batch
   int K = 64;  // neighbour capacity per atom, grown on overflow
@@ -379,6 +379,7 @@ mtp::EvalArgs<T> make_args(mtp_model* M, int64_t n_atoms, int stride, const int3
   a.M = M->Mbuf.as<T>();
   a.G = M->Gbuf.as<T>();
   a.D = M->Dbuf.as<T>();
+  a.Gpart = M->var->partial_rows ? M->Gpart.as<T>() : nullptr;
   a.g = M->gpair.as<T>();
   a.atom_virial = M->wv.as<T>();
   a.own = M->own.as<double>();
@@ -445,6 +446,7 @@ int run_eval(mtp_model* M, const mtp_batch* bt, const mtp_out* out, int precisio
     NEED(M->Mbuf, tsz * (size_t)M->var->C * stride);
     // dV/dg per graph, then (table-driven bases) the graph values
     NEED(M->Dbuf, tsz * 2 * (size_t)M->var->n_graphs * stride);
+    if (M->var->partial_rows) NEED(M->Gpart, tsz * (size_t)M->var->partial_rows * stride);
     NEED(M->site, tsz * stride);
     NEED(M->wv, tsz * 9 * stride);
     if (want_b) NEED(M->B, tsz * (size_t)M->m * stride);
@@ -1273,12 +1275,14 @@ int mtp_normal_equations(mtp_model* M, const mtp_batch* bt, const double* E_t, c
         ea.xi = M->fit_eye.as<double>() + row;
         ea.G = (double*)G; ea.D = (double*)D; ea.g = (double*)gp; ea.site = (double*)site;
         ea.atom_virial = (double*)wv; ea.own = own;
+        ea.Gpart = nullptr;   // one wavefront per atom: the lanes share no partial rows
         HIP_TRY(M->var->launch_eval(precision, flags, M->schedule64, &ea, L.s), "evaluation kernels");
       } else {
         auto ea = make_args<float>(M, N, stride, bt->species, false);
         ea.xi = M->fit_eye.as<float>() + row;
         ea.G = (float*)G; ea.D = (float*)D; ea.g = (float*)gp; ea.site = (float*)site;
         ea.atom_virial = (float*)wv; ea.own = own;
+        ea.Gpart = nullptr;
         HIP_TRY(M->var->launch_eval(precision, flags, 0, &ea, L.s), "evaluation kernels");
       }
     }

@@ -55,6 +55,8 @@ struct EvalArgs {
   T* atom_virial;        // [9][stride]  sum_j g_a r_b
   double* own;          // [3][stride]  sum_j g_ij in FP64 (the atom's own share of its force)
   T* D;                  // [n_graphs][stride] dV_i / dg for every connected graph g
+  T* Gpart;              // [partial_rows][stride] shares of the table-driven contraction's
+                         // wavefronts (BasisVariant::partial_rows; null: one wavefront per atom)
   T* B;                  // [m][b_stride] optional basis values
   int b_stride;
 };

@@ -50,6 +50,8 @@ struct BasisVariant {
   hipError_t (*launch_loss)(int precision, const void* eval_args, const void* loss_args, hipStream_t stream);
   int block;                     // atoms per workgroup of the per-atom kernels
   int n_schedules;               // FP64 schedules compiled (pass splits)
+  int partial_rows;              // table-driven bases: rows per atom of args.Gpart for the
+                                 // wavefront-split contraction (0: none)
 };
 
 extern const BasisVariant* const kVariants[];

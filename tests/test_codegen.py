@@ -43,7 +43,8 @@ def test_table_level_launches(level):
     src, meta = codegen.generate_table(level)
     launched = set(re.findall(r"hipLaunchKernelGGL\(\((?:mtp::)?(\w+)<", src))
     defined = set(re.findall(r"(\w+_c?kernel)\(const mtp::EvalArgs", src))
-    defined |= {"contract_table_kernel", "contract_table_loss_kernel"}   # csrc/contract_table.h
+    defined |= {"contract_table_kernel", "contract_table_loss_kernel", "contract_table_split_kernel",
+                "contract_table_loss_split_kernel"}   # csrc/contract_table.h
     defined |= {"adjoint_sums_kernel"}   # csrc/mtp_device.h
     assert launched and launched <= defined, launched - defined
     assert meta["table"] and meta["loss"] and meta["trie_nodes"] > 0
