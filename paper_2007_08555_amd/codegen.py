@@ -1526,9 +1526,12 @@ constexpr int BLOCK = 64;
 __device__ __forceinline__ int clamp_species(int z, int S) {{ return z < 0 ? 0 : (z >= S ? S - 1 : z); }}
 
 #if MTP_PART >= 1
-// trie nodes (k, c0, c1, 0), leaf weights, roots (graph, r0, r1, 0) by depth,
-// basis functions as lists of graphs
+// trie nodes (k, c0, c1, slot), leaf weights, roots (graph, r0, r1, share) by
+// depth, basis functions as lists of graphs, and per graph the components of
+// its kSlots local slots (-1: unused); a node's slot is that of its k within
+// its graph, or -1 when k is not among the graph's kSlots most frequent
 __device__ const int kNode[] __attribute__((aligned(16))) = {{ {node_data} }};
+__device__ const int kSlotK[] = {{ {slot_data} }};
 __device__ const double kCoef[] = {{ {coef_data} }};
 __device__ const int kRoots[] __attribute__((aligned(16))) = {{ {root_data} }};
 __device__ const int kFOff[] = {{ {foff_data} }};
@@ -1540,7 +1543,9 @@ struct Tab {{
   static constexpr int kM = {m};
   static constexpr int kDepth = {depth};
   static constexpr int kMaxFactors = {qmax};
+  static constexpr int kSlots = {slots};
   __device__ static const int4* node() {{ return reinterpret_cast<const int4*>(kNode); }}
+  __device__ static const int* slot_k() {{ return kSlotK; }}
   __device__ static const double* coef() {{ return kCoef; }}
   __device__ static const int4* roots() {{ return reinterpret_cast<const int4*>(kRoots); }}
   __device__ static int root_begin(int d) {{
@@ -1666,6 +1671,8 @@ SCHEDULE_TABLE = {"f64": {"mom": 85, "adj": 90}, "f32": {"mom": 120, "adj": 120}
 TABLE_LOSS_MAX_LEVEL = 20
 # wavefronts sharing a workgroup's 64 atoms in the split table kernels
 TABLE_WAVES = 4
+# local LDS slots per graph for the split kernels' dV/dM shares
+TABLE_SLOTS = 24
 
 
 def _moments_launch(tag, split):
@@ -1718,6 +1725,28 @@ def generate_table(lev_max):
                 n += trie_size(nodes[t][1], nodes[t][2], level + 1, depth_)
         return n
     sizes = {g: trie_size(r0, r1, 1, d) for d, lst in roots.items() for g, r0, r1 in lst}
+    # local slots: per graph its TABLE_SLOTS most frequent components (the
+    # split kernels add their dV/dM shares in LDS, flushed once per graph)
+    node_slot = [-1] * len(nodes)
+    slot_k = [-1] * (TABLE_SLOTS * len(s.keys))
+    for d, lst in roots.items():
+        for g, r0, r1 in lst:
+            members, stack = [], [(r0, r1, 1)]
+            while stack:
+                a, b, level = stack.pop()
+                for t in range(a, b):
+                    members.append(t)
+                    if level < d:
+                        stack.append((nodes[t][1], nodes[t][2], level + 1))
+            freq = defaultdict(int)
+            for t in members:
+                freq[nodes[t][0]] += 1
+            top = sorted(freq, key=lambda k: (-freq[k], k))[:TABLE_SLOTS]
+            slot_of = {k: j for j, k in enumerate(top)}
+            for j, k in enumerate(top):
+                slot_k[g * TABLE_SLOTS + j] = k
+            for t in members:
+                node_slot[t] = slot_of.get(nodes[t][0], -1)
     load, share = [0] * TABLE_WAVES, {}
     for g in sorted(sizes, key=lambda g: (-sizes[g], g)):
         w = min(range(TABLE_WAVES), key=lambda t: (load[t], t))
@@ -1790,7 +1819,8 @@ def generate_table(lev_max):
     src = TABLE_TEMPLATE.format(
         level=lev_max, m=len(s.funcs), ngraphs=len(s.keys), C=s.C, n_mu=s.n_mu, nu_max=s.nu_max, ns=ns,
         nnodes=len(nodes), depth=depth, qmax=qmax,
-        node_data=join(v for nd in nodes for v in (nd[0], nd[1], nd[2], 0)),
+        node_data=join(v for t, nd in enumerate(nodes) for v in (nd[0], nd[1], nd[2], node_slot[t])),
+        slot_data=join(slot_k), slots=TABLE_SLOTS,
         coef_data=", ".join(repr(float(c)) for c in coefs),
         root_data=join(root_list), root_begin=join(root_begin),
         foff_data=join(func_offsets), ffac_data=join(func_factors),

@@ -75,6 +75,25 @@ __device__ T trie_reverse(int a, int b, T P, const MLoad& mload, const GAdd& gad
   return s;
 }
 
+// As trie_reverse, with gadd given the node record (k in .x, local slot in .w).
+template <typename T, int L, int D, typename Tab, typename MLoad, typename GAdd>
+__device__ T trie_reverse_nd(int a, int b, T P, const MLoad& mload, const GAdd& gadd) {
+  T s = T(0);
+  for (int n = a; n < b; ++n) {
+    const int4 nd = Tab::node()[n];
+    const T m = mload(nd.x);
+    T sub;
+    if constexpr (L == D) {
+      sub = from_coef<T>(Tab::coef()[nd.y]);
+    } else {
+      sub = trie_reverse_nd<T, L + 1, D, Tab>(nd.y, nd.z, P * m, mload, gadd);
+    }
+    gadd(nd, P * sub);
+    s += m * sub;
+  }
+  return s;
+}
+
 // Graph values of every graph with D vertices (roots listed per depth) whose
 // root entry e (graph e.x, trie e.y .. e.z, workgroup share e.w) take(e)
 // accepts.
@@ -117,6 +136,40 @@ __device__ __forceinline__ void graphs_reverse(const MLoad& mload, const DgLoad&
 template <typename T, int D, typename Tab, typename MLoad, typename DgLoad, typename GAdd>
 __device__ __forceinline__ void graphs_reverse(const MLoad& mload, const DgLoad& dgload, const GAdd& gadd) {
   graphs_reverse<T, D, Tab>(mload, dgload, gadd, [](const int4&) { return true; });
+}
+
+// graphs_reverse for the split kernels: the shares of each graph's kSlots
+// most frequent components are added into local slots (szero, sadd; an
+// atom's slots in LDS) and flushed into the atom's rows once per graph
+// (sflush(j, k)); the other components go to the rows directly (gadd).  In
+// the level-24 tries the slots take about 85 % of the reverse walk's adds.
+template <typename T, int D, typename Tab, typename MLoad, typename DgLoad, typename SZero, typename SAdd,
+          typename SFlush, typename GAdd, typename Take>
+__device__ __forceinline__ void graphs_reverse_slots(const MLoad& mload, const DgLoad& dgload, const SZero& szero,
+                                                     const SAdd& sadd, const SFlush& sflush, const GAdd& gadd,
+                                                     const Take& take) {
+  if constexpr (D <= Tab::kDepth) {
+    for (int r = Tab::root_begin(D); r < Tab::root_begin(D + 1); ++r) {
+      const int4 e = Tab::roots()[r];
+      if (!take(e)) continue;
+      const T P = dgload(e.x);
+      if constexpr (std::is_floating_point<T>::value) {
+        if (P == T(0)) continue;
+      }
+      for (int j = 0; j < Tab::kSlots; ++j) szero(j);
+      (void)trie_reverse_nd<T, 1, D, Tab>(e.y, e.z, P, mload, [&](const int4& nd, T v) {
+        if (nd.w >= 0)
+          sadd(nd.w, v);
+        else
+          gadd(nd.x, v);
+      });
+      for (int j = 0; j < Tab::kSlots; ++j) {
+        const int k = Tab::slot_k()[e.x * Tab::kSlots + j];
+        if (k >= 0) sflush(j, k);
+      }
+    }
+    graphs_reverse_slots<T, D + 1, Tab>(mload, dgload, szero, sadd, sflush, gadd, take);
+  }
 }
 
 // Basis functions B_alpha = product of graph values (eq. MTPbasisLevel8 and
@@ -239,11 +292,13 @@ __global__ void __launch_bounds__(64) contract_table_kernel(const EvalArgs<T> ar
 // args.Gpart: C rows for dV/dM, then n_graphs rows for dV/dg), and the
 // shares are added in wavefront order where they are read (bitwise
 // repeatable; a different order of the sums than the one-wavefront kernel).
+// The reverse walks add into per-graph LDS slots (graphs_reverse_slots).
 template <typename T, bool WANT_B, typename Tab, bool M32, int W>
 __global__ void __launch_bounds__(64 * W) contract_table_split_kernel(const EvalArgs<T> args) {
   __shared__ uint32_t need[(Tab::kGraphs + 31) / 32];
   __shared__ int n_zero;
   __shared__ T vpart[W][64];
+  __shared__ T gslot[W][Tab::kSlots][64];   // local dV/dM slots of each wavefront's graph
   if constexpr (!WANT_B) {
     for (int w = threadIdx.x; w < (Tab::kGraphs + 31) / 32; w += 64 * W) need[w] = 0u;
     if (threadIdx.x == 0) n_zero = 0;
@@ -312,7 +367,11 @@ __global__ void __launch_bounds__(64 * W) contract_table_split_kernel(const Eval
       for (int w = 1; w < W; ++w) d += args.Gpart[((size_t)(w - 1) * rows + Tab::kC + g) * st + i];
       return d;
     };
-    graphs_reverse<T, 1, Tab>(mload, dgload, [&](int k, T v) { Gw[(size_t)k * st] += v; }, mine);
+    graphs_reverse_slots<T, 1, Tab>(
+        mload, dgload, [&](int j) { gslot[wave][j][lane] = T(0); },
+        [&](int j, T v) { gslot[wave][j][lane] += v; },
+        [&](int j, int k) { Gw[(size_t)k * st] += gslot[wave][j][lane]; },
+        [&](int k, T v) { Gw[(size_t)k * st] += v; }, mine);
   }
   __syncthreads();   // every share of dV/dM written
   if (active)
@@ -372,6 +431,7 @@ template <typename R, typename Tab, int W>
 __global__ void __launch_bounds__(64 * W) contract_table_loss_split_kernel(const EvalArgs<R> args,
                                                                           const LossArgs<R> la) {
   using T = Dual<R>;
+  __shared__ R gslot[W][Tab::kSlots][64];   // local slots of the tangent of dV/dM
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int i = blockIdx.x * 64 + lane;
   const bool active = i < args.n_atoms;
@@ -418,7 +478,11 @@ __global__ void __launch_bounds__(64 * W) contract_table_loss_split_kernel(const
       }
       return T(v, d);
     };
-    graphs_reverse<T, 1, Tab>(mload, dgload, [&](int k, T v) { dGw[(size_t)k * st] += v.d; }, mine);
+    graphs_reverse_slots<T, 1, Tab>(
+        mload, dgload, [&](int j) { gslot[wave][j][lane] = R(0); },
+        [&](int j, T v) { gslot[wave][j][lane] += v.d; },
+        [&](int j, int k) { dGw[(size_t)k * st] += gslot[wave][j][lane]; },
+        [&](int k, T v) { dGw[(size_t)k * st] += v.d; }, mine);
   }
   __syncthreads();   // every share of dG written
   if (active)

@@ -81,3 +81,41 @@ def test_tables_stay_in_bounds(level):
                         stack.append((nodes[n, 1], nodes[n, 2], lev + 1))
     assert (reached == 1).all()
     assert max(len(f) for f in s.funcs) <= 12 and max(roots) <= 6
+
+
+def test_split_kernel_tables_level20():
+    """The split kernels' tables: every root has a share in [0, TABLE_WAVES)
+    and the shares' trie sizes are balanced; a node's local slot s >= 0 names
+    its own component in its graph's slot list, and the slot lists hold
+    distinct components."""
+    import re
+    src, _meta = cg.generate_table(20)
+
+    def arr(name):
+        m = re.search(r"__device__ const int " + name + r"\[\][^=]*= \{([^}]*)\}", src)
+        return [int(x) for x in m.group(1).split(",") if x.strip()]
+
+    node = np.array(arr("kNode")).reshape(-1, 4)
+    roots = np.array(arr("kRoots")).reshape(-1, 4)
+    slot_k = np.array(arr("kSlotK")).reshape(-1, cg.TABLE_SLOTS)
+    begin = [int(x) for x in re.search(r"constexpr int b\[\] = \{([^}]*)\}", src).group(1).split(",")]
+    load = np.zeros(cg.TABLE_WAVES)
+    for d in range(1, len(begin) - 1):
+        for g, r0, r1, w in roots[begin[d]:begin[d + 1]]:
+            assert 0 <= w < cg.TABLE_WAVES
+            ks = [k for k in slot_k[g] if k >= 0]
+            assert len(ks) == len(set(ks))
+            stack, n = [(r0, r1, 1)], 0
+            while stack:
+                a, b, level = stack.pop()
+                for t in range(a, b):
+                    n += 1
+                    k, c0, c1, s = node[t]
+                    if s >= 0:
+                        assert slot_k[g, s] == k
+                    else:
+                        assert k not in ks
+                    if level < d:
+                        stack.append((c0, c1, level + 1))
+            load[w] += n
+    assert load.max() <= 1.05 * load.mean()
