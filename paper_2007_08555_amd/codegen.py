@@ -1671,8 +1671,15 @@ SCHEDULE_TABLE = {"f64": {"mom": 85, "adj": 90}, "f32": {"mom": 120, "adj": 120}
 TABLE_LOSS_MAX_LEVEL = 20
 # wavefronts sharing a workgroup's 64 atoms in the split table kernels
 TABLE_WAVES = 4
-# local LDS slots per graph for the split kernels' dV/dM shares
-TABLE_SLOTS = 24
+# local LDS slots per graph for the split kernels' dV/dM shares, per level:
+# more slots catch more of the reverse walk's adds but hold fewer workgroups
+# per CU (measured: level 24 runs best with 16 (32 kB per workgroup), level 20
+# with 24)
+TABLE_SLOTS = {20: 24, 24: 16}
+
+
+def table_slots(level):
+    return TABLE_SLOTS.get(level, 16)
 
 
 def _moments_launch(tag, split):
@@ -1725,10 +1732,11 @@ def generate_table(lev_max):
                 n += trie_size(nodes[t][1], nodes[t][2], level + 1, depth_)
         return n
     sizes = {g: trie_size(r0, r1, 1, d) for d, lst in roots.items() for g, r0, r1 in lst}
-    # local slots: per graph its TABLE_SLOTS most frequent components (the
+    # local slots: per graph its nslot most frequent components (the
     # split kernels add their dV/dM shares in LDS, flushed once per graph)
     node_slot = [-1] * len(nodes)
-    slot_k = [-1] * (TABLE_SLOTS * len(s.keys))
+    nslot = table_slots(lev_max)
+    slot_k = [-1] * (nslot * len(s.keys))
     for d, lst in roots.items():
         for g, r0, r1 in lst:
             members, stack = [], [(r0, r1, 1)]
@@ -1741,10 +1749,10 @@ def generate_table(lev_max):
             freq = defaultdict(int)
             for t in members:
                 freq[nodes[t][0]] += 1
-            top = sorted(freq, key=lambda k: (-freq[k], k))[:TABLE_SLOTS]
+            top = sorted(freq, key=lambda k: (-freq[k], k))[:nslot]
             slot_of = {k: j for j, k in enumerate(top)}
             for j, k in enumerate(top):
-                slot_k[g * TABLE_SLOTS + j] = k
+                slot_k[g * nslot + j] = k
             for t in members:
                 node_slot[t] = slot_of.get(nodes[t][0], -1)
     load, share = [0] * TABLE_WAVES, {}
@@ -1820,7 +1828,7 @@ def generate_table(lev_max):
         level=lev_max, m=len(s.funcs), ngraphs=len(s.keys), C=s.C, n_mu=s.n_mu, nu_max=s.nu_max, ns=ns,
         nnodes=len(nodes), depth=depth, qmax=qmax,
         node_data=join(v for t, nd in enumerate(nodes) for v in (nd[0], nd[1], nd[2], node_slot[t])),
-        slot_data=join(slot_k), slots=TABLE_SLOTS,
+        slot_data=join(slot_k), slots=nslot,
         coef_data=", ".join(repr(float(c)) for c in coefs),
         root_data=join(root_list), root_begin=join(root_begin),
         foff_data=join(func_offsets), ffac_data=join(func_factors),
