@@ -277,8 +277,12 @@ __global__ void __launch_bounds__(64) contract_table_kernel(const EvalArgs<T> ar
       });
   args.site[i] = V;
   for (int k = 0; k < Tab::kC; ++k) Gi[(size_t)k * st] = T(0);
+  // graphs outside the need mask have dV/dg = 0 exactly: skipped without
+  // loading their dV/dg (the loads of every root, each waited on before its
+  // branch, dominated the degree-masked calls of the normal equations)
   graphs_reverse<T, 1, Tab>(mload, [&](int g) { return Dg[(size_t)g * st]; },
-                            [&](int k, T v) { Gi[(size_t)k * st] += v; });
+                            [&](int k, T v) { Gi[(size_t)k * st] += v; },
+                            [&](const int4& e) { return need_all || ((need[e.x >> 5] >> (e.x & 31)) & 1u); });
 }
 
 // The same with the work of a workgroup's 64 atoms shared out among W
