@@ -76,3 +76,24 @@ def test_level20_loss_gradient(lev20):
     log(f"[lev20 loss] gpu {loss:.10e} oracle {L_o:.10e}; grad max rel err {err.max():.3e}")
     assert abs(loss - L_o) <= 1e-10 * abs(L_o)
     assert err.max() <= 1e-8
+
+
+def test_level20_split_contraction_is_bitwise_repeatable(lev20):
+    """The table contraction of full evaluations and of the loss is shared
+    out among four wavefronts per workgroup, each with its own rows and LDS
+    slots, added in a fixed order: energies, forces, b and the loss gradient
+    agree bit for bit between calls, for a batch of several hundred atoms per
+    configuration (many workgroups, partial last workgroup)."""
+    from paper_2007_08555_amd import Batch
+    batch = synth.mixed_batch(seed=53, n_configs=12, n_min=40, n_max=200, n_species_model=3)
+    runs = [gpu_batch(lev20, batch, "fp64") for _ in range(2)]
+    for key in ("energy", "forces", "virial", "b", "site"):
+        np.testing.assert_array_equal(runs[0][key], runs[1][key])
+    K, N = len(batch["n_atoms"]), int(batch["n_atoms"].sum())
+    rng = np.random.default_rng(7)   # arbitrary targets: only repeatability is checked
+    tg = (rng.normal(0, 1, K), rng.normal(0, 1, (N, 3)), rng.normal(0, 1, (K, 9)))
+    B = Batch.from_arrays(batch)
+    g = [lev20.loss_grad(B, *tg, precision="fp64")[1].cpu().numpy() for _ in range(2)]
+    assert np.abs(g[0]).max() > 0
+    np.testing.assert_array_equal(g[0], g[1])
+    assert N % 64 != 0
