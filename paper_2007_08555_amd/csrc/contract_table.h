@@ -179,13 +179,17 @@ __device__ __forceinline__ void graphs_reverse_slots(const MLoad& mload, const D
 // products give the product of the other factors.  bout(alpha, B) receives
 // every B when ALL_B; otherwise functions with xi_alpha exactly zero, which
 // add nothing, are skipped.  Only the functions a0, a0 + a_step, ... are
-// formed (a share of a workgroup's wavefronts).
+// formed (a share of a workgroup's wavefronts), or, with alist, the acount
+// functions it lists in ascending order.
 template <typename T, typename Tab, bool ALL_B, typename XiLoad, typename VLoad, typename DgAdd, typename BOut>
 __device__ __forceinline__ T basis_products(const XiLoad& xiload, const VLoad& vload, const DgAdd& dgadd,
-                                            const BOut& bout, int a0 = 0, int a_step = 1) {
+                                            const BOut& bout, int a0 = 0, int a_step = 1,
+                                            const int* alist = nullptr, int acount = 0) {
   constexpr int Q = Tab::kMaxFactors;
   T V = T(0);
-  for (int a = a0; a < Tab::kM; a += a_step) {
+  const int n_iter = alist ? acount : (Tab::kM - a0 + a_step - 1) / a_step;
+  for (int t = 0; t < n_iter; ++t) {
+    const int a = alist ? alist[t] : a0 + t * a_step;
     if constexpr (!ALL_B && std::is_floating_point<T>::value) {
       if (xiload(a) == T(0)) continue;
     }
@@ -224,23 +228,31 @@ __device__ __forceinline__ T basis_products(const XiLoad& xiload, const VLoad& v
 template <typename T, bool WANT_B, typename Tab, bool M32 = false>
 __global__ void __launch_bounds__(64) contract_table_kernel(const EvalArgs<T> args) {
   // graphs that some function with xi_alpha != 0 uses (a bit per graph),
-  // and whether that is all of them
+  // whether that is all of them, and the functions with xi_alpha != 0 in
+  // ascending order (the workgroup is one wavefront: ballots compact them)
   __shared__ uint32_t need[(Tab::kGraphs + 31) / 32];
-  __shared__ int n_zero;
+  __shared__ int alist[WANT_B ? 1 : Tab::kM];
+  int n_zero = 0, acount = Tab::kM;
   if constexpr (!WANT_B) {
     for (int w = threadIdx.x; w < (Tab::kGraphs + 31) / 32; w += 64) need[w] = 0u;
-    if (threadIdx.x == 0) n_zero = 0;
-    __syncthreads();
-    for (int a = threadIdx.x; a < Tab::kM; a += 64)
-      if (args.xi[a] == T(0)) atomicAdd(&n_zero, 1);
+    const int lane = threadIdx.x;
+    int base = 0;
+    for (int a0 = 0; a0 < Tab::kM; a0 += 64) {
+      const int a = a0 + lane;
+      const bool nz = a < Tab::kM && args.xi[a] != T(0);
+      const unsigned long long bal = __ballot(nz);
+      if (nz) alist[base + __popcll(bal & ((1ull << lane) - 1ull))] = a;
+      base += __popcll(bal);
+    }
+    acount = base;
+    n_zero = Tab::kM - base;
     __syncthreads();
     if (n_zero > 0) {   // uniform over the workgroup
-      for (int a = threadIdx.x; a < Tab::kM; a += 64)
-        if (args.xi[a] != T(0))
-          for (int t = Tab::func_off()[a]; t < Tab::func_off()[a + 1]; ++t) {
-            const int g = Tab::func_fac()[t];
-            atomicOr(&need[g >> 5], 1u << (g & 31));
-          }
+      for (int t0 = threadIdx.x; t0 < acount; t0 += 64)
+        for (int t = Tab::func_off()[alist[t0]]; t < Tab::func_off()[alist[t0] + 1]; ++t) {
+          const int g = Tab::func_fac()[t];
+          atomicOr(&need[g >> 5], 1u << (g & 31));
+        }
       __syncthreads();
     }
   }
@@ -269,12 +281,15 @@ __global__ void __launch_bounds__(64) contract_table_kernel(const EvalArgs<T> ar
                               [&](const int4& e) { return all || ((need[e.x >> 5] >> (e.x & 31)) & 1u); });
   }
   for (int g = 0; g < Tab::kGraphs; ++g) Dg[(size_t)g * st] = T(0);
+  // with some xi_alpha zero (xi = e_alpha in the normal equations) only the
+  // listed functions are formed: the others would add nothing
   const T V = basis_products<T, Tab, WANT_B>(
       [&](int a) { return args.xi[a]; }, [&](int g) { return Dv[(size_t)g * st]; },
       [&](int g, T v) { Dg[(size_t)g * st] += v; },
       [&](int a, T B) {
         if (WANT_B) args.B[(size_t)a * args.b_stride + i] = B;
-      });
+      },
+      0, 1, need_all ? nullptr : alist, acount);
   args.site[i] = V;
   for (int k = 0; k < Tab::kC; ++k) Gi[(size_t)k * st] = T(0);
   // graphs outside the need mask have dV/dg = 0 exactly: skipped without
