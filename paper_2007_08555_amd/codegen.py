@@ -1543,7 +1543,9 @@ struct Tab {{
   static constexpr int kM = {m};
   static constexpr int kDepth = {depth};
   static constexpr int kMaxFactors = {qmax};
-  static constexpr int kSlots = {slots};
+  static constexpr int kSlots = {slots};       // slots per graph in the table
+  static constexpr int kSlots32 = {slots32};   // slots the FP32 kernels use (the first ones)
+  static constexpr int kSlots64 = {slots64};   // slots the FP64 kernels use
   __device__ static const int4* node() {{ return reinterpret_cast<const int4*>(kNode); }}
   __device__ static const int* slot_k() {{ return kSlotK; }}
   __device__ static const double* coef() {{ return kCoef; }}
@@ -1671,15 +1673,18 @@ SCHEDULE_TABLE = {"f64": {"mom": 85, "adj": 90}, "f32": {"mom": 120, "adj": 120}
 TABLE_LOSS_MAX_LEVEL = 20
 # wavefronts sharing a workgroup's 64 atoms in the split table kernels
 TABLE_WAVES = 4
-# local LDS slots per graph for the split kernels' dV/dM shares, per level:
-# more slots catch more of the reverse walk's adds but hold fewer workgroups
-# per CU (measured: level 24 runs best with 16 (32 kB per workgroup), level 20
-# with 24)
-TABLE_SLOTS = {20: 24, 24: 16}
+# local LDS slots per graph for the split kernels' dV/dM shares, per level,
+# (FP32, FP64): more slots catch more of the reverse walk's adds but hold
+# fewer workgroups per CU (measured at level 24: FP64 best with 16 slots of
+# 12, 16, 24, 32; FP32 best with 16 of 8, 16, 32; level 20 with 24)
+TABLE_SLOTS = {20: (24, 24), 24: (16, 16)}
 
 
-def table_slots(level):
-    return TABLE_SLOTS.get(level, 16)
+def table_slots(level, fp64=None):
+    """Slots the FP32 (fp64=False) or FP64 (fp64=True) kernels use at a level;
+    with fp64=None the table's slot count per graph (the larger)."""
+    s32, s64 = TABLE_SLOTS.get(level, (16, 16))
+    return max(s32, s64) if fp64 is None else (s64 if fp64 else s32)
 
 
 def _moments_launch(tag, split):
@@ -1828,7 +1833,8 @@ def generate_table(lev_max):
         level=lev_max, m=len(s.funcs), ngraphs=len(s.keys), C=s.C, n_mu=s.n_mu, nu_max=s.nu_max, ns=ns,
         nnodes=len(nodes), depth=depth, qmax=qmax,
         node_data=join(v for t, nd in enumerate(nodes) for v in (nd[0], nd[1], nd[2], node_slot[t])),
-        slot_data=join(slot_k), slots=nslot,
+        slot_data=join(slot_k), slots=nslot, slots32=table_slots(lev_max, fp64=False),
+        slots64=table_slots(lev_max, fp64=True),
         coef_data=", ".join(repr(float(c)) for c in coefs),
         root_data=join(root_list), root_begin=join(root_begin),
         foff_data=join(func_offsets), ffac_data=join(func_factors),

@@ -138,13 +138,14 @@ __device__ __forceinline__ void graphs_reverse(const MLoad& mload, const DgLoad&
   graphs_reverse<T, D, Tab>(mload, dgload, gadd, [](const int4&) { return true; });
 }
 
-// graphs_reverse for the split kernels: the shares of each graph's kSlots
-// most frequent components are added into local slots (szero, sadd; an
+// graphs_reverse for the split kernels: the shares of each graph's L (at
+// most kSlots, the table's slot count) most frequent components are added
+// into local slots (szero, sadd; an
 // atom's slots in LDS) and flushed into the atom's rows once per graph
 // (sflush(j, k)); the other components go to the rows directly (gadd).  The
 // slot count trades the share of adds the slots catch (level 24 with 16
 // slots: 72 %; level 20 with 24: 91 %) against workgroups per CU.
-template <typename T, int D, typename Tab, typename MLoad, typename DgLoad, typename SZero, typename SAdd,
+template <typename T, int D, typename Tab, int L, typename MLoad, typename DgLoad, typename SZero, typename SAdd,
           typename SFlush, typename GAdd, typename Take>
 __device__ __forceinline__ void graphs_reverse_slots(const MLoad& mload, const DgLoad& dgload, const SZero& szero,
                                                      const SAdd& sadd, const SFlush& sflush, const GAdd& gadd,
@@ -157,19 +158,19 @@ __device__ __forceinline__ void graphs_reverse_slots(const MLoad& mload, const D
       if constexpr (std::is_floating_point<T>::value) {
         if (P == T(0)) continue;
       }
-      for (int j = 0; j < Tab::kSlots; ++j) szero(j);
+      for (int j = 0; j < L; ++j) szero(j);
       (void)trie_reverse_nd<T, 1, D, Tab>(e.y, e.z, P, mload, [&](const int4& nd, T v) {
-        if (nd.w >= 0)
+        if (nd.w >= 0 && nd.w < L)
           sadd(nd.w, v);
         else
           gadd(nd.x, v);
       });
-      for (int j = 0; j < Tab::kSlots; ++j) {
+      for (int j = 0; j < L; ++j) {
         const int k = Tab::slot_k()[e.x * Tab::kSlots + j];
         if (k >= 0) sflush(j, k);
       }
     }
-    graphs_reverse_slots<T, D + 1, Tab>(mload, dgload, szero, sadd, sflush, gadd, take);
+    graphs_reverse_slots<T, D + 1, Tab, L>(mload, dgload, szero, sadd, sflush, gadd, take);
   }
 }
 
@@ -318,7 +319,10 @@ __global__ void __launch_bounds__(64 * W) contract_table_split_kernel(const Eval
   __shared__ uint32_t need[(Tab::kGraphs + 31) / 32];
   __shared__ int n_zero;
   __shared__ T vpart[W][64];
-  __shared__ T gslot[W][Tab::kSlots][64];   // local dV/dM slots of each wavefront's graph
+  // local dV/dM slots of each wavefront's graph (the first kSlots32 or
+  // kSlots64 of the table's slots, by precision)
+  constexpr int L = sizeof(T) == 8 ? Tab::kSlots64 : Tab::kSlots32;
+  __shared__ T gslot[W][L][64];
   if constexpr (!WANT_B) {
     for (int w = threadIdx.x; w < (Tab::kGraphs + 31) / 32; w += 64 * W) need[w] = 0u;
     if (threadIdx.x == 0) n_zero = 0;
@@ -387,7 +391,7 @@ __global__ void __launch_bounds__(64 * W) contract_table_split_kernel(const Eval
       for (int w = 1; w < W; ++w) d += args.Gpart[((size_t)(w - 1) * rows + Tab::kC + g) * st + i];
       return d;
     };
-    graphs_reverse_slots<T, 1, Tab>(
+    graphs_reverse_slots<T, 1, Tab, L>(
         mload, dgload, [&](int j) { gslot[wave][j][lane] = T(0); },
         [&](int j, T v) { gslot[wave][j][lane] += v; },
         [&](int j, int k) { Gw[(size_t)k * st] += gslot[wave][j][lane]; },
@@ -451,7 +455,8 @@ template <typename R, typename Tab, int W>
 __global__ void __launch_bounds__(64 * W) contract_table_loss_split_kernel(const EvalArgs<R> args,
                                                                           const LossArgs<R> la) {
   using T = Dual<R>;
-  __shared__ R gslot[W][Tab::kSlots][64];   // local slots of the tangent of dV/dM
+  constexpr int L = sizeof(R) == 8 ? Tab::kSlots64 : Tab::kSlots32;
+  __shared__ R gslot[W][L][64];   // local slots of the tangent of dV/dM
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int i = blockIdx.x * 64 + lane;
   const bool active = i < args.n_atoms;
@@ -498,7 +503,7 @@ __global__ void __launch_bounds__(64 * W) contract_table_loss_split_kernel(const
       }
       return T(v, d);
     };
-    graphs_reverse_slots<T, 1, Tab>(
+    graphs_reverse_slots<T, 1, Tab, L>(
         mload, dgload, [&](int j) { gslot[wave][j][lane] = R(0); },
         [&](int j, T v) { gslot[wave][j][lane] += v.d; },
         [&](int j, int k) { dGw[(size_t)k * st] += gslot[wave][j][lane]; },

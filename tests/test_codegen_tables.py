@@ -98,6 +98,7 @@ def test_split_kernel_tables_level20():
     node = np.array(arr("kNode")).reshape(-1, 4)
     roots = np.array(arr("kRoots")).reshape(-1, 4)
     slot_k = np.array(arr("kSlotK")).reshape(-1, cg.table_slots(20))
+    assert cg.table_slots(20, fp64=True) <= cg.table_slots(20) and cg.table_slots(20, fp64=False) <= cg.table_slots(20)
     begin = [int(x) for x in re.search(r"constexpr int b\[\] = \{([^}]*)\}", src).group(1).split(",")]
     load = np.zeros(cg.TABLE_WAVES)
     for d in range(1, len(begin) - 1):
